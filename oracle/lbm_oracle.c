@@ -1,0 +1,323 @@
+/*
+ * Oracle: plain, slow FP64 CPU implementation of the EWOD lattice Boltzmann
+ * step.  TEST INFRASTRUCTURE ONLY: it exists to check the GPU library, it is
+ * not part of the product path, and it shares no code with it.
+ *
+ * Model (Li, Li, Chen & Fang, "Lattice Boltzmann simulation of
+ * electrowetting-on-dielectric in a rough-wall channel", arXiv:0708.4182):
+ *   - D2Q9 velocities e_alpha and BGK evolution, eq. (1);
+ *   - density and velocity as moments of f, eq. (2);
+ *   - equilibrium with weights 4/9, 1/9, 1/36, eq. (3);
+ *   - Shan-Chen interparticle force with pseudopotential
+ *     phi = rho0 (1 - exp(-rho/rho0)) and Green function G_alpha, eq. (5);
+ *   - fluid-wall force with W_alpha and the solid indicator S, eq. (6);
+ *   - electric force f n on the conductive (rho >= rho_c) liquid in the layer
+ *     next to the insulator, n pointing to the electrode, eq. (9) and the text
+ *     around the critical density;
+ *   - velocity shift rho u' = rho u + tau (F_sigma + F_w + f), eq. (10);
+ *   - flux Q = (1/L) sum of u_x over the channel, eq. (11).
+ *
+ * Readings where the paper is silent (each one is a parameter or a stated rule):
+ *   - the Green function is given per direction class (g_axis for |e| = 1,
+ *     g_diag for |e| = sqrt 2), likewise the wall strength (w_axis, w_diag);
+ *   - F_sigma sums over fluid neighbours only; solid neighbours enter through F_w;
+ *   - walls use halfway bounce-back: a population that would stream from a
+ *     solid node is replaced by the opposite post-collision population of the
+ *     node itself;
+ *   - the electric layer is every fluid node within Chebyshev distance
+ *     elec_layers of a solid node, on the half of the domain (y < ny/2: bottom,
+ *     else top) whose wall is an electrode; n = -y at the bottom, +y at the top;
+ *   - a driving acceleration g adds F_b = rho g to the force of eq. (10);
+ *   - the domain is periodic in x and y; walls are solid rows in the mask.
+ *
+ * Arrays are row-major [ny][nx]; populations are planes [9][ny][nx].
+ * Solid nodes carry no populations (their entries are ignored and left 0).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int32_t nx, ny;
+    double tau, rho0;
+    double g_axis, g_diag;
+    double w_axis, w_diag;
+    double rho_c;
+    double f_elec;
+    int32_t elec_layers;
+    uint32_t elec_walls; /* bit 0: bottom wall is an electrode, bit 1: top */
+    double accel_x, accel_y;
+} orc_params;
+
+/* ---------------------------------------------------------------- lattice */
+static int E[9][2];     /* e_alpha, built from the paper's trigonometric definition */
+static double WT[9];    /* w_alpha of eq. (3) */
+static int OPP[9];      /* e_opp(alpha) = -e_alpha */
+static int lattice_ready = 0;
+
+static void lattice_init(void)
+{
+    if (lattice_ready) return;
+    const double pi = 3.14159265358979323846;
+    E[0][0] = 0; E[0][1] = 0;
+    for (int a = 1; a <= 4; ++a) {
+        E[a][0] = (int)lround(cos(pi * (a - 1) / 2.0));
+        E[a][1] = (int)lround(sin(pi * (a - 1) / 2.0));
+    }
+    for (int a = 5; a <= 8; ++a) {
+        E[a][0] = (int)lround(sqrt(2.0) * cos(pi * (2 * a - 1) / 4.0));
+        E[a][1] = (int)lround(sqrt(2.0) * sin(pi * (2 * a - 1) / 4.0));
+    }
+    WT[0] = 4.0 / 9.0;
+    for (int a = 1; a <= 4; ++a) WT[a] = 1.0 / 9.0;
+    for (int a = 5; a <= 8; ++a) WT[a] = 1.0 / 36.0;
+    for (int a = 0; a < 9; ++a)
+        for (int b = 0; b < 9; ++b)
+            if (E[b][0] == -E[a][0] && E[b][1] == -E[a][1]) OPP[a] = b;
+    lattice_ready = 1;
+}
+
+void orc_velocity_set(int32_t *ex, int32_t *ey, double *w, int32_t *opp)
+{
+    lattice_init();
+    for (int a = 0; a < 9; ++a) {
+        ex[a] = E[a][0]; ey[a] = E[a][1]; w[a] = WT[a]; opp[a] = OPP[a];
+    }
+}
+
+static inline int wrap(int i, int n) { i %= n; return i < 0 ? i + n : i; }
+static inline size_t at(const orc_params *p, int x, int y)
+{
+    return (size_t)wrap(y, p->ny) * (size_t)p->nx + (size_t)wrap(x, p->nx);
+}
+
+/* eq. (3) */
+void orc_equilibrium(double rho, double ux, double uy, double *feq)
+{
+    lattice_init();
+    double uu = ux * ux + uy * uy;
+    for (int a = 0; a < 9; ++a) {
+        double eu = E[a][0] * ux + E[a][1] * uy;
+        feq[a] = WT[a] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+    }
+}
+
+/* pseudopotential phi(rho) */
+double orc_phi(double rho0, double rho) { return rho0 * (1.0 - exp(-rho / rho0)); }
+
+/* --------------------------------------------------------------- geometry */
+/* Electric layer and electrode side of every node (see the header). */
+void orc_electric_layer(const orc_params *p, const uint8_t *solid, uint8_t *layer, uint8_t *top)
+{
+    int k = p->elec_layers;
+    for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x) {
+            size_t i = at(p, x, y);
+            int is_top = (y >= p->ny / 2);
+            top[i] = (uint8_t)(solid[i] ? 0 : is_top);
+            layer[i] = 0;
+            if (solid[i] || k <= 0) continue;
+            uint32_t wall_bit = is_top ? 2u : 1u;
+            if (!(p->elec_walls & wall_bit)) continue;
+            int near = 0;
+            for (int dy = -k; dy <= k && !near; ++dy)
+                for (int dx = -k; dx <= k; ++dx)
+                    if (solid[at(p, x + dx, y + dy)]) { near = 1; break; }
+            layer[i] = (uint8_t)near;
+        }
+}
+
+/*
+ * Per-node flag word, the format the GPU library exports for byte-exact
+ * comparison: bit (alpha-1) = S(x + e_alpha) for alpha = 1..8, bit 8 = S(x),
+ * bit 9 = electric layer, bit 10 = top electrode side.  A solid node is 0x100.
+ */
+void orc_flags(const orc_params *p, const uint8_t *solid, uint16_t *flags)
+{
+    lattice_init();
+    size_t n = (size_t)p->nx * p->ny;
+    uint8_t *layer = calloc(n, 1), *top = calloc(n, 1);
+    orc_electric_layer(p, solid, layer, top);
+    for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x) {
+            size_t i = at(p, x, y);
+            if (solid[i]) { flags[i] = 0x100; continue; }
+            uint16_t v = 0;
+            for (int a = 1; a <= 8; ++a)
+                if (solid[at(p, x + E[a][0], y + E[a][1])]) v |= (uint16_t)(1u << (a - 1));
+            if (layer[i]) v |= 0x200;
+            if (top[i]) v |= 0x400;
+            flags[i] = v;
+        }
+    free(layer); free(top);
+}
+
+/* ------------------------------------------------------------------ moments */
+/* eq. (2): rho = sum f, rho u = sum f e.  Solid nodes get 0. */
+void orc_moments(const orc_params *p, const uint8_t *solid, const double *f,
+                 double *rho, double *ux, double *uy)
+{
+    lattice_init();
+    size_t n = (size_t)p->nx * p->ny;
+    for (size_t i = 0; i < n; ++i) {
+        if (solid[i]) { rho[i] = ux[i] = uy[i] = 0.0; continue; }
+        double r = 0, jx = 0, jy = 0;
+        for (int a = 0; a < 9; ++a) {
+            double fa = f[(size_t)a * n + i];
+            r += fa; jx += fa * E[a][0]; jy += fa * E[a][1];
+        }
+        rho[i] = r; ux[i] = jx / r; uy[i] = jy / r;
+    }
+}
+
+/* ------------------------------------------------------------------- forces */
+/*
+ * From the density field: Fs = eq. (5) over fluid neighbours, Fw = eq. (6),
+ * Fe = electric force on conductive layer nodes.  Each output is [2][ny][nx]
+ * (x plane then y plane); solid nodes get 0.  Any output may be NULL.
+ */
+static void forces_on(const orc_params *p, const uint8_t *solid, const uint8_t *layer,
+                      const uint8_t *top, const double *rho, double *Fs, double *Fw, double *Fe)
+{
+    size_t n = (size_t)p->nx * p->ny;
+    double G[9], W[9];
+    G[0] = W[0] = 0.0;
+    for (int a = 1; a <= 4; ++a) { G[a] = p->g_axis; W[a] = p->w_axis; }
+    for (int a = 5; a <= 8; ++a) { G[a] = p->g_diag; W[a] = p->w_diag; }
+
+    double *phi = malloc(n * sizeof(double));
+    for (size_t i = 0; i < n; ++i) phi[i] = solid[i] ? 0.0 : orc_phi(p->rho0, rho[i]);
+
+    for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x) {
+            size_t i = at(p, x, y);
+            double sx = 0, sy = 0, wx = 0, wy = 0, ex = 0, ey = 0;
+            if (!solid[i]) {
+                for (int a = 1; a <= 8; ++a) {
+                    size_t j = at(p, x + E[a][0], y + E[a][1]);
+                    if (solid[j]) {          /* eq. (6), S = 1 */
+                        wx += W[a] * E[a][0];
+                        wy += W[a] * E[a][1];
+                    } else {                 /* eq. (5) */
+                        sx += G[a] * phi[j] * E[a][0];
+                        sy += G[a] * phi[j] * E[a][1];
+                    }
+                }
+                sx *= -phi[i]; sy *= -phi[i];
+                wx *= -phi[i]; wy *= -phi[i];
+                if (layer[i] && rho[i] >= p->rho_c)
+                    ey = top[i] ? p->f_elec : -p->f_elec;
+            }
+            if (Fs) { Fs[i] = sx; Fs[n + i] = sy; }
+            if (Fw) { Fw[i] = wx; Fw[n + i] = wy; }
+            if (Fe) { Fe[i] = ex; Fe[n + i] = ey; }
+        }
+    free(phi);
+}
+
+void orc_forces(const orc_params *p, const uint8_t *solid, const double *rho,
+                double *Fs, double *Fw, double *Fe)
+{
+    lattice_init();
+    size_t n = (size_t)p->nx * p->ny;
+    uint8_t *layer = calloc(n, 1), *top = calloc(n, 1);
+    orc_electric_layer(p, solid, layer, top);
+    forces_on(p, solid, layer, top, rho, Fs, Fw, Fe);
+    free(layer); free(top);
+}
+
+/* --------------------------------------------------------------------- init */
+/* f_alpha(x, 0) = f_alpha^eq(rho_init, u_init) on fluid nodes, 0 on solids. */
+void orc_init(const orc_params *p, const uint8_t *solid, const double *rho,
+              const double *ux, const double *uy, double *f)
+{
+    lattice_init();
+    size_t n = (size_t)p->nx * p->ny;
+    double feq[9];
+    for (size_t i = 0; i < n; ++i) {
+        if (solid[i]) { for (int a = 0; a < 9; ++a) f[(size_t)a * n + i] = 0.0; continue; }
+        orc_equilibrium(rho[i], ux ? ux[i] : 0.0, uy ? uy[i] : 0.0, feq);
+        for (int a = 0; a < 9; ++a) f[(size_t)a * n + i] = feq[a];
+    }
+}
+
+/* --------------------------------------------------------------------- step */
+/*
+ * Advance nsteps time steps in place.  f holds the populations after
+ * streaming (the state at time t).  One step:
+ *   1. rho, u from eq. (2);
+ *   2. forces Fs (5), Fw (6), electric f n, body rho g;
+ *   3. u' from eq. (10);
+ *   4. collision f* = f - (f - f^eq(rho, u'))/tau (right side of eq. (1));
+ *   5. streaming f(x + e, t + 1) = f*(x) (left side of eq. (1)), with a
+ *      population arriving from a solid node replaced by bounce-back.
+ * Returns 0, or 1 if a fluid density became non-positive or not finite.
+ */
+int orc_step(const orc_params *p, const uint8_t *solid, double *f, int64_t nsteps)
+{
+    lattice_init();
+    size_t n = (size_t)p->nx * p->ny;
+    double *rho = malloc(n * sizeof(double)), *ux = malloc(n * sizeof(double)),
+           *uy = malloc(n * sizeof(double));
+    double *Fs = malloc(2 * n * sizeof(double)), *Fw = malloc(2 * n * sizeof(double)),
+           *Fe = malloc(2 * n * sizeof(double));
+    double *fs = malloc(9 * n * sizeof(double));
+    uint8_t *layer = calloc(n, 1), *top = calloc(n, 1);
+    orc_electric_layer(p, solid, layer, top);
+    int bad = 0;
+
+    for (int64_t t = 0; t < nsteps && !bad; ++t) {
+        orc_moments(p, solid, f, rho, ux, uy);
+        for (size_t i = 0; i < n; ++i)
+            if (!solid[i] && !(rho[i] > 0.0 && isfinite(rho[i]))) bad = 1;
+        if (bad) break;
+        forces_on(p, solid, layer, top, rho, Fs, Fw, Fe);
+
+        /* collision */
+        double feq[9];
+        for (size_t i = 0; i < n; ++i) {
+            if (solid[i]) { for (int a = 0; a < 9; ++a) fs[(size_t)a * n + i] = 0.0; continue; }
+            double Fx = Fs[i] + Fw[i] + Fe[i] + rho[i] * p->accel_x;
+            double Fy = Fs[n + i] + Fw[n + i] + Fe[n + i] + rho[i] * p->accel_y;
+            double upx = (rho[i] * ux[i] + p->tau * Fx) / rho[i];  /* eq. (10) */
+            double upy = (rho[i] * uy[i] + p->tau * Fy) / rho[i];
+            orc_equilibrium(rho[i], upx, upy, feq);
+            for (int a = 0; a < 9; ++a) {
+                double fa = f[(size_t)a * n + i];
+                fs[(size_t)a * n + i] = fa - (fa - feq[a]) / p->tau;
+            }
+        }
+
+        /* streaming with halfway bounce-back */
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                size_t i = at(p, x, y);
+                if (solid[i]) continue;
+                for (int a = 0; a < 9; ++a) {
+                    size_t src = at(p, x - E[a][0], y - E[a][1]);
+                    f[(size_t)a * n + i] = solid[src] ? fs[(size_t)OPP[a] * n + i]
+                                                      : fs[(size_t)a * n + src];
+                }
+            }
+    }
+    free(rho); free(ux); free(uy); free(Fs); free(Fw); free(Fe); free(fs);
+    free(layer); free(top);
+    return bad;
+}
+
+/* ------------------------------------------------------------------- outputs */
+/* eq. (11) with L = nx: Q = (1/nx) sum over fluid nodes of u_x; M = sum rho. */
+void orc_flux(const orc_params *p, const uint8_t *solid, const double *f, double *Q, double *M)
+{
+    size_t n = (size_t)p->nx * p->ny;
+    double *rho = malloc(n * sizeof(double)), *ux = malloc(n * sizeof(double)),
+           *uy = malloc(n * sizeof(double));
+    orc_moments(p, solid, f, rho, ux, uy);
+    double q = 0, m = 0;
+    for (size_t i = 0; i < n; ++i)
+        if (!solid[i]) { q += ux[i]; m += rho[i]; }
+    *Q = q / p->nx;
+    *M = m;
+    free(rho); free(ux); free(uy);
+}

@@ -1,0 +1,63 @@
+"""Pins of the oracle's lattice, equilibrium and pseudopotential (CPU only).
+
+Each check is a value the mathematics of the paper's eqs. (2)-(3) fixes, not a
+re-evaluation of the oracle's own formula.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+
+# D2Q9 velocities as listed explicitly (angles 0, 90, 180, 270 degrees for
+# alpha = 1..4 and 45, 135, 225, 315 degrees times sqrt 2 for alpha = 5..8).
+PAPER_E = np.array([(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1),
+                    (1, 1), (-1, 1), (-1, -1), (1, -1)])
+
+
+def test_velocity_set_matches_paper_listing():
+    e, w, opp = O.velocity_set()
+    np.testing.assert_array_equal(e, PAPER_E)
+    np.testing.assert_allclose(w, [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4, rtol=0, atol=1e-17)
+    for a in range(9):
+        np.testing.assert_array_equal(e[opp[a]], -e[a])
+    # pairs 1<->3, 2<->4, 5<->7, 6<->8
+    assert list(opp) == [0, 3, 4, 1, 2, 7, 8, 5, 6]
+
+
+def test_lattice_isotropy():
+    e, w, _ = O.velocity_set()
+    assert abs(w.sum() - 1) < 1e-15
+    np.testing.assert_allclose(w @ e, 0, atol=1e-16)
+    np.testing.assert_allclose((w[:, None, None] * e[:, :, None] * e[:, None, :]).sum(0),
+                               np.eye(2) / 3, atol=1e-16)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_equilibrium_moments_closed_form(seed):
+    """sum f^eq = rho, sum f^eq e = rho u, sum f^eq e e = rho (I/3 + u u)."""
+    rng = np.random.default_rng(seed)
+    e = PAPER_E.astype(float)
+    for _ in range(20):
+        rho = rng.uniform(0.1, 3.0)
+        u = rng.uniform(-0.2, 0.2, 2)
+        feq = O.equilibrium(rho, *u)
+        assert abs(feq.sum() - rho) < 1e-14 * rho
+        np.testing.assert_allclose(feq @ e, rho * u, atol=1e-15)
+        Pi = (feq[:, None, None] * e[:, :, None] * e[:, None, :]).sum(0)
+        np.testing.assert_allclose(Pi, rho * (np.eye(2) / 3 + np.outer(u, u)), atol=1e-14)
+
+
+def test_equilibrium_at_rest_is_weights():
+    np.testing.assert_allclose(O.equilibrium(2.5, 0, 0),
+                               2.5 * np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4), rtol=1e-15)
+
+
+@pytest.mark.parametrize("rho0", [1.0, 0.7, 2.0])
+def test_pseudopotential_special_values(rho0):
+    """phi = rho0 (1 - exp(-rho/rho0)): phi(0) = 0, phi(rho0 ln 2) = rho0/2,
+    phi -> rho0 for rho >> rho0, slope 1 at rho = 0."""
+    assert O.phi(rho0, 0.0) == 0.0
+    assert abs(O.phi(rho0, rho0 * np.log(2.0)) - rho0 / 2) < 1e-15
+    assert abs(O.phi(rho0, 50 * rho0) - rho0) < 1e-15
+    h = 1e-7
+    assert abs(O.phi(rho0, h) / h - 1) < 1e-6
