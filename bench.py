@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Throughput of the fused EWOD Shan-Chen D2Q9 step on one MI355X.
+
+Workload: one rough-wall channel of 8192 x 2048 nodes with random steps on both
+walls (height 2..8, pitch 16..64, width pitch/4), liquid with a vapour layer at
+the walls, G = -5, tau = 1, electric force 1e-3 on the near-wall liquid and a
+driving acceleration of 1e-6 along x (synthetic, seed 0).
+
+A timed step is one launch of the fused collide-stream kernel over the whole
+lattice; the timed region ends with one FP64 flux/mass reduction (the monitor
+a steady-flux run takes every few hundred steps).  Inputs are resident in HBM
+before timing starts.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + % HBM roofline; steady-flux lattice updates, warm-start vs plain"
+HBM_PEAK_GBS = 8000.0
+STORAGES = {"f32": 0, "f16": 1, "bf16": 2}
+ELEM_BYTES = {0: 4, 1: 2, 2: 2}
+KERNEL_SRC = os.path.join(ROOT, "paper_0708_4182_amd", "csrc", "lbm_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(storage_name: str):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, or None
+    if they were taken on a different kernel source."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    e = t.get(storage_name)
+    if not e or e.get("kernel_sha") != kernel_sha():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def time_storage(case, storage, steps, warmup, tile):
+    import torch
+    from paper_0708_4182_amd import lbm
+
+    from paper_0708_4182_amd import autotune
+
+    c = case.params.replace(storage=storage)
+    sim = lbm.Simulation(c, case.solid, case.rho, case.ux, case.uy)
+    if tile:
+        sim.set_tile(*tile)
+        chosen = list(tile)
+    else:
+        bx, rows, us, cached = autotune.tune(sim, reps=5, cache=None)
+        chosen = [bx, rows]
+    sim.step(warmup)
+    sim.flux()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    with torch.cuda.stream(sim.stream):
+        t0 = time.perf_counter()
+        ev[0].record(sim.stream)
+        sim.step(steps)
+        ev[1].record(sim.stream)
+        Q, M = sim.flux()            # synchronizes
+        ev[2].record(sim.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = ev[0].elapsed_time(ev[1]) / steps
+    total_ms = ev[0].elapsed_time(ev[2])
+    del sim
+    torch.cuda.empty_cache()
+    return dict(step_ms=step_ms, total_ms=total_ms, wall_s=wall, Q=Q, M=M, tile=chosen)
+
+
+def copy_ceiling(nbytes: int, reps: int = 20):
+    """GB/s of a plain device-to-device copy (read + write counted) of a buffer
+    the size of one population buffer: the practical HBM ceiling."""
+    import torch
+
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"GB/s": round(2 * nbytes / (ms * 1e-3) / 1e9, 1), "bytes_copied": nbytes, "ms": round(ms, 4)}
+
+
+def cpu_baseline(steps: int):
+    import oracle as O
+    from paper_0708_4182_amd import inputs as I
+
+    c = I.random_channel_case(nx=512, ny=128, seed=0)
+    f = O.init(c.params, c.solid, c.rho)
+    t0 = time.perf_counter()
+    O.step(c.params, c.solid, f, steps)
+    dt = time.perf_counter() - t0
+    return {"value": round(512 * 128 * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"FP64 oracle, single thread, 512x128 instance of the same random-step "
+                      f"generator (seed 0), {steps} steps, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--storage", default="f32", choices=sorted(STORAGES))
+    ap.add_argument("--variants", default="f16,bf16",
+                    help="other storages timed after the main line ('' for none)")
+    ap.add_argument("--nx", type=int, default=8192)
+    ap.add_argument("--ny", type=int, default=2048)
+    ap.add_argument("--tile", default="auto",
+                    help="block_x x rows (e.g. 512x64; rows 0 = one wave of workgroups) or 'auto'")
+    ap.add_argument("--cpu-steps", type=int, default=2000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-copy-ceiling", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
+              "the multi-GPU halo exchange is not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_0708_4182_amd import inputs as I
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    tile = None if args.tile in ("", "auto") else tuple(int(v) for v in args.tile.split("x"))
+    case = I.random_channel_case(nx=args.nx, ny=args.ny, f_elec=1e-3, seed=0)
+    nsites = args.nx * args.ny
+    nfluid = int((case.solid == 0).sum())
+
+    def line_for(name, r):
+        s = STORAGES[name]
+        alg_bytes = 18 * ELEM_BYTES[s] * nfluid
+        achieved = alg_bytes / (r["step_ms"] * 1e-3) / 1e9
+        traffic = measured_traffic(name)
+        return {
+            "tile": r["tile"],
+            "mlups": round(nsites / (r["step_ms"] * 1e-3) / 1e6, 1),
+            "ms_per_step": round(r["step_ms"], 5),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "traffic": traffic},
+        }
+
+    main_r = time_storage(case, STORAGES[args.storage], args.steps, args.warmup, tile)
+    print(f"# {args.storage}: tile {main_r['tile']} {main_r['step_ms']*1e3:.1f} us/step, "
+          f"Q={main_r['Q']:.6e} M={main_r['M']:.6e}",
+          file=sys.stderr, flush=True)
+    main_line = line_for(args.storage, main_r)
+    variants = {}
+    for v in [v for v in args.variants.split(",") if v and v != args.storage]:
+        r = time_storage(case, STORAGES[v], args.steps, args.warmup, tile)
+        print(f"# {v}: tile {r['tile']} {r['step_ms']*1e3:.1f} us/step", file=sys.stderr, flush=True)
+        variants[v] = line_for(v, r)
+
+    ms_per_step = main_r["total_ms"] / args.steps
+    value = nsites * args.steps / (main_r["total_ms"] * 1e-3) / 1e6
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"random-step rough channel {args.nx}x{args.ny} (step height 2-8, "
+                               f"pitch 16-64), G=-5, tau=1, f_elec=1e-3, g=1e-6, seed 0",
+                   "nx": args.nx, "ny": args.ny, "storage": args.storage,
+                   "tile": main_r["tile"], "tile_choice": "fixed" if tile else "autotuned",
+                   "fluid_nodes": nfluid},
+        "roofline": main_line["roofline"],
+        "kernel": "k_step (fused pull-stream + bounce-back + Shan-Chen/EWOD forces + BGK)",
+        "variants": variants,
+    }
+    if not args.no_copy_ceiling:
+        out["copy_ceiling"] = copy_ceiling(9 * nsites * ELEM_BYTES[STORAGES[args.storage]])
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,167 @@
+/*
+ * liblbm: D2Q9 Shan-Chen lattice Boltzmann with the electrowetting-on-dielectric
+ * (EWOD) electric force, for AMD Instinct MI355X (gfx950).
+ *
+ * The model is the one of Li, Li, Chen & Fang, "Lattice Boltzmann simulation of
+ * electrowetting-on-dielectric in a rough-wall channel" (arXiv:0708.4182):
+ *   eq. (1)  BGK evolution f_a(x + e_a, t + 1) - f_a(x, t) = -(f_a - f_a^eq)/tau
+ *   eq. (2)  rho = sum_a f_a,  rho u = sum_a f_a e_a
+ *   eq. (3)  f_a^eq = w_a rho [1 + 3 e_a.u + 9/2 (e_a.u)^2 - 3/2 u^2]
+ *   eq. (5)  F_sigma = -phi(x) sum_a G_a phi(x + e_a) e_a,  phi = rho0 (1 - exp(-rho/rho0))
+ *   eq. (6)  F_w = -phi(x) sum_a W_a S(x + e_a) e_a
+ *   eq. (9)  electric force f n on the conductive liquid (rho >= rho_c) in the
+ *            layer next to the insulator, n pointing to the electrode
+ *   eq. (10) rho u' = rho u + tau (F_sigma + F_w + f), u' enters f^eq in eq. (1)
+ *   eq. (11) Q = (1/L) integral of u_x over the channel
+ * Walls are solid nodes of a mask; populations arriving from a solid node are
+ * replaced by halfway bounce-back.  The domain is periodic in x and y.
+ *
+ * Conventions for every entry point:
+ *   - the return value is an lbm_status: 0 on success, < 0 on error; nothing
+ *     throws across this interface;
+ *   - host arrays are row-major [ny][nx] with x fastest; "device" pointers are
+ *     HIP device addresses on the device current when lbm_init was called;
+ *   - the caller owns every array it passes and the device workspace; the
+ *     library copies what it needs during the call and never allocates device
+ *     memory itself; it owns only the opaque handle;
+ *   - all GPU work of a handle is issued on the HIP stream given to lbm_init;
+ *     calls marked "asynchronous" return before the GPU finishes;
+ *   - one handle must not be used from two threads at once;
+ *   - after an error other than LBM_EINVAL the handle is in an error state
+ *     (sticky) and every later call returns LBM_ESTATE until lbm_free.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,    /* bad argument or parameter; nothing was launched       */
+    LBM_ENOMEM = -2,    /* workspace too small                                   */
+    LBM_EDEVICE = -3,   /* a HIP call failed (message in lbm_last_error)         */
+    LBM_EDIVERGED = -4, /* a fluid density became <= 0 or not finite             */
+    LBM_ESTATE = -5     /* handle is in a sticky error state                     */
+} lbm_status;
+
+/* How populations are stored in device memory.  The arithmetic is FP32 in all
+ * three cases.  F16 and BF16 store the deviation d_a = f_a - w_a rho0 rounded to
+ * nearest even, and decode f_a = w_a rho0 + d_a in FP32. */
+typedef enum { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 } lbm_storage;
+
+/* Electrode walls (bit set): the electric layer exists only next to these. */
+#define LBM_ELEC_BOTTOM 1u /* nodes with y <  ny/2, n = (0, -1) */
+#define LBM_ELEC_TOP 2u    /* nodes with y >= ny/2, n = (0, +1) */
+
+typedef struct {
+    int32_t nx, ny;        /* lattice size; both >= 3                                  */
+    double tau;            /* relaxation time of eq. (1); > 0.5                        */
+    double rho0;           /* constant of the pseudopotential phi; > 0                 */
+    double g_axis, g_diag; /* Green function G_a of eq. (5) for |e_a| = 1 and sqrt 2   */
+    double w_axis, w_diag; /* fluid-wall strength W_a of eq. (6), same classes         */
+    double rho_c;          /* critical density: fluid with rho >= rho_c is conductive  */
+    double f_elec;         /* magnitude f of the electric force per layer node         */
+    int32_t elec_layers;   /* layer = fluid within this Chebyshev distance of a solid  */
+    uint32_t elec_walls;   /* LBM_ELEC_BOTTOM | LBM_ELEC_TOP                            */
+    double accel_x, accel_y; /* driving acceleration g: body force rho g on every node */
+    int32_t storage;       /* lbm_storage                                              */
+} lbm_params;
+
+typedef struct lbm_sim lbm_sim;
+
+/* Bytes of device workspace lbm_init needs for these parameters (0 if the
+ * parameters are invalid).  The workspace holds two population buffers, the
+ * per-node flag words and reduction scratch. */
+size_t lbm_workspace_bytes(const lbm_params *p);
+
+/*
+ * Create a simulation.  solid: host uint8 [ny][nx], 1 = solid node (the paper's
+ * S = 1).  rho_init, ux_init, uy_init: host float64 [ny][nx]; the velocities may
+ * be NULL (rest).  Populations start at f_a^eq(rho_init, u_init) of eq. (3) on
+ * fluid nodes.  dev_ws: device workspace of ws_bytes >= lbm_workspace_bytes(p),
+ * 256-byte aligned, owned by the caller, not touched by anything else while
+ * the handle lives.  stream: hipStream_t (NULL = default stream).
+ * Validates everything before any GPU work: nx, ny >= 3; tau > 0.5; rho0 > 0;
+ * at least one fluid node; storage valid; elec_layers >= 0; finite values.
+ * Synchronizes the stream before returning.  On success *out is a new handle.
+ */
+lbm_status lbm_init(lbm_sim **out, const lbm_params *p, const uint8_t *solid,
+                    const double *rho_init, const double *ux_init, const double *uy_init,
+                    void *dev_ws, size_t ws_bytes, void *stream);
+
+/* Re-initialise the populations of an existing handle to f^eq(rho, u) from
+ * device float32 fields [ny][nx] (e.g. a predicted steady state used as a
+ * warm start).  Geometry and parameters are kept.  Asynchronous. */
+lbm_status lbm_init_device(lbm_sim *sim, const float *rho, const float *ux, const float *uy);
+
+/* Advance nsteps >= 0 full time steps of eq. (1) (collision with the forces of
+ * eqs. (5), (6), (9), (10), then streaming with bounce-back).  Asynchronous. */
+lbm_status lbm_step(lbm_sim *sim, int64_t nsteps);
+
+/* Density and velocity of eq. (2) (u before the force shift of eq. (10)) of
+ * the current state, as float32 [ny][nx]; solid nodes give 0.  on_device != 0:
+ * the three pointers are device arrays and the call is asynchronous; else they
+ * are host arrays and the call synchronizes.  Any pointer may be NULL. */
+lbm_status lbm_moments(lbm_sim *sim, float *rho, float *ux, float *uy, int on_device);
+
+/* Flux of eq. (11) with L = nx, Q = (1/nx) sum over fluid nodes of u_x, and the
+ * total fluid mass M = sum of rho, both accumulated in FP64 on the GPU in a
+ * fixed order (bitwise reproducible).  Synchronizes.  Returns LBM_EDIVERGED
+ * (sticky) if any fluid density is <= 0 or not finite; Q and M are still set. */
+lbm_status lbm_flux(lbm_sim *sim, double *Q, double *M);
+
+/* Per-node flag words (host uint16 [ny][nx]): bit (a-1) = S(x + e_a) for
+ * a = 1..8 with e_1..e_8 = (1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1);
+ * bit 8 = S(x); bit 9 = electric layer; bit 10 = top electrode side.  A solid
+ * node is exactly 0x100.  Synchronizes. */
+lbm_status lbm_geometry(lbm_sim *sim, uint16_t *flags);
+
+/* Change the electric force magnitude and the driving acceleration without
+ * re-initialising (parameter sweeps).  Takes effect at the next lbm_step. */
+lbm_status lbm_set_forces(lbm_sim *sim, double f_elec, double accel_x, double accel_y);
+
+/* Kernel tile: block_x columns per workgroup (64, 128, 256 or 512) and about
+ * rows_per_block rows marched by one workgroup; 0 picks as many row chunks as
+ * fill one wave of resident workgroups (chunks of at least 8 rows).  Results
+ * do not depend on the tile (bitwise).  Default 256 x 0.  Takes effect at the
+ * next lbm_step. */
+lbm_status lbm_set_tile(lbm_sim *sim, int32_t block_x, int32_t rows_per_block);
+
+/* Autotuner: times each candidate tile (block_x in 64..512, rows_per_block in
+ * {0, 32, 64, 128}) for `reps` launches on the current state and keeps the
+ * fastest.  The trial launches write only the spare population buffer, so the
+ * simulation state and step count are unchanged.  Synchronizes.  The chosen
+ * tile and its time per step (microseconds) are returned through the non-NULL
+ * pointers. */
+lbm_status lbm_autotune(lbm_sim *sim, int32_t reps, int32_t *block_x, int32_t *rows_per_block,
+                        float *us_per_step);
+
+/* Checkpoint: raw device state (stored populations + step counter) to/from a
+ * host buffer of lbm_state_bytes(sim) bytes.  Both synchronize.  Loading a
+ * saved state and stepping gives bitwise the same result as never stopping. */
+size_t lbm_state_bytes(const lbm_sim *sim);
+lbm_status lbm_save_state(lbm_sim *sim, void *host, size_t bytes);
+lbm_status lbm_load_state(lbm_sim *sim, const void *host, size_t bytes);
+
+/* Time steps taken since lbm_init (or the loaded checkpoint). */
+int64_t lbm_steps_done(const lbm_sim *sim);
+
+/* Free the handle (not the workspace, which the caller owns).  NULL is a no-op. */
+void lbm_free(lbm_sim *sim);
+
+/* Last error message of a handle (or of the last failed lbm_init if sim is
+ * NULL); never NULL. */
+const char *lbm_last_error(const lbm_sim *sim);
+
+/* Name of a status code. */
+const char *lbm_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -1,0 +1,557 @@
+// Host side of liblbm: the C ABI declared in include/lbm.h.
+//
+// Validates parameters, derives the per-node flag words from the solid mask
+// (integer arithmetic on the host), carves the caller's device workspace into
+// two population buffers, the flags and reduction scratch, and issues the
+// kernels of lbm_kernels.hip on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+using lbm::Grid;
+using lbm::Model;
+
+struct lbm_sim {
+    lbm_params p{};
+    Grid g{};
+    Model m{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    char *buf[2] = {nullptr, nullptr};
+    size_t buf_bytes = 0;
+    uint16_t *flags = nullptr;
+    double *partials = nullptr;
+    double *result = nullptr;
+    int cur = 0;
+    int64_t steps = 0;
+    int block_x = 256;
+    int rows = 0;          // rows per chunk; 0 = one wave of resident workgroups
+    int cus = 0;           // compute units of the device
+    int chunks = 0;        // cached tiling (0 = recompute)
+    lbm_status sticky = LBM_OK;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_init_error;
+
+constexpr size_t kAlign = 256;
+constexpr uint64_t kStateMagic = 0x314d54534d424c00ull;  // "\0LBMSTM1"
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t elem_size(int storage) { return storage == LBM_F32 ? 4 : 2; }
+
+struct Layout {
+    Grid g;
+    size_t buf_bytes, flags_off, flags_bytes, part_off, res_off, total;
+    size_t buf_off[2];
+};
+
+bool finite_all(const lbm_params *p) {
+    const double v[] = {p->tau, p->rho0, p->g_axis, p->g_diag, p->w_axis, p->w_diag,
+                        p->rho_c, p->f_elec, p->accel_x, p->accel_y};
+    for (double d : v)
+        if (!std::isfinite(d)) return false;
+    return true;
+}
+
+// Returns an empty string if the parameters are valid, else the reason.
+std::string check_params(const lbm_params *p) {
+    if (!p) return "params is NULL";
+    if (p->nx < 3 || p->ny < 3) return "nx and ny must be >= 3";
+    if (!finite_all(p)) return "parameters must be finite";
+    if (!(p->tau > 0.5)) return "tau must be > 0.5";
+    if (!(p->rho0 > 0.0)) return "rho0 must be > 0";
+    if (p->storage < LBM_F32 || p->storage > LBM_BF16) return "storage must be LBM_F32, LBM_F16 or LBM_BF16";
+    if (p->elec_layers < 0 || p->elec_layers > 1024) return "elec_layers must be in [0, 1024]";
+    if (p->elec_walls > 3u) return "elec_walls must be a combination of LBM_ELEC_BOTTOM and LBM_ELEC_TOP";
+    return "";
+}
+
+bool make_layout(const lbm_params *p, Layout &L) {
+    if (!check_params(p).empty()) return false;
+    L.g.nx = p->nx;
+    L.g.ny = p->ny;
+    L.g.pitch = (int32_t)align_up((size_t)p->nx, 64);
+    const size_t plane = (size_t)L.g.pitch * (size_t)p->ny;
+    L.buf_bytes = align_up(9 * plane * elem_size(p->storage), kAlign);
+    // 32-bit byte offsets inside one population buffer
+    if (9 * plane * elem_size(p->storage) >= (size_t(1) << 32)) return false;
+    // the init staging (3 float32 planes) lives in the spare population buffer
+    if (3 * (size_t)p->nx * p->ny * sizeof(float) > L.buf_bytes) return false;
+    L.g.plane = (uint32_t)plane;
+    L.buf_off[0] = 0;
+    L.buf_off[1] = L.buf_bytes;
+    L.flags_off = 2 * L.buf_bytes;
+    L.flags_bytes = align_up(plane * sizeof(uint16_t), kAlign);
+    L.part_off = L.flags_off + L.flags_bytes;
+    L.res_off = L.part_off + align_up(4 * sizeof(double) * (size_t)lbm::max_reduce_blocks(), kAlign);
+    L.total = L.res_off + kAlign;
+    return true;
+}
+
+Model make_model(const lbm_params *p) {
+    Model m;
+    m.tau = (float)p->tau;
+    m.omega = (float)(1.0 / p->tau);
+    m.rho0 = (float)p->rho0;
+    m.inv_rho0 = (float)(1.0 / p->rho0);
+    m.rho_off = p->storage == LBM_F32 ? 0.f : (float)p->rho0;
+    m.ga = (float)p->g_axis;
+    m.gd = (float)p->g_diag;
+    m.wa = (float)p->w_axis;
+    m.wd = (float)p->w_diag;
+    m.rho_c = (float)p->rho_c;
+    m.f_elec = (float)p->f_elec;
+    m.gx = (float)p->accel_x;
+    m.gy = (float)p->accel_y;
+    return m;
+}
+
+// Flag words (see lbm_geometry in lbm.h).  The electric layer is the set of
+// fluid nodes whose Chebyshev distance to a solid node is <= elec_layers, on
+// the half of the domain next to an electrode wall; the Chebyshev ball is a
+// square, so the test is a separable max-filter along x then along y.
+void derive_flags(const lbm_params *p, const uint8_t *solid, std::vector<uint16_t> &out) {
+    const int nx = p->nx, ny = p->ny;
+    const int k = p->elec_layers;
+    auto S = [&](int x, int y) -> int {
+        x %= nx; if (x < 0) x += nx;
+        y %= ny; if (y < 0) y += ny;
+        return solid[(size_t)y * nx + x] ? 1 : 0;
+    };
+    std::vector<uint8_t> near((size_t)nx * ny, 0);
+    if (k > 0) {
+        std::vector<uint8_t> rowmax((size_t)nx * ny, 0);
+        const int kx = std::min(k, nx), ky = std::min(k, ny);
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                uint8_t v = 0;
+                for (int d = -kx; d <= kx && !v; ++d) v = (uint8_t)S(x + d, y);
+                rowmax[(size_t)y * nx + x] = v;
+            }
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                uint8_t v = 0;
+                for (int d = -ky; d <= ky && !v; ++d) {
+                    int yy = (y + d) % ny; if (yy < 0) yy += ny;
+                    v = rowmax[(size_t)yy * nx + x];
+                }
+                near[(size_t)y * nx + x] = v;
+            }
+    }
+    // e_1..e_8
+    static const int ex[8] = {1, 0, -1, 0, 1, -1, -1, 1};
+    static const int ey[8] = {0, 1, 0, -1, 1, 1, -1, -1};
+    out.assign((size_t)nx * ny, 0);
+    for (int y = 0; y < ny; ++y) {
+        const bool top = y >= ny / 2;
+        const bool electrode = (p->elec_walls & (top ? LBM_ELEC_TOP : LBM_ELEC_BOTTOM)) != 0;
+        for (int x = 0; x < nx; ++x) {
+            const size_t i = (size_t)y * nx + x;
+            if (solid[i]) { out[i] = (uint16_t)lbm::FL_SOLID; continue; }
+            uint32_t v = 0;
+            for (int b = 0; b < 8; ++b)
+                if (S(x + ex[b], y + ey[b])) v |= 1u << b;
+            if (electrode && near[i]) v |= lbm::FL_LAYER;
+            if (top) v |= lbm::FL_TOP;
+            out[i] = (uint16_t)v;
+        }
+    }
+}
+
+lbm_status fail(lbm_sim *s, lbm_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (s) {
+        s->err = buf;
+        if (st != LBM_EINVAL) s->sticky = st;
+    } else {
+        g_init_error = buf;
+    }
+    return st;
+}
+
+#define HIP_TRY(sim, expr)                                                                      \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail((sim), LBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess || prev == dev || hipSetDevice(dev) != hipSuccess) prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+lbm_status usable(lbm_sim *s) {
+    if (!s) return LBM_EINVAL;
+    if (s->sticky != LBM_OK) return LBM_ESTATE;
+    return LBM_OK;
+}
+
+lbm_status do_flux(lbm_sim *s, double *Q, double *M) {
+    HIP_TRY(s, lbm::launch_reduce(s->p.storage, s->buf[s->cur], s->flags, s->g, s->m.rho_off,
+                                  s->partials, s->result, s->stream));
+    double host[3];
+    HIP_TRY(s, hipMemcpyAsync(host, s->result, sizeof host, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    if (Q) *Q = host[0];
+    if (M) *M = host[1];
+    if (host[2] != 0.0)
+        return fail(s, LBM_EDIVERGED, "%.0f fluid nodes have a density <= 0 or not finite after %lld steps",
+                    host[2], (long long)s->steps);
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_params *p) {
+    Layout L;
+    return make_layout(p, L) ? L.total : 0;
+}
+
+lbm_status lbm_init(lbm_sim **out, const lbm_params *p, const uint8_t *solid, const double *rho_init,
+                    const double *ux_init, const double *uy_init, void *dev_ws, size_t ws_bytes,
+                    void *stream) {
+    if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    const std::string why = check_params(p);
+    if (!why.empty()) return fail(nullptr, LBM_EINVAL, "%s", why.c_str());
+    if (!solid || !rho_init) return fail(nullptr, LBM_EINVAL, "solid and rho_init must not be NULL");
+    Layout L;
+    if (!make_layout(p, L))
+        return fail(nullptr, LBM_EINVAL, "lattice %dx%d too large for one population buffer", p->nx, p->ny);
+    if (!dev_ws) return fail(nullptr, LBM_EINVAL, "workspace is NULL");
+    if ((uintptr_t)dev_ws % kAlign) return fail(nullptr, LBM_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total)
+        return fail(nullptr, LBM_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
+    const size_t n = (size_t)p->nx * p->ny;
+    size_t nfluid = 0;
+    for (size_t i = 0; i < n; ++i) {
+        if (solid[i]) continue;
+        ++nfluid;
+        const double r = rho_init[i];
+        const double u = ux_init ? ux_init[i] : 0.0, v = uy_init ? uy_init[i] : 0.0;
+        if (!(r > 0.0) || !std::isfinite(r) || !std::isfinite(u) || !std::isfinite(v))
+            return fail(nullptr, LBM_EINVAL, "initial density must be > 0 and finite on fluid nodes (node %zu)", i);
+    }
+    if (nfluid == 0) return fail(nullptr, LBM_EINVAL, "the mask has no fluid node");
+
+    lbm_sim *s = new lbm_sim();
+    s->p = *p;
+    s->g = L.g;
+    s->m = make_model(p);
+    s->stream = (hipStream_t)stream;
+    if (hipGetDevice(&s->device) != hipSuccess ||
+        hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess) {
+        delete s;
+        return fail(nullptr, LBM_EDEVICE, "cannot query the current HIP device");
+    }
+    char *ws = (char *)dev_ws;
+    s->buf[0] = ws + L.buf_off[0];
+    s->buf[1] = ws + L.buf_off[1];
+    s->buf_bytes = L.buf_bytes;
+    s->flags = (uint16_t *)(ws + L.flags_off);
+    s->partials = (double *)(ws + L.part_off);
+    s->result = (double *)(ws + L.res_off);
+
+    // flags, padded to the row pitch
+    std::vector<uint16_t> fl;
+    derive_flags(p, solid, fl);
+    std::vector<uint16_t> padded((size_t)L.g.plane, (uint16_t)lbm::FL_SOLID);
+    for (int y = 0; y < p->ny; ++y)
+        std::memcpy(&padded[(size_t)y * L.g.pitch], &fl[(size_t)y * p->nx], sizeof(uint16_t) * p->nx);
+    // initial fields as float32 [3][ny][nx]
+    std::vector<float> stage(3 * n);
+    for (size_t i = 0; i < n; ++i) {
+        stage[i] = solid[i] ? 0.f : (float)rho_init[i];
+        stage[n + i] = (solid[i] || !ux_init) ? 0.f : (float)ux_init[i];
+        stage[2 * n + i] = (solid[i] || !uy_init) ? 0.f : (float)uy_init[i];
+    }
+    auto cleanup = [&](lbm_status st) {
+        g_init_error = s->err;
+        delete s;
+        return st;
+    };
+    lbm_status st;
+#define INIT_TRY(expr)                                                               \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess) {                                                      \
+            st = fail(s, LBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+            return cleanup(st);                                                      \
+        }                                                                            \
+    } while (0)
+    INIT_TRY(hipMemcpyAsync(s->flags, padded.data(), padded.size() * sizeof(uint16_t),
+                            hipMemcpyHostToDevice, s->stream));
+    INIT_TRY(lbm::launch_fill(s->buf[0], s->buf_bytes, s->stream));
+    float *dstage = (float *)s->buf[1];
+    INIT_TRY(hipMemcpyAsync(dstage, stage.data(), stage.size() * sizeof(float), hipMemcpyHostToDevice,
+                            s->stream));
+    INIT_TRY(lbm::launch_init(p->storage, s->buf[0], s->flags, s->g, s->m.rho0, dstage, dstage + n,
+                              dstage + 2 * n, p->nx, s->stream));
+    INIT_TRY(lbm::launch_fill(s->buf[1], s->buf_bytes, s->stream));
+    INIT_TRY(hipStreamSynchronize(s->stream));
+#undef INIT_TRY
+    s->cur = 0;
+    s->steps = 0;
+    *out = s;
+    return LBM_OK;
+}
+
+lbm_status lbm_init_device(lbm_sim *s, const float *rho, const float *ux, const float *uy) {
+    lbm_status st = usable(s);
+    if (st) return st;
+    if (!rho) return fail(s, LBM_EINVAL, "rho must not be NULL");
+    DeviceGuard dg(s->device);
+    HIP_TRY(s, lbm::launch_fill(s->buf[s->cur], s->buf_bytes, s->stream));
+    HIP_TRY(s, lbm::launch_init(s->p.storage, s->buf[s->cur], s->flags, s->g, s->m.rho0, rho, ux, uy,
+                                s->p.nx, s->stream));
+    return LBM_OK;
+}
+
+namespace {
+// Launch arguments of the step kernel for the handle's current tile.
+lbm::StepArgs step_args(lbm_sim *s) {
+    if (s->chunks == 0) {
+        const int strips = (s->p.nx + s->block_x - 1) / s->block_x;
+        int chunks;
+        if (s->rows > 0) {
+            chunks = (s->p.ny + s->rows - 1) / s->rows;
+        } else {
+            // one wave of resident workgroups, chunks of at least 8 rows
+            const int cap = s->cus * lbm::step_blocks_per_cu(s->p.storage, s->block_x);
+            chunks = std::max(1, cap / strips);
+            chunks = std::min(chunks, std::max(1, s->p.ny / 8));
+        }
+        s->chunks = std::max(1, std::min(chunks, s->p.ny));
+    }
+    lbm::StepArgs a;
+    a.flags = s->flags;
+    a.g = s->g;
+    a.m = s->m;
+    a.chunks = s->chunks;
+    a.ntiles = ((s->p.nx + s->block_x - 1) / s->block_x) * s->chunks;
+    a.tiles_per_xcd = (a.ntiles + 7) / 8;
+    a.src = s->buf[s->cur];
+    a.dst = s->buf[s->cur ^ 1];
+    return a;
+}
+}  // namespace
+
+lbm_status lbm_step(lbm_sim *s, int64_t nsteps) {
+    lbm_status st = usable(s);
+    if (st) return st;
+    if (nsteps < 0) return fail(s, LBM_EINVAL, "nsteps must be >= 0");
+    DeviceGuard dg(s->device);
+    lbm::StepArgs a = step_args(s);
+    for (int64_t k = 0; k < nsteps; ++k) {
+        a.src = s->buf[s->cur];
+        a.dst = s->buf[s->cur ^ 1];
+        HIP_TRY(s, lbm::launch_step(s->p.storage, a, s->block_x, s->stream));
+        s->cur ^= 1;
+        ++s->steps;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_sim *s, float *rho, float *ux, float *uy, int on_device) {
+    lbm_status st = usable(s);
+    if (st) return st;
+    DeviceGuard dg(s->device);
+    const size_t n = (size_t)s->p.nx * s->p.ny;
+    if (on_device) {
+        HIP_TRY(s, lbm::launch_moments(s->p.storage, s->buf[s->cur], s->flags, s->g, s->m.rho_off, rho, ux,
+                                       uy, s->stream));
+        return LBM_OK;
+    }
+    // stage in the spare population buffer, then copy out
+    float *d = (float *)s->buf[s->cur ^ 1];
+    HIP_TRY(s, lbm::launch_moments(s->p.storage, s->buf[s->cur], s->flags, s->g, s->m.rho_off,
+                                   rho ? d : nullptr, ux ? d + n : nullptr, uy ? d + 2 * n : nullptr,
+                                   s->stream));
+    if (rho) HIP_TRY(s, hipMemcpyAsync(rho, d, n * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    if (ux) HIP_TRY(s, hipMemcpyAsync(ux, d + n, n * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    if (uy) HIP_TRY(s, hipMemcpyAsync(uy, d + 2 * n, n * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_flux(lbm_sim *s, double *Q, double *M) {
+    lbm_status st = usable(s);
+    if (st) return st;
+    DeviceGuard dg(s->device);
+    return do_flux(s, Q, M);
+}
+
+lbm_status lbm_geometry(lbm_sim *s, uint16_t *flags) {
+    lbm_status st = usable(s);
+    if (st) return st;
+    if (!flags) return fail(s, LBM_EINVAL, "flags must not be NULL");
+    DeviceGuard dg(s->device);
+    HIP_TRY(s, hipMemcpy2DAsync(flags, (size_t)s->p.nx * sizeof(uint16_t), s->flags,
+                                (size_t)s->g.pitch * sizeof(uint16_t), (size_t)s->p.nx * sizeof(uint16_t),
+                                (size_t)s->p.ny, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_set_forces(lbm_sim *s, double f_elec, double accel_x, double accel_y) {
+    lbm_status st = usable(s);
+    if (st) return st;
+    if (!std::isfinite(f_elec) || !std::isfinite(accel_x) || !std::isfinite(accel_y))
+        return fail(s, LBM_EINVAL, "forces must be finite");
+    s->p.f_elec = f_elec;
+    s->p.accel_x = accel_x;
+    s->p.accel_y = accel_y;
+    s->m = make_model(&s->p);
+    return LBM_OK;
+}
+
+lbm_status lbm_set_tile(lbm_sim *s, int32_t block_x, int32_t rows) {
+    lbm_status st = usable(s);
+    if (st) return st;
+    if (block_x != 64 && block_x != 128 && block_x != 256 && block_x != 512)
+        return fail(s, LBM_EINVAL, "block_x must be 64, 128, 256 or 512");
+    if (rows < 0) return fail(s, LBM_EINVAL, "rows_per_block must be >= 0");
+    s->block_x = block_x;
+    s->rows = rows;
+    s->chunks = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *rows, float *us_per_step) {
+    lbm_status st = usable(s);
+    if (st) return st;
+    if (reps < 1) return fail(s, LBM_EINVAL, "reps must be >= 1");
+    DeviceGuard dg(s->device);
+    static const int kBX[] = {64, 128, 256, 512};
+    static const int kRows[] = {0, 32, 64, 128};
+    hipEvent_t e0, e1;
+    HIP_TRY(s, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(s, LBM_EDEVICE, "hipEventCreate failed");
+    }
+    const int keep_bx = s->block_x, keep_rows = s->rows;
+    float best = 0.f;
+    int best_bx = keep_bx, best_rows = keep_rows;
+    lbm_status res = LBM_OK;
+    for (int bx : kBX) {
+        for (int r : kRows) {
+            if (r > 0 && r >= s->p.ny) continue;
+            s->block_x = bx;
+            s->rows = r;
+            s->chunks = 0;
+            // trial launches read the current buffer and write the spare one,
+            // so the state is left as it was
+            lbm::StepArgs a = step_args(s);
+            hipError_t e = lbm::launch_step(s->p.storage, a, bx, s->stream);
+            if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
+            for (int k = 0; k < reps && e == hipSuccess; ++k) e = lbm::launch_step(s->p.storage, a, bx, s->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                res = fail(s, LBM_EDEVICE, "autotune trial %dx%d failed: %s", bx, r, hipGetErrorString(e));
+                break;
+            }
+            const float us = 1000.f * ms / (float)reps;
+            if (best == 0.f || us < best) {
+                best = us;
+                best_bx = bx;
+                best_rows = r;
+            }
+        }
+        if (res != LBM_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (res != LBM_OK) return res;
+    s->block_x = best_bx;
+    s->rows = best_rows;
+    s->chunks = 0;
+    if (block_x) *block_x = best_bx;
+    if (rows) *rows = best_rows;
+    if (us_per_step) *us_per_step = best;
+    return LBM_OK;
+}
+
+size_t lbm_state_bytes(const lbm_sim *s) {
+    if (!s) return 0;
+    return 2 * sizeof(uint64_t) + (size_t)9 * s->g.plane * elem_size(s->p.storage);
+}
+
+lbm_status lbm_save_state(lbm_sim *s, void *host, size_t bytes) {
+    lbm_status st = usable(s);
+    if (st) return st;
+    if (!host || bytes < lbm_state_bytes(s)) return fail(s, LBM_EINVAL, "host buffer too small");
+    DeviceGuard dg(s->device);
+    uint64_t hdr[2] = {kStateMagic, (uint64_t)s->steps};
+    std::memcpy(host, hdr, sizeof hdr);
+    HIP_TRY(s, hipMemcpyAsync((char *)host + sizeof hdr, s->buf[s->cur], lbm_state_bytes(s) - sizeof hdr,
+                              hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_load_state(lbm_sim *s, const void *host, size_t bytes) {
+    lbm_status st = usable(s);
+    if (st) return st;
+    if (!host || bytes < lbm_state_bytes(s)) return fail(s, LBM_EINVAL, "host buffer too small");
+    uint64_t hdr[2];
+    std::memcpy(hdr, host, sizeof hdr);
+    if (hdr[0] != kStateMagic) return fail(s, LBM_EINVAL, "not an lbm state buffer");
+    DeviceGuard dg(s->device);
+    HIP_TRY(s, hipMemcpyAsync(s->buf[s->cur], (const char *)host + sizeof hdr, lbm_state_bytes(s) - sizeof hdr,
+                              hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    s->steps = (int64_t)hdr[1];
+    return LBM_OK;
+}
+
+int64_t lbm_steps_done(const lbm_sim *s) { return s ? s->steps : -1; }
+
+void lbm_free(lbm_sim *s) { delete s; }
+
+const char *lbm_last_error(const lbm_sim *s) {
+    if (!s) return g_init_error.c_str();
+    return s->err.c_str();
+}
+
+const char *lbm_status_string(int st) {
+    switch (st) {
+    case LBM_OK: return "LBM_OK";
+    case LBM_EINVAL: return "LBM_EINVAL";
+    case LBM_ENOMEM: return "LBM_ENOMEM";
+    case LBM_EDEVICE: return "LBM_EDEVICE";
+    case LBM_EDIVERGED: return "LBM_EDIVERGED";
+    case LBM_ESTATE: return "LBM_ESTATE";
+    default: return "unknown lbm_status";
+    }
+}
+
+}  // extern "C"

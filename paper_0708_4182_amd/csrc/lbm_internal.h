@@ -1,0 +1,63 @@
+// Internal interface between the host library (lbm_api.hip) and the kernels
+// (lbm_kernels.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Flag word of a node (the format lbm_geometry exports).
+constexpr uint32_t FL_SOLID = 0x100u;  // S(x) = 1
+constexpr uint32_t FL_LAYER = 0x200u;  // electric layer
+constexpr uint32_t FL_TOP = 0x400u;    // top electrode side, n = (0, +1)
+
+// Geometry of the device arrays: planes [9][ny][pitch], flags [ny][pitch].
+struct Grid {
+    int32_t nx, ny;
+    int32_t pitch;     // row pitch in elements (multiple of 64)
+    uint32_t plane;    // elements per plane = ny * pitch
+};
+
+// Model constants in FP32 as the kernels use them.
+struct Model {
+    float tau, omega;          // omega = 1 / tau
+    float rho0, inv_rho0;
+    float rho_off;             // 0 for FP32 storage, rho0 for deviation storage
+    float ga, gd, wa, wd;      // G_a and W_a per direction class
+    float rho_c, f_elec;
+    float gx, gy;              // driving acceleration
+};
+
+struct StepArgs {
+    const void *src;
+    void *dst;
+    const uint16_t *flags;
+    Grid g;
+    Model m;
+    // Tiling: the lattice is cut into strips of block_x columns, each strip
+    // into `chunks` chunks of consecutive rows (sizes differ by at most one);
+    // tile t = strip * chunks + chunk.  Workgroup b runs tile
+    // (b mod 8) * tiles_per_xcd + b / 8, so an XCD gets consecutive tiles.
+    int32_t chunks;
+    int32_t ntiles;
+    int32_t tiles_per_xcd;
+};
+
+// Launchers; each returns the hipError_t of its launch.
+hipError_t launch_step(int storage, const StepArgs &a, int block_x, hipStream_t s);
+// Resident workgroups of the step kernel per compute unit.
+int step_blocks_per_cu(int storage, int block_x);
+hipError_t launch_init(int storage, void *dst, const uint16_t *flags, const Grid &g, float rho0,
+                       const float *rho, const float *ux, const float *uy, int dense_pitch,
+                       hipStream_t s);
+hipError_t launch_fill(void *dst, size_t bytes, hipStream_t s);
+hipError_t launch_moments(int storage, const void *src, const uint16_t *flags, const Grid &g,
+                          float rho_off, float *rho, float *ux, float *uy, hipStream_t s);
+// FP64 reduction: out[0] = sum u_x, out[1] = sum rho, out[2] = number of bad
+// nodes; partials must hold 4 * max_reduce_blocks() doubles.
+int max_reduce_blocks();
+hipError_t launch_reduce(int storage, const void *src, const uint16_t *flags, const Grid &g,
+                         float rho_off, double *partials, double *out, hipStream_t s);
+
+}  // namespace lbm

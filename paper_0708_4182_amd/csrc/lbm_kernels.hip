@@ -1,0 +1,636 @@
+// HIP kernels of the EWOD Shan-Chen D2Q9 lattice Boltzmann step for gfx950.
+//
+// Data layout: populations in structure-of-arrays planes [9][ny][pitch] (x
+// fastest, pitch a multiple of 64 elements), double-buffered.  A buffer holds
+// the post-collision populations f* of the last step; a step pulls
+// f_a(x) = f*_a(x - e_a) (or the bounce-back f*_opp(a)(x) when x - e_a is solid),
+// which is the streaming half of eq. (1), then collides.
+//
+// Velocity numbering (as in the paper): e_0 = (0,0); e_1..e_4 = (1,0), (0,1),
+// (-1,0), (0,-1); e_5..e_8 = (1,1), (-1,1), (-1,-1), (1,-1).
+#include "lbm_internal.h"
+
+namespace lbm {
+namespace {
+
+enum { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
+
+// Storage codecs.  FP32 stores f itself; FP16/BF16 store d = f - w_a rho0,
+// rounded to nearest even by the hardware conversion.
+template <int S> struct Codec;
+template <> struct Codec<ST_F32> {
+    using T = float;
+    __device__ static float dec(T v) { return v; }
+    __device__ static T enc(float v) { return v; }
+};
+template <> struct Codec<ST_F16> {
+    using T = _Float16;
+    __device__ static float dec(T v) { return (float)v; }
+    __device__ static T enc(float v) { return (_Float16)v; }
+};
+template <> struct Codec<ST_BF16> {
+    using T = __bf16;
+    __device__ static float dec(T v) { return (float)v; }
+    __device__ static T enc(float v) { return (__bf16)v; }
+};
+
+constexpr float W1 = 1.f / 9.f, W5 = 1.f / 36.f;
+
+// Element access by 32-bit element offset from the buffer base; the offsets
+// of one buffer stay below 2^32 bytes (checked by the host), so the address
+// is base + zero-extended byte offset.
+template <class T>
+__device__ __forceinline__ T ld(const T *__restrict__ base, uint32_t off) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void st(T *__restrict__ base, uint32_t off, T v) {
+#ifdef LBM_NT_STORES
+    __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off * (uint32_t)sizeof(T)));
+#else
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off * (uint32_t)sizeof(T)) = v;
+#endif
+}
+
+// Buffer-resource access (raw buffer instructions): per-lane byte offset in a
+// VGPR plus a wave-uniform byte offset in an SGPR.  The resource covers the
+// whole buffer (< 4 GiB, checked by the host); reads outside it return 0.
+constexpr int kBufWord3 = 0x00020000;   // gfx9-family raw buffer, 32-bit data
+constexpr int kStoreNT = 2;             // non-temporal store (streamed output)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, kBufWord3);
+}
+template <class T> __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <> __device__ __forceinline__ _Float16 bload<_Float16>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0));
+}
+template <> __device__ __forceinline__ __bf16 bload<__bf16>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ uint32_t bload_flag(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, kStoreNT);
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, _Float16 v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)voff, (int)soff, kStoreNT);
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, __bf16 v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)voff, (int)soff, kStoreNT);
+}
+
+// Source offsets of the nine populations of node x under streaming with
+// halfway bounce-back (pull form).  fl holds the neighbour solid bits of x:
+// bit (b-1) = S(x + e_b).  Population a comes from x - e_a = x + e_opp(a); if
+// that node is solid it is the post-collision population opp(a) of x itself.
+// rm/r0/rp: element offsets of rows y-1, y, y+1; xm/x/xp: columns x-1, x, x+1
+// (periodic).
+__device__ __forceinline__ void pull_offsets(uint32_t fl, uint32_t plane, uint32_t rm, uint32_t r0,
+                                             uint32_t rp, uint32_t xm, uint32_t x, uint32_t xp,
+                                             uint32_t o[9]) {
+    const uint32_t own = r0 + x;
+    o[0] = own;
+    o[1] = (fl & 0x04u) ? 3u * plane + own : 1u * plane + r0 + xm;   // from x-1     (e_3 side)
+    o[2] = (fl & 0x08u) ? 4u * plane + own : 2u * plane + rm + x;    // from y-1     (e_4 side)
+    o[3] = (fl & 0x01u) ? 1u * plane + own : 3u * plane + r0 + xp;   // from x+1     (e_1 side)
+    o[4] = (fl & 0x02u) ? 2u * plane + own : 4u * plane + rp + x;    // from y+1     (e_2 side)
+    o[5] = (fl & 0x40u) ? 7u * plane + own : 5u * plane + rm + xm;   // from (-1,-1) (e_7 side)
+    o[6] = (fl & 0x80u) ? 8u * plane + own : 6u * plane + rm + xp;   // from (+1,-1) (e_8 side)
+    o[7] = (fl & 0x10u) ? 5u * plane + own : 7u * plane + rp + xp;   // from (+1,+1) (e_5 side)
+    o[8] = (fl & 0x20u) ? 6u * plane + own : 8u * plane + rp + xm;   // from (-1,+1) (e_6 side)
+}
+
+template <class C>
+__device__ __forceinline__ void pull9(const typename C::T *__restrict__ src, uint32_t plane,
+                                      uint32_t fl, uint32_t rm, uint32_t r0, uint32_t rp,
+                                      uint32_t xm, uint32_t x, uint32_t xp, float d[9]) {
+    uint32_t o[9];
+    pull_offsets(fl, plane, rm, r0, rp, xm, x, xp, o);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) d[a] = C::dec(ld(src, o[a]));
+}
+
+// eq. (2) on decoded values: s = sum d (= rho - rho_off), j = sum d e.  The
+// rest offsets w_a rho0 of deviation storage sum to rho0 and carry no momentum.
+__device__ __forceinline__ void moments9(const float d[9], float &s, float &jx, float &jy) {
+    s = (((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]))) + d[8];
+    jx = (d[1] - d[3]) + ((d[5] - d[7]) + (d[8] - d[6]));
+    jy = (d[2] - d[4]) + ((d[5] - d[7]) + (d[6] - d[8]));
+}
+
+__device__ __forceinline__ float pseudopotential(const Model &m, float rho) {
+    return m.rho0 * (1.f - expf(-rho * m.inv_rho0));
+}
+
+// f^eq of eq. (3) minus the stored rest offset w_a rho_off, for density rho
+// (= rho_off + s) and momentum (jx, jy) = rho u.  Arranged so that the zeroth
+// and first moments hold up to unbiased rounding even though 1/9 and 1/36 are
+// not representable: the second-order part E of each opposite pair, the rest
+// population as the remainder of the mass s, and the odd parts of the axis
+// pairs as the remainder of the momentum.  In exact arithmetic this is eq. (3).
+// Contraction into FMAs is off here: fusing 4.5 u_x u_x against the separately
+// rounded u^2 breaks the consistency of the rounded second-order terms, and the
+// resulting stress bias accumulates in slow near-wall films (measured: FP32
+// results drift from FP64 by 1.6e-5 over 700 steps with contraction, 1.2e-6
+// without).
+__device__ __forceinline__ void equilibrium(float rho, float s, float jx, float jy, float feq[9]) {
+#pragma clang fp contract(off)
+    const float inv = __builtin_amdgcn_rcpf(rho);
+    const float ux = jx * inv, uy = jy * inv;
+    const float usq = 1.5f * (ux * ux + uy * uy);
+    const float a = ux + uy, b = uy - ux;
+    const float E1 = W1 * (s + rho * (4.5f * ux * ux - usq));
+    const float E2 = W1 * (s + rho * (4.5f * uy * uy - usq));
+    const float E5 = W5 * (s + rho * (4.5f * a * a - usq));
+    const float E6 = W5 * (s + rho * (4.5f * b * b - usq));
+    const float E0 = s - 2.f * ((E1 + E2) + (E5 + E6));
+    const float O5 = (jx + jy) * (1.f / 12.f);
+    const float O6 = (jy - jx) * (1.f / 12.f);
+    const float O1 = 0.5f * jx - (O5 - O6);
+    const float O2 = 0.5f * jy - (O5 + O6);
+    feq[0] = E0;
+    feq[1] = E1 + O1;
+    feq[3] = E1 - O1;
+    feq[2] = E2 + O2;
+    feq[4] = E2 - O2;
+    feq[5] = E5 + O5;
+    feq[7] = E5 - O5;
+    feq[6] = E6 + O6;
+    feq[8] = E6 - O6;
+}
+
+// Force, velocity shift (eq. (10)) and BGK collision (eq. (1)) of one node,
+// then the store of its nine post-collision populations.  phi of the 3x3
+// neighbourhood comes from LDS rows rowm (y-1), row0 (y), rowp (y+1) at
+// column c; solid neighbours hold phi = 0 there, which removes them from
+// eq. (5) as the model requires.
+template <class C>
+__device__ __forceinline__ void collide_store(const Model &m, const float d[9], float s, float jx,
+                                              float jy, uint32_t fl, const float *rowm,
+                                              const float *row0, const float *rowp, int c,
+                                              __amdgpu_buffer_rsrc_t dst, uint32_t plane,
+                                              uint32_t row, uint32_t lane_byte) {
+    const float rho = m.rho_off + s;
+    const float pc = row0[c];
+    const float p1 = row0[c + 1], p3 = row0[c - 1];
+    const float p2 = rowp[c], p4 = rowm[c];
+    const float p5 = rowp[c + 1], p6 = rowp[c - 1], p7 = rowm[c - 1], p8 = rowm[c + 1];
+    // eq. (5)
+    float sx = m.ga * (p1 - p3) + m.gd * ((p5 - p7) + (p8 - p6));
+    float sy = m.ga * (p2 - p4) + m.gd * ((p5 - p7) + (p6 - p8));
+    // eq. (6): S(x + e_b) = bit (b-1) of fl
+    if (fl & 0xFFu) {
+        const float s1 = (float)(fl & 1u), s2 = (float)((fl >> 1) & 1u), s3 = (float)((fl >> 2) & 1u),
+                    s4 = (float)((fl >> 3) & 1u), s5 = (float)((fl >> 4) & 1u), s6 = (float)((fl >> 5) & 1u),
+                    s7 = (float)((fl >> 6) & 1u), s8 = (float)((fl >> 7) & 1u);
+        sx += m.wa * (s1 - s3) + m.wd * ((s5 - s7) + (s8 - s6));
+        sy += m.wa * (s2 - s4) + m.wd * ((s5 - s7) + (s6 - s8));
+    }
+    float Fx = -pc * sx, Fy = -pc * sy;
+    // electric force on the conductive part of the layer, n towards the electrode
+    if ((fl & FL_LAYER) && rho >= m.rho_c) Fy += (fl & FL_TOP) ? m.f_elec : -m.f_elec;
+    // driving body force
+    Fx += rho * m.gx;
+    Fy += rho * m.gy;
+    // eq. (10): rho u' = rho u + tau F
+    float feq[9];
+    equilibrium(rho, s, jx + m.tau * Fx, jy + m.tau * Fy, feq);
+    const float om = m.omega;
+    constexpr uint32_t E = sizeof(typename C::T);
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+        bstore(dst, lane_byte, ((uint32_t)a * plane + row) * E, C::enc(d[a] + om * (feq[a] - d[a])));
+}
+
+// Barrier that orders LDS only; global loads in flight are not waited for.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Per-direction constants for the halo gather.
+__constant__ int8_t kEX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__constant__ int8_t kEY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__constant__ int8_t kOPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+// neighbour bit of x - e_a (= bit of opp(a) - 1); none for the rest population
+__constant__ uint16_t kSRCBIT[9] = {0, 0x04, 0x08, 0x01, 0x02, 0x40, 0x80, 0x10, 0x20};
+
+__device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Fused step.  A workgroup of BX threads owns the columns [x0, x0 + BX) of one
+// strip and marches through the rows [y0, y1) of one chunk, upwards for even
+// chunks and downwards for odd ones (so that two chunks read their shared
+// halo rows at about the same time).  For each pulled row it computes rho and
+// phi (one node per thread) and puts phi in a 4-row LDS ring that carries one
+// halo column on each side; after one barrier it collides the previous row,
+// whose phi neighbourhood is then complete.  The flag word of a row is loaded
+// two rows ahead and its populations one row ahead, with the bounce-back
+// addresses already resolved, so HBM latency overlaps the collision.  The halo
+// columns are gathered by 18 lanes of wave 0 (one population each) and
+// reduced with lane shuffles.  Workgroups map to tiles so that consecutive
+// chunks of a strip run on the same XCD.
+constexpr int RING = 4;
+
+template <int S>
+__global__ void __launch_bounds__(512) k_step(const StepArgs a) {
+    using C = Codec<S>;
+    using T = typename C::T;
+    extern __shared__ float ring[];
+    const int BX = blockDim.x, W = BX + 2;
+    const int tid = threadIdx.x;
+    const int nx = a.g.nx, ny = a.g.ny;
+    const uint32_t pitch = (uint32_t)a.g.pitch, plane = a.g.plane;
+    const Model &m = a.m;
+    constexpr uint32_t E = sizeof(T);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.src, 9u * plane * E);
+    const __amdgpu_buffer_rsrc_t rd = make_rsrc(a.dst, 9u * plane * E);
+    const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.flags, plane * 2u);
+
+    const int tile = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
+    if (tile >= a.ntiles) return;   // uniform for the workgroup, before any barrier
+    const int strip = tile / a.chunks, chunk = tile - strip * a.chunks;
+    const int x0 = strip * BX;
+    const int y0 = (int)(((int64_t)chunk * ny) / a.chunks);
+    const int y1 = (int)(((int64_t)(chunk + 1) * ny) / a.chunks);
+    const bool up = (chunk & 1) == 0;
+    const int nrows = y1 - y0 + 2;      // pulled rows: the chunk plus one halo row per side
+
+    const int nact = min(BX, nx - x0);
+    const bool act = tid < nact;
+    const int x = x0 + (act ? tid : 0);
+    const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+
+    // halo gather lanes: 0..8 left column, 16..24 right column, one population each
+    const int hl = tid & 15;
+    const bool hlane = tid < 32 && hl < 9;
+    const int hx = (tid < 16) ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + nact == nx ? 0 : x0 + nact);
+    const int ha = hlane ? hl : 0;
+    const uint32_t hsx = (uint32_t)wrapi(hx - kEX[ha], nx);
+    const int hdy = -kEY[ha];                    // source row offset
+    const uint32_t hsrcbit = kSRCBIT[ha];
+    const uint32_t hopp = (uint32_t)kOPP[ha];
+
+    auto row_at = [&](int i) {
+        const int r = up ? y0 - 1 + i : y1 - i;
+        return wrapi(r, ny);
+    };
+
+    // pipeline registers
+    uint32_t fl1 = FL_SOLID, fl2 = FL_SOLID, hfl1 = FL_SOLID, hfl2 = FL_SOLID;   // rows i+1, i+2
+    T raw[9];
+    T hraw = C::enc(0.f);
+    float pd[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float ps = 0.f, pjx = 0.f, pjy = 0.f;
+    uint32_t pfl = FL_SOLID;
+    int pyr = 0;
+
+    // Every lane loads (no per-lane branches): inactive lanes use the clamped
+    // column x0, solid nodes have no neighbour bits and read their (wrapped)
+    // neighbours, and lanes of wave 0 outside the halo gather read population 0
+    // of a halo node, so every address is inside the buffer.  Those values are
+    // discarded.
+    // A wave whose columns do not wrap around x and none of whose nodes in the
+    // row has a solid neighbour takes the fast path: byte offsets of columns
+    // x-1, x, x+1 are loop invariants and plane and row go into the scalar
+    // offset, so the nine loads need no address arithmetic.
+    const int wave_x0 = x0 + (tid & ~63);
+    const bool wave_wraps = wave_x0 == 0 || wave_x0 + 64 > nx - 1;
+    const uint32_t v0 = (uint32_t)x * E, vm = xm * E, vp = xp * E;
+    const uint32_t vf = (uint32_t)x * 2u, vhf = (uint32_t)hx * 2u;
+    auto issue_pops = [&](int yr, uint32_t fl, uint32_t hfl) {
+        const int ym = yr == 0 ? ny - 1 : yr - 1, yp = yr == ny - 1 ? 0 : yr + 1;
+        const uint32_t r0 = (uint32_t)yr * pitch, rm = (uint32_t)ym * pitch, rp = (uint32_t)yp * pitch;
+        if (!wave_wraps && __builtin_amdgcn_ballot_w64((fl & 0xFFu) != 0u) == 0) {
+            raw[0] = bload<T>(rs, v0, (0u * plane + r0) * E);
+            raw[1] = bload<T>(rs, vm, (1u * plane + r0) * E);
+            raw[2] = bload<T>(rs, v0, (2u * plane + rm) * E);
+            raw[3] = bload<T>(rs, vp, (3u * plane + r0) * E);
+            raw[4] = bload<T>(rs, v0, (4u * plane + rp) * E);
+            raw[5] = bload<T>(rs, vm, (5u * plane + rm) * E);
+            raw[6] = bload<T>(rs, vp, (6u * plane + rm) * E);
+            raw[7] = bload<T>(rs, vp, (7u * plane + rp) * E);
+            raw[8] = bload<T>(rs, vm, (8u * plane + rp) * E);
+        } else {
+            uint32_t o[9];
+            pull_offsets(fl & 0xFFu, plane, rm, r0, rp, xm, (uint32_t)x, xp, o);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) raw[q] = bload<T>(rs, o[q] * E, 0u);
+        }
+        if (tid < 64) {
+            const uint32_t hrow = hdy < 0 ? rm : (hdy > 0 ? rp : r0);
+            const uint32_t off = (hfl & hsrcbit) ? hopp * plane + r0 + (uint32_t)hx
+                                                 : (uint32_t)ha * plane + hrow + hsx;
+            hraw = bload<T>(rs, off * E, 0u);
+        }
+    };
+    auto issue_flags = [&](int yr, uint32_t &fl, uint32_t &hfl) {
+        const uint32_t r0b = (uint32_t)yr * pitch * 2u;
+        fl = bload_flag(rf, vf, r0b);
+        if (tid < 64) hfl = bload_flag(rf, vhf, r0b);
+    };
+
+    // prologue: flags of rows 0 and 1, populations of row 0
+    {
+        uint32_t f0 = FL_SOLID, h0 = FL_SOLID;
+        issue_flags(row_at(0), f0, h0);
+        issue_flags(row_at(1), fl2, hfl2);
+        issue_pops(row_at(0), f0, h0);
+        fl1 = f0;
+        hfl1 = h0;
+    }
+
+    for (int i = 0; i < nrows; ++i) {
+        const int yr = row_at(i);
+        // take row i from the pipeline and start rows i+1 (populations) and i+2 (flags)
+        const uint32_t cfl = fl1, chfl = hfl1;
+        T craw[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) craw[q] = raw[q];
+        const T chraw = hraw;
+        fl1 = fl2;
+        hfl1 = hfl2;
+        // past the end of the chunk the last row is fetched again (cache hits),
+        // which keeps the pipeline free of branches
+        issue_flags(row_at(min(i + 2, nrows - 1)), fl2, hfl2);
+        issue_pops(row_at(min(i + 1, nrows - 1)), fl1, hfl1);
+
+        float *slot = ring + (i & (RING - 1)) * W;
+        float cd[9], cs = 0.f, cjx = 0.f, cjy = 0.f;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) cd[q] = C::dec(craw[q]);
+        moments9(cd, cs, cjx, cjy);
+        if (act) slot[tid + 1] = (cfl & FL_SOLID) ? 0.f : pseudopotential(m, m.rho_off + cs);
+        if (tid < 64) {
+            // rho of the two halo nodes, summed in the same order as moments9 so
+            // that a column gets bitwise the same phi as a halo or as an own node
+            const float hv = (hlane && !(chfl & FL_SOLID)) ? C::dec(chraw) : 0.f;
+            const int base = tid & ~15;
+            float g[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) g[q] = __shfl(hv, base + q, 64);
+            if (tid == 0 || tid == 16) {
+                const float hs = (((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]))) + g[8];
+                const float phi = (chfl & FL_SOLID) ? 0.f : pseudopotential(m, m.rho_off + hs);
+                slot[tid == 0 ? 0 : nact + 1] = phi;
+            }
+        }
+        lds_barrier();
+        if (i >= 2 && act && !(pfl & FL_SOLID)) {
+            const float *older = ring + ((i - 2) & (RING - 1)) * W;
+            const float *mid = ring + ((i - 1) & (RING - 1)) * W;
+            const float *rowm = up ? older : slot;
+            const float *rowp = up ? slot : older;
+            collide_store<C>(m, pd, ps, pjx, pjy, pfl, rowm, mid, rowp, tid + 1, rd, plane,
+                             (uint32_t)pyr * pitch, v0);
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) pd[q] = cd[q];
+        ps = cs;
+        pjx = cjx;
+        pjy = cjy;
+        pfl = cfl;
+        pyr = yr;
+    }
+}
+
+// Populations at t = 0: f_a = f_a^eq(rho, u) of eq. (3), written where the
+// first pull will find them (the inverse of streaming with bounce-back).
+template <int S>
+__global__ void k_init(typename Codec<S>::T *__restrict__ dst, const uint16_t *__restrict__ flags,
+                       Grid g, const float *__restrict__ rho_in,
+                       const float *__restrict__ ux_in, const float *__restrict__ uy_in,
+                       int dense_pitch, float rho_off) {
+    using C = Codec<S>;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= g.nx) return;
+    const uint32_t pitch = (uint32_t)g.pitch, plane = g.plane;
+    const uint32_t own = (uint32_t)y * pitch + x;
+    const uint32_t fl = flags[own];
+    if (fl & FL_SOLID) return;
+    const int di = y * dense_pitch + x;
+    const float rho = rho_in[di], ux = ux_in ? ux_in[di] : 0.f, uy = uy_in ? uy_in[di] : 0.f;
+    const uint32_t xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+    const uint32_t rm = (uint32_t)(y == 0 ? g.ny - 1 : y - 1) * pitch;
+    const uint32_t r0 = (uint32_t)y * pitch;
+    const uint32_t rp = (uint32_t)(y == g.ny - 1 ? 0 : y + 1) * pitch;
+    float feq[9];
+    equilibrium(rho, rho - rho_off, rho * ux, rho * uy, feq);
+    // target of population a: node x - e_a in plane a, or plane opp(a) of x
+    st(dst, own, C::enc(feq[0]));
+    st(dst, (fl & 0x04u) ? 3u * plane + own : 1u * plane + r0 + xm, C::enc(feq[1]));
+    st(dst, (fl & 0x08u) ? 4u * plane + own : 2u * plane + rm + x, C::enc(feq[2]));
+    st(dst, (fl & 0x01u) ? 1u * plane + own : 3u * plane + r0 + xp, C::enc(feq[3]));
+    st(dst, (fl & 0x02u) ? 2u * plane + own : 4u * plane + rp + x, C::enc(feq[4]));
+    st(dst, (fl & 0x40u) ? 7u * plane + own : 5u * plane + rm + xm, C::enc(feq[5]));
+    st(dst, (fl & 0x80u) ? 8u * plane + own : 6u * plane + rm + xp, C::enc(feq[6]));
+    st(dst, (fl & 0x10u) ? 5u * plane + own : 7u * plane + rp + xp, C::enc(feq[7]));
+    st(dst, (fl & 0x20u) ? 6u * plane + own : 8u * plane + rp + xm, C::enc(feq[8]));
+}
+
+__global__ void k_fill(uint4 *__restrict__ p, size_t n16) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n16; i += stride) p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// eq. (2) moments of the current state into dense float32 [ny][nx] arrays.
+template <int S>
+__global__ void k_moments(const typename Codec<S>::T *__restrict__ src,
+                          const uint16_t *__restrict__ flags, Grid g, float rho_off,
+                          float *__restrict__ rho_out, float *__restrict__ ux_out,
+                          float *__restrict__ uy_out) {
+    using C = Codec<S>;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= g.nx) return;
+    const uint32_t pitch = (uint32_t)g.pitch;
+    const uint32_t r0 = (uint32_t)y * pitch;
+    const uint32_t fl = flags[r0 + x];
+    float rho = 0.f, ux = 0.f, uy = 0.f;
+    if (!(fl & FL_SOLID)) {
+        const uint32_t xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+        const uint32_t rm = (uint32_t)(y == 0 ? g.ny - 1 : y - 1) * pitch;
+        const uint32_t rp = (uint32_t)(y == g.ny - 1 ? 0 : y + 1) * pitch;
+        float d[9], sd, jx, jy;
+        pull9<C>(src, g.plane, fl, rm, r0, rp, xm, (uint32_t)x, xp, d);
+        moments9(d, sd, jx, jy);
+        rho = rho_off + sd;
+        ux = jx / rho;
+        uy = jy / rho;
+    }
+    const size_t o = (size_t)y * g.nx + x;
+    if (rho_out) rho_out[o] = rho;
+    if (ux_out) ux_out[o] = ux;
+    if (uy_out) uy_out[o] = uy;
+}
+
+// FP64 reduction of sum u_x, sum rho and the count of bad densities over the
+// fluid nodes.  Each block walks a fixed, contiguous range of rows, so the
+// partial sums and their final order do not depend on timing.
+constexpr int RED_THREADS = 256;
+constexpr int RED_MAX_BLOCKS = 1024;
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+    return t;
+}
+
+template <int S>
+__global__ void __launch_bounds__(RED_THREADS) k_reduce(const typename Codec<S>::T *__restrict__ src,
+                                                        const uint16_t *__restrict__ flags, Grid g,
+                                                        float rho_off, int rows_per_block,
+                                                        double *__restrict__ partials) {
+    using C = Codec<S>;
+    __shared__ double sh[RED_THREADS / 64];
+    const uint32_t pitch = (uint32_t)g.pitch;
+    double q = 0.0, mass = 0.0, bad = 0.0;
+    const int ya = blockIdx.x * rows_per_block, yb = min(ya + rows_per_block, g.ny);
+    for (int y = ya; y < yb; ++y) {
+        const uint32_t r0 = (uint32_t)y * pitch;
+        const uint32_t rm = (uint32_t)(y == 0 ? g.ny - 1 : y - 1) * pitch;
+        const uint32_t rp = (uint32_t)(y == g.ny - 1 ? 0 : y + 1) * pitch;
+        for (int x = threadIdx.x; x < g.nx; x += blockDim.x) {
+            const uint32_t fl = flags[r0 + x];
+            if (fl & FL_SOLID) continue;
+            const uint32_t xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+            float d[9];
+            pull9<C>(src, g.plane, fl, rm, r0, rp, xm, (uint32_t)x, xp, d);
+            double rho = (double)rho_off, jx = 0.0;
+#pragma unroll
+            for (int a = 0; a < 9; ++a) rho += (double)d[a];
+            jx = ((double)d[1] - (double)d[3]) + (((double)d[5] - (double)d[7]) + ((double)d[8] - (double)d[6]));
+            if (!(rho > 0.0) || !isfinite(rho)) {
+                bad += 1.0;
+                continue;
+            }
+            q += jx / rho;
+            mass += rho;
+        }
+    }
+    const double tq = block_sum(q, sh);
+    const double tm = block_sum(mass, sh);
+    const double tb = block_sum(bad, sh);
+    if (threadIdx.x == 0) {
+        partials[4 * blockIdx.x + 0] = tq;
+        partials[4 * blockIdx.x + 1] = tm;
+        partials[4 * blockIdx.x + 2] = tb;
+        partials[4 * blockIdx.x + 3] = 0.0;
+    }
+}
+
+__global__ void k_reduce_final(const double *__restrict__ partials, int n, double inv_nx,
+                               double *__restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double q = 0.0, mass = 0.0, bad = 0.0;
+    for (int b = 0; b < n; ++b) {
+        q += partials[4 * b + 0];
+        mass += partials[4 * b + 1];
+        bad += partials[4 * b + 2];
+    }
+    out[0] = q * inv_nx;
+    out[1] = mass;
+    out[2] = bad;
+}
+
+}  // namespace
+
+hipError_t launch_step(int storage, const StepArgs &a, int block_x, hipStream_t s) {
+    const unsigned blocks = 8u * (unsigned)a.tiles_per_xcd;
+    const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
+    switch (storage) {
+    case ST_F32: k_step<ST_F32><<<blocks, block_x, lds, s>>>(a); break;
+    case ST_F16: k_step<ST_F16><<<blocks, block_x, lds, s>>>(a); break;
+    case ST_BF16: k_step<ST_BF16><<<blocks, block_x, lds, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int step_blocks_per_cu(int storage, int block_x) {
+    const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (storage) {
+    case ST_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_F32>, block_x, lds); break;
+    case ST_F16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_F16>, block_x, lds); break;
+    case ST_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_BF16>, block_x, lds); break;
+    default: break;
+    }
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+
+hipError_t launch_init(int storage, void *dst, const uint16_t *flags, const Grid &g, float rho0,
+                       const float *rho, const float *ux, const float *uy, int dense_pitch,
+                       hipStream_t s) {
+    const dim3 grid((g.nx + 255) / 256, g.ny);
+    const float off = storage == ST_F32 ? 0.f : rho0;
+    switch (storage) {
+    case ST_F32:
+        k_init<ST_F32><<<grid, 256, 0, s>>>((float *)dst, flags, g, rho, ux, uy, dense_pitch, off);
+        break;
+    case ST_F16:
+        k_init<ST_F16><<<grid, 256, 0, s>>>((_Float16 *)dst, flags, g, rho, ux, uy, dense_pitch, off);
+        break;
+    case ST_BF16:
+        k_init<ST_BF16><<<grid, 256, 0, s>>>((__bf16 *)dst, flags, g, rho, ux, uy, dense_pitch, off);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(void *dst, size_t bytes, hipStream_t s) {
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return hipSuccess;
+    const size_t blocks = (n16 + 255) / 256;
+    k_fill<<<(unsigned)(blocks < 8192 ? blocks : 8192), 256, 0, s>>>((uint4 *)dst, n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(int storage, const void *src, const uint16_t *flags, const Grid &g,
+                          float rho_off, float *rho, float *ux, float *uy, hipStream_t s) {
+    const dim3 grid((g.nx + 255) / 256, g.ny);
+    switch (storage) {
+    case ST_F32: k_moments<ST_F32><<<grid, 256, 0, s>>>((const float *)src, flags, g, rho_off, rho, ux, uy); break;
+    case ST_F16: k_moments<ST_F16><<<grid, 256, 0, s>>>((const _Float16 *)src, flags, g, rho_off, rho, ux, uy); break;
+    case ST_BF16: k_moments<ST_BF16><<<grid, 256, 0, s>>>((const __bf16 *)src, flags, g, rho_off, rho, ux, uy); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int max_reduce_blocks() { return RED_MAX_BLOCKS; }
+
+hipError_t launch_reduce(int storage, const void *src, const uint16_t *flags, const Grid &g,
+                         float rho_off, double *partials, double *out, hipStream_t s) {
+    int rows = (g.ny + RED_MAX_BLOCKS - 1) / RED_MAX_BLOCKS;
+    if (rows < 1) rows = 1;
+    const int blocks = (g.ny + rows - 1) / rows;
+    switch (storage) {
+    case ST_F32: k_reduce<ST_F32><<<blocks, RED_THREADS, 0, s>>>((const float *)src, flags, g, rho_off, rows, partials); break;
+    case ST_F16: k_reduce<ST_F16><<<blocks, RED_THREADS, 0, s>>>((const _Float16 *)src, flags, g, rho_off, rows, partials); break;
+    case ST_BF16: k_reduce<ST_BF16><<<blocks, RED_THREADS, 0, s>>>((const __bf16 *)src, flags, g, rho_off, rows, partials); break;
+    default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_reduce_final<<<1, 64, 0, s>>>(partials, blocks, 1.0 / (double)g.nx, out);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,224 @@
+"""ctypes binding of liblbm (include/lbm.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``liblbm.so``.  PyTorch provides the device workspace (through its
+caching allocator) and the HIP stream.  There is no fallback: if the library
+has not been built, or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("LBM_LIB") or os.path.join(HERE, "liblbm.so")
+
+LBM_F32, LBM_F16, LBM_BF16 = 0, 1, 2
+STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
+          -4: "LBM_EDIVERGED", -5: "LBM_ESTATE"}
+
+# Exported symbols of include/lbm.h (checked by the CPU tests).
+SYMBOLS = ("lbm_workspace_bytes", "lbm_init", "lbm_init_device", "lbm_step", "lbm_moments",
+           "lbm_flux", "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_autotune", "lbm_state_bytes",
+           "lbm_save_state", "lbm_load_state", "lbm_steps_done", "lbm_free", "lbm_last_error",
+           "lbm_status_string")
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Diverged(LBMError):
+    pass
+
+
+class lbm_params(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32),
+                ("tau", C.c_double), ("rho0", C.c_double),
+                ("g_axis", C.c_double), ("g_diag", C.c_double),
+                ("w_axis", C.c_double), ("w_diag", C.c_double),
+                ("rho_c", C.c_double), ("f_elec", C.c_double),
+                ("elec_layers", C.c_int32), ("elec_walls", C.c_uint32),
+                ("accel_x", C.c_double), ("accel_y", C.c_double),
+                ("storage", C.c_int32)]
+
+
+def to_c_params(p) -> lbm_params:
+    return lbm_params(int(p.nx), int(p.ny), float(p.tau), float(p.rho0), float(p.g_axis),
+                      float(p.g_diag), float(p.w_axis), float(p.w_diag), float(p.rho_c),
+                      float(p.f_elec), int(p.elec_layers), int(p.elec_walls), float(p.accel_x),
+                      float(p.accel_y), int(getattr(p, "storage", 0)))
+
+
+_lib = None
+
+
+def load_library():
+    """Load liblbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_0708_4182_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    vp, P = C.c_void_p, C.POINTER(lbm_params)
+    dp, fp = C.POINTER(C.c_double), C.POINTER(C.c_float)
+    lib.lbm_workspace_bytes.argtypes = [P]
+    lib.lbm_workspace_bytes.restype = C.c_size_t
+    lib.lbm_init.argtypes = [C.POINTER(vp), P, C.POINTER(C.c_uint8), dp, dp, dp, vp, C.c_size_t, vp]
+    lib.lbm_init_device.argtypes = [vp, vp, vp, vp]
+    lib.lbm_step.argtypes = [vp, C.c_int64]
+    lib.lbm_moments.argtypes = [vp, vp, vp, vp, C.c_int]
+    lib.lbm_flux.argtypes = [vp, dp, dp]
+    lib.lbm_geometry.argtypes = [vp, C.POINTER(C.c_uint16)]
+    lib.lbm_set_forces.argtypes = [vp, C.c_double, C.c_double, C.c_double]
+    lib.lbm_set_tile.argtypes = [vp, C.c_int32, C.c_int32]
+    lib.lbm_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_float)]
+    lib.lbm_state_bytes.argtypes = [vp]
+    lib.lbm_state_bytes.restype = C.c_size_t
+    lib.lbm_save_state.argtypes = [vp, vp, C.c_size_t]
+    lib.lbm_load_state.argtypes = [vp, vp, C.c_size_t]
+    lib.lbm_steps_done.argtypes = [vp]
+    lib.lbm_steps_done.restype = C.c_int64
+    lib.lbm_free.argtypes = [vp]
+    lib.lbm_free.restype = None
+    lib.lbm_last_error.argtypes = [vp]
+    lib.lbm_last_error.restype = C.c_char_p
+    lib.lbm_status_string.argtypes = [C.c_int]
+    lib.lbm_status_string.restype = C.c_char_p
+    for name in ("lbm_init", "lbm_init_device", "lbm_step", "lbm_moments", "lbm_flux",
+                 "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_autotune", "lbm_save_state",
+                 "lbm_load_state"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def workspace_bytes(p) -> int:
+    return int(load_library().lbm_workspace_bytes(C.byref(to_c_params(p))))
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Simulation:
+    """One lattice on one GPU: owns a torch workspace and a liblbm handle."""
+
+    def __init__(self, params, solid, rho, ux=None, uy=None, stream=None, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("liblbm needs a HIP GPU; torch.cuda.is_available() is False")
+        lib = load_library()
+        self.torch = torch
+        self.params = params
+        self.device = torch.device("cuda" if device is None else device)
+        self.nx, self.ny = int(params.nx), int(params.ny)
+        cp = to_c_params(params)
+        self._cp = cp
+        nbytes = int(lib.lbm_workspace_bytes(C.byref(cp)))
+        if nbytes == 0:
+            raise LBMError(-1, "invalid parameters (lbm_workspace_bytes returned 0)")
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream() if stream is None else stream
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            solid = np.ascontiguousarray(solid, np.uint8)
+            rho = np.ascontiguousarray(rho, np.float64)
+            ux = None if ux is None else np.ascontiguousarray(ux, np.float64)
+            uy = None if uy is None else np.ascontiguousarray(uy, np.float64)
+            h = C.c_void_p()
+            st = lib.lbm_init(C.byref(h), C.byref(cp), solid.ctypes.data_as(C.POINTER(C.c_uint8)),
+                              _dptr(rho), None if ux is None else _dptr(ux),
+                              None if uy is None else _dptr(uy), C.c_void_p(self.ws.data_ptr()),
+                              nbytes, C.c_void_p(self.stream.cuda_stream))
+            if st != 0:
+                raise LBMError(st, lib.lbm_last_error(None).decode())
+        self.h = h
+        self.lib = lib
+
+    # ------------------------------------------------------------- helpers
+    def _check(self, st):
+        if st != 0:
+            msg = self.lib.lbm_last_error(self.h).decode()
+            raise (Diverged if st == -4 else LBMError)(st, msg)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.lbm_free(h)
+            self.h = None
+
+    close = __del__
+
+    # ------------------------------------------------------------- calls
+    def step(self, n: int = 1):
+        self._check(self.lib.lbm_step(self.h, int(n)))
+
+    def moments(self):
+        """(rho, ux, uy) as host float32 [ny][nx] numpy arrays (synchronizes)."""
+        out = [np.empty((self.ny, self.nx), np.float32) for _ in range(3)]
+        self._check(self.lib.lbm_moments(self.h, *[C.c_void_p(o.ctypes.data) for o in out], 0))
+        return tuple(out)
+
+    def moments_device(self):
+        """(rho, ux, uy) as float32 torch tensors on the device (asynchronous)."""
+        t = self.torch.empty((3, self.ny, self.nx), dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.lbm_moments(self.h, C.c_void_p(t[0].data_ptr()),
+                                         C.c_void_p(t[1].data_ptr()), C.c_void_p(t[2].data_ptr()), 1))
+        return t
+
+    def flux(self):
+        """(Q, M) of eq. (11) and the fluid mass, FP64 (synchronizes)."""
+        Q, M = C.c_double(), C.c_double()
+        self._check(self.lib.lbm_flux(self.h, C.byref(Q), C.byref(M)))
+        return Q.value, M.value
+
+    def geometry(self) -> np.ndarray:
+        out = np.empty((self.ny, self.nx), np.uint16)
+        self._check(self.lib.lbm_geometry(self.h, out.ctypes.data_as(C.POINTER(C.c_uint16))))
+        return out
+
+    def set_forces(self, f_elec: float, accel_x: float = 0.0, accel_y: float = 0.0):
+        self._check(self.lib.lbm_set_forces(self.h, float(f_elec), float(accel_x), float(accel_y)))
+
+    def set_tile(self, block_x: int, rows: int):
+        self._check(self.lib.lbm_set_tile(self.h, int(block_x), int(rows)))
+
+    def autotune(self, reps: int = 5):
+        """Pick the fastest tile on the device; returns (block_x, rows, us/step)."""
+        bx, rows, us = C.c_int32(), C.c_int32(), C.c_float()
+        self._check(self.lib.lbm_autotune(self.h, int(reps), C.byref(bx), C.byref(rows), C.byref(us)))
+        return bx.value, rows.value, us.value
+
+    def init_device(self, rho, ux=None, uy=None):
+        """Re-initialise from device float32 tensors [ny][nx] (warm start)."""
+        ptr = lambda t: None if t is None else C.c_void_p(t.contiguous().data_ptr())
+        self._keep = (rho, ux, uy)
+        self._check(self.lib.lbm_init_device(self.h, ptr(rho), ptr(ux), ptr(uy)))
+
+    def save_state(self) -> bytes:
+        n = int(self.lib.lbm_state_bytes(self.h))
+        buf = C.create_string_buffer(n)
+        self._check(self.lib.lbm_save_state(self.h, buf, n))
+        return buf.raw
+
+    def load_state(self, data: bytes):
+        buf = C.create_string_buffer(data, len(data))
+        self._check(self.lib.lbm_load_state(self.h, buf, len(data)))
+
+    @property
+    def steps_done(self) -> int:
+        return int(self.lib.lbm_steps_done(self.h))
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+
+def from_case(case, **kw) -> Simulation:
+    """Simulation from an ``inputs.Case``."""
+    return Simulation(case.params, case.solid, case.rho, case.ux, case.uy, **kw)

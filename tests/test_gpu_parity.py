@@ -1,0 +1,260 @@
+"""GPU parity: the HIP library through its C ABI against the FP64 oracle.
+
+Bars (stated, not loosened per case):
+  - flag words (neighbour-solid bits, solid, electric layer, side): bit-exact;
+  - FP32 storage: density and velocity within 1e-5 relative after a fixed
+    number of steps, with err_rho = max|rho_gpu - rho_orc| / max|rho_orc| and
+    err_u = max|u_gpu - u_orc|_2 / max|u_orc|_2 over fluid nodes;
+  - flux Q and mass M (FP64 reductions on the GPU): mass to 1e-6 relative,
+    |dQ| <= 1e-5 * (1/nx) sum|u_x|;
+  - FP16/BF16 deviation storage: errors measured and bounded loosely (the
+    storage rounding, not the kernel, sets them).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_0708_4182_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0708_4182_amd import lbm as L
+    L.load_library()
+    return L
+
+
+def errors(case, rho_g, ux_g, uy_g, f_orc):
+    rho_o, ux_o, uy_o = O.moments(case.params, case.solid, f_orc)
+    fl = case.solid == 0
+    err_rho = np.abs(rho_g - rho_o)[fl].max() / np.abs(rho_o[fl]).max()
+    du = np.hypot(ux_g - ux_o, uy_g - uy_o)[fl].max()
+    umax = np.hypot(ux_o, uy_o)[fl].max()
+    return err_rho, du / umax, umax
+
+
+def run_both(lbm, case, nsteps, tile=None):
+    sim = lbm.from_case(case)
+    if tile:
+        sim.set_tile(*tile)
+    sim.step(nsteps)
+    rho, ux, uy = sim.moments()
+    f = O.run(case, nsteps)
+    return sim, (rho.astype(np.float64), ux.astype(np.float64), uy.astype(np.float64)), f
+
+
+def conductivity_margin(case, nsteps):
+    """Smallest |rho - rho_c| over electric-layer nodes along the oracle's
+    trajectory.  rho >= rho_c switches the electric force on; a node closer to
+    rho_c than the FP32 trajectory error can switch differently on the GPU, so
+    the parity cases are chosen with a margin well above that error."""
+    p, s = case.params, case.solid
+    layer, _ = O.electric_layer(p, s)
+    sel = layer == 1
+    if not sel.any() or p.f_elec == 0:
+        return np.inf
+    f = O.init(p, s, case.rho, case.ux, case.uy)
+    m = np.inf
+    for _ in range(nsteps + 1):
+        r, _, _ = O.moments(p, s, f)
+        m = min(m, float(np.abs(r - p.rho_c)[sel].min()))
+        O.step(p, s, f, 1)
+    return m
+
+
+def tiny_rough(nx, ny, seed, **kw):
+    solid = I.periodic_bumps(nx, ny, 3, 2, 9, seed)
+    return I.channel_case(nx, ny, solid, seed=seed, **kw)
+
+
+CASES = {
+    "droplet128x64": lambda: I.droplet_case(f_elec=1e-3),
+    "rough256x128": lambda: I.rough_channel_case(nx=256, ny=128, f_elec=2e-3, accel=1e-6, seed=5),
+    "ragged37x19": lambda: tiny_rough(37, 19, 1, f_elec=3e-3, accel=1e-5, layers=2),
+    "ragged130x67": lambda: tiny_rough(130, 67, 2, f_elec=1e-3, accel=2e-6),
+    "ragged300x5": lambda: tiny_rough(300, 5, 3, f_elec=1e-3, accel=1e-6, vapor_layer=1),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_flags_bit_exact(lbm, name):
+    c = CASES[name]()
+    sim = lbm.from_case(c)
+    np.testing.assert_array_equal(sim.geometry(), O.flags(c.params, c.solid))
+
+
+def test_flags_bit_exact_large_random_channel(lbm):
+    c = I.random_channel_case(nx=8192, ny=2048, seed=0)
+    sim = lbm.from_case(c)
+    g = sim.geometry()
+    o = O.flags(c.params, c.solid)
+    assert (g != o).sum() == 0
+
+
+def test_init_moments_equal_initial_fields(lbm):
+    c = CASES["ragged130x67"]()
+    rng = np.random.default_rng(0)
+    c.ux = np.where(c.solid == 0, rng.uniform(-0.05, 0.05, c.rho.shape), 0.0)
+    c.uy = np.where(c.solid == 0, rng.uniform(-0.05, 0.05, c.rho.shape), 0.0)
+    sim = lbm.from_case(c)
+    rho, ux, uy = sim.moments()
+    fl = c.solid == 0
+    assert np.abs(rho - c.rho)[fl].max() < 1e-6
+    assert np.abs(ux - c.ux)[fl].max() < 1e-6 and np.abs(uy - c.uy)[fl].max() < 1e-6
+    assert np.all(rho[~fl] == 0)
+
+
+@pytest.mark.parametrize("name,nsteps", [("droplet128x64", 1000), ("rough256x128", 1000),
+                                         ("ragged37x19", 300), ("ragged130x67", 300),
+                                         ("ragged300x5", 300)])
+def test_fp32_parity(lbm, name, nsteps):
+    c = CASES[name]()
+    margin = conductivity_margin(c, nsteps)
+    assert margin > 1e-5, f"case too close to the conductivity threshold ({margin:.1e})"
+    sim, (rho, ux, uy), f = run_both(lbm, c, nsteps)
+    er, eu, umax = errors(c, rho, ux, uy, f)
+    print(f"{name} N={nsteps}: err_rho={er:.2e} err_u={eu:.2e} (max|u|={umax:.2e}, "
+          f"conductivity margin {margin:.1e})")
+    assert er < TOL and eu < TOL
+
+
+def test_flux_and_mass_parity(lbm):
+    c = CASES["rough256x128"]()
+    sim, (rho, ux, uy), f = run_both(lbm, c, 500)
+    Q, M = sim.flux()
+    Qo, Mo = O.flux(c.params, c.solid, f)
+    _, uxo, _ = O.moments(c.params, c.solid, f)
+    scale = np.abs(uxo[c.solid == 0]).sum() / c.params.nx
+    assert abs(M - Mo) / Mo < 1e-6
+    assert abs(Q - Qo) <= TOL * scale
+    # the FP64 reduction is deterministic
+    assert sim.flux() == (Q, M)
+
+
+@pytest.mark.parametrize("tile", [(64, 1), (64, 7), (128, 16), (256, 32), (512, 5), (512, 200)])
+def test_tile_shapes_bitwise_identical(lbm, tile):
+    c = CASES["ragged130x67"]()
+    ref = lbm.from_case(c)
+    ref.step(50)
+    a = ref.moments()
+    sim = lbm.from_case(c)
+    sim.set_tile(*tile)
+    sim.step(50)
+    b = sim.moments()
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_autotune_keeps_state_and_results(lbm):
+    c = CASES["ragged130x67"]()
+    a = lbm.from_case(c)
+    a.step(10)
+    before = a.moments()
+    bx, rows, us = a.autotune(reps=2)
+    assert bx in (64, 128, 256, 512) and rows >= 0 and us > 0
+    assert a.steps_done == 10
+    for x, y in zip(before, a.moments()):
+        np.testing.assert_array_equal(x, y)
+    a.step(20)
+    b = lbm.from_case(c)
+    b.step(30)
+    for x, y in zip(a.moments(), b.moments()):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_full_size_random_channel_parity(lbm):
+    """8192x2048 random-step channel in the benchmark's launch configuration:
+    3 steps of the GPU against 3 steps of the oracle on the whole lattice."""
+    c = I.random_channel_case(nx=8192, ny=2048, seed=0)
+    sim, (rho, ux, uy), f = run_both(lbm, c, 3)
+    er, eu, umax = errors(c, rho, ux, uy, f)
+    print(f"8192x2048 N=3: err_rho={er:.2e} err_u={eu:.2e}")
+    assert er < TOL and eu < TOL
+
+
+def test_checkpoint_resume_is_bitwise(lbm):
+    c = CASES["ragged130x67"]()
+    a = lbm.from_case(c)
+    a.step(40)
+    state = a.save_state()
+    a.step(25)
+    ra = a.moments()
+    b = lbm.from_case(c)
+    b.load_state(state)
+    assert b.steps_done == 40
+    b.step(25)
+    for x, y in zip(ra, b.moments()):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_set_forces_matches_fresh_init(lbm):
+    c = CASES["ragged130x67"]()
+    a = lbm.from_case(c)
+    a.step(30)
+    ra = a.moments()
+    b = lbm.from_case(c.__class__(c.params.replace(f_elec=0.0, accel_x=0.0), c.solid, c.rho))
+    b.set_forces(c.params.f_elec, c.params.accel_x, c.params.accel_y)
+    b.step(30)
+    for x, y in zip(ra, b.moments()):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_init_device_matches_host_init(lbm):
+    import torch
+    c = CASES["droplet128x64"]()
+    a = lbm.from_case(c)
+    a.step(20)
+    ra = a.moments()
+    b = lbm.from_case(c)
+    b.step(7)                                   # some other state first
+    rho = torch.tensor(c.rho.astype(np.float32), device="cuda")
+    b.init_device(rho, None, None)
+    b.step(20)
+    for x, y in zip(ra, b.moments()):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_divergence_is_reported(lbm):
+    """A parameter set the oracle blows up with makes lbm_flux return
+    LBM_EDIVERGED, and the handle then stays in the error state."""
+    n = 32
+    p = I.params_for_G(n, n, -12.0, tau=0.52)
+    solid = np.zeros((n, n), np.uint8)
+    rho = 1.0 + 0.5 * I.noise(7, (n, n), 1.0)
+    case = I.Case(p, solid, rho)
+    with pytest.raises(FloatingPointError):
+        O.run(case, 400)
+    sim = lbm.from_case(case)
+    sim.step(400)
+    with pytest.raises(lbm.Diverged):
+        sim.flux()
+    with pytest.raises(lbm.LBMError):
+        sim.step(1)
+
+
+# Bounds from the error the storage format itself causes: the FP64 oracle with
+# its populations rounded to the same 16-bit deviations after every step gives
+# err_rho = 1.3e-3 (FP16) and 8.8e-2 (BF16) on this case at 300 steps.
+@pytest.mark.parametrize("storage,bound", [(1, 1e-2), (2, 0.15)])
+def test_low_precision_storage_error_is_bounded(lbm, storage, bound):
+    """FP16/BF16 deviation storage against the FP64 oracle (the printed numbers
+    are the statement; the bounds only catch a broken codec)."""
+    c = CASES["rough256x128"]()
+    c.params = c.params.replace(storage=storage)
+    sim = lbm.from_case(c)
+    _, M0 = sim.flux()
+    sim.step(300)
+    rho, ux, uy = (a.astype(np.float64) for a in sim.moments())
+    _, M1 = sim.flux()
+    f = O.run(c, 300)
+    er, eu, umax = errors(c, rho, ux, uy, f)
+    print(f"storage={storage}: err_rho={er:.2e} err_u={eu:.2e} mass drift={(M1 - M0) / M0:.2e}")
+    assert er < bound
+    assert abs(M1 - M0) / M0 < 10 * bound

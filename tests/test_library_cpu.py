@@ -1,0 +1,123 @@
+"""CPU-only checks of the C-ABI library: it loads, exports every entry point the
+header declares, sizes workspaces and rejects invalid parameters before any
+GPU work (so these run without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_0708_4182_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_0708_4182_amd import lbm
+    if not os.path.exists(lbm.LIB_PATH):
+        from paper_0708_4182_amd import build
+        build.build()
+    return lbm.load_library()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("lbm_init", "lbm_step", "lbm_moments", "lbm_flux"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_0708_4182_amd import lbm
+    names = declared_functions()
+    assert set(names) == set(lbm.SYMBOLS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_workspace_bytes(lib):
+    from paper_0708_4182_amd import lbm
+    p = I.Params(nx=130, ny=67)
+    n32 = lbm.workspace_bytes(p)
+    pitch = 192
+    assert n32 >= 2 * 9 * pitch * 67 * 4 + pitch * 67 * 2
+    n16 = lbm.workspace_bytes(p.replace(storage=1))
+    assert n16 >= 2 * 9 * pitch * 67 * 2 and n16 < n32
+    assert lbm.workspace_bytes(p.replace(nx=2)) == 0
+    assert lbm.workspace_bytes(p.replace(tau=0.5)) == 0
+    assert lbm.workspace_bytes(p.replace(storage=7)) == 0
+    assert lbm.workspace_bytes(p.replace(rho0=0.0)) == 0
+    assert lbm.workspace_bytes(p.replace(tau=float("nan"))) == 0
+    # one population buffer must stay below 4 GiB (32-bit offsets)
+    assert lbm.workspace_bytes(I.Params(nx=65536, ny=4096)) == 0
+
+
+@pytest.mark.parametrize("bad", [dict(nx=2), dict(tau=0.4), dict(elec_walls=4),
+                                 dict(elec_layers=-1), dict(storage=3)])
+def test_init_rejects_invalid_params_without_gpu_work(lib, bad):
+    from paper_0708_4182_amd import lbm
+    import numpy as np
+    p = I.Params(nx=16, ny=8).replace(**bad)
+    cp = lbm.to_c_params(p)
+    n = max(p.nx, 1) * p.ny
+    solid = np.zeros(n, np.uint8)
+    rho = np.ones(n)
+    h = C.c_void_p()
+    st = lib.lbm_init(C.byref(h), C.byref(cp), solid.ctypes.data_as(C.POINTER(C.c_uint8)),
+                      rho.ctypes.data_as(C.POINTER(C.c_double)), None, None,
+                      C.c_void_p(256), 1 << 30, None)
+    assert st == -1 and not h.value
+    assert lib.lbm_last_error(None)
+
+
+def test_init_rejects_bad_fields_without_gpu_work(lib):
+    from paper_0708_4182_amd import lbm
+    import numpy as np
+    p = I.Params(nx=16, ny=8)
+    cp = lbm.to_c_params(p)
+    h = C.c_void_p()
+    args = lambda solid, rho: (C.byref(h), C.byref(cp), solid.ctypes.data_as(C.POINTER(C.c_uint8)),
+                               rho.ctypes.data_as(C.POINTER(C.c_double)), None, None,
+                               C.c_void_p(256), 1 << 30, None)
+    rho = np.ones(128)
+    rho[5] = float("nan")
+    assert lib.lbm_init(*args(np.zeros(128, np.uint8), rho)) == -1
+    assert b"density" in lib.lbm_last_error(None)
+    assert lib.lbm_init(*args(np.ones(128, np.uint8), np.ones(128))) == -1
+    assert b"no fluid" in lib.lbm_last_error(None)
+    # misaligned workspace
+    st = lib.lbm_init(C.byref(h), C.byref(cp), np.zeros(128, np.uint8).ctypes.data_as(C.POINTER(C.c_uint8)),
+                      np.ones(128).ctypes.data_as(C.POINTER(C.c_double)), None, None,
+                      C.c_void_p(4096 + 8), 1 << 30, None)
+    assert st == -1
+    # workspace too small
+    st = lib.lbm_init(C.byref(h), C.byref(cp), np.zeros(128, np.uint8).ctypes.data_as(C.POINTER(C.c_uint8)),
+                      np.ones(128).ctypes.data_as(C.POINTER(C.c_double)), None, None,
+                      C.c_void_p(4096), 16, None)
+    assert st == -2
+
+
+def test_null_handle_calls(lib):
+    assert lib.lbm_step(None, 1) == -1
+    assert lib.lbm_flux(None, None, None) == -1
+    assert lib.lbm_steps_done(None) == -1
+    lib.lbm_free(None)
+    assert lib.lbm_status_string(-4) == b"LBM_EDIVERGED"
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The package and the HIP sources never reference the oracle."""
+    pkg = os.path.join(ROOT, "paper_0708_4182_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "lbm_oracle" not in text and "orc_" not in text, f
