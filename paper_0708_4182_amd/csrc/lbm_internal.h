@@ -44,6 +44,29 @@ struct StepArgs {
     int32_t tiles_per_xcd;
 };
 
+// One channel of a batch: its lattice, model and device arrays.
+struct ChannelDesc {
+    Grid g;
+    Model m;
+    int32_t chunks;            // row chunks per strip
+    int32_t pad;
+    const void *buf[2];        // population buffers A and B
+    const uint16_t *flags;
+};
+
+// Persistent batched step: workgroups take tiles from a queue (one counter
+// per step slot, zeroed before use) until the list is exhausted.  A tile is
+// (channel << 16) | (strip * chunks + chunk).
+struct BatchStepArgs {
+    const ChannelDesc *descs;
+    const uint32_t *tiles;
+    uint32_t *counters;
+    int32_t ntiles;
+    int32_t slot;
+    int32_t parity;            // index of the source buffer of every active channel
+    int32_t pad;
+};
+
 // Launchers; each returns the hipError_t of its launch.
 hipError_t launch_step(int storage, const StepArgs &a, int block_x, hipStream_t s);
 // Resident workgroups of the step kernel per compute unit.
@@ -54,6 +77,12 @@ hipError_t launch_init(int storage, void *dst, const uint16_t *flags, const Grid
 hipError_t launch_fill(void *dst, size_t bytes, hipStream_t s);
 hipError_t launch_moments(int storage, const void *src, const uint16_t *flags, const Grid &g,
                           float rho_off, float *rho, float *ux, float *uy, hipStream_t s);
+hipError_t launch_batch_step(int storage, const BatchStepArgs &a, int block_x, int grid, hipStream_t s);
+int batch_blocks_per_cu(int storage, int block_x);
+// Per-channel FP64 reduction of channels ids[0..n): out[4*k] = Q, out[4*k+1] =
+// mass, out[4*k+2] = bad nodes, for the buffer index cur[ids[k]].
+hipError_t launch_batch_reduce(int storage, const ChannelDesc *descs, const int32_t *ids,
+                               const int32_t *cur, int n, double *out, hipStream_t s);
 // FP64 reduction: out[0] = sum u_x, out[1] = sum rho, out[2] = number of bad
 // nodes; partials must hold 4 * max_reduce_blocks() doubles.
 int max_reduce_blocks();

@@ -238,27 +238,19 @@ __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >
 constexpr int RING = 4;
 
 template <int S>
-__global__ void __launch_bounds__(512) k_step(const StepArgs a) {
+__device__ __forceinline__ void step_tile(const void *src_ptr, void *dst_ptr, const uint16_t *flags_ptr,
+                                          const Grid &g, const Model &m, int x0, int y0, int y1, bool up,
+                                          float *ring) {
     using C = Codec<S>;
     using T = typename C::T;
-    extern __shared__ float ring[];
     const int BX = blockDim.x, W = BX + 2;
     const int tid = threadIdx.x;
-    const int nx = a.g.nx, ny = a.g.ny;
-    const uint32_t pitch = (uint32_t)a.g.pitch, plane = a.g.plane;
-    const Model &m = a.m;
+    const int nx = g.nx, ny = g.ny;
+    const uint32_t pitch = (uint32_t)g.pitch, plane = g.plane;
     constexpr uint32_t E = sizeof(T);
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.src, 9u * plane * E);
-    const __amdgpu_buffer_rsrc_t rd = make_rsrc(a.dst, 9u * plane * E);
-    const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.flags, plane * 2u);
-
-    const int tile = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
-    if (tile >= a.ntiles) return;   // uniform for the workgroup, before any barrier
-    const int strip = tile / a.chunks, chunk = tile - strip * a.chunks;
-    const int x0 = strip * BX;
-    const int y0 = (int)(((int64_t)chunk * ny) / a.chunks);
-    const int y1 = (int)(((int64_t)(chunk + 1) * ny) / a.chunks);
-    const bool up = (chunk & 1) == 0;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(src_ptr, 9u * plane * E);
+    const __amdgpu_buffer_rsrc_t rd = make_rsrc(dst_ptr, 9u * plane * E);
+    const __amdgpu_buffer_rsrc_t rf = make_rsrc(flags_ptr, plane * 2u);
     const int nrows = y1 - y0 + 2;      // pulled rows: the chunk plus one halo row per side
 
     const int nact = min(BX, nx - x0);
@@ -399,6 +391,17 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs a) {
     }
 }
 
+template <int S>
+__global__ void __launch_bounds__(512) k_step(const StepArgs a) {
+    extern __shared__ float ring[];
+    const int tile = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
+    if (tile >= a.ntiles) return;   // uniform for the workgroup, before any barrier
+    const int strip = tile / a.chunks, chunk = tile - strip * a.chunks;
+    const int y0 = (int)(((int64_t)chunk * a.g.ny) / a.chunks);
+    const int y1 = (int)(((int64_t)(chunk + 1) * a.g.ny) / a.chunks);
+    step_tile<S>(a.src, a.dst, a.flags, a.g, a.m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring);
+}
+
 // Populations at t = 0: f_a = f_a^eq(rho, u) of eq. (3), written where the
 // first pull will find them (the inverse of streaming with bounce-back).
 template <int S>
@@ -533,18 +536,107 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce(const typename Codec<S>:
     }
 }
 
-__global__ void k_reduce_final(const double *__restrict__ partials, int n, double inv_nx,
-                               double *__restrict__ out) {
-    if (threadIdx.x != 0) return;
+__global__ void __launch_bounds__(64) k_reduce_final(const double *__restrict__ partials, int n,
+                                                     double inv_nx, double *__restrict__ out) {
+    // lane l sums a contiguous slice in order, lane 0 then sums the 64 slices
+    // in order: the same tree for every call
+    __shared__ double part[3][64];
+    const int l = threadIdx.x;
+    const int a = (int)(((int64_t)l * n) / 64), b = (int)(((int64_t)(l + 1) * n) / 64);
     double q = 0.0, mass = 0.0, bad = 0.0;
-    for (int b = 0; b < n; ++b) {
-        q += partials[4 * b + 0];
-        mass += partials[4 * b + 1];
-        bad += partials[4 * b + 2];
+    for (int k = a; k < b; ++k) {
+        q += partials[4 * k + 0];
+        mass += partials[4 * k + 1];
+        bad += partials[4 * k + 2];
     }
-    out[0] = q * inv_nx;
-    out[1] = mass;
-    out[2] = bad;
+    part[0][l] = q;
+    part[1][l] = mass;
+    part[2][l] = bad;
+    __syncthreads();
+    if (l == 0) {
+        q = mass = bad = 0.0;
+        for (int k = 0; k < 64; ++k) {
+            q += part[0][k];
+            mass += part[1][k];
+            bad += part[2][k];
+        }
+        out[0] = q * inv_nx;
+        out[1] = mass;
+        out[2] = bad;
+    }
+}
+
+// Batched step over many lattices in one persistent launch.  Workgroups pull
+// tiles from a queue (one atomic per tile), so uneven channels balance
+// dynamically; every channel uses the same tile code as a single lattice.
+template <int S>
+__global__ void __launch_bounds__(512) k_batch_step(const BatchStepArgs a) {
+    extern __shared__ float ring[];
+    __shared__ int next_tile;
+    for (;;) {
+        if (threadIdx.x == 0) next_tile = (int)atomicAdd(&a.counters[a.slot], 1u);
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(next_tile);
+        __syncthreads();                 // next_tile is rewritten only after all have read it
+        if (t >= a.ntiles) break;
+        const uint32_t packed = a.tiles[t];
+        const ChannelDesc d = a.descs[packed >> 16];
+        const int local = (int)(packed & 0xFFFFu);
+        const int strip = local / d.chunks, chunk = local - strip * d.chunks;
+        const int y0 = (int)(((int64_t)chunk * d.g.ny) / d.chunks);
+        const int y1 = (int)(((int64_t)(chunk + 1) * d.g.ny) / d.chunks);
+        step_tile<S>(d.buf[a.parity], const_cast<void *>(d.buf[a.parity ^ 1]), d.flags, d.g, d.m,
+                     strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring);
+    }
+}
+
+// Per-channel FP64 flux/mass reduction: one workgroup per channel, rows in
+// order, fixed reduction tree (bitwise reproducible).
+template <int S>
+__global__ void __launch_bounds__(256) k_batch_reduce(const ChannelDesc *__restrict__ descs,
+                                                      const int32_t *__restrict__ ids,
+                                                      const int32_t *__restrict__ cur,
+                                                      double *__restrict__ out) {
+    using C = Codec<S>;
+    __shared__ double sh[4];
+    const int id = ids[blockIdx.x];
+    const ChannelDesc d = descs[id];
+    const Grid g = d.g;
+    const typename C::T *src = static_cast<const typename C::T *>(d.buf[cur[id]]);
+    const uint32_t pitch = (uint32_t)g.pitch;
+    double q = 0.0, mass = 0.0, bad = 0.0;
+    for (int y = 0; y < g.ny; ++y) {
+        const uint32_t r0 = (uint32_t)y * pitch;
+        const uint32_t rm = (uint32_t)(y == 0 ? g.ny - 1 : y - 1) * pitch;
+        const uint32_t rp = (uint32_t)(y == g.ny - 1 ? 0 : y + 1) * pitch;
+        for (int x = threadIdx.x; x < g.nx; x += blockDim.x) {
+            const uint32_t fl = d.flags[r0 + x];
+            if (fl & FL_SOLID) continue;
+            const uint32_t xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+            float v[9];
+            pull9<C>(src, g.plane, fl, rm, r0, rp, xm, (uint32_t)x, xp, v);
+            double rho = (double)d.m.rho_off;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) rho += (double)v[k];
+            const double jx = ((double)v[1] - (double)v[3]) +
+                              (((double)v[5] - (double)v[7]) + ((double)v[8] - (double)v[6]));
+            if (!(rho > 0.0) || !isfinite(rho)) {
+                bad += 1.0;
+                continue;
+            }
+            q += jx / rho;
+            mass += rho;
+        }
+    }
+    const double tq = block_sum(q, sh);
+    const double tm = block_sum(mass, sh);
+    const double tb = block_sum(bad, sh);
+    if (threadIdx.x == 0) {
+        out[4 * blockIdx.x + 0] = tq / (double)g.nx;
+        out[4 * blockIdx.x + 1] = tm;
+        out[4 * blockIdx.x + 2] = tb;
+        out[4 * blockIdx.x + 3] = 0.0;
+    }
 }
 
 }  // namespace
@@ -630,6 +722,43 @@ hipError_t launch_reduce(int storage, const void *src, const uint16_t *flags, co
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_reduce_final<<<1, 64, 0, s>>>(partials, blocks, 1.0 / (double)g.nx, out);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_batch_step(int storage, const BatchStepArgs &a, int block_x, int grid, hipStream_t s) {
+    const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
+    switch (storage) {
+    case ST_F32: k_batch_step<ST_F32><<<grid, block_x, lds, s>>>(a); break;
+    case ST_F16: k_batch_step<ST_F16><<<grid, block_x, lds, s>>>(a); break;
+    case ST_BF16: k_batch_step<ST_BF16><<<grid, block_x, lds, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int batch_blocks_per_cu(int storage, int block_x) {
+    const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (storage) {
+    case ST_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_step<ST_F32>, block_x, lds); break;
+    case ST_F16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_step<ST_F16>, block_x, lds); break;
+    case ST_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_step<ST_BF16>, block_x, lds); break;
+    default: break;
+    }
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+
+hipError_t launch_batch_reduce(int storage, const ChannelDesc *descs, const int32_t *ids,
+                               const int32_t *cur, int n, double *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    switch (storage) {
+    case ST_F32: k_batch_reduce<ST_F32><<<n, 256, 0, s>>>(descs, ids, cur, out); break;
+    case ST_F16: k_batch_reduce<ST_F16><<<n, 256, 0, s>>>(descs, ids, cur, out); break;
+    case ST_BF16: k_batch_reduce<ST_BF16><<<n, 256, 0, s>>>(descs, ids, cur, out); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
