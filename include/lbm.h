@@ -148,6 +148,79 @@ size_t lbm_state_bytes(const lbm_sim *sim);
 lbm_status lbm_save_state(lbm_sim *sim, void *host, size_t bytes);
 lbm_status lbm_load_state(lbm_sim *sim, const void *host, size_t bytes);
 
+/* ------------------------------------------------------------------------
+ * Batched engine: n independent lattices ("channels") of uneven sizes, each
+ * with its own parameters and geometry (the paper's sweeps over field
+ * strength, channel width and roughness, Figs. 3, 5-8).  Every time step is
+ * one persistent kernel launch whose workgroups take tiles of all channels
+ * from a queue; K steps can be captured as one hipGraph and replayed.
+ * Conventions as above; all channels share one storage format; all active
+ * channels advance together.  A retired channel keeps its last state and is
+ * no longer stepped.
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_batch lbm_batch;
+
+/* Device workspace for the batch (0 if any parameter set is invalid). */
+size_t lbm_batch_workspace_bytes(int32_t n, const lbm_params *p /* [n] */);
+
+/* Create a batch.  p, solid, rho_init: arrays of n entries (host), channel i
+ * with arrays [ny_i][nx_i] as for lbm_init; ux_init / uy_init may be NULL or
+ * contain NULL entries.  Validation as for lbm_init, per channel, before any
+ * GPU work.  Synchronizes. */
+lbm_status lbm_batch_init(lbm_batch **out, int32_t n, const lbm_params *p, const uint8_t *const *solid,
+                          const double *const *rho_init, const double *const *ux_init,
+                          const double *const *uy_init, void *dev_ws, size_t ws_bytes, void *stream);
+
+/* Advance every active channel by nsteps time steps.  With a graph length K
+ * (lbm_batch_set_graph) the steps run as hipGraph replays of K persistent
+ * launches, the remainder eagerly.  Asynchronous. */
+lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
+
+/* Flux Q_i (eq. (11), L = nx_i) and mass M_i of every channel, FP64, fixed
+ * reduction order.  Synchronizes.  Returns LBM_EDIVERGED (not sticky) if any
+ * channel has a density <= 0 or not finite; its Q_i is NaN. */
+lbm_status lbm_batch_flux(lbm_batch *b, double *Q /* [n] */, double *M /* [n] */);
+
+/* eq. (2) moments of channel i, as lbm_moments. */
+lbm_status lbm_batch_moments(lbm_batch *b, int32_t i, float *rho, float *ux, float *uy, int on_device);
+
+/* Flag words of channel i, as lbm_geometry. */
+lbm_status lbm_batch_geometry(lbm_batch *b, int32_t i, uint16_t *flags);
+
+/* Re-initialise channel i to f^eq(rho, u) from device float32 fields
+ * [ny_i][nx_i] (warm start); its step count restarts at 0.  Asynchronous. */
+lbm_status lbm_batch_init_device(lbm_batch *b, int32_t i, const float *rho, const float *ux, const float *uy);
+
+/* Change the electric force and driving acceleration of channel i. */
+lbm_status lbm_batch_set_forces(lbm_batch *b, int32_t i, double f_elec, double accel_x, double accel_y);
+
+/* Stop stepping the channels with done[i] != 0 (host uint8 [n]); rebuilds the
+ * tile list.  Synchronizes. */
+lbm_status lbm_batch_retire(lbm_batch *b, const uint8_t *done);
+
+/* Tile shape: block_x columns (64..512) by about rows_per_tile rows (>= 8).
+ * Results do not depend on it (bitwise).  Default 256 x 32. */
+lbm_status lbm_batch_set_tile(lbm_batch *b, int32_t block_x, int32_t rows_per_tile);
+
+/* Time steps per captured graph: 0 (eager launches) or an even number up to
+ * 1024.  Default 0. */
+lbm_status lbm_batch_set_graph(lbm_batch *b, int32_t steps_per_graph);
+
+/* Autotuner for the batch tile (block_x x rows in {16, 32, 64}); trial
+ * launches write only the spare buffers, so the state is unchanged. */
+lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *block_x, int32_t *rows_per_tile,
+                              float *us_per_step);
+
+/* Steps taken by channel i (-1 for a bad index). */
+int64_t lbm_batch_steps_done(const lbm_batch *b, int32_t i);
+
+/* Free the handle (not the workspace). */
+void lbm_batch_free(lbm_batch *b);
+
+/* Last error message of the batch (or of the last failed lbm_batch_init if b
+ * is NULL). */
+const char *lbm_batch_last_error(const lbm_batch *b);
+
 /* Time steps taken since lbm_init (or the loaded checkpoint). */
 int64_t lbm_steps_done(const lbm_sim *sim);
 

@@ -225,6 +225,14 @@ lbm_status do_flux(lbm_sim *s, double *Q, double *M) {
 
 }  // namespace
 
+namespace lbm {
+std::string check_params_str(const lbm_params *p) { return check_params(p); }
+Model make_model_of(const lbm_params *p) { return make_model(p); }
+void derive_flags_of(const lbm_params *p, const uint8_t *solid, std::vector<uint16_t> &out) {
+    derive_flags(p, solid, out);
+}
+}  // namespace lbm
+
 extern "C" {
 
 size_t lbm_workspace_bytes(const lbm_params *p) {

@@ -23,7 +23,10 @@ STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
 SYMBOLS = ("lbm_workspace_bytes", "lbm_init", "lbm_init_device", "lbm_step", "lbm_moments",
            "lbm_flux", "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_autotune", "lbm_state_bytes",
            "lbm_save_state", "lbm_load_state", "lbm_steps_done", "lbm_free", "lbm_last_error",
-           "lbm_status_string")
+           "lbm_status_string", "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_step",
+           "lbm_batch_flux", "lbm_batch_moments", "lbm_batch_geometry", "lbm_batch_init_device",
+           "lbm_batch_set_forces", "lbm_batch_retire", "lbm_batch_set_tile", "lbm_batch_set_graph",
+           "lbm_batch_autotune", "lbm_batch_steps_done", "lbm_batch_free", "lbm_batch_last_error")
 
 
 class LBMError(RuntimeError):
@@ -91,6 +94,32 @@ def load_library():
     lib.lbm_last_error.restype = C.c_char_p
     lib.lbm_status_string.argtypes = [C.c_int]
     lib.lbm_status_string.restype = C.c_char_p
+    PP = C.POINTER(C.c_void_p)
+    lib.lbm_batch_workspace_bytes.argtypes = [C.c_int32, P]
+    lib.lbm_batch_workspace_bytes.restype = C.c_size_t
+    lib.lbm_batch_init.argtypes = [C.POINTER(vp), C.c_int32, P, PP, PP, PP, PP, vp, C.c_size_t, vp]
+    lib.lbm_batch_step.argtypes = [vp, C.c_int64]
+    lib.lbm_batch_flux.argtypes = [vp, dp, dp]
+    lib.lbm_batch_moments.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int]
+    lib.lbm_batch_geometry.argtypes = [vp, C.c_int32, C.POINTER(C.c_uint16)]
+    lib.lbm_batch_init_device.argtypes = [vp, C.c_int32, vp, vp, vp]
+    lib.lbm_batch_set_forces.argtypes = [vp, C.c_int32, C.c_double, C.c_double, C.c_double]
+    lib.lbm_batch_retire.argtypes = [vp, C.POINTER(C.c_uint8)]
+    lib.lbm_batch_set_tile.argtypes = [vp, C.c_int32, C.c_int32]
+    lib.lbm_batch_set_graph.argtypes = [vp, C.c_int32]
+    lib.lbm_batch_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_float)]
+    lib.lbm_batch_steps_done.argtypes = [vp, C.c_int32]
+    lib.lbm_batch_steps_done.restype = C.c_int64
+    lib.lbm_batch_free.argtypes = [vp]
+    lib.lbm_batch_free.restype = None
+    lib.lbm_batch_last_error.argtypes = [vp]
+    lib.lbm_batch_last_error.restype = C.c_char_p
+    for name in ("lbm_batch_init", "lbm_batch_step", "lbm_batch_flux", "lbm_batch_moments",
+                 "lbm_batch_geometry", "lbm_batch_init_device", "lbm_batch_set_forces",
+                 "lbm_batch_retire", "lbm_batch_set_tile", "lbm_batch_set_graph",
+                 "lbm_batch_autotune"):
+        getattr(lib, name).restype = C.c_int
     for name in ("lbm_init", "lbm_init_device", "lbm_step", "lbm_moments", "lbm_flux",
                  "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_autotune", "lbm_save_state",
                  "lbm_load_state"):
@@ -222,3 +251,134 @@ class Simulation:
 def from_case(case, **kw) -> Simulation:
     """Simulation from an ``inputs.Case``."""
     return Simulation(case.params, case.solid, case.rho, case.ux, case.uy, **kw)
+
+
+class Batch:
+    """Many channels of uneven sizes on one GPU (lbm_batch_* of the C ABI)."""
+
+    def __init__(self, cases, stream=None, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("liblbm needs a HIP GPU; torch.cuda.is_available() is False")
+        lib = load_library()
+        self.torch = torch
+        self.lib = lib
+        self.n = len(cases)
+        self.shapes = [(int(c.params.ny), int(c.params.nx)) for c in cases]
+        self.params = [c.params for c in cases]
+        self.device = torch.device("cuda" if device is None else device)
+        cps = (lbm_params * self.n)(*[to_c_params(c.params) for c in cases])
+        nbytes = int(lib.lbm_batch_workspace_bytes(self.n, cps))
+        if nbytes == 0:
+            raise LBMError(-1, "invalid batch parameters (lbm_batch_workspace_bytes returned 0)")
+        keep = []
+
+        def ptrs(arrs, dtype):
+            out = (C.c_void_p * self.n)()
+            for i, a in enumerate(arrs):
+                if a is None:
+                    out[i] = None
+                else:
+                    a = np.ascontiguousarray(a, dtype)
+                    keep.append(a)
+                    out[i] = a.ctypes.data
+            return out
+
+        solid = ptrs([c.solid for c in cases], np.uint8)
+        rho = ptrs([c.rho for c in cases], np.float64)
+        ux = ptrs([c.ux for c in cases], np.float64)
+        uy = ptrs([c.uy for c in cases], np.float64)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream() if stream is None else stream
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            h = C.c_void_p()
+            st = lib.lbm_batch_init(C.byref(h), self.n, cps, solid, rho, ux, uy,
+                                    C.c_void_p(self.ws.data_ptr()), nbytes,
+                                    C.c_void_p(self.stream.cuda_stream))
+            if st != 0:
+                raise LBMError(st, lib.lbm_batch_last_error(None).decode())
+        self.h = h
+
+    def _check(self, st):
+        if st != 0:
+            msg = self.lib.lbm_batch_last_error(self.h).decode()
+            raise (Diverged if st == -4 else LBMError)(st, msg)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.lbm_batch_free(h)
+            self.h = None
+
+    close = __del__
+
+    def step(self, n: int = 1):
+        self._check(self.lib.lbm_batch_step(self.h, int(n)))
+
+    def flux(self):
+        """(Q [n], M [n]) float64 numpy arrays; raises Diverged if any channel diverged."""
+        Q = np.zeros(self.n)
+        M = np.zeros(self.n)
+        self._check(self.lib.lbm_batch_flux(self.h, Q.ctypes.data_as(C.POINTER(C.c_double)),
+                                            M.ctypes.data_as(C.POINTER(C.c_double))))
+        return Q, M
+
+    def flux_nocheck(self):
+        """(Q, M, status): like flux() but returns the status instead of raising."""
+        Q = np.zeros(self.n)
+        M = np.zeros(self.n)
+        st = self.lib.lbm_batch_flux(self.h, Q.ctypes.data_as(C.POINTER(C.c_double)),
+                                     M.ctypes.data_as(C.POINTER(C.c_double)))
+        return Q, M, st
+
+    def moments(self, i: int):
+        ny, nx = self.shapes[i]
+        out = [np.empty((ny, nx), np.float32) for _ in range(3)]
+        self._check(self.lib.lbm_batch_moments(self.h, int(i), *[C.c_void_p(o.ctypes.data) for o in out], 0))
+        return tuple(out)
+
+    def moments_device(self, i: int):
+        ny, nx = self.shapes[i]
+        t = self.torch.empty((3, ny, nx), dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.lbm_batch_moments(self.h, int(i), C.c_void_p(t[0].data_ptr()),
+                                               C.c_void_p(t[1].data_ptr()), C.c_void_p(t[2].data_ptr()), 1))
+        return t
+
+    def geometry(self, i: int) -> np.ndarray:
+        ny, nx = self.shapes[i]
+        out = np.empty((ny, nx), np.uint16)
+        self._check(self.lib.lbm_batch_geometry(self.h, int(i), out.ctypes.data_as(C.POINTER(C.c_uint16))))
+        return out
+
+    def init_device(self, i: int, rho, ux=None, uy=None):
+        ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())
+        tensors = [None if t is None else t.contiguous() for t in (rho, ux, uy)]
+        self._keep = tensors
+        self._check(self.lib.lbm_batch_init_device(self.h, int(i), *[ptr(t) for t in tensors]))
+
+    def set_forces(self, i: int, f_elec: float, accel_x: float = 0.0, accel_y: float = 0.0):
+        self._check(self.lib.lbm_batch_set_forces(self.h, int(i), float(f_elec), float(accel_x),
+                                                  float(accel_y)))
+
+    def retire(self, done):
+        d = np.ascontiguousarray(np.asarray(done, np.uint8))
+        assert d.shape == (self.n,)
+        self._check(self.lib.lbm_batch_retire(self.h, d.ctypes.data_as(C.POINTER(C.c_uint8))))
+
+    def set_tile(self, block_x: int, rows: int):
+        self._check(self.lib.lbm_batch_set_tile(self.h, int(block_x), int(rows)))
+
+    def set_graph(self, steps_per_graph: int):
+        self._check(self.lib.lbm_batch_set_graph(self.h, int(steps_per_graph)))
+
+    def autotune(self, reps: int = 3):
+        bx, rows, us = C.c_int32(), C.c_int32(), C.c_float()
+        self._check(self.lib.lbm_batch_autotune(self.h, int(reps), C.byref(bx), C.byref(rows), C.byref(us)))
+        return bx.value, rows.value, us.value
+
+    def steps_done(self, i: int) -> int:
+        return int(self.lib.lbm_batch_steps_done(self.h, int(i)))
+
+    def synchronize(self):
+        self.stream.synchronize()
+

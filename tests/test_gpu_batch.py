@@ -1,0 +1,172 @@
+"""GPU tests of the batched engine (lbm_batch_* through the C ABI).
+
+The batch runs every channel with the same tile code as a single lattice, so a
+channel inside the batch must be bitwise identical to the same channel run
+alone; graph replays must be bitwise identical to eager launches; retiring a
+channel freezes it.  Parity against the FP64 oracle uses the same 1e-5 bar as
+the single-lattice tests.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_0708_4182_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0708_4182_amd import lbm as L
+    L.load_library()
+    return L
+
+
+def small_sweep(n=6, seed=3, storage=0):
+    """Sweep-table channels shrunk to test sizes (uneven shapes, own G and f)."""
+    rng = I.SplitMix64(seed)
+    cases = []
+    for i in range(n):
+        ny = rng.randint(20, 70)
+        nx = rng.randint(40, 300)
+        b = rng.randint(0, 4)
+        G = -5.5 + rng.uniform()
+        f = 3e-3 * rng.uniform()
+        solid = I.periodic_bumps(nx, ny, 5, b, 16, seed * 100 + i)
+        cases.append(I.channel_case(nx, ny, solid, G=G, f_elec=f, accel=2e-6, seed=seed * 100 + i,
+                                    storage=storage, name=f"ch{i}"))
+    return cases
+
+
+def run_single(lbm, case, n):
+    s = lbm.from_case(case)
+    s.step(n)
+    return s
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_channel_in_batch_is_bitwise_single(lbm, storage):
+    cases = small_sweep(storage=storage)
+    b = lbm.Batch(cases)
+    b.step(60)
+    for i, c in enumerate(cases):
+        ref = run_single(lbm, c, 60).moments()
+        for x, y in zip(b.moments(i), ref):
+            np.testing.assert_array_equal(x, y)
+        assert b.steps_done(i) == 60
+
+
+def test_geometry_bit_exact(lbm):
+    cases = small_sweep()
+    b = lbm.Batch(cases)
+    for i, c in enumerate(cases):
+        np.testing.assert_array_equal(b.geometry(i), O.flags(c.params, c.solid))
+
+
+def test_graph_replays_equal_eager(lbm):
+    cases = small_sweep(n=5, seed=7)
+    eager = lbm.Batch(cases)
+    graph = lbm.Batch(cases)
+    graph.set_graph(10)
+    for rep in range(3):
+        eager.step(10)
+        graph.step(10)
+        # eager work and synchronisation between replays
+        Qe, Me = eager.flux()
+        Qg, Mg = graph.flux()
+        np.testing.assert_array_equal(Qe, Qg)
+        np.testing.assert_array_equal(Me, Mg)
+        for i in range(len(cases)):
+            for x, y in zip(eager.moments(i), graph.moments(i)):
+                np.testing.assert_array_equal(x, y)
+    # an odd remainder runs eagerly after the replays
+    eager.step(13)
+    graph.step(13)
+    for i in range(len(cases)):
+        for x, y in zip(eager.moments(i), graph.moments(i)):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_retire_freezes_channels(lbm):
+    cases = small_sweep(n=5, seed=11)
+    b = lbm.Batch(cases)
+    b.set_graph(4)
+    b.step(20)
+    frozen = {i: b.moments(i) for i in (1, 3)}
+    b.retire([0, 1, 0, 1, 0])
+    b.step(21)
+    for i in (1, 3):
+        for x, y in zip(b.moments(i), frozen[i]):
+            np.testing.assert_array_equal(x, y)
+        assert b.steps_done(i) == 20
+    for i in (0, 2, 4):
+        ref = run_single(lbm, cases[i], 41).moments()
+        for x, y in zip(b.moments(i), ref):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_batch_flux_matches_single(lbm):
+    cases = small_sweep(n=4, seed=5)
+    b = lbm.Batch(cases)
+    b.step(40)
+    Q, M = b.flux()
+    for i, c in enumerate(cases):
+        q, m = run_single(lbm, c, 40).flux()
+        assert abs(M[i] - m) <= 1e-12 * m
+        assert abs(Q[i] - q) <= 1e-12 * max(abs(q), 1e-12)
+
+
+def test_batch_parity_vs_oracle(lbm):
+    from test_gpu_parity import conductivity_margin
+    cases = small_sweep(n=3, seed=21)
+    for c in cases:
+        assert conductivity_margin(c, 200) > 1e-5
+    b = lbm.Batch(cases)
+    b.step(200)
+    for i, c in enumerate(cases):
+        rho, ux, uy = (a.astype(np.float64) for a in b.moments(i))
+        f = O.run(c, 200)
+        ro, uxo, uyo = O.moments(c.params, c.solid, f)
+        fl = c.solid == 0
+        er = np.abs(rho - ro)[fl].max() / ro[fl].max()
+        eu = np.hypot(ux - uxo, uy - uyo)[fl].max() / np.hypot(uxo, uyo)[fl].max()
+        print(f"channel {i} {c.params.nx}x{c.params.ny}: err_rho={er:.2e} err_u={eu:.2e}")
+        assert er < 1e-5 and eu < 1e-5
+
+
+def test_batch_autotune_keeps_state(lbm):
+    cases = small_sweep(n=4, seed=9)
+    b = lbm.Batch(cases)
+    b.step(10)
+    before = [b.moments(i) for i in range(len(cases))]
+    bx, rows, us = b.autotune(reps=2)
+    assert bx in (64, 128, 256, 512) and rows in (16, 32, 64) and us > 0
+    for i in range(len(cases)):
+        for x, y in zip(b.moments(i), before[i]):
+            np.testing.assert_array_equal(x, y)
+    b.step(15)
+    for i, c in enumerate(cases):
+        for x, y in zip(b.moments(i), run_single(lbm, c, 25).moments()):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_batch_set_forces_and_init_device(lbm):
+    import torch
+    cases = small_sweep(n=3, seed=13)
+    b = lbm.Batch(cases)
+    b.set_forces(1, 2.5e-3, 3e-6)
+    c1 = cases[1]
+    c1.params = c1.params.replace(f_elec=2.5e-3, accel_x=3e-6)
+    b.step(30)
+    for x, y in zip(b.moments(1), run_single(lbm, c1, 30).moments()):
+        np.testing.assert_array_equal(x, y)
+    # warm start of channel 2 from device fields equals a fresh start
+    rho = torch.tensor(cases[2].rho.astype(np.float32), device="cuda")
+    b.init_device(2, rho)
+    assert b.steps_done(2) == 0
+    b.step(30)
+    for x, y in zip(b.moments(2), run_single(lbm, cases[2], 30).moments()):
+        np.testing.assert_array_equal(x, y)

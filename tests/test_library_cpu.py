@@ -121,3 +121,17 @@ def test_product_path_has_no_oracle_dependency():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "lbm_oracle" not in text and "orc_" not in text, f
+
+
+def test_batch_workspace_validation(lib):
+    from paper_0708_4182_amd import lbm
+    ps = [I.Params(nx=40, ny=20), I.Params(nx=64, ny=33), I.Params(nx=300, ny=70)]
+    arr = (lbm.lbm_params * 3)(*[lbm.to_c_params(p) for p in ps])
+    n = lib.lbm_batch_workspace_bytes(3, arr)
+    single = sum(lbm.workspace_bytes(p) for p in ps)
+    assert n > 0.9 * single
+    mixed = (lbm.lbm_params * 2)(lbm.to_c_params(ps[0]), lbm.to_c_params(ps[1].replace(storage=1)))
+    assert lib.lbm_batch_workspace_bytes(2, mixed) == 0
+    assert lib.lbm_batch_workspace_bytes(0, arr) == 0
+    bad = (lbm.lbm_params * 2)(lbm.to_c_params(ps[0]), lbm.to_c_params(ps[1].replace(tau=0.3)))
+    assert lib.lbm_batch_workspace_bytes(2, bad) == 0
