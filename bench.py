@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-ceiling", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-sweep line (256 uneven channels, FP16 storage)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -204,6 +206,19 @@ def main():
         "kernel": "k_step (fused pull-stream + bounce-back + Shan-Chen/EWOD forces + BGK)",
         "variants": variants,
     }
+    if not args.no_batch:
+        from paper_0708_4182_amd import experiments
+        bt = experiments.sweep_throughput()
+        print(f"# batch: {bt['channels']} channels, {bt['nodes']} nodes, tile {bt['tile']}, "
+              f"{bt['ms_per_step']*1e3:.1f} us/step", file=sys.stderr, flush=True)
+        out["batch"] = {"workload": "256-channel sweep table (width 32-256, length 512-4096, "
+                                    "step height 0-8, f in [0,3e-3), G in [-5.5,-4.5]), FP16 storage, "
+                                    "one persistent launch per step, hipGraph of 10 steps",
+                        "mlups": round(bt["mlups"], 1), "ms_per_step": round(bt["ms_per_step"], 4),
+                        "tile": bt["tile"],
+                        "roofline": {"bound": "hbm", "achieved": round(bt["achieved_GBs"], 1),
+                                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": round(bt["achieved_GBs"] / HBM_PEAK_GBS, 4)}}
     if not args.no_copy_ceiling:
         out["copy_ceiling"] = copy_ceiling(9 * nsites * ELEM_BYTES[STORAGES[args.storage]])
     if not args.no_cpu_baseline:

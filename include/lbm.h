@@ -202,12 +202,19 @@ lbm_status lbm_batch_retire(lbm_batch *b, const uint8_t *done);
  * Results do not depend on it (bitwise).  Default 256 x 32. */
 lbm_status lbm_batch_set_tile(lbm_batch *b, int32_t block_x, int32_t rows_per_tile);
 
+/* Work distribution of a step launch: persistent != 0 runs a persistent grid
+ * (resident workgroups take tiles from an atomic queue until it is empty);
+ * 0 launches one workgroup per tile and lets the hardware dispatcher balance.
+ * Results are bitwise the same.  Default 0. */
+lbm_status lbm_batch_set_schedule(lbm_batch *b, int32_t persistent);
+
 /* Time steps per captured graph: 0 (eager launches) or an even number up to
  * 1024.  Default 0. */
 lbm_status lbm_batch_set_graph(lbm_batch *b, int32_t steps_per_graph);
 
-/* Autotuner for the batch tile (block_x x rows in {16, 32, 64}); trial
- * launches write only the spare buffers, so the state is unchanged. */
+/* Autotuner for the batch: schedule (persistent or one workgroup per tile) x
+ * block_x x rows in {16, 32, 64}; keeps the fastest.  Trial launches write
+ * only the spare buffers, so the state is unchanged. */
 lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *block_x, int32_t *rows_per_tile,
                               float *us_per_step);
 

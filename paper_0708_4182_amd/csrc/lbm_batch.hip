@@ -1,6 +1,7 @@
 // Host side of the batched engine: many independent lattices ("channels") of
-// uneven sizes advanced together by one persistent kernel launch per time
-// step, optionally replayed as a hipGraph of K steps.  Declared in
+// uneven sizes advanced together by one kernel launch per time step (a
+// persistent grid fed by a tile queue, or one workgroup per tile), optionally
+// replayed as a hipGraph of K steps.  Declared in
 // include/lbm.h (lbm_batch_*).
 #include <hip/hip_runtime.h>
 
@@ -134,6 +135,7 @@ struct lbm_batch {
     std::vector<uint32_t> host_tiles;
     std::vector<int32_t> host_ids;
     int graph_steps = 0;
+    int persistent = 0;                // 1: persistent queue kernel, 0: one workgroup per tile
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     lbm_status sticky = LBM_OK;
@@ -214,7 +216,9 @@ lbm_status upload_tiles(lbm_batch *b) {
     return LBM_OK;
 }
 
+// Grid of a step launch: the persistent grid, or 0 for one workgroup per tile.
 int persistent_grid(lbm_batch *b) {
+    if (!b->persistent) return 0;
     const int per_cu = lbm::batch_blocks_per_cu(b->storage, b->block_x);
     return std::max(1, std::min(b->ntiles, b->cus * per_cu));
 }
@@ -234,7 +238,7 @@ hipError_t enqueue_step(lbm_batch *b, hipStream_t s, int slot, int parity, int g
 lbm_status capture_graph(lbm_batch *b, int parity) {
     const int K = b->graph_steps, grid = persistent_grid(b);
     BHIP(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
-    hipError_t e = lbm::launch_fill(b->d_counters, align_up(4 * (size_t)K, 16), b->cap);
+    hipError_t e = grid > 0 ? lbm::launch_fill(b->d_counters, align_up(4 * (size_t)K, 16), b->cap) : hipSuccess;
     for (int k = 0; k < K && e == hipSuccess; ++k) e = enqueue_step(b, b->cap, k, parity ^ (k & 1), grid);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(b->cap, &g);
@@ -255,7 +259,7 @@ lbm_status capture_graph(lbm_batch *b, int parity) {
 }
 
 lbm_status eager_step(lbm_batch *b, int parity, int grid) {
-    BHIP(b, lbm::launch_fill(b->d_counters, 16, b->stream));
+    if (grid > 0) BHIP(b, lbm::launch_fill(b->d_counters, 16, b->stream));
     BHIP(b, enqueue_step(b, b->stream, 0, parity, grid));
     return LBM_OK;
 }
@@ -522,6 +526,14 @@ lbm_status lbm_batch_set_tile(lbm_batch *b, int32_t block_x, int32_t rows) {
     return upload_tiles(b);
 }
 
+lbm_status lbm_batch_set_schedule(lbm_batch *b, int32_t persistent) {
+    lbm_status st = busable(b);
+    if (st) return st;
+    b->persistent = persistent ? 1 : 0;
+    drop_graphs(b);
+    return LBM_OK;
+}
+
 lbm_status lbm_batch_set_graph(lbm_batch *b, int32_t steps_per_graph) {
     lbm_status st = busable(b);
     if (st) return st;
@@ -545,9 +557,11 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *block_x, int3
         return bfail(b, LBM_EDEVICE, "hipEventCreate failed");
     }
     float best = 0.f;
-    int best_bx = b->block_x, best_rows = b->tile_rows;
+    int best_bx = b->block_x, best_rows = b->tile_rows, best_pers = b->persistent;
+    for (int pers = 0; pers < 2 && st == LBM_OK; ++pers)
     for (int bx : kBX) {
         for (int r : kRows) {
+            b->persistent = pers;
             b->block_x = bx;
             b->tile_rows = r;
             if ((st = upload_tiles(b)) != LBM_OK) break;
@@ -557,7 +571,7 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *block_x, int3
             if ((st = eager_step(b, b->parity, grid)) != LBM_OK) break;
             hipError_t e = hipEventRecord(e0, b->stream);
             for (int k = 0; k < reps && e == hipSuccess; ++k) {
-                e = lbm::launch_fill(b->d_counters, 16, b->stream);
+                if (grid > 0) e = lbm::launch_fill(b->d_counters, 16, b->stream);
                 if (e == hipSuccess) e = enqueue_step(b, b->stream, 0, b->parity, grid);
             }
             if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
@@ -573,6 +587,7 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *block_x, int3
                 best = us;
                 best_bx = bx;
                 best_rows = r;
+                best_pers = pers;
             }
         }
         if (st != LBM_OK) break;
@@ -582,6 +597,7 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *block_x, int3
     if (st != LBM_OK) return st;
     b->block_x = best_bx;
     b->tile_rows = best_rows;
+    b->persistent = best_pers;
     if ((st = upload_tiles(b)) != LBM_OK) return st;
     if (block_x) *block_x = best_bx;
     if (rows) *rows = best_rows;

@@ -77,6 +77,8 @@ hipError_t launch_init(int storage, void *dst, const uint16_t *flags, const Grid
 hipError_t launch_fill(void *dst, size_t bytes, hipStream_t s);
 hipError_t launch_moments(int storage, const void *src, const uint16_t *flags, const Grid &g,
                           float rho_off, float *rho, float *ux, float *uy, hipStream_t s);
+// grid > 0: persistent kernel with that many workgroups taking tiles from the
+// queue (counter a.slot); grid <= 0: one workgroup per tile (no counter).
 hipError_t launch_batch_step(int storage, const BatchStepArgs &a, int block_x, int grid, hipStream_t s);
 int batch_blocks_per_cu(int storage, int block_x);
 // Per-channel FP64 reduction of channels ids[0..n): out[4*k] = Q, out[4*k+1] =

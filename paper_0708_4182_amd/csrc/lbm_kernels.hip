@@ -570,24 +570,55 @@ __global__ void __launch_bounds__(64) k_reduce_final(const double *__restrict__ 
 // tiles from a queue (one atomic per tile), so uneven channels balance
 // dynamically; every channel uses the same tile code as a single lattice.
 template <int S>
-__global__ void __launch_bounds__(512) k_batch_step(const BatchStepArgs a) {
+__global__ void __launch_bounds__(512) k_batch_step(const ChannelDesc *__restrict__ descs,
+                                                    const uint32_t *__restrict__ tiles,
+                                                    uint32_t *__restrict__ counters, int ntiles, int slot,
+                                                    int parity) {
     extern __shared__ float ring[];
     __shared__ int next_tile;
     for (;;) {
-        if (threadIdx.x == 0) next_tile = (int)atomicAdd(&a.counters[a.slot], 1u);
+        if (threadIdx.x == 0) next_tile = (int)atomicAdd(&counters[slot], 1u);
         __syncthreads();
         const int t = __builtin_amdgcn_readfirstlane(next_tile);
         __syncthreads();                 // next_tile is rewritten only after all have read it
-        if (t >= a.ntiles) break;
-        const uint32_t packed = a.tiles[t];
-        const ChannelDesc d = a.descs[packed >> 16];
+        if (t >= ntiles) break;
+        const uint32_t packed = __builtin_amdgcn_readfirstlane(tiles[t]);
+        const ChannelDesc *d = descs + (packed >> 16);
+        const Grid g = d->g;
+        const Model m = d->m;
+        const int chunks = d->chunks;
+        const void *src = parity ? d->buf[1] : d->buf[0];
+        void *dst = const_cast<void *>(parity ? d->buf[0] : d->buf[1]);
         const int local = (int)(packed & 0xFFFFu);
-        const int strip = local / d.chunks, chunk = local - strip * d.chunks;
-        const int y0 = (int)(((int64_t)chunk * d.g.ny) / d.chunks);
-        const int y1 = (int)(((int64_t)(chunk + 1) * d.g.ny) / d.chunks);
-        step_tile<S>(d.buf[a.parity], const_cast<void *>(d.buf[a.parity ^ 1]), d.flags, d.g, d.m,
-                     strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring);
+        const int strip = local / chunks, chunk = local - strip * chunks;
+        const int y0 = (int)(((int64_t)chunk * g.ny) / chunks);
+        const int y1 = (int)(((int64_t)(chunk + 1) * g.ny) / chunks);
+        step_tile<S>(src, dst, d->flags, g, m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring);
     }
+}
+
+// The same batched step with one workgroup per tile (grid = number of tiles,
+// tiles mapped to XCDs in contiguous ranges): the hardware dispatcher does the
+// balancing and no state is carried between tiles.
+template <int S>
+__global__ void __launch_bounds__(512) k_batch_tiles(const ChannelDesc *__restrict__ descs,
+                                                     const uint32_t *__restrict__ tiles, int ntiles,
+                                                     int tiles_per_xcd, int parity) {
+    extern __shared__ float ring[];
+    const int t = (int)(blockIdx.x & 7u) * tiles_per_xcd + (int)(blockIdx.x >> 3);
+    if (t >= ntiles) return;
+    const uint32_t packed = __builtin_amdgcn_readfirstlane(tiles[t]);
+    const ChannelDesc *d = descs + (packed >> 16);
+    const Grid g = d->g;
+    const Model m = d->m;
+    const int chunks = d->chunks;
+    const void *src = parity ? d->buf[1] : d->buf[0];
+    void *dst = const_cast<void *>(parity ? d->buf[0] : d->buf[1]);
+    const int local = (int)(packed & 0xFFFFu);
+    const int strip = local / chunks, chunk = local - strip * chunks;
+    const int y0 = (int)(((int64_t)chunk * g.ny) / chunks);
+    const int y1 = (int)(((int64_t)(chunk + 1) * g.ny) / chunks);
+    step_tile<S>(src, dst, d->flags, g, m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring);
 }
 
 // Per-channel FP64 flux/mass reduction: one workgroup per channel, rows in
@@ -728,10 +759,20 @@ hipError_t launch_reduce(int storage, const void *src, const uint16_t *flags, co
 
 hipError_t launch_batch_step(int storage, const BatchStepArgs &a, int block_x, int grid, hipStream_t s) {
     const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
+    if (grid <= 0) {   // one workgroup per tile
+        const int per = (a.ntiles + 7) / 8;
+        switch (storage) {
+        case ST_F32: k_batch_tiles<ST_F32><<<8 * per, block_x, lds, s>>>(a.descs, a.tiles, a.ntiles, per, a.parity); break;
+        case ST_F16: k_batch_tiles<ST_F16><<<8 * per, block_x, lds, s>>>(a.descs, a.tiles, a.ntiles, per, a.parity); break;
+        case ST_BF16: k_batch_tiles<ST_BF16><<<8 * per, block_x, lds, s>>>(a.descs, a.tiles, a.ntiles, per, a.parity); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (storage) {
-    case ST_F32: k_batch_step<ST_F32><<<grid, block_x, lds, s>>>(a); break;
-    case ST_F16: k_batch_step<ST_F16><<<grid, block_x, lds, s>>>(a); break;
-    case ST_BF16: k_batch_step<ST_BF16><<<grid, block_x, lds, s>>>(a); break;
+    case ST_F32: k_batch_step<ST_F32><<<grid, block_x, lds, s>>>(a.descs, a.tiles, a.counters, a.ntiles, a.slot, a.parity); break;
+    case ST_F16: k_batch_step<ST_F16><<<grid, block_x, lds, s>>>(a.descs, a.tiles, a.counters, a.ntiles, a.slot, a.parity); break;
+    case ST_BF16: k_batch_step<ST_BF16><<<grid, block_x, lds, s>>>(a.descs, a.tiles, a.counters, a.ntiles, a.slot, a.parity); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

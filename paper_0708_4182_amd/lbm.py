@@ -26,6 +26,7 @@ SYMBOLS = ("lbm_workspace_bytes", "lbm_init", "lbm_init_device", "lbm_step", "lb
            "lbm_status_string", "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_step",
            "lbm_batch_flux", "lbm_batch_moments", "lbm_batch_geometry", "lbm_batch_init_device",
            "lbm_batch_set_forces", "lbm_batch_retire", "lbm_batch_set_tile", "lbm_batch_set_graph",
+           "lbm_batch_set_schedule",
            "lbm_batch_autotune", "lbm_batch_steps_done", "lbm_batch_free", "lbm_batch_last_error")
 
 
@@ -107,6 +108,7 @@ def load_library():
     lib.lbm_batch_retire.argtypes = [vp, C.POINTER(C.c_uint8)]
     lib.lbm_batch_set_tile.argtypes = [vp, C.c_int32, C.c_int32]
     lib.lbm_batch_set_graph.argtypes = [vp, C.c_int32]
+    lib.lbm_batch_set_schedule.argtypes = [vp, C.c_int32]
     lib.lbm_batch_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                        C.POINTER(C.c_float)]
     lib.lbm_batch_steps_done.argtypes = [vp, C.c_int32]
@@ -118,7 +120,7 @@ def load_library():
     for name in ("lbm_batch_init", "lbm_batch_step", "lbm_batch_flux", "lbm_batch_moments",
                  "lbm_batch_geometry", "lbm_batch_init_device", "lbm_batch_set_forces",
                  "lbm_batch_retire", "lbm_batch_set_tile", "lbm_batch_set_graph",
-                 "lbm_batch_autotune"):
+                 "lbm_batch_set_schedule", "lbm_batch_autotune"):
         getattr(lib, name).restype = C.c_int
     for name in ("lbm_init", "lbm_init_device", "lbm_step", "lbm_moments", "lbm_flux",
                  "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_autotune", "lbm_save_state",
@@ -367,6 +369,9 @@ class Batch:
 
     def set_tile(self, block_x: int, rows: int):
         self._check(self.lib.lbm_batch_set_tile(self.h, int(block_x), int(rows)))
+
+    def set_schedule(self, persistent: bool):
+        self._check(self.lib.lbm_batch_set_schedule(self.h, int(bool(persistent))))
 
     def set_graph(self, steps_per_graph: int):
         self._check(self.lib.lbm_batch_set_graph(self.h, int(steps_per_graph)))

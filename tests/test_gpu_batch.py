@@ -47,10 +47,11 @@ def run_single(lbm, case, n):
     return s
 
 
-@pytest.mark.parametrize("storage", [0, 1])
-def test_channel_in_batch_is_bitwise_single(lbm, storage):
+@pytest.mark.parametrize("storage,persistent", [(0, False), (1, False), (0, True), (1, True)])
+def test_channel_in_batch_is_bitwise_single(lbm, storage, persistent):
     cases = small_sweep(storage=storage)
     b = lbm.Batch(cases)
+    b.set_schedule(persistent)
     b.step(60)
     for i, c in enumerate(cases):
         ref = run_single(lbm, c, 60).moments()
@@ -66,10 +67,12 @@ def test_geometry_bit_exact(lbm):
         np.testing.assert_array_equal(b.geometry(i), O.flags(c.params, c.solid))
 
 
-def test_graph_replays_equal_eager(lbm):
+@pytest.mark.parametrize("persistent", [False, True])
+def test_graph_replays_equal_eager(lbm, persistent):
     cases = small_sweep(n=5, seed=7)
     eager = lbm.Batch(cases)
     graph = lbm.Batch(cases)
+    graph.set_schedule(persistent)
     graph.set_graph(10)
     for rep in range(3):
         eager.step(10)
