@@ -248,7 +248,7 @@ def droplet_case(f_elec: float = 0.0, seed: int = 0, nx: int = 128, ny: int = 64
 
 def channel_case(nx: int, ny: int, solid: np.ndarray, G: float = -5.0, f_elec: float = 0.0,
                  accel: float = 1e-6, seed: int = 0, noise_amp: float = 1e-3,
-                 vapor_layer: int = 2, layers: int = 1, tau: float = 1.0, storage: int = 0,
+                 vapor_layer: int = 2, layers: int = 2, tau: float = 1.0, storage: int = 0,
                  name: str = "channel") -> Case:
     """Liquid-filled channel with a vapour layer within ``vapor_layer`` cells of the walls."""
     rv, rl = coexistence(G)

@@ -25,7 +25,7 @@ def lbm():
     return L
 
 
-def small_sweep(n=6, seed=3, storage=0):
+def small_sweep(n=6, seed=3, storage=0, layers=2):
     """Sweep-table channels shrunk to test sizes (uneven shapes, own G and f)."""
     rng = I.SplitMix64(seed)
     cases = []
@@ -37,7 +37,7 @@ def small_sweep(n=6, seed=3, storage=0):
         f = 3e-3 * rng.uniform()
         solid = I.periodic_bumps(nx, ny, 5, b, 16, seed * 100 + i)
         cases.append(I.channel_case(nx, ny, solid, G=G, f_elec=f, accel=2e-6, seed=seed * 100 + i,
-                                    storage=storage, name=f"ch{i}"))
+                                    storage=storage, layers=layers, name=f"ch{i}"))
     return cases
 
 

@@ -76,9 +76,10 @@ def tiny_rough(nx, ny, seed, **kw):
 
 CASES = {
     "droplet128x64": lambda: I.droplet_case(f_elec=1e-3),
-    "rough256x128": lambda: I.rough_channel_case(nx=256, ny=128, f_elec=2e-3, accel=1e-6, seed=5),
+    "rough256x128": lambda: I.rough_channel_case(nx=256, ny=128, f_elec=2e-3, accel=1e-6, seed=5,
+                                                 layers=1),
     "ragged37x19": lambda: tiny_rough(37, 19, 1, f_elec=3e-3, accel=1e-5, layers=2),
-    "ragged130x67": lambda: tiny_rough(130, 67, 2, f_elec=1e-3, accel=2e-6),
+    "ragged130x67": lambda: tiny_rough(130, 67, 2, f_elec=1e-3, accel=2e-6, layers=1),
     "ragged300x5": lambda: tiny_rough(300, 5, 3, f_elec=1e-3, accel=1e-6, vapor_layer=1),
 }
 
