@@ -22,6 +22,12 @@ in the order above, W[cout][cin][kh][kw] then b[cout].
 Plain loops over channels with numpy slicing over pixels: obviously correct,
 slow, FP64.  The gradients are checked against finite differences in
 tests/test_cnn_oracle.py.
+
+Stored activations in bf16 (the production setting) are defined as the same
+network with every stored activation (each conv + ReLU output and each pooled
+tensor; upsampling and concatenation only move stored values) rounded to the
+nearest bf16 value, ties to even, and the gradient passed through the rounding
+unchanged.  ``forward``/``backward`` take that rounding as ``act=round_bf16``.
 """
 from __future__ import annotations
 
@@ -62,6 +68,17 @@ def init_params(specs, seed=0):
         parts.append(rng.standard_normal(co * ci * k * k) * np.sqrt(2.0 / (ci * k * k)))
         parts.append(np.zeros(co))
     return np.concatenate(parts)
+
+
+def round_bf16(a):
+    """Nearest value with 8 significant bits (bf16), ties to even; exponent range
+    of the values met here is far inside bf16's."""
+    m, e = np.frexp(np.asarray(a, np.float64))     # a = m 2^e, 1/2 <= |m| < 1
+    return np.ldexp(np.round(np.ldexp(m, 8)), e - 8)
+
+
+def _identity(a):
+    return a
 
 
 # ------------------------------------------------------------------ layers
@@ -138,20 +155,21 @@ def up_backward(dy):
 
 
 # ----------------------------------------------------------------- network
-def forward(theta, specs, x, keep=False):
+def forward(theta, specs, x, keep=False, act=_identity):
+    """Network output; ``act`` rounds every stored activation (identity: FP64)."""
     P = unpack(theta, specs)
     cache = {}
 
     def block(name_a, name_b, inp):
-        za = conv(inp, *P[name_a]); ya = relu(za)
-        zb = conv(ya, *P[name_b]); yb = relu(zb)
+        za = conv(inp, *P[name_a]); ya = act(relu(za))
+        zb = conv(ya, *P[name_b]); yb = act(relu(zb))
         cache[name_a] = (inp, za); cache[name_b] = (ya, zb)
         return yb
 
     e1 = block("e1a", "e1b", x)
-    e2 = block("e2a", "e2b", pool(e1))
-    e3 = block("e3a", "e3b", pool(e2))
-    bt = block("b_a", "b_b", pool(e3))
+    e2 = block("e2a", "e2b", act(pool(e1)))
+    e3 = block("e3a", "e3b", act(pool(e2)))
+    bt = block("b_a", "b_b", act(pool(e3)))
     d3 = block("d3a", "d3b", np.concatenate([up(bt), e3], 1))
     d2 = block("d2a", "d2b", np.concatenate([up(d3), e2], 1))
     d1 = block("d1a", "d1b", np.concatenate([up(d2), e1], 1))
@@ -174,9 +192,10 @@ def loss_grad(y, t, fluid):
     return 2.0 * (y - t) * m / cnt
 
 
-def backward(theta, specs, x, t, fluid):
-    """(loss, gradient of the loss with respect to theta)."""
-    y, cache = forward(theta, specs, x, keep=True)
+def backward(theta, specs, x, t, fluid, act=_identity):
+    """(loss, gradient of the loss with respect to theta); with ``act`` the
+    gradient passes through the activation rounding unchanged."""
+    y, cache = forward(theta, specs, x, keep=True, act=act)
     P = unpack(theta, specs)
     grads = {}
     dy = loss_grad(y, t, fluid)

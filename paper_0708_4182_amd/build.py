@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_kernels.hip", "lbm_api.hip", "lbm_batch.hip"]
+SOURCES = ["lbm_kernels.hip", "lbm_api.hip", "lbm_batch.hip", "net_kernels.hip", "net_api.hip"]
 
 # Packed FP32 instructions are disabled for all device code.
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

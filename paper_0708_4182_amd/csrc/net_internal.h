@@ -1,0 +1,51 @@
+// Internal interface of the warm-start network kernels (net_kernels.hip) used
+// by the runner (net_api.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+namespace lbmnet {
+
+// A tensor view: element (n, c, y, x) is at p[n * bs + (c * H + y) * W + x].
+struct View {
+    void *p;
+    int C, H, W;
+    long long bs;
+};
+
+template <class TI, class TO>
+hipError_t conv3x3(const View &in, const float *w, const float *bias, const View &out, int N, int cin, int cout,
+                   bool relu, hipStream_t s);
+hipError_t flip_transpose(const float *w, float *wt, int cin, int cout, hipStream_t s);
+int dw_chunks(int N, int H, int W, int cin, int cout);
+template <class TI>
+hipError_t conv3x3_dw(const View &x, const float *dz, int N, int cin, int cout, float *partial, int chunks,
+                      float *dw, hipStream_t s);
+hipError_t bias_grad(const float *dz, int N, int C, int HW, float *db, hipStream_t s);
+template <class TA>
+hipError_t relu_mask(const View &g, const View &y, int N, int C, float *dz, hipStream_t s);
+template <class TA>
+hipError_t pool(const View &in, const View &out, int N, int C, hipStream_t s);
+hipError_t pool_back_acc(const View &dy, const View &dx, int N, int C, hipStream_t s);
+template <class TA>
+hipError_t up(const View &in, const View &out, int N, int C, hipStream_t s);
+hipError_t up_back(const View &dy, const View &dx, int N, int C, hipStream_t s);
+template <class TA>
+hipError_t conv1x1(const View &in, const float *w, const float *b, int N, int cin, int cout, float *out,
+                   hipStream_t s);
+hipError_t conv1x1_dx(const float *g, const float *w, int N, int cin, int cout, int HW, const View &dx,
+                      hipStream_t s);
+template <class TA>
+hipError_t conv1x1_dw(const View &x, const float *g, int N, int cin, int cout, float *dw, float *db,
+                      hipStream_t s);
+int loss_blocks();
+hipError_t loss_and_grad(const float *y, const float *t, const uint8_t *mask, int N, int C, int HW, double *part,
+                         double *stats, float *g, hipStream_t s);
+hipError_t adam(float *th, const float *g, float *m, float *v, int n, float lr, float b1, float b2, float eps,
+                float c1, float c2, hipStream_t s);
+hipError_t zero(float *p, size_t n, hipStream_t s);
+
+}  // namespace lbmnet

@@ -1,0 +1,506 @@
+// HIP kernels of the warm-start network (training and inference) for gfx950.
+//
+// Tensors are NCHW; activations are stored as bf16 (or fp32 for checking) and
+// every product and sum is FP32.  A tensor view is a pointer to channel 0 of
+// sample 0 plus the channel count, H, W and the distance between samples, so
+// a channel slice of a concatenation buffer is a view like any other.
+// Convolutions are 3x3, periodic along x and zero-padded along y (the
+// channels are periodic in x and bounded by walls in y).
+#include "net_internal.h"
+
+namespace lbmnet {
+namespace {
+
+template <class T> __device__ __forceinline__ float tof(T v) { return (float)v; }
+template <class T> __device__ __forceinline__ T fromf(float v) { return (T)v; }
+
+// --------------------------------------------------------------- conv 3x3
+// One workgroup: 8 x 32 output pixels of one sample, 16 output channels.
+// Input channels are staged through LDS 8 at a time, with a one-pixel halo
+// (x wraps around, y outside the lattice reads 0).
+constexpr int TH = 8, TW = 32, CO_T = 16, CI_T = 8;
+
+template <class TI, class TO>
+__global__ void __launch_bounds__(256) k_conv3x3(View in, const float *__restrict__ w,
+                                                 const float *__restrict__ bias, View out, int cin,
+                                                 int cout, int relu) {
+    __shared__ float xs[CI_T][TH + 2][TW + 2];
+    __shared__ float4 ws[CI_T][9][CO_T / 4];
+    const int H = in.H, W = in.W;
+    const int tiles_x = (W + TW - 1) / TW;
+    const int tx0 = (blockIdx.x % tiles_x) * TW, ty0 = (blockIdx.x / tiles_x) * TH;
+    const int ncob = (cout + CO_T - 1) / CO_T;
+    const int n = blockIdx.y / ncob, co0 = (blockIdx.y % ncob) * CO_T;
+    const int tid = threadIdx.x, px = tid % TW, py = tid / TW;
+    const TI *__restrict__ xin = static_cast<const TI *>(in.p) + (size_t)n * in.bs;
+    float acc[CO_T];
+#pragma unroll
+    for (int o = 0; o < CO_T; ++o) acc[o] = 0.f;
+    for (int ci0 = 0; ci0 < cin; ci0 += CI_T) {
+        for (int e = tid; e < CI_T * (TH + 2) * (TW + 2); e += 256) {
+            const int c = e / ((TH + 2) * (TW + 2)), r = (e / (TW + 2)) % (TH + 2), q = e % (TW + 2);
+            const int y = ty0 - 1 + r;
+            const int x = (tx0 - 1 + q + W) % W;   // periodic; W may be narrower than a tile
+            float v = 0.f;
+            if (ci0 + c < cin && y >= 0 && y < H) v = tof(xin[(size_t)(ci0 + c) * H * W + (size_t)y * W + x]);
+            xs[c][r][q] = v;
+        }
+        for (int e = tid; e < CI_T * 9 * CO_T; e += 256) {
+            const int c = e / (9 * CO_T), t = (e / CO_T) % 9, o = e % CO_T;
+            float v = 0.f;
+            if (ci0 + c < cin && co0 + o < cout) v = w[((size_t)(co0 + o) * cin + ci0 + c) * 9 + t];
+            reinterpret_cast<float *>(&ws[c][t][0])[o] = v;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int c = 0; c < CI_T; ++c) {
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const float xv = xs[c][py + t / 3][px + t % 3];
+#pragma unroll
+                for (int o4 = 0; o4 < CO_T / 4; ++o4) {
+                    const float4 wv = ws[c][t][o4];
+                    acc[4 * o4 + 0] += wv.x * xv;
+                    acc[4 * o4 + 1] += wv.y * xv;
+                    acc[4 * o4 + 2] += wv.z * xv;
+                    acc[4 * o4 + 3] += wv.w * xv;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const int y = ty0 + py, x = tx0 + px;
+    if (y >= H || x >= W) return;
+    TO *__restrict__ yo = static_cast<TO *>(out.p) + (size_t)n * out.bs;
+#pragma unroll
+    for (int o = 0; o < CO_T; ++o) {
+        if (co0 + o >= cout) break;
+        float v = acc[o] + (bias ? bias[co0 + o] : 0.f);
+        if (relu) v = fmaxf(v, 0.f);
+        yo[(size_t)(co0 + o) * H * W + (size_t)y * W + x] = fromf<TO>(v);
+    }
+}
+
+// W'[ci][co][8 - t] = W[co][ci][t]: the weights of the transposed convolution
+// used for the input gradient.
+__global__ void k_flip_transpose(const float *__restrict__ w, float *__restrict__ wt, int cin, int cout) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cin * cout * 9) return;
+    const int t = i % 9, co = (i / 9) % cout, ci = i / (9 * cout);
+    wt[i] = w[((size_t)co * cin + ci) * 9 + (8 - t)];
+}
+
+// ------------------------------------------------------- weight gradient
+// dW[co][ci][t] = sum over samples and pixels of dz[co](p) x[ci](p + shift t).
+// Workgroup (chunk, co block of 16, ci block of 8) accumulates over the tiles
+// of its chunk; threads 0..143 own (co = t % 16, tap = t / 16) and 8 ci each.
+// Partials [chunk][co][ci][tap] are summed in chunk order by k_sum_partials.
+template <class TI>
+__global__ void __launch_bounds__(256) k_conv3x3_dw(View x, const float *__restrict__ dz, int N, int cin,
+                                                    int cout, int tiles_per_chunk,
+                                                    float *__restrict__ partial) {
+    __shared__ float xs[CI_T][TH + 2][TW + 2];
+    __shared__ float ds[CO_T][TH * TW];
+    const int H = x.H, W = x.W;
+    const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
+    const int ntiles = N * tiles_x * tiles_y;
+    const int chunk = blockIdx.x, co0 = blockIdx.y * CO_T, ci0 = blockIdx.z * CI_T;
+    const int tid = threadIdx.x;
+    const int my_co = tid % CO_T, my_tap = tid / CO_T;
+    const bool owner = tid < CO_T * 9;
+    float acc[CI_T];
+#pragma unroll
+    for (int c = 0; c < CI_T; ++c) acc[c] = 0.f;
+    const int t_begin = chunk * tiles_per_chunk, t_end = min(ntiles, t_begin + tiles_per_chunk);
+    for (int tile = t_begin; tile < t_end; ++tile) {
+        const int n = tile / (tiles_x * tiles_y), rem = tile % (tiles_x * tiles_y);
+        const int ty0 = (rem / tiles_x) * TH, tx0 = (rem % tiles_x) * TW;
+        const TI *__restrict__ xin = static_cast<const TI *>(x.p) + (size_t)n * x.bs;
+        for (int e = tid; e < CI_T * (TH + 2) * (TW + 2); e += 256) {
+            const int c = e / ((TH + 2) * (TW + 2)), r = (e / (TW + 2)) % (TH + 2), q = e % (TW + 2);
+            const int y = ty0 - 1 + r;
+            const int xx = (tx0 - 1 + q + W) % W;
+            float v = 0.f;
+            if (ci0 + c < cin && y >= 0 && y < H) v = tof(xin[(size_t)(ci0 + c) * H * W + (size_t)y * W + xx]);
+            xs[c][r][q] = v;
+        }
+        for (int e = tid; e < CO_T * TH * TW; e += 256) {
+            const int o = e / (TH * TW), p = e % (TH * TW);
+            const int y = ty0 + p / TW, xx = tx0 + p % TW;
+            float v = 0.f;
+            if (co0 + o < cout && y < H && xx < W)
+                v = dz[((size_t)n * cout + co0 + o) * H * W + (size_t)y * W + xx];
+            ds[o][p] = v;
+        }
+        __syncthreads();
+        if (owner) {
+            const int ky = my_tap / 3, kx = my_tap % 3;
+            for (int p = 0; p < TH * TW; ++p) {
+                const float d = ds[my_co][p];
+                const int py = p / TW, px = p % TW;
+#pragma unroll
+                for (int c = 0; c < CI_T; ++c) acc[c] += d * xs[c][py + ky][px + kx];
+            }
+        }
+        __syncthreads();
+    }
+    if (owner) {
+#pragma unroll
+        for (int c = 0; c < CI_T; ++c) {
+            if (ci0 + c >= cin || co0 + my_co >= cout) continue;
+            partial[(((size_t)chunk * cout + co0 + my_co) * cin + ci0 + c) * 9 + my_tap] = acc[c];
+        }
+    }
+}
+
+// out[i] = sum over k of partial[k][i], k in order (deterministic).
+__global__ void k_sum_partials(const float *__restrict__ partial, int nchunks, int n, float *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int k = 0; k < nchunks; ++k) s += partial[(size_t)k * n + i];
+    out[i] = s;
+}
+
+// db[co] = sum of dz[n][co][...] over samples and pixels: one workgroup per
+// channel, fixed tree.
+__global__ void __launch_bounds__(256) k_bias_grad(const float *__restrict__ dz, int N, int C, int HW,
+                                                   float *__restrict__ db) {
+    __shared__ float sh[256];
+    const int co = blockIdx.x;
+    float s = 0.f;
+    for (int n = 0; n < N; ++n)
+        for (int i = threadIdx.x; i < HW; i += 256) s += dz[((size_t)n * C + co) * HW + i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[co] = sh[0];
+}
+
+// dz = g * (y > 0) (ReLU derivative from the stored output), dense fp32 out.
+template <class TA>
+__global__ void k_relu_mask(View g, View y, int N, int C, float *__restrict__ dz) {
+    const size_t HW = (size_t)y.H * y.W, per = (size_t)C * HW;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)N * per) return;
+    const size_t n = i / per, r = i % per;
+    const float gv = static_cast<const float *>(g.p)[n * g.bs + r];
+    const float yv = tof(static_cast<const TA *>(y.p)[n * y.bs + r]);
+    dz[i] = yv > 0.f ? gv : 0.f;
+}
+
+// ------------------------------------------------------ pool / upsample
+template <class TA>
+__global__ void k_pool(View in, View out, int N, int C) {
+    const int Ho = out.H, Wo = out.W;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)N * C * Ho * Wo) return;
+    const int x = i % Wo, y = (i / Wo) % Ho, c = (i / ((size_t)Wo * Ho)) % C;
+    const size_t n = i / ((size_t)C * Ho * Wo);
+    const TA *s = static_cast<const TA *>(in.p) + n * in.bs + (size_t)c * in.H * in.W;
+    const float v = 0.25f * ((tof(s[(2 * y) * in.W + 2 * x]) + tof(s[(2 * y) * in.W + 2 * x + 1])) +
+                             (tof(s[(2 * y + 1) * in.W + 2 * x]) + tof(s[(2 * y + 1) * in.W + 2 * x + 1])));
+    static_cast<TA *>(out.p)[n * out.bs + (size_t)c * Ho * Wo + (size_t)y * Wo + x] = fromf<TA>(v);
+}
+
+// gradient of pool: dx (fine, fp32) += dy (coarse) / 4
+__global__ void k_pool_back_acc(View dy, View dx, int N, int C) {
+    const int H = dx.H, W = dx.W;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)N * C * H * W) return;
+    const int x = i % W, y = (i / W) % H, c = (i / ((size_t)W * H)) % C;
+    const size_t n = i / ((size_t)C * H * W);
+    const float g = static_cast<const float *>(dy.p)[n * dy.bs + (size_t)c * dy.H * dy.W + (size_t)(y / 2) * dy.W + x / 2];
+    static_cast<float *>(dx.p)[n * dx.bs + (size_t)c * H * W + (size_t)y * W + x] += 0.25f * g;
+}
+
+template <class TA>
+__global__ void k_up(View in, View out, int N, int C) {
+    const int H = out.H, W = out.W;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)N * C * H * W) return;
+    const int x = i % W, y = (i / W) % H, c = (i / ((size_t)W * H)) % C;
+    const size_t n = i / ((size_t)C * H * W);
+    static_cast<TA *>(out.p)[n * out.bs + (size_t)c * H * W + (size_t)y * W + x] =
+        static_cast<const TA *>(in.p)[n * in.bs + (size_t)c * in.H * in.W + (size_t)(y / 2) * in.W + x / 2];
+}
+
+// gradient of upsample: dx (coarse, fp32) = sum of the 2x2 block of dy
+__global__ void k_up_back(View dy, View dx, int N, int C) {
+    const int Ho = dx.H, Wo = dx.W;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)N * C * Ho * Wo) return;
+    const int x = i % Wo, y = (i / Wo) % Ho, c = (i / ((size_t)Wo * Ho)) % C;
+    const size_t n = i / ((size_t)C * Ho * Wo);
+    const float *s = static_cast<const float *>(dy.p) + n * dy.bs + (size_t)c * dy.H * dy.W;
+    const float v = (s[(2 * y) * dy.W + 2 * x] + s[(2 * y) * dy.W + 2 * x + 1]) +
+                    (s[(2 * y + 1) * dy.W + 2 * x] + s[(2 * y + 1) * dy.W + 2 * x + 1]);
+    static_cast<float *>(dx.p)[n * dx.bs + (size_t)c * Ho * Wo + (size_t)y * Wo + x] = v;
+}
+
+// ---------------------------------------------------------- 1x1 output
+template <class TA>
+__global__ void k_conv1x1(View in, const float *__restrict__ w, const float *__restrict__ b, int N, int cin,
+                          int cout, float *__restrict__ out) {
+    const size_t HW = (size_t)in.H * in.W;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)N * HW) return;
+    const size_t n = i / HW, p = i % HW;
+    const TA *s = static_cast<const TA *>(in.p) + n * in.bs + p;
+    for (int o = 0; o < cout; ++o) {
+        float acc = b[o];
+        for (int c = 0; c < cin; ++c) acc += w[o * cin + c] * tof(s[(size_t)c * HW]);
+        out[(n * cout + o) * HW + p] = acc;
+    }
+}
+
+// gradient of 1x1 input: dx[c] = sum_o w[o][c] g[o]
+__global__ void k_conv1x1_dx(const float *__restrict__ g, const float *__restrict__ w, int N, int cin, int cout,
+                             int HW, View dx) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)N * HW) return;
+    const size_t n = i / HW, p = i % HW;
+    for (int c = 0; c < cin; ++c) {
+        float acc = 0.f;
+        for (int o = 0; o < cout; ++o) acc += w[o * cin + c] * g[(n * cout + o) * HW + p];
+        static_cast<float *>(dx.p)[n * dx.bs + (size_t)c * HW + p] = acc;
+    }
+}
+
+// 1x1 weight and bias gradients: one workgroup per (o, c) entry, and c = cin
+// for the bias; fixed tree.
+template <class TA>
+__global__ void __launch_bounds__(256) k_conv1x1_dw(View x, const float *__restrict__ g, int N, int cin, int cout,
+                                                    float *__restrict__ dw, float *__restrict__ db) {
+    __shared__ float sh[256];
+    const int o = blockIdx.x / (cin + 1), c = blockIdx.x % (cin + 1);
+    const size_t HW = (size_t)x.H * x.W;
+    float s = 0.f;
+    for (int n = 0; n < N; ++n)
+        for (size_t p = threadIdx.x; p < HW; p += 256) {
+            const float gv = g[((size_t)n * cout + o) * HW + p];
+            s += c < cin ? gv * tof(static_cast<const TA *>(x.p)[(size_t)n * x.bs + (size_t)c * HW + p]) : gv;
+        }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (c < cin) dw[o * cin + c] = sh[0];
+        else db[o] = sh[0];
+    }
+}
+
+// ------------------------------------------------------------ loss, Adam
+// Count of fluid nodes times channels and the sum of squared errors, in FP64
+// partials per workgroup (fixed order), then the gradient 2 (y - t) m / count.
+__global__ void __launch_bounds__(256) k_loss_partial(const float *__restrict__ y, const float *__restrict__ t,
+                                                      const uint8_t *__restrict__ mask, int N, int C, int HW,
+                                                      double *__restrict__ part) {
+    __shared__ double sh[2][256];
+    double se = 0.0, cnt = 0.0;
+    const size_t total = (size_t)N * HW;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
+        if (!mask[i]) continue;
+        const size_t n = i / HW, p = i % HW;
+        for (int c = 0; c < C; ++c) {
+            const double d = (double)y[(n * C + c) * HW + p] - (double)t[(n * C + c) * HW + p];
+            se += d * d;
+        }
+        cnt += C;
+    }
+    sh[0][threadIdx.x] = se;
+    sh[1][threadIdx.x] = cnt;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + k];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sh[0][0];
+        part[2 * blockIdx.x + 1] = sh[1][0];
+    }
+}
+
+__global__ void k_loss_final(const double *__restrict__ part, int n, double *__restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double se = 0.0, cnt = 0.0;
+    for (int k = 0; k < n; ++k) {
+        se += part[2 * k];
+        cnt += part[2 * k + 1];
+    }
+    out[0] = cnt > 0 ? se / cnt : 0.0;
+    out[1] = cnt;
+}
+
+__global__ void k_loss_grad(const float *__restrict__ y, const float *__restrict__ t, const uint8_t *__restrict__ mask,
+                            int N, int C, int HW, const double *__restrict__ stats, float *__restrict__ g) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)N * C * HW) return;
+    const size_t p = i % HW, n = i / ((size_t)C * HW);
+    const float scale = (float)(2.0 / stats[1]);
+    g[i] = mask[n * HW + p] ? scale * (y[i] - t[i]) : 0.f;
+}
+
+// Adam (Kingma & Ba 2015) with bias correction; c1 = 1 - b1^t, c2 = 1 - b2^t.
+__global__ void k_adam(float *__restrict__ th, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, int n, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_zero(float *__restrict__ p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.f;
+}
+
+inline unsigned nblk(size_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+template <class TI, class TO>
+hipError_t conv3x3(const View &in, const float *w, const float *bias, const View &out, int N, int cin, int cout,
+                   bool relu, hipStream_t s) {
+    const int tiles = ((in.W + TW - 1) / TW) * ((in.H + TH - 1) / TH);
+    const dim3 grid(tiles, N * ((cout + CO_T - 1) / CO_T));
+    k_conv3x3<TI, TO><<<grid, 256, 0, s>>>(in, w, bias, out, cin, cout, relu ? 1 : 0);
+    return hipGetLastError();
+}
+template hipError_t conv3x3<float, float>(const View &, const float *, const float *, const View &, int, int, int, bool, hipStream_t);
+template hipError_t conv3x3<float, __bf16>(const View &, const float *, const float *, const View &, int, int, int, bool, hipStream_t);
+template hipError_t conv3x3<__bf16, __bf16>(const View &, const float *, const float *, const View &, int, int, int, bool, hipStream_t);
+
+hipError_t flip_transpose(const float *w, float *wt, int cin, int cout, hipStream_t s) {
+    k_flip_transpose<<<nblk((size_t)cin * cout * 9), 256, 0, s>>>(w, wt, cin, cout);
+    return hipGetLastError();
+}
+
+int dw_chunks(int N, int H, int W, int cin, int cout) {
+    const int ntiles = N * ((W + TW - 1) / TW) * ((H + TH - 1) / TH);
+    const int blocks = ((cout + CO_T - 1) / CO_T) * ((cin + CI_T - 1) / CI_T);
+    // aim for >= 2048 workgroups, at least 2 tiles per chunk
+    int chunks = std::max(1, std::min(ntiles / 2, (2048 + blocks - 1) / blocks));
+    return std::max(1, chunks);
+}
+
+template <class TI>
+hipError_t conv3x3_dw(const View &x, const float *dz, int N, int cin, int cout, float *partial, int chunks,
+                      float *dw, hipStream_t s) {
+    const int ntiles = N * ((x.W + TW - 1) / TW) * ((x.H + TH - 1) / TH);
+    const int per = (ntiles + chunks - 1) / chunks;
+    const dim3 grid(chunks, (cout + CO_T - 1) / CO_T, (cin + CI_T - 1) / CI_T);
+    k_conv3x3_dw<TI><<<grid, 256, 0, s>>>(x, dz, N, cin, cout, per, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int n = cout * cin * 9;
+    k_sum_partials<<<nblk(n), 256, 0, s>>>(partial, chunks, n, dw);
+    return hipGetLastError();
+}
+template hipError_t conv3x3_dw<float>(const View &, const float *, int, int, int, float *, int, float *, hipStream_t);
+template hipError_t conv3x3_dw<__bf16>(const View &, const float *, int, int, int, float *, int, float *, hipStream_t);
+
+hipError_t bias_grad(const float *dz, int N, int C, int HW, float *db, hipStream_t s) {
+    k_bias_grad<<<C, 256, 0, s>>>(dz, N, C, HW, db);
+    return hipGetLastError();
+}
+
+template <class TA>
+hipError_t relu_mask(const View &g, const View &y, int N, int C, float *dz, hipStream_t s) {
+    k_relu_mask<TA><<<nblk((size_t)N * C * y.H * y.W), 256, 0, s>>>(g, y, N, C, dz);
+    return hipGetLastError();
+}
+template hipError_t relu_mask<float>(const View &, const View &, int, int, float *, hipStream_t);
+template hipError_t relu_mask<__bf16>(const View &, const View &, int, int, float *, hipStream_t);
+
+template <class TA>
+hipError_t pool(const View &in, const View &out, int N, int C, hipStream_t s) {
+    k_pool<TA><<<nblk((size_t)N * C * out.H * out.W), 256, 0, s>>>(in, out, N, C);
+    return hipGetLastError();
+}
+template hipError_t pool<float>(const View &, const View &, int, int, hipStream_t);
+template hipError_t pool<__bf16>(const View &, const View &, int, int, hipStream_t);
+
+hipError_t pool_back_acc(const View &dy, const View &dx, int N, int C, hipStream_t s) {
+    k_pool_back_acc<<<nblk((size_t)N * C * dx.H * dx.W), 256, 0, s>>>(dy, dx, N, C);
+    return hipGetLastError();
+}
+
+template <class TA>
+hipError_t up(const View &in, const View &out, int N, int C, hipStream_t s) {
+    k_up<TA><<<nblk((size_t)N * C * out.H * out.W), 256, 0, s>>>(in, out, N, C);
+    return hipGetLastError();
+}
+template hipError_t up<float>(const View &, const View &, int, int, hipStream_t);
+template hipError_t up<__bf16>(const View &, const View &, int, int, hipStream_t);
+
+hipError_t up_back(const View &dy, const View &dx, int N, int C, hipStream_t s) {
+    k_up_back<<<nblk((size_t)N * C * dx.H * dx.W), 256, 0, s>>>(dy, dx, N, C);
+    return hipGetLastError();
+}
+
+template <class TA>
+hipError_t conv1x1(const View &in, const float *w, const float *b, int N, int cin, int cout, float *out,
+                   hipStream_t s) {
+    k_conv1x1<TA><<<nblk((size_t)N * in.H * in.W), 256, 0, s>>>(in, w, b, N, cin, cout, out);
+    return hipGetLastError();
+}
+template hipError_t conv1x1<float>(const View &, const float *, const float *, int, int, int, float *, hipStream_t);
+template hipError_t conv1x1<__bf16>(const View &, const float *, const float *, int, int, int, float *, hipStream_t);
+
+hipError_t conv1x1_dx(const float *g, const float *w, int N, int cin, int cout, int HW, const View &dx,
+                      hipStream_t s) {
+    k_conv1x1_dx<<<nblk((size_t)N * HW), 256, 0, s>>>(g, w, N, cin, cout, HW, dx);
+    return hipGetLastError();
+}
+
+template <class TA>
+hipError_t conv1x1_dw(const View &x, const float *g, int N, int cin, int cout, float *dw, float *db,
+                      hipStream_t s) {
+    k_conv1x1_dw<TA><<<cout * (cin + 1), 256, 0, s>>>(x, g, N, cin, cout, dw, db);
+    return hipGetLastError();
+}
+template hipError_t conv1x1_dw<float>(const View &, const float *, int, int, int, float *, float *, hipStream_t);
+template hipError_t conv1x1_dw<__bf16>(const View &, const float *, int, int, int, float *, float *, hipStream_t);
+
+constexpr int LOSS_BLOCKS = 256;
+int loss_blocks() { return LOSS_BLOCKS; }
+
+hipError_t loss_and_grad(const float *y, const float *t, const uint8_t *mask, int N, int C, int HW, double *part,
+                         double *stats, float *g, hipStream_t s) {
+    k_loss_partial<<<LOSS_BLOCKS, 256, 0, s>>>(y, t, mask, N, C, HW, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_loss_final<<<1, 64, 0, s>>>(part, LOSS_BLOCKS, stats);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (g) k_loss_grad<<<nblk((size_t)N * C * HW), 256, 0, s>>>(y, t, mask, N, C, HW, stats, g);
+    return hipGetLastError();
+}
+
+hipError_t adam(float *th, const float *g, float *m, float *v, int n, float lr, float b1, float b2, float eps,
+                float c1, float c2, hipStream_t s) {
+    k_adam<<<nblk(n), 256, 0, s>>>(th, g, m, v, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t zero(float *p, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    k_zero<<<(unsigned)std::min<size_t>(4096, nblk(n)), 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+}  // namespace lbmnet

@@ -79,3 +79,36 @@ def test_adam_first_step_is_sign_step():
     g = rng.standard_normal(10)
     new, m, v = cnn.adam(th, g, np.zeros(10), np.zeros(10), 1, lr=0.01)
     np.testing.assert_allclose(th - new, 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def test_round_bf16_fixed_values():
+    """8 significant bits, ties to even, sign symmetric."""
+    r = cnn.round_bf16
+    assert r(1.0) == 1.0 and r(0.0) == 0.0
+    assert r(1 + 2.0 ** -8) == 1.0                      # tie -> even (1.0)
+    assert r(1 + 3 * 2.0 ** -8) == 1 + 2.0 ** -6        # tie -> even (1 + 4 * 2^-8)
+    assert r(1 + 2.0 ** -8 + 2.0 ** -20) == 1 + 2.0 ** -7
+    assert r(-(1 + 3 * 2.0 ** -8)) == -(1 + 2.0 ** -6)
+    assert r(3.0) == 3.0 and r(255.0) == 255.0 and r(257.0) == 256.0 and r(259.0) == 260.0
+    assert r(2.0 ** -100 * 1.00390625) == 2.0 ** -100     # scale invariance
+
+
+def test_round_bf16_matches_library_conversion():
+    """Against torch's float32 -> bfloat16 conversion (round to nearest even) on
+    values exactly representable in float32."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(9)
+    a = (rng.standard_normal(20000) * np.exp(rng.uniform(-20, 20, 20000))).astype(np.float32)
+    lib = torch.from_numpy(a).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(cnn.round_bf16(a.astype(np.float64)), lib)
+
+
+def test_rounded_network_is_close_and_identity_is_default():
+    specs = cnn.layer_specs(chans=(3, 4, 4, 5))
+    theta = cnn.init_params(specs, seed=4)
+    x = np.random.default_rng(5).standard_normal((1, 3, 8, 16))
+    y = cnn.forward(theta, specs, x)
+    assert np.array_equal(y, cnn.forward(theta, specs, x, act=lambda a: a))
+    yb = cnn.forward(theta, specs, x, act=cnn.round_bf16)
+    err = np.linalg.norm(yb - y) / np.linalg.norm(y)
+    assert 1e-5 < err < 5e-2          # rounding is applied, and it is a small perturbation

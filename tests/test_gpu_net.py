@@ -1,0 +1,202 @@
+"""GPU tests of the warm-start network kernels (lbm_net_* through the C ABI).
+
+Forward outputs, the loss and the gradient of every layer are compared with the
+FP64 oracle (oracle/cnn.py, itself pinned to finite differences), norm-wise
+relative error per layer:
+  - FP32 activations against the FP64 network: <= 1e-5;
+  - bf16 activations against the FP64 network with the same activations
+    rounded to bf16 (the definition of that build): <= 1e-2;
+  - bf16 activations against the unrounded FP64 network: the error of storing
+    activations in bf16 (8 significant bits, 2^-9 relative per rounding, grown
+    through 15 layers and amplified where few pixels feed a gradient, as at the
+    2 x 8 bottom level): forward <= 2e-2, gradients <= 1e-1.
+Shapes are chosen ragged: channel counts that are not multiples of the 8 x 16
+channel tiles and coarse levels smaller than one 8 x 32 pixel tile.
+"""
+import numpy as np
+import pytest
+
+import oracle.cnn as CNN
+
+pytestmark = pytest.mark.gpu
+
+SMALL = dict(H=16, W=64, chans=(12, 20, 24, 16))
+
+
+@pytest.fixture(scope="module")
+def net():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0708_4182_amd import net as N
+    N.load_library()
+    return N
+
+
+def problem(H, W, n, chans, seed):
+    """Random inputs, targets, a fluid mask with walls and He-initialised params."""
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, 3, H, W))
+    x[:, 0] = rng.random((n, H, W)) < 0.2
+    t = rng.standard_normal((n, 3, H, W))
+    fluid = rng.random((n, H, W)) > 0.25
+    specs = CNN.layer_specs(3, 3, chans)
+    theta = CNN.init_params(specs, seed)
+    # nonzero biases so that the bias paths are exercised
+    o = 0
+    for _, ci, co, k in specs:
+        o += co * ci * k * k
+        theta[o:o + co] = 0.05 * rng.standard_normal(co)
+        o += co
+    theta = theta.astype(np.float32).astype(np.float64)
+    return x.astype(np.float32), t.astype(np.float32), fluid.astype(np.uint8), specs, theta
+
+
+def to_dev(*arrs):
+    import torch
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
+
+
+def layer_errors(a, b, specs):
+    """Norm-wise relative error of every weight and bias block."""
+    out, o = {}, 0
+    for name, ci, co, k in specs:
+        for part, n in (("W", co * ci * k * k), ("b", co)):
+            ref = b[o:o + n]
+            out[f"{name}.{part}"] = np.linalg.norm(a[o:o + n] - ref) / max(np.linalg.norm(ref), 1e-30)
+            o += n
+    return out
+
+
+ROUND = {False: dict(), True: dict(act=CNN.round_bf16)}
+
+
+@pytest.mark.parametrize("bf16,tol", [(False, 1e-5), (True, 1e-2)])
+def test_forward_matches_oracle(net, bf16, tol):
+    x, t, fluid, specs, theta = problem(n=3, seed=1, **SMALL)
+    m = net.Net(SMALL["H"], SMALL["W"], 3, chans=SMALL["chans"], act_bf16=bf16)
+    m.set_params(theta)
+    (xd,) = to_dev(x)
+    y = m.forward(xd).cpu().numpy()
+    ref = CNN.forward(theta, specs, x.astype(np.float64), **ROUND[bf16])
+    err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    print(f"forward bf16={bf16} rel={err:.3e}")
+    assert err <= tol
+    if bf16:
+        plain = CNN.forward(theta, specs, x.astype(np.float64))
+        e = np.linalg.norm(y - plain) / np.linalg.norm(plain)
+        print(f"forward bf16 vs unrounded rel={e:.3e}")
+        assert e <= 2e-2
+    # fewer samples than the batch: same values for those samples
+    y2 = m.forward(xd[:1].contiguous()).cpu().numpy()
+    np.testing.assert_array_equal(y2[0], y[0])
+
+
+@pytest.mark.parametrize("bf16,tol", [(False, 1e-5), (True, 1e-2)])
+def test_gradient_matches_oracle(net, bf16, tol):
+    x, t, fluid, specs, theta = problem(n=2, seed=2, **SMALL)
+    m = net.Net(SMALL["H"], SMALL["W"], 2, chans=SMALL["chans"], act_bf16=bf16)
+    m.set_params(theta)
+    loss, g = m.gradient(*to_dev(x, t, fluid))
+    args = (theta, specs, x.astype(np.float64), t.astype(np.float64), fluid.astype(bool))
+    ref_loss, ref_g = CNN.backward(*args, **ROUND[bf16])
+    assert abs(loss - ref_loss) <= tol * ref_loss
+    errs = layer_errors(g.astype(np.float64), ref_g, specs)
+    worst = max(errs, key=errs.get)
+    print(f"gradient bf16={bf16} worst {worst} {errs[worst]:.3e}")
+    assert errs[worst] <= tol, errs
+    if bf16:
+        _, plain_g = CNN.backward(*args)
+        e = layer_errors(g.astype(np.float64), plain_g, specs)
+        w = max(e, key=e.get)
+        print(f"gradient bf16 vs unrounded worst {w} {e[w]:.3e}")
+        assert e[w] <= 1e-1, e
+
+
+def test_gradient_is_deterministic(net):
+    x, t, fluid, specs, theta = problem(n=2, seed=3, **SMALL)
+    m = net.Net(SMALL["H"], SMALL["W"], 2, chans=SMALL["chans"])
+    m.set_params(theta)
+    d = to_dev(x, t, fluid)
+    l1, g1 = m.gradient(*d)
+    l2, g2 = m.gradient(*d)
+    assert l1 == l2
+    np.testing.assert_array_equal(g1, g2)
+
+
+def test_full_size_matches_oracle(net):
+    """The warm-start configuration itself (64 x 256, channels 32/64/128/128),
+    one sample, FP32 activations.
+
+    At this size about 40 pre-activations lie within 1e-5 rms of zero (the
+    oracle counts them below), closer than the FP32 rounding of a 1152- to
+    2304-term sum, so FP32 takes the other ReLU branch at a few of them.  The
+    forward output is continuous across such a flip and keeps the 1e-5 bar, as
+    does the output layer's gradient, which no flip reaches; the gradient of a
+    layer at or below a flipped node moves by about 1e-4 (bar: 1e-3).  The
+    small ragged cases above have no such node and hold 1e-5 on every layer."""
+    H, W, chans = 64, 256, (32, 64, 128, 128)
+    x, t, fluid, specs, theta = problem(H, W, 1, chans, seed=4)
+    m = net.Net(H, W, 1, chans=chans, act_bf16=False)
+    m.set_params(theta)
+    d = to_dev(x, t, fluid)
+    y = m.forward(d[0]).cpu().numpy()
+    loss, g = m.gradient(*d)
+    x64 = x.astype(np.float64)
+    y_ref, cache = CNN.forward(theta, specs, x64, keep=True)
+    ambiguous = sum(int((np.abs(z) < 1e-5 * np.sqrt((z ** 2).mean())).sum())
+                    for name, *_ in specs[:-1] for z in [cache[name][1]])
+    e_fwd = np.linalg.norm(y - y_ref) / np.linalg.norm(y_ref)
+    ref_loss, ref_g = CNN.backward(theta, specs, x64, t.astype(np.float64), fluid.astype(bool))
+    errs = layer_errors(g.astype(np.float64), ref_g, specs)
+    worst = max(errs, key=errs.get)
+    print(f"full-size forward {e_fwd:.3e}, ambiguous ReLU decisions {ambiguous}, "
+          f"gradient worst {worst} {errs[worst]:.3e}, out.W {errs['out.W']:.3e}")
+    print("  " + " ".join(f"{k}={v:.1e}" for k, v in errs.items()))
+    assert e_fwd <= 1e-5
+    assert abs(loss - ref_loss) <= 1e-5 * ref_loss
+    assert errs["out.W"] <= 1e-5 and errs["out.b"] <= 1e-5
+    assert errs[worst] <= 1e-3, errs
+
+
+def test_adam_step_matches_oracle(net):
+    x, t, fluid, specs, theta = problem(n=2, seed=5, **SMALL)
+    m = net.Net(SMALL["H"], SMALL["W"], 2, chans=SMALL["chans"])
+    m.set_params(theta)
+    d = to_dev(x, t, fluid)
+    th = theta.astype(np.float32).astype(np.float64)
+    mo = np.zeros_like(th)
+    vo = np.zeros_like(th)
+    for step in (1, 2, 3):
+        _, g = m.gradient(*d)
+        m.adam(lr=1e-3)
+        th, mo, vo = CNN.adam(th, g.astype(np.float64), mo, vo, step, lr=1e-3)
+        got = m.get_params().astype(np.float64)
+        np.testing.assert_allclose(got, th, rtol=1e-6, atol=1e-7)
+        th = got
+
+
+def test_training_reduces_the_loss(net):
+    """Fit a fixed small batch: the loss must fall well below its start."""
+    x, t, fluid, specs, theta = problem(n=4, seed=6, **SMALL)
+    t = (0.5 * x[:, :1] + 0.1).repeat(3, axis=1).astype(np.float32)
+    m = net.Net(SMALL["H"], SMALL["W"], 4, chans=SMALL["chans"])
+    m.set_params(theta)
+    d = to_dev(x, t, fluid)
+    first = m.train_step(*d, lr=2e-3)
+    for _ in range(150):
+        last = m.train_step(*d, lr=2e-3)
+    print(f"loss {first:.4e} -> {last:.4e}")
+    assert np.isfinite(last) and last < 0.2 * first
+
+
+def test_invalid_calls(net):
+    import torch
+    from paper_0708_4182_amd import lbm
+    m = net.Net(16, 64, 2, chans=SMALL["chans"])
+    with pytest.raises(lbm.LBMError, match="EINVAL"):
+        m.forward(torch.zeros((3, 3, 16, 64), device="cuda"))
+    with pytest.raises(lbm.LBMError, match="ESTATE"):
+        m.adam()
+    with pytest.raises(ValueError):
+        m.set_params(np.zeros(5, np.float32))

@@ -10,7 +10,7 @@ import pytest
 from paper_0708_4182_amd import inputs as I
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "lbm.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("lbm.h", "lbm_net.h")]
 
 
 @pytest.fixture(scope="module")
@@ -23,7 +23,7 @@ def lib():
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
 
@@ -35,9 +35,9 @@ def test_header_declares_the_boundary():
 
 
 def test_library_exports_every_declared_symbol(lib):
-    from paper_0708_4182_amd import lbm
+    from paper_0708_4182_amd import lbm, net
     names = declared_functions()
-    assert set(names) == set(lbm.SYMBOLS)
+    assert set(names) == set(lbm.SYMBOLS) | set(net.SYMBOLS)
     for n in names:
         assert hasattr(lib, n), n
 
@@ -135,3 +135,42 @@ def test_batch_workspace_validation(lib):
     assert lib.lbm_batch_workspace_bytes(0, arr) == 0
     bad = (lbm.lbm_params * 2)(lbm.to_c_params(ps[0]), lbm.to_c_params(ps[1].replace(tau=0.3)))
     assert lib.lbm_batch_workspace_bytes(2, bad) == 0
+
+
+def test_net_param_count_matches_the_network_definition(lib):
+    """Parameter count and layout of lbm_net.h: 15 layers, W then b each."""
+    from paper_0708_4182_amd import net
+    import oracle.cnn as CNN
+    for chans in [(32, 64, 128, 128), (12, 20, 24, 16)]:
+        n = net.param_count(H=64, W=256, batch=4, chans=chans)
+        assert n == CNN.param_count(CNN.layer_specs(3, 3, chans))
+    assert net.param_count(H=64, W=256, batch=4) == 1209411
+
+
+@pytest.mark.parametrize("bad", [dict(H=12), dict(W=4), dict(batch=0), dict(cin=0),
+                                 dict(chans=(32, 0, 8, 8))])
+def test_net_rejects_invalid_configs_without_gpu_work(lib, bad):
+    from paper_0708_4182_amd import net
+    cfg = dict(H=64, W=256, batch=2)
+    cfg.update(bad)
+    assert net.workspace_bytes(**cfg) == 0
+    assert net.param_count(**cfg) == -1
+    c = net.make_config(**cfg)
+    h = C.c_void_p()
+    assert lib.lbm_net_create(C.byref(h), C.byref(c), C.c_void_p(256), 1 << 30, None) == -1
+    assert not h.value and lib.lbm_net_last_error(None)
+
+
+def test_net_workspace_checks_without_gpu_work(lib):
+    from paper_0708_4182_amd import net
+    c = net.make_config(64, 256, 8)
+    n = net.workspace_bytes(H=64, W=256, batch=8)
+    n16 = net.workspace_bytes(H=64, W=256, batch=8, act_bf16=False)
+    assert 0 < n < n16
+    assert net.workspace_bytes(H=64, W=256, batch=16) > n
+    h = C.c_void_p()
+    assert lib.lbm_net_create(C.byref(h), C.byref(c), C.c_void_p(256 + 8), n, None) == -1
+    assert lib.lbm_net_create(C.byref(h), C.byref(c), C.c_void_p(256), n - 1, None) == -2
+    assert lib.lbm_net_forward(None, None, None, 1) == -1
+    assert lib.lbm_net_adam(None, 1e-3, 0.9, 0.999, 1e-8) == -1
+    lib.lbm_net_free(None)
