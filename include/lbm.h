@@ -50,8 +50,9 @@ typedef enum {
 } lbm_status;
 
 /* How populations are stored in device memory.  The arithmetic is FP32 in all
- * three cases.  F16 and BF16 store the deviation d_a = f_a - w_a rho0 rounded to
- * nearest even, and decode f_a = w_a rho0 + d_a in FP32. */
+ * three cases.  Each format stores the deviation d_a = f_a - w_a rho_ref from the
+ * rest populations of a reference density (lbm_params.rho_ref), rounded to
+ * nearest even, and decodes f_a = w_a rho_ref + d_a in FP32. */
 typedef enum { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 } lbm_storage;
 
 /* Electrode walls (bit set): the electric layer exists only next to these. */
@@ -70,6 +71,11 @@ typedef struct {
     uint32_t elec_walls;   /* LBM_ELEC_BOTTOM | LBM_ELEC_TOP                            */
     double accel_x, accel_y; /* driving acceleration g: body force rho g on every node */
     int32_t storage;       /* lbm_storage                                              */
+    double rho_ref;        /* storage reference density (>= 0): populations are held as
+                              d_a = f_a - w_a rho_ref; 0 selects the default, raw f for
+                              LBM_F32 and rho0 for LBM_F16 / LBM_BF16.  A value near the
+                              liquid density keeps the stored numbers small where the
+                              flow is, which FP32 needs to resolve slow velocity modes  */
 } lbm_params;
 
 typedef struct lbm_sim lbm_sim;

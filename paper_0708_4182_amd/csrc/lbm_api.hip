@@ -60,7 +60,7 @@ struct Layout {
 
 bool finite_all(const lbm_params *p) {
     const double v[] = {p->tau, p->rho0, p->g_axis, p->g_diag, p->w_axis, p->w_diag,
-                        p->rho_c, p->f_elec, p->accel_x, p->accel_y};
+                        p->rho_c, p->f_elec, p->accel_x, p->accel_y, p->rho_ref};
     for (double d : v)
         if (!std::isfinite(d)) return false;
     return true;
@@ -73,6 +73,7 @@ std::string check_params(const lbm_params *p) {
     if (!finite_all(p)) return "parameters must be finite";
     if (!(p->tau > 0.5)) return "tau must be > 0.5";
     if (!(p->rho0 > 0.0)) return "rho0 must be > 0";
+    if (!(p->rho_ref >= 0.0)) return "rho_ref must be >= 0";
     if (p->storage < LBM_F32 || p->storage > LBM_BF16) return "storage must be LBM_F32, LBM_F16 or LBM_BF16";
     if (p->elec_layers < 0 || p->elec_layers > 1024) return "elec_layers must be in [0, 1024]";
     if (p->elec_walls > 3u) return "elec_walls must be a combination of LBM_ELEC_BOTTOM and LBM_ELEC_TOP";
@@ -101,13 +102,20 @@ bool make_layout(const lbm_params *p, Layout &L) {
     return true;
 }
 
+// Reference density of the stored deviations (lbm_params.rho_ref, else the
+// format's default).
+float storage_offset(const lbm_params *p) {
+    if (p->rho_ref > 0.0) return (float)p->rho_ref;
+    return p->storage == LBM_F32 ? 0.f : (float)p->rho0;
+}
+
 Model make_model(const lbm_params *p) {
     Model m;
     m.tau = (float)p->tau;
     m.omega = (float)(1.0 / p->tau);
     m.rho0 = (float)p->rho0;
     m.inv_rho0 = (float)(1.0 / p->rho0);
-    m.rho_off = p->storage == LBM_F32 ? 0.f : (float)p->rho0;
+    m.rho_off = storage_offset(p);
     m.ga = (float)p->g_axis;
     m.gd = (float)p->g_diag;
     m.wa = (float)p->w_axis;
@@ -228,6 +236,7 @@ lbm_status do_flux(lbm_sim *s, double *Q, double *M) {
 namespace lbm {
 std::string check_params_str(const lbm_params *p) { return check_params(p); }
 Model make_model_of(const lbm_params *p) { return make_model(p); }
+float storage_offset_of(const lbm_params *p) { return storage_offset(p); }
 void derive_flags_of(const lbm_params *p, const uint8_t *solid, std::vector<uint16_t> &out) {
     derive_flags(p, solid, out);
 }
@@ -318,7 +327,7 @@ lbm_status lbm_init(lbm_sim **out, const lbm_params *p, const uint8_t *solid, co
     float *dstage = (float *)s->buf[1];
     INIT_TRY(hipMemcpyAsync(dstage, stage.data(), stage.size() * sizeof(float), hipMemcpyHostToDevice,
                             s->stream));
-    INIT_TRY(lbm::launch_init(p->storage, s->buf[0], s->flags, s->g, s->m.rho0, dstage, dstage + n,
+    INIT_TRY(lbm::launch_init(p->storage, s->buf[0], s->flags, s->g, s->m.rho_off, dstage, dstage + n,
                               dstage + 2 * n, p->nx, s->stream));
     INIT_TRY(lbm::launch_fill(s->buf[1], s->buf_bytes, s->stream));
     INIT_TRY(hipStreamSynchronize(s->stream));
@@ -335,7 +344,7 @@ lbm_status lbm_init_device(lbm_sim *s, const float *rho, const float *ux, const 
     if (!rho) return fail(s, LBM_EINVAL, "rho must not be NULL");
     DeviceGuard dg(s->device);
     HIP_TRY(s, lbm::launch_fill(s->buf[s->cur], s->buf_bytes, s->stream));
-    HIP_TRY(s, lbm::launch_init(s->p.storage, s->buf[s->cur], s->flags, s->g, s->m.rho0, rho, ux, uy,
+    HIP_TRY(s, lbm::launch_init(s->p.storage, s->buf[s->cur], s->flags, s->g, s->m.rho_off, rho, ux, uy,
                                 s->p.nx, s->stream));
     return LBM_OK;
 }

@@ -25,6 +25,7 @@ namespace lbm {
 // shared with lbm_api.hip
 std::string check_params_str(const lbm_params *p);
 Model make_model_of(const lbm_params *p);
+float storage_offset_of(const lbm_params *p);
 void derive_flags_of(const lbm_params *p, const uint8_t *solid, std::vector<uint16_t> &out);
 }  // namespace lbm
 
@@ -377,7 +378,7 @@ lbm_status lbm_batch_init(lbm_batch **out, int32_t n, const lbm_params *p, const
         if (e == hipSuccess)
             e = hipMemcpyAsync(dstage, stage.data(), 4 * stage.size(), hipMemcpyHostToDevice, b->stream);
         if (e == hipSuccess)
-            e = lbm::launch_init(b->storage, b->buf0[i], b->flags[i], g, (float)p[i].rho0, dstage, dstage + m,
+            e = lbm::launch_init(b->storage, b->buf0[i], b->flags[i], g, lbm::storage_offset_of(&p[i]), dstage, dstage + m,
                                  dstage + 2 * m, g.nx, b->stream);
         if (e == hipSuccess) e = lbm::launch_fill(b->buf1[i], align_up(bb, 16), b->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(b->stream);   // host staging is reused
@@ -450,7 +451,7 @@ lbm_status lbm_batch_moments(lbm_batch *b, int32_t i, float *rho, float *ux, flo
     const Grid &g = b->g[i];
     const size_t m = (size_t)g.nx * g.ny;
     const char *src = b->cur[i] ? b->buf1[i] : b->buf0[i];
-    const float off = b->storage == LBM_F32 ? 0.f : (float)b->p[i].rho0;
+    const float off = lbm::storage_offset_of(&b->p[i]);
     if (on_device) {
         BHIP(b, lbm::launch_moments(b->storage, src, b->flags[i], g, off, rho, ux, uy, b->stream));
         return LBM_OK;
@@ -486,7 +487,7 @@ lbm_status lbm_batch_init_device(lbm_batch *b, int32_t i, const float *rho, cons
     char *dst = b->cur[i] ? b->buf1[i] : b->buf0[i];
     const size_t bb = 9 * (size_t)g.plane * elem_size(b->storage);
     BHIP(b, lbm::launch_fill(dst, align_up(bb, 16), b->stream));
-    BHIP(b, lbm::launch_init(b->storage, dst, b->flags[i], g, (float)b->p[i].rho0, rho, ux, uy, g.nx, b->stream));
+    BHIP(b, lbm::launch_init(b->storage, dst, b->flags[i], g, lbm::storage_offset_of(&b->p[i]), rho, ux, uy, g.nx, b->stream));
     b->steps[i] = 0;
     return LBM_OK;
 }

@@ -23,7 +23,7 @@ struct Grid {
 struct Model {
     float tau, omega;          // omega = 1 / tau
     float rho0, inv_rho0;
-    float rho_off;             // 0 for FP32 storage, rho0 for deviation storage
+    float rho_off;             // reference density of the stored deviations (0: raw f)
     float ga, gd, wa, wd;      // G_a and W_a per direction class
     float rho_c, f_elec;
     float gx, gy;              // driving acceleration
@@ -71,7 +71,8 @@ struct BatchStepArgs {
 hipError_t launch_step(int storage, const StepArgs &a, int block_x, hipStream_t s);
 // Resident workgroups of the step kernel per compute unit.
 int step_blocks_per_cu(int storage, int block_x);
-hipError_t launch_init(int storage, void *dst, const uint16_t *flags, const Grid &g, float rho0,
+// f^eq(rho, u) on fluid nodes, stored as deviations from w_a * rho_off.
+hipError_t launch_init(int storage, void *dst, const uint16_t *flags, const Grid &g, float rho_off,
                        const float *rho, const float *ux, const float *uy, int dense_pitch,
                        hipStream_t s);
 hipError_t launch_fill(void *dst, size_t bytes, hipStream_t s);

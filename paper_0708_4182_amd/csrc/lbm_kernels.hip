@@ -15,8 +15,8 @@ namespace {
 
 enum { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
 
-// Storage codecs.  FP32 stores f itself; FP16/BF16 store d = f - w_a rho0,
-// rounded to nearest even by the hardware conversion.
+// Storage codecs.  Every format stores d = f - w_a rho_off (rho_off = 0 keeps
+// f itself), FP16/BF16 rounded to nearest even by the hardware conversion.
 template <int S> struct Codec;
 template <> struct Codec<ST_F32> {
     using T = float;
@@ -116,7 +116,7 @@ __device__ __forceinline__ void pull9(const typename C::T *__restrict__ src, uin
 }
 
 // eq. (2) on decoded values: s = sum d (= rho - rho_off), j = sum d e.  The
-// rest offsets w_a rho0 of deviation storage sum to rho0 and carry no momentum.
+// rest offsets w_a rho_off of the stored deviations sum to rho_off and carry no momentum.
 __device__ __forceinline__ void moments9(const float d[9], float &s, float &jx, float &jy) {
     s = (((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]))) + d[8];
     jx = (d[1] - d[3]) + ((d[5] - d[7]) + (d[8] - d[6]));
@@ -697,11 +697,10 @@ int step_blocks_per_cu(int storage, int block_x) {
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
-hipError_t launch_init(int storage, void *dst, const uint16_t *flags, const Grid &g, float rho0,
+hipError_t launch_init(int storage, void *dst, const uint16_t *flags, const Grid &g, float off,
                        const float *rho, const float *ux, const float *uy, int dense_pitch,
                        hipStream_t s) {
     const dim3 grid((g.nx + 255) / 256, g.ny);
-    const float off = storage == ST_F32 ? 0.f : rho0;
     switch (storage) {
     case ST_F32:
         k_init<ST_F32><<<grid, 256, 0, s>>>((float *)dst, flags, g, rho, ux, uy, dense_pitch, off);

@@ -5,8 +5,11 @@
                   batch, all advanced together to steady flux).
   sweep_throughput aggregate MLUPS of the batched engine on the 256-channel
                   sweep table (uneven widths, lengths, roughness, f and G).
+  warm_start      train the encoder-decoder on steady channels and compare
+                  lattice updates to steady flux, warm start against cold.
 
-Run as ``python -m paper_0708_4182_amd.experiments <name>``; prints JSON.
+Run as ``python -m paper_0708_4182_amd.experiments <name> [key=value ...]``;
+prints JSON.
 """
 from __future__ import annotations
 
@@ -63,10 +66,90 @@ def sweep_throughput(n=256, seed=0, storage=1, steps=60, warmup=20, graph=10, tu
             "achieved_GBs": 18 * es * fluid / (ms * 1e-3) / 1e9}
 
 
+def warm_start(train=4096, test=512, nx=256, ny=64, epochs=30, batch=32, lr=1e-3, lr_min=1e-5,
+               bf16=1, chans="32,64,128,128", max_steps=100_000, seed=0, out="", modes="snap",
+               params=""):
+    """Learned warm start: steady states of train + test channels (cold starts),
+    training of the encoder-decoder on the first ``train`` seeds, and the
+    warm-vs-cold comparison on the next ``test`` seeds."""
+    import os
+
+    import torch
+
+    from . import net, warmstart as WS
+
+    def log(msg):
+        print(f"# {msg}", flush=True)
+
+    chans = tuple(int(c) for c in str(chans).split(","))
+    seeds = list(range(train + test))
+    cases = [I.warm_case(s, nx=nx, ny=ny) for s in seeds]
+    log(f"{len(cases)} channels {nx}x{ny}: steady states (cold starts)")
+    data = WS.steady_states(cases, max_steps=max_steps, log=log)
+    X, fluid = WS.features(cases)
+    T = data["T"]
+    scales = WS.Scales.fit(T[:train], fluid[:train])
+    Tn = (T - scales.mean.reshape(1, 3, 1, 1)) / scales.std.reshape(1, 3, 1, 1)
+    Xd = torch.from_numpy(X).cuda()
+    Td = torch.from_numpy(Tn.astype(np.float32)).cuda()
+    Fd = torch.from_numpy(fluid).cuda()
+    model = net.Net(ny, nx, batch, chans=chans, act_bf16=bool(int(bf16)))
+    if params:
+        theta = np.load(params) if params.endswith(".npy") else np.fromfile(params, np.float32)
+        model.set_params(theta)
+        log(f"parameters loaded from {params}; no training")
+        losses, train_s, epochs = [(0, float("nan"))], float("nan"), 0
+    else:
+        model.set_params(net.he_init(net.layer_shapes(chans=chans), seed))
+        log(f"training: {model.n_params} parameters, {epochs} epochs of {train // batch} steps")
+        t0 = time.perf_counter()
+        losses = WS.train(model, Xd[:train], Td[:train], Fd[:train], epochs, batch, lr, lr_min, seed,
+                          log=log)
+        train_s = time.perf_counter() - t0
+    pred = WS.predict(model, Xd[train:], scales)
+    Ttest = torch.from_numpy(T[train:]).cuda()
+    test_mse = WS.normalised_mse(pred, Ttest, Fd[train:], scales)
+    log(f"test MSE per normalised plane {test_mse}")
+    res = {"experiment": "warm_start", "nx": nx, "ny": ny, "train": train, "test": test,
+           "epochs": epochs, "batch": batch, "bf16_activations": bool(int(bf16)), "chans": chans,
+           "params": model.n_params, "train_seconds": train_s,
+           "train_steps_per_s": epochs * (train // batch) / train_s if epochs else None,
+           "final_train_loss": losses[-1][1], "test_mse_normalised": test_mse,
+           "cold_converged": int(data["converged"].sum()), "scales": scales.to_dict(), "results": []}
+    per_seed = dict(seeds=np.array(seeds[train:]), cold=data["cold"][train:], Q=data["Q"][train:])
+    for mode in str(modes).split(","):
+        stats, warm, sur, q_end = WS.warm_vs_cold(model, scales, cases[train:], data["Q"][train:],
+                                                  data["cold"][train:], max_steps=max_steps, log=log,
+                                                  pred=pred, mode=mode)
+        res["results"].append(stats)
+        per_seed.update({f"warm_{mode}": warm, f"surrogate_{mode}": sur, f"Q_end_{mode}": q_end})
+    if out:
+        os.makedirs(out, exist_ok=True)
+        np.save(os.path.join(out, "params.npy"), model.get_params())
+        np.savez(os.path.join(out, "per_seed.npz"), **per_seed)
+        json.dump({**res, "losses": losses}, open(os.path.join(out, "warm_start.json"), "w"), indent=1)
+    return res
+
+
+def _kwargs(items):
+    kw = {}
+    for it in items:
+        k, v = it.split("=", 1)
+        try:
+            kw[k] = int(v)
+        except ValueError:
+            try:
+                kw[k] = float(v)
+            except ValueError:
+                kw[k] = v
+    return kw
+
+
 def main(argv):
     name = argv[1] if len(argv) > 1 else "flux_vs_field"
-    fn = {"flux_vs_field": flux_vs_field, "sweep_throughput": sweep_throughput}[name]
-    print(json.dumps(fn()), flush=True)
+    fn = {"flux_vs_field": flux_vs_field, "sweep_throughput": sweep_throughput,
+          "warm_start": warm_start}[name]
+    print(json.dumps(fn(**_kwargs(argv[2:]))), flush=True)
 
 
 if __name__ == "__main__":

@@ -115,7 +115,8 @@ class Params:
     elec_walls: int = ELEC_BOTTOM | ELEC_TOP
     accel_x: float = 0.0
     accel_y: float = 0.0
-    storage: int = 0  # 0 = fp32, 1 = fp16 deviations, 2 = bf16 deviations
+    storage: int = 0  # 0 = fp32, 1 = fp16, 2 = bf16
+    rho_ref: float = 0.0  # stored deviations are f - w rho_ref (0: raw f for fp32, rho0 for 16-bit)
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)
@@ -249,13 +250,20 @@ def droplet_case(f_elec: float = 0.0, seed: int = 0, nx: int = 128, ny: int = 64
 def channel_case(nx: int, ny: int, solid: np.ndarray, G: float = -5.0, f_elec: float = 0.0,
                  accel: float = 1e-6, seed: int = 0, noise_amp: float = 1e-3,
                  vapor_layer: int = 2, layers: int = 2, tau: float = 1.0, storage: int = 0,
-                 name: str = "channel") -> Case:
-    """Liquid-filled channel with a vapour layer within ``vapor_layer`` cells of the walls."""
+                 name: str = "channel", rho_ref: float | None = None) -> Case:
+    """Liquid-filled channel with a vapour layer within ``vapor_layer`` cells of the walls.
+
+    With ``rho_ref`` None, populations are stored as deviations from the rest
+    state of the majority phase (the median initial fluid density), so that the
+    stored numbers are small on most nodes; pass 0 for the format's default."""
     rv, rl = coexistence(G)
-    p = params_for_G(nx, ny, G, f_elec=f_elec, elec_layers=layers,
-                     elec_walls=ELEC_BOTTOM | ELEC_TOP, accel_x=accel, tau=tau, storage=storage)
     near = chebyshev_dilate(solid, vapor_layer)
     rho = np.where(near, rv, rl).astype(np.float64)
+    if rho_ref is None:
+        rho_ref = float(np.median(rho[solid == 0])) if (solid == 0).any() else 0.0
+    p = params_for_G(nx, ny, G, f_elec=f_elec, elec_layers=layers,
+                     elec_walls=ELEC_BOTTOM | ELEC_TOP, accel_x=accel, tau=tau, storage=storage,
+                     rho_ref=rho_ref)
     if noise_amp:
         rho = rho + noise(seed, rho.shape, noise_amp)
     return Case(p, solid, rho, name=name)
@@ -302,3 +310,26 @@ def sweep_case(row: dict, storage: int = 1, accel: float = 1e-6, noise_amp: floa
     return channel_case(nx, ny, solid, G=row["G"], f_elec=row["f_elec"], accel=accel,
                         seed=row["seed"], noise_amp=noise_amp, storage=storage,
                         name=f"sweep{row['index']}")
+
+
+def warm_row(seed: int) -> dict:
+    """Channel descriptor of the warm-start data set, drawn in order from
+    SplitMix64(seed): step height b ~ U{0..8} (steps of width 8, pitch 32),
+    field strength f ~ U(0, 3e-3), G ~ U[-5.5, -4.5], and the seed of the step
+    phases."""
+    rng = SplitMix64(seed)
+    b = rng.randint(0, 8)
+    f = 3e-3 * rng.uniform()
+    G = -5.5 + rng.uniform()
+    geo = rng.next() >> 32                  # stream of the step phases
+    return dict(seed=seed, b=b, f_elec=f, G=G, geo_seed=geo)
+
+
+def warm_case(seed: int, nx: int = 256, ny: int = 64, storage: int = 0, accel: float = 1e-6) -> Case:
+    """One 256 x 64 channel of the warm-start data set (see ``warm_row``)."""
+    row = warm_row(seed)
+    solid = periodic_bumps(nx, ny, 8, row["b"], 32, row["geo_seed"])
+    c = channel_case(nx, ny, solid, G=row["G"], f_elec=row["f_elec"], accel=accel, seed=seed,
+                     storage=storage, name=f"warm{seed}")
+    c.meta.update(row)
+    return c

@@ -31,6 +31,25 @@ def make_config(H, W, batch, cin=3, cout=3, chans=(32, 64, 128, 128), act_bf16=T
     return c
 
 
+def layer_shapes(cin=3, cout=3, chans=(32, 64, 128, 128)):
+    """(name, cin, cout, k) of the 15 layers in parameter order (lbm_net.h)."""
+    c1, c2, c3, c4 = chans
+    return [("e1a", cin, c1, 3), ("e1b", c1, c1, 3), ("e2a", c1, c2, 3), ("e2b", c2, c2, 3),
+            ("e3a", c2, c3, 3), ("e3b", c3, c3, 3), ("b_a", c3, c4, 3), ("b_b", c4, c4, 3),
+            ("d3a", c4 + c3, c3, 3), ("d3b", c3, c3, 3), ("d2a", c3 + c2, c2, 3), ("d2b", c2, c2, 3),
+            ("d1a", c2 + c1, c1, 3), ("d1b", c1, c1, 3), ("out", c1, cout, 1)]
+
+
+def he_init(shapes, seed=0) -> np.ndarray:
+    """He-normal weights (std sqrt(2 / fan_in)), zero biases; FP32 vector."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for _, ci, co, k in shapes:
+        parts.append(rng.standard_normal(co * ci * k * k) * np.sqrt(2.0 / (ci * k * k)))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts).astype(np.float32)
+
+
 _typed = False
 
 
@@ -89,6 +108,7 @@ class Net:
         lib = load_library()
         self.torch, self.lib = torch, lib
         self.H, self.W, self.batch, self.cin, self.cout = H, W, batch, cin, cout
+        self.chans = tuple(chans)
         self.cfg = make_config(H, W, batch, cin, cout, chans, act_bf16)
         self.n_params = int(lib.lbm_net_param_count(C.byref(self.cfg)))
         nbytes = int(lib.lbm_net_workspace_bytes(C.byref(self.cfg)))
@@ -117,13 +137,23 @@ class Net:
 
     close = __del__
 
-    def _inputs(self, *ts):
-        out = []
-        for t in ts:
-            if t.device.type != "cuda" or not t.is_contiguous():
+    def _inputs(self, x, t=None, fluid=None):
+        """Check device, layout, dtype and shape: the kernels read n x (planes x
+        H x W) elements behind each pointer."""
+        torch = self.torch
+        n = x.shape[0] if x.dim() == 4 else -1
+        want = [(x, torch.float32, (n, self.cin, self.H, self.W))]
+        if t is not None:
+            want.append((t, torch.float32, (n, self.cout, self.H, self.W)))
+            want.append((fluid, torch.uint8, (n, self.H, self.W)))
+        for a, dt, shape in want:
+            if a is None or a.device.type != "cuda" or not a.is_contiguous():
                 raise ValueError("network tensors must be contiguous device tensors")
-            out.append(t)
-        return out
+            if a.dtype != dt or tuple(a.shape) != shape:
+                raise ValueError(f"expected {dt} of shape {shape}, got {a.dtype} {tuple(a.shape)}")
+        if not 1 <= n <= self.batch:
+            raise ValueError(f"batch of {n} samples; this network takes 1..{self.batch}")
+        return [a for a, _, _ in want]
 
     def set_params(self, theta):
         a = np.ascontiguousarray(theta, np.float32)

@@ -23,7 +23,7 @@ class SweepResult:
 
     def steps_to_within(self, i: int, Q_ref: float, rtol: float) -> int:
         """First recorded step after which every later record of channel i is
-        within rtol of Q_ref (the R17 'steady' time); -1 if never."""
+        within rtol of Q_ref; -1 if never."""
         hist = self.history[i]
         ok = [abs(q - Q_ref) <= rtol * abs(Q_ref) for _, q in hist]
         t = -1
@@ -36,8 +36,9 @@ class SweepResult:
 
 def run_to_steady(batch, check_every: int = 100, window: int = 1000, rtol: float = 1e-8,
                   max_steps: int = 200_000, graph_steps: int | None = None,
-                  min_steps: int = 0) -> SweepResult:
-    """Step every channel of ``batch`` until its flux is steady (see module doc)."""
+                  min_steps: int = 0, log=None, log_every: int = 5000) -> SweepResult:
+    """Step every channel of ``batch`` until its flux is steady (see module doc);
+    ``log`` (if given) receives a progress line every ``log_every`` steps."""
     n = batch.n
     if graph_steps is None:
         graph_steps = check_every if check_every % 2 == 0 else 0
@@ -71,6 +72,8 @@ def run_to_steady(batch, check_every: int = 100, window: int = 1000, rtol: float
         if done.any():
             active &= ~done
             batch.retire(~active)
+        if log and t % log_every == 0:
+            log(f"  step {t}: {int(active.sum())} of {n} channels still running")
     for i in np.nonzero(active)[0]:
         steps[i] = t
         Qfin[i] = hist[i][-1][1] if hist[i] else np.nan

@@ -194,8 +194,14 @@ def test_invalid_calls(net):
     import torch
     from paper_0708_4182_amd import lbm
     m = net.Net(16, 64, 2, chans=SMALL["chans"])
-    with pytest.raises(lbm.LBMError, match="EINVAL"):
-        m.forward(torch.zeros((3, 3, 16, 64), device="cuda"))
+    x = torch.zeros((3, 3, 16, 64), device="cuda")
+    y = torch.empty((3, 3, 16, 64), device="cuda")
+    with pytest.raises(ValueError):                      # the binding: more samples than the batch
+        m.forward(x)
+    with pytest.raises(ValueError):                      # the binding: wrong width
+        m.forward(torch.zeros((1, 3, 16, 32), device="cuda"))
+    assert m.lib.lbm_net_forward(m.h, x.data_ptr(), y.data_ptr(), 3) == -1     # the C ABI, before launching
+    assert m.lib.lbm_net_forward(m.h, None, y.data_ptr(), 1) == -1
     with pytest.raises(lbm.LBMError, match="ESTATE"):
         m.adam()
     with pytest.raises(ValueError):

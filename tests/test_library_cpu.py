@@ -55,12 +55,15 @@ def test_workspace_bytes(lib):
     assert lbm.workspace_bytes(p.replace(storage=7)) == 0
     assert lbm.workspace_bytes(p.replace(rho0=0.0)) == 0
     assert lbm.workspace_bytes(p.replace(tau=float("nan"))) == 0
+    assert lbm.workspace_bytes(p.replace(rho_ref=-1.0)) == 0
+    assert lbm.workspace_bytes(p.replace(rho_ref=float("nan"))) == 0
+    assert lbm.workspace_bytes(p.replace(rho_ref=1.8)) == n32
     # one population buffer must stay below 4 GiB (32-bit offsets)
     assert lbm.workspace_bytes(I.Params(nx=65536, ny=4096)) == 0
 
 
 @pytest.mark.parametrize("bad", [dict(nx=2), dict(tau=0.4), dict(elec_walls=4),
-                                 dict(elec_layers=-1), dict(storage=3)])
+                                 dict(elec_layers=-1), dict(storage=3), dict(rho_ref=-0.5)])
 def test_init_rejects_invalid_params_without_gpu_work(lib, bad):
     from paper_0708_4182_amd import lbm
     import numpy as np

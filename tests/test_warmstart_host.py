@@ -1,0 +1,161 @@
+"""Host logic of the learned warm start (CPU only): the steadiness rule, the
+incremental driver that applies it while stepping, the prediction guard, the
+input planes and the data-set generator."""
+import numpy as np
+import pytest
+
+from paper_0708_4182_amd import inputs as I
+from paper_0708_4182_amd import warmstart as WS
+
+
+def hist_of(q, every=100):
+    return [((k + 1) * every, float(v)) for k, v in enumerate(q)]
+
+
+def test_steady_time_exponential_approach():
+    # Q(t) = 1 + 0.1 exp(-t / 1000): within 1e-4 once 0.1 exp(-t/1000) <= 1e-4, t >= 1000 ln(1000)
+    t = np.arange(100, 30001, 100)
+    q = 1 + 0.1 * np.exp(-t / 1000.0)
+    h = [(int(a), float(b)) for a, b in zip(t, q)]
+    t_exact = 1000 * np.log(1000.0)                 # 6907.8 -> first check at 7000
+    assert WS.steady_time(h, 1.0) == 7000
+    assert t_exact < 7000
+    # the history must extend to t + hold
+    assert WS.steady_time([x for x in h if x[0] <= 11900], 1.0) == -1
+    assert WS.steady_time([x for x in h if x[0] <= 12000], 1.0) == 7000
+
+
+def test_steady_time_restarts_after_an_excursion():
+    q = np.full(200, 1.0)
+    q[:10] = 2.0
+    q[60] = 1.01                       # one check outside 1e-4 at step 6100
+    h = hist_of(q)
+    assert WS.steady_time(h, 1.0) == 6200
+    assert WS.steady_time(h, 1.0, hold=4900) == 1100     # 1100..6000 is a window of 4900
+    assert WS.steady_time(hist_of(np.full(10, 2.0)), 1.0) == -1
+    assert WS.steady_time([], 1.0) == -1
+    assert WS.steady_time(h, float("nan")) == -1
+
+
+class FakeBatch:
+    """Stands in for lbm.Batch: channel i follows Q_i(t) given as a function."""
+
+    def __init__(self, funcs):
+        self.funcs = funcs
+        self.n = len(funcs)
+        self.t = np.zeros(self.n, np.int64)
+        self.active = np.ones(self.n, bool)
+
+    def set_graph(self, k):
+        pass
+
+    def step(self, k):
+        self.t[self.active] += k
+
+    def flux_nocheck(self):
+        return np.array([f(t) for f, t in zip(self.funcs, self.t)]), np.zeros(self.n), 0
+
+    def retire(self, done):
+        self.active = ~np.asarray(done, bool)
+
+
+def test_run_until_steady_applies_the_same_rule():
+    funcs = [lambda t: 1 + 0.1 * np.exp(-t / 1000.0),
+             lambda t: 1 + 0.1 * np.exp(-t / 300.0) * np.cos(t / 200.0),
+             lambda t: 1.5,                                  # another branch: never steady
+             lambda t: float("nan") if t > 500 else 1.0]     # diverges
+    b = FakeBatch(funcs)
+    res, hist = WS.run_until_steady(b, [1.0, 1.0, 1.0, 1.0], max_steps=40000)
+    for i in range(2):
+        full = hist_of([funcs[i](t) for t in range(100, 40001, 100)])
+        assert res[i] == WS.steady_time(full, 1.0) > 0
+        assert hist[i][-1][0] == res[i] + WS.STEADY_HOLD        # retired as soon as the rule holds
+    assert res[2] == -1 and hist[2][-1][0] == 40000
+    assert res[3] == -1 and len(hist[3]) == 6                   # stopped at the first NaN
+
+
+def test_warm_fields_guard_clip_and_mass():
+    c = I.warm_case(3, nx=64, ny=32)
+    G = c.meta["G"]
+    rv, rl = I.coexistence(G)
+    fl = c.solid == 0
+    mass = float(c.rho[fl].sum())
+    rng = np.random.default_rng(1)
+    pred = np.stack([np.where(c.solid, 0.0, rl) + 0.05 * rng.standard_normal(c.solid.shape),
+                     np.full(c.solid.shape, 1e-3), np.zeros(c.solid.shape)]).astype(np.float32)
+    F = WS.warm_fields(pred, c.solid, G, mass, "raw")
+    assert F.dtype == np.float32 and F.shape == pred.shape
+    assert abs(F[0][fl].sum(dtype=np.float64) - mass) <= 1e-6 * mass     # the cold start's mass
+    assert (F[:, c.solid != 0] == 0).all()
+    np.testing.assert_allclose(F[1][fl], 1e-3, rtol=1e-6)
+    # the seeded density is a positive multiple of the clipped prediction
+    ratio = F[0][fl] / pred[0][fl]
+    assert np.allclose(ratio, ratio[0], rtol=1e-5) and ratio[0] > 0
+    bad = pred.copy()
+    bad[1, 5, 5] = np.nan
+    assert WS.warm_fields(bad, c.solid, G, mass, "raw") is None
+    assert WS.warm_fields(bad, c.solid, G, mass, "snap") is None
+    bad = pred.copy()
+    bad[0, 10, 10] = -3.0                      # clipped up to rho_v / 2 before the scaling
+    bad[0, 11, 10] = 50.0                      # clipped down to 1.5 rho_l
+    bad[1, 12, 10] = 0.7                       # velocity clipped to U_MAX
+    F = WS.warm_fields(bad, c.solid, G, mass, "raw")
+    s = mass / np.where(fl, np.clip(bad[0].astype(np.float64), 0.5 * rv, 1.5 * rl), 0).sum()
+    assert F[0, 10, 10] == pytest.approx(0.5 * rv * s, rel=1e-6)
+    assert F[0, 11, 10] == pytest.approx(1.5 * rl * s, rel=1e-6)
+    assert F[1, 12, 10] == pytest.approx(WS.U_MAX)
+    sol = pred.copy()
+    sol[:, c.solid != 0] = np.nan              # solid nodes are not looked at
+    assert WS.warm_fields(sol, c.solid, G, mass, "raw") is not None
+    assert WS.warm_fields(sol, c.solid, G, mass, "snap") is not None
+
+
+def test_warm_fields_snap_keeps_the_phase_map_and_the_mass():
+    c = I.warm_case(5, nx=64, ny=32)
+    G = c.meta["G"]
+    rv, rl = I.coexistence(G)
+    fl = c.solid == 0
+    mass = float(c.rho[fl].sum())
+    rng = np.random.default_rng(2)
+    rho = np.where(I.chebyshev_dilate(c.solid, 2), rv, rl) + 0.2 * rng.standard_normal(c.solid.shape)
+    pred = np.stack([rho, np.full(c.solid.shape, 2e-3), np.zeros(c.solid.shape)]).astype(np.float32)
+    F = WS.warm_fields(pred, c.solid, G, mass, "snap")
+    liquid = fl & (pred[0] >= 0.5 * (rv + rl))
+    vapour = fl & ~liquid
+    assert np.allclose(F[0][vapour], rv, rtol=1e-6)
+    assert np.ptp(F[0][liquid]) == 0 and abs(F[0][liquid][0] - rl) < 0.05 * rl
+    assert abs(F[0][fl].sum(dtype=np.float64) - mass) <= 1e-6 * mass
+    assert (F[0][~fl] == 0).all()
+    with pytest.raises(ValueError):
+        WS.warm_fields(pred, c.solid, G, mass, "other")
+
+
+def test_features_and_rows():
+    cases = [I.warm_case(s, nx=64, ny=32) for s in (0, 1, 2)]
+    X, fluid = WS.features(cases)
+    assert X.shape == (3, 3, 32, 64) and X.dtype == np.float32 and fluid.dtype == np.uint8
+    for i, c in enumerate(cases):
+        np.testing.assert_array_equal(X[i, 0], c.solid)
+        np.testing.assert_array_equal(fluid[i], 1 - c.solid)
+        assert np.allclose(X[i, 1], c.params.f_elec / 3e-3, rtol=1e-6)
+        assert np.allclose(X[i, 2], (c.meta["G"] + 5) / 0.5, rtol=1e-6, atol=1e-7)
+    rows = [I.warm_row(s) for s in range(4096, 4096 + 200)]
+    assert rows == [I.warm_row(s) for s in range(4096, 4096 + 200)]
+    assert {r["b"] for r in rows} == set(range(9))
+    assert all(0 <= r["f_elec"] < 3e-3 and -5.5 <= r["G"] < -4.5 for r in rows)
+    c = I.warm_case(7)
+    assert c.solid.shape == (64, 256) and c.params.elec_layers == 2 and c.params.accel_x == 1e-6
+
+
+def test_scales_fit():
+    rng = np.random.default_rng(0)
+    T = rng.standard_normal((5, 3, 8, 16)) * np.array([1, 2, 3]).reshape(1, 3, 1, 1) + 7
+    fluid = (rng.random((5, 8, 16)) > 0.3).astype(np.uint8)
+    for p in range(3):
+        T[:, p][fluid == 0] = 1e9                # solid values are ignored
+    s = WS.Scales.fit(T, fluid)
+    m = fluid.astype(bool)
+    for p in range(3):
+        assert s.mean[p] == pytest.approx(T[:, p][m].mean())
+        assert s.std[p] == pytest.approx(T[:, p][m].std())
+    assert WS.Scales.from_dict(s.to_dict()).std.tolist() == s.std.tolist()
