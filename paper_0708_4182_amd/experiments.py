@@ -67,7 +67,7 @@ def sweep_throughput(n=256, seed=0, storage=1, steps=60, warmup=20, graph=10, tu
 
 
 def warm_start(train=4096, test=512, nx=256, ny=64, epochs=30, batch=32, lr=1e-3, lr_min=1e-5,
-               bf16=1, chans="32,64,128,128", max_steps=100_000, seed=0, out="", modes="snap",
+               bf16=1, chans="32,64,128,128", max_steps=100_000, seed=0, out="", modes="flow,snap,raw",
                params=""):
     """Learned warm start: steady states of train + test channels (cold starts),
     training of the encoder-decoder on the first ``train`` seeds, and the

@@ -215,7 +215,8 @@ def normalised_mse(pred, T, fluid, scales: Scales):
 U_MAX = 0.1             # lattice speed cap for a seeded velocity (Mach ~ 0.17)
 
 
-def warm_fields(pred: np.ndarray, solid: np.ndarray, G: float, mass: float, mode: str = "snap"):
+def warm_fields(pred: np.ndarray, solid: np.ndarray, G: float, mass: float, mode: str = "flow",
+                rho_cold: np.ndarray | None = None):
     """Initial (rho, ux, uy) [3][ny][nx] float32 from a prediction, or None if
     the prediction is not finite on the fluid.
 
@@ -226,7 +227,9 @@ def warm_fields(pred: np.ndarray, solid: np.ndarray, G: float, mass: float, mode
       - mode "snap": each fluid node takes the phase of its predicted density
         (vapour below the mean of rho_v and rho_l, liquid otherwise) at the
         coexistence density rho_v, and the liquid density is set so that the
-        mass is ``mass``: a sharp phase map like the cold start's.
+        mass is ``mass``: a sharp phase map like the cold start's;
+      - mode "flow": the cold start's own density ``rho_cold`` (so its phase
+        map and mass), with the predicted velocity.
     The velocity is clipped to |u_x|, |u_y| <= U_MAX; solid nodes get 0."""
     fl = solid == 0
     if not all(np.isfinite(pred[p][fl]).all() for p in range(3)):
@@ -243,6 +246,8 @@ def warm_fields(pred: np.ndarray, solid: np.ndarray, G: float, mass: float, mode
         if not rho_l > 0:
             return None
         rho = np.where(liquid, rho_l, np.where(vapour, rv, 0.0))
+    elif mode == "flow":
+        rho = np.where(fl, rho_cold, 0.0)
     else:
         raise ValueError(f"unknown mode {mode!r}")
     ux = np.where(fl, np.clip(pred[1], -U_MAX, U_MAX), 0.0)
@@ -252,7 +257,7 @@ def warm_fields(pred: np.ndarray, solid: np.ndarray, G: float, mass: float, mode
 
 # -------------------------------------------------------------------- evaluation
 def warm_vs_cold(model, scales: Scales, cases, Q_inf, cold, max_steps: int = 100_000, log=None,
-                 pred=None, mode: str = "snap"):
+                 pred=None, mode: str = "flow"):
     """Warm-start every case from the network and time it to steadiness against
     the cold start's Q_inf; ``cold`` holds the cold start's steady steps."""
     import torch
@@ -266,7 +271,7 @@ def warm_vs_cold(model, scales: Scales, cases, Q_inf, cold, max_steps: int = 100
     seeded = []
     for i, c in enumerate(cases):
         mass = float(c.rho[c.solid == 0].sum())
-        F = warm_fields(P[i], c.solid, c.meta["G"], mass, mode)
+        F = warm_fields(P[i], c.solid, c.meta["G"], mass, mode, rho_cold=c.rho)
         if F is not None:
             Fd = torch.from_numpy(F).to(pred.device)
             seeded.append(Fd)

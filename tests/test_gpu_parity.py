@@ -241,8 +241,10 @@ def test_divergence_is_reported(lbm):
 
 
 # Bounds from the error the storage format itself causes: the FP64 oracle with
-# its populations rounded to the same 16-bit deviations after every step gives
-# err_rho = 1.3e-3 (FP16) and 8.8e-2 (BF16) on this case at 300 steps.
+# its populations rounded to the same 16-bit deviations (from w_a rho_l, the
+# case's storage reference) after every step gives err_rho / err_u =
+# 1.1e-3 / 7.1e-3 (FP16) and 3.3e-2 / 7.2e-2 (BF16) on this case at 300 steps;
+# the GPU measures 8.1e-4 / 7.3e-3 and 3.6e-2 / 7.2e-2.
 @pytest.mark.parametrize("storage,bound", [(1, 1e-2), (2, 0.15)])
 def test_low_precision_storage_error_is_bounded(lbm, storage, bound):
     """FP16/BF16 deviation storage against the FP64 oracle (the printed numbers

@@ -128,6 +128,9 @@ def test_warm_fields_snap_keeps_the_phase_map_and_the_mass():
     assert (F[0][~fl] == 0).all()
     with pytest.raises(ValueError):
         WS.warm_fields(pred, c.solid, G, mass, "other")
+    F = WS.warm_fields(pred, c.solid, G, mass, "flow", rho_cold=c.rho)
+    np.testing.assert_array_equal(F[0], c.rho.astype(np.float32))
+    np.testing.assert_allclose(F[1][fl], 2e-3, rtol=1e-6)
 
 
 def test_features_and_rows():
