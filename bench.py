@@ -58,11 +58,13 @@ def time_storage(case, storage, steps, warmup, tile):
     c = case.params.replace(storage=storage)
     sim = lbm.Simulation(c, case.solid, case.rho, case.ux, case.uy)
     if tile:
-        sim.set_tile(*tile)
-        chosen = list(tile)
+        kernel, bx, rows = tile
+        sim.set_kernel(kernel)
+        sim.set_tile(bx, rows)
+        chosen = [bx, rows, kernel]
     else:
-        bx, rows, us, cached = autotune.tune(sim, reps=5, cache=None)
-        chosen = [bx, rows]
+        kernel, bx, rows, us, cached = autotune.tune(sim, reps=5, cache=None)
+        chosen = [bx, rows, kernel]
     sim.step(warmup)
     sim.flux()
     torch.cuda.synchronize()
@@ -130,7 +132,8 @@ def main():
     ap.add_argument("--nx", type=int, default=8192)
     ap.add_argument("--ny", type=int, default=2048)
     ap.add_argument("--tile", default="auto",
-                    help="block_x x rows (e.g. 512x64; rows 0 = one wave of workgroups) or 'auto'")
+                    help="[kernel:]block_x x rows, e.g. 512x64 or split:128x0 (rows 0 = one wave of "
+                         "workgroups; kernel fused or split), or 'auto'")
     ap.add_argument("--cpu-steps", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-ceiling", action="store_true")
@@ -152,7 +155,11 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    tile = None if args.tile in ("", "auto") else tuple(int(v) for v in args.tile.split("x"))
+    tile = None
+    if args.tile not in ("", "auto"):
+        kernel, _, t = args.tile.rpartition(":")
+        bx, rows = (int(v) for v in t.split("x"))
+        tile = (kernel or "fused", bx, rows)
     case = I.random_channel_case(nx=args.nx, ny=args.ny, f_elec=1e-3, seed=0)
     nsites = args.nx * args.ny
     nfluid = int((case.solid == 0).sum())

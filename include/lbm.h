@@ -131,19 +131,34 @@ lbm_status lbm_geometry(lbm_sim *sim, uint16_t *flags);
  * re-initialising (parameter sweeps).  Takes effect at the next lbm_step. */
 lbm_status lbm_set_forces(lbm_sim *sim, double f_elec, double accel_x, double accel_y);
 
-/* Kernel tile: block_x columns per workgroup (64, 128, 256 or 512) and about
+/* Kernel tile: block_x columns per workgroup (64, 128, 256 or 512; 128 or 256
+ * for the split kernel) and about
  * rows_per_block rows marched by one workgroup; 0 picks as many row chunks as
  * fill one wave of resident workgroups (chunks of at least 8 rows).  Results
  * do not depend on the tile (bitwise).  Default 256 x 0.  Takes effect at the
  * next lbm_step. */
 lbm_status lbm_set_tile(lbm_sim *sim, int32_t block_x, int32_t rows_per_block);
 
-/* Autotuner: times each candidate tile (block_x in 64..512, rows_per_block in
- * {0, 32, 64, 128}) for `reps` launches on the current state and keeps the
- * fastest.  The trial launches write only the spare population buffer, so the
- * simulation state and step count are unchanged.  Synchronizes.  The chosen
- * tile and its time per step (microseconds) are returned through the non-NULL
- * pointers. */
+/* Step kernel.  LBM_KERNEL_FUSED: every thread loads, computes and stores its
+ * column.  LBM_KERNEL_SPLIT: one producer wave per workgroup streams the pulled
+ * rows into LDS two rows ahead with direct-to-LDS loads and block_x compute
+ * threads only read LDS and store (block_x 128 or 256; selecting it with
+ * another block_x sets block_x to 128).  Both give bitwise the same results.
+ * Default LBM_KERNEL_FUSED.  Takes effect at the next lbm_step. */
+#define LBM_KERNEL_FUSED 0
+#define LBM_KERNEL_SPLIT 1
+lbm_status lbm_set_kernel(lbm_sim *sim, int32_t kernel);
+
+/* The current kernel, block_x and rows_per_block (any pointer may be NULL). */
+lbm_status lbm_get_tile(const lbm_sim *sim, int32_t *kernel, int32_t *block_x, int32_t *rows_per_block);
+
+/* Autotuner: times each candidate (fused kernel: block_x in 64..512; split
+ * kernel: block_x 128 or 256; rows_per_block in {0, 32, 64, 128}) for `reps`
+ * launches on the current state and keeps the fastest.  The trial launches
+ * write only the spare population buffer, so the simulation state and step
+ * count are unchanged.  Synchronizes.  The chosen tile and its time per step
+ * (microseconds) are returned through the non-NULL pointers; lbm_get_tile
+ * tells the chosen kernel. */
 lbm_status lbm_autotune(lbm_sim *sim, int32_t reps, int32_t *block_x, int32_t *rows_per_block,
                         float *us_per_step);
 

@@ -39,16 +39,20 @@ def _save(path: str, data: dict) -> None:
 
 
 def tune(sim, reps: int = 5, cache: str | None = CACHE, refresh: bool = False):
-    """Set the fastest tile on ``sim``; returns (block_x, rows, us_per_step, cached)."""
+    """Set the fastest kernel and tile on ``sim``; returns
+    (kernel, block_x, rows, us_per_step, cached)."""
     key = f"{_arch(sim)}/storage{int(sim.params.storage)}/{sim.nx}x{sim.ny}"
     data = _load(cache) if cache else {}
-    if not refresh and key in data:
-        bx, rows, us = data[key]
+    entry = data.get(key)
+    if not refresh and isinstance(entry, list) and len(entry) == 4:
+        kernel, bx, rows, us = entry
+        sim.set_kernel(str(kernel))
         sim.set_tile(int(bx), int(rows))
-        return int(bx), int(rows), float(us), True
+        return str(kernel), int(bx), int(rows), float(us), True
     bx, rows, us = sim.autotune(reps)
+    kernel = sim.tile()[0]
     if cache:
         data = _load(cache)
-        data[key] = [bx, rows, us]
+        data[key] = [kernel, bx, rows, us]
         _save(cache, data)
-    return bx, rows, us, False
+    return kernel, bx, rows, us, False

@@ -35,6 +35,7 @@ struct lbm_sim {
     int64_t steps = 0;
     int block_x = 256;
     int rows = 0;          // rows per chunk; 0 = one wave of resident workgroups
+    int kernel = LBM_KERNEL_FUSED;
     int cus = 0;           // compute units of the device
     int chunks = 0;        // cached tiling (0 = recompute)
     lbm_status sticky = LBM_OK;
@@ -359,7 +360,9 @@ lbm::StepArgs step_args(lbm_sim *s) {
             chunks = (s->p.ny + s->rows - 1) / s->rows;
         } else {
             // one wave of resident workgroups, chunks of at least 8 rows
-            const int cap = s->cus * lbm::step_blocks_per_cu(s->p.storage, s->block_x);
+            const int per_cu = s->kernel == LBM_KERNEL_SPLIT ? lbm::split_blocks_per_cu(s->p.storage, s->block_x)
+                                                             : lbm::step_blocks_per_cu(s->p.storage, s->block_x);
+            const int cap = s->cus * per_cu;
             chunks = std::max(1, cap / strips);
             chunks = std::min(chunks, std::max(1, s->p.ny / 8));
         }
@@ -376,6 +379,11 @@ lbm::StepArgs step_args(lbm_sim *s) {
     a.dst = s->buf[s->cur ^ 1];
     return a;
 }
+
+hipError_t launch(const lbm_sim *s, const lbm::StepArgs &a) {
+    return s->kernel == LBM_KERNEL_SPLIT ? lbm::launch_step_split(s->p.storage, a, s->block_x, s->stream)
+                                         : lbm::launch_step(s->p.storage, a, s->block_x, s->stream);
+}
 }  // namespace
 
 lbm_status lbm_step(lbm_sim *s, int64_t nsteps) {
@@ -387,7 +395,7 @@ lbm_status lbm_step(lbm_sim *s, int64_t nsteps) {
     for (int64_t k = 0; k < nsteps; ++k) {
         a.src = s->buf[s->cur];
         a.dst = s->buf[s->cur ^ 1];
-        HIP_TRY(s, lbm::launch_step(s->p.storage, a, s->block_x, s->stream));
+        HIP_TRY(s, launch(s, a));
         s->cur ^= 1;
         ++s->steps;
     }
@@ -452,10 +460,31 @@ lbm_status lbm_set_tile(lbm_sim *s, int32_t block_x, int32_t rows) {
     if (st) return st;
     if (block_x != 64 && block_x != 128 && block_x != 256 && block_x != 512)
         return fail(s, LBM_EINVAL, "block_x must be 64, 128, 256 or 512");
+    if (s->kernel == LBM_KERNEL_SPLIT && block_x != 128 && block_x != 256)
+        return fail(s, LBM_EINVAL, "the split kernel takes block_x 128 or 256");
     if (rows < 0) return fail(s, LBM_EINVAL, "rows_per_block must be >= 0");
     s->block_x = block_x;
     s->rows = rows;
     s->chunks = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_kernel(lbm_sim *s, int32_t kernel) {
+    lbm_status st = usable(s);
+    if (st) return st;
+    if (kernel != LBM_KERNEL_FUSED && kernel != LBM_KERNEL_SPLIT)
+        return fail(s, LBM_EINVAL, "kernel must be LBM_KERNEL_FUSED or LBM_KERNEL_SPLIT");
+    s->kernel = kernel;
+    if (kernel == LBM_KERNEL_SPLIT && s->block_x != 128 && s->block_x != 256) s->block_x = 128;
+    s->chunks = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_tile(const lbm_sim *s, int32_t *kernel, int32_t *block_x, int32_t *rows) {
+    if (!s) return LBM_EINVAL;
+    if (kernel) *kernel = s->kernel;
+    if (block_x) *block_x = s->block_x;
+    if (rows) *rows = s->rows;
     return LBM_OK;
 }
 
@@ -464,7 +493,9 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *row
     if (st) return st;
     if (reps < 1) return fail(s, LBM_EINVAL, "reps must be >= 1");
     DeviceGuard dg(s->device);
-    static const int kBX[] = {64, 128, 256, 512};
+    struct Cand { int kernel, bx; };
+    static const Cand kCand[] = {{LBM_KERNEL_FUSED, 64}, {LBM_KERNEL_FUSED, 128}, {LBM_KERNEL_FUSED, 256},
+                                 {LBM_KERNEL_FUSED, 512}, {LBM_KERNEL_SPLIT, 128}, {LBM_KERNEL_SPLIT, 256}};
     static const int kRows[] = {0, 32, 64, 128};
     hipEvent_t e0, e1;
     HIP_TRY(s, hipEventCreate(&e0));
@@ -472,22 +503,24 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *row
         (void)hipEventDestroy(e0);
         return fail(s, LBM_EDEVICE, "hipEventCreate failed");
     }
-    const int keep_bx = s->block_x, keep_rows = s->rows;
+    const int keep_bx = s->block_x, keep_rows = s->rows, keep_kernel = s->kernel;
     float best = 0.f;
-    int best_bx = keep_bx, best_rows = keep_rows;
+    int best_bx = keep_bx, best_rows = keep_rows, best_kernel = keep_kernel;
     lbm_status res = LBM_OK;
-    for (int bx : kBX) {
+    for (const Cand &cand : kCand) {
+        const int bx = cand.bx;
         for (int r : kRows) {
             if (r > 0 && r >= s->p.ny) continue;
+            s->kernel = cand.kernel;
             s->block_x = bx;
             s->rows = r;
             s->chunks = 0;
             // trial launches read the current buffer and write the spare one,
             // so the state is left as it was
             lbm::StepArgs a = step_args(s);
-            hipError_t e = lbm::launch_step(s->p.storage, a, bx, s->stream);
+            hipError_t e = launch(s, a);
             if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
-            for (int k = 0; k < reps && e == hipSuccess; ++k) e = lbm::launch_step(s->p.storage, a, bx, s->stream);
+            for (int k = 0; k < reps && e == hipSuccess; ++k) e = launch(s, a);
             if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
@@ -501,13 +534,21 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *row
                 best = us;
                 best_bx = bx;
                 best_rows = r;
+                best_kernel = cand.kernel;
             }
         }
         if (res != LBM_OK) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (res != LBM_OK) return res;
+    if (res != LBM_OK) {
+        s->kernel = keep_kernel;
+        s->block_x = keep_bx;
+        s->rows = keep_rows;
+        s->chunks = 0;
+        return res;
+    }
+    s->kernel = best_kernel;
     s->block_x = best_bx;
     s->rows = best_rows;
     s->chunks = 0;

@@ -71,6 +71,10 @@ struct BatchStepArgs {
 hipError_t launch_step(int storage, const StepArgs &a, int block_x, hipStream_t s);
 // Resident workgroups of the step kernel per compute unit.
 int step_blocks_per_cu(int storage, int block_x);
+// The split step (a producer wave streams rows into LDS for block_x compute
+// threads; block_x = 128 or 256) and its resident workgroups per compute unit.
+hipError_t launch_step_split(int storage, const StepArgs &a, int block_x, hipStream_t s);
+int split_blocks_per_cu(int storage, int block_x);
 // f^eq(rho, u) on fluid nodes, stored as deviations from w_a * rho_off.
 hipError_t launch_init(int storage, void *dst, const uint16_t *flags, const Grid &g, float rho_off,
                        const float *rho, const float *ux, const float *uy, int dense_pitch,

@@ -402,6 +402,218 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs a) {
     step_tile<S>(a.src, a.dst, a.flags, a.g, a.m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring);
 }
 
+// ---------------------------------------------------------------------------
+// Split step: the arithmetic of step_tile, bitwise, with the HBM reads moved
+// to a producer wave.
+//
+// A wave that both loads and stores cannot keep loads in flight across its
+// own waits: its stores and loads share one counter, so waiting for a load
+// also waits for every store before it.  Here the BX compute threads (the
+// consumer waves) only read LDS and store, and one producer wave only loads:
+// it streams each pulled row straight into an LDS ring with direct-to-LDS
+// buffer loads, two rows ahead of the consumers, and its waits count loads
+// only.  Per row the producer resolves the bounce-back addresses from the flag
+// words (loaded two rows ahead into registers) and also copies the flag words
+// into LDS for the consumers.  One workgroup barrier per row, as in step_tile.
+//
+// LDS: NR = 3 row slots of 9 x BX populations plus 18 halo populations (one
+// dword per value; 16-bit values arrive zero-extended in the low half; slots
+// 16-byte aligned for the 16-byte loads), 3 slots
+// of BX + 2 flag words, and the 4-row phi ring.
+constexpr int SPLIT_NR = 3;
+
+template <int S>
+__device__ __forceinline__ float dec_word(uint32_t w) {
+    using C = Codec<S>;
+    using T = typename C::T;
+    if constexpr (sizeof(T) == 4) return C::dec(__builtin_bit_cast(T, w));
+    else return C::dec(__builtin_bit_cast(T, (unsigned short)(w & 0xFFFFu)));
+}
+
+// Direct-to-LDS load: lane l writes lds[l] (one dword) with BYTES bytes read
+// at byte offset voff of the buffer.
+template <int BYTES>
+__device__ __forceinline__ void dma(__amdgpu_buffer_rsrc_t r, uint32_t *lds, uint32_t voff) {
+    static_assert(BYTES == 2 || BYTES == 4, "2- or 4-byte loads");
+    auto *p = (__attribute__((address_space(3))) void *)lds;
+    if constexpr (BYTES == 4) __builtin_amdgcn_raw_ptr_buffer_load_lds(r, p, 4, (int)voff, 0, 0, 0);
+    else __builtin_amdgcn_raw_ptr_buffer_load_lds(r, p, 2, (int)voff, 0, 0, 0);
+}
+
+// Wait until at most N vector-memory operations of this wave are outstanding
+// (gfx9 encoding: vmcnt in bits 3:0 and 15:14; expcnt and lgkmcnt not waited).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+template <int S, int BX>
+__global__ void __launch_bounds__(BX + 64) k_step_split(const StepArgs a) {
+    using C = Codec<S>;
+    constexpr uint32_t E = sizeof(typename C::T);
+    constexpr int NG = BX / 64;                 // column groups of a producer lane
+    constexpr int NF = NG + 1;                  // flag loads per row (own columns + halo)
+    constexpr int NP = 9 * NG + 1 + NG + 1;     // LDS loads per row (populations + flags)
+    constexpr int POPS = 9 * BX + 20;           // 18 halo values, rounded up to 16-byte slots
+    __shared__ __attribute__((aligned(16))) uint32_t pring[SPLIT_NR][POPS];
+    __shared__ uint32_t fring[SPLIT_NR][BX + 2];
+    __shared__ float psi[RING][BX + 2];
+
+    const int tile = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
+    if (tile >= a.ntiles) return;   // uniform for the workgroup, before any barrier
+    const int strip = tile / a.chunks, chunk = tile - strip * a.chunks;
+    const int y0 = (int)(((int64_t)chunk * a.g.ny) / a.chunks);
+    const int y1 = (int)(((int64_t)(chunk + 1) * a.g.ny) / a.chunks);
+    const bool up = (chunk & 1) == 0;
+    const Grid &g = a.g;
+    const Model &m = a.m;
+    const int nx = g.nx, ny = g.ny;
+    const uint32_t pitch = (uint32_t)g.pitch, plane = g.plane;
+    const int x0 = strip * BX;
+    const int nrows = y1 - y0 + 2;       // the chunk plus one halo row per side
+    const int nact = min(BX, nx - x0);
+    const int tid = threadIdx.x;
+    const int hxl = x0 == 0 ? nx - 1 : x0 - 1;
+    const int hxr = x0 + nact == nx ? 0 : x0 + nact;
+    auto row_at = [&](int i) {
+        const int r = up ? y0 - 1 + i : y1 - i;
+        return wrapi(r, ny);
+    };
+
+    if (tid >= BX) {
+        // ---- producer wave
+        const int lane = tid - BX;
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.src, 9u * plane * E);
+        const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.flags, plane * 2u);
+        uint32_t xc[NG], xmc[NG], xpc[NG];
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+            const int c = 64 * k + lane;
+            const int x = x0 + (c < nact ? c : 0);
+            xc[k] = (uint32_t)x;
+            xmc[k] = x == 0 ? nx - 1 : x - 1;
+            xpc[k] = x == nx - 1 ? 0 : x + 1;
+        }
+        // halo populations: lanes 0..8 the left column, 9..17 the right one
+        const int side = lane >= 9 ? 1 : 0;
+        const int ha = lane < 18 ? lane - 9 * side : 0;
+        const int hx = side ? hxr : hxl;
+        const uint32_t hsx = (uint32_t)wrapi(hx - kEX[ha], nx);
+        const int hdy = -kEY[ha];
+        const uint32_t hsrcbit = kSRCBIT[ha];
+        const uint32_t hopp = (uint32_t)kOPP[ha];
+        const uint32_t hflag_x = (uint32_t)(lane == 1 ? hxr : hxl);   // flag copies: lane 0 left, 1 right
+
+        auto load_flags = [&](int yr, uint32_t (&f)[NF]) {
+            const uint32_t rb = (uint32_t)yr * pitch * 2u;
+#pragma unroll
+            for (int k = 0; k < NG; ++k) f[k] = bload_flag(rf, xc[k] * 2u, rb);
+            f[NG] = bload_flag(rf, (uint32_t)hx * 2u, rb);
+        };
+        auto issue_row = [&](int yr, int slot, const uint32_t (&f)[NF]) {
+            const int ym = yr == 0 ? ny - 1 : yr - 1, yp = yr == ny - 1 ? 0 : yr + 1;
+            const uint32_t r0 = (uint32_t)yr * pitch, rm = (uint32_t)ym * pitch, rp = (uint32_t)yp * pitch;
+            uint32_t *pr = pring[slot];
+#pragma unroll
+            for (int k = 0; k < NG; ++k) {
+                uint32_t o[9];
+                pull_offsets(f[k] & 0xFFu, plane, rm, r0, rp, xmc[k], xc[k], xpc[k], o);
+#pragma unroll
+                for (int q = 0; q < 9; ++q) dma<E>(rs, pr + q * BX + 64 * k, o[q] * E);
+            }
+            if (lane < 18) {
+                const uint32_t hrow = hdy < 0 ? rm : (hdy > 0 ? rp : r0);
+                const uint32_t off = (f[NG] & hsrcbit) ? hopp * plane + r0 + (uint32_t)hx
+                                                       : (uint32_t)ha * plane + hrow + hsx;
+                dma<E>(rs, pr + 9 * BX, off * E);
+            }
+            uint32_t *fr = fring[slot];
+#pragma unroll
+            for (int k = 0; k < NG; ++k) dma<2>(rf, fr + 64 * k, (r0 + xc[k]) * 2u);
+            if (lane < 2) dma<2>(rf, fr + BX, (r0 + hflag_x) * 2u);
+        };
+
+        // Rows are issued two ahead of the consumers: at iteration i the
+        // producer issues row i + 2 into slot (i + 2) % 3 (the slot of row
+        // i - 1, read before barrier i - 1), loads the flags of row i + 4, and
+        // waits until row i + 1 has landed before barrier i.  Past the end of
+        // the chunk the last row is issued again (cache hits), so every
+        // iteration has the same number of loads and the waits are exact.
+        // Even and odd rows keep their flags in separate registers.
+        uint32_t fe[NF], fo[NF];
+        load_flags(row_at(0), fe);
+        load_flags(row_at(1), fo);
+        issue_row(row_at(0), 0, fe);
+        load_flags(row_at(min(2, nrows - 1)), fe);
+        issue_row(row_at(1), 1, fo);
+        load_flags(row_at(min(3, nrows - 1)), fo);
+        wait_vm<2 * NF + NP>();               // row 0 has landed
+        __builtin_amdgcn_s_barrier();
+        for (int i = 0; i < nrows; i += 2) {
+            issue_row(row_at(min(i + 2, nrows - 1)), (i + 2) % SPLIT_NR, fe);
+            load_flags(row_at(min(i + 4, nrows - 1)), fe);
+            wait_vm<2 * NF + NP>();           // row i + 1 has landed
+            __builtin_amdgcn_s_barrier();
+            if (i + 1 < nrows) {
+                issue_row(row_at(min(i + 3, nrows - 1)), (i + 3) % SPLIT_NR, fo);
+                load_flags(row_at(min(i + 5, nrows - 1)), fo);
+                wait_vm<2 * NF + NP>();       // row i + 2 has landed
+                __builtin_amdgcn_s_barrier();
+            }
+        }
+        wait_vm<0>();   // no load into LDS may land after the workgroup ends
+        return;
+    }
+
+    // ---- consumer waves: one column per thread
+    const __amdgpu_buffer_rsrc_t rd = make_rsrc(a.dst, 9u * plane * E);
+    const bool act = tid < nact;
+    const uint32_t v0 = (uint32_t)(x0 + (act ? tid : 0)) * E;
+    float pd[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float ps = 0.f, pjx = 0.f, pjy = 0.f;
+    uint32_t pfl = FL_SOLID;
+    int pyr = 0;
+    lds_barrier();
+    for (int i = 0; i < nrows; ++i) {
+        const int yr = row_at(i);
+        const int sl = i % SPLIT_NR;
+        const uint32_t *pr = pring[sl];
+        float cd[9], cs = 0.f, cjx = 0.f, cjy = 0.f;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) cd[q] = dec_word<S>(pr[q * BX + tid]);
+        const uint32_t cfl = fring[sl][tid] & 0xFFFFu;
+        moments9(cd, cs, cjx, cjy);
+        float *slot = psi[i & (RING - 1)];
+        if (act) slot[tid + 1] = (cfl & FL_SOLID) ? 0.f : pseudopotential(m, m.rho_off + cs);
+        if (tid < 2) {
+            // rho of a halo node from its nine populations, in the order of moments9
+            float hd[9], hs = 0.f, hjx = 0.f, hjy = 0.f;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) hd[q] = dec_word<S>(pr[9 * BX + 9 * tid + q]);
+            const uint32_t hfl = fring[sl][BX + tid] & 0xFFFFu;
+            moments9(hd, hs, hjx, hjy);
+            slot[tid == 0 ? 0 : nact + 1] = (hfl & FL_SOLID) ? 0.f : pseudopotential(m, m.rho_off + hs);
+        }
+        lds_barrier();
+        if (i >= 2 && act && !(pfl & FL_SOLID)) {
+            const float *older = psi[(i - 2) & (RING - 1)];
+            const float *mid = psi[(i - 1) & (RING - 1)];
+            const float *rowm = up ? older : slot;
+            const float *rowp = up ? slot : older;
+            collide_store<C>(m, pd, ps, pjx, pjy, pfl, rowm, mid, rowp, tid + 1, rd, plane,
+                             (uint32_t)pyr * pitch, v0);
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) pd[q] = cd[q];
+        ps = cs;
+        pjx = cjx;
+        pjy = cjy;
+        pfl = cfl;
+        pyr = yr;
+    }
+}
+
 // Populations at t = 0: f_a = f_a^eq(rho, u) of eq. (3), written where the
 // first pull will find them (the inverse of streaming with bounce-back).
 template <int S>
@@ -682,6 +894,43 @@ hipError_t launch_step(int storage, const StepArgs &a, int block_x, hipStream_t 
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int BX>
+hipError_t launch_split_bx(int storage, const StepArgs &a, hipStream_t s) {
+    const unsigned blocks = 8u * (unsigned)a.tiles_per_xcd;
+    switch (storage) {
+    case ST_F32: k_step_split<ST_F32, BX><<<blocks, BX + 64, 0, s>>>(a); break;
+    case ST_F16: k_step_split<ST_F16, BX><<<blocks, BX + 64, 0, s>>>(a); break;
+    case ST_BF16: k_step_split<ST_BF16, BX><<<blocks, BX + 64, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_split(int storage, const StepArgs &a, int block_x, hipStream_t s) {
+    switch (block_x) {
+    case 128: return launch_split_bx<128>(storage, a, s);
+    case 256: return launch_split_bx<256>(storage, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int BX>
+int split_blocks_bx(int storage) {
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (storage) {
+    case ST_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_split<ST_F32, BX>, BX + 64, 0); break;
+    case ST_F16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_split<ST_F16, BX>, BX + 64, 0); break;
+    case ST_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_split<ST_BF16, BX>, BX + 64, 0); break;
+    default: break;
+    }
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+
+int split_blocks_per_cu(int storage, int block_x) {
+    return block_x == 128 ? split_blocks_bx<128>(storage) : split_blocks_bx<256>(storage);
 }
 
 int step_blocks_per_cu(int storage, int block_x) {

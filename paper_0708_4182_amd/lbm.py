@@ -16,12 +16,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LBM_LIB") or os.path.join(HERE, "liblbm.so")
 
 LBM_F32, LBM_F16, LBM_BF16 = 0, 1, 2
+KERNELS = {"fused": 0, "split": 1}
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
           -4: "LBM_EDIVERGED", -5: "LBM_ESTATE"}
 
 # Exported symbols of include/lbm.h (checked by the CPU tests).
 SYMBOLS = ("lbm_workspace_bytes", "lbm_init", "lbm_init_device", "lbm_step", "lbm_moments",
-           "lbm_flux", "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_autotune", "lbm_state_bytes",
+           "lbm_flux", "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_set_kernel", "lbm_get_tile",
+           "lbm_autotune", "lbm_state_bytes",
            "lbm_save_state", "lbm_load_state", "lbm_steps_done", "lbm_free", "lbm_last_error",
            "lbm_status_string", "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_step",
            "lbm_batch_flux", "lbm_batch_moments", "lbm_batch_geometry", "lbm_batch_init_device",
@@ -81,6 +83,8 @@ def load_library():
     lib.lbm_geometry.argtypes = [vp, C.POINTER(C.c_uint16)]
     lib.lbm_set_forces.argtypes = [vp, C.c_double, C.c_double, C.c_double]
     lib.lbm_set_tile.argtypes = [vp, C.c_int32, C.c_int32]
+    lib.lbm_set_kernel.argtypes = [vp, C.c_int32]
+    lib.lbm_get_tile.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.lbm_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                  C.POINTER(C.c_float)]
     lib.lbm_state_bytes.argtypes = [vp]
@@ -123,7 +127,8 @@ def load_library():
                  "lbm_batch_set_schedule", "lbm_batch_autotune"):
         getattr(lib, name).restype = C.c_int
     for name in ("lbm_init", "lbm_init_device", "lbm_step", "lbm_moments", "lbm_flux",
-                 "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_autotune", "lbm_save_state",
+                 "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_set_kernel", "lbm_get_tile",
+                 "lbm_autotune", "lbm_save_state",
                  "lbm_load_state"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -219,6 +224,17 @@ class Simulation:
 
     def set_tile(self, block_x: int, rows: int):
         self._check(self.lib.lbm_set_tile(self.h, int(block_x), int(rows)))
+
+    def set_kernel(self, kernel: str):
+        """'fused' (every thread loads, computes, stores) or 'split' (a producer
+        wave streams rows into LDS); both give bitwise the same results."""
+        self._check(self.lib.lbm_set_kernel(self.h, KERNELS[kernel]))
+
+    def tile(self):
+        """(kernel name, block_x, rows) currently in use."""
+        k, bx, r = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self.lib.lbm_get_tile(self.h, C.byref(k), C.byref(bx), C.byref(r)))
+        return {v: n for n, v in KERNELS.items()}[k.value], bx.value, r.value
 
     def autotune(self, reps: int = 5):
         """Pick the fastest tile on the device; returns (block_x, rows, us/step)."""

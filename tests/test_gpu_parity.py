@@ -153,6 +153,37 @@ def test_tile_shapes_bitwise_identical(lbm, tile):
         np.testing.assert_array_equal(x, y)
 
 
+@pytest.mark.parametrize("storage", [0, 1, 2])
+@pytest.mark.parametrize("tile", [(128, 0), (256, 0), (128, 7), (256, 64)])
+def test_split_kernel_bitwise_equals_fused(lbm, storage, tile):
+    """The producer/consumer split kernel does the fused kernel's arithmetic:
+    bitwise equal moments on every parity case, ragged ones included."""
+    for name in sorted(CASES):
+        c = CASES[name]()
+        c.params = c.params.replace(storage=storage)
+        a = lbm.from_case(c)
+        b = lbm.from_case(c)
+        b.set_kernel("split")
+        b.set_tile(*tile)
+        assert b.tile() == ("split",) + tile
+        a.step(40)
+        b.step(40)
+        for x, y in zip(a.moments(), b.moments()):
+            np.testing.assert_array_equal(x, y, err_msg=name)
+        assert a.flux() == b.flux()
+
+
+def test_split_kernel_full_size(lbm):
+    c = I.random_channel_case(nx=8192, ny=2048, seed=0)
+    a = lbm.from_case(c)
+    b = lbm.from_case(c)
+    b.set_kernel("split")
+    a.step(3)
+    b.step(3)
+    for x, y in zip(a.moments(), b.moments()):
+        np.testing.assert_array_equal(x, y)
+
+
 def test_autotune_keeps_state_and_results(lbm):
     c = CASES["ragged130x67"]()
     a = lbm.from_case(c)
