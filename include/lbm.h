@@ -140,20 +140,26 @@ lbm_status lbm_set_forces(lbm_sim *sim, double f_elec, double accel_x, double ac
 lbm_status lbm_set_tile(lbm_sim *sim, int32_t block_x, int32_t rows_per_block);
 
 /* Step kernel.  LBM_KERNEL_FUSED: every thread loads, computes and stores its
- * column.  LBM_KERNEL_SPLIT: one producer wave per workgroup streams the pulled
- * rows into LDS two rows ahead with direct-to-LDS loads and block_x compute
- * threads only read LDS and store (block_x 128 or 256; selecting it with
- * another block_x sets block_x to 128).  Both give bitwise the same results.
- * Default LBM_KERNEL_FUSED.  Takes effect at the next lbm_step. */
+ * column.  LBM_KERNEL_WIDE2 / LBM_KERNEL_WIDE4: the same with 2 or 4 adjacent
+ * columns per thread, so each plane moves as 2 or 4 values per lane (a strip
+ * of block_x threads covers 2 or 4 x block_x columns).  LBM_KERNEL_SPLIT: one
+ * producer wave per workgroup streams the pulled rows into LDS two rows ahead
+ * with direct-to-LDS loads and block_x compute threads only read LDS and store
+ * (block_x 128 or 256; selecting it with another block_x sets block_x to 128).
+ * All give bitwise the same results.  Default LBM_KERNEL_FUSED.  Takes effect
+ * at the next lbm_step. */
 #define LBM_KERNEL_FUSED 0
 #define LBM_KERNEL_SPLIT 1
+#define LBM_KERNEL_WIDE2 2
+#define LBM_KERNEL_WIDE4 3
 lbm_status lbm_set_kernel(lbm_sim *sim, int32_t kernel);
 
 /* The current kernel, block_x and rows_per_block (any pointer may be NULL). */
 lbm_status lbm_get_tile(const lbm_sim *sim, int32_t *kernel, int32_t *block_x, int32_t *rows_per_block);
 
-/* Autotuner: times each candidate (fused kernel: block_x in 64..512; split
- * kernel: block_x 128 or 256; rows_per_block in {0, 32, 64, 128}) for `reps`
+/* Autotuner: times each candidate (fused kernel: block_x in 64..512; wide
+ * kernels: block_x 64..256; split kernel: block_x 128 or 256; rows_per_block
+ * in {0, 32, 64, 128}) for `reps`
  * launches on the current state and keeps the fastest.  The trial launches
  * write only the spare population buffer, so the simulation state and step
  * count are unchanged.  Synchronizes.  The chosen tile and its time per step

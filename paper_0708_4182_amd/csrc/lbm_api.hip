@@ -351,17 +351,32 @@ lbm_status lbm_init_device(lbm_sim *s, const float *rho, const float *ux, const 
 }
 
 namespace {
+// Columns of one strip (one workgroup's width) for the handle's kernel.
+int strip_columns(const lbm_sim *s) {
+    switch (s->kernel) {
+    case LBM_KERNEL_WIDE2: return 2 * s->block_x;
+    case LBM_KERNEL_WIDE4: return 4 * s->block_x;
+    default: return s->block_x;
+    }
+}
+
 // Launch arguments of the step kernel for the handle's current tile.
 lbm::StepArgs step_args(lbm_sim *s) {
+    const int cols = strip_columns(s);
     if (s->chunks == 0) {
-        const int strips = (s->p.nx + s->block_x - 1) / s->block_x;
+        const int strips = (s->p.nx + cols - 1) / cols;
         int chunks;
         if (s->rows > 0) {
             chunks = (s->p.ny + s->rows - 1) / s->rows;
         } else {
             // one wave of resident workgroups, chunks of at least 8 rows
-            const int per_cu = s->kernel == LBM_KERNEL_SPLIT ? lbm::split_blocks_per_cu(s->p.storage, s->block_x)
-                                                             : lbm::step_blocks_per_cu(s->p.storage, s->block_x);
+            int per_cu;
+            switch (s->kernel) {
+            case LBM_KERNEL_SPLIT: per_cu = lbm::split_blocks_per_cu(s->p.storage, s->block_x); break;
+            case LBM_KERNEL_WIDE2: per_cu = lbm::wide_blocks_per_cu(s->p.storage, s->block_x, 2); break;
+            case LBM_KERNEL_WIDE4: per_cu = lbm::wide_blocks_per_cu(s->p.storage, s->block_x, 4); break;
+            default: per_cu = lbm::step_blocks_per_cu(s->p.storage, s->block_x); break;
+            }
             const int cap = s->cus * per_cu;
             chunks = std::max(1, cap / strips);
             chunks = std::min(chunks, std::max(1, s->p.ny / 8));
@@ -373,7 +388,7 @@ lbm::StepArgs step_args(lbm_sim *s) {
     a.g = s->g;
     a.m = s->m;
     a.chunks = s->chunks;
-    a.ntiles = ((s->p.nx + s->block_x - 1) / s->block_x) * s->chunks;
+    a.ntiles = ((s->p.nx + cols - 1) / cols) * s->chunks;
     a.tiles_per_xcd = (a.ntiles + 7) / 8;
     a.src = s->buf[s->cur];
     a.dst = s->buf[s->cur ^ 1];
@@ -381,8 +396,12 @@ lbm::StepArgs step_args(lbm_sim *s) {
 }
 
 hipError_t launch(const lbm_sim *s, const lbm::StepArgs &a) {
-    return s->kernel == LBM_KERNEL_SPLIT ? lbm::launch_step_split(s->p.storage, a, s->block_x, s->stream)
-                                         : lbm::launch_step(s->p.storage, a, s->block_x, s->stream);
+    switch (s->kernel) {
+    case LBM_KERNEL_SPLIT: return lbm::launch_step_split(s->p.storage, a, s->block_x, s->stream);
+    case LBM_KERNEL_WIDE2: return lbm::launch_step_wide(s->p.storage, a, s->block_x, 2, s->stream);
+    case LBM_KERNEL_WIDE4: return lbm::launch_step_wide(s->p.storage, a, s->block_x, 4, s->stream);
+    default: return lbm::launch_step(s->p.storage, a, s->block_x, s->stream);
+    }
 }
 }  // namespace
 
@@ -462,6 +481,8 @@ lbm_status lbm_set_tile(lbm_sim *s, int32_t block_x, int32_t rows) {
         return fail(s, LBM_EINVAL, "block_x must be 64, 128, 256 or 512");
     if (s->kernel == LBM_KERNEL_SPLIT && block_x != 128 && block_x != 256)
         return fail(s, LBM_EINVAL, "the split kernel takes block_x 128 or 256");
+    if ((s->kernel == LBM_KERNEL_WIDE2 || s->kernel == LBM_KERNEL_WIDE4) && block_x > 256)
+        return fail(s, LBM_EINVAL, "the wide kernels take block_x 64, 128 or 256");
     if (rows < 0) return fail(s, LBM_EINVAL, "rows_per_block must be >= 0");
     s->block_x = block_x;
     s->rows = rows;
@@ -472,10 +493,11 @@ lbm_status lbm_set_tile(lbm_sim *s, int32_t block_x, int32_t rows) {
 lbm_status lbm_set_kernel(lbm_sim *s, int32_t kernel) {
     lbm_status st = usable(s);
     if (st) return st;
-    if (kernel != LBM_KERNEL_FUSED && kernel != LBM_KERNEL_SPLIT)
-        return fail(s, LBM_EINVAL, "kernel must be LBM_KERNEL_FUSED or LBM_KERNEL_SPLIT");
+    if (kernel < LBM_KERNEL_FUSED || kernel > LBM_KERNEL_WIDE4)
+        return fail(s, LBM_EINVAL, "kernel must be one of LBM_KERNEL_FUSED, _SPLIT, _WIDE2, _WIDE4");
     s->kernel = kernel;
     if (kernel == LBM_KERNEL_SPLIT && s->block_x != 128 && s->block_x != 256) s->block_x = 128;
+    if ((kernel == LBM_KERNEL_WIDE2 || kernel == LBM_KERNEL_WIDE4) && s->block_x > 256) s->block_x = 256;
     s->chunks = 0;
     return LBM_OK;
 }
@@ -494,8 +516,10 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *row
     if (reps < 1) return fail(s, LBM_EINVAL, "reps must be >= 1");
     DeviceGuard dg(s->device);
     struct Cand { int kernel, bx; };
-    static const Cand kCand[] = {{LBM_KERNEL_FUSED, 64}, {LBM_KERNEL_FUSED, 128}, {LBM_KERNEL_FUSED, 256},
-                                 {LBM_KERNEL_FUSED, 512}, {LBM_KERNEL_SPLIT, 128}, {LBM_KERNEL_SPLIT, 256}};
+    static const Cand kCand[] = {{LBM_KERNEL_FUSED, 64},  {LBM_KERNEL_FUSED, 128}, {LBM_KERNEL_FUSED, 256},
+                                 {LBM_KERNEL_FUSED, 512}, {LBM_KERNEL_WIDE2, 64},  {LBM_KERNEL_WIDE2, 128},
+                                 {LBM_KERNEL_WIDE2, 256}, {LBM_KERNEL_WIDE4, 64},  {LBM_KERNEL_WIDE4, 128},
+                                 {LBM_KERNEL_SPLIT, 128}, {LBM_KERNEL_SPLIT, 256}};
     static const int kRows[] = {0, 32, 64, 128};
     hipEvent_t e0, e1;
     HIP_TRY(s, hipEventCreate(&e0));

@@ -75,6 +75,10 @@ int step_blocks_per_cu(int storage, int block_x);
 // threads; block_x = 128 or 256) and its resident workgroups per compute unit.
 hipError_t launch_step_split(int storage, const StepArgs &a, int block_x, hipStream_t s);
 int split_blocks_per_cu(int storage, int block_x);
+// The wide step: v = 2 or 4 adjacent columns per thread, block_x threads per
+// workgroup (block_x * v columns per strip).
+hipError_t launch_step_wide(int storage, const StepArgs &a, int block_x, int v, hipStream_t s);
+int wide_blocks_per_cu(int storage, int block_x, int v);
 // f^eq(rho, u) on fluid nodes, stored as deviations from w_a * rho_off.
 hipError_t launch_init(int storage, void *dst, const uint16_t *flags, const Grid &g, float rho_off,
                        const float *rho, const float *ux, const float *uy, int dense_pitch,

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LBM_LIB") or os.path.join(HERE, "liblbm.so")
 
 LBM_F32, LBM_F16, LBM_BF16 = 0, 1, 2
-KERNELS = {"fused": 0, "split": 1}
+KERNELS = {"fused": 0, "split": 1, "wide2": 2, "wide4": 3}
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
           -4: "LBM_EDIVERGED", -5: "LBM_ESTATE"}
 
@@ -226,8 +226,9 @@ class Simulation:
         self._check(self.lib.lbm_set_tile(self.h, int(block_x), int(rows)))
 
     def set_kernel(self, kernel: str):
-        """'fused' (every thread loads, computes, stores) or 'split' (a producer
-        wave streams rows into LDS); both give bitwise the same results."""
+        """'fused' (every thread loads, computes, stores its column), 'wide2' /
+        'wide4' (2 or 4 adjacent columns per thread) or 'split' (a producer
+        wave streams rows into LDS); all give bitwise the same results."""
         self._check(self.lib.lbm_set_kernel(self.h, KERNELS[kernel]))
 
     def tile(self):

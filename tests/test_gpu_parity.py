@@ -153,19 +153,24 @@ def test_tile_shapes_bitwise_identical(lbm, tile):
         np.testing.assert_array_equal(x, y)
 
 
+KERNEL_TILES = [("split", (128, 0)), ("split", (256, 0)), ("split", (128, 7)), ("split", (256, 64)),
+                ("wide2", (64, 0)), ("wide2", (128, 7)), ("wide2", (256, 64)),
+                ("wide4", (64, 5)), ("wide4", (128, 0))]
+
+
 @pytest.mark.parametrize("storage", [0, 1, 2])
-@pytest.mark.parametrize("tile", [(128, 0), (256, 0), (128, 7), (256, 64)])
-def test_split_kernel_bitwise_equals_fused(lbm, storage, tile):
-    """The producer/consumer split kernel does the fused kernel's arithmetic:
-    bitwise equal moments on every parity case, ragged ones included."""
+@pytest.mark.parametrize("kernel,tile", KERNEL_TILES)
+def test_kernels_bitwise_equal_fused(lbm, storage, kernel, tile):
+    """The split and wide kernels do the fused kernel's arithmetic: bitwise
+    equal moments and flux on every parity case, ragged ones included."""
     for name in sorted(CASES):
         c = CASES[name]()
         c.params = c.params.replace(storage=storage)
         a = lbm.from_case(c)
         b = lbm.from_case(c)
-        b.set_kernel("split")
+        b.set_kernel(kernel)
         b.set_tile(*tile)
-        assert b.tile() == ("split",) + tile
+        assert b.tile() == (kernel,) + tile
         a.step(40)
         b.step(40)
         for x, y in zip(a.moments(), b.moments()):
@@ -173,11 +178,12 @@ def test_split_kernel_bitwise_equals_fused(lbm, storage, tile):
         assert a.flux() == b.flux()
 
 
-def test_split_kernel_full_size(lbm):
+@pytest.mark.parametrize("kernel", ["split", "wide2", "wide4"])
+def test_kernels_full_size(lbm, kernel):
     c = I.random_channel_case(nx=8192, ny=2048, seed=0)
     a = lbm.from_case(c)
     b = lbm.from_case(c)
-    b.set_kernel("split")
+    b.set_kernel(kernel)
     a.step(3)
     b.step(3)
     for x, y in zip(a.moments(), b.moments()):
