@@ -36,15 +36,25 @@ def kernel_sha() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(storage_name: str):
+KERNEL_NAMES = {
+    "fused": "k_step (fused pull-stream + bounce-back + Shan-Chen/EWOD forces + BGK, one column per thread)",
+    "wide2": "k_step_wide<2> (the fused step, two adjacent columns per thread)",
+    "wide4": "k_step_wide<4> (the fused step, four adjacent columns per thread)",
+    "split": "k_step_split (producer wave streams rows into LDS; compute waves collide and store)",
+}
+
+
+def measured_traffic(storage_name: str, tile):
     """HBM bytes per launch from the committed rocprofv3 counter runs, or None
-    if they were taken on a different kernel source."""
+    if they were taken on a different kernel source, kernel or tile."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     e = t.get(storage_name)
     if not e or e.get("kernel_sha") != kernel_sha():
+        return None
+    if list(e.get("tile", [])) != list(tile):
         return None
     return e.get("bytes_per_launch")
 
@@ -168,7 +178,7 @@ def main():
         s = STORAGES[name]
         alg_bytes = 18 * ELEM_BYTES[s] * nfluid
         achieved = alg_bytes / (r["step_ms"] * 1e-3) / 1e9
-        traffic = measured_traffic(name)
+        traffic = measured_traffic(name, r["tile"])
         return {
             "tile": r["tile"],
             "mlups": round(nsites / (r["step_ms"] * 1e-3) / 1e6, 1),
@@ -210,7 +220,7 @@ def main():
                    "tile": main_r["tile"], "tile_choice": "fixed" if tile else "autotuned",
                    "fluid_nodes": nfluid},
         "roofline": main_line["roofline"],
-        "kernel": "k_step (fused pull-stream + bounce-back + Shan-Chen/EWOD forces + BGK)",
+        "kernel": KERNEL_NAMES[main_r["tile"][2]],
         "variants": variants,
     }
     if not args.no_batch:
