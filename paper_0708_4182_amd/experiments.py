@@ -5,6 +5,8 @@
                   batch, all advanced together to steady flux).
   sweep_throughput aggregate MLUPS of the batched engine on the 256-channel
                   sweep table (uneven widths, lengths, roughness, f and G).
+  sweep_steady    the sweep table driven to steady flux: steps, lattice
+                  updates and wall time per channel.
   warm_start      train the encoder-decoder on steady channels and compare
                   lattice updates to steady flux, warm start against cold.
 
@@ -64,6 +66,41 @@ def sweep_throughput(n=256, seed=0, storage=1, steps=60, warmup=20, graph=10, tu
             "storage": storage, "tile": tile, "graph_steps": graph, "ms_per_step": ms,
             "mlups": nodes / (ms * 1e-3) / 1e6,
             "achieved_GBs": 18 * es * fluid / (ms * 1e-3) / 1e9}
+
+
+def sweep_steady(n=256, seed=0, storage=1, max_steps=200_000, check_every=200, window=2000, rtol=1e-8):
+    """The 256-channel sweep table driven to steady flux in one batch (one
+    launch per step, hipGraph of check_every steps, channels retired as they
+    converge): per-channel steps, lattice updates and wall time."""
+    import torch
+    rows = I.sweep_table(n, seed)
+    cases = [I.sweep_case(r, storage=storage) for r in rows]
+    b = lbm.Batch(cases)
+    bx, r, us = b.autotune(reps=3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = run_to_steady(b, check_every=check_every, window=window, rtol=rtol, max_steps=max_steps,
+                        log=lambda m: print("#", m, flush=True), log_every=20_000)
+    wall = time.perf_counter() - t0
+    from .warmstart import steady_time
+    nodes = np.array([c.params.nx * c.params.ny for c in cases], np.float64)
+    widths = np.array([c.params.ny for c in cases])
+    conv = res.converged
+    # the steady time of the warm-start comparison: within 1e-4 of the final flux for 5000 steps
+    st = np.array([steady_time(res.history[i], res.Q[i]) for i in range(n)])
+    return {"experiment": "sweep_steady", "channels": n, "storage": storage, "tile": [bx, r],
+            "max_steps": max_steps, "converged": int(conv.sum()),
+            "steps_median": float(np.median(res.steps)), "steps_max": int(res.steps.max()),
+            "lattice_updates": res.node_updates, "wall_seconds": wall,
+            "steady_1e-4_found": int((st >= 0).sum()),
+            "steady_1e-4_median_steps": float(np.median(st[st >= 0])) if (st >= 0).any() else None,
+            "lattice_updates_to_steady_1e-4": float((nodes * np.where(st >= 0, st, res.steps)).sum()),
+            "mlups_during_sweep": res.node_updates / wall / 1e6,
+            "unconverged_widths": sorted(int(w) for w in widths[~conv]),
+            "converged_width_max": int(widths[conv].max()) if conv.any() else None,
+            "per_channel": [{"ny": int(c.params.ny), "nx": int(c.params.nx), "steps": int(sp),
+                             "converged": bool(cv), "steady_1e-4": int(t4), "Q": float(q)}
+                            for c, sp, cv, t4, q in zip(cases, res.steps, conv, st, res.Q)]}
 
 
 def warm_start(train=4096, test=512, nx=256, ny=64, epochs=30, batch=32, lr=1e-3, lr_min=1e-5,
@@ -148,7 +185,7 @@ def _kwargs(items):
 def main(argv):
     name = argv[1] if len(argv) > 1 else "flux_vs_field"
     fn = {"flux_vs_field": flux_vs_field, "sweep_throughput": sweep_throughput,
-          "warm_start": warm_start}[name]
+          "sweep_steady": sweep_steady, "warm_start": warm_start}[name]
     print(json.dumps(fn(**_kwargs(argv[2:]))), flush=True)
 
 
