@@ -30,8 +30,11 @@
  * work runs on the stream given to lbm_net_create.  Tensors x, y and t are
  * device FP32 arrays [n][planes][H][W] (x fastest); fluid is a device uint8
  * array [n][H][W], nonzero where the loss counts.  Activations are stored in
- * bf16 (act_bf16 = 1) or FP32 (act_bf16 = 0, the checking build); every
- * product and sum is FP32, the loss is reduced in FP64.
+ * bf16 (act_bf16 = 1) or FP32 (act_bf16 = 0, the checking build).  With bf16
+ * activations the forward 3x3 convolutions after the first run on matrix
+ * cores with the weights rounded to bf16 and FP32 accumulation; everything
+ * else (and the FP32 build throughout) multiplies and sums in FP32.  The loss
+ * is reduced in FP64; master weights, gradients and Adam moments are FP32.
  */
 #ifndef LBM_NET_H
 #define LBM_NET_H

@@ -28,6 +28,11 @@ network with every stored activation (each conv + ReLU output and each pooled
 tensor; upsampling and concatenation only move stored values) rounded to the
 nearest bf16 value, ties to even, and the gradient passed through the rounding
 unchanged.  ``forward``/``backward`` take that rounding as ``act=round_bf16``.
+The production build also multiplies on bf16 matrix cores in the forward 3x3
+convolutions after the first, with the weights rounded to bf16 there; that is
+``wround=round_bf16``: those forward convolutions use rounded weights, and the
+backward pass uses the unrounded weights (the gradient passes the weight
+rounding unchanged too).
 """
 from __future__ import annotations
 
@@ -155,14 +160,20 @@ def up_backward(dy):
 
 
 # ----------------------------------------------------------------- network
-def forward(theta, specs, x, keep=False, act=_identity):
-    """Network output; ``act`` rounds every stored activation (identity: FP64)."""
+def forward(theta, specs, x, keep=False, act=_identity, wround=_identity):
+    """Network output; ``act`` rounds every stored activation and ``wround``
+    the weights of the forward 3x3 convolutions after the first (identity:
+    FP64 throughout)."""
     P = unpack(theta, specs)
     cache = {}
 
+    def cv(name, inp):
+        W, b = P[name]
+        return conv(inp, W if name == specs[0][0] else wround(W), b)
+
     def block(name_a, name_b, inp):
-        za = conv(inp, *P[name_a]); ya = act(relu(za))
-        zb = conv(ya, *P[name_b]); yb = act(relu(zb))
+        za = cv(name_a, inp); ya = act(relu(za))
+        zb = cv(name_b, ya); yb = act(relu(zb))
         cache[name_a] = (inp, za); cache[name_b] = (ya, zb)
         return yb
 
@@ -192,10 +203,10 @@ def loss_grad(y, t, fluid):
     return 2.0 * (y - t) * m / cnt
 
 
-def backward(theta, specs, x, t, fluid, act=_identity):
-    """(loss, gradient of the loss with respect to theta); with ``act`` the
-    gradient passes through the activation rounding unchanged."""
-    y, cache = forward(theta, specs, x, keep=True, act=act)
+def backward(theta, specs, x, t, fluid, act=_identity, wround=_identity):
+    """(loss, gradient of the loss with respect to theta); with ``act`` and
+    ``wround`` the gradient passes through both roundings unchanged."""
+    y, cache = forward(theta, specs, x, keep=True, act=act, wround=wround)
     P = unpack(theta, specs)
     grads = {}
     dy = loss_grad(y, t, fluid)

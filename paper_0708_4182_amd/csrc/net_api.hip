@@ -71,6 +71,7 @@ struct Buffers {
     float *g_e1a, *g_cat1, *g_p1, *g_e2a, *g_cat2, *g_p2, *g_e3a, *g_cat3, *g_p3, *g_ba, *g_bb, *g_d3a, *g_d3b,
         *g_d2a, *g_d2b, *g_d1a, *g_d1b, *g_out, *y, *dz, *wt, *partial;
     float *theta, *grad, *m, *v;
+    __bf16 *wp;                      // packed bf16 weights of the matrix-core convolution
     double *loss_part, *loss_stats;
     size_t total, partial_floats;
 };
@@ -109,8 +110,13 @@ bool layout(const Plan &P, char *base, Buffers &b) {
         if (P.lk[l] == 3) {
             const int ch = lbmnet::dw_chunks(P.B, lh[l], lw[l], P.lcin[l], P.lcout[l]);
             partmax = std::max(partmax, (size_t)ch * P.lcout[l] * P.lcin[l] * 9);
+            partmax = std::max(partmax, (size_t)lbmnet::bias_scratch(P.lcout[l]));
         }
     }
+    size_t wpmax = 0;
+    for (int l = 1; l < NLAYERS; ++l)
+        if (P.lk[l] == 3) wpmax = std::max(wpmax, (size_t)9 * P.lcout[l] * lbmnet::pad32(P.lcin[l]));
+    b.wp = (__bf16 *)take(2 * wpmax);
     b.dz = (float *)take(4 * dzmax);
     b.wt = (float *)take(4 * wtmax);
     b.partial = (float *)take(4 * partmax);
@@ -254,12 +260,17 @@ void layer_io(const Tensors &t, LayerIO io[NLAYERS]) {
     io[D1B] = {t.d1a, t.d1b, t.g_d1a, t.g_d1b, true};
 }
 
+// Forward convolution of layer l: the first layer reads the FP32 input with
+// FP32 products; with bf16 activations every other layer runs on matrix
+// cores (bf16 weights and activations, FP32 accumulation).
 template <class TA>
 hipError_t conv_fwd(lbm_net *n, int l, const View &X, const View &Y, int N, bool first) {
     const Plan &P = n->P;
     const float *w = n->b.theta + P.woff[l], *bias = n->b.theta + P.boff[l];
     if (first) return lbmnet::conv3x3<float, TA>(X, w, bias, Y, N, P.lcin[l], P.lcout[l], true, n->s);
-    return lbmnet::conv3x3<TA, TA>(X, w, bias, Y, N, P.lcin[l], P.lcout[l], true, n->s);
+    if constexpr (sizeof(TA) == 2)
+        return lbmnet::conv3x3_mfma(X, w, bias, Y, N, P.lcin[l], P.lcout[l], true, n->b.wp, n->s);
+    else return lbmnet::conv3x3<TA, TA>(X, w, bias, Y, N, P.lcin[l], P.lcout[l], true, n->s);
 }
 
 template <class TA>
@@ -306,7 +317,7 @@ lbm_status conv_back(lbm_net *n, int l, const LayerIO &io, int N) {
         NHIP(n, lbmnet::conv3x3_dw<float>(io.X, b.dz, N, cin, cout, b.partial, chunks, b.grad + P.woff[l], n->s));
     else
         NHIP(n, lbmnet::conv3x3_dw<TA>(io.X, b.dz, N, cin, cout, b.partial, chunks, b.grad + P.woff[l], n->s));
-    NHIP(n, lbmnet::bias_grad(b.dz, N, cout, H * W, b.grad + P.boff[l], n->s));
+    NHIP(n, lbmnet::bias_grad(b.dz, N, cout, H * W, b.partial, b.grad + P.boff[l], n->s));
     if (io.has_gx) {
         NHIP(n, lbmnet::flip_transpose(b.theta + P.woff[l], b.wt, cin, cout, n->s));
         const View dz = view(b.dz, cout, H, W, cout, 0, 4);

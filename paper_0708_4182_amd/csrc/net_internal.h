@@ -19,12 +19,20 @@ struct View {
 template <class TI, class TO>
 hipError_t conv3x3(const View &in, const float *w, const float *bias, const View &out, int N, int cin, int cout,
                    bool relu, hipStream_t s);
+// The same for bf16 input and output on matrix cores: the weights are first
+// packed to bf16 [tap][cout][cin rounded up to 32] in wp (9 * cout * pad32(cin)
+// values), then the convolution accumulates bf16 products in FP32.
+int pad32(int c);
+hipError_t conv3x3_mfma(const View &in, const float *w, const float *bias, const View &out, int N, int cin,
+                        int cout, bool relu, __bf16 *wp, hipStream_t s);
 hipError_t flip_transpose(const float *w, float *wt, int cin, int cout, hipStream_t s);
 int dw_chunks(int N, int H, int W, int cin, int cout);
 template <class TI>
 hipError_t conv3x3_dw(const View &x, const float *dz, int N, int cin, int cout, float *partial, int chunks,
                       float *dw, hipStream_t s);
-hipError_t bias_grad(const float *dz, int N, int C, int HW, float *db, hipStream_t s);
+// floats of scratch bias_grad needs for C channels
+int bias_scratch(int C);
+hipError_t bias_grad(const float *dz, int N, int C, int HW, float *part, float *db, hipStream_t s);
 template <class TA>
 hipError_t relu_mask(const View &g, const View &y, int N, int C, float *dz, hipStream_t s);
 template <class TA>

@@ -162,22 +162,37 @@ __global__ void k_sum_partials(const float *__restrict__ partial, int nchunks, i
     out[i] = s;
 }
 
-// db[co] = sum of dz[n][co][...] over samples and pixels: one workgroup per
-// channel, fixed tree.
-__global__ void __launch_bounds__(256) k_bias_grad(const float *__restrict__ dz, int N, int C, int HW,
-                                                   float *__restrict__ db) {
+// db[co] = sum of dz[n][co][...] over samples and pixels, in two passes with a
+// fixed order: workgroup (co, b) sums its contiguous share of the N * HW
+// values of channel co (fixed tree), then one thread per channel adds the
+// BIAS_PARTS shares in order.
+constexpr int BIAS_PARTS = 64;
+__global__ void __launch_bounds__(256) k_bias_partial(const float *__restrict__ dz, int N, int C, int HW,
+                                                      float *__restrict__ part) {
     __shared__ float sh[256];
-    const int co = blockIdx.x;
+    const int co = blockIdx.x, b = blockIdx.y;
+    const size_t total = (size_t)N * HW, len = (total + BIAS_PARTS - 1) / BIAS_PARTS;
+    const size_t e0 = (size_t)b * len, e1 = min(total, e0 + len);
     float s = 0.f;
-    for (int n = 0; n < N; ++n)
-        for (int i = threadIdx.x; i < HW; i += 256) s += dz[((size_t)n * C + co) * HW + i];
+    for (size_t e = e0 + threadIdx.x; e < e1; e += 256) {
+        const size_t n = e / (size_t)HW, p = e % (size_t)HW;
+        s += dz[(n * C + co) * HW + p];
+    }
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
         if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
         __syncthreads();
     }
-    if (threadIdx.x == 0) db[co] = sh[0];
+    if (threadIdx.x == 0) part[(size_t)co * BIAS_PARTS + b] = sh[0];
+}
+
+__global__ void k_bias_final(const float *__restrict__ part, int C, float *__restrict__ db) {
+    const int co = blockIdx.x * blockDim.x + threadIdx.x;
+    if (co >= C) return;
+    float s = 0.f;
+    for (int b = 0; b < BIAS_PARTS; ++b) s += part[(size_t)co * BIAS_PARTS + b];
+    db[co] = s;
 }
 
 // dz = g * (y > 0) (ReLU derivative from the stored output), dense fp32 out.
@@ -368,6 +383,103 @@ __global__ void k_zero(float *__restrict__ p, size_t n) {
         p[i] = 0.f;
 }
 
+// ------------------------------------------------------- conv 3x3 on MFMA
+// bf16 activations and weights, FP32 accumulation: out[co][p] = bias[co] +
+// sum over taps t and input channels ci of W[co][ci][t] x[ci][p + d_t], as a
+// GEMM per tap with M = output channels, N = pixels, K = input channels, on
+// v_mfma_f32_16x16x32_bf16.  Operand layout of that instruction (checked on
+// the device): lane l holds A[l % 16][8 (l / 16) + e] and B[8 (l / 16) + e][l % 16]
+// for e = 0..7 and receives D[4 (l / 16) + r][l % 16] for r = 0..3.
+//
+// A workgroup (4 waves) computes an 8 x 32 pixel tile for 64 output channels;
+// wave w owns pixel rows 2w and 2w + 1 (four 16-pixel N tiles) and all four
+// 16-channel M tiles.  Input channels are staged 32 at a time through LDS
+// channel-last ([y][x][ci], 40 bf16 per pixel so that the 16-byte fragment
+// reads of 16 consecutive pixels fall in distinct banks), with the one-pixel
+// halo (periodic x, zero y); the packed weights ([t][co][ci], see
+// k_pack_weights) likewise.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int MH = 8, MW = 32, MCO = 64, MCI = 32, MPS = 40;
+
+// Wp[t][co][ci] (bf16, ci padded with zeros to cin_pad) from W[co][ci][t] (FP32)
+__global__ void k_pack_weights(const float *__restrict__ w, __bf16 *__restrict__ wp, int cin, int cout, int cin_pad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 9 * cout * cin_pad) return;
+    const int ci = i % cin_pad, co = (i / cin_pad) % cout, t = i / (cin_pad * cout);
+    wp[i] = (__bf16)(ci < cin ? w[((size_t)co * cin + ci) * 9 + t] : 0.f);
+}
+
+__global__ void __launch_bounds__(256) k_conv3x3_mfma(View in, const __bf16 *__restrict__ wp,
+                                                      const float *__restrict__ bias, View out, int cin,
+                                                      int cout, int cin_pad, int relu) {
+    __shared__ __attribute__((aligned(16))) __bf16 xs[(MH + 2) * (MW + 2) * MPS];
+    __shared__ __attribute__((aligned(16))) __bf16 ws[9 * MCO * MPS];
+    const int H = in.H, W = in.W;
+    const int tiles_x = (W + MW - 1) / MW;
+    const int tx0 = (blockIdx.x % tiles_x) * MW, ty0 = (blockIdx.x / tiles_x) * MH;
+    const int ncob = (cout + MCO - 1) / MCO;
+    const int n = blockIdx.y / ncob, co0 = (blockIdx.y % ncob) * MCO;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = (lane >> 4) * 8;
+    const __bf16 *__restrict__ xin = static_cast<const __bf16 *>(in.p) + (size_t)n * in.bs;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[m][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int ci0 = 0; ci0 < cin; ci0 += MCI) {
+        for (int e = tid; e < MCI * (MH + 2) * (MW + 2); e += 256) {
+            const int q = e % (MW + 2), r = (e / (MW + 2)) % (MH + 2), c = e / ((MW + 2) * (MH + 2));
+            const int y = ty0 - 1 + r;
+            const int x = (tx0 - 1 + q + W) % W;
+            __bf16 v = (__bf16)0.f;
+            if (ci0 + c < cin && y >= 0 && y < H) v = xin[(size_t)(ci0 + c) * H * W + (size_t)y * W + x];
+            xs[(r * (MW + 2) + q) * MPS + c] = v;
+        }
+        for (int e = tid; e < 9 * MCO * (MCI / 8); e += 256) {
+            const int c8 = e % (MCI / 8), co = (e / (MCI / 8)) % MCO, t = e / ((MCI / 8) * MCO);
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (co0 + co < cout)
+                v = *reinterpret_cast<const uint4 *>(wp + ((size_t)t * cout + co0 + co) * cin_pad + ci0 + 8 * c8);
+            *reinterpret_cast<uint4 *>(&ws[(t * MCO + co) * MPS + 8 * c8]) = v;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3, dx = t % 3;
+            bf16x8 a[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                a[m] = *reinterpret_cast<const bf16x8 *>(&ws[(t * MCO + 16 * m + lr) * MPS + lk]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int pr = 2 * wave + (q >> 1), pc = (q & 1) * 16 + lr;
+                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&xs[((pr + dy) * (MW + 2) + pc + dx) * MPS + lk]);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b, acc[m][q], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    __bf16 *__restrict__ yo = static_cast<__bf16 *>(out.p) + (size_t)n * out.bs;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int y = ty0 + 2 * wave + (q >> 1), x = tx0 + (q & 1) * 16 + lr;
+            if (y >= H || x >= W) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = co0 + 16 * m + (lane >> 4) * 4 + r;
+                if (co >= cout) continue;
+                float v = acc[m][q][r] + bias[co];
+                if (relu) v = fmaxf(v, 0.f);
+                yo[(size_t)co * H * W + (size_t)y * W + x] = (__bf16)v;
+            }
+        }
+}
+
 inline unsigned nblk(size_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -384,6 +496,20 @@ hipError_t conv3x3(const View &in, const float *w, const float *bias, const View
 template hipError_t conv3x3<float, float>(const View &, const float *, const float *, const View &, int, int, int, bool, hipStream_t);
 template hipError_t conv3x3<float, __bf16>(const View &, const float *, const float *, const View &, int, int, int, bool, hipStream_t);
 template hipError_t conv3x3<__bf16, __bf16>(const View &, const float *, const float *, const View &, int, int, int, bool, hipStream_t);
+
+int pad32(int c) { return (c + MCI - 1) / MCI * MCI; }
+
+hipError_t conv3x3_mfma(const View &in, const float *w, const float *bias, const View &out, int N, int cin,
+                        int cout, bool relu, __bf16 *wp, hipStream_t s) {
+    const int cin_pad = pad32(cin);
+    k_pack_weights<<<nblk((size_t)9 * cout * cin_pad), 256, 0, s>>>(w, wp, cin, cout, cin_pad);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int tiles = ((in.W + MW - 1) / MW) * ((in.H + MH - 1) / MH);
+    const dim3 grid(tiles, N * ((cout + MCO - 1) / MCO));
+    k_conv3x3_mfma<<<grid, 256, 0, s>>>(in, wp, bias, out, cin, cout, cin_pad, relu ? 1 : 0);
+    return hipGetLastError();
+}
 
 hipError_t flip_transpose(const float *w, float *wt, int cin, int cout, hipStream_t s) {
     k_flip_transpose<<<nblk((size_t)cin * cout * 9), 256, 0, s>>>(w, wt, cin, cout);
@@ -414,8 +540,13 @@ hipError_t conv3x3_dw(const View &x, const float *dz, int N, int cin, int cout, 
 template hipError_t conv3x3_dw<float>(const View &, const float *, int, int, int, float *, int, float *, hipStream_t);
 template hipError_t conv3x3_dw<__bf16>(const View &, const float *, int, int, int, float *, int, float *, hipStream_t);
 
-hipError_t bias_grad(const float *dz, int N, int C, int HW, float *db, hipStream_t s) {
-    k_bias_grad<<<C, 256, 0, s>>>(dz, N, C, HW, db);
+int bias_scratch(int C) { return C * BIAS_PARTS; }
+
+hipError_t bias_grad(const float *dz, int N, int C, int HW, float *part, float *db, hipStream_t s) {
+    k_bias_partial<<<dim3(C, BIAS_PARTS), 256, 0, s>>>(dz, N, C, HW, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_bias_final<<<nblk(C, 64), 64, 0, s>>>(part, C, db);
     return hipGetLastError();
 }
 

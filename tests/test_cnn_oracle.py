@@ -112,3 +112,29 @@ def test_rounded_network_is_close_and_identity_is_default():
     yb = cnn.forward(theta, specs, x, act=cnn.round_bf16)
     err = np.linalg.norm(yb - y) / np.linalg.norm(y)
     assert 1e-5 < err < 5e-2          # rounding is applied, and it is a small perturbation
+
+
+def test_weight_rounding_applies_to_the_inner_3x3_layers_only():
+    """wround rounds exactly the forward 3x3 convolutions after the first:
+    the same as pre-rounding those weights by hand."""
+    specs = cnn.layer_specs(chans=(3, 4, 4, 5))
+    theta = cnn.init_params(specs, seed=6)
+    x = np.random.default_rng(7).standard_normal((1, 3, 8, 16))
+    y0 = cnn.forward(theta, specs, x)
+    assert np.array_equal(y0, cnn.forward(theta, specs, x, wround=lambda w: w))
+    manual, o = theta.copy(), 0
+    for i, (name, ci, co, k) in enumerate(specs):
+        n = co * ci * k * k
+        if i > 0 and k == 3:
+            manual[o:o + n] = cnn.round_bf16(theta[o:o + n])
+        o += n + co
+    y1 = cnn.forward(theta, specs, x, wround=cnn.round_bf16)
+    np.testing.assert_array_equal(y1, cnn.forward(manual, specs, x))
+    assert not np.array_equal(y1, y0)
+    # the backward pass differentiates with the unrounded weights
+    t = np.zeros_like(y0)
+    fluid = np.ones((1, 8, 16), bool)
+    _, g1 = cnn.backward(theta, specs, x, t, fluid, wround=cnn.round_bf16)
+    _, g2 = cnn.backward(manual, specs, x, t, fluid)
+    rel = np.linalg.norm(g1 - g2) / np.linalg.norm(g2)
+    assert 0 < rel < 2e-2          # differs only through the 2^-9 weight rounding in dx
