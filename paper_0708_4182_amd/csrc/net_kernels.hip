@@ -92,65 +92,73 @@ __global__ void k_flip_transpose(const float *__restrict__ w, float *__restrict_
 
 // ------------------------------------------------------- weight gradient
 // dW[co][ci][t] = sum over samples and pixels of dz[co](p) x[ci](p + shift t).
-// Workgroup (chunk, co block of 16, ci block of 8) accumulates over the tiles
-// of its chunk; threads 0..143 own (co = t % 16, tap = t / 16) and 8 ci each.
+// Workgroup (chunk, co block of 16, ci block of 16) accumulates over the tiles
+// of its chunk; thread t owns (co = t / 16, ci = t % 16) and all 9 taps.  For
+// each output row it walks the three staged input rows with a sliding window
+// of 3 values, so one dz read and three x reads feed 9 FMAs.  Channel strides
+// in LDS are odd, so the 16 ci (and 4 co) of a wave hit distinct banks.
 // Partials [chunk][co][ci][tap] are summed in chunk order by k_sum_partials.
+constexpr int DW_CO = 16, DW_CI = 16;
+constexpr int XS_STRIDE = (TH + 2) * (TW + 2) + 1, DS_STRIDE = TH * TW + 1;
+
 template <class TI>
 __global__ void __launch_bounds__(256) k_conv3x3_dw(View x, const float *__restrict__ dz, int N, int cin,
                                                     int cout, int tiles_per_chunk,
                                                     float *__restrict__ partial) {
-    __shared__ float xs[CI_T][TH + 2][TW + 2];
-    __shared__ float ds[CO_T][TH * TW];
+    __shared__ float xs[DW_CI * XS_STRIDE];
+    __shared__ float ds[DW_CO * DS_STRIDE];
     const int H = x.H, W = x.W;
     const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
     const int ntiles = N * tiles_x * tiles_y;
-    const int chunk = blockIdx.x, co0 = blockIdx.y * CO_T, ci0 = blockIdx.z * CI_T;
+    const int chunk = blockIdx.x, co0 = blockIdx.y * DW_CO, ci0 = blockIdx.z * DW_CI;
     const int tid = threadIdx.x;
-    const int my_co = tid % CO_T, my_tap = tid / CO_T;
-    const bool owner = tid < CO_T * 9;
-    float acc[CI_T];
+    const int my_co = tid / DW_CI, my_ci = tid % DW_CI;
+    float acc[9];
 #pragma unroll
-    for (int c = 0; c < CI_T; ++c) acc[c] = 0.f;
+    for (int t = 0; t < 9; ++t) acc[t] = 0.f;
     const int t_begin = chunk * tiles_per_chunk, t_end = min(ntiles, t_begin + tiles_per_chunk);
     for (int tile = t_begin; tile < t_end; ++tile) {
         const int n = tile / (tiles_x * tiles_y), rem = tile % (tiles_x * tiles_y);
         const int ty0 = (rem / tiles_x) * TH, tx0 = (rem % tiles_x) * TW;
         const TI *__restrict__ xin = static_cast<const TI *>(x.p) + (size_t)n * x.bs;
-        for (int e = tid; e < CI_T * (TH + 2) * (TW + 2); e += 256) {
+        for (int e = tid; e < DW_CI * (TH + 2) * (TW + 2); e += 256) {
             const int c = e / ((TH + 2) * (TW + 2)), r = (e / (TW + 2)) % (TH + 2), q = e % (TW + 2);
             const int y = ty0 - 1 + r;
             const int xx = (tx0 - 1 + q + W) % W;
             float v = 0.f;
             if (ci0 + c < cin && y >= 0 && y < H) v = tof(xin[(size_t)(ci0 + c) * H * W + (size_t)y * W + xx]);
-            xs[c][r][q] = v;
+            xs[c * XS_STRIDE + r * (TW + 2) + q] = v;
         }
-        for (int e = tid; e < CO_T * TH * TW; e += 256) {
+        for (int e = tid; e < DW_CO * TH * TW; e += 256) {
             const int o = e / (TH * TW), p = e % (TH * TW);
             const int y = ty0 + p / TW, xx = tx0 + p % TW;
             float v = 0.f;
             if (co0 + o < cout && y < H && xx < W)
                 v = dz[((size_t)n * cout + co0 + o) * H * W + (size_t)y * W + xx];
-            ds[o][p] = v;
+            ds[o * DS_STRIDE + p] = v;
         }
         __syncthreads();
-        if (owner) {
-            const int ky = my_tap / 3, kx = my_tap % 3;
-            for (int p = 0; p < TH * TW; ++p) {
-                const float d = ds[my_co][p];
-                const int py = p / TW, px = p % TW;
-#pragma unroll
-                for (int c = 0; c < CI_T; ++c) acc[c] += d * xs[c][py + ky][px + kx];
+        const float *__restrict__ xc = xs + my_ci * XS_STRIDE;
+        const float *__restrict__ dc = ds + my_co * DS_STRIDE;
+        for (int py = 0; py < TH; ++py) {
+            const float *r0 = xc + py * (TW + 2), *r1 = r0 + (TW + 2), *r2 = r1 + (TW + 2);
+            float a0 = r0[0], a1 = r0[1], b0 = r1[0], b1 = r1[1], c0 = r2[0], c1 = r2[1];
+#pragma unroll 8
+            for (int px = 0; px < TW; ++px) {
+                const float d = dc[py * TW + px];
+                const float a2 = r0[px + 2], b2 = r1[px + 2], c2 = r2[px + 2];
+                acc[0] += d * a0; acc[1] += d * a1; acc[2] += d * a2;
+                acc[3] += d * b0; acc[4] += d * b1; acc[5] += d * b2;
+                acc[6] += d * c0; acc[7] += d * c1; acc[8] += d * c2;
+                a0 = a1; a1 = a2; b0 = b1; b1 = b2; c0 = c1; c1 = c2;
             }
         }
         __syncthreads();
     }
-    if (owner) {
+    if (ci0 + my_ci >= cin || co0 + my_co >= cout) return;
+    float *__restrict__ dst = partial + (((size_t)chunk * cout + co0 + my_co) * cin + ci0 + my_ci) * 9;
 #pragma unroll
-        for (int c = 0; c < CI_T; ++c) {
-            if (ci0 + c >= cin || co0 + my_co >= cout) continue;
-            partial[(((size_t)chunk * cout + co0 + my_co) * cin + ci0 + c) * 9 + my_tap] = acc[c];
-        }
-    }
+    for (int t = 0; t < 9; ++t) dst[t] = acc[t];
 }
 
 // out[i] = sum over k of partial[k][i], k in order (deterministic).
@@ -518,7 +526,7 @@ hipError_t flip_transpose(const float *w, float *wt, int cin, int cout, hipStrea
 
 int dw_chunks(int N, int H, int W, int cin, int cout) {
     const int ntiles = N * ((W + TW - 1) / TW) * ((H + TH - 1) / TH);
-    const int blocks = ((cout + CO_T - 1) / CO_T) * ((cin + CI_T - 1) / CI_T);
+    const int blocks = ((cout + DW_CO - 1) / DW_CO) * ((cin + DW_CI - 1) / DW_CI);
     // aim for >= 2048 workgroups, at least 2 tiles per chunk
     int chunks = std::max(1, std::min(ntiles / 2, (2048 + blocks - 1) / blocks));
     return std::max(1, chunks);
@@ -529,7 +537,7 @@ hipError_t conv3x3_dw(const View &x, const float *dz, int N, int cin, int cout, 
                       float *dw, hipStream_t s) {
     const int ntiles = N * ((x.W + TW - 1) / TW) * ((x.H + TH - 1) / TH);
     const int per = (ntiles + chunks - 1) / chunks;
-    const dim3 grid(chunks, (cout + CO_T - 1) / CO_T, (cin + CI_T - 1) / CI_T);
+    const dim3 grid(chunks, (cout + DW_CO - 1) / DW_CO, (cin + DW_CI - 1) / DW_CI);
     k_conv3x3_dw<TI><<<grid, 256, 0, s>>>(x, dz, N, cin, cout, per, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
