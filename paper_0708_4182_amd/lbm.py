@@ -70,6 +70,11 @@ def load_library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_0708_4182_amd/build.py")
+    # torch's HIP runtime must be in the process first: the library then binds
+    # to it (same soname).  Loaded the other way round, torch would add its own
+    # copy of the runtime next to the system one, and memory, streams and
+    # devices of one would be unknown to the other.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     vp, P = C.c_void_p, C.POINTER(lbm_params)
     dp, fp = C.POINTER(C.c_double), C.POINTER(C.c_float)

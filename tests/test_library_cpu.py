@@ -128,6 +128,21 @@ def test_product_path_has_no_oracle_dependency():
                 assert "lbm_oracle" not in text and "orc_" not in text, f
 
 
+def test_one_hip_runtime_in_the_process():
+    """Loading the library first and torch afterwards leaves one HIP runtime
+    mapped: the loader brings torch in before the library, so the library
+    binds to torch's copy of the runtime instead of adding the system one."""
+    import subprocess
+    import sys
+    code = ("from paper_0708_4182_amd import lbm; lbm.load_library(); import torch; "
+            "maps = open('/proc/self/maps').read().split(chr(10)); "
+            "paths = sorted({l.split()[-1] for l in maps if 'libamdhip64' in l}); "
+            "print(len(paths)); print(paths)")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split()[0] == "1", out.stdout
+
+
 def test_batch_workspace_validation(lib):
     from paper_0708_4182_amd import lbm
     ps = [I.Params(nx=40, ny=20), I.Params(nx=64, ny=33), I.Params(nx=300, ny=70)]
