@@ -111,6 +111,8 @@ bool layout(const Plan &P, char *base, Buffers &b) {
             const int ch = lbmnet::dw_chunks(P.B, lh[l], lw[l], P.lcin[l], P.lcout[l]);
             partmax = std::max(partmax, (size_t)ch * P.lcout[l] * P.lcin[l] * 9);
             partmax = std::max(partmax, (size_t)lbmnet::bias_scratch(P.lcout[l]));
+        } else {
+            partmax = std::max(partmax, (size_t)lbmnet::conv1x1_dw_scratch(P.lcin[l], P.lcout[l]));
         }
     }
     size_t wpmax = 0;
@@ -338,7 +340,8 @@ lbm_status gradient_t(lbm_net *n, const float *x, const float *tgt, const uint8_
     const Tensors t = tensors(n, x);
     LayerIO io[NLAYERS];
     layer_io(t, io);
-    NHIP(n, lbmnet::conv1x1_dw<TA>(t.d1b, b.g_out, N, P.c[0], P.cout, b.grad + P.woff[OUT], b.grad + P.boff[OUT], s));
+    NHIP(n, lbmnet::conv1x1_dw<TA>(t.d1b, b.g_out, N, P.c[0], P.cout, b.partial, b.grad + P.woff[OUT],
+                                    b.grad + P.boff[OUT], s));
     NHIP(n, lbmnet::conv1x1_dx(b.g_out, b.theta + P.woff[OUT], N, P.c[0], P.cout, HW, t.g_d1b, s));
 #define BACK(L)                                          \
     do {                                                 \

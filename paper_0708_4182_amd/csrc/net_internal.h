@@ -46,8 +46,9 @@ hipError_t conv1x1(const View &in, const float *w, const float *b, int N, int ci
                    hipStream_t s);
 hipError_t conv1x1_dx(const float *g, const float *w, int N, int cin, int cout, int HW, const View &dx,
                       hipStream_t s);
+int conv1x1_dw_scratch(int cin, int cout);
 template <class TA>
-hipError_t conv1x1_dw(const View &x, const float *g, int N, int cin, int cout, float *dw, float *db,
+hipError_t conv1x1_dw(const View &x, const float *g, int N, int cin, int cout, float *part, float *dw, float *db,
                       hipStream_t s);
 int loss_blocks();
 hipError_t loss_and_grad(const float *y, const float *t, const uint8_t *mask, int N, int C, int HW, double *part,

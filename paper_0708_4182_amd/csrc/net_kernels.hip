@@ -161,13 +161,21 @@ __global__ void __launch_bounds__(256) k_conv3x3_dw(View x, const float *__restr
     for (int t = 0; t < 9; ++t) dst[t] = acc[t];
 }
 
-// out[i] = sum over k of partial[k][i], k in order (deterministic).
+// out[i] = sum over k of partial[k][i] (deterministic): eight running sums
+// over k = j mod 8, so eight loads are in flight, then added in a fixed tree.
 __global__ void k_sum_partials(const float *__restrict__ partial, int nchunks, int n, float *__restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    float s = 0.f;
-    for (int k = 0; k < nchunks; ++k) s += partial[(size_t)k * n + i];
-    out[i] = s;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int k = 0;
+    for (; k + 8 <= nchunks; k += 8) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s[j] += partial[(size_t)(k + j) * n + i];
+    }
+#pragma unroll
+    for (int j = 0; j < 7; ++j)
+        if (k + j < nchunks) s[j] += partial[(size_t)(k + j) * n + i];
+    out[i] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 // db[co] = sum of dz[n][co][...] over samples and pixels, in two passes with a
@@ -295,28 +303,44 @@ __global__ void k_conv1x1_dx(const float *__restrict__ g, const float *__restric
 
 // 1x1 weight and bias gradients: one workgroup per (o, c) entry, and c = cin
 // for the bias; fixed tree.
+// dW[o][c] = sum of g[n][o](p) x[n][c](p), db[o] = sum of g[n][o](p) (pair c =
+// cin), in two passes with a fixed order: workgroup (pair, b) sums its
+// contiguous share of the N * HW products (fixed tree) into part[pair][b],
+// then k_pair_final adds the BIAS_PARTS shares of each pair in order.
 template <class TA>
-__global__ void __launch_bounds__(256) k_conv1x1_dw(View x, const float *__restrict__ g, int N, int cin, int cout,
-                                                    float *__restrict__ dw, float *__restrict__ db) {
+__global__ void __launch_bounds__(256) k_conv1x1_dw_partial(View x, const float *__restrict__ g, int N, int cin,
+                                                            int cout, float *__restrict__ part) {
     __shared__ float sh[256];
-    const int o = blockIdx.x / (cin + 1), c = blockIdx.x % (cin + 1);
-    const size_t HW = (size_t)x.H * x.W;
+    const int pair = blockIdx.x, b = blockIdx.y;
+    const int o = pair / (cin + 1), c = pair % (cin + 1);
+    const size_t HW = (size_t)x.H * x.W, total = (size_t)N * HW;
+    const size_t len = (total + BIAS_PARTS - 1) / BIAS_PARTS;
+    const size_t e0 = (size_t)b * len, e1 = min(total, e0 + len);
+    const TA *__restrict__ xp = static_cast<const TA *>(x.p);
     float s = 0.f;
-    for (int n = 0; n < N; ++n)
-        for (size_t p = threadIdx.x; p < HW; p += 256) {
-            const float gv = g[((size_t)n * cout + o) * HW + p];
-            s += c < cin ? gv * tof(static_cast<const TA *>(x.p)[(size_t)n * x.bs + (size_t)c * HW + p]) : gv;
-        }
+    for (size_t e = e0 + threadIdx.x; e < e1; e += 256) {
+        const size_t n = e / HW, p = e % HW;
+        const float gv = g[(n * cout + o) * HW + p];
+        s += c < cin ? gv * tof(xp[n * x.bs + (size_t)c * HW + p]) : gv;
+    }
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
         if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        if (c < cin) dw[o * cin + c] = sh[0];
-        else db[o] = sh[0];
-    }
+    if (threadIdx.x == 0) part[(size_t)pair * BIAS_PARTS + b] = sh[0];
+}
+
+__global__ void k_conv1x1_dw_final(const float *__restrict__ part, int cin, int cout, float *__restrict__ dw,
+                                   float *__restrict__ db) {
+    const int pair = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pair >= cout * (cin + 1)) return;
+    float s = 0.f;
+    for (int b = 0; b < BIAS_PARTS; ++b) s += part[(size_t)pair * BIAS_PARTS + b];
+    const int o = pair / (cin + 1), c = pair % (cin + 1);
+    if (c < cin) dw[o * cin + c] = s;
+    else db[o] = s;
 }
 
 // ------------------------------------------------------------ loss, Adam
@@ -607,14 +631,22 @@ hipError_t conv1x1_dx(const float *g, const float *w, int N, int cin, int cout, 
     return hipGetLastError();
 }
 
+int conv1x1_dw_scratch(int cin, int cout) { return cout * (cin + 1) * BIAS_PARTS; }
+
 template <class TA>
-hipError_t conv1x1_dw(const View &x, const float *g, int N, int cin, int cout, float *dw, float *db,
+hipError_t conv1x1_dw(const View &x, const float *g, int N, int cin, int cout, float *part, float *dw, float *db,
                       hipStream_t s) {
-    k_conv1x1_dw<TA><<<cout * (cin + 1), 256, 0, s>>>(x, g, N, cin, cout, dw, db);
+    const int pairs = cout * (cin + 1);
+    k_conv1x1_dw_partial<TA><<<dim3(pairs, BIAS_PARTS), 256, 0, s>>>(x, g, N, cin, cout, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_conv1x1_dw_final<<<nblk(pairs, 64), 64, 0, s>>>(part, cin, cout, dw, db);
     return hipGetLastError();
 }
-template hipError_t conv1x1_dw<float>(const View &, const float *, int, int, int, float *, float *, hipStream_t);
-template hipError_t conv1x1_dw<__bf16>(const View &, const float *, int, int, int, float *, float *, hipStream_t);
+template hipError_t conv1x1_dw<float>(const View &, const float *, int, int, int, float *, float *, float *,
+                                      hipStream_t);
+template hipError_t conv1x1_dw<__bf16>(const View &, const float *, int, int, int, float *, float *, float *,
+                                       hipStream_t);
 
 constexpr int LOSS_BLOCKS = 256;
 int loss_blocks() { return LOSS_BLOCKS; }
