@@ -146,18 +146,22 @@ lbm_status lbm_set_tile(lbm_sim *sim, int32_t block_x, int32_t rows_per_block);
  * producer wave per workgroup streams the pulled rows into LDS two rows ahead
  * with direct-to-LDS loads and block_x compute threads only read LDS and store
  * (block_x 128 or 256; selecting it with another block_x sets block_x to 128).
+ * LBM_KERNEL_FUSED8: the fused kernel compiled for 8 resident waves per SIMD
+ * (64 registers; a few loop invariants live in scratch memory) instead of 6.
  * All give bitwise the same results.  Default LBM_KERNEL_FUSED.  Takes effect
  * at the next lbm_step. */
 #define LBM_KERNEL_FUSED 0
 #define LBM_KERNEL_SPLIT 1
 #define LBM_KERNEL_WIDE2 2
 #define LBM_KERNEL_WIDE4 3
+#define LBM_KERNEL_FUSED8 4
 lbm_status lbm_set_kernel(lbm_sim *sim, int32_t kernel);
 
 /* The current kernel, block_x and rows_per_block (any pointer may be NULL). */
 lbm_status lbm_get_tile(const lbm_sim *sim, int32_t *kernel, int32_t *block_x, int32_t *rows_per_block);
 
-/* Autotuner: times each candidate (fused kernel: block_x in 64..512; wide
+/* Autotuner: times each candidate (fused kernels: block_x in 64..512 (6 waves)
+ * or 128..512 (8 waves); wide
  * kernels: block_x 64..256; split kernel: block_x 128 or 256; rows_per_block
  * in {0, 32, 64, 128}) for `reps`
  * launches on the current state and keeps the fastest.  The trial launches

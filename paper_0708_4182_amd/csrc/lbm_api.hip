@@ -375,6 +375,7 @@ lbm::StepArgs step_args(lbm_sim *s) {
             case LBM_KERNEL_SPLIT: per_cu = lbm::split_blocks_per_cu(s->p.storage, s->block_x); break;
             case LBM_KERNEL_WIDE2: per_cu = lbm::wide_blocks_per_cu(s->p.storage, s->block_x, 2); break;
             case LBM_KERNEL_WIDE4: per_cu = lbm::wide_blocks_per_cu(s->p.storage, s->block_x, 4); break;
+            case LBM_KERNEL_FUSED8: per_cu = lbm::step8_blocks_per_cu(s->p.storage, s->block_x); break;
             default: per_cu = lbm::step_blocks_per_cu(s->p.storage, s->block_x); break;
             }
             const int cap = s->cus * per_cu;
@@ -400,6 +401,7 @@ hipError_t launch(const lbm_sim *s, const lbm::StepArgs &a) {
     case LBM_KERNEL_SPLIT: return lbm::launch_step_split(s->p.storage, a, s->block_x, s->stream);
     case LBM_KERNEL_WIDE2: return lbm::launch_step_wide(s->p.storage, a, s->block_x, 2, s->stream);
     case LBM_KERNEL_WIDE4: return lbm::launch_step_wide(s->p.storage, a, s->block_x, 4, s->stream);
+    case LBM_KERNEL_FUSED8: return lbm::launch_step8(s->p.storage, a, s->block_x, s->stream);
     default: return lbm::launch_step(s->p.storage, a, s->block_x, s->stream);
     }
 }
@@ -493,8 +495,8 @@ lbm_status lbm_set_tile(lbm_sim *s, int32_t block_x, int32_t rows) {
 lbm_status lbm_set_kernel(lbm_sim *s, int32_t kernel) {
     lbm_status st = usable(s);
     if (st) return st;
-    if (kernel < LBM_KERNEL_FUSED || kernel > LBM_KERNEL_WIDE4)
-        return fail(s, LBM_EINVAL, "kernel must be one of LBM_KERNEL_FUSED, _SPLIT, _WIDE2, _WIDE4");
+    if (kernel < LBM_KERNEL_FUSED || kernel > LBM_KERNEL_FUSED8)
+        return fail(s, LBM_EINVAL, "kernel must be one of LBM_KERNEL_FUSED, _SPLIT, _WIDE2, _WIDE4, _FUSED8");
     s->kernel = kernel;
     if (kernel == LBM_KERNEL_SPLIT && s->block_x != 128 && s->block_x != 256) s->block_x = 128;
     if ((kernel == LBM_KERNEL_WIDE2 || kernel == LBM_KERNEL_WIDE4) && s->block_x > 256) s->block_x = 256;
@@ -519,7 +521,8 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *row
     static const Cand kCand[] = {{LBM_KERNEL_FUSED, 64},  {LBM_KERNEL_FUSED, 128}, {LBM_KERNEL_FUSED, 256},
                                  {LBM_KERNEL_FUSED, 512}, {LBM_KERNEL_WIDE2, 64},  {LBM_KERNEL_WIDE2, 128},
                                  {LBM_KERNEL_WIDE2, 256}, {LBM_KERNEL_WIDE4, 64},  {LBM_KERNEL_WIDE4, 128},
-                                 {LBM_KERNEL_SPLIT, 128}, {LBM_KERNEL_SPLIT, 256}};
+                                 {LBM_KERNEL_SPLIT, 128}, {LBM_KERNEL_SPLIT, 256}, {LBM_KERNEL_FUSED8, 128},
+                                 {LBM_KERNEL_FUSED8, 256}, {LBM_KERNEL_FUSED8, 512}};
     static const int kRows[] = {0, 32, 64, 128};
     hipEvent_t e0, e1;
     HIP_TRY(s, hipEventCreate(&e0));

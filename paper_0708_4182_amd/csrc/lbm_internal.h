@@ -71,6 +71,9 @@ struct BatchStepArgs {
 hipError_t launch_step(int storage, const StepArgs &a, int block_x, hipStream_t s);
 // Resident workgroups of the step kernel per compute unit.
 int step_blocks_per_cu(int storage, int block_x);
+// The step kernel compiled for 8 waves per SIMD, and its resident workgroups.
+hipError_t launch_step8(int storage, const StepArgs &a, int block_x, hipStream_t s);
+int step8_blocks_per_cu(int storage, int block_x);
 // The split step (a producer wave streams rows into LDS for block_x compute
 // threads; block_x = 128 or 256) and its resident workgroups per compute unit.
 hipError_t launch_step_split(int storage, const StepArgs &a, int block_x, hipStream_t s);

@@ -401,14 +401,30 @@ __device__ __forceinline__ void step_tile(const void *src_ptr, void *dst_ptr, co
 }
 
 template <int S>
-__global__ void __launch_bounds__(512) k_step(const StepArgs a) {
-    extern __shared__ float ring[];
+__device__ __forceinline__ void step_tiles(const StepArgs &a, float *ring) {
     const int tile = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
     if (tile >= a.ntiles) return;   // uniform for the workgroup, before any barrier
     const int strip = tile / a.chunks, chunk = tile - strip * a.chunks;
     const int y0 = (int)(((int64_t)chunk * a.g.ny) / a.chunks);
     const int y1 = (int)(((int64_t)(chunk + 1) * a.g.ny) / a.chunks);
     step_tile<S>(a.src, a.dst, a.flags, a.g, a.m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring);
+}
+
+template <int S>
+__global__ void __launch_bounds__(512) k_step(const StepArgs a) {
+    extern __shared__ float ring[];
+    step_tiles<S>(a, ring);
+}
+
+// The same kernel compiled for 8 resident waves per SIMD (64 VGPRs) instead of
+// the 6 its natural register count allows.  The compiler keeps a few
+// loop-invariant values in scratch (reloaded per row from the L1 cache); the
+// extra waves keep a third more loads in flight.  Same arithmetic, bitwise the
+// same results; which one is faster depends on the storage width and tile.
+template <int S>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8, 8))) k_step8(const StepArgs a) {
+    extern __shared__ float ring[];
+    step_tiles<S>(a, ring);
 }
 
 // ---------------------------------------------------------------------------
@@ -1165,6 +1181,18 @@ hipError_t launch_step(int storage, const StepArgs &a, int block_x, hipStream_t 
     return hipGetLastError();
 }
 
+hipError_t launch_step8(int storage, const StepArgs &a, int block_x, hipStream_t s) {
+    const unsigned blocks = 8u * (unsigned)a.tiles_per_xcd;
+    const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
+    switch (storage) {
+    case ST_F32: k_step8<ST_F32><<<blocks, block_x, lds, s>>>(a); break;
+    case ST_F16: k_step8<ST_F16><<<blocks, block_x, lds, s>>>(a); break;
+    case ST_BF16: k_step8<ST_BF16><<<blocks, block_x, lds, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <int V>
 hipError_t launch_wide_v(int storage, const StepArgs &a, int block_x, hipStream_t s) {
     const unsigned blocks = 8u * (unsigned)a.tiles_per_xcd;
@@ -1249,6 +1277,19 @@ int step_blocks_per_cu(int storage, int block_x) {
     case ST_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_F32>, block_x, lds); break;
     case ST_F16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_F16>, block_x, lds); break;
     case ST_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_BF16>, block_x, lds); break;
+    default: break;
+    }
+    return e == hipSuccess && n > 0 ? n : 1;
+}
+
+int step8_blocks_per_cu(int storage, int block_x) {
+    const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (storage) {
+    case ST_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step8<ST_F32>, block_x, lds); break;
+    case ST_F16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step8<ST_F16>, block_x, lds); break;
+    case ST_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step8<ST_BF16>, block_x, lds); break;
     default: break;
     }
     return e == hipSuccess && n > 0 ? n : 1;

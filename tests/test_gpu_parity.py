@@ -155,13 +155,14 @@ def test_tile_shapes_bitwise_identical(lbm, tile):
 
 KERNEL_TILES = [("split", (128, 0)), ("split", (256, 0)), ("split", (128, 7)), ("split", (256, 64)),
                 ("wide2", (64, 0)), ("wide2", (128, 7)), ("wide2", (256, 64)),
-                ("wide4", (64, 5)), ("wide4", (128, 0))]
+                ("wide4", (64, 5)), ("wide4", (128, 0)),
+                ("fused8", (256, 0)), ("fused8", (128, 7)), ("fused8", (512, 64))]
 
 
 @pytest.mark.parametrize("storage", [0, 1, 2])
 @pytest.mark.parametrize("kernel,tile", KERNEL_TILES)
 def test_kernels_bitwise_equal_fused(lbm, storage, kernel, tile):
-    """The split and wide kernels do the fused kernel's arithmetic: bitwise
+    """The split, wide and 8-wave kernels do the fused kernel's arithmetic: bitwise
     equal moments and flux on every parity case, ragged ones included."""
     for name in sorted(CASES):
         c = CASES[name]()
@@ -178,7 +179,7 @@ def test_kernels_bitwise_equal_fused(lbm, storage, kernel, tile):
         assert a.flux() == b.flux()
 
 
-@pytest.mark.parametrize("kernel", ["split", "wide2", "wide4"])
+@pytest.mark.parametrize("kernel", ["split", "wide2", "wide4", "fused8"])
 def test_kernels_full_size(lbm, kernel):
     c = I.random_channel_case(nx=8192, ny=2048, seed=0)
     a = lbm.from_case(c)
