@@ -52,12 +52,11 @@ def measured_traffic(storage_name: str, tile):
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    e = t.get(storage_name)
-    if not e or e.get("kernel_sha") != kernel_sha():
-        return None
-    if list(e.get("tile", [])) != list(tile):
-        return None
-    return e.get("bytes_per_launch")
+    recs = t.get(storage_name) or []
+    for e in [recs] if isinstance(recs, dict) else recs:
+        if isinstance(e, dict) and e.get("kernel_sha") == kernel_sha() and list(e.get("tile", [])) == list(tile):
+            return e.get("bytes_per_launch")
+    return None
 
 
 def time_storage(case, storage, steps, warmup, tile):

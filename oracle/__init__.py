@@ -38,7 +38,8 @@ class _Params(C.Structure):
                 ("w_axis", C.c_double), ("w_diag", C.c_double),
                 ("rho_c", C.c_double), ("f_elec", C.c_double),
                 ("elec_layers", C.c_int32), ("elec_walls", C.c_uint32),
-                ("accel_x", C.c_double), ("accel_y", C.c_double)]
+                ("accel_x", C.c_double), ("accel_y", C.c_double),
+                ("collision", C.c_int32), ("trt_magic", C.c_double)]
 
 
 _lib = None
@@ -66,6 +67,8 @@ def _load():
         lib.orc_step.argtypes = [P, u8, dp, C.c_int64]
         lib.orc_step.restype = C.c_int
         lib.orc_flux.argtypes = [P, u8, dp, dp, dp]
+        lib.orc_trt_omega_minus.argtypes = [C.c_double, C.c_double]
+        lib.orc_trt_omega_minus.restype = C.c_double
         _lib = lib
     return _lib
 
@@ -74,7 +77,8 @@ def _params(p) -> _Params:
     return _Params(int(p.nx), int(p.ny), float(p.tau), float(p.rho0), float(p.g_axis),
                    float(p.g_diag), float(p.w_axis), float(p.w_diag), float(p.rho_c),
                    float(p.f_elec), int(p.elec_layers), int(p.elec_walls),
-                   float(p.accel_x), float(p.accel_y))
+                   float(p.accel_x), float(p.accel_y), int(getattr(p, "collision", 0)),
+                   float(getattr(p, "trt_magic", 3.0 / 16.0)))
 
 
 def _d(a):
@@ -110,6 +114,11 @@ def equilibrium(rho: float, ux: float, uy: float) -> np.ndarray:
 
 def phi(rho0: float, rho: float) -> float:
     return _load().orc_phi(float(rho0), float(rho))
+
+
+def trt_omega_minus(tau: float, magic: float) -> float:
+    """omega- of the TRT operator: (tau - 1/2)(1/omega- - 1/2) = Lambda."""
+    return _load().orc_trt_omega_minus(float(tau), float(magic))
 
 
 def electric_layer(p, solid):

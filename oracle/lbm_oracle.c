@@ -30,6 +30,16 @@
  *   - a driving acceleration g adds F_b = rho g to the force of eq. (10);
  *   - the domain is periodic in x and y; walls are solid rows in the mask.
  *
+ * A second collision operator, not in the paper, can replace steps 3-4 of the
+ * step (collision = 1): two-relaxation-time (TRT) collision (Ginzburg 2005;
+ * Ginzburg, Verhaeghe & d'Humieres 2008) with the forcing term of Guo, Zheng &
+ * Shi (Phys. Rev. E 65, 046308, 2002).  The force is the same F of eq. (10);
+ * the equilibrium takes u = (sum f e + F/2) / rho, the symmetric and
+ * antisymmetric parts of f - f^eq relax at omega+ = 1/tau and omega- with
+ * (1/omega+ - 1/2)(1/omega- - 1/2) = Lambda (trt_magic), and the source
+ * S_a = w_a [3 (e_a - u) + 9 (e_a . u) e_a] . F enters split the same way,
+ * weighted (1 - omega+/2) and (1 - omega-/2).
+ *
  * Arrays are row-major [ny][nx]; populations are planes [9][ny][nx].
  * Solid nodes carry no populations (their entries are ignored and left 0).
  */
@@ -48,6 +58,8 @@ typedef struct {
     int32_t elec_layers;
     uint32_t elec_walls; /* bit 0: bottom wall is an electrode, bit 1: top */
     double accel_x, accel_y;
+    int32_t collision;   /* 0: BGK with the velocity shift of eq. (10); 1: TRT with Guo forcing */
+    double trt_magic;    /* Lambda of the TRT operator */
 } orc_params;
 
 /* ---------------------------------------------------------------- lattice */
@@ -242,6 +254,42 @@ void orc_init(const orc_params *p, const uint8_t *solid, const double *rho,
     }
 }
 
+/* ------------------------------------------------------ TRT with Guo forcing */
+/* omega- of the TRT operator from tau (omega+ = 1/tau) and Lambda. */
+double orc_trt_omega_minus(double tau, double magic)
+{
+    return 1.0 / (magic / (tau - 0.5) + 0.5);
+}
+
+/*
+ * Collision of node i (see the header): rho and u = j / rho from eq. (2), F
+ * the total force.  Writes the nine post-collision populations to fs.
+ */
+static void collide_trt_guo(const orc_params *p, const double *f, double *fs, size_t n, size_t i,
+                            double rho, double ux, double uy, double Fx, double Fy)
+{
+    const double wp = 1.0 / p->tau;
+    const double wm = orc_trt_omega_minus(p->tau, p->trt_magic);
+    /* velocity of the equilibrium and of the source: (j + F/2) / rho */
+    const double vx = ux + 0.5 * Fx / rho, vy = uy + 0.5 * Fy / rho;
+    double feq[9], S[9], neq[9];
+    orc_equilibrium(rho, vx, vy, feq);
+    for (int a = 0; a < 9; ++a) {
+        const double eu = E[a][0] * vx + E[a][1] * vy;
+        const double eF = E[a][0] * Fx + E[a][1] * Fy;
+        const double uF = vx * Fx + vy * Fy;
+        S[a] = WT[a] * (3.0 * (eF - uF) + 9.0 * eu * eF);
+        neq[a] = f[(size_t)a * n + i] - feq[a];
+    }
+    for (int a = 0; a < 9; ++a) {
+        const int b = OPP[a];
+        const double np = 0.5 * (neq[a] + neq[b]), nm = 0.5 * (neq[a] - neq[b]);
+        const double sp = 0.5 * (S[a] + S[b]), sm = 0.5 * (S[a] - S[b]);
+        fs[(size_t)a * n + i] = f[(size_t)a * n + i] - wp * np - wm * nm
+                                + (1.0 - 0.5 * wp) * sp + (1.0 - 0.5 * wm) * sm;
+    }
+}
+
 /* --------------------------------------------------------------------- step */
 /*
  * Advance nsteps time steps in place.  f holds the populations after
@@ -250,6 +298,7 @@ void orc_init(const orc_params *p, const uint8_t *solid, const double *rho,
  *   2. forces Fs (5), Fw (6), electric f n, body rho g;
  *   3. u' from eq. (10);
  *   4. collision f* = f - (f - f^eq(rho, u'))/tau (right side of eq. (1));
+ *      (collision = 1: steps 3-4 are the TRT collision with Guo forcing);
  *   5. streaming f(x + e, t + 1) = f*(x) (left side of eq. (1)), with a
  *      population arriving from a solid node replaced by bounce-back.
  * Returns 0, or 1 if a fluid density became non-positive or not finite.
@@ -280,6 +329,10 @@ int orc_step(const orc_params *p, const uint8_t *solid, double *f, int64_t nstep
             if (solid[i]) { for (int a = 0; a < 9; ++a) fs[(size_t)a * n + i] = 0.0; continue; }
             double Fx = Fs[i] + Fw[i] + Fe[i] + rho[i] * p->accel_x;
             double Fy = Fs[n + i] + Fw[n + i] + Fe[n + i] + rho[i] * p->accel_y;
+            if (p->collision == 1) {
+                collide_trt_guo(p, f, fs, n, i, rho[i], ux[i], uy[i], Fx, Fy);
+                continue;
+            }
             double upx = (rho[i] * ux[i] + p->tau * Fx) / rho[i];  /* eq. (10) */
             double upy = (rho[i] * uy[i] + p->tau * Fy) / rho[i];
             orc_equilibrium(rho[i], upx, upy, feq);

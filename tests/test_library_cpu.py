@@ -194,3 +194,26 @@ def test_net_workspace_checks_without_gpu_work(lib):
     assert lib.lbm_net_forward(None, None, None, 1) == -1
     assert lib.lbm_net_adam(None, 1e-3, 0.9, 0.999, 1e-8) == -1
     lib.lbm_net_free(None)
+
+
+def test_bench_traffic_lookup(tmp_path, monkeypatch):
+    """bench.py reports counter traffic only for a record of the current kernel
+    source and the timed tile; records in either layout (one per storage, or a
+    list per storage) are read, and stale or foreign ones give None."""
+    import json
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    sha = bench.kernel_sha()
+    table = {"f32": [{"kernel_sha": sha, "tile": [512, 0, "fused8"], "bytes_per_launch": 123},
+                     {"kernel_sha": "0" * 16, "tile": [512, 64, "fused"], "bytes_per_launch": 7}],
+             "f16": {"kernel_sha": sha, "tile": [512, 0, "fused"], "bytes_per_launch": 45},
+             "_note": "text"}
+    f = tmp_path / "traffic.json"
+    f.write_text(json.dumps(table))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.measured_traffic("f32", [512, 0, "fused8"]) == 123
+    assert bench.measured_traffic("f32", [512, 64, "fused"]) is None      # another kernel source
+    assert bench.measured_traffic("f32", [256, 0, "fused8"]) is None      # another tile
+    assert bench.measured_traffic("f16", (512, 0, "fused")) == 45
+    assert bench.measured_traffic("bf16", [512, 0, "fused"]) is None
