@@ -27,6 +27,8 @@ if ROOT not in sys.path:
 METRIC = "MLUPS + % HBM roofline; steady-flux lattice updates, warm-start vs plain"
 HBM_PEAK_GBS = 8000.0
 STORAGES = {"f32": 0, "f16": 1, "bf16": 2}
+# extra lines: name -> (storage, collision); collision 1 is the TRT operator with Guo forcing
+VARIANTS = {"f16": (1, 0), "bf16": (2, 0), "f32_trt": (0, 1)}
 ELEM_BYTES = {0: 4, 1: 2, 2: 2}
 KERNEL_SRC = os.path.join(ROOT, "paper_0708_4182_amd", "csrc", "lbm_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
@@ -59,13 +61,13 @@ def measured_traffic(storage_name: str, tile):
     return None
 
 
-def time_storage(case, storage, steps, warmup, tile):
+def time_storage(case, storage, steps, warmup, tile, collision=0):
     import torch
     from paper_0708_4182_amd import lbm
 
     from paper_0708_4182_amd import autotune
 
-    c = case.params.replace(storage=storage)
+    c = case.params.replace(storage=storage, collision=collision)
     sim = lbm.Simulation(c, case.solid, case.rho, case.ux, case.uy)
     if tile:
         kernel, bx, rows = tile
@@ -73,7 +75,7 @@ def time_storage(case, storage, steps, warmup, tile):
         sim.set_tile(bx, rows)
         chosen = [bx, rows, kernel]
     else:
-        kernel, bx, rows, us, cached = autotune.tune(sim, reps=5, cache=None)
+        kernel, bx, rows, us, cached = autotune.tune(sim, reps=20, cache=None)
         chosen = [bx, rows, kernel]
     sim.step(warmup)
     sim.flux()
@@ -137,8 +139,9 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--storage", default="f32", choices=sorted(STORAGES))
-    ap.add_argument("--variants", default="f16,bf16",
-                    help="other storages timed after the main line ('' for none)")
+    ap.add_argument("--variants", default="f16,bf16,f32_trt",
+                    help="other lines timed after the main one: f16, bf16 (storage), f32_trt (FP32 storage "
+                         "with the TRT collision and Guo forcing); '' for none")
     ap.add_argument("--nx", type=int, default=8192)
     ap.add_argument("--ny", type=int, default=2048)
     ap.add_argument("--tile", default="auto",
@@ -175,7 +178,7 @@ def main():
     nfluid = int((case.solid == 0).sum())
 
     def line_for(name, r):
-        s = STORAGES[name]
+        s = STORAGES[name] if name in STORAGES else VARIANTS[name][0]
         alg_bytes = 18 * ELEM_BYTES[s] * nfluid
         achieved = alg_bytes / (r["step_ms"] * 1e-3) / 1e9
         traffic = measured_traffic(name, r["tile"])
@@ -195,7 +198,11 @@ def main():
     main_line = line_for(args.storage, main_r)
     variants = {}
     for v in [v for v in args.variants.split(",") if v and v != args.storage]:
-        r = time_storage(case, STORAGES[v], args.steps, args.warmup, tile)
+        st, coll = VARIANTS[v] if v in VARIANTS else (STORAGES[v], 0)
+        vt = tile
+        if coll and tile and tile[0] not in ("fused", "fused8"):
+            vt = ("fused", tile[1], tile[2])     # the TRT operator runs in the fused kernels only
+        r = time_storage(case, st, args.steps, args.warmup, vt, collision=coll)
         print(f"# {v}: tile {r['tile']} {r['step_ms']*1e3:.1f} us/step", file=sys.stderr, flush=True)
         variants[v] = line_for(v, r)
 

@@ -76,7 +76,25 @@ typedef struct {
                               LBM_F32 and rho0 for LBM_F16 / LBM_BF16.  A value near the
                               liquid density keeps the stored numbers small where the
                               flow is, which FP32 needs to resolve slow velocity modes  */
+    int32_t collision;     /* LBM_COLLIDE_BGK: the paper's velocity shift, eq. (10), and
+                              BGK relaxation, eq. (1).  LBM_COLLIDE_TRT_GUO (not in the
+                              paper): the same force F with Guo's forcing term and a
+                              two-relaxation-time collision, see below               */
+    double trt_magic;      /* Lambda of LBM_COLLIDE_TRT_GUO (> 0; 3/16 puts halfway
+                              bounce-back walls exactly halfway for plane Poiseuille
+                              flow at any tau); ignored for LBM_COLLIDE_BGK           */
 } lbm_params;
+
+/* Collision operators (lbm_params.collision).  LBM_COLLIDE_TRT_GUO: the
+ * equilibrium of eq. (3) takes u = (sum f e + F/2) / rho; the symmetric and
+ * antisymmetric parts of f - f^eq relax at omega+ = 1/tau and omega- with
+ * (1/omega+ - 1/2)(1/omega- - 1/2) = trt_magic; the source
+ * S_a = w_a [3 (e_a - u) + 9 (e_a . u) e_a] . F of Guo, Zheng & Shi (2002)
+ * is split the same way and weighted (1 - omega+/2), (1 - omega-/2).  F is the
+ * total force of eq. (10) (eqs. (5), (6), the electric force and rho g).
+ * lbm_moments and lbm_flux report u = sum f e / rho of eq. (2) for both. */
+#define LBM_COLLIDE_BGK 0
+#define LBM_COLLIDE_TRT_GUO 1
 
 typedef struct lbm_sim lbm_sim;
 
@@ -147,9 +165,10 @@ lbm_status lbm_set_tile(lbm_sim *sim, int32_t block_x, int32_t rows_per_block);
  * with direct-to-LDS loads and block_x compute threads only read LDS and store
  * (block_x 128 or 256; selecting it with another block_x sets block_x to 128).
  * LBM_KERNEL_FUSED8: the fused kernel compiled for 8 resident waves per SIMD
- * (64 registers; a few loop invariants live in scratch memory) instead of 6.
+ * (64 registers; a few loop invariants live in scratch memory) instead of 7.
  * All give bitwise the same results.  Default LBM_KERNEL_FUSED.  Takes effect
- * at the next lbm_step. */
+ * at the next lbm_step.  With LBM_COLLIDE_TRT_GUO only LBM_KERNEL_FUSED and
+ * LBM_KERNEL_FUSED8 are accepted (LBM_EINVAL otherwise) and tuned. */
 #define LBM_KERNEL_FUSED 0
 #define LBM_KERNEL_SPLIT 1
 #define LBM_KERNEL_WIDE2 2

@@ -61,7 +61,7 @@ struct Layout {
 
 bool finite_all(const lbm_params *p) {
     const double v[] = {p->tau, p->rho0, p->g_axis, p->g_diag, p->w_axis, p->w_diag,
-                        p->rho_c, p->f_elec, p->accel_x, p->accel_y, p->rho_ref};
+                        p->rho_c, p->f_elec, p->accel_x, p->accel_y, p->rho_ref, p->trt_magic};
     for (double d : v)
         if (!std::isfinite(d)) return false;
     return true;
@@ -78,6 +78,9 @@ std::string check_params(const lbm_params *p) {
     if (p->storage < LBM_F32 || p->storage > LBM_BF16) return "storage must be LBM_F32, LBM_F16 or LBM_BF16";
     if (p->elec_layers < 0 || p->elec_layers > 1024) return "elec_layers must be in [0, 1024]";
     if (p->elec_walls > 3u) return "elec_walls must be a combination of LBM_ELEC_BOTTOM and LBM_ELEC_TOP";
+    if (p->collision != LBM_COLLIDE_BGK && p->collision != LBM_COLLIDE_TRT_GUO)
+        return "collision must be LBM_COLLIDE_BGK or LBM_COLLIDE_TRT_GUO";
+    if (p->collision == LBM_COLLIDE_TRT_GUO && !(p->trt_magic > 0.0)) return "trt_magic must be > 0";
     return "";
 }
 
@@ -125,6 +128,11 @@ Model make_model(const lbm_params *p) {
     m.f_elec = (float)p->f_elec;
     m.gx = (float)p->accel_x;
     m.gy = (float)p->accel_y;
+    m.trt = p->collision == LBM_COLLIDE_TRT_GUO ? 1 : 0;
+    const double om_m = m.trt ? 1.0 / (p->trt_magic / (p->tau - 0.5) + 0.5) : 1.0 / p->tau;
+    m.omega_m = (float)om_m;
+    m.src_p = (float)(1.0 - 0.5 / p->tau);
+    m.src_m = (float)(1.0 - 0.5 * om_m);
     return m;
 }
 
@@ -375,8 +383,8 @@ lbm::StepArgs step_args(lbm_sim *s) {
             case LBM_KERNEL_SPLIT: per_cu = lbm::split_blocks_per_cu(s->p.storage, s->block_x); break;
             case LBM_KERNEL_WIDE2: per_cu = lbm::wide_blocks_per_cu(s->p.storage, s->block_x, 2); break;
             case LBM_KERNEL_WIDE4: per_cu = lbm::wide_blocks_per_cu(s->p.storage, s->block_x, 4); break;
-            case LBM_KERNEL_FUSED8: per_cu = lbm::step8_blocks_per_cu(s->p.storage, s->block_x); break;
-            default: per_cu = lbm::step_blocks_per_cu(s->p.storage, s->block_x); break;
+            case LBM_KERNEL_FUSED8: per_cu = lbm::step8_blocks_per_cu(s->p.storage, s->block_x, s->m.trt != 0); break;
+            default: per_cu = lbm::step_blocks_per_cu(s->p.storage, s->block_x, s->m.trt != 0); break;
             }
             const int cap = s->cus * per_cu;
             chunks = std::max(1, cap / strips);
@@ -497,6 +505,8 @@ lbm_status lbm_set_kernel(lbm_sim *s, int32_t kernel) {
     if (st) return st;
     if (kernel < LBM_KERNEL_FUSED || kernel > LBM_KERNEL_FUSED8)
         return fail(s, LBM_EINVAL, "kernel must be one of LBM_KERNEL_FUSED, _SPLIT, _WIDE2, _WIDE4, _FUSED8");
+    if (s->m.trt && kernel != LBM_KERNEL_FUSED && kernel != LBM_KERNEL_FUSED8)
+        return fail(s, LBM_EINVAL, "the TRT operator runs in LBM_KERNEL_FUSED and LBM_KERNEL_FUSED8 only");
     s->kernel = kernel;
     if (kernel == LBM_KERNEL_SPLIT && s->block_x != 128 && s->block_x != 256) s->block_x = 128;
     if ((kernel == LBM_KERNEL_WIDE2 || kernel == LBM_KERNEL_WIDE4) && s->block_x > 256) s->block_x = 256;
@@ -536,6 +546,7 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *row
     lbm_status res = LBM_OK;
     for (const Cand &cand : kCand) {
         const int bx = cand.bx;
+        if (s->m.trt && cand.kernel != LBM_KERNEL_FUSED && cand.kernel != LBM_KERNEL_FUSED8) continue;
         for (int r : kRows) {
             if (r > 0 && r >= s->p.ny) continue;
             s->kernel = cand.kernel;

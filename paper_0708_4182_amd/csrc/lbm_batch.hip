@@ -62,6 +62,10 @@ bool make_batch_layout(int n, const lbm_params *p, BatchLayout &L, std::string &
             why = "channel " + std::to_string(i) + ": " + w;
             return false;
         }
+        if (p[i].collision != p[0].collision) {
+            why = "all channels must use the same collision operator";
+            return false;
+        }
         if (p[i].storage != p[0].storage) {
             why = "all channels must use the same storage";
             return false;
@@ -111,6 +115,7 @@ bool make_batch_layout(int n, const lbm_params *p, BatchLayout &L, std::string &
 struct lbm_batch {
     int n = 0;
     int storage = 0;
+    bool trt = false;           // collision operator of every channel
     std::vector<lbm_params> p;
     std::vector<Grid> g;
     std::vector<ChannelDesc> desc;     // host mirror of the device table
@@ -220,7 +225,7 @@ lbm_status upload_tiles(lbm_batch *b) {
 // Grid of a step launch: the persistent grid, or 0 for one workgroup per tile.
 int persistent_grid(lbm_batch *b) {
     if (!b->persistent) return 0;
-    const int per_cu = lbm::batch_blocks_per_cu(b->storage, b->block_x);
+    const int per_cu = lbm::batch_blocks_per_cu(b->storage, b->block_x, b->trt);
     return std::max(1, std::min(b->ntiles, b->cus * per_cu));
 }
 
@@ -232,7 +237,7 @@ hipError_t enqueue_step(lbm_batch *b, hipStream_t s, int slot, int parity, int g
     a.ntiles = b->ntiles;
     a.slot = slot;
     a.parity = parity;
-    a.pad = 0;
+    a.trt = b->trt ? 1 : 0;
     return lbm::launch_batch_step(b->storage, a, b->block_x, grid, s);
 }
 
@@ -311,6 +316,7 @@ lbm_status lbm_batch_init(lbm_batch **out, int32_t n, const lbm_params *p, const
     lbm_batch *b = new lbm_batch();
     b->n = n;
     b->storage = p[0].storage;
+    b->trt = p[0].collision == LBM_COLLIDE_TRT_GUO;
     b->p.assign(p, p + n);
     b->g = L.g;
     b->stream = (hipStream_t)stream;

@@ -27,6 +27,9 @@ struct Model {
     float ga, gd, wa, wd;      // G_a and W_a per direction class
     float rho_c, f_elec;
     float gx, gy;              // driving acceleration
+    int32_t trt;               // 0: BGK with the velocity shift; 1: TRT with Guo forcing
+    float omega_m;             // TRT: relaxation rate of the antisymmetric part
+    float src_p, src_m;        // TRT: source weights 1 - omega/2 and 1 - omega_m/2
 };
 
 struct StepArgs {
@@ -64,16 +67,16 @@ struct BatchStepArgs {
     int32_t ntiles;
     int32_t slot;
     int32_t parity;            // index of the source buffer of every active channel
-    int32_t pad;
+    int32_t trt;               // collision operator of every channel (Model::trt)
 };
 
 // Launchers; each returns the hipError_t of its launch.
 hipError_t launch_step(int storage, const StepArgs &a, int block_x, hipStream_t s);
 // Resident workgroups of the step kernel per compute unit.
-int step_blocks_per_cu(int storage, int block_x);
+int step_blocks_per_cu(int storage, int block_x, bool trt);
 // The step kernel compiled for 8 waves per SIMD, and its resident workgroups.
 hipError_t launch_step8(int storage, const StepArgs &a, int block_x, hipStream_t s);
-int step8_blocks_per_cu(int storage, int block_x);
+int step8_blocks_per_cu(int storage, int block_x, bool trt);
 // The split step (a producer wave streams rows into LDS for block_x compute
 // threads; block_x = 128 or 256) and its resident workgroups per compute unit.
 hipError_t launch_step_split(int storage, const StepArgs &a, int block_x, hipStream_t s);
@@ -92,7 +95,7 @@ hipError_t launch_moments(int storage, const void *src, const uint16_t *flags, c
 // grid > 0: persistent kernel with that many workgroups taking tiles from the
 // queue (counter a.slot); grid <= 0: one workgroup per tile (no counter).
 hipError_t launch_batch_step(int storage, const BatchStepArgs &a, int block_x, int grid, hipStream_t s);
-int batch_blocks_per_cu(int storage, int block_x);
+int batch_blocks_per_cu(int storage, int block_x, bool trt);
 // Per-channel FP64 reduction of channels ids[0..n): out[4*k] = Q, out[4*k+1] =
 // mass, out[4*k+2] = bad nodes, for the buffer index cur[ids[k]].
 hipError_t launch_batch_reduce(int storage, const ChannelDesc *descs, const int32_t *ids,

@@ -34,7 +34,7 @@ template <> struct Codec<ST_BF16> {
     __device__ static T enc(float v) { return (__bf16)v; }
 };
 
-constexpr float W1 = 1.f / 9.f, W5 = 1.f / 36.f;
+constexpr float W0 = 4.f / 9.f, W1 = 1.f / 9.f, W5 = 1.f / 36.f;
 
 // Element access by 32-bit element offset from the buffer base; the offsets
 // of one buffer stay below 2^32 bytes (checked by the host), so the address
@@ -164,12 +164,47 @@ __device__ __forceinline__ void equilibrium(float rho, float s, float jx, float 
     feq[8] = E6 - O6;
 }
 
+// Two-relaxation-time collision with Guo's forcing term (lbm_params.collision
+// = LBM_COLLIDE_TRT_GUO; not the paper's scheme).  The equilibrium and the
+// source take u = (j + F/2) / rho; each opposite pair (a, b) relaxes its
+// symmetric part n+ = ((f - feq)_a + (f - feq)_b) / 2 at omega+ and its
+// antisymmetric part n- at omega-, and gets the matching parts of
+// S_a = w_a [3 (e_a - u) . F + 9 (e_a . u)(e_a . F)]:
+// S+ = w (9 (e.u)(e.F) - 3 u.F) weighted 1 - omega+/2, S- = 3 w e.F weighted
+// 1 - omega-/2.  Deviations d and feq share the offset w rho_off, which
+// cancels in n+ and n-.
+template <class C>
+__device__ __forceinline__ void collide_trt(const Model &m, const float d[9], float rho, float s, float jx,
+                                            float jy, float Fx, float Fy, typename C::T out[9]) {
+#pragma clang fp contract(off)
+    const float hx = jx + 0.5f * Fx, hy = jy + 0.5f * Fy;
+    float feq[9];
+    equilibrium(rho, s, hx, hy, feq);
+    const float inv = __builtin_amdgcn_rcpf(rho);
+    const float ux = hx * inv, uy = hy * inv;
+    const float uF3 = 3.f * (ux * Fx + uy * Fy);
+    const float wp = m.omega, wm = m.omega_m, cp = m.src_p, cm = m.src_m;
+    out[0] = C::enc(d[0] - wp * (d[0] - feq[0]) - cp * (W0 * uF3));
+    auto pair = [&](int a, int b, float eu, float eF, float w) {
+        const float na = d[a] - feq[a], nb = d[b] - feq[b];
+        const float np = 0.5f * (na + nb), nm = 0.5f * (na - nb);
+        const float sp = w * (9.f * eu * eF - uF3), sm = 3.f * w * eF;
+        const float sym = cp * sp - wp * np, anti = cm * sm - wm * nm;
+        out[a] = C::enc(d[a] + (sym + anti));
+        out[b] = C::enc(d[b] + (sym - anti));
+    };
+    pair(1, 3, ux, Fx, W1);
+    pair(2, 4, uy, Fy, W1);
+    pair(5, 7, ux + uy, Fx + Fy, W5);
+    pair(6, 8, uy - ux, Fy - Fx, W5);
+}
+
 // Force, velocity shift (eq. (10)) and BGK collision (eq. (1)) of one node,
 // then the store of its nine post-collision populations.  phi of the 3x3
 // neighbourhood comes from LDS rows rowm (y-1), row0 (y), rowp (y+1) at
 // column c; solid neighbours hold phi = 0 there, which removes them from
 // eq. (5) as the model requires.
-template <class C>
+template <class C, bool TRT = false>
 __device__ __forceinline__ void collide(const Model &m, const float d[9], float s, float jx, float jy,
                                         uint32_t fl, const float *rowm, const float *row0,
                                         const float *rowp, int c, typename C::T out[9]) {
@@ -195,6 +230,10 @@ __device__ __forceinline__ void collide(const Model &m, const float d[9], float 
     // driving body force
     Fx += rho * m.gx;
     Fy += rho * m.gy;
+    if constexpr (TRT) {
+        collide_trt<C>(m, d, rho, s, jx, jy, Fx, Fy, out);
+        return;
+    }
     // eq. (10): rho u' = rho u + tau F
     float feq[9];
     equilibrium(rho, s, jx + m.tau * Fx, jy + m.tau * Fy, feq);
@@ -203,14 +242,14 @@ __device__ __forceinline__ void collide(const Model &m, const float d[9], float 
     for (int a = 0; a < 9; ++a) out[a] = C::enc(d[a] + om * (feq[a] - d[a]));
 }
 
-template <class C>
+template <class C, bool TRT = false>
 __device__ __forceinline__ void collide_store(const Model &m, const float d[9], float s, float jx,
                                               float jy, uint32_t fl, const float *rowm,
                                               const float *row0, const float *rowp, int c,
                                               __amdgpu_buffer_rsrc_t dst, uint32_t plane,
                                               uint32_t row, uint32_t lane_byte) {
     typename C::T out[9];
-    collide<C>(m, d, s, jx, jy, fl, rowm, row0, rowp, c, out);
+    collide<C, TRT>(m, d, s, jx, jy, fl, rowm, row0, rowp, c, out);
     constexpr uint32_t E = sizeof(typename C::T);
 #pragma unroll
     for (int a = 0; a < 9; ++a) bstore(dst, lane_byte, ((uint32_t)a * plane + row) * E, out[a]);
@@ -246,7 +285,7 @@ __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >
 // chunks of a strip run on the same XCD.
 constexpr int RING = 4;
 
-template <int S>
+template <int S, bool TRT = false>
 __device__ __forceinline__ void step_tile(const void *src_ptr, void *dst_ptr, const uint16_t *flags_ptr,
                                           const Grid &g, const Model &m, int x0, int y0, int y1, bool up,
                                           float *ring) {
@@ -267,15 +306,17 @@ __device__ __forceinline__ void step_tile(const void *src_ptr, void *dst_ptr, co
     const int x = x0 + (act ? tid : 0);
     const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
 
-    // halo gather lanes: 0..8 left column, 16..24 right column, one population each
-    const int hl = tid & 15;
-    const bool hlane = tid < 32 && hl < 9;
-    const int hx = (tid < 16) ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + nact == nx ? 0 : x0 + nact);
-    const int ha = hlane ? hl : 0;
-    const uint32_t hsx = (uint32_t)wrapi(hx - kEX[ha], nx);
-    const int hdy = -kEY[ha];                    // source row offset
-    const uint32_t hsrcbit = kSRCBIT[ha];
-    const uint32_t hopp = (uint32_t)kOPP[ha];
+    // halo gather lanes: 0..8 left column, 16..24 right column, one population
+    // each; lanes of wave 0 outside the gather take population 0.  Their
+    // addressing is recomputed per row (wave 0 only) from a copy of the thread
+    // index the compiler cannot see through, so that it is not held in
+    // registers of every wave through the collision.
+    const bool hlane = tid < 32 && (tid & 15) < 9;
+    auto opaque = [](int v) {
+        asm volatile("" : "+v"(v));
+        return v;
+    };
+    auto halo_x = [&](int t) { return (t < 16) ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + nact == nx ? 0 : x0 + nact); };
 
     auto row_at = [&](int i) {
         const int r = up ? y0 - 1 + i : y1 - i;
@@ -303,7 +344,7 @@ __device__ __forceinline__ void step_tile(const void *src_ptr, void *dst_ptr, co
     const int wave_x0 = x0 + (tid & ~63);
     const bool wave_wraps = wave_x0 == 0 || wave_x0 + 64 > nx - 1;
     const uint32_t v0 = (uint32_t)x * E, vm = xm * E, vp = xp * E;
-    const uint32_t vf = (uint32_t)x * 2u, vhf = (uint32_t)hx * 2u;
+    const uint32_t vf = (uint32_t)x * 2u;
     auto issue_pops = [&](int yr, uint32_t fl, uint32_t hfl) {
         const int ym = yr == 0 ? ny - 1 : yr - 1, yp = yr == ny - 1 ? 0 : yr + 1;
         const uint32_t r0 = (uint32_t)yr * pitch, rm = (uint32_t)ym * pitch, rp = (uint32_t)yp * pitch;
@@ -324,16 +365,26 @@ __device__ __forceinline__ void step_tile(const void *src_ptr, void *dst_ptr, co
             for (int q = 0; q < 9; ++q) raw[q] = bload<T>(rs, o[q] * E, 0u);
         }
         if (tid < 64) {
-            const uint32_t hrow = hdy < 0 ? rm : (hdy > 0 ? rp : r0);
-            const uint32_t off = (hfl & hsrcbit) ? hopp * plane + r0 + (uint32_t)hx
-                                                 : (uint32_t)ha * plane + hrow + hsx;
+            // e_a and opp(a) of the gathered population a from packed tables:
+            // e_x + 1 and e_y + 1 in 2 bits, opp(a) in 4 bits per direction
+            const int t = opaque(tid);
+            const int ha = (t < 32 && (t & 15) < 9) ? (t & 15) : 0;
+            const int hx = halo_x(t);
+            const int ex = (int)((0x20919u >> (2 * ha)) & 3u) - 1;
+            const int ey = (int)((0x02865u >> (2 * ha)) & 3u) - 1;
+            const uint32_t opp = (uint32_t)((0x658721430ull >> (4 * ha)) & 15u);
+            const uint32_t srcbit = ha == 0 ? 0u : 1u << (opp - 1u);    // bit of x - e_a
+            const uint32_t hsx = (uint32_t)wrapi(hx - ex, nx);
+            const uint32_t hrow = ey > 0 ? rm : (ey < 0 ? rp : r0);   // row of y - e_y
+            const uint32_t off = (hfl & srcbit) ? opp * plane + r0 + (uint32_t)hx
+                                                : (uint32_t)ha * plane + hrow + hsx;
             hraw = bload<T>(rs, off * E, 0u);
         }
     };
     auto issue_flags = [&](int yr, uint32_t &fl, uint32_t &hfl) {
         const uint32_t r0b = (uint32_t)yr * pitch * 2u;
         fl = bload_flag(rf, vf, r0b);
-        if (tid < 64) hfl = bload_flag(rf, vhf, r0b);
+        if (tid < 64) hfl = bload_flag(rf, (uint32_t)halo_x(opaque(tid)) * 2u, r0b);
     };
 
     // prologue: flags of rows 0 and 1, populations of row 0
@@ -387,7 +438,7 @@ __device__ __forceinline__ void step_tile(const void *src_ptr, void *dst_ptr, co
             const float *mid = ring + ((i - 1) & (RING - 1)) * W;
             const float *rowm = up ? older : slot;
             const float *rowp = up ? slot : older;
-            collide_store<C>(m, pd, ps, pjx, pjy, pfl, rowm, mid, rowp, tid + 1, rd, plane,
+            collide_store<C, TRT>(m, pd, ps, pjx, pjy, pfl, rowm, mid, rowp, tid + 1, rd, plane,
                              (uint32_t)pyr * pitch, v0);
         }
 #pragma unroll
@@ -400,31 +451,34 @@ __device__ __forceinline__ void step_tile(const void *src_ptr, void *dst_ptr, co
     }
 }
 
-template <int S>
+template <int S, bool TRT>
 __device__ __forceinline__ void step_tiles(const StepArgs &a, float *ring) {
     const int tile = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
     if (tile >= a.ntiles) return;   // uniform for the workgroup, before any barrier
     const int strip = tile / a.chunks, chunk = tile - strip * a.chunks;
     const int y0 = (int)(((int64_t)chunk * a.g.ny) / a.chunks);
     const int y1 = (int)(((int64_t)(chunk + 1) * a.g.ny) / a.chunks);
-    step_tile<S>(a.src, a.dst, a.flags, a.g, a.m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring);
+    step_tile<S, TRT>(a.src, a.dst, a.flags, a.g, a.m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring);
 }
 
-template <int S>
+// TRT selects the collision operator at compile time (a run-time branch would
+// cost the paper's operator registers and occupancy).
+template <int S, bool TRT>
 __global__ void __launch_bounds__(512) k_step(const StepArgs a) {
     extern __shared__ float ring[];
-    step_tiles<S>(a, ring);
+    step_tiles<S, TRT>(a, ring);
 }
 
 // The same kernel compiled for 8 resident waves per SIMD (64 VGPRs) instead of
-// the 6 its natural register count allows.  The compiler keeps a few
-// loop-invariant values in scratch (reloaded per row from the L1 cache); the
-// extra waves keep a third more loads in flight.  Same arithmetic, bitwise the
-// same results; which one is faster depends on the storage width and tile.
-template <int S>
+// the 7 its natural register count allows.  The compiler keeps a few
+// loop-invariant values in scratch (12 bytes per lane, reloaded per row from
+// the L1 cache) and schedules the row loop differently.  Same arithmetic,
+// bitwise the same results; which one is faster depends on the storage width
+// and tile (the autotuner decides).
+template <int S, bool TRT>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8, 8))) k_step8(const StepArgs a) {
     extern __shared__ float ring[];
-    step_tiles<S>(a, ring);
+    step_tiles<S, TRT>(a, ring);
 }
 
 // ---------------------------------------------------------------------------
@@ -1066,7 +1120,7 @@ __global__ void __launch_bounds__(64) k_reduce_final(const double *__restrict__ 
 // Batched step over many lattices in one persistent launch.  Workgroups pull
 // tiles from a queue (one atomic per tile), so uneven channels balance
 // dynamically; every channel uses the same tile code as a single lattice.
-template <int S>
+template <int S, bool TRT>
 __global__ void __launch_bounds__(512) k_batch_step(const ChannelDesc *__restrict__ descs,
                                                     const uint32_t *__restrict__ tiles,
                                                     uint32_t *__restrict__ counters, int ntiles, int slot,
@@ -1090,14 +1144,14 @@ __global__ void __launch_bounds__(512) k_batch_step(const ChannelDesc *__restric
         const int strip = local / chunks, chunk = local - strip * chunks;
         const int y0 = (int)(((int64_t)chunk * g.ny) / chunks);
         const int y1 = (int)(((int64_t)(chunk + 1) * g.ny) / chunks);
-        step_tile<S>(src, dst, d->flags, g, m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring);
+        step_tile<S, TRT>(src, dst, d->flags, g, m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring);
     }
 }
 
 // The same batched step with one workgroup per tile (grid = number of tiles,
 // tiles mapped to XCDs in contiguous ranges): the hardware dispatcher does the
 // balancing and no state is carried between tiles.
-template <int S>
+template <int S, bool TRT>
 __global__ void __launch_bounds__(512) k_batch_tiles(const ChannelDesc *__restrict__ descs,
                                                      const uint32_t *__restrict__ tiles, int ntiles,
                                                      int tiles_per_xcd, int parity) {
@@ -1115,7 +1169,7 @@ __global__ void __launch_bounds__(512) k_batch_tiles(const ChannelDesc *__restri
     const int strip = local / chunks, chunk = local - strip * chunks;
     const int y0 = (int)(((int64_t)chunk * g.ny) / chunks);
     const int y1 = (int)(((int64_t)(chunk + 1) * g.ny) / chunks);
-    step_tile<S>(src, dst, d->flags, g, m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring);
+    step_tile<S, TRT>(src, dst, d->flags, g, m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring);
 }
 
 // Per-channel FP64 flux/mass reduction: one workgroup per channel, rows in
@@ -1172,10 +1226,20 @@ __global__ void __launch_bounds__(256) k_batch_reduce(const ChannelDesc *__restr
 hipError_t launch_step(int storage, const StepArgs &a, int block_x, hipStream_t s) {
     const unsigned blocks = 8u * (unsigned)a.tiles_per_xcd;
     const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
+    const bool trt = a.m.trt != 0;
     switch (storage) {
-    case ST_F32: k_step<ST_F32><<<blocks, block_x, lds, s>>>(a); break;
-    case ST_F16: k_step<ST_F16><<<blocks, block_x, lds, s>>>(a); break;
-    case ST_BF16: k_step<ST_BF16><<<blocks, block_x, lds, s>>>(a); break;
+    case ST_F32:
+        if (trt) k_step<ST_F32, true><<<blocks, block_x, lds, s>>>(a);
+        else k_step<ST_F32, false><<<blocks, block_x, lds, s>>>(a);
+        break;
+    case ST_F16:
+        if (trt) k_step<ST_F16, true><<<blocks, block_x, lds, s>>>(a);
+        else k_step<ST_F16, false><<<blocks, block_x, lds, s>>>(a);
+        break;
+    case ST_BF16:
+        if (trt) k_step<ST_BF16, true><<<blocks, block_x, lds, s>>>(a);
+        else k_step<ST_BF16, false><<<blocks, block_x, lds, s>>>(a);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1184,10 +1248,20 @@ hipError_t launch_step(int storage, const StepArgs &a, int block_x, hipStream_t 
 hipError_t launch_step8(int storage, const StepArgs &a, int block_x, hipStream_t s) {
     const unsigned blocks = 8u * (unsigned)a.tiles_per_xcd;
     const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
+    const bool trt = a.m.trt != 0;
     switch (storage) {
-    case ST_F32: k_step8<ST_F32><<<blocks, block_x, lds, s>>>(a); break;
-    case ST_F16: k_step8<ST_F16><<<blocks, block_x, lds, s>>>(a); break;
-    case ST_BF16: k_step8<ST_BF16><<<blocks, block_x, lds, s>>>(a); break;
+    case ST_F32:
+        if (trt) k_step8<ST_F32, true><<<blocks, block_x, lds, s>>>(a);
+        else k_step8<ST_F32, false><<<blocks, block_x, lds, s>>>(a);
+        break;
+    case ST_F16:
+        if (trt) k_step8<ST_F16, true><<<blocks, block_x, lds, s>>>(a);
+        else k_step8<ST_F16, false><<<blocks, block_x, lds, s>>>(a);
+        break;
+    case ST_BF16:
+        if (trt) k_step8<ST_BF16, true><<<blocks, block_x, lds, s>>>(a);
+        else k_step8<ST_BF16, false><<<blocks, block_x, lds, s>>>(a);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1269,27 +1343,45 @@ int split_blocks_per_cu(int storage, int block_x) {
     return block_x == 128 ? split_blocks_bx<128>(storage) : split_blocks_bx<256>(storage);
 }
 
-int step_blocks_per_cu(int storage, int block_x) {
+int step_blocks_per_cu(int storage, int block_x, bool trt) {
     const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
     switch (storage) {
-    case ST_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_F32>, block_x, lds); break;
-    case ST_F16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_F16>, block_x, lds); break;
-    case ST_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_BF16>, block_x, lds); break;
+    case ST_F32:
+        e = trt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_F32, true>, block_x, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_F32, false>, block_x, lds);
+        break;
+    case ST_F16:
+        e = trt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_F16, true>, block_x, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_F16, false>, block_x, lds);
+        break;
+    case ST_BF16:
+        e = trt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_BF16, true>, block_x, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_BF16, false>, block_x, lds);
+        break;
     default: break;
     }
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
-int step8_blocks_per_cu(int storage, int block_x) {
+int step8_blocks_per_cu(int storage, int block_x, bool trt) {
     const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
     switch (storage) {
-    case ST_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step8<ST_F32>, block_x, lds); break;
-    case ST_F16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step8<ST_F16>, block_x, lds); break;
-    case ST_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step8<ST_BF16>, block_x, lds); break;
+    case ST_F32:
+        e = trt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step8<ST_F32, true>, block_x, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step8<ST_F32, false>, block_x, lds);
+        break;
+    case ST_F16:
+        e = trt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step8<ST_F16, true>, block_x, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step8<ST_F16, false>, block_x, lds);
+        break;
+    case ST_BF16:
+        e = trt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step8<ST_BF16, true>, block_x, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step8<ST_BF16, false>, block_x, lds);
+        break;
     default: break;
     }
     return e == hipSuccess && n > 0 ? n : 1;
@@ -1354,38 +1446,49 @@ hipError_t launch_reduce(int storage, const void *src, const uint16_t *flags, co
 }
 
 
-hipError_t launch_batch_step(int storage, const BatchStepArgs &a, int block_x, int grid, hipStream_t s) {
-    const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
+template <bool TRT>
+hipError_t launch_batch_t(int storage, const BatchStepArgs &a, int block_x, int grid, size_t lds, hipStream_t s) {
     if (grid <= 0) {   // one workgroup per tile
         const int per = (a.ntiles + 7) / 8;
         switch (storage) {
-        case ST_F32: k_batch_tiles<ST_F32><<<8 * per, block_x, lds, s>>>(a.descs, a.tiles, a.ntiles, per, a.parity); break;
-        case ST_F16: k_batch_tiles<ST_F16><<<8 * per, block_x, lds, s>>>(a.descs, a.tiles, a.ntiles, per, a.parity); break;
-        case ST_BF16: k_batch_tiles<ST_BF16><<<8 * per, block_x, lds, s>>>(a.descs, a.tiles, a.ntiles, per, a.parity); break;
+        case ST_F32: k_batch_tiles<ST_F32, TRT><<<8 * per, block_x, lds, s>>>(a.descs, a.tiles, a.ntiles, per, a.parity); break;
+        case ST_F16: k_batch_tiles<ST_F16, TRT><<<8 * per, block_x, lds, s>>>(a.descs, a.tiles, a.ntiles, per, a.parity); break;
+        case ST_BF16: k_batch_tiles<ST_BF16, TRT><<<8 * per, block_x, lds, s>>>(a.descs, a.tiles, a.ntiles, per, a.parity); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
     }
     switch (storage) {
-    case ST_F32: k_batch_step<ST_F32><<<grid, block_x, lds, s>>>(a.descs, a.tiles, a.counters, a.ntiles, a.slot, a.parity); break;
-    case ST_F16: k_batch_step<ST_F16><<<grid, block_x, lds, s>>>(a.descs, a.tiles, a.counters, a.ntiles, a.slot, a.parity); break;
-    case ST_BF16: k_batch_step<ST_BF16><<<grid, block_x, lds, s>>>(a.descs, a.tiles, a.counters, a.ntiles, a.slot, a.parity); break;
+    case ST_F32: k_batch_step<ST_F32, TRT><<<grid, block_x, lds, s>>>(a.descs, a.tiles, a.counters, a.ntiles, a.slot, a.parity); break;
+    case ST_F16: k_batch_step<ST_F16, TRT><<<grid, block_x, lds, s>>>(a.descs, a.tiles, a.counters, a.ntiles, a.slot, a.parity); break;
+    case ST_BF16: k_batch_step<ST_BF16, TRT><<<grid, block_x, lds, s>>>(a.descs, a.tiles, a.counters, a.ntiles, a.slot, a.parity); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-int batch_blocks_per_cu(int storage, int block_x) {
+hipError_t launch_batch_step(int storage, const BatchStepArgs &a, int block_x, int grid, hipStream_t s) {
     const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
+    if (a.trt) return launch_batch_t<true>(storage, a, block_x, grid, lds, s);
+    return launch_batch_t<false>(storage, a, block_x, grid, lds, s);
+}
+
+template <bool TRT>
+int batch_blocks_t(int storage, size_t lds, int block_x) {
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
     switch (storage) {
-    case ST_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_step<ST_F32>, block_x, lds); break;
-    case ST_F16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_step<ST_F16>, block_x, lds); break;
-    case ST_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_step<ST_BF16>, block_x, lds); break;
+    case ST_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_step<ST_F32, TRT>, block_x, lds); break;
+    case ST_F16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_step<ST_F16, TRT>, block_x, lds); break;
+    case ST_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_step<ST_BF16, TRT>, block_x, lds); break;
     default: break;
     }
     return e == hipSuccess && n > 0 ? n : 1;
+}
+
+int batch_blocks_per_cu(int storage, int block_x, bool trt) {
+    const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
+    return trt ? batch_blocks_t<true>(storage, lds, block_x) : batch_blocks_t<false>(storage, lds, block_x);
 }
 
 hipError_t launch_batch_reduce(int storage, const ChannelDesc *descs, const int32_t *ids,

@@ -58,12 +58,20 @@ def test_workspace_bytes(lib):
     assert lbm.workspace_bytes(p.replace(rho_ref=-1.0)) == 0
     assert lbm.workspace_bytes(p.replace(rho_ref=float("nan"))) == 0
     assert lbm.workspace_bytes(p.replace(rho_ref=1.8)) == n32
+    # collision operator: BGK (0) or TRT with Guo forcing (1), Lambda > 0 for TRT
+    assert lbm.workspace_bytes(p.replace(collision=1)) == n32
+    assert lbm.workspace_bytes(p.replace(collision=2)) == 0
+    assert lbm.workspace_bytes(p.replace(collision=-1)) == 0
+    assert lbm.workspace_bytes(p.replace(collision=1, trt_magic=0.0)) == 0
+    assert lbm.workspace_bytes(p.replace(collision=1, trt_magic=float("inf"))) == 0
+    assert lbm.workspace_bytes(p.replace(collision=0, trt_magic=0.0)) == n32
     # one population buffer must stay below 4 GiB (32-bit offsets)
     assert lbm.workspace_bytes(I.Params(nx=65536, ny=4096)) == 0
 
 
 @pytest.mark.parametrize("bad", [dict(nx=2), dict(tau=0.4), dict(elec_walls=4),
-                                 dict(elec_layers=-1), dict(storage=3), dict(rho_ref=-0.5)])
+                                 dict(elec_layers=-1), dict(storage=3), dict(rho_ref=-0.5),
+                                 dict(collision=5), dict(collision=1, trt_magic=-1.0)])
 def test_init_rejects_invalid_params_without_gpu_work(lib, bad):
     from paper_0708_4182_amd import lbm
     import numpy as np
@@ -155,6 +163,11 @@ def test_batch_workspace_validation(lib):
     assert lib.lbm_batch_workspace_bytes(0, arr) == 0
     bad = (lbm.lbm_params * 2)(lbm.to_c_params(ps[0]), lbm.to_c_params(ps[1].replace(tau=0.3)))
     assert lib.lbm_batch_workspace_bytes(2, bad) == 0
+    # one collision operator per batch
+    ops = (lbm.lbm_params * 2)(lbm.to_c_params(ps[0]), lbm.to_c_params(ps[1].replace(collision=1)))
+    assert lib.lbm_batch_workspace_bytes(2, ops) == 0
+    trt = (lbm.lbm_params * 2)(*[lbm.to_c_params(q.replace(collision=1)) for q in ps[:2]])
+    assert lib.lbm_batch_workspace_bytes(2, trt) > 0
 
 
 def test_net_param_count_matches_the_network_definition(lib):
