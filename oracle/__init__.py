@@ -39,7 +39,8 @@ class _Params(C.Structure):
                 ("rho_c", C.c_double), ("f_elec", C.c_double),
                 ("elec_layers", C.c_int32), ("elec_walls", C.c_uint32),
                 ("accel_x", C.c_double), ("accel_y", C.c_double),
-                ("collision", C.c_int32), ("trt_magic", C.c_double)]
+                ("collision", C.c_int32), ("trt_magic", C.c_double),
+                ("elec_normal", C.c_int32)]
 
 
 _lib = None
@@ -61,6 +62,7 @@ def _load():
         lib.orc_phi.restype = C.c_double
         lib.orc_electric_layer.argtypes = [P, u8, u8, u8]
         lib.orc_flags.argtypes = [P, u8, C.POINTER(C.c_uint16)]
+        lib.orc_electric_normal.argtypes = [P, u8, u8]
         lib.orc_moments.argtypes = [P, u8, dp, dp, dp, dp]
         lib.orc_forces.argtypes = [P, u8, dp, dp, dp, dp]
         lib.orc_init.argtypes = [P, u8, dp, dp, dp, dp]
@@ -78,7 +80,7 @@ def _params(p) -> _Params:
                    float(p.g_diag), float(p.w_axis), float(p.w_diag), float(p.rho_c),
                    float(p.f_elec), int(p.elec_layers), int(p.elec_walls),
                    float(p.accel_x), float(p.accel_y), int(getattr(p, "collision", 0)),
-                   float(getattr(p, "trt_magic", 3.0 / 16.0)))
+                   float(getattr(p, "trt_magic", 3.0 / 16.0)), int(getattr(p, "elec_normal", 0)))
 
 
 def _d(a):
@@ -114,6 +116,15 @@ def equilibrium(rho: float, ux: float, uy: float) -> np.ndarray:
 
 def phi(rho0: float, rho: float) -> float:
     return _load().orc_phi(float(rho0), float(rho))
+
+
+def electric_normal(p, solid):
+    """Direction code (0: towards the electrode; a in 1..8: along e_a) of the
+    electric force per node."""
+    s = _solid(p, solid)
+    code = np.zeros_like(s)
+    _load().orc_electric_normal(C.byref(_params(p)), _u8(s), _u8(code))
+    return code
 
 
 def trt_omega_minus(tau: float, magic: float) -> float:

@@ -30,6 +30,13 @@
  *   - a driving acceleration g adds F_b = rho g to the force of eq. (10);
  *   - the domain is periodic in x and y; walls are solid rows in the mask.
  *
+ * Optionally (elec_normal = 1) the electric force acts along the local face
+ * normal of the insulator instead of towards the flat electrode: for a layer
+ * node x at Chebyshev distance d from the nearest solid node, v = sum of
+ * (s - x) over the solid nodes s at exactly that distance, and n is the unit
+ * lattice direction (sgn v_x, sgn v_y); if v = 0, n falls back to the
+ * electrode direction.  On flat walls this is the electrode direction.
+ *
  * A second collision operator, not in the paper, can replace steps 3-4 of the
  * step (collision = 1): two-relaxation-time (TRT) collision (Ginzburg 2005;
  * Ginzburg, Verhaeghe & d'Humieres 2008) with the forcing term of Guo, Zheng &
@@ -60,6 +67,7 @@ typedef struct {
     double accel_x, accel_y;
     int32_t collision;   /* 0: BGK with the velocity shift of eq. (10); 1: TRT with Guo forcing */
     double trt_magic;    /* Lambda of the TRT operator */
+    int32_t elec_normal; /* 0: n towards the electrode wall; 1: local face normal */
 } orc_params;
 
 /* ---------------------------------------------------------------- lattice */
@@ -141,16 +149,55 @@ void orc_electric_layer(const orc_params *p, const uint8_t *solid, uint8_t *laye
 }
 
 /*
- * Per-node flag word, the format the GPU library exports for byte-exact
- * comparison: bit (alpha-1) = S(x + e_alpha) for alpha = 1..8, bit 8 = S(x),
- * bit 9 = electric layer, bit 10 = top electrode side.  A solid node is 0x100.
+ * Direction of the electric force on every node with elec_normal = 1 (see the
+ * header): code[i] = alpha in 1..8 with n = e_alpha / |e_alpha|, or 0 where the
+ * electrode direction applies (not a layer node, v = 0, or elec_normal = 0).
+ * Brute force over the Chebyshev ball of radius elec_layers.
  */
-void orc_flags(const orc_params *p, const uint8_t *solid, uint16_t *flags)
+void orc_electric_normal(const orc_params *p, const uint8_t *solid, uint8_t *code)
 {
     lattice_init();
     size_t n = (size_t)p->nx * p->ny;
     uint8_t *layer = calloc(n, 1), *top = calloc(n, 1);
     orc_electric_layer(p, solid, layer, top);
+    int k = p->elec_layers;
+    for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x) {
+            size_t i = at(p, x, y);
+            code[i] = 0;
+            if (!p->elec_normal || !layer[i]) continue;
+            int dmin = k + 1;
+            for (int dy = -k; dy <= k; ++dy)
+                for (int dx = -k; dx <= k; ++dx) {
+                    int d = abs(dx) > abs(dy) ? abs(dx) : abs(dy);
+                    if (solid[at(p, x + dx, y + dy)] && d < dmin) dmin = d;
+                }
+            long vx = 0, vy = 0;
+            for (int dy = -dmin; dy <= dmin; ++dy)
+                for (int dx = -dmin; dx <= dmin; ++dx) {
+                    int d = abs(dx) > abs(dy) ? abs(dx) : abs(dy);
+                    if (d == dmin && solid[at(p, x + dx, y + dy)]) { vx += dx; vy += dy; }
+                }
+            int sx = (vx > 0) - (vx < 0), sy = (vy > 0) - (vy < 0);
+            for (int a = 1; a <= 8; ++a)
+                if (E[a][0] == sx && E[a][1] == sy) code[i] = (uint8_t)a;
+        }
+    free(layer); free(top);
+}
+
+/*
+ * Per-node flag word, the format the GPU library exports for byte-exact
+ * comparison: bit (alpha-1) = S(x + e_alpha) for alpha = 1..8, bit 8 = S(x),
+ * bit 9 = electric layer, bit 10 = top electrode side, bits 11-14 = the
+ * direction code of orc_electric_normal.  A solid node is 0x100.
+ */
+void orc_flags(const orc_params *p, const uint8_t *solid, uint16_t *flags)
+{
+    lattice_init();
+    size_t n = (size_t)p->nx * p->ny;
+    uint8_t *layer = calloc(n, 1), *top = calloc(n, 1), *code = calloc(n, 1);
+    orc_electric_layer(p, solid, layer, top);
+    orc_electric_normal(p, solid, code);
     for (int y = 0; y < p->ny; ++y)
         for (int x = 0; x < p->nx; ++x) {
             size_t i = at(p, x, y);
@@ -160,9 +207,10 @@ void orc_flags(const orc_params *p, const uint8_t *solid, uint16_t *flags)
                 if (solid[at(p, x + E[a][0], y + E[a][1])]) v |= (uint16_t)(1u << (a - 1));
             if (layer[i]) v |= 0x200;
             if (top[i]) v |= 0x400;
+            v |= (uint16_t)(code[i] << 11);
             flags[i] = v;
         }
-    free(layer); free(top);
+    free(layer); free(top); free(code);
 }
 
 /* ------------------------------------------------------------------ moments */
@@ -190,7 +238,8 @@ void orc_moments(const orc_params *p, const uint8_t *solid, const double *f,
  * (x plane then y plane); solid nodes get 0.  Any output may be NULL.
  */
 static void forces_on(const orc_params *p, const uint8_t *solid, const uint8_t *layer,
-                      const uint8_t *top, const double *rho, double *Fs, double *Fw, double *Fe)
+                      const uint8_t *top, const uint8_t *code, const double *rho, double *Fs, double *Fw,
+                      double *Fe)
 {
     size_t n = (size_t)p->nx * p->ny;
     double G[9], W[9];
@@ -218,8 +267,16 @@ static void forces_on(const orc_params *p, const uint8_t *solid, const uint8_t *
                 }
                 sx *= -phi[i]; sy *= -phi[i];
                 wx *= -phi[i]; wy *= -phi[i];
-                if (layer[i] && rho[i] >= p->rho_c)
-                    ey = top[i] ? p->f_elec : -p->f_elec;
+                if (layer[i] && rho[i] >= p->rho_c) {
+                    int a = code[i];
+                    if (a == 0) {
+                        ey = top[i] ? p->f_elec : -p->f_elec;
+                    } else {        /* f along e_a / |e_a| */
+                        double len = (a <= 4) ? 1.0 : sqrt(2.0);
+                        ex = p->f_elec * (E[a][0] / len);
+                        ey = p->f_elec * (E[a][1] / len);
+                    }
+                }
             }
             if (Fs) { Fs[i] = sx; Fs[n + i] = sy; }
             if (Fw) { Fw[i] = wx; Fw[n + i] = wy; }
@@ -233,10 +290,11 @@ void orc_forces(const orc_params *p, const uint8_t *solid, const double *rho,
 {
     lattice_init();
     size_t n = (size_t)p->nx * p->ny;
-    uint8_t *layer = calloc(n, 1), *top = calloc(n, 1);
+    uint8_t *layer = calloc(n, 1), *top = calloc(n, 1), *code = calloc(n, 1);
     orc_electric_layer(p, solid, layer, top);
-    forces_on(p, solid, layer, top, rho, Fs, Fw, Fe);
-    free(layer); free(top);
+    orc_electric_normal(p, solid, code);
+    forces_on(p, solid, layer, top, code, rho, Fs, Fw, Fe);
+    free(layer); free(top); free(code);
 }
 
 /* --------------------------------------------------------------------- init */
@@ -312,8 +370,9 @@ int orc_step(const orc_params *p, const uint8_t *solid, double *f, int64_t nstep
     double *Fs = malloc(2 * n * sizeof(double)), *Fw = malloc(2 * n * sizeof(double)),
            *Fe = malloc(2 * n * sizeof(double));
     double *fs = malloc(9 * n * sizeof(double));
-    uint8_t *layer = calloc(n, 1), *top = calloc(n, 1);
+    uint8_t *layer = calloc(n, 1), *top = calloc(n, 1), *code = calloc(n, 1);
     orc_electric_layer(p, solid, layer, top);
+    orc_electric_normal(p, solid, code);
     int bad = 0;
 
     for (int64_t t = 0; t < nsteps && !bad; ++t) {
@@ -321,7 +380,7 @@ int orc_step(const orc_params *p, const uint8_t *solid, double *f, int64_t nstep
         for (size_t i = 0; i < n; ++i)
             if (!solid[i] && !(rho[i] > 0.0 && isfinite(rho[i]))) bad = 1;
         if (bad) break;
-        forces_on(p, solid, layer, top, rho, Fs, Fw, Fe);
+        forces_on(p, solid, layer, top, code, rho, Fs, Fw, Fe);
 
         /* collision */
         double feq[9];
@@ -355,7 +414,7 @@ int orc_step(const orc_params *p, const uint8_t *solid, double *f, int64_t nstep
             }
     }
     free(rho); free(ux); free(uy); free(Fs); free(Fw); free(Fe); free(fs);
-    free(layer); free(top);
+    free(layer); free(top); free(code);
     return bad;
 }
 

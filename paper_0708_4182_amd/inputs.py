@@ -119,6 +119,7 @@ class Params:
     rho_ref: float = 0.0  # stored deviations are f - w rho_ref (0: raw f for fp32, rho0 for 16-bit)
     collision: int = 0  # 0: BGK with the velocity shift of eq. (10); 1: TRT with Guo forcing
     trt_magic: float = 3.0 / 16.0  # Lambda of the TRT operator
+    elec_normal: int = 0  # 0: electric force towards the electrode wall; 1: along the local face normal
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)
