@@ -83,6 +83,14 @@ typedef struct {
     double trt_magic;      /* Lambda of LBM_COLLIDE_TRT_GUO (> 0; 3/16 puts halfway
                               bounce-back walls exactly halfway for plane Poiseuille
                               flow at any tau); ignored for LBM_COLLIDE_BGK           */
+    int32_t elec_normal;   /* direction n of the electric force f n.  0: towards the
+                              electrode wall, (0, -1) on the bottom half and (0, +1)
+                              on the top half.  1: the local face normal of the
+                              insulator: for a layer node at Chebyshev distance d from
+                              the nearest solid node, the lattice direction
+                              (sgn v_x, sgn v_y) of v = sum of (s - x) over the solid
+                              nodes s at distance d, normalised (diagonals by
+                              1/sqrt 2); the electrode direction where v = 0         */
 } lbm_params;
 
 /* Collision operators (lbm_params.collision).  LBM_COLLIDE_TRT_GUO: the
@@ -141,8 +149,9 @@ lbm_status lbm_flux(lbm_sim *sim, double *Q, double *M);
 
 /* Per-node flag words (host uint16 [ny][nx]): bit (a-1) = S(x + e_a) for
  * a = 1..8 with e_1..e_8 = (1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1);
- * bit 8 = S(x); bit 9 = electric layer; bit 10 = top electrode side.  A solid
- * node is exactly 0x100.  Synchronizes. */
+ * bit 8 = S(x); bit 9 = electric layer; bit 10 = top electrode side; bits
+ * 11-14 = a in 1..8 where the electric force acts along e_a (elec_normal = 1),
+ * else 0.  A solid node is exactly 0x100.  Synchronizes. */
 lbm_status lbm_geometry(lbm_sim *sim, uint16_t *flags);
 
 /* Change the electric force magnitude and the driving acceleration without

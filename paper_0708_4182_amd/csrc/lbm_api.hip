@@ -81,6 +81,7 @@ std::string check_params(const lbm_params *p) {
     if (p->collision != LBM_COLLIDE_BGK && p->collision != LBM_COLLIDE_TRT_GUO)
         return "collision must be LBM_COLLIDE_BGK or LBM_COLLIDE_TRT_GUO";
     if (p->collision == LBM_COLLIDE_TRT_GUO && !(p->trt_magic > 0.0)) return "trt_magic must be > 0";
+    if (p->elec_normal != 0 && p->elec_normal != 1) return "elec_normal must be 0 or 1";
     return "";
 }
 
@@ -126,6 +127,7 @@ Model make_model(const lbm_params *p) {
     m.wd = (float)p->w_diag;
     m.rho_c = (float)p->rho_c;
     m.f_elec = (float)p->f_elec;
+    m.f_elec_diag = (float)(p->f_elec / std::sqrt(2.0));
     m.gx = (float)p->accel_x;
     m.gy = (float)p->accel_y;
     m.trt = p->collision == LBM_COLLIDE_TRT_GUO ? 1 : 0;
@@ -171,6 +173,23 @@ void derive_flags(const lbm_params *p, const uint8_t *solid, std::vector<uint16_
     // e_1..e_8
     static const int ex[8] = {1, 0, -1, 0, 1, -1, -1, 1};
     static const int ey[8] = {0, 1, 0, -1, 1, 1, -1, -1};
+    // direction a (1..8) of the electric force along the local face normal:
+    // sign of the summed displacements to the nearest solid nodes (Chebyshev
+    // distance), 0 where they cancel
+    auto normal_code = [&](int x, int y) -> uint32_t {
+        int dmin = k + 1;
+        for (int dy = -k; dy <= k; ++dy)
+            for (int dx = -k; dx <= k; ++dx)
+                if (S(x + dx, y + dy)) dmin = std::min(dmin, std::max(std::abs(dx), std::abs(dy)));
+        long vx = 0, vy = 0;
+        for (int dy = -dmin; dy <= dmin; ++dy)
+            for (int dx = -dmin; dx <= dmin; ++dx)
+                if (std::max(std::abs(dx), std::abs(dy)) == dmin && S(x + dx, y + dy)) { vx += dx; vy += dy; }
+        const int sx = (vx > 0) - (vx < 0), sy = (vy > 0) - (vy < 0);
+        for (int b = 0; b < 8; ++b)
+            if (ex[b] == sx && ey[b] == sy) return (uint32_t)(b + 1);
+        return 0u;
+    };
     out.assign((size_t)nx * ny, 0);
     for (int y = 0; y < ny; ++y) {
         const bool top = y >= ny / 2;
@@ -181,7 +200,10 @@ void derive_flags(const lbm_params *p, const uint8_t *solid, std::vector<uint16_
             uint32_t v = 0;
             for (int b = 0; b < 8; ++b)
                 if (S(x + ex[b], y + ey[b])) v |= 1u << b;
-            if (electrode && near[i]) v |= lbm::FL_LAYER;
+            if (electrode && near[i]) {
+                v |= lbm::FL_LAYER;
+                if (p->elec_normal) v |= normal_code(x, y) << lbm::FL_NSHIFT;
+            }
             if (top) v |= lbm::FL_TOP;
             out[i] = (uint16_t)v;
         }

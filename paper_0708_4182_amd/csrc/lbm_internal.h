@@ -11,6 +11,7 @@ namespace lbm {
 constexpr uint32_t FL_SOLID = 0x100u;  // S(x) = 1
 constexpr uint32_t FL_LAYER = 0x200u;  // electric layer
 constexpr uint32_t FL_TOP = 0x400u;    // top electrode side, n = (0, +1)
+constexpr uint32_t FL_NSHIFT = 11u;     // bits 11-14: direction a of the electric force, 0 = electrode
 
 // Geometry of the device arrays: planes [9][ny][pitch], flags [ny][pitch].
 struct Grid {
@@ -26,6 +27,7 @@ struct Model {
     float rho_off;             // reference density of the stored deviations (0: raw f)
     float ga, gd, wa, wd;      // G_a and W_a per direction class
     float rho_c, f_elec;
+    float f_elec_diag;         // f_elec / sqrt 2 (force along a diagonal face normal)
     float gx, gy;              // driving acceleration
     int32_t trt;               // 0: BGK with the velocity shift; 1: TRT with Guo forcing
     float omega_m;             // TRT: relaxation rate of the antisymmetric part

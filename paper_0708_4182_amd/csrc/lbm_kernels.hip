@@ -226,7 +226,16 @@ __device__ __forceinline__ void collide(const Model &m, const float d[9], float 
     }
     float Fx = -pc * sx, Fy = -pc * sy;
     // electric force on the conductive part of the layer, n towards the electrode
-    if ((fl & FL_LAYER) && rho >= m.rho_c) Fy += (fl & FL_TOP) ? m.f_elec : -m.f_elec;
+    if ((fl & FL_LAYER) && rho >= m.rho_c) {
+        const uint32_t a = (fl >> FL_NSHIFT) & 15u;
+        if (a == 0u) {
+            Fy += (fl & FL_TOP) ? m.f_elec : -m.f_elec;
+        } else {   // along e_a / |e_a|; e_x + 1, e_y + 1 packed in 2 bits per direction
+            const float fa = a >= 5u ? m.f_elec_diag : m.f_elec;
+            Fx += fa * (float)((int)((0x20919u >> (2u * a)) & 3u) - 1);
+            Fy += fa * (float)((int)((0x02865u >> (2u * a)) & 3u) - 1);
+        }
+    }
     // driving body force
     Fx += rho * m.gx;
     Fy += rho * m.gy;

@@ -65,13 +65,17 @@ def test_workspace_bytes(lib):
     assert lbm.workspace_bytes(p.replace(collision=1, trt_magic=0.0)) == 0
     assert lbm.workspace_bytes(p.replace(collision=1, trt_magic=float("inf"))) == 0
     assert lbm.workspace_bytes(p.replace(collision=0, trt_magic=0.0)) == n32
+    # direction of the electric force: 0 (electrode) or 1 (local face normal)
+    assert lbm.workspace_bytes(p.replace(elec_normal=1)) == n32
+    assert lbm.workspace_bytes(p.replace(elec_normal=2)) == 0
     # one population buffer must stay below 4 GiB (32-bit offsets)
     assert lbm.workspace_bytes(I.Params(nx=65536, ny=4096)) == 0
 
 
 @pytest.mark.parametrize("bad", [dict(nx=2), dict(tau=0.4), dict(elec_walls=4),
                                  dict(elec_layers=-1), dict(storage=3), dict(rho_ref=-0.5),
-                                 dict(collision=5), dict(collision=1, trt_magic=-1.0)])
+                                 dict(collision=5), dict(collision=1, trt_magic=-1.0),
+                                 dict(elec_normal=-1)])
 def test_init_rejects_invalid_params_without_gpu_work(lib, bad):
     from paper_0708_4182_amd import lbm
     import numpy as np
