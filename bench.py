@@ -150,6 +150,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-ceiling", action="store_true")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the launch-bound line (128x64 droplet, 1024x128 rough channel)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-sweep line (256 uneven channels, FP16 storage)")
     args = ap.parse_args()
@@ -243,6 +245,15 @@ def main():
                         "roofline": {"bound": "hbm", "achieved": round(bt["achieved_GBs"], 1),
                                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                      "frac": round(bt["achieved_GBs"] / HBM_PEAK_GBS, 4)}}
+    if not args.no_small:
+        from paper_0708_4182_amd import experiments
+        sm = experiments.small_configs()
+        print(f"# small: {sm}", file=sys.stderr, flush=True)
+        out["small"] = {"workload": "launch-bound lattices, FP32, autotuned: 128x64 droplet (R = 20, f = 1e-3) "
+                                    "and 1024x128 rough channel (a=8, b=4, p=32, f = 1e-3); eager lbm_step "
+                                    "launches vs a one-channel batch replaying a hipGraph of 50 steps; no "
+                                    "roofline claim (the lattices fit in cache)",
+                        **sm}
     if not args.no_copy_ceiling:
         out["copy_ceiling"] = copy_ceiling(9 * nsites * ELEM_BYTES[STORAGES[args.storage]])
     if not args.no_cpu_baseline:

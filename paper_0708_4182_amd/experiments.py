@@ -68,6 +68,41 @@ def sweep_throughput(n=256, seed=0, storage=1, steps=60, warmup=20, graph=10, tu
             "achieved_GBs": 18 * es * fluid / (ms * 1e-3) / 1e9}
 
 
+def small_configs(steps=2000, warmup=200, graph=50):
+    """Launch-bound workloads: the 128 x 64 droplet (config 1) and the
+    1024 x 128 rough channel (config 2), FP32, each timed as eager lbm_step
+    launches on one lattice and as a one-channel batch replaying a hipGraph of
+    ``graph`` steps.  MLUPS over all nodes."""
+    import torch
+    out = {}
+    for name, case in (("droplet128x64", I.droplet_case(f_elec=1e-3)),
+                       ("rough1024x128", I.rough_channel_case(nx=1024, ny=128, f_elec=1e-3, seed=0))):
+        nodes = case.params.nx * case.params.ny
+        res = {}
+        for mode in ("eager", "graph"):
+            if mode == "eager":
+                sim = lbm.from_case(case)
+                sim.autotune(reps=20)
+                run, stream = sim.step, sim.stream
+            else:
+                sim = lbm.Batch([case])
+                sim.autotune(reps=20)
+                sim.set_graph(graph)
+                run, stream = sim.step, sim.stream
+            run(warmup)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            run(steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            us = 1000.0 * e0.elapsed_time(e1) / steps
+            res[mode] = {"us_per_step": round(us, 2), "mlups": round(nodes / us, 1)}
+            del sim
+        out[name] = res
+    return out
+
+
 def sweep_steady(n=256, seed=0, storage=1, max_steps=200_000, check_every=200, window=2000, rtol=1e-8):
     """The 256-channel sweep table driven to steady flux in one batch (one
     launch per step, hipGraph of check_every steps, channels retired as they
