@@ -250,9 +250,9 @@ def main():
         sm = experiments.small_configs()
         print(f"# small: {sm}", file=sys.stderr, flush=True)
         out["small"] = {"workload": "launch-bound lattices, FP32, autotuned: 128x64 droplet (R = 20, f = 1e-3) "
-                                    "and 1024x128 rough channel (a=8, b=4, p=32, f = 1e-3); eager lbm_step "
-                                    "launches vs a one-channel batch replaying a hipGraph of 50 steps; no "
-                                    "roofline claim (the lattices fit in cache)",
+                                    "and 1024x128 rough channel (a=8, b=4, p=32, f = 1e-3); ordinary lbm_step "
+                                    "launches vs hipGraph replays of 50 steps (lbm_set_graph); no roofline "
+                                    "claim (the lattices fit in cache)",
                         **sm}
     if not args.no_copy_ceiling:
         out["copy_ceiling"] = copy_ceiling(9 * nsites * ELEM_BYTES[STORAGES[args.storage]])

@@ -185,13 +185,24 @@ lbm_status lbm_set_tile(lbm_sim *sim, int32_t block_x, int32_t rows_per_block);
 #define LBM_KERNEL_FUSED8 4
 lbm_status lbm_set_kernel(lbm_sim *sim, int32_t kernel);
 
+/* Replay steps as hipGraphs: lbm_step(n) runs floor(n / steps_per_graph)
+ * replays of a captured graph of steps_per_graph launches, then the remainder
+ * as ordinary launches.  steps_per_graph: 0 (ordinary launches only, the
+ * default) or an even number in [2, 4096].  A graph is captured on a private
+ * stream at the first replay from each buffer parity and holds kernel launches
+ * only; it bakes in the tile, kernel and forces, so lbm_set_tile,
+ * lbm_set_kernel, lbm_set_forces and lbm_autotune drop it.  Results are
+ * bitwise those of ordinary launches.  Worth it for small lattices, whose
+ * steps are bound by launch overhead. */
+lbm_status lbm_set_graph(lbm_sim *sim, int32_t steps_per_graph);
+
 /* The current kernel, block_x and rows_per_block (any pointer may be NULL). */
 lbm_status lbm_get_tile(const lbm_sim *sim, int32_t *kernel, int32_t *block_x, int32_t *rows_per_block);
 
 /* Autotuner: times each candidate (fused kernels: block_x in 64..512 (6 waves)
  * or 128..512 (8 waves); wide
  * kernels: block_x 64..256; split kernel: block_x 128 or 256; rows_per_block
- * in {0, 32, 64, 128}) for `reps`
+ * in {0, 4, 8, 16, 32, 64, 128}) for `reps`
  * launches on the current state and keeps the fastest.  The trial launches
  * write only the spare population buffer, so the simulation state and step
  * count are unchanged.  Synchronizes.  The chosen tile and its time per step

@@ -38,6 +38,10 @@ struct lbm_sim {
     int kernel = LBM_KERNEL_FUSED;
     int cus = 0;           // compute units of the device
     int chunks = 0;        // cached tiling (0 = recompute)
+    int graph_steps = 0;   // steps per hipGraph replay (0: eager launches only)
+    hipStream_t cap = nullptr;                  // private stream used only for graph capture
+    hipGraph_t graph[2] = {nullptr, nullptr};   // per source-buffer parity
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
     lbm_status sticky = LBM_OK;
     std::string err;
 };
@@ -426,14 +430,59 @@ lbm::StepArgs step_args(lbm_sim *s) {
     return a;
 }
 
-hipError_t launch(const lbm_sim *s, const lbm::StepArgs &a) {
+hipError_t launch_on(const lbm_sim *s, const lbm::StepArgs &a, hipStream_t st) {
     switch (s->kernel) {
-    case LBM_KERNEL_SPLIT: return lbm::launch_step_split(s->p.storage, a, s->block_x, s->stream);
-    case LBM_KERNEL_WIDE2: return lbm::launch_step_wide(s->p.storage, a, s->block_x, 2, s->stream);
-    case LBM_KERNEL_WIDE4: return lbm::launch_step_wide(s->p.storage, a, s->block_x, 4, s->stream);
-    case LBM_KERNEL_FUSED8: return lbm::launch_step8(s->p.storage, a, s->block_x, s->stream);
-    default: return lbm::launch_step(s->p.storage, a, s->block_x, s->stream);
+    case LBM_KERNEL_SPLIT: return lbm::launch_step_split(s->p.storage, a, s->block_x, st);
+    case LBM_KERNEL_WIDE2: return lbm::launch_step_wide(s->p.storage, a, s->block_x, 2, st);
+    case LBM_KERNEL_WIDE4: return lbm::launch_step_wide(s->p.storage, a, s->block_x, 4, st);
+    case LBM_KERNEL_FUSED8: return lbm::launch_step8(s->p.storage, a, s->block_x, st);
+    default: return lbm::launch_step(s->p.storage, a, s->block_x, st);
     }
+}
+
+hipError_t launch(const lbm_sim *s, const lbm::StepArgs &a) { return launch_on(s, a, s->stream); }
+
+// Graphs bake in the tile, kernel and model: any change drops them.
+void drop_graphs(lbm_sim *s) {
+    for (int k = 0; k < 2; ++k) {
+        if (s->gexec[k]) (void)hipGraphExecDestroy(s->gexec[k]);
+        if (s->graph[k]) (void)hipGraphDestroy(s->graph[k]);
+        s->gexec[k] = nullptr;
+        s->graph[k] = nullptr;
+    }
+}
+
+// Capture graph_steps launches starting from buffer `parity` on the private
+// stream (kernel launches only: no memset or copy nodes).
+lbm_status capture_graph(lbm_sim *s, int parity) {
+    if (!s->cap && hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking) != hipSuccess) {
+        s->cap = nullptr;
+        return fail(s, LBM_EDEVICE, "cannot create the capture stream");
+    }
+    lbm::StepArgs a = step_args(s);
+    HIP_TRY(s, hipStreamBeginCapture(s->cap, hipStreamCaptureModeRelaxed));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < s->graph_steps && e == hipSuccess; ++k) {
+        const int from = parity ^ (k & 1);
+        a.src = s->buf[from];
+        a.dst = s->buf[from ^ 1];
+        e = launch_on(s, a, s->cap);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(s->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(s, LBM_EDEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t x = nullptr;
+    const hipError_t e3 = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e3 != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(s, LBM_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e3));
+    }
+    s->graph[parity] = g;
+    s->gexec[parity] = x;
+    return LBM_OK;
 }
 }  // namespace
 
@@ -442,8 +491,17 @@ lbm_status lbm_step(lbm_sim *s, int64_t nsteps) {
     if (st) return st;
     if (nsteps < 0) return fail(s, LBM_EINVAL, "nsteps must be >= 0");
     DeviceGuard dg(s->device);
+    int64_t left = nsteps;
+    if (s->graph_steps > 0) {
+        while (left >= s->graph_steps) {
+            if (!s->gexec[s->cur] && (st = capture_graph(s, s->cur)) != LBM_OK) return st;
+            HIP_TRY(s, hipGraphLaunch(s->gexec[s->cur], s->stream));
+            left -= s->graph_steps;     // an even number of steps: the parity is unchanged
+            s->steps += s->graph_steps;
+        }
+    }
     lbm::StepArgs a = step_args(s);
-    for (int64_t k = 0; k < nsteps; ++k) {
+    for (int64_t k = 0; k < left; ++k) {
         a.src = s->buf[s->cur];
         a.dst = s->buf[s->cur ^ 1];
         HIP_TRY(s, launch(s, a));
@@ -503,6 +561,7 @@ lbm_status lbm_set_forces(lbm_sim *s, double f_elec, double accel_x, double acce
     s->p.accel_x = accel_x;
     s->p.accel_y = accel_y;
     s->m = make_model(&s->p);
+    drop_graphs(s);
     return LBM_OK;
 }
 
@@ -519,6 +578,7 @@ lbm_status lbm_set_tile(lbm_sim *s, int32_t block_x, int32_t rows) {
     s->block_x = block_x;
     s->rows = rows;
     s->chunks = 0;
+    drop_graphs(s);
     return LBM_OK;
 }
 
@@ -533,6 +593,18 @@ lbm_status lbm_set_kernel(lbm_sim *s, int32_t kernel) {
     if (kernel == LBM_KERNEL_SPLIT && s->block_x != 128 && s->block_x != 256) s->block_x = 128;
     if ((kernel == LBM_KERNEL_WIDE2 || kernel == LBM_KERNEL_WIDE4) && s->block_x > 256) s->block_x = 256;
     s->chunks = 0;
+    drop_graphs(s);
+    return LBM_OK;
+}
+
+lbm_status lbm_set_graph(lbm_sim *s, int32_t steps_per_graph) {
+    lbm_status st = usable(s);
+    if (st) return st;
+    if (steps_per_graph != 0 && (steps_per_graph < 2 || steps_per_graph > 4096 || steps_per_graph % 2))
+        return fail(s, LBM_EINVAL, "steps_per_graph must be 0 or an even number in [2, 4096]");
+    DeviceGuard dg(s->device);
+    drop_graphs(s);
+    s->graph_steps = steps_per_graph;
     return LBM_OK;
 }
 
@@ -555,7 +627,7 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *row
                                  {LBM_KERNEL_WIDE2, 256}, {LBM_KERNEL_WIDE4, 64},  {LBM_KERNEL_WIDE4, 128},
                                  {LBM_KERNEL_SPLIT, 128}, {LBM_KERNEL_SPLIT, 256}, {LBM_KERNEL_FUSED8, 128},
                                  {LBM_KERNEL_FUSED8, 256}, {LBM_KERNEL_FUSED8, 512}};
-    static const int kRows[] = {0, 32, 64, 128};
+    static const int kRows[] = {0, 4, 8, 16, 32, 64, 128};
     hipEvent_t e0, e1;
     HIP_TRY(s, hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -601,6 +673,7 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *row
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    drop_graphs(s);
     if (res != LBM_OK) {
         s->kernel = keep_kernel;
         s->block_x = keep_bx;
@@ -653,7 +726,15 @@ lbm_status lbm_load_state(lbm_sim *s, const void *host, size_t bytes) {
 
 int64_t lbm_steps_done(const lbm_sim *s) { return s ? s->steps : -1; }
 
-void lbm_free(lbm_sim *s) { delete s; }
+void lbm_free(lbm_sim *s) {
+    if (!s) return;
+    {
+        DeviceGuard dg(s->device);
+        drop_graphs(s);
+        if (s->cap) (void)hipStreamDestroy(s->cap);
+    }
+    delete s;
+}
 
 const char *lbm_last_error(const lbm_sim *s) {
     if (!s) return g_init_error.c_str();

@@ -70,9 +70,9 @@ def sweep_throughput(n=256, seed=0, storage=1, steps=60, warmup=20, graph=10, tu
 
 def small_configs(steps=2000, warmup=200, graph=50):
     """Launch-bound workloads: the 128 x 64 droplet (config 1) and the
-    1024 x 128 rough channel (config 2), FP32, each timed as eager lbm_step
-    launches on one lattice and as a one-channel batch replaying a hipGraph of
-    ``graph`` steps.  MLUPS over all nodes."""
+    1024 x 128 rough channel (config 2), FP32, each timed with ordinary
+    lbm_step launches and with hipGraph replays of ``graph`` steps
+    (lbm_set_graph).  MLUPS over all nodes."""
     import torch
     out = {}
     for name, case in (("droplet128x64", I.droplet_case(f_elec=1e-3)),
@@ -80,15 +80,11 @@ def small_configs(steps=2000, warmup=200, graph=50):
         nodes = case.params.nx * case.params.ny
         res = {}
         for mode in ("eager", "graph"):
-            if mode == "eager":
-                sim = lbm.from_case(case)
-                sim.autotune(reps=20)
-                run, stream = sim.step, sim.stream
-            else:
-                sim = lbm.Batch([case])
-                sim.autotune(reps=20)
+            sim = lbm.from_case(case)
+            sim.autotune(reps=20)
+            if mode == "graph":
                 sim.set_graph(graph)
-                run, stream = sim.step, sim.stream
+            run, stream = sim.step, sim.stream
             run(warmup)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

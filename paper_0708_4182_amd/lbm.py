@@ -22,7 +22,8 @@ STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
 
 # Exported symbols of include/lbm.h (checked by the CPU tests).
 SYMBOLS = ("lbm_workspace_bytes", "lbm_init", "lbm_init_device", "lbm_step", "lbm_moments",
-           "lbm_flux", "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_set_kernel", "lbm_get_tile",
+           "lbm_flux", "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_set_kernel", "lbm_set_graph",
+           "lbm_get_tile",
            "lbm_autotune", "lbm_state_bytes",
            "lbm_save_state", "lbm_load_state", "lbm_steps_done", "lbm_free", "lbm_last_error",
            "lbm_status_string", "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_step",
@@ -93,6 +94,7 @@ def load_library():
     lib.lbm_set_forces.argtypes = [vp, C.c_double, C.c_double, C.c_double]
     lib.lbm_set_tile.argtypes = [vp, C.c_int32, C.c_int32]
     lib.lbm_set_kernel.argtypes = [vp, C.c_int32]
+    lib.lbm_set_graph.argtypes = [vp, C.c_int32]
     lib.lbm_get_tile.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.lbm_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                  C.POINTER(C.c_float)]
@@ -239,6 +241,10 @@ class Simulation:
         'wide4' (2 or 4 adjacent columns per thread) or 'split' (a producer
         wave streams rows into LDS); all give bitwise the same results."""
         self._check(self.lib.lbm_set_kernel(self.h, KERNELS[kernel]))
+
+    def set_graph(self, steps_per_graph: int):
+        """Replay steps as hipGraphs of steps_per_graph launches (0: off)."""
+        self._check(self.lib.lbm_set_graph(self.h, int(steps_per_graph)))
 
     def tile(self):
         """(kernel name, block_x, rows) currently in use."""

@@ -92,3 +92,30 @@ def test_critical_density_separates_the_phases():
     for G in (-4.5, -5.0, -5.5):
         rv, rl = I.coexistence(G)
         assert rv < P["rho_c"] < rl
+
+
+def test_literal_normalisation_of_the_printed_parameters_diverges():
+    """Reading R1: the printed strengths (G = -0.52 with 2G on the axes, w =
+    -0.14 likewise, tau = 0.9, rho0 = 1) taken literally in eq. (4)/(6), from
+    the printed homogeneous state rho = 0.85 (+-1e-3 noise) on the printed
+    100 x 50 box with flat walls, drive the FP64 oracle to negative densities
+    within a few steps; the workloads' normalisation G w_a with G = -5 from the
+    same state separates into two phases and stays bounded."""
+    import numpy as np
+    import pytest
+    P = paper_parameters()
+    nx, ny = int(P["box_nx"]), int(P["box_ny"])
+    G, w = P["G_fluid_fluid"], P["w_fluid_wall"]
+    s = I.flat_channel(nx, ny)
+    rho = P["rho_init"] + I.noise(0, (ny, nx), 1e-3)
+    p = I.Params(nx=nx, ny=ny, tau=P["tau"], rho0=P["rho0"], g_axis=2 * G, g_diag=G, w_axis=2 * w,
+                 w_diag=w, f_elec=0.0)
+    f = O.init(p, s, rho)
+    with pytest.raises(FloatingPointError):
+        O.step(p, s, f, 50)
+    q = I.params_for_G(nx, ny, -5.0, tau=P["tau"], rho0=P["rho0"])
+    f = O.init(q, s, rho)
+    O.step(q, s, f, 3000)
+    r, _, _ = O.moments(q, s, f)
+    fl = s == 0
+    assert 0.1 < r[fl].min() < 0.3 and 1.7 < r[fl].max() < 2.1
