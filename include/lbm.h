@@ -147,6 +147,13 @@ lbm_status lbm_moments(lbm_sim *sim, float *rho, float *ux, float *uy, int on_de
  * (sticky) if any fluid density is <= 0 or not finite; Q and M are still set. */
 lbm_status lbm_flux(lbm_sim *sim, double *Q, double *M);
 
+/* Channel-averaged velocity profile: ux_mean[y] = (1/nx) sum over the fluid
+ * nodes of row y of u_x from eq. (2) (the profile of the paper's velocity
+ * figure), host float64 [ny], accumulated in FP64 on the GPU in a fixed order;
+ * its sum over the rows is the flux Q of lbm_flux up to summation order.
+ * Synchronizes. */
+lbm_status lbm_profile(lbm_sim *sim, double *ux_mean);
+
 /* Per-node flag words (host uint16 [ny][nx]): bit (a-1) = S(x + e_a) for
  * a = 1..8 with e_1..e_8 = (1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1);
  * bit 8 = S(x); bit 9 = electric layer; bit 10 = top electrode side; bits
@@ -253,6 +260,9 @@ lbm_status lbm_batch_flux(lbm_batch *b, double *Q /* [n] */, double *M /* [n] */
 
 /* eq. (2) moments of channel i, as lbm_moments. */
 lbm_status lbm_batch_moments(lbm_batch *b, int32_t i, float *rho, float *ux, float *uy, int on_device);
+
+/* Velocity profile of channel i, as lbm_profile (host float64 [ny_i]). */
+lbm_status lbm_batch_profile(lbm_batch *b, int32_t i, double *ux_mean);
 
 /* Flag words of channel i, as lbm_geometry. */
 lbm_status lbm_batch_geometry(lbm_batch *b, int32_t i, uint16_t *flags);

@@ -69,6 +69,7 @@ def _load():
         lib.orc_step.argtypes = [P, u8, dp, C.c_int64]
         lib.orc_step.restype = C.c_int
         lib.orc_flux.argtypes = [P, u8, dp, dp, dp]
+        lib.orc_profile.argtypes = [P, u8, dp, dp]
         lib.orc_trt_omega_minus.argtypes = [C.c_double, C.c_double]
         lib.orc_trt_omega_minus.restype = C.c_double
         _lib = lib
@@ -195,6 +196,15 @@ def flux(p, solid, f):
     Q = C.c_double(); M = C.c_double()
     _load().orc_flux(C.byref(_params(p)), _u8(s), _d(f), C.byref(Q), C.byref(M))
     return Q.value, M.value
+
+
+def profile(p, solid, f):
+    """Channel-averaged u_x per row: (1/nx) sum over the row's fluid nodes."""
+    s = _solid(p, solid)
+    f = np.ascontiguousarray(f, np.float64)
+    out = np.zeros(p.ny)
+    _load().orc_profile(C.byref(_params(p)), _u8(s), _d(f), _d(out))
+    return out
 
 
 def run(case, nsteps: int):

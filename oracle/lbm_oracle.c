@@ -419,6 +419,26 @@ int orc_step(const orc_params *p, const uint8_t *solid, double *f, int64_t nstep
 }
 
 /* ------------------------------------------------------------------- outputs */
+/* Channel-averaged velocity profile (the paper's velocity figure): out[y] =
+ * (1/nx) sum over the fluid nodes of row y of u_x from eq. (2), so that the
+ * flux of eq. (11) is the sum of out over the rows. */
+void orc_profile(const orc_params *p, const uint8_t *solid, const double *f, double *out)
+{
+    size_t n = (size_t)p->nx * p->ny;
+    double *rho = malloc(n * sizeof(double)), *ux = malloc(n * sizeof(double)),
+           *uy = malloc(n * sizeof(double));
+    orc_moments(p, solid, f, rho, ux, uy);
+    for (int y = 0; y < p->ny; ++y) {
+        double q = 0;
+        for (int x = 0; x < p->nx; ++x) {
+            size_t i = at(p, x, y);
+            if (!solid[i]) q += ux[i];
+        }
+        out[y] = q / p->nx;
+    }
+    free(rho); free(ux); free(uy);
+}
+
 /* eq. (11) with L = nx: Q = (1/nx) sum over fluid nodes of u_x; M = sum rho. */
 void orc_flux(const orc_params *p, const uint8_t *solid, const double *f, double *Q, double *M)
 {

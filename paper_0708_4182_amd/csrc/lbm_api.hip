@@ -511,6 +511,18 @@ lbm_status lbm_step(lbm_sim *s, int64_t nsteps) {
     return LBM_OK;
 }
 
+lbm_status lbm_profile(lbm_sim *s, double *ux_mean) {
+    lbm_status st = usable(s);
+    if (st) return st;
+    if (!ux_mean) return fail(s, LBM_EINVAL, "ux_mean must not be NULL");
+    DeviceGuard dg(s->device);
+    double *d = (double *)s->buf[s->cur ^ 1];     // staged in the spare population buffer
+    HIP_TRY(s, lbm::launch_profile(s->p.storage, s->buf[s->cur], s->flags, s->g, s->m.rho_off, d, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(ux_mean, d, sizeof(double) * (size_t)s->p.ny, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    return LBM_OK;
+}
+
 lbm_status lbm_moments(lbm_sim *s, float *rho, float *ux, float *uy, int on_device) {
     lbm_status st = usable(s);
     if (st) return st;

@@ -472,6 +472,20 @@ lbm_status lbm_batch_moments(lbm_batch *b, int32_t i, float *rho, float *ux, flo
     return LBM_OK;
 }
 
+lbm_status lbm_batch_profile(lbm_batch *b, int32_t i, double *ux_mean) {
+    lbm_status st = busable(b);
+    if (st) return st;
+    if ((st = check_index(b, i)) != LBM_OK) return st;
+    if (!ux_mean) return bfail(b, LBM_EINVAL, "ux_mean must not be NULL");
+    const Grid &g = b->g[i];
+    const char *src = b->cur[i] ? b->buf1[i] : b->buf0[i];
+    double *d = (double *)(b->cur[i] ? b->buf0[i] : b->buf1[i]);
+    BHIP(b, lbm::launch_profile(b->storage, src, b->flags[i], g, lbm::storage_offset_of(&b->p[i]), d, b->stream));
+    BHIP(b, hipMemcpyAsync(ux_mean, d, sizeof(double) * (size_t)g.ny, hipMemcpyDeviceToHost, b->stream));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    return LBM_OK;
+}
+
 lbm_status lbm_batch_geometry(lbm_batch *b, int32_t i, uint16_t *flags) {
     lbm_status st = busable(b);
     if (st) return st;

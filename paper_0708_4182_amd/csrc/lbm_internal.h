@@ -107,5 +107,8 @@ hipError_t launch_batch_reduce(int storage, const ChannelDesc *descs, const int3
 int max_reduce_blocks();
 hipError_t launch_reduce(int storage, const void *src, const uint16_t *flags, const Grid &g,
                          float rho_off, double *partials, double *out, hipStream_t s);
+// Channel-averaged u_x per row into out[ny] (device), one workgroup per row.
+hipError_t launch_profile(int storage, const void *src, const uint16_t *flags, const Grid &g, float rho_off,
+                          double *out, hipStream_t s);
 
 }  // namespace lbm

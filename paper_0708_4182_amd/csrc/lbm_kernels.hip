@@ -1096,6 +1096,38 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce(const typename Codec<S>:
     }
 }
 
+// Channel-averaged velocity profile: out[y] = (1/nx) sum over the fluid nodes
+// of row y of u_x = j_x / rho (eq. (2)), per node exactly as k_reduce forms it
+// (FP64 from the decoded populations); one workgroup per row, fixed tree, so
+// the profile sums to the flux of eq. (11) up to the order of the sums.
+template <int S>
+__global__ void __launch_bounds__(RED_THREADS) k_profile(const typename Codec<S>::T *__restrict__ src,
+                                                         const uint16_t *__restrict__ flags, Grid g,
+                                                         float rho_off, double inv_nx, double *__restrict__ out) {
+    using C = Codec<S>;
+    __shared__ double sh[RED_THREADS / 64];
+    const uint32_t pitch = (uint32_t)g.pitch;
+    const int y = blockIdx.x;
+    const uint32_t r0 = (uint32_t)y * pitch;
+    const uint32_t rm = (uint32_t)(y == 0 ? g.ny - 1 : y - 1) * pitch;
+    const uint32_t rp = (uint32_t)(y == g.ny - 1 ? 0 : y + 1) * pitch;
+    double q = 0.0;
+    for (int x = threadIdx.x; x < g.nx; x += blockDim.x) {
+        const uint32_t fl = flags[r0 + x];
+        if (fl & FL_SOLID) continue;
+        const uint32_t xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+        float d[9];
+        pull9<C>(src, g.plane, fl, rm, r0, rp, xm, (uint32_t)x, xp, d);
+        double rho = (double)rho_off;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) rho += (double)d[a];
+        const double jx = ((double)d[1] - (double)d[3]) + (((double)d[5] - (double)d[7]) + ((double)d[8] - (double)d[6]));
+        if (rho > 0.0 && isfinite(rho)) q += jx / rho;
+    }
+    const double t = block_sum(q, sh);
+    if (threadIdx.x == 0) out[y] = t * inv_nx;
+}
+
 __global__ void __launch_bounds__(64) k_reduce_final(const double *__restrict__ partials, int n,
                                                      double inv_nx, double *__restrict__ out) {
     // lane l sums a contiguous slice in order, lane 0 then sums the 64 slices
@@ -1436,6 +1468,18 @@ hipError_t launch_moments(int storage, const void *src, const uint16_t *flags, c
 }
 
 int max_reduce_blocks() { return RED_MAX_BLOCKS; }
+
+hipError_t launch_profile(int storage, const void *src, const uint16_t *flags, const Grid &g, float rho_off,
+                          double *out, hipStream_t s) {
+    const double inv_nx = 1.0 / (double)g.nx;
+    switch (storage) {
+    case ST_F32: k_profile<ST_F32><<<g.ny, RED_THREADS, 0, s>>>((const float *)src, flags, g, rho_off, inv_nx, out); break;
+    case ST_F16: k_profile<ST_F16><<<g.ny, RED_THREADS, 0, s>>>((const _Float16 *)src, flags, g, rho_off, inv_nx, out); break;
+    case ST_BF16: k_profile<ST_BF16><<<g.ny, RED_THREADS, 0, s>>>((const __bf16 *)src, flags, g, rho_off, inv_nx, out); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_reduce(int storage, const void *src, const uint16_t *flags, const Grid &g,
                          float rho_off, double *partials, double *out, hipStream_t s) {

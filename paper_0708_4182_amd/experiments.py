@@ -9,6 +9,10 @@
                   updates and wall time per channel.
   warm_start      train the encoder-decoder on steady channels and compare
                   lattice updates to steady flux, warm start against cold.
+  channel_study   rough channels of the paper's widths 80 and 160 over a
+                  sweep of f, to steady flux: Q/Q0 and velocity profiles.
+  small_configs   the launch-bound 128x64 and 1024x128 lattices, ordinary
+                  launches against hipGraph replays.
 
 Run as ``python -m paper_0708_4182_amd.experiments <name> [key=value ...]``;
 prints JSON.
@@ -97,6 +101,49 @@ def small_configs(steps=2000, warmup=200, graph=50):
             del sim
         out[name] = res
     return out
+
+
+def channel_study(widths="80,160", forces="0,5e-4,1e-3,1.5e-3,2e-3,3e-3", nx=256, storage=0,
+                  max_steps=400_000, check_every=200, window=4000, rtol=1e-8, layers=2, out=""):
+    """Rough channels of the paper's two widths (steps a = 8, b = 4, p = 32 on
+    both walls, both walls electrodes) over a sweep of the electric force, all
+    in one batch driven to steady flux: Q / Q0 per width and the
+    channel-averaged velocity profiles (the paper's flux and velocity figures)
+    in the normalisation of reading R1.  Writes profiles.npz and study.json
+    under ``out`` if given."""
+    import json
+    import os
+    import torch
+    ws = [int(v) for v in str(widths).split(",")]
+    fs = [float(v) for v in str(forces).split(",")]
+    cases, keys = [], []
+    for w in ws:
+        for f in fs:
+            cases.append(I.rough_channel_case(nx=nx, ny=w, f_elec=f, seed=0, layers=layers, storage=storage))
+            keys.append((w, f))
+    b = lbm.Batch(cases)
+    b.autotune(reps=3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = run_to_steady(b, check_every=check_every, window=window, rtol=rtol, max_steps=max_steps,
+                        log=lambda m: print("#", m, flush=True), log_every=20_000)
+    wall = time.perf_counter() - t0
+    prof = [b.profile(i) for i in range(len(cases))]
+    table = {}
+    for w in ws:
+        q0 = res.Q[keys.index((w, 0.0))] if 0.0 in fs else float("nan")
+        table[w] = {f"{f:g}": {"Q": float(res.Q[keys.index((w, f))]),
+                               "Q_over_Q0": float(res.Q[keys.index((w, f))] / q0),
+                               "steps": int(res.steps[keys.index((w, f))]),
+                               "converged": bool(res.converged[keys.index((w, f))])} for f in fs}
+    summary = {"experiment": "channel_study", "nx": nx, "widths": ws, "forces": fs, "storage": storage,
+               "layers": layers, "wall_s": wall, "node_updates": res.node_updates, "table": table}
+    if out:
+        os.makedirs(out, exist_ok=True)
+        np.savez(os.path.join(out, "profiles.npz"), keys=np.array(keys), **{f"p{i}": p for i, p in enumerate(prof)})
+        with open(os.path.join(out, "study.json"), "w") as fh:
+            json.dump(summary, fh, indent=1)
+    return summary
 
 
 def sweep_steady(n=256, seed=0, storage=1, max_steps=200_000, check_every=200, window=2000, rtol=1e-8):
@@ -216,7 +263,8 @@ def _kwargs(items):
 def main(argv):
     name = argv[1] if len(argv) > 1 else "flux_vs_field"
     fn = {"flux_vs_field": flux_vs_field, "sweep_throughput": sweep_throughput,
-          "sweep_steady": sweep_steady, "warm_start": warm_start}[name]
+          "sweep_steady": sweep_steady, "warm_start": warm_start, "channel_study": channel_study,
+          "small_configs": small_configs}[name]
     print(json.dumps(fn(**_kwargs(argv[2:]))), flush=True)
 
 

@@ -22,12 +22,14 @@ STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
 
 # Exported symbols of include/lbm.h (checked by the CPU tests).
 SYMBOLS = ("lbm_workspace_bytes", "lbm_init", "lbm_init_device", "lbm_step", "lbm_moments",
-           "lbm_flux", "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_set_kernel", "lbm_set_graph",
+           "lbm_flux", "lbm_profile", "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_set_kernel",
+           "lbm_set_graph",
            "lbm_get_tile",
            "lbm_autotune", "lbm_state_bytes",
            "lbm_save_state", "lbm_load_state", "lbm_steps_done", "lbm_free", "lbm_last_error",
            "lbm_status_string", "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_step",
-           "lbm_batch_flux", "lbm_batch_moments", "lbm_batch_geometry", "lbm_batch_init_device",
+           "lbm_batch_flux", "lbm_batch_moments", "lbm_batch_profile", "lbm_batch_geometry",
+           "lbm_batch_init_device",
            "lbm_batch_set_forces", "lbm_batch_retire", "lbm_batch_set_tile", "lbm_batch_set_graph",
            "lbm_batch_set_schedule",
            "lbm_batch_autotune", "lbm_batch_steps_done", "lbm_batch_free", "lbm_batch_last_error")
@@ -95,6 +97,8 @@ def load_library():
     lib.lbm_set_tile.argtypes = [vp, C.c_int32, C.c_int32]
     lib.lbm_set_kernel.argtypes = [vp, C.c_int32]
     lib.lbm_set_graph.argtypes = [vp, C.c_int32]
+    lib.lbm_profile.argtypes = [vp, dp]
+    lib.lbm_batch_profile.argtypes = [vp, C.c_int32, dp]
     lib.lbm_get_tile.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.lbm_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                  C.POINTER(C.c_float)]
@@ -218,6 +222,12 @@ class Simulation:
         self._check(self.lib.lbm_moments(self.h, C.c_void_p(t[0].data_ptr()),
                                          C.c_void_p(t[1].data_ptr()), C.c_void_p(t[2].data_ptr()), 1))
         return t
+
+    def profile(self):
+        """Channel-averaged u_x per row (float64 [ny]); sums to the flux Q."""
+        out = np.zeros(self.ny)
+        self._check(self.lib.lbm_profile(self.h, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
 
     def flux(self):
         """(Q, M) of eq. (11) and the fluid mass, FP64 (synchronizes)."""
@@ -348,6 +358,12 @@ class Batch:
 
     def step(self, n: int = 1):
         self._check(self.lib.lbm_batch_step(self.h, int(n)))
+
+    def profile(self, i: int):
+        """Channel-averaged u_x per row of channel i (float64 [ny_i])."""
+        out = np.zeros(self.shapes[i][0])
+        self._check(self.lib.lbm_batch_profile(self.h, int(i), out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
 
     def flux(self):
         """(Q [n], M [n]) float64 numpy arrays; raises Diverged if any channel diverged."""

@@ -125,6 +125,7 @@ def test_null_handle_calls(lib):
     assert lib.lbm_steps_done(None) == -1
     assert lib.lbm_set_kernel(None, 1) == -1
     assert lib.lbm_set_graph(None, 2) == -1
+    assert lib.lbm_profile(None, None) == -1
     assert lib.lbm_get_tile(None, None, None, None) == -1
     lib.lbm_free(None)
     assert lib.lbm_status_string(-4) == b"LBM_EDIVERGED"

@@ -301,3 +301,25 @@ def test_rotation_covariance():
     O.step(p, s, f, 3)
     O.step(p, rot(s), g, 3)
     np.testing.assert_allclose(rot_f(f), g, atol=1e-14)
+
+
+def test_velocity_profile_is_the_zero_slip_parabola():
+    """The channel-averaged profile of a steady Poiseuille flow at
+    tau = 1/2 + sqrt(3)/4 is the exact parabola (after the g/2 shift to the
+    physical velocity), and its sum over the rows is the flux of eq. (11)."""
+    p, s, f, u, uy, analytic, nu, g = poiseuille(0.5 + np.sqrt(3) / 4)
+    prof = O.profile(p, s, f)
+    assert prof[0] == 0 and prof[-1] == 0                 # solid rows
+    np.testing.assert_allclose(prof[1:-1] + g / 2, analytic, rtol=1e-8, atol=1e-9 * analytic.max())
+    Q, _ = O.flux(p, s, f)
+    assert abs(prof.sum() - Q) <= 1e-14 * abs(Q)
+
+
+def test_velocity_profile_rough_channel_sums_to_flux():
+    c = I.rough_channel_case(nx=64, ny=40, f_elec=1e-3, accel=1e-6, seed=1)
+    f = O.run(c, 300)
+    prof = O.profile(c.params, c.solid, f)
+    _, ux, _ = O.moments(c.params, c.solid, f)
+    np.testing.assert_allclose(prof, ux.sum(1) / c.params.nx, rtol=1e-13, atol=1e-18)
+    Q, _ = O.flux(c.params, c.solid, f)
+    assert abs(prof.sum() - Q) <= 1e-13 * abs(Q)
