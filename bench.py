@@ -150,6 +150,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-ceiling", action="store_true")
+    ap.add_argument("--no-network", action="store_true",
+                    help="skip the warm-start network line (training and inference rate)")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the launch-bound line (128x64 droplet, 1024x128 rough channel)")
     ap.add_argument("--no-batch", action="store_true",
@@ -245,6 +247,17 @@ def main():
                         "roofline": {"bound": "hbm", "achieved": round(bt["achieved_GBs"], 1),
                                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                      "frac": round(bt["achieved_GBs"] / HBM_PEAK_GBS, 4)}}
+    if not args.no_network:
+        from paper_0708_4182_amd import experiments
+        nt = experiments.net_throughput()
+        print(f"# network: {nt}", file=sys.stderr, flush=True)
+        out["network"] = {"workload": "warm-start encoder-decoder (channels 32/64/128/128, 15 layers), batch of 32 "
+                                      "samples of 3 x 64 x 256, bf16 activations, random He-initialised weights "
+                                      "and random inputs; train = forward + backward + Adam",
+                          **nt,
+                          "roofline": {"bound": "mfma", "achieved": nt["infer"]["tflops"], "peak": 2500.0,
+                                       "unit": "TFLOP/s", "frac": round(nt["infer"]["tflops"] / 2500.0, 4),
+                                       "note": "inference; the bf16 dense MFMA peak"}}
     if not args.no_small:
         from paper_0708_4182_amd import experiments
         sm = experiments.small_configs()

@@ -15,6 +15,10 @@
  *   eq. (11) Q = (1/L) integral of u_x over the channel
  * Walls are solid nodes of a mask; populations arriving from a solid node are
  * replaced by halfway bounce-back.  The domain is periodic in x and y.
+ * Two options are not the paper's and are off by default: a two-relaxation-
+ * time collision with Guo's forcing term in place of eq. (10) and BGK
+ * (lbm_params.collision), and the electric force along the local face normal
+ * of a rough wall instead of towards the electrode (lbm_params.elec_normal).
  *
  * Conventions for every entry point:
  *   - the return value is an lbm_status: 0 on success, < 0 on error; nothing

@@ -13,6 +13,7 @@
                   sweep of f, to steady flux: Q/Q0 and velocity profiles.
   small_configs   the launch-bound 128x64 and 1024x128 lattices, ordinary
                   launches against hipGraph replays.
+  net_throughput  training and inference rate of the warm-start network.
 
 Run as ``python -m paper_0708_4182_amd.experiments <name> [key=value ...]``;
 prints JSON.
@@ -146,6 +147,55 @@ def channel_study(widths="80,160", forces="0,5e-4,1e-3,1.5e-3,2e-3,3e-3", nx=256
     return summary
 
 
+def net_flops(H=64, W=256, cin=3, cout=3, chans=(32, 64, 128, 128)):
+    """(forward, backward) multiply-add FLOPs of one sample of the warm-start
+    network: 2 k^2 cin cout per output pixel and layer; the backward does the
+    input gradient (all layers but the first) and the weight gradient."""
+    from . import net
+    sizes = [(H, W)] * 2 + [(H // 2, W // 2)] * 2 + [(H // 4, W // 4)] * 2 + [(H // 8, W // 8)] * 2 \
+        + [(H // 4, W // 4)] * 2 + [(H // 2, W // 2)] * 2 + [(H, W)] * 3
+    fwd = bwd = 0.0
+    for i, ((_, ci, co, k), (h, w)) in enumerate(zip(net.layer_shapes(cin, cout, chans), sizes)):
+        f = 2.0 * k * k * ci * co * h * w
+        fwd += f
+        bwd += f * (2 if i > 0 else 1)
+    return fwd, bwd
+
+
+def net_throughput(batch=32, H=64, W=256, steps=50, warmup=5, seed=0):
+    """Training steps (forward, backward, Adam) and inference of the warm-start
+    network on random inputs of the warm-start shape, bf16 activations:
+    samples per second and delivered TFLOP/s."""
+    import torch
+    from . import net
+    m = net.Net(H, W, batch, act_bf16=True)
+    m.set_params(net.he_init(net.layer_shapes(), seed))
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    x = torch.randn((batch, 3, H, W), generator=g, device="cuda")
+    t = torch.randn((batch, 3, H, W), generator=g, device="cuda")
+    fluid = (torch.rand((batch, H, W), generator=g, device="cuda") > 0.1).to(torch.uint8)
+    fwd, bwd = net_flops(H, W)
+    out = {}
+    for mode in ("train", "infer"):
+        run = (lambda: m.train_step(x, t, fluid, lr=1e-4, want_loss=False)) if mode == "train" \
+            else (lambda: m.forward(x))
+        for _ in range(warmup):
+            run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(m.stream)
+        for _ in range(steps):
+            run()
+        e1.record(m.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        flops = batch * (fwd + bwd if mode == "train" else fwd)
+        out[mode] = {"ms_per_batch": round(ms, 3), "samples_per_s": round(batch / (ms * 1e-3), 1),
+                     "tflops": round(flops / (ms * 1e-3) / 1e12, 2)}
+    out["gflop_per_sample"] = {"forward": round(fwd / 1e9, 3), "backward": round(bwd / 1e9, 3)}
+    return out
+
+
 def sweep_steady(n=256, seed=0, storage=1, max_steps=200_000, check_every=200, window=2000, rtol=1e-8):
     """The 256-channel sweep table driven to steady flux in one batch (one
     launch per step, hipGraph of check_every steps, channels retired as they
@@ -264,7 +314,7 @@ def main(argv):
     name = argv[1] if len(argv) > 1 else "flux_vs_field"
     fn = {"flux_vs_field": flux_vs_field, "sweep_throughput": sweep_throughput,
           "sweep_steady": sweep_steady, "warm_start": warm_start, "channel_study": channel_study,
-          "small_configs": small_configs}[name]
+          "small_configs": small_configs, "net_throughput": net_throughput}[name]
     print(json.dumps(fn(**_kwargs(argv[2:]))), flush=True)
 
 
