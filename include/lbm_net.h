@@ -32,9 +32,11 @@
  * array [n][H][W], nonzero where the loss counts.  Activations are stored in
  * bf16 (act_bf16 = 1) or FP32 (act_bf16 = 0, the checking build).  With bf16
  * activations the forward 3x3 convolutions after the first run on matrix
- * cores with the weights rounded to bf16 and FP32 accumulation; everything
- * else (and the FP32 build throughout) multiplies and sums in FP32.  The loss
- * is reduced in FP64; master weights, gradients and Adam moments are FP32.
+ * cores with the weights rounded to bf16 and FP32 accumulation, and so do the
+ * input-gradient convolutions of the backward pass, with the layer gradient
+ * and the weights rounded to bf16; everything else (and the FP32 build
+ * throughout) multiplies and sums in FP32.  The loss is reduced in FP64;
+ * master weights, gradients and Adam moments are FP32.
  */
 #ifndef LBM_NET_H
 #define LBM_NET_H

@@ -32,7 +32,9 @@ The production build also multiplies on bf16 matrix cores in the forward 3x3
 convolutions after the first, with the weights rounded to bf16 there; that is
 ``wround=round_bf16``: those forward convolutions use rounded weights, and the
 backward pass uses the unrounded weights (the gradient passes the weight
-rounding unchanged too).
+rounding unchanged too).  Its input-gradient convolutions (every 3x3 layer
+but the first) also run on bf16 matrix cores, with the layer gradient and the
+weights rounded to bf16 there: ``ground=round_bf16`` in ``backward``.
 """
 from __future__ import annotations
 
@@ -110,8 +112,10 @@ def conv(x, W, b):
     return y
 
 
-def conv_backward(x, W, dy):
-    """Gradients (dx, dW, db) of conv for upstream dy."""
+def conv_backward(x, W, dy, dxr=None):
+    """Gradients (dx, dW, db) of conv for upstream dy; with ``dxr`` the input
+    gradient of a 3x3 layer is formed from dxr(dy) and dxr(W) (the weight
+    gradient keeps dy as it is)."""
     N, ci, H, Wd = x.shape
     co, _, k, _ = W.shape
     db = dy.sum(axis=(0, 2, 3))
@@ -123,6 +127,7 @@ def conv_backward(x, W, dy):
     xp[:, :, 1:-1, 1:-1] = x
     xp[:, :, 1:-1, 0] = x[:, :, :, -1]
     xp[:, :, 1:-1, -1] = x[:, :, :, 0]
+    dyx, Wx = (dy, W) if dxr is None else (dxr(dy), dxr(W))
     dW = np.zeros_like(W)
     dxp = np.zeros_like(xp)
     for o in range(co):
@@ -130,7 +135,7 @@ def conv_backward(x, W, dy):
             for ky in range(3):
                 for kx in range(3):
                     dW[o, c, ky, kx] = (dy[:, o] * xp[:, c, ky:ky + H, kx:kx + Wd]).sum()
-                    dxp[:, c, ky:ky + H, kx:kx + Wd] += W[o, c, ky, kx] * dy[:, o]
+                    dxp[:, c, ky:ky + H, kx:kx + Wd] += Wx[o, c, ky, kx] * dyx[:, o]
     dx = dxp[:, :, 1:-1, 1:-1].copy()
     dx[:, :, :, -1] += dxp[:, :, 1:-1, 0]      # the left pad was column W-1
     dx[:, :, :, 0] += dxp[:, :, 1:-1, -1]      # the right pad was column 0
@@ -203,9 +208,12 @@ def loss_grad(y, t, fluid):
     return 2.0 * (y - t) * m / cnt
 
 
-def backward(theta, specs, x, t, fluid, act=_identity, wround=_identity):
+def backward(theta, specs, x, t, fluid, act=_identity, wround=_identity, ground=None):
     """(loss, gradient of the loss with respect to theta); with ``act`` and
-    ``wround`` the gradient passes through both roundings unchanged."""
+    ``wround`` the gradient passes through both roundings unchanged; with
+    ``ground`` the input gradient of every 3x3 layer is formed from the
+    rounded layer gradient and rounded weights (the bf16 build's input-gradient
+    convolution runs on matrix cores)."""
     y, cache = forward(theta, specs, x, keep=True, act=act, wround=wround)
     P = unpack(theta, specs)
     grads = {}
@@ -217,11 +225,11 @@ def backward(theta, specs, x, t, fluid, act=_identity, wround=_identity):
     def block_back(name_a, name_b, dout):
         ya, zb = cache[name_b]
         dzb = dout * (zb > 0)
-        dya, dW, db = conv_backward(ya, P[name_b][0], dzb)
+        dya, dW, db = conv_backward(ya, P[name_b][0], dzb, ground)
         grads[name_b] = (dW, db)
         inp, za = cache[name_a]
         dza = dya * (za > 0)
-        dinp, dW, db = conv_backward(inp, P[name_a][0], dza)
+        dinp, dW, db = conv_backward(inp, P[name_a][0], dza, ground)
         grads[name_a] = (dW, db)
         return dinp
 

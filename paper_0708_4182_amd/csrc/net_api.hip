@@ -117,7 +117,10 @@ bool layout(const Plan &P, char *base, Buffers &b) {
     }
     size_t wpmax = 0;
     for (int l = 1; l < NLAYERS; ++l)
-        if (P.lk[l] == 3) wpmax = std::max(wpmax, (size_t)9 * P.lcout[l] * lbmnet::pad32(P.lcin[l]));
+        if (P.lk[l] == 3) {
+            wpmax = std::max(wpmax, (size_t)9 * P.lcout[l] * lbmnet::pad32(P.lcin[l]));   // forward
+            wpmax = std::max(wpmax, (size_t)9 * P.lcin[l] * lbmnet::pad32(P.lcout[l]));   // input gradient
+        }
     b.wp = (__bf16 *)take(2 * wpmax);
     b.dz = (float *)take(4 * dzmax);
     b.wt = (float *)take(4 * wtmax);
@@ -321,9 +324,14 @@ lbm_status conv_back(lbm_net *n, int l, const LayerIO &io, int N) {
         NHIP(n, lbmnet::conv3x3_dw<TA>(io.X, b.dz, N, cin, cout, b.partial, chunks, b.grad + P.woff[l], n->s));
     NHIP(n, lbmnet::bias_grad(b.dz, N, cout, H * W, b.partial, b.grad + P.boff[l], n->s));
     if (io.has_gx) {
-        NHIP(n, lbmnet::flip_transpose(b.theta + P.woff[l], b.wt, cin, cout, n->s));
         const View dz = view(b.dz, cout, H, W, cout, 0, 4);
-        NHIP(n, (lbmnet::conv3x3<float, float>(dz, b.wt, nullptr, io.gX, N, cout, cin, false, n->s)));
+        if (sizeof(TA) == 2) {
+            // bf16 build: matrix cores, dz and W rounded to bf16
+            NHIP(n, lbmnet::conv3x3_mfma_dx(dz, b.theta + P.woff[l], io.gX, N, cin, cout, b.wp, n->s));
+        } else {
+            NHIP(n, lbmnet::flip_transpose(b.theta + P.woff[l], b.wt, cin, cout, n->s));
+            NHIP(n, (lbmnet::conv3x3<float, float>(dz, b.wt, nullptr, io.gX, N, cout, cin, false, n->s)));
+        }
     }
     return LBM_OK;
 }

@@ -25,6 +25,10 @@ hipError_t conv3x3(const View &in, const float *w, const float *bias, const View
 int pad32(int c);
 hipError_t conv3x3_mfma(const View &in, const float *w, const float *bias, const View &out, int N, int cin,
                         int cout, bool relu, __bf16 *wp, hipStream_t s);
+// Input gradient of a 3x3 layer on matrix cores (dz and W rounded to bf16);
+// wp holds 9 * cin * pad32(cout) bf16.
+hipError_t conv3x3_mfma_dx(const View &dz, const float *w, const View &dx, int N, int cin, int cout, __bf16 *wp,
+                           hipStream_t s);
 hipError_t flip_transpose(const float *w, float *wt, int cin, int cout, hipStream_t s);
 int dw_chunks(int N, int H, int W, int cin, int cout);
 template <class TI>

@@ -442,6 +442,19 @@ __global__ void k_pack_weights(const float *__restrict__ w, __bf16 *__restrict__
     wp[i] = (__bf16)(ci < cin ? w[((size_t)co * cin + ci) * 9 + t] : 0.f);
 }
 
+// W'[t][ci][co] = W[co][ci][8 - t] packed as bf16 with co padded to cout_pad:
+// the weights of the input-gradient convolution in the layout above.
+__global__ void k_pack_weights_flip(const float *__restrict__ w, __bf16 *__restrict__ wp, int cin, int cout,
+                                    int cout_pad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 9 * cin * cout_pad) return;
+    const int co = i % cout_pad, ci = (i / cout_pad) % cin, t = i / (cout_pad * cin);
+    wp[i] = (__bf16)(co < cout ? w[((size_t)co * cin + ci) * 9 + (8 - t)] : 0.f);
+}
+
+// TI: input type (bf16 activations, or the FP32 layer gradient, rounded to
+// bf16 as it is staged); TO: output type; bias may be NULL.
+template <class TI, class TO>
 __global__ void __launch_bounds__(256) k_conv3x3_mfma(View in, const __bf16 *__restrict__ wp,
                                                       const float *__restrict__ bias, View out, int cin,
                                                       int cout, int cin_pad, int relu) {
@@ -454,7 +467,7 @@ __global__ void __launch_bounds__(256) k_conv3x3_mfma(View in, const __bf16 *__r
     const int n = blockIdx.y / ncob, co0 = (blockIdx.y % ncob) * MCO;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = (lane >> 4) * 8;
-    const __bf16 *__restrict__ xin = static_cast<const __bf16 *>(in.p) + (size_t)n * in.bs;
+    const TI *__restrict__ xin = static_cast<const TI *>(in.p) + (size_t)n * in.bs;
     f32x4 acc[4][4];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -466,7 +479,7 @@ __global__ void __launch_bounds__(256) k_conv3x3_mfma(View in, const __bf16 *__r
             const int y = ty0 - 1 + r;
             const int x = (tx0 - 1 + q + W) % W;
             __bf16 v = (__bf16)0.f;
-            if (ci0 + c < cin && y >= 0 && y < H) v = xin[(size_t)(ci0 + c) * H * W + (size_t)y * W + x];
+            if (ci0 + c < cin && y >= 0 && y < H) v = (__bf16)xin[(size_t)(ci0 + c) * H * W + (size_t)y * W + x];
             xs[(r * (MW + 2) + q) * MPS + c] = v;
         }
         for (int e = tid; e < 9 * MCO * (MCI / 8); e += 256) {
@@ -494,7 +507,7 @@ __global__ void __launch_bounds__(256) k_conv3x3_mfma(View in, const __bf16 *__r
         }
         __syncthreads();
     }
-    __bf16 *__restrict__ yo = static_cast<__bf16 *>(out.p) + (size_t)n * out.bs;
+    TO *__restrict__ yo = static_cast<TO *>(out.p) + (size_t)n * out.bs;
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -505,9 +518,9 @@ __global__ void __launch_bounds__(256) k_conv3x3_mfma(View in, const __bf16 *__r
             for (int r = 0; r < 4; ++r) {
                 const int co = co0 + 16 * m + (lane >> 4) * 4 + r;
                 if (co >= cout) continue;
-                float v = acc[m][q][r] + bias[co];
+                float v = acc[m][q][r] + (bias ? bias[co] : 0.f);
                 if (relu) v = fmaxf(v, 0.f);
-                yo[(size_t)co * H * W + (size_t)y * W + x] = (__bf16)v;
+                yo[(size_t)co * H * W + (size_t)y * W + x] = fromf<TO>(v);
             }
         }
 }
@@ -539,7 +552,21 @@ hipError_t conv3x3_mfma(const View &in, const float *w, const float *bias, const
     if (e != hipSuccess) return e;
     const int tiles = ((in.W + MW - 1) / MW) * ((in.H + MH - 1) / MH);
     const dim3 grid(tiles, N * ((cout + MCO - 1) / MCO));
-    k_conv3x3_mfma<<<grid, 256, 0, s>>>(in, wp, bias, out, cin, cout, cin_pad, relu ? 1 : 0);
+    k_conv3x3_mfma<__bf16, __bf16><<<grid, 256, 0, s>>>(in, wp, bias, out, cin, cout, cin_pad, relu ? 1 : 0);
+    return hipGetLastError();
+}
+
+// Input gradient dX = conv(dz, flipped transposed W) on matrix cores: dz (FP32,
+// cout planes) and the weights rounded to bf16, FP32 accumulation, FP32 out.
+hipError_t conv3x3_mfma_dx(const View &dz, const float *w, const View &dx, int N, int cin, int cout, __bf16 *wp,
+                           hipStream_t s) {
+    const int cout_pad = pad32(cout);
+    k_pack_weights_flip<<<nblk((size_t)9 * cin * cout_pad), 256, 0, s>>>(w, wp, cin, cout, cout_pad);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int tiles = ((dz.W + MW - 1) / MW) * ((dz.H + MH - 1) / MH);
+    const dim3 grid(tiles, N * ((cin + MCO - 1) / MCO));
+    k_conv3x3_mfma<float, float><<<grid, 256, 0, s>>>(dz, wp, nullptr, dx, cout, cin, cout_pad, 0);
     return hipGetLastError();
 }
 

@@ -138,3 +138,30 @@ def test_weight_rounding_applies_to_the_inner_3x3_layers_only():
     _, g2 = cnn.backward(manual, specs, x, t, fluid)
     rel = np.linalg.norm(g1 - g2) / np.linalg.norm(g2)
     assert 0 < rel < 2e-2          # differs only through the 2^-9 weight rounding in dx
+
+
+def test_input_gradient_rounding_hook():
+    """ground rounds the layer gradient and the weights in the input-gradient
+    convolutions only: identity leaves the gradient unchanged; rounding keeps
+    the output layer's and the last 3x3 layer's own gradients (their dz is not
+    rounded) and perturbs the earlier ones by about the bf16 rounding."""
+    specs = cnn.layer_specs(chans=(3, 4, 4, 5))
+    theta = cnn.init_params(specs, seed=8)
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((2, 3, 8, 16))
+    t = rng.standard_normal((2, 3, 8, 16))
+    fluid = rng.random((2, 8, 16)) > 0.2
+    _, g0 = cnn.backward(theta, specs, x, t, fluid)
+    _, gi = cnn.backward(theta, specs, x, t, fluid, ground=lambda a: a)
+    assert np.array_equal(g0, gi)
+    _, g1 = cnn.backward(theta, specs, x, t, fluid, ground=cnn.round_bf16)
+    o = 0
+    for name, ci, co, k in specs:
+        n = co * ci * k * k + co
+        a, b = g0[o:o + n], g1[o:o + n]
+        if name in ("out", "d1b"):
+            assert np.array_equal(a, b), name
+        else:
+            rel = np.linalg.norm(a - b) / np.linalg.norm(a)
+            assert 0 < rel < 2e-2, (name, rel)
+        o += n

@@ -69,7 +69,11 @@ def layer_errors(a, b, specs):
     return out
 
 
+# the bf16 build as the FP64 network defines it (oracle/cnn.py): stored
+# activations, the forward 3x3 weights after the first layer, and the layer
+# gradient and weights of the input-gradient convolutions rounded to bf16
 ROUND = {False: dict(), True: dict(act=CNN.round_bf16, wround=CNN.round_bf16)}
+GROUND = {False: dict(), True: dict(ground=CNN.round_bf16)}
 
 
 @pytest.mark.parametrize("bf16,tol", [(False, 1e-5), (True, 1e-2)])
@@ -100,7 +104,7 @@ def test_gradient_matches_oracle(net, bf16, tol):
     m.set_params(theta)
     loss, g = m.gradient(*to_dev(x, t, fluid))
     args = (theta, specs, x.astype(np.float64), t.astype(np.float64), fluid.astype(bool))
-    ref_loss, ref_g = CNN.backward(*args, **ROUND[bf16])
+    ref_loss, ref_g = CNN.backward(*args, **ROUND[bf16], **GROUND[bf16])
     assert abs(loss - ref_loss) <= tol * ref_loss
     errs = layer_errors(g.astype(np.float64), ref_g, specs)
     worst = max(errs, key=errs.get)
