@@ -34,8 +34,10 @@
  * activations the forward 3x3 convolutions after the first run on matrix
  * cores with the weights rounded to bf16 and FP32 accumulation, and so do the
  * input-gradient convolutions of the backward pass, with the layer gradient
- * and the weights rounded to bf16; everything else (and the FP32 build
- * throughout) multiplies and sums in FP32.  The loss is reduced in FP64;
+ * and the weights rounded to bf16, and the weight gradients of those layers,
+ * with the layer gradient rounded to bf16 against the bf16 activations;
+ * everything else (and the FP32 build throughout) multiplies and sums in
+ * FP32.  The loss is reduced in FP64;
  * master weights, gradients and Adam moments are FP32.
  */
 #ifndef LBM_NET_H

@@ -32,9 +32,12 @@ The production build also multiplies on bf16 matrix cores in the forward 3x3
 convolutions after the first, with the weights rounded to bf16 there; that is
 ``wround=round_bf16``: those forward convolutions use rounded weights, and the
 backward pass uses the unrounded weights (the gradient passes the weight
-rounding unchanged too).  Its input-gradient convolutions (every 3x3 layer
-but the first) also run on bf16 matrix cores, with the layer gradient and the
-weights rounded to bf16 there: ``ground=round_bf16`` in ``backward``.
+rounding unchanged too).  Its backward contractions of the 3x3 layers after
+the first (input gradient and weight gradient) also run on bf16 matrix cores,
+with the layer gradient rounded to bf16 in both and the weights in the input
+gradient:
+``ground=round_bf16`` in ``backward`` (the bias gradient sums the unrounded
+layer gradient).
 """
 from __future__ import annotations
 
@@ -113,9 +116,9 @@ def conv(x, W, b):
 
 
 def conv_backward(x, W, dy, dxr=None):
-    """Gradients (dx, dW, db) of conv for upstream dy; with ``dxr`` the input
-    gradient of a 3x3 layer is formed from dxr(dy) and dxr(W) (the weight
-    gradient keeps dy as it is)."""
+    """Gradients (dx, dW, db) of conv for upstream dy; with ``dxr`` both
+    contractions of a 3x3 layer take dxr(dy), and the input gradient also
+    dxr(W) (the bias gradient keeps dy as it is)."""
     N, ci, H, Wd = x.shape
     co, _, k, _ = W.shape
     db = dy.sum(axis=(0, 2, 3))
@@ -134,7 +137,7 @@ def conv_backward(x, W, dy, dxr=None):
         for c in range(ci):
             for ky in range(3):
                 for kx in range(3):
-                    dW[o, c, ky, kx] = (dy[:, o] * xp[:, c, ky:ky + H, kx:kx + Wd]).sum()
+                    dW[o, c, ky, kx] = (dyx[:, o] * xp[:, c, ky:ky + H, kx:kx + Wd]).sum()
                     dxp[:, c, ky:ky + H, kx:kx + Wd] += Wx[o, c, ky, kx] * dyx[:, o]
     dx = dxp[:, :, 1:-1, 1:-1].copy()
     dx[:, :, :, -1] += dxp[:, :, 1:-1, 0]      # the left pad was column W-1
@@ -211,9 +214,9 @@ def loss_grad(y, t, fluid):
 def backward(theta, specs, x, t, fluid, act=_identity, wround=_identity, ground=None):
     """(loss, gradient of the loss with respect to theta); with ``act`` and
     ``wround`` the gradient passes through both roundings unchanged; with
-    ``ground`` the input gradient of every 3x3 layer is formed from the
-    rounded layer gradient and rounded weights (the bf16 build's input-gradient
-    convolution runs on matrix cores)."""
+    ``ground`` both backward contractions of every 3x3 layer after the first
+    take the rounded layer gradient and the input gradient also the rounded
+    weights (the bf16 build runs them on matrix cores)."""
     y, cache = forward(theta, specs, x, keep=True, act=act, wround=wround)
     P = unpack(theta, specs)
     grads = {}
@@ -229,7 +232,7 @@ def backward(theta, specs, x, t, fluid, act=_identity, wround=_identity, ground=
         grads[name_b] = (dW, db)
         inp, za = cache[name_a]
         dza = dya * (za > 0)
-        dinp, dW, db = conv_backward(inp, P[name_a][0], dza, ground)
+        dinp, dW, db = conv_backward(inp, P[name_a][0], dza, ground if name_a != specs[0][0] else None)
         grads[name_a] = (dW, db)
         return dinp
 

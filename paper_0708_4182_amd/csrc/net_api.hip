@@ -108,7 +108,8 @@ bool layout(const Plan &P, char *base, Buffers &b) {
         dzmax = std::max(dzmax, B * P.lcout[l] * (size_t)lh[l] * lw[l]);
         wtmax = std::max(wtmax, (size_t)P.lcout[l] * P.lcin[l] * 9);
         if (P.lk[l] == 3) {
-            const int ch = lbmnet::dw_chunks(P.B, lh[l], lw[l], P.lcin[l], P.lcout[l]);
+            const int ch = std::max(lbmnet::dw_chunks(P.B, lh[l], lw[l], P.lcin[l], P.lcout[l]),
+                                    lbmnet::dw_chunks_mfma(P.B, lh[l], lw[l], P.lcin[l], P.lcout[l]));
             partmax = std::max(partmax, (size_t)ch * P.lcout[l] * P.lcin[l] * 9);
             partmax = std::max(partmax, (size_t)lbmnet::bias_scratch(P.lcout[l]));
         } else {
@@ -316,10 +317,13 @@ lbm_status conv_back(lbm_net *n, int l, const LayerIO &io, int N) {
     Buffers &b = n->b;
     const int cin = P.lcin[l], cout = P.lcout[l], H = io.Y.H, W = io.Y.W;
     NHIP(n, lbmnet::relu_mask<TA>(io.gY, io.Y, N, cout, b.dz, n->s));
-    const int chunks = lbmnet::dw_chunks(N, H, W, cin, cout);
+    const bool mfma = sizeof(TA) == 2 && l != E1A;   // bf16 build, bf16 input activations
+    const int chunks = mfma ? lbmnet::dw_chunks_mfma(N, H, W, cin, cout) : lbmnet::dw_chunks(N, H, W, cin, cout);
     if ((size_t)chunks * cout * cin * 9 > b.partial_floats) return nfail(n, LBM_EINVAL, "dW scratch too small");
     if (l == E1A)
         NHIP(n, lbmnet::conv3x3_dw<float>(io.X, b.dz, N, cin, cout, b.partial, chunks, b.grad + P.woff[l], n->s));
+    else if (mfma)
+        NHIP(n, lbmnet::conv3x3_dw_mfma(io.X, b.dz, N, cin, cout, b.partial, chunks, b.grad + P.woff[l], n->s));
     else
         NHIP(n, lbmnet::conv3x3_dw<TA>(io.X, b.dz, N, cin, cout, b.partial, chunks, b.grad + P.woff[l], n->s));
     NHIP(n, lbmnet::bias_grad(b.dz, N, cout, H * W, b.partial, b.grad + P.boff[l], n->s));

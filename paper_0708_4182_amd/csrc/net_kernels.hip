@@ -525,6 +525,134 @@ __global__ void __launch_bounds__(256) k_conv3x3_mfma(View in, const __bf16 *__r
         }
 }
 
+// Weight gradient on matrix cores (bf16 build, 3x3 layers after the first):
+// for each tap (dy, dx), dW[co][ci] = sum over pixels p of round_bf16(dz[co](p))
+// x[ci](p + (dy - 1, dx - 1)), a product with K = pixels.  A workgroup owns 32
+// output x 32 input channels (a 2 x 2 grid of waves, 16 x 16 each, all nine
+// taps in 36 accumulation registers) and walks a chunk of 4 x 32 pixel tiles.
+// The lane's eight K values are eight consecutive pixels of one row, so the
+// operands of the three column shifts come from one 16-byte LDS read of the
+// staged input row plus one neighbouring dword each; each staged row r then
+// serves the dz rows r - dy of the three row shifts.  Partials
+// [chunk][co][ci][tap] are summed in chunk order by k_sum_partials.
+constexpr int DM_CO = 32, DM_CI = 32, DM_TR = 4, DM_TW = 32, DM_PX = DM_TR * DM_TW;
+constexpr int DM_DZS = DM_PX + 8;                 // dz channel stride (bf16)
+constexpr int DM_XR = DM_TW + 16;                 // staged x row: 8 | 32 pixels | 8, halo at 7 and 40
+constexpr int DM_XSC = (DM_TR + 2) * DM_XR + 8;   // x channel stride (bf16)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+// x column tx0 + c (c in [-1, 32]) as the staged tile holds it: periodic at
+// both ends of the row; columns more than one past the last one feed no
+// output pixel and hold zero (-1 returned).
+__device__ __forceinline__ int dw_col(int tx0, int c, int W) {
+    const int col = tx0 + c;
+    if (col < 0) return W - 1;
+    if (col == W) return 0;
+    return col < W ? col : -1;
+}
+
+__global__ void __launch_bounds__(256) k_conv3x3_dw_mfma(View x, const float *__restrict__ dz, int N, int cin,
+                                                         int cout, int tiles_per_chunk, int vec,
+                                                         float *__restrict__ partial) {
+    __shared__ __attribute__((aligned(16))) __bf16 dzs[DM_CO * DM_DZS];
+    __shared__ __attribute__((aligned(16))) __bf16 xs[DM_CI * DM_XSC];
+    const int H = x.H, W = x.W;
+    const int tiles_x = (W + DM_TW - 1) / DM_TW, tiles_y = (H + DM_TR - 1) / DM_TR;
+    const int ntiles = N * tiles_x * tiles_y;
+    const int chunk = blockIdx.x, co0 = blockIdx.y * DM_CO, ci0 = blockIdx.z * DM_CI;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wco = (wave & 1) * 16, wci = (wave >> 1) * 16;
+    const int lr = lane & 15, lk = (lane >> 4) * 8;
+    f32x4 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const __bf16 zero = (__bf16)0.f;
+    const int t_begin = chunk * tiles_per_chunk, t_end = min(ntiles, t_begin + tiles_per_chunk);
+    for (int tile = t_begin; tile < t_end; ++tile) {
+        const int n = tile / (tiles_x * tiles_y), rem = tile % (tiles_x * tiles_y);
+        const int ty0 = (rem / tiles_x) * DM_TR, tx0 = (rem % tiles_x) * DM_TW;
+        const __bf16 *__restrict__ xin = static_cast<const __bf16 *>(x.p) + (size_t)n * x.bs;
+        const float *__restrict__ dzn = dz + (size_t)n * cout * H * W;
+        if (vec) {
+            // whole 32-pixel rows, 16-byte aligned: 4 dz values or 8 x values per load
+            for (int e = tid; e < DM_CO * DM_TR * (DM_TW / 4); e += 256) {
+                const int q = (e % (DM_TW / 4)) * 4, j = (e / (DM_TW / 4)) % DM_TR, o = e / (DM_TR * DM_TW / 4);
+                const int y = ty0 + j;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (co0 + o < cout && y < H)
+                    v = *reinterpret_cast<const float4 *>(&dzn[(size_t)(co0 + o) * H * W + (size_t)y * W + tx0 + q]);
+                *reinterpret_cast<bf16x4 *>(&dzs[o * DM_DZS + j * DM_TW + q]) =
+                    bf16x4{(__bf16)v.x, (__bf16)v.y, (__bf16)v.z, (__bf16)v.w};
+            }
+            for (int e = tid; e < DM_CI * (DM_TR + 2) * (DM_TW / 8); e += 256) {
+                const int q = (e % (DM_TW / 8)) * 8, r = (e / (DM_TW / 8)) % (DM_TR + 2), c = e / ((DM_TR + 2) * DM_TW / 8);
+                const int y = ty0 - 1 + r;
+                bf16x8 v = bf16x8{zero, zero, zero, zero, zero, zero, zero, zero};
+                if (ci0 + c < cin && y >= 0 && y < H)
+                    v = *reinterpret_cast<const bf16x8 *>(&xin[(size_t)(ci0 + c) * H * W + (size_t)y * W + tx0 + q]);
+                *reinterpret_cast<bf16x8 *>(&xs[c * DM_XSC + r * DM_XR + 8 + q]) = v;
+            }
+        } else {
+            for (int e = tid; e < DM_CO * DM_PX; e += 256) {
+                const int o = e / DM_PX, p = e % DM_PX;
+                const int y = ty0 + p / DM_TW, xx = tx0 + p % DM_TW;
+                float v = 0.f;
+                if (co0 + o < cout && y < H && xx < W) v = dzn[(size_t)(co0 + o) * H * W + (size_t)y * W + xx];
+                dzs[o * DM_DZS + p] = (__bf16)v;
+            }
+            for (int e = tid; e < DM_CI * (DM_TR + 2) * DM_TW; e += 256) {
+                const int q = e % DM_TW, r = (e / DM_TW) % (DM_TR + 2), c = e / ((DM_TR + 2) * DM_TW);
+                const int y = ty0 - 1 + r, col = dw_col(tx0, q, W);
+                __bf16 v = zero;
+                if (ci0 + c < cin && y >= 0 && y < H && col >= 0) v = xin[(size_t)(ci0 + c) * H * W + (size_t)y * W + col];
+                xs[c * DM_XSC + r * DM_XR + 8 + q] = v;
+            }
+        }
+        // halo columns -1 and 32 of every staged row
+        for (int e = tid; e < DM_CI * (DM_TR + 2) * 2; e += 256) {
+            const int side = e & 1, r = (e >> 1) % (DM_TR + 2), c = (e >> 1) / (DM_TR + 2);
+            const int y = ty0 - 1 + r, col = dw_col(tx0, side ? DM_TW : -1, W);
+            __bf16 v = zero;
+            if (ci0 + c < cin && y >= 0 && y < H && col >= 0) v = xin[(size_t)(ci0 + c) * H * W + (size_t)y * W + col];
+            xs[c * DM_XSC + r * DM_XR + (side ? 8 + DM_TW : 7)] = v;
+        }
+        __syncthreads();
+        bf16x8 a[DM_TR];
+#pragma unroll
+        for (int j = 0; j < DM_TR; ++j)
+            a[j] = *reinterpret_cast<const bf16x8 *>(&dzs[(wco + lr) * DM_DZS + j * DM_TW + lk]);
+#pragma unroll
+        for (int r = 0; r < DM_TR + 2; ++r) {
+            const __bf16 *row = &xs[(wci + lr) * DM_XSC + r * DM_XR + 8 + lk];
+            const u32x4 c = __builtin_bit_cast(u32x4, *reinterpret_cast<const bf16x8 *>(row));
+            const uint32_t lw = *reinterpret_cast<const uint32_t *>(row - 2);   // pixels lk - 2, lk - 1
+            const uint32_t rw = *reinterpret_cast<const uint32_t *>(row + 8);   // pixels lk + 8, lk + 9
+            const uint32_t m1 = (c.x >> 16) | (c.y << 16), m2 = (c.y >> 16) | (c.z << 16),
+                           m3 = (c.z >> 16) | (c.w << 16);
+            const bf16x8 b[3] = {__builtin_bit_cast(bf16x8, u32x4{(lw >> 16) | (c.x << 16), m1, m2, m3}),
+                                 __builtin_bit_cast(bf16x8, c),
+                                 __builtin_bit_cast(bf16x8, u32x4{m1, m2, m3, (c.w >> 16) | (rw << 16)})};
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy) {
+                const int j = r - dy;
+                if (j < 0 || j >= DM_TR) continue;
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+                    acc[dy * 3 + dx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j], b[dx], acc[dy * 3 + dx], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int co = co0 + wco + (lane >> 4) * 4 + r, ci = ci0 + wci + lr;
+            if (co < cout && ci < cin) partial[(((size_t)chunk * cout + co) * cin + ci) * 9 + t] = acc[t][r];
+        }
+}
+
 inline unsigned nblk(size_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -598,6 +726,30 @@ hipError_t conv3x3_dw(const View &x, const float *dz, int N, int cin, int cout, 
 }
 template hipError_t conv3x3_dw<float>(const View &, const float *, int, int, int, float *, int, float *, hipStream_t);
 template hipError_t conv3x3_dw<__bf16>(const View &, const float *, int, int, int, float *, int, float *, hipStream_t);
+
+int dw_chunks_mfma(int N, int H, int W, int cin, int cout) {
+    const int ntiles = N * ((W + DM_TW - 1) / DM_TW) * ((H + DM_TR - 1) / DM_TR);
+    const int blocks = ((cout + DM_CO - 1) / DM_CO) * ((cin + DM_CI - 1) / DM_CI);
+    // about 1024 workgroups (four fit a compute unit), at least 2 tiles per chunk
+    return std::max(1, std::min(ntiles / 2, (1024 + blocks - 1) / blocks));
+}
+
+hipError_t conv3x3_dw_mfma(const View &x, const float *dz, int N, int cin, int cout, float *partial, int chunks,
+                           float *dw, hipStream_t s) {
+    const int ntiles = N * ((x.W + DM_TW - 1) / DM_TW) * ((x.H + DM_TR - 1) / DM_TR);
+    const int per = (ntiles + chunks - 1) / chunks;
+    // vector staging: whole tile rows and 16-byte aligned rows of x and dz
+    const size_t hw = (size_t)x.H * x.W;
+    const int vec = x.W % DM_TW == 0 && hw % 8 == 0 && x.bs % 8 == 0 && (uintptr_t)x.p % 16 == 0 &&
+                    (uintptr_t)dz % 16 == 0;
+    const dim3 grid(chunks, (cout + DM_CO - 1) / DM_CO, (cin + DM_CI - 1) / DM_CI);
+    k_conv3x3_dw_mfma<<<grid, 256, 0, s>>>(x, dz, N, cin, cout, per, vec, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int n = cout * cin * 9;
+    k_sum_partials<<<nblk(n), 256, 0, s>>>(partial, chunks, n, dw);
+    return hipGetLastError();
+}
 
 int bias_scratch(int C) { return C * BIAS_PARTS; }
 

@@ -140,11 +140,14 @@ def test_weight_rounding_applies_to_the_inner_3x3_layers_only():
     assert 0 < rel < 2e-2          # differs only through the 2^-9 weight rounding in dx
 
 
-def test_input_gradient_rounding_hook():
-    """ground rounds the layer gradient and the weights in the input-gradient
-    convolutions only: identity leaves the gradient unchanged; rounding keeps
-    the output layer's and the last 3x3 layer's own gradients (their dz is not
-    rounded) and perturbs the earlier ones by about the bf16 rounding."""
+def test_backward_rounding_hook():
+    """ground rounds the layer gradient in the 3x3 layers' weight- and
+    input-gradient contractions and the weights in the input gradient:
+    identity leaves the gradient unchanged; rounding keeps the output layer's
+    gradients and every bias gradient of the last 3x3 layer (their inputs are
+    not rounded), and moves the other gradients by about the bf16 rounding;
+    the last 3x3 layer's weight gradient equals the one formed by hand from
+    the rounded layer gradient."""
     specs = cnn.layer_specs(chans=(3, 4, 4, 5))
     theta = cnn.init_params(specs, seed=8)
     rng = np.random.default_rng(9)
@@ -157,11 +160,23 @@ def test_input_gradient_rounding_hook():
     _, g1 = cnn.backward(theta, specs, x, t, fluid, ground=cnn.round_bf16)
     o = 0
     for name, ci, co, k in specs:
-        n = co * ci * k * k + co
-        a, b = g0[o:o + n], g1[o:o + n]
-        if name in ("out", "d1b"):
-            assert np.array_equal(a, b), name
+        nw = co * ci * k * k
+        aw, bw = g0[o:o + nw], g1[o:o + nw]
+        ab, bb = g0[o + nw:o + nw + co], g1[o + nw:o + nw + co]
+        if name == "out":
+            assert np.array_equal(aw, bw) and np.array_equal(ab, bb)
         else:
-            rel = np.linalg.norm(a - b) / np.linalg.norm(a)
+            rel = np.linalg.norm(aw - bw) / np.linalg.norm(aw)
             assert 0 < rel < 2e-2, (name, rel)
-        o += n
+        if name == "d1b":
+            assert np.array_equal(ab, bb)
+        o += nw + co
+    # d1b by hand: its layer gradient is (dL/d output of d1b) * relu'(z)
+    y, cache = cnn.forward(theta, specs, x, keep=True)
+    P = cnn.unpack(theta, specs)
+    dd1, _, _ = cnn.conv_backward(cache["out"][0], P["out"][0], cnn.loss_grad(y, t, fluid))
+    ya, zb = cache["d1b"]
+    _, dW, _ = cnn.conv_backward(ya, P["d1b"][0], cnn.round_bf16(dd1 * (zb > 0)))
+    names = [nm for nm, *_ in specs]
+    o = sum(co_ * ci_ * k_ * k_ + co_ for _, ci_, co_, k_ in specs[:names.index("d1b")])
+    np.testing.assert_allclose(g1[o:o + dW.size], dW.ravel(), rtol=0, atol=1e-15)
