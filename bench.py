@@ -27,8 +27,9 @@ if ROOT not in sys.path:
 METRIC = "MLUPS + % HBM roofline; steady-flux lattice updates, warm-start vs plain"
 HBM_PEAK_GBS = 8000.0
 STORAGES = {"f32": 0, "f16": 1, "bf16": 2}
-# extra lines: name -> (storage, collision); collision 1 is the TRT operator with Guo forcing
-VARIANTS = {"f16": (1, 0), "bf16": (2, 0), "f32_trt": (0, 1)}
+# extra lines: name -> (storage, collision, rounding); collision 1 is the TRT operator with Guo
+# forcing, rounding 1 the stochastic rounding of 16-bit stores
+VARIANTS = {"f16": (1, 0, 0), "bf16": (2, 0, 0), "f32_trt": (0, 1, 0), "f16_sr": (1, 0, 1), "bf16_sr": (2, 0, 1)}
 ELEM_BYTES = {0: 4, 1: 2, 2: 2}
 KERNEL_SRC = os.path.join(ROOT, "paper_0708_4182_amd", "csrc", "lbm_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
@@ -61,13 +62,13 @@ def measured_traffic(storage_name: str, tile):
     return None
 
 
-def time_storage(case, storage, steps, warmup, tile, collision=0):
+def time_storage(case, storage, steps, warmup, tile, collision=0, rounding=0):
     import torch
     from paper_0708_4182_amd import lbm
 
     from paper_0708_4182_amd import autotune
 
-    c = case.params.replace(storage=storage, collision=collision)
+    c = case.params.replace(storage=storage, collision=collision, rounding=rounding)
     sim = lbm.Simulation(c, case.solid, case.rho, case.ux, case.uy)
     if tile:
         kernel, bx, rows = tile
@@ -139,9 +140,10 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--storage", default="f32", choices=sorted(STORAGES))
-    ap.add_argument("--variants", default="f16,bf16,f32_trt",
+    ap.add_argument("--variants", default="f16,bf16,f32_trt,f16_sr,bf16_sr",
                     help="other lines timed after the main one: f16, bf16 (storage), f32_trt (FP32 storage "
-                         "with the TRT collision and Guo forcing); '' for none")
+                         "with the TRT collision and Guo forcing), f16_sr, bf16_sr (16-bit storage with "
+                         "stochastic rounding); '' for none")
     ap.add_argument("--nx", type=int, default=8192)
     ap.add_argument("--ny", type=int, default=2048)
     ap.add_argument("--tile", default="auto",
@@ -202,11 +204,11 @@ def main():
     main_line = line_for(args.storage, main_r)
     variants = {}
     for v in [v for v in args.variants.split(",") if v and v != args.storage]:
-        st, coll = VARIANTS[v] if v in VARIANTS else (STORAGES[v], 0)
+        st, coll, rnd = VARIANTS[v] if v in VARIANTS else (STORAGES[v], 0, 0)
         vt = tile
-        if coll and tile and tile[0] not in ("fused", "fused8"):
-            vt = ("fused", tile[1], tile[2])     # the TRT operator runs in the fused kernels only
-        r = time_storage(case, st, args.steps, args.warmup, vt, collision=coll)
+        if (coll or rnd) and tile and tile[0] not in ("fused", "fused8"):
+            vt = ("fused", tile[1], tile[2])     # TRT and stochastic rounding run in the fused kernels only
+        r = time_storage(case, st, args.steps, args.warmup, vt, collision=coll, rounding=rnd)
         print(f"# {v}: tile {r['tile']} {r['step_ms']*1e3:.1f} us/step", file=sys.stderr, flush=True)
         variants[v] = line_for(v, r)
 

@@ -19,6 +19,8 @@
  * time collision with Guo's forcing term in place of eq. (10) and BGK
  * (lbm_params.collision), and the electric force along the local face normal
  * of a rough wall instead of towards the electrode (lbm_params.elec_normal).
+ * 16-bit population storage and its stochastic rounding (lbm_params.storage,
+ * lbm_params.rounding) are storage formats, not part of the model.
  *
  * Conventions for every entry point:
  *   - the return value is an lbm_status: 0 on success, < 0 on error; nothing
@@ -95,7 +97,28 @@ typedef struct {
                               (sgn v_x, sgn v_y) of v = sum of (s - x) over the solid
                               nodes s at distance d, normalised (diagonals by
                               1/sqrt 2); the electrode direction where v = 0         */
+    int32_t rounding;      /* rounding of the stored 16-bit deviations, see below:
+                              LBM_ROUND_NEAREST (default) or LBM_ROUND_STOCHASTIC
+                              (LBM_F16 and LBM_BF16 only; LBM_EINVAL with LBM_F32)    */
 } lbm_params;
+
+/* Rounding of 16-bit storage (lbm_params.rounding).  LBM_ROUND_NEAREST rounds
+ * every stored deviation to nearest even.  Where the flow is nearly steady a
+ * node's post-collision values repeat from step to step, so do their rounding
+ * errors, and the mass they add or remove grows linearly with time (a droplet
+ * at rest can gain 10% in 20,000 steps).  LBM_ROUND_STOCHASTIC rounds each
+ * value up or down with probabilities that make the expected stored value
+ * exact: the magnitude rounds up when 16 random bits added below the result's
+ * last place carry into it (for FP16 the top 13 of them on normal values).
+ * The bits are a counter-based hash (lowbias32) of the node's offset in its
+ * population plane and the number of steps taken, so runs are reproducible:
+ * the same calls give bitwise the same results, hipGraph replays equal eager
+ * steps, and a channel of a batch equals the same lattice run alone.  Mass
+ * errors then grow like the square root of the step count.  Runs in
+ * LBM_KERNEL_FUSED and LBM_KERNEL_FUSED8 only; lbm_load_state restarts the
+ * count at the state's step number. */
+#define LBM_ROUND_NEAREST 0
+#define LBM_ROUND_STOCHASTIC 1
 
 /* Collision operators (lbm_params.collision).  LBM_COLLIDE_TRT_GUO: the
  * equilibrium of eq. (3) takes u = (sum f e + F/2) / rho; the symmetric and
@@ -187,8 +210,9 @@ lbm_status lbm_set_tile(lbm_sim *sim, int32_t block_x, int32_t rows_per_block);
  * LBM_KERNEL_FUSED8: the fused kernel compiled for 8 resident waves per SIMD
  * (64 registers; a few loop invariants live in scratch memory) instead of 7.
  * All give bitwise the same results.  Default LBM_KERNEL_FUSED.  Takes effect
- * at the next lbm_step.  With LBM_COLLIDE_TRT_GUO only LBM_KERNEL_FUSED and
- * LBM_KERNEL_FUSED8 are accepted (LBM_EINVAL otherwise) and tuned. */
+ * at the next lbm_step.  With LBM_COLLIDE_TRT_GUO or LBM_ROUND_STOCHASTIC
+ * only LBM_KERNEL_FUSED and LBM_KERNEL_FUSED8 are accepted (LBM_EINVAL
+ * otherwise) and tuned. */
 #define LBM_KERNEL_FUSED 0
 #define LBM_KERNEL_SPLIT 1
 #define LBM_KERNEL_WIDE2 2
@@ -235,8 +259,9 @@ lbm_status lbm_load_state(lbm_sim *sim, const void *host, size_t bytes);
  * strength, channel width and roughness, Figs. 3, 5-8).  Every time step is
  * one persistent kernel launch whose workgroups take tiles of all channels
  * from a queue; K steps can be captured as one hipGraph and replayed.
- * Conventions as above; all channels share one storage format; all active
- * channels advance together.  A retired channel keeps its last state and is
+ * Conventions as above; all channels share one storage format, collision
+ * operator and rounding (LBM_EINVAL otherwise); all active channels advance
+ * together.  A retired channel keeps its last state and is
  * no longer stepped.
  * ------------------------------------------------------------------------ */
 typedef struct lbm_batch lbm_batch;

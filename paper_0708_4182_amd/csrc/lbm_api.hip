@@ -31,6 +31,8 @@ struct lbm_sim {
     uint16_t *flags = nullptr;
     double *partials = nullptr;
     double *result = nullptr;
+    uint32_t *rng = nullptr;   // two-slot step counter of stochastic rounding
+    uint32_t rng_host[2] = {0u, 0u};
     int cur = 0;
     int64_t steps = 0;
     int block_x = 256;
@@ -59,7 +61,7 @@ size_t elem_size(int storage) { return storage == LBM_F32 ? 4 : 2; }
 
 struct Layout {
     Grid g;
-    size_t buf_bytes, flags_off, flags_bytes, part_off, res_off, total;
+    size_t buf_bytes, flags_off, flags_bytes, part_off, res_off, rng_off, total;
     size_t buf_off[2];
 };
 
@@ -86,6 +88,10 @@ std::string check_params(const lbm_params *p) {
         return "collision must be LBM_COLLIDE_BGK or LBM_COLLIDE_TRT_GUO";
     if (p->collision == LBM_COLLIDE_TRT_GUO && !(p->trt_magic > 0.0)) return "trt_magic must be > 0";
     if (p->elec_normal != 0 && p->elec_normal != 1) return "elec_normal must be 0 or 1";
+    if (p->rounding != LBM_ROUND_NEAREST && p->rounding != LBM_ROUND_STOCHASTIC)
+        return "rounding must be LBM_ROUND_NEAREST or LBM_ROUND_STOCHASTIC";
+    if (p->rounding == LBM_ROUND_STOCHASTIC && p->storage == LBM_F32)
+        return "LBM_ROUND_STOCHASTIC needs LBM_F16 or LBM_BF16 storage";
     return "";
 }
 
@@ -107,7 +113,8 @@ bool make_layout(const lbm_params *p, Layout &L) {
     L.flags_bytes = align_up(plane * sizeof(uint16_t), kAlign);
     L.part_off = L.flags_off + L.flags_bytes;
     L.res_off = L.part_off + align_up(4 * sizeof(double) * (size_t)lbm::max_reduce_blocks(), kAlign);
-    L.total = L.res_off + kAlign;
+    L.rng_off = L.res_off + kAlign;
+    L.total = L.rng_off + kAlign;
     return true;
 }
 
@@ -139,6 +146,7 @@ Model make_model(const lbm_params *p) {
     m.omega_m = (float)om_m;
     m.src_p = (float)(1.0 - 0.5 / p->tau);
     m.src_m = (float)(1.0 - 0.5 * om_m);
+    m.sround = p->rounding == LBM_ROUND_STOCHASTIC ? 1 : 0;
     return m;
 }
 
@@ -328,6 +336,7 @@ lbm_status lbm_init(lbm_sim **out, const lbm_params *p, const uint8_t *solid, co
     s->flags = (uint16_t *)(ws + L.flags_off);
     s->partials = (double *)(ws + L.part_off);
     s->result = (double *)(ws + L.res_off);
+    s->rng = (uint32_t *)(ws + L.rng_off);
 
     // flags, padded to the row pitch
     std::vector<uint16_t> fl;
@@ -365,6 +374,7 @@ lbm_status lbm_init(lbm_sim **out, const lbm_params *p, const uint8_t *solid, co
     INIT_TRY(lbm::launch_init(p->storage, s->buf[0], s->flags, s->g, s->m.rho_off, dstage, dstage + n,
                               dstage + 2 * n, p->nx, s->stream));
     INIT_TRY(lbm::launch_fill(s->buf[1], s->buf_bytes, s->stream));
+    INIT_TRY(hipMemcpyAsync(s->rng, s->rng_host, sizeof s->rng_host, hipMemcpyHostToDevice, s->stream));
     INIT_TRY(hipStreamSynchronize(s->stream));
 #undef INIT_TRY
     s->cur = 0;
@@ -409,8 +419,8 @@ lbm::StepArgs step_args(lbm_sim *s) {
             case LBM_KERNEL_SPLIT: per_cu = lbm::split_blocks_per_cu(s->p.storage, s->block_x); break;
             case LBM_KERNEL_WIDE2: per_cu = lbm::wide_blocks_per_cu(s->p.storage, s->block_x, 2); break;
             case LBM_KERNEL_WIDE4: per_cu = lbm::wide_blocks_per_cu(s->p.storage, s->block_x, 4); break;
-            case LBM_KERNEL_FUSED8: per_cu = lbm::step8_blocks_per_cu(s->p.storage, s->block_x, s->m.trt != 0); break;
-            default: per_cu = lbm::step_blocks_per_cu(s->p.storage, s->block_x, s->m.trt != 0); break;
+            case LBM_KERNEL_FUSED8: per_cu = lbm::step8_blocks_per_cu(s->p.storage, s->block_x, s->m.trt != 0, s->m.sround != 0); break;
+            default: per_cu = lbm::step_blocks_per_cu(s->p.storage, s->block_x, s->m.trt != 0, s->m.sround != 0); break;
             }
             const int cap = s->cus * per_cu;
             chunks = std::max(1, cap / strips);
@@ -427,6 +437,8 @@ lbm::StepArgs step_args(lbm_sim *s) {
     a.tiles_per_xcd = (a.ntiles + 7) / 8;
     a.src = s->buf[s->cur];
     a.dst = s->buf[s->cur ^ 1];
+    a.rng = s->rng;
+    a.par = s->cur;
     return a;
 }
 
@@ -466,6 +478,7 @@ lbm_status capture_graph(lbm_sim *s, int parity) {
         const int from = parity ^ (k & 1);
         a.src = s->buf[from];
         a.dst = s->buf[from ^ 1];
+        a.par = from;
         e = launch_on(s, a, s->cap);
     }
     hipGraph_t g = nullptr;
@@ -504,6 +517,7 @@ lbm_status lbm_step(lbm_sim *s, int64_t nsteps) {
     for (int64_t k = 0; k < left; ++k) {
         a.src = s->buf[s->cur];
         a.dst = s->buf[s->cur ^ 1];
+        a.par = s->cur;
         HIP_TRY(s, launch(s, a));
         s->cur ^= 1;
         ++s->steps;
@@ -601,6 +615,8 @@ lbm_status lbm_set_kernel(lbm_sim *s, int32_t kernel) {
         return fail(s, LBM_EINVAL, "kernel must be one of LBM_KERNEL_FUSED, _SPLIT, _WIDE2, _WIDE4, _FUSED8");
     if (s->m.trt && kernel != LBM_KERNEL_FUSED && kernel != LBM_KERNEL_FUSED8)
         return fail(s, LBM_EINVAL, "the TRT operator runs in LBM_KERNEL_FUSED and LBM_KERNEL_FUSED8 only");
+    if (s->m.sround && kernel != LBM_KERNEL_FUSED && kernel != LBM_KERNEL_FUSED8)
+        return fail(s, LBM_EINVAL, "stochastic rounding runs in LBM_KERNEL_FUSED and LBM_KERNEL_FUSED8 only");
     s->kernel = kernel;
     if (kernel == LBM_KERNEL_SPLIT && s->block_x != 128 && s->block_x != 256) s->block_x = 128;
     if ((kernel == LBM_KERNEL_WIDE2 || kernel == LBM_KERNEL_WIDE4) && s->block_x > 256) s->block_x = 256;
@@ -652,7 +668,8 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *row
     lbm_status res = LBM_OK;
     for (const Cand &cand : kCand) {
         const int bx = cand.bx;
-        if (s->m.trt && cand.kernel != LBM_KERNEL_FUSED && cand.kernel != LBM_KERNEL_FUSED8) continue;
+        if ((s->m.trt || s->m.sround) && cand.kernel != LBM_KERNEL_FUSED && cand.kernel != LBM_KERNEL_FUSED8)
+            continue;
         for (int r : kRows) {
             if (r > 0 && r >= s->p.ny) continue;
             s->kernel = cand.kernel;
@@ -731,6 +748,10 @@ lbm_status lbm_load_state(lbm_sim *s, const void *host, size_t bytes) {
     DeviceGuard dg(s->device);
     HIP_TRY(s, hipMemcpyAsync(s->buf[s->cur], (const char *)host + sizeof hdr, lbm_state_bytes(s) - sizeof hdr,
                               hipMemcpyHostToDevice, s->stream));
+    // the stochastic-rounding count of the next step is the state's step number
+    s->rng_host[s->cur] = (uint32_t)hdr[1];
+    HIP_TRY(s, hipMemcpyAsync(s->rng + s->cur, s->rng_host + s->cur, sizeof(uint32_t), hipMemcpyHostToDevice,
+                              s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     s->steps = (int64_t)hdr[1];
     return LBM_OK;

@@ -40,7 +40,7 @@ struct BatchLayout {
     std::vector<Grid> g;
     std::vector<size_t> buf0, buf1, flags;
     size_t buf_bytes_max = 0;
-    size_t descs, tiles, counters, ids, cur, out, total;
+    size_t descs, tiles, counters, ids, cur, out, rng, total;
     size_t max_tiles;
 };
 
@@ -64,6 +64,10 @@ bool make_batch_layout(int n, const lbm_params *p, BatchLayout &L, std::string &
         }
         if (p[i].collision != p[0].collision) {
             why = "all channels must use the same collision operator";
+            return false;
+        }
+        if (p[i].rounding != p[0].rounding) {
+            why = "all channels must use the same rounding";
             return false;
         }
         if (p[i].storage != p[0].storage) {
@@ -107,6 +111,8 @@ bool make_batch_layout(int n, const lbm_params *p, BatchLayout &L, std::string &
     off += align_up(4 * (size_t)n, kAlign);
     L.out = off;
     off += align_up(32 * (size_t)n, kAlign);
+    L.rng = off;
+    off += kAlign;
     L.total = off;
     return true;
 }
@@ -116,6 +122,9 @@ struct lbm_batch {
     int n = 0;
     int storage = 0;
     bool trt = false;           // collision operator of every channel
+    bool sround = false;        // stochastic rounding of every channel
+    uint32_t *d_rng = nullptr;  // two-slot step counter of stochastic rounding
+    uint32_t rng_host[2] = {0u, 0u};
     std::vector<lbm_params> p;
     std::vector<Grid> g;
     std::vector<ChannelDesc> desc;     // host mirror of the device table
@@ -225,7 +234,7 @@ lbm_status upload_tiles(lbm_batch *b) {
 // Grid of a step launch: the persistent grid, or 0 for one workgroup per tile.
 int persistent_grid(lbm_batch *b) {
     if (!b->persistent) return 0;
-    const int per_cu = lbm::batch_blocks_per_cu(b->storage, b->block_x, b->trt);
+    const int per_cu = lbm::batch_blocks_per_cu(b->storage, b->block_x, b->trt, b->sround);
     return std::max(1, std::min(b->ntiles, b->cus * per_cu));
 }
 
@@ -238,6 +247,8 @@ hipError_t enqueue_step(lbm_batch *b, hipStream_t s, int slot, int parity, int g
     a.slot = slot;
     a.parity = parity;
     a.trt = b->trt ? 1 : 0;
+    a.sround = b->sround ? 1 : 0;
+    a.rng = b->d_rng;
     return lbm::launch_batch_step(b->storage, a, b->block_x, grid, s);
 }
 
@@ -317,6 +328,7 @@ lbm_status lbm_batch_init(lbm_batch **out, int32_t n, const lbm_params *p, const
     b->n = n;
     b->storage = p[0].storage;
     b->trt = p[0].collision == LBM_COLLIDE_TRT_GUO;
+    b->sround = p[0].rounding == LBM_ROUND_STOCHASTIC;
     b->p.assign(p, p + n);
     b->g = L.g;
     b->stream = (hipStream_t)stream;
@@ -343,6 +355,11 @@ lbm_status lbm_batch_init(lbm_batch **out, int32_t n, const lbm_params *p, const
     b->d_ids = (int32_t *)(ws + L.ids);
     b->d_cur = (int32_t *)(ws + L.cur);
     b->d_out = (double *)(ws + L.out);
+    b->d_rng = (uint32_t *)(ws + L.rng);
+    if (hipMemcpyAsync(b->d_rng, b->rng_host, sizeof b->rng_host, hipMemcpyHostToDevice, b->stream) != hipSuccess) {
+        bfail(b, LBM_EDEVICE, "cannot set the rounding step counter");
+        return cleanup(LBM_EDEVICE);
+    }
     b->desc.resize(n);
     b->active.assign(n, 1);
     b->cur.assign(n, 0);

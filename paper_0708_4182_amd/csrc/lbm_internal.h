@@ -32,6 +32,7 @@ struct Model {
     int32_t trt;               // 0: BGK with the velocity shift; 1: TRT with Guo forcing
     float omega_m;             // TRT: relaxation rate of the antisymmetric part
     float src_p, src_m;        // TRT: source weights 1 - omega/2 and 1 - omega_m/2
+    int32_t sround;            // 1: stochastic rounding of 16-bit stores (0: nearest)
 };
 
 struct StepArgs {
@@ -47,6 +48,10 @@ struct StepArgs {
     int32_t chunks;
     int32_t ntiles;
     int32_t tiles_per_xcd;
+    // Stochastic rounding: two-slot step counter (slot par is this step's,
+    // the kernel writes the next count to the other slot).
+    uint32_t *rng;
+    int32_t par;
 };
 
 // One channel of a batch: its lattice, model and device arrays.
@@ -70,15 +75,17 @@ struct BatchStepArgs {
     int32_t slot;
     int32_t parity;            // index of the source buffer of every active channel
     int32_t trt;               // collision operator of every channel (Model::trt)
+    int32_t sround;            // rounding of every channel (Model::sround)
+    uint32_t *rng;             // two-slot step counter of stochastic rounding (slot parity is read)
 };
 
 // Launchers; each returns the hipError_t of its launch.
 hipError_t launch_step(int storage, const StepArgs &a, int block_x, hipStream_t s);
 // Resident workgroups of the step kernel per compute unit.
-int step_blocks_per_cu(int storage, int block_x, bool trt);
+int step_blocks_per_cu(int storage, int block_x, bool trt, bool sr);
 // The step kernel compiled for 8 waves per SIMD, and its resident workgroups.
 hipError_t launch_step8(int storage, const StepArgs &a, int block_x, hipStream_t s);
-int step8_blocks_per_cu(int storage, int block_x, bool trt);
+int step8_blocks_per_cu(int storage, int block_x, bool trt, bool sr);
 // The split step (a producer wave streams rows into LDS for block_x compute
 // threads; block_x = 128 or 256) and its resident workgroups per compute unit.
 hipError_t launch_step_split(int storage, const StepArgs &a, int block_x, hipStream_t s);
@@ -97,7 +104,7 @@ hipError_t launch_moments(int storage, const void *src, const uint16_t *flags, c
 // grid > 0: persistent kernel with that many workgroups taking tiles from the
 // queue (counter a.slot); grid <= 0: one workgroup per tile (no counter).
 hipError_t launch_batch_step(int storage, const BatchStepArgs &a, int block_x, int grid, hipStream_t s);
-int batch_blocks_per_cu(int storage, int block_x, bool trt);
+int batch_blocks_per_cu(int storage, int block_x, bool trt, bool sr);
 // Per-channel FP64 reduction of channels ids[0..n): out[4*k] = Q, out[4*k+1] =
 // mass, out[4*k+2] = bad nodes, for the buffer index cur[ids[k]].
 hipError_t launch_batch_reduce(int storage, const ChannelDesc *descs, const int32_t *ids,

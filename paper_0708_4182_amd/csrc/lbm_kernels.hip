@@ -27,12 +27,59 @@ template <> struct Codec<ST_F16> {
     using T = _Float16;
     __device__ static float dec(T v) { return (float)v; }
     __device__ static T enc(float v) { return (_Float16)v; }
+    // Stochastic rounding with random bits r: the magnitude rounds up with
+    // probability (dropped part) / (last place of the result), so the expected
+    // result is v.  13 + sh bits lie below the FP16 result's last place: sh = 0
+    // for FP16 normals (FP32 biased exponent e >= 113), sh = 113 - e in the
+    // FP16 subnormal range (last place 2^-24), where the 13 random bits are
+    // shifted to the top of the dropped field (rounding probabilities then
+    // resolved to 2^-13).  Below 2^-24, sh stops at 10 and the result is 0 or
+    // 2^-24 (error below 2^-24).  The cleared word is exact in FP16 (Inf and
+    // NaN keep their class), so the final conversion does not round.
+    __device__ static T enc_sr(float v, uint32_t r) {
+        uint32_t u = __builtin_bit_cast(uint32_t, v);
+        const int e = (int)((u >> 23) & 0xFFu);
+        const uint32_t sh = (uint32_t)min(max(113 - e, 0), 10);
+        const uint32_t mask = (0x2000u << sh) - 1u;
+        u = (u + ((r & 0x1FFFu) << sh)) & ~mask;
+        return (_Float16)__builtin_bit_cast(float, u);
+    }
 };
 template <> struct Codec<ST_BF16> {
     using T = __bf16;
     __device__ static float dec(T v) { return (float)v; }
     __device__ static T enc(float v) { return (__bf16)v; }
+    // Stochastic rounding: BF16 keeps the top 16 bits of the FP32 word, so the
+    // 16 random bits cover the whole dropped field (exactly unbiased).
+    __device__ static T enc_sr(float v, uint32_t r) {
+        uint32_t u = __builtin_bit_cast(uint32_t, v);
+        if (((u >> 23) & 0xFFu) < 255u) u = (u + (r & 0xFFFFu)) & 0xFFFF0000u;
+        return (__bf16)__builtin_bit_cast(float, u);
+    }
 };
+
+// 32-bit integer hash "lowbias32" (C. Wellons, hash-prospector: xor-shift 16,
+// multiply, xor-shift 15, multiply, xor-shift 16).  Counter-based random bits
+// for stochastic rounding: input = (node offset * 5 + k) xor a per-step mix.
+__device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Per-step random-bit mix of a stochastic-rounding step kernel.  The step
+// count lives in a two-slot device counter: the kernel reads slot par (its
+// source-buffer parity) and one lane of workgroup 0 writes count + 1 to the
+// other slot, which only the next step reads.  The count therefore advances
+// across hipGraph replays as across eager launches.
+__device__ __forceinline__ uint32_t sr_step_mix(uint32_t *rng, int par) {
+    const uint32_t count = rng[par];
+    if (blockIdx.x == 0 && threadIdx.x == 0) rng[par ^ 1] = count + 1u;
+    return lowbias32(count + 0x9e3779b9u);
+}
 
 constexpr float W0 = 4.f / 9.f, W1 = 1.f / 9.f, W5 = 1.f / 36.f;
 
@@ -173,9 +220,8 @@ __device__ __forceinline__ void equilibrium(float rho, float s, float jx, float 
 // S+ = w (9 (e.u)(e.F) - 3 u.F) weighted 1 - omega+/2, S- = 3 w e.F weighted
 // 1 - omega-/2.  Deviations d and feq share the offset w rho_off, which
 // cancels in n+ and n-.
-template <class C>
 __device__ __forceinline__ void collide_trt(const Model &m, const float d[9], float rho, float s, float jx,
-                                            float jy, float Fx, float Fy, typename C::T out[9]) {
+                                            float jy, float Fx, float Fy, float out[9]) {
 #pragma clang fp contract(off)
     const float hx = jx + 0.5f * Fx, hy = jy + 0.5f * Fy;
     float feq[9];
@@ -184,14 +230,14 @@ __device__ __forceinline__ void collide_trt(const Model &m, const float d[9], fl
     const float ux = hx * inv, uy = hy * inv;
     const float uF3 = 3.f * (ux * Fx + uy * Fy);
     const float wp = m.omega, wm = m.omega_m, cp = m.src_p, cm = m.src_m;
-    out[0] = C::enc(d[0] - wp * (d[0] - feq[0]) - cp * (W0 * uF3));
+    out[0] = d[0] - wp * (d[0] - feq[0]) - cp * (W0 * uF3);
     auto pair = [&](int a, int b, float eu, float eF, float w) {
         const float na = d[a] - feq[a], nb = d[b] - feq[b];
         const float np = 0.5f * (na + nb), nm = 0.5f * (na - nb);
         const float sp = w * (9.f * eu * eF - uF3), sm = 3.f * w * eF;
         const float sym = cp * sp - wp * np, anti = cm * sm - wm * nm;
-        out[a] = C::enc(d[a] + (sym + anti));
-        out[b] = C::enc(d[b] + (sym - anti));
+        out[a] = d[a] + (sym + anti);
+        out[b] = d[b] + (sym - anti);
     };
     pair(1, 3, ux, Fx, W1);
     pair(2, 4, uy, Fy, W1);
@@ -204,10 +250,10 @@ __device__ __forceinline__ void collide_trt(const Model &m, const float d[9], fl
 // neighbourhood comes from LDS rows rowm (y-1), row0 (y), rowp (y+1) at
 // column c; solid neighbours hold phi = 0 there, which removes them from
 // eq. (5) as the model requires.
-template <class C, bool TRT = false>
-__device__ __forceinline__ void collide(const Model &m, const float d[9], float s, float jx, float jy,
-                                        uint32_t fl, const float *rowm, const float *row0,
-                                        const float *rowp, int c, typename C::T out[9]) {
+template <bool TRT>
+__device__ __forceinline__ void collide_post(const Model &m, const float d[9], float s, float jx, float jy,
+                                             uint32_t fl, const float *rowm, const float *row0,
+                                             const float *rowp, int c, float out[9]) {
     const float rho = m.rho_off + s;
     const float pc = row0[c];
     const float p1 = row0[c + 1], p3 = row0[c - 1];
@@ -240,7 +286,7 @@ __device__ __forceinline__ void collide(const Model &m, const float d[9], float 
     Fx += rho * m.gx;
     Fy += rho * m.gy;
     if constexpr (TRT) {
-        collide_trt<C>(m, d, rho, s, jx, jy, Fx, Fy, out);
+        collide_trt(m, d, rho, s, jx, jy, Fx, Fy, out);
         return;
     }
     // eq. (10): rho u' = rho u + tau F
@@ -248,18 +294,42 @@ __device__ __forceinline__ void collide(const Model &m, const float d[9], float 
     equilibrium(rho, s, jx + m.tau * Fx, jy + m.tau * Fy, feq);
     const float om = m.omega;
 #pragma unroll
-    for (int a = 0; a < 9; ++a) out[a] = C::enc(d[a] + om * (feq[a] - d[a]));
+    for (int a = 0; a < 9; ++a) out[a] = d[a] + om * (feq[a] - d[a]);
 }
 
+// The collision with its nine results encoded for storage (nearest).
 template <class C, bool TRT = false>
+__device__ __forceinline__ void collide(const Model &m, const float d[9], float s, float jx, float jy,
+                                        uint32_t fl, const float *rowm, const float *row0,
+                                        const float *rowp, int c, typename C::T out[9]) {
+    float p[9];
+    collide_post<TRT>(m, d, s, jx, jy, fl, rowm, row0, rowp, c, p);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) out[a] = C::enc(p[a]);
+}
+
+// With SR the nine results are rounded stochastically: 16 random bits each,
+// from five hashes of (node offset * 5 + k) xor the step's mix.
+template <class C, bool TRT = false, bool SR = false>
 __device__ __forceinline__ void collide_store(const Model &m, const float d[9], float s, float jx,
                                               float jy, uint32_t fl, const float *rowm,
                                               const float *row0, const float *rowp, int c,
                                               __amdgpu_buffer_rsrc_t dst, uint32_t plane,
-                                              uint32_t row, uint32_t lane_byte) {
-    typename C::T out[9];
-    collide<C, TRT>(m, d, s, jx, jy, fl, rowm, row0, rowp, c, out);
+                                              uint32_t row, uint32_t lane_byte, uint32_t mix = 0u) {
     constexpr uint32_t E = sizeof(typename C::T);
+    typename C::T out[9];
+    if constexpr (SR) {
+        float p[9];
+        collide_post<TRT>(m, d, s, jx, jy, fl, rowm, row0, rowp, c, p);
+        const uint32_t k0 = (row + lane_byte / E) * 5u;
+        uint32_t h[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) h[k] = lowbias32((k0 + (uint32_t)k) ^ mix);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) out[a] = C::enc_sr(p[a], (a & 1) ? (h[a >> 1] >> 16) : (h[a >> 1] & 0xFFFFu));
+    } else {
+        collide<C, TRT>(m, d, s, jx, jy, fl, rowm, row0, rowp, c, out);
+    }
 #pragma unroll
     for (int a = 0; a < 9; ++a) bstore(dst, lane_byte, ((uint32_t)a * plane + row) * E, out[a]);
 }
@@ -294,10 +364,10 @@ __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >
 // chunks of a strip run on the same XCD.
 constexpr int RING = 4;
 
-template <int S, bool TRT = false>
+template <int S, bool TRT = false, bool SR = false>
 __device__ __forceinline__ void step_tile(const void *src_ptr, void *dst_ptr, const uint16_t *flags_ptr,
                                           const Grid &g, const Model &m, int x0, int y0, int y1, bool up,
-                                          float *ring) {
+                                          float *ring, uint32_t mix = 0u) {
     using C = Codec<S>;
     using T = typename C::T;
     const int BX = blockDim.x, W = BX + 2;
@@ -447,8 +517,8 @@ __device__ __forceinline__ void step_tile(const void *src_ptr, void *dst_ptr, co
             const float *mid = ring + ((i - 1) & (RING - 1)) * W;
             const float *rowm = up ? older : slot;
             const float *rowp = up ? slot : older;
-            collide_store<C, TRT>(m, pd, ps, pjx, pjy, pfl, rowm, mid, rowp, tid + 1, rd, plane,
-                             (uint32_t)pyr * pitch, v0);
+            collide_store<C, TRT, SR>(m, pd, ps, pjx, pjy, pfl, rowm, mid, rowp, tid + 1, rd, plane,
+                                      (uint32_t)pyr * pitch, v0, mix);
         }
 #pragma unroll
         for (int q = 0; q < 9; ++q) pd[q] = cd[q];
@@ -460,22 +530,26 @@ __device__ __forceinline__ void step_tile(const void *src_ptr, void *dst_ptr, co
     }
 }
 
-template <int S, bool TRT>
+template <int S, bool TRT, bool SR>
 __device__ __forceinline__ void step_tiles(const StepArgs &a, float *ring) {
+    uint32_t mix = 0u;
+    if constexpr (SR) mix = sr_step_mix(a.rng, a.par);
     const int tile = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
     if (tile >= a.ntiles) return;   // uniform for the workgroup, before any barrier
     const int strip = tile / a.chunks, chunk = tile - strip * a.chunks;
     const int y0 = (int)(((int64_t)chunk * a.g.ny) / a.chunks);
     const int y1 = (int)(((int64_t)(chunk + 1) * a.g.ny) / a.chunks);
-    step_tile<S, TRT>(a.src, a.dst, a.flags, a.g, a.m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring);
+    step_tile<S, TRT, SR>(a.src, a.dst, a.flags, a.g, a.m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0,
+                          ring, mix);
 }
 
-// TRT selects the collision operator at compile time (a run-time branch would
-// cost the paper's operator registers and occupancy).
-template <int S, bool TRT>
+// TRT selects the collision operator and SR the rounding of 16-bit stores at
+// compile time (run-time branches would cost the paper's operator registers
+// and occupancy).
+template <int S, bool TRT, bool SR>
 __global__ void __launch_bounds__(512) k_step(const StepArgs a) {
     extern __shared__ float ring[];
-    step_tiles<S, TRT>(a, ring);
+    step_tiles<S, TRT, SR>(a, ring);
 }
 
 // The same kernel compiled for 8 resident waves per SIMD (64 VGPRs) instead of
@@ -484,10 +558,10 @@ __global__ void __launch_bounds__(512) k_step(const StepArgs a) {
 // the L1 cache) and schedules the row loop differently.  Same arithmetic,
 // bitwise the same results; which one is faster depends on the storage width
 // and tile (the autotuner decides).
-template <int S, bool TRT>
+template <int S, bool TRT, bool SR>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8, 8))) k_step8(const StepArgs a) {
     extern __shared__ float ring[];
-    step_tiles<S, TRT>(a, ring);
+    step_tiles<S, TRT, SR>(a, ring);
 }
 
 // ---------------------------------------------------------------------------
@@ -1161,13 +1235,15 @@ __global__ void __launch_bounds__(64) k_reduce_final(const double *__restrict__ 
 // Batched step over many lattices in one persistent launch.  Workgroups pull
 // tiles from a queue (one atomic per tile), so uneven channels balance
 // dynamically; every channel uses the same tile code as a single lattice.
-template <int S, bool TRT>
+template <int S, bool TRT, bool SR>
 __global__ void __launch_bounds__(512) k_batch_step(const ChannelDesc *__restrict__ descs,
                                                     const uint32_t *__restrict__ tiles,
                                                     uint32_t *__restrict__ counters, int ntiles, int slot,
-                                                    int parity) {
+                                                    int parity, uint32_t *rng) {
     extern __shared__ float ring[];
     __shared__ int next_tile;
+    uint32_t mix = 0u;
+    if constexpr (SR) mix = sr_step_mix(rng, parity);
     for (;;) {
         if (threadIdx.x == 0) next_tile = (int)atomicAdd(&counters[slot], 1u);
         __syncthreads();
@@ -1185,18 +1261,21 @@ __global__ void __launch_bounds__(512) k_batch_step(const ChannelDesc *__restric
         const int strip = local / chunks, chunk = local - strip * chunks;
         const int y0 = (int)(((int64_t)chunk * g.ny) / chunks);
         const int y1 = (int)(((int64_t)(chunk + 1) * g.ny) / chunks);
-        step_tile<S, TRT>(src, dst, d->flags, g, m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring);
+        step_tile<S, TRT, SR>(src, dst, d->flags, g, m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring,
+                              mix);
     }
 }
 
 // The same batched step with one workgroup per tile (grid = number of tiles,
 // tiles mapped to XCDs in contiguous ranges): the hardware dispatcher does the
 // balancing and no state is carried between tiles.
-template <int S, bool TRT>
+template <int S, bool TRT, bool SR>
 __global__ void __launch_bounds__(512) k_batch_tiles(const ChannelDesc *__restrict__ descs,
                                                      const uint32_t *__restrict__ tiles, int ntiles,
-                                                     int tiles_per_xcd, int parity) {
+                                                     int tiles_per_xcd, int parity, uint32_t *rng) {
     extern __shared__ float ring[];
+    uint32_t mix = 0u;
+    if constexpr (SR) mix = sr_step_mix(rng, parity);
     const int t = (int)(blockIdx.x & 7u) * tiles_per_xcd + (int)(blockIdx.x >> 3);
     if (t >= ntiles) return;
     const uint32_t packed = __builtin_amdgcn_readfirstlane(tiles[t]);
@@ -1210,7 +1289,7 @@ __global__ void __launch_bounds__(512) k_batch_tiles(const ChannelDesc *__restri
     const int strip = local / chunks, chunk = local - strip * chunks;
     const int y0 = (int)(((int64_t)chunk * g.ny) / chunks);
     const int y1 = (int)(((int64_t)(chunk + 1) * g.ny) / chunks);
-    step_tile<S, TRT>(src, dst, d->flags, g, m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring);
+    step_tile<S, TRT, SR>(src, dst, d->flags, g, m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring, mix);
 }
 
 // Per-channel FP64 flux/mass reduction: one workgroup per channel, rows in
@@ -1264,48 +1343,47 @@ __global__ void __launch_bounds__(256) k_batch_reduce(const ChannelDesc *__restr
 
 }  // namespace
 
-hipError_t launch_step(int storage, const StepArgs &a, int block_x, hipStream_t s) {
-    const unsigned blocks = 8u * (unsigned)a.tiles_per_xcd;
-    const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
-    const bool trt = a.m.trt != 0;
+// The fused step kernel for (storage, collision, rounding); null for
+// stochastic rounding of FP32 data (not instantiated).
+using StepKernel = void (*)(const StepArgs);
+template <bool EIGHT, int S, bool TRT, bool SR>
+StepKernel step_k() {
+    if constexpr (EIGHT) return k_step8<S, TRT, SR>;
+    else return k_step<S, TRT, SR>;
+}
+template <bool EIGHT, int S>
+StepKernel step_k16(bool trt, bool sr) {
+    return trt ? (sr ? step_k<EIGHT, S, true, true>() : step_k<EIGHT, S, true, false>())
+               : (sr ? step_k<EIGHT, S, false, true>() : step_k<EIGHT, S, false, false>());
+}
+template <bool EIGHT>
+StepKernel step_kernel(int storage, bool trt, bool sr) {
     switch (storage) {
     case ST_F32:
-        if (trt) k_step<ST_F32, true><<<blocks, block_x, lds, s>>>(a);
-        else k_step<ST_F32, false><<<blocks, block_x, lds, s>>>(a);
-        break;
-    case ST_F16:
-        if (trt) k_step<ST_F16, true><<<blocks, block_x, lds, s>>>(a);
-        else k_step<ST_F16, false><<<blocks, block_x, lds, s>>>(a);
-        break;
-    case ST_BF16:
-        if (trt) k_step<ST_BF16, true><<<blocks, block_x, lds, s>>>(a);
-        else k_step<ST_BF16, false><<<blocks, block_x, lds, s>>>(a);
-        break;
-    default: return hipErrorInvalidValue;
+        if (sr) return nullptr;
+        return trt ? step_k<EIGHT, ST_F32, true, false>() : step_k<EIGHT, ST_F32, false, false>();
+    case ST_F16: return step_k16<EIGHT, ST_F16>(trt, sr);
+    case ST_BF16: return step_k16<EIGHT, ST_BF16>(trt, sr);
+    default: return nullptr;
     }
+}
+
+template <bool EIGHT>
+hipError_t launch_step_k(int storage, const StepArgs &a, int block_x, hipStream_t s) {
+    const StepKernel k = step_kernel<EIGHT>(storage, a.m.trt != 0, a.m.sround != 0);
+    if (!k) return hipErrorInvalidValue;
+    const unsigned blocks = 8u * (unsigned)a.tiles_per_xcd;
+    const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
+    k<<<blocks, block_x, lds, s>>>(a);
     return hipGetLastError();
 }
 
+hipError_t launch_step(int storage, const StepArgs &a, int block_x, hipStream_t s) {
+    return launch_step_k<false>(storage, a, block_x, s);
+}
+
 hipError_t launch_step8(int storage, const StepArgs &a, int block_x, hipStream_t s) {
-    const unsigned blocks = 8u * (unsigned)a.tiles_per_xcd;
-    const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
-    const bool trt = a.m.trt != 0;
-    switch (storage) {
-    case ST_F32:
-        if (trt) k_step8<ST_F32, true><<<blocks, block_x, lds, s>>>(a);
-        else k_step8<ST_F32, false><<<blocks, block_x, lds, s>>>(a);
-        break;
-    case ST_F16:
-        if (trt) k_step8<ST_F16, true><<<blocks, block_x, lds, s>>>(a);
-        else k_step8<ST_F16, false><<<blocks, block_x, lds, s>>>(a);
-        break;
-    case ST_BF16:
-        if (trt) k_step8<ST_BF16, true><<<blocks, block_x, lds, s>>>(a);
-        else k_step8<ST_BF16, false><<<blocks, block_x, lds, s>>>(a);
-        break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return launch_step_k<true>(storage, a, block_x, s);
 }
 
 template <int V>
@@ -1384,48 +1462,22 @@ int split_blocks_per_cu(int storage, int block_x) {
     return block_x == 128 ? split_blocks_bx<128>(storage) : split_blocks_bx<256>(storage);
 }
 
-int step_blocks_per_cu(int storage, int block_x, bool trt) {
+template <bool EIGHT>
+int step_k_blocks_per_cu(int storage, int block_x, bool trt, bool sr) {
+    const StepKernel k = step_kernel<EIGHT>(storage, trt, sr);
+    if (!k) return 1;
     const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
     int n = 0;
-    hipError_t e = hipErrorInvalidValue;
-    switch (storage) {
-    case ST_F32:
-        e = trt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_F32, true>, block_x, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_F32, false>, block_x, lds);
-        break;
-    case ST_F16:
-        e = trt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_F16, true>, block_x, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_F16, false>, block_x, lds);
-        break;
-    case ST_BF16:
-        e = trt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_BF16, true>, block_x, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step<ST_BF16, false>, block_x, lds);
-        break;
-    default: break;
-    }
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, block_x, lds);
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
-int step8_blocks_per_cu(int storage, int block_x, bool trt) {
-    const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
-    int n = 0;
-    hipError_t e = hipErrorInvalidValue;
-    switch (storage) {
-    case ST_F32:
-        e = trt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step8<ST_F32, true>, block_x, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step8<ST_F32, false>, block_x, lds);
-        break;
-    case ST_F16:
-        e = trt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step8<ST_F16, true>, block_x, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step8<ST_F16, false>, block_x, lds);
-        break;
-    case ST_BF16:
-        e = trt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step8<ST_BF16, true>, block_x, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step8<ST_BF16, false>, block_x, lds);
-        break;
-    default: break;
-    }
-    return e == hipSuccess && n > 0 ? n : 1;
+int step_blocks_per_cu(int storage, int block_x, bool trt, bool sr) {
+    return step_k_blocks_per_cu<false>(storage, block_x, trt, sr);
+}
+
+int step8_blocks_per_cu(int storage, int block_x, bool trt, bool sr) {
+    return step_k_blocks_per_cu<true>(storage, block_x, trt, sr);
 }
 
 hipError_t launch_init(int storage, void *dst, const uint16_t *flags, const Grid &g, float off,
@@ -1499,49 +1551,54 @@ hipError_t launch_reduce(int storage, const void *src, const uint16_t *flags, co
 }
 
 
-template <bool TRT>
-hipError_t launch_batch_t(int storage, const BatchStepArgs &a, int block_x, int grid, size_t lds, hipStream_t s) {
-    if (grid <= 0) {   // one workgroup per tile
-        const int per = (a.ntiles + 7) / 8;
-        switch (storage) {
-        case ST_F32: k_batch_tiles<ST_F32, TRT><<<8 * per, block_x, lds, s>>>(a.descs, a.tiles, a.ntiles, per, a.parity); break;
-        case ST_F16: k_batch_tiles<ST_F16, TRT><<<8 * per, block_x, lds, s>>>(a.descs, a.tiles, a.ntiles, per, a.parity); break;
-        case ST_BF16: k_batch_tiles<ST_BF16, TRT><<<8 * per, block_x, lds, s>>>(a.descs, a.tiles, a.ntiles, per, a.parity); break;
-        default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
-    }
+// Batch kernels for (storage, collision, rounding), as for the single lattice.
+using BatchTilesKernel = void (*)(const ChannelDesc *, const uint32_t *, int, int, int, uint32_t *);
+using BatchQueueKernel = void (*)(const ChannelDesc *, const uint32_t *, uint32_t *, int, int, int, uint32_t *);
+template <bool QUEUE, int S, bool TRT, bool SR>
+auto batch_k() {
+    if constexpr (QUEUE) return k_batch_step<S, TRT, SR>;
+    else return k_batch_tiles<S, TRT, SR>;
+}
+template <bool QUEUE, int S>
+auto batch_k16(bool trt, bool sr) {
+    return trt ? (sr ? batch_k<QUEUE, S, true, true>() : batch_k<QUEUE, S, true, false>())
+               : (sr ? batch_k<QUEUE, S, false, true>() : batch_k<QUEUE, S, false, false>());
+}
+template <bool QUEUE>
+auto batch_kernel(int storage, bool trt, bool sr) -> decltype(batch_k<QUEUE, ST_F32, false, false>()) {
     switch (storage) {
-    case ST_F32: k_batch_step<ST_F32, TRT><<<grid, block_x, lds, s>>>(a.descs, a.tiles, a.counters, a.ntiles, a.slot, a.parity); break;
-    case ST_F16: k_batch_step<ST_F16, TRT><<<grid, block_x, lds, s>>>(a.descs, a.tiles, a.counters, a.ntiles, a.slot, a.parity); break;
-    case ST_BF16: k_batch_step<ST_BF16, TRT><<<grid, block_x, lds, s>>>(a.descs, a.tiles, a.counters, a.ntiles, a.slot, a.parity); break;
-    default: return hipErrorInvalidValue;
+    case ST_F32:
+        if (sr) return nullptr;
+        return trt ? batch_k<QUEUE, ST_F32, true, false>() : batch_k<QUEUE, ST_F32, false, false>();
+    case ST_F16: return batch_k16<QUEUE, ST_F16>(trt, sr);
+    case ST_BF16: return batch_k16<QUEUE, ST_BF16>(trt, sr);
+    default: return nullptr;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_batch_step(int storage, const BatchStepArgs &a, int block_x, int grid, hipStream_t s) {
     const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
-    if (a.trt) return launch_batch_t<true>(storage, a, block_x, grid, lds, s);
-    return launch_batch_t<false>(storage, a, block_x, grid, lds, s);
-}
-
-template <bool TRT>
-int batch_blocks_t(int storage, size_t lds, int block_x) {
-    int n = 0;
-    hipError_t e = hipErrorInvalidValue;
-    switch (storage) {
-    case ST_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_step<ST_F32, TRT>, block_x, lds); break;
-    case ST_F16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_step<ST_F16, TRT>, block_x, lds); break;
-    case ST_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_step<ST_BF16, TRT>, block_x, lds); break;
-    default: break;
+    const bool trt = a.trt != 0, sr = a.sround != 0;
+    if (grid <= 0) {   // one workgroup per tile
+        const BatchTilesKernel k = batch_kernel<false>(storage, trt, sr);
+        if (!k) return hipErrorInvalidValue;
+        const int per = (a.ntiles + 7) / 8;
+        k<<<8 * per, block_x, lds, s>>>(a.descs, a.tiles, a.ntiles, per, a.parity, a.rng);
+        return hipGetLastError();
     }
-    return e == hipSuccess && n > 0 ? n : 1;
+    const BatchQueueKernel k = batch_kernel<true>(storage, trt, sr);
+    if (!k) return hipErrorInvalidValue;
+    k<<<grid, block_x, lds, s>>>(a.descs, a.tiles, a.counters, a.ntiles, a.slot, a.parity, a.rng);
+    return hipGetLastError();
 }
 
-int batch_blocks_per_cu(int storage, int block_x, bool trt) {
+int batch_blocks_per_cu(int storage, int block_x, bool trt, bool sr) {
+    const BatchQueueKernel k = batch_kernel<true>(storage, trt, sr);
+    if (!k) return 1;
     const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);
-    return trt ? batch_blocks_t<true>(storage, lds, block_x) : batch_blocks_t<false>(storage, lds, block_x);
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, block_x, lds);
+    return e == hipSuccess && n > 0 ? n : 1;
 }
 
 hipError_t launch_batch_reduce(int storage, const ChannelDesc *descs, const int32_t *ids,

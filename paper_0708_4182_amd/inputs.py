@@ -120,6 +120,7 @@ class Params:
     collision: int = 0  # 0: BGK with the velocity shift of eq. (10); 1: TRT with Guo forcing
     trt_magic: float = 3.0 / 16.0  # Lambda of the TRT operator
     elec_normal: int = 0  # 0: electric force towards the electrode wall; 1: along the local face normal
+    rounding: int = 0  # 16-bit storage: 0 nearest even, 1 stochastic (unbiased; see lbm_params.rounding)
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)

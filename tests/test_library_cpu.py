@@ -68,6 +68,11 @@ def test_workspace_bytes(lib):
     # direction of the electric force: 0 (electrode) or 1 (local face normal)
     assert lbm.workspace_bytes(p.replace(elec_normal=1)) == n32
     assert lbm.workspace_bytes(p.replace(elec_normal=2)) == 0
+    # rounding of 16-bit storage: 0 (nearest) or 1 (stochastic, 16-bit storage only)
+    assert lbm.workspace_bytes(p.replace(storage=1, rounding=1)) == n16
+    assert lbm.workspace_bytes(p.replace(storage=2, rounding=1)) == lbm.workspace_bytes(p.replace(storage=2))
+    assert lbm.workspace_bytes(p.replace(storage=0, rounding=1)) == 0
+    assert lbm.workspace_bytes(p.replace(storage=1, rounding=2)) == 0
     # one population buffer must stay below 4 GiB (32-bit offsets)
     assert lbm.workspace_bytes(I.Params(nx=65536, ny=4096)) == 0
 
@@ -75,7 +80,7 @@ def test_workspace_bytes(lib):
 @pytest.mark.parametrize("bad", [dict(nx=2), dict(tau=0.4), dict(elec_walls=4),
                                  dict(elec_layers=-1), dict(storage=3), dict(rho_ref=-0.5),
                                  dict(collision=5), dict(collision=1, trt_magic=-1.0),
-                                 dict(elec_normal=-1)])
+                                 dict(elec_normal=-1), dict(rounding=1), dict(storage=1, rounding=-1)])
 def test_init_rejects_invalid_params_without_gpu_work(lib, bad):
     from paper_0708_4182_amd import lbm
     import numpy as np
@@ -174,6 +179,12 @@ def test_batch_workspace_validation(lib):
     assert lib.lbm_batch_workspace_bytes(2, ops) == 0
     trt = (lbm.lbm_params * 2)(*[lbm.to_c_params(q.replace(collision=1)) for q in ps[:2]])
     assert lib.lbm_batch_workspace_bytes(2, trt) > 0
+    # one rounding per batch
+    f16 = [q.replace(storage=1) for q in ps[:2]]
+    rnd = (lbm.lbm_params * 2)(lbm.to_c_params(f16[0]), lbm.to_c_params(f16[1].replace(rounding=1)))
+    assert lib.lbm_batch_workspace_bytes(2, rnd) == 0
+    sr = (lbm.lbm_params * 2)(*[lbm.to_c_params(q.replace(rounding=1)) for q in f16])
+    assert lib.lbm_batch_workspace_bytes(2, sr) > 0
 
 
 def test_net_param_count_matches_the_network_definition(lib):
