@@ -45,10 +45,10 @@ def flux_vs_field(nx=1024, ny=128, fs=(0.0, 5e-4, 1e-3, 1.5e-3, 2e-3), seed=0, s
             "steps": res.steps.tolist(), "converged": res.converged.tolist(), "seconds": dt}
 
 
-def sweep_throughput(n=256, seed=0, storage=1, steps=60, warmup=20, graph=10, tune=True):
+def sweep_throughput(n=256, seed=0, storage=1, steps=60, warmup=20, graph=10, tune=True, rounding=0):
     import torch
     rows = I.sweep_table(n, seed)
-    cases = [I.sweep_case(r, storage=storage) for r in rows]
+    cases = [I.sweep_case(r, storage=storage, rounding=rounding) for r in rows]
     nodes = sum(c.params.nx * c.params.ny for c in cases)
     fluid = sum(int((c.solid == 0).sum()) for c in cases)
     b = lbm.Batch(cases)
@@ -68,7 +68,7 @@ def sweep_throughput(n=256, seed=0, storage=1, steps=60, warmup=20, graph=10, tu
     ms = e0.elapsed_time(e1) / steps
     es = {0: 4, 1: 2, 2: 2}[storage]
     return {"experiment": "sweep_throughput", "channels": n, "nodes": nodes, "fluid_nodes": fluid,
-            "storage": storage, "tile": tile, "graph_steps": graph, "ms_per_step": ms,
+            "storage": storage, "rounding": rounding, "tile": tile, "graph_steps": graph, "ms_per_step": ms,
             "mlups": nodes / (ms * 1e-3) / 1e6,
             "achieved_GBs": 18 * es * fluid / (ms * 1e-3) / 1e9}
 
@@ -196,13 +196,18 @@ def net_throughput(batch=32, H=64, W=256, steps=50, warmup=5, seed=0):
     return out
 
 
-def sweep_steady(n=256, seed=0, storage=1, max_steps=200_000, check_every=200, window=2000, rtol=1e-8):
+def sweep_steady(n=256, seed=0, storage=1, max_steps=200_000, check_every=200, window=2000, rtol=1e-8,
+                 rounding=0):
     """The 256-channel sweep table driven to steady flux in one batch (one
     launch per step, hipGraph of check_every steps, channels retired as they
-    converge): per-channel steps, lattice updates and wall time."""
+    converge): per-channel steps, lattice updates and wall time.  With nearest
+    rounding (the default) a 16-bit lattice settles on an exact fixed point,
+    which the rtol test detects, but that point carries the rounding bias;
+    stochastic rounding (rounding=1) removes the bias and leaves noise of
+    about 1e-4 in the flux, which a 1e-8 test never passes."""
     import torch
     rows = I.sweep_table(n, seed)
-    cases = [I.sweep_case(r, storage=storage) for r in rows]
+    cases = [I.sweep_case(r, storage=storage, rounding=rounding) for r in rows]
     b = lbm.Batch(cases)
     bx, r, us = b.autotune(reps=3)
     torch.cuda.synchronize()
@@ -216,7 +221,7 @@ def sweep_steady(n=256, seed=0, storage=1, max_steps=200_000, check_every=200, w
     conv = res.converged
     # the steady time of the warm-start comparison: within 1e-4 of the final flux for 5000 steps
     st = np.array([steady_time(res.history[i], res.Q[i]) for i in range(n)])
-    return {"experiment": "sweep_steady", "channels": n, "storage": storage, "tile": [bx, r],
+    return {"experiment": "sweep_steady", "channels": n, "storage": storage, "rounding": rounding, "tile": [bx, r],
             "max_steps": max_steps, "converged": int(conv.sum()),
             "steps_median": float(np.median(res.steps)), "steps_max": int(res.steps.max()),
             "lattice_updates": res.node_updates, "wall_seconds": wall,

@@ -307,13 +307,16 @@ def sweep_table(n: int = 256, seed: int = 0):
     return rows
 
 
-def sweep_case(row: dict, storage: int = 1, accel: float = 1e-6, noise_amp: float = 1e-3) -> Case:
+def sweep_case(row: dict, storage: int = 1, accel: float = 1e-6, noise_amp: float = 1e-3,
+               rounding: int = 0) -> Case:
     """Build one channel of the sweep table (steps a = 8, pitch 32, random phases)."""
     nx, ny = row["nx"], row["ny"]
     solid = periodic_bumps(nx, ny, 8, row["b"], 32, row["seed"])
-    return channel_case(nx, ny, solid, G=row["G"], f_elec=row["f_elec"], accel=accel,
-                        seed=row["seed"], noise_amp=noise_amp, storage=storage,
-                        name=f"sweep{row['index']}")
+    c = channel_case(nx, ny, solid, G=row["G"], f_elec=row["f_elec"], accel=accel,
+                     seed=row["seed"], noise_amp=noise_amp, storage=storage,
+                     name=f"sweep{row['index']}")
+    c.params = c.params.replace(rounding=rounding)
+    return c
 
 
 def warm_row(seed: int) -> dict:
