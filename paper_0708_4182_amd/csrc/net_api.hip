@@ -72,6 +72,7 @@ struct Buffers {
         *g_d2a, *g_d2b, *g_d1a, *g_d1b, *g_out, *y, *dz, *wt, *partial;
     float *theta, *grad, *m, *v;
     __bf16 *wp;                      // packed bf16 weights of the matrix-core convolution
+    __bf16 *dzh;                     // the layer gradient rounded to bf16 (bf16 build, input gradient)
     double *loss_part, *loss_stats;
     size_t total, partial_floats;
 };
@@ -124,6 +125,7 @@ bool layout(const Plan &P, char *base, Buffers &b) {
         }
     b.wp = (__bf16 *)take(2 * wpmax);
     b.dz = (float *)take(4 * dzmax);
+    b.dzh = (__bf16 *)take(2 * dzmax);
     b.wt = (float *)take(4 * wtmax);
     b.partial = (float *)take(4 * partmax);
     b.partial_floats = partmax;
@@ -316,7 +318,7 @@ lbm_status conv_back(lbm_net *n, int l, const LayerIO &io, int N) {
     const Plan &P = n->P;
     Buffers &b = n->b;
     const int cin = P.lcin[l], cout = P.lcout[l], H = io.Y.H, W = io.Y.W;
-    NHIP(n, lbmnet::relu_mask<TA>(io.gY, io.Y, N, cout, b.dz, n->s));
+    NHIP(n, lbmnet::relu_mask<TA>(io.gY, io.Y, N, cout, b.dz, sizeof(TA) == 2 ? b.dzh : nullptr, n->s));
     const bool mfma = sizeof(TA) == 2 && l != E1A;   // bf16 build, bf16 input activations
     const int chunks = mfma ? lbmnet::dw_chunks_mfma(N, H, W, cin, cout) : lbmnet::dw_chunks(N, H, W, cin, cout);
     if ((size_t)chunks * cout * cin * 9 > b.partial_floats) return nfail(n, LBM_EINVAL, "dW scratch too small");
@@ -330,8 +332,9 @@ lbm_status conv_back(lbm_net *n, int l, const LayerIO &io, int N) {
     if (io.has_gx) {
         const View dz = view(b.dz, cout, H, W, cout, 0, 4);
         if (sizeof(TA) == 2) {
-            // bf16 build: matrix cores, dz and W rounded to bf16
-            NHIP(n, lbmnet::conv3x3_mfma_dx(dz, b.theta + P.woff[l], io.gX, N, cin, cout, b.wp, n->s));
+            // bf16 build: matrix cores, dz (rounded to bf16 by relu_mask) and W rounded to bf16
+            const View dzh = view(b.dzh, cout, H, W, cout, 0, 2);
+            NHIP(n, lbmnet::conv3x3_mfma_dx(dzh, b.theta + P.woff[l], io.gX, N, cin, cout, b.wp, n->s));
         } else {
             NHIP(n, lbmnet::flip_transpose(b.theta + P.woff[l], b.wt, cin, cout, n->s));
             NHIP(n, (lbmnet::conv3x3<float, float>(dz, b.wt, nullptr, io.gX, N, cout, cin, false, n->s)));

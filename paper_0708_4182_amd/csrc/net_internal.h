@@ -25,7 +25,8 @@ hipError_t conv3x3(const View &in, const float *w, const float *bias, const View
 int pad32(int c);
 hipError_t conv3x3_mfma(const View &in, const float *w, const float *bias, const View &out, int N, int cin,
                         int cout, bool relu, __bf16 *wp, hipStream_t s);
-// Input gradient of a 3x3 layer on matrix cores (dz and W rounded to bf16);
+// Input gradient of a 3x3 layer on matrix cores: dz is the layer gradient
+// already rounded to bf16, the weights are rounded to bf16 as they are packed;
 // wp holds 9 * cin * pad32(cout) bf16.
 hipError_t conv3x3_mfma_dx(const View &dz, const float *w, const View &dx, int N, int cin, int cout, __bf16 *wp,
                            hipStream_t s);
@@ -43,7 +44,7 @@ hipError_t conv3x3_dw(const View &x, const float *dz, int N, int cin, int cout, 
 int bias_scratch(int C);
 hipError_t bias_grad(const float *dz, int N, int C, int HW, float *part, float *db, hipStream_t s);
 template <class TA>
-hipError_t relu_mask(const View &g, const View &y, int N, int C, float *dz, hipStream_t s);
+hipError_t relu_mask(const View &g, const View &y, int N, int C, float *dz, __bf16 *dzh, hipStream_t s);
 template <class TA>
 hipError_t pool(const View &in, const View &out, int N, int C, hipStream_t s);
 hipError_t pool_back_acc(const View &dy, const View &dx, int N, int C, hipStream_t s);

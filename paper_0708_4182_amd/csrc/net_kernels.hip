@@ -213,14 +213,16 @@ __global__ void k_bias_final(const float *__restrict__ part, int C, float *__res
 
 // dz = g * (y > 0) (ReLU derivative from the stored output), dense fp32 out.
 template <class TA>
-__global__ void k_relu_mask(View g, View y, int N, int C, float *__restrict__ dz) {
+__global__ void k_relu_mask(View g, View y, int N, int C, float *__restrict__ dz, __bf16 *__restrict__ dzh) {
     const size_t HW = (size_t)y.H * y.W, per = (size_t)C * HW;
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (size_t)N * per) return;
     const size_t n = i / per, r = i % per;
     const float gv = static_cast<const float *>(g.p)[n * g.bs + r];
     const float yv = tof(static_cast<const TA *>(y.p)[n * y.bs + r]);
-    dz[i] = yv > 0.f ? gv : 0.f;
+    const float v = yv > 0.f ? gv : 0.f;
+    dz[i] = v;
+    if (dzh) dzh[i] = (__bf16)v;
 }
 
 // ------------------------------------------------------ pool / upsample
@@ -474,13 +476,22 @@ __global__ void __launch_bounds__(256) k_conv3x3_mfma(View in, const __bf16 *__r
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[m][q] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int ci0 = 0; ci0 < cin; ci0 += MCI) {
-        for (int e = tid; e < MCI * (MH + 2) * (MW + 2); e += 256) {
-            const int q = e % (MW + 2), r = (e / (MW + 2)) % (MH + 2), c = e / ((MW + 2) * (MH + 2));
+        // one pixel and 8 channels per thread: 8 coalesced loads, one 16-byte LDS store
+        for (int e = tid; e < (MCI / 8) * (MH + 2) * (MW + 2); e += 256) {
+            const int q = e % (MW + 2), r = (e / (MW + 2)) % (MH + 2), c8 = e / ((MW + 2) * (MH + 2));
             const int y = ty0 - 1 + r;
-            const int x = (tx0 - 1 + q + W) % W;
-            __bf16 v = (__bf16)0.f;
-            if (ci0 + c < cin && y >= 0 && y < H) v = (__bf16)xin[(size_t)(ci0 + c) * H * W + (size_t)y * W + x];
-            xs[(r * (MW + 2) + q) * MPS + c] = v;
+            int x = tx0 - 1 + q;      // periodic in x; x < W + 33, so the loop ends
+            if (x < 0) x += W;
+            while (x >= W) x -= W;
+            const bool row_ok = y >= 0 && y < H;
+            const TI *src = xin + (size_t)(row_ok ? y : 0) * W + x;
+            bf16x8 v;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int c = ci0 + 8 * c8 + j;
+                v[j] = (row_ok && c < cin) ? (__bf16)src[(size_t)c * H * W] : (__bf16)0.f;
+            }
+            *reinterpret_cast<bf16x8 *>(&xs[(r * (MW + 2) + q) * MPS + 8 * c8]) = v;
         }
         for (int e = tid; e < 9 * MCO * (MCI / 8); e += 256) {
             const int c8 = e % (MCI / 8), co = (e / (MCI / 8)) % MCO, t = e / ((MCI / 8) * MCO);
@@ -694,7 +705,7 @@ hipError_t conv3x3_mfma_dx(const View &dz, const float *w, const View &dx, int N
     if (e != hipSuccess) return e;
     const int tiles = ((dz.W + MW - 1) / MW) * ((dz.H + MH - 1) / MH);
     const dim3 grid(tiles, N * ((cin + MCO - 1) / MCO));
-    k_conv3x3_mfma<float, float><<<grid, 256, 0, s>>>(dz, wp, nullptr, dx, cout, cin, cout_pad, 0);
+    k_conv3x3_mfma<__bf16, float><<<grid, 256, 0, s>>>(dz, wp, nullptr, dx, cout, cin, cout_pad, 0);
     return hipGetLastError();
 }
 
@@ -762,12 +773,12 @@ hipError_t bias_grad(const float *dz, int N, int C, int HW, float *part, float *
 }
 
 template <class TA>
-hipError_t relu_mask(const View &g, const View &y, int N, int C, float *dz, hipStream_t s) {
-    k_relu_mask<TA><<<nblk((size_t)N * C * y.H * y.W), 256, 0, s>>>(g, y, N, C, dz);
+hipError_t relu_mask(const View &g, const View &y, int N, int C, float *dz, __bf16 *dzh, hipStream_t s) {
+    k_relu_mask<TA><<<nblk((size_t)N * C * y.H * y.W), 256, 0, s>>>(g, y, N, C, dz, dzh);
     return hipGetLastError();
 }
-template hipError_t relu_mask<float>(const View &, const View &, int, int, float *, hipStream_t);
-template hipError_t relu_mask<__bf16>(const View &, const View &, int, int, float *, hipStream_t);
+template hipError_t relu_mask<float>(const View &, const View &, int, int, float *, __bf16 *, hipStream_t);
+template hipError_t relu_mask<__bf16>(const View &, const View &, int, int, float *, __bf16 *, hipStream_t);
 
 template <class TA>
 hipError_t pool(const View &in, const View &out, int N, int C, hipStream_t s) {
