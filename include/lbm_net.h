@@ -54,9 +54,9 @@ extern "C" {
 
 typedef struct {
     int32_t H, W;      /* lattice rows and columns, multiples of 8           */
-    int32_t batch;     /* largest n a call may pass                          */
-    int32_t cin, cout; /* input and output planes                            */
-    int32_t chans[4];  /* c1..c4                                             */
+    int32_t batch;     /* largest n a call may pass, 1..512                  */
+    int32_t cin, cout; /* input and output planes, 1..2048                   */
+    int32_t chans[4];  /* c1..c4, 1..2048 each                               */
     int32_t act_bf16;  /* 1: bf16 activations, 0: FP32 activations          */
 } lbm_net_config;
 

@@ -41,8 +41,11 @@ bool make_plan(const lbm_net_config *cfg, Plan &P, std::string &why) {
     if (!cfg) { why = "config is NULL"; return false; }
     if (cfg->H < 8 || cfg->W < 8 || cfg->H % 8 || cfg->W % 8) { why = "H and W must be multiples of 8"; return false; }
     if (cfg->batch < 1 || cfg->cin < 1 || cfg->cout < 1) { why = "batch, cin and cout must be >= 1"; return false; }
+    // grid dimensions y and z (at most 65535) carry samples x channel blocks
+    if (cfg->batch > 512) { why = "batch must be <= 512"; return false; }
+    if (cfg->cin > 2048 || cfg->cout > 2048) { why = "cin and cout must be <= 2048"; return false; }
     for (int i = 0; i < 4; ++i)
-        if (cfg->chans[i] < 1) { why = "channel counts must be >= 1"; return false; }
+        if (cfg->chans[i] < 1 || cfg->chans[i] > 2048) { why = "channel counts must be in [1, 2048]"; return false; }
     P.H = cfg->H; P.W = cfg->W; P.B = cfg->batch; P.cin = cfg->cin; P.cout = cfg->cout;
     for (int i = 0; i < 4; ++i) P.c[i] = cfg->chans[i];
     P.bf16 = cfg->act_bf16 != 0;
@@ -325,7 +328,7 @@ lbm_status conv_back(lbm_net *n, int l, const LayerIO &io, int N) {
     if (l == E1A)
         NHIP(n, lbmnet::conv3x3_dw<float>(io.X, b.dz, N, cin, cout, b.partial, chunks, b.grad + P.woff[l], n->s));
     else if (mfma)
-        NHIP(n, lbmnet::conv3x3_dw_mfma(io.X, b.dz, N, cin, cout, b.partial, chunks, b.grad + P.woff[l], n->s));
+        NHIP(n, lbmnet::conv3x3_dw_mfma(io.X, b.dzh, N, cin, cout, b.partial, chunks, b.grad + P.woff[l], n->s));
     else
         NHIP(n, lbmnet::conv3x3_dw<TA>(io.X, b.dz, N, cin, cout, b.partial, chunks, b.grad + P.woff[l], n->s));
     NHIP(n, lbmnet::bias_grad(b.dz, N, cout, H * W, b.partial, b.grad + P.boff[l], n->s));

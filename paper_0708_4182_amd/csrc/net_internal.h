@@ -32,10 +32,11 @@ hipError_t conv3x3_mfma_dx(const View &dz, const float *w, const View &dx, int N
                            hipStream_t s);
 hipError_t flip_transpose(const float *w, float *wt, int cin, int cout, hipStream_t s);
 int dw_chunks(int N, int H, int W, int cin, int cout);
-// The weight gradient on matrix cores (bf16 activations x, dz rounded to bf16),
-// and its chunk count (partials hold chunks * cout * cin * 9 floats).
+// The weight gradient on matrix cores (bf16 activations x, the layer gradient
+// dz already rounded to bf16), and its chunk count (partials hold chunks *
+// cout * cin * 9 floats).
 int dw_chunks_mfma(int N, int H, int W, int cin, int cout);
-hipError_t conv3x3_dw_mfma(const View &x, const float *dz, int N, int cin, int cout, float *partial, int chunks,
+hipError_t conv3x3_dw_mfma(const View &x, const __bf16 *dz, int N, int cin, int cout, float *partial, int chunks,
                            float *dw, hipStream_t s);
 template <class TI>
 hipError_t conv3x3_dw(const View &x, const float *dz, int N, int cin, int cout, float *partial, int chunks,

@@ -213,11 +213,14 @@ __global__ void k_bias_final(const float *__restrict__ part, int C, float *__res
 
 // dz = g * (y > 0) (ReLU derivative from the stored output), dense fp32 out.
 template <class TA>
+// Elementwise kernels run on (pixel blocks, channel, sample) grids, so that a
+// thread finds its element without 64-bit divisions.
 __global__ void k_relu_mask(View g, View y, int N, int C, float *__restrict__ dz, __bf16 *__restrict__ dzh) {
-    const size_t HW = (size_t)y.H * y.W, per = (size_t)C * HW;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)N * per) return;
-    const size_t n = i / per, r = i % per;
+    const uint32_t HW = (uint32_t)y.H * (uint32_t)y.W;
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= HW) return;
+    const uint32_t c = blockIdx.y, n = blockIdx.z;
+    const size_t r = (size_t)c * HW + p, i = ((size_t)n * C + c) * HW + p;
     const float gv = static_cast<const float *>(g.p)[n * g.bs + r];
     const float yv = tof(static_cast<const TA *>(y.p)[n * y.bs + r]);
     const float v = yv > 0.f ? gv : 0.f;
@@ -228,50 +231,46 @@ __global__ void k_relu_mask(View g, View y, int N, int C, float *__restrict__ dz
 // ------------------------------------------------------ pool / upsample
 template <class TA>
 __global__ void k_pool(View in, View out, int N, int C) {
-    const int Ho = out.H, Wo = out.W;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)N * C * Ho * Wo) return;
-    const int x = i % Wo, y = (i / Wo) % Ho, c = (i / ((size_t)Wo * Ho)) % C;
-    const size_t n = i / ((size_t)C * Ho * Wo);
+    const uint32_t Ho = out.H, Wo = out.W;
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= Ho * Wo) return;
+    const uint32_t y = p / Wo, x = p - y * Wo, c = blockIdx.y, n = blockIdx.z;
     const TA *s = static_cast<const TA *>(in.p) + n * in.bs + (size_t)c * in.H * in.W;
     const float v = 0.25f * ((tof(s[(2 * y) * in.W + 2 * x]) + tof(s[(2 * y) * in.W + 2 * x + 1])) +
                              (tof(s[(2 * y + 1) * in.W + 2 * x]) + tof(s[(2 * y + 1) * in.W + 2 * x + 1])));
-    static_cast<TA *>(out.p)[n * out.bs + (size_t)c * Ho * Wo + (size_t)y * Wo + x] = fromf<TA>(v);
+    static_cast<TA *>(out.p)[n * out.bs + (size_t)c * Ho * Wo + p] = fromf<TA>(v);
 }
 
 // gradient of pool: dx (fine, fp32) += dy (coarse) / 4
 __global__ void k_pool_back_acc(View dy, View dx, int N, int C) {
-    const int H = dx.H, W = dx.W;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)N * C * H * W) return;
-    const int x = i % W, y = (i / W) % H, c = (i / ((size_t)W * H)) % C;
-    const size_t n = i / ((size_t)C * H * W);
+    const uint32_t H = dx.H, W = dx.W;
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= H * W) return;
+    const uint32_t y = p / W, x = p - y * W, c = blockIdx.y, n = blockIdx.z;
     const float g = static_cast<const float *>(dy.p)[n * dy.bs + (size_t)c * dy.H * dy.W + (size_t)(y / 2) * dy.W + x / 2];
-    static_cast<float *>(dx.p)[n * dx.bs + (size_t)c * H * W + (size_t)y * W + x] += 0.25f * g;
+    static_cast<float *>(dx.p)[n * dx.bs + (size_t)c * H * W + p] += 0.25f * g;
 }
 
 template <class TA>
 __global__ void k_up(View in, View out, int N, int C) {
-    const int H = out.H, W = out.W;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)N * C * H * W) return;
-    const int x = i % W, y = (i / W) % H, c = (i / ((size_t)W * H)) % C;
-    const size_t n = i / ((size_t)C * H * W);
-    static_cast<TA *>(out.p)[n * out.bs + (size_t)c * H * W + (size_t)y * W + x] =
+    const uint32_t H = out.H, W = out.W;
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= H * W) return;
+    const uint32_t y = p / W, x = p - y * W, c = blockIdx.y, n = blockIdx.z;
+    static_cast<TA *>(out.p)[n * out.bs + (size_t)c * H * W + p] =
         static_cast<const TA *>(in.p)[n * in.bs + (size_t)c * in.H * in.W + (size_t)(y / 2) * in.W + x / 2];
 }
 
 // gradient of upsample: dx (coarse, fp32) = sum of the 2x2 block of dy
 __global__ void k_up_back(View dy, View dx, int N, int C) {
-    const int Ho = dx.H, Wo = dx.W;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)N * C * Ho * Wo) return;
-    const int x = i % Wo, y = (i / Wo) % Ho, c = (i / ((size_t)Wo * Ho)) % C;
-    const size_t n = i / ((size_t)C * Ho * Wo);
+    const uint32_t Ho = dx.H, Wo = dx.W;
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= Ho * Wo) return;
+    const uint32_t y = p / Wo, x = p - y * Wo, c = blockIdx.y, n = blockIdx.z;
     const float *s = static_cast<const float *>(dy.p) + n * dy.bs + (size_t)c * dy.H * dy.W;
     const float v = (s[(2 * y) * dy.W + 2 * x] + s[(2 * y) * dy.W + 2 * x + 1]) +
                     (s[(2 * y + 1) * dy.W + 2 * x] + s[(2 * y + 1) * dy.W + 2 * x + 1]);
-    static_cast<float *>(dx.p)[n * dx.bs + (size_t)c * Ho * Wo + (size_t)y * Wo + x] = v;
+    static_cast<float *>(dx.p)[n * dx.bs + (size_t)c * Ho * Wo + p] = v;
 }
 
 // ---------------------------------------------------------- 1x1 output
@@ -537,8 +536,9 @@ __global__ void __launch_bounds__(256) k_conv3x3_mfma(View in, const __bf16 *__r
 }
 
 // Weight gradient on matrix cores (bf16 build, 3x3 layers after the first):
-// for each tap (dy, dx), dW[co][ci] = sum over pixels p of round_bf16(dz[co](p))
-// x[ci](p + (dy - 1, dx - 1)), a product with K = pixels.  A workgroup owns 32
+// for each tap (dy, dx), dW[co][ci] = sum over pixels p of dz[co](p)
+// x[ci](p + (dy - 1, dx - 1)), a product with K = pixels, where dz is the layer
+// gradient rounded to bf16 by k_relu_mask.  A workgroup owns 32
 // output x 32 input channels (a 2 x 2 grid of waves, 16 x 16 each, all nine
 // taps in 36 accumulation registers) and walks a chunk of 4 x 32 pixel tiles.
 // The lane's eight K values are eight consecutive pixels of one row, so the
@@ -563,7 +563,7 @@ __device__ __forceinline__ int dw_col(int tx0, int c, int W) {
     return col < W ? col : -1;
 }
 
-__global__ void __launch_bounds__(256) k_conv3x3_dw_mfma(View x, const float *__restrict__ dz, int N, int cin,
+__global__ void __launch_bounds__(256) k_conv3x3_dw_mfma(View x, const __bf16 *__restrict__ dz, int N, int cin,
                                                          int cout, int tiles_per_chunk, int vec,
                                                          float *__restrict__ partial) {
     __shared__ __attribute__((aligned(16))) __bf16 dzs[DM_CO * DM_DZS];
@@ -584,17 +584,16 @@ __global__ void __launch_bounds__(256) k_conv3x3_dw_mfma(View x, const float *__
         const int n = tile / (tiles_x * tiles_y), rem = tile % (tiles_x * tiles_y);
         const int ty0 = (rem / tiles_x) * DM_TR, tx0 = (rem % tiles_x) * DM_TW;
         const __bf16 *__restrict__ xin = static_cast<const __bf16 *>(x.p) + (size_t)n * x.bs;
-        const float *__restrict__ dzn = dz + (size_t)n * cout * H * W;
+        const __bf16 *__restrict__ dzn = dz + (size_t)n * cout * H * W;
         if (vec) {
-            // whole 32-pixel rows, 16-byte aligned: 4 dz values or 8 x values per load
-            for (int e = tid; e < DM_CO * DM_TR * (DM_TW / 4); e += 256) {
-                const int q = (e % (DM_TW / 4)) * 4, j = (e / (DM_TW / 4)) % DM_TR, o = e / (DM_TR * DM_TW / 4);
+            // whole 32-pixel rows, 16-byte aligned: 8 dz or x values per load
+            for (int e = tid; e < DM_CO * DM_TR * (DM_TW / 8); e += 256) {
+                const int q = (e % (DM_TW / 8)) * 8, j = (e / (DM_TW / 8)) % DM_TR, o = e / (DM_TR * DM_TW / 8);
                 const int y = ty0 + j;
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                bf16x8 v = bf16x8{zero, zero, zero, zero, zero, zero, zero, zero};
                 if (co0 + o < cout && y < H)
-                    v = *reinterpret_cast<const float4 *>(&dzn[(size_t)(co0 + o) * H * W + (size_t)y * W + tx0 + q]);
-                *reinterpret_cast<bf16x4 *>(&dzs[o * DM_DZS + j * DM_TW + q]) =
-                    bf16x4{(__bf16)v.x, (__bf16)v.y, (__bf16)v.z, (__bf16)v.w};
+                    v = *reinterpret_cast<const bf16x8 *>(&dzn[(size_t)(co0 + o) * H * W + (size_t)y * W + tx0 + q]);
+                *reinterpret_cast<bf16x8 *>(&dzs[o * DM_DZS + j * DM_TW + q]) = v;
             }
             for (int e = tid; e < DM_CI * (DM_TR + 2) * (DM_TW / 8); e += 256) {
                 const int q = (e % (DM_TW / 8)) * 8, r = (e / (DM_TW / 8)) % (DM_TR + 2), c = e / ((DM_TR + 2) * DM_TW / 8);
@@ -608,9 +607,9 @@ __global__ void __launch_bounds__(256) k_conv3x3_dw_mfma(View x, const float *__
             for (int e = tid; e < DM_CO * DM_PX; e += 256) {
                 const int o = e / DM_PX, p = e % DM_PX;
                 const int y = ty0 + p / DM_TW, xx = tx0 + p % DM_TW;
-                float v = 0.f;
+                __bf16 v = zero;
                 if (co0 + o < cout && y < H && xx < W) v = dzn[(size_t)(co0 + o) * H * W + (size_t)y * W + xx];
-                dzs[o * DM_DZS + p] = (__bf16)v;
+                dzs[o * DM_DZS + p] = v;
             }
             for (int e = tid; e < DM_CI * (DM_TR + 2) * DM_TW; e += 256) {
                 const int q = e % DM_TW, r = (e / DM_TW) % (DM_TR + 2), c = e / ((DM_TR + 2) * DM_TW);
@@ -665,6 +664,8 @@ __global__ void __launch_bounds__(256) k_conv3x3_dw_mfma(View x, const float *__
 }
 
 inline unsigned nblk(size_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+// (pixel blocks of 256, channel, sample) grid of the elementwise kernels
+inline dim3 pix_grid(int H, int W, int C, int N) { return dim3(nblk((size_t)H * W), (unsigned)C, (unsigned)N); }
 
 }  // namespace
 
@@ -745,7 +746,7 @@ int dw_chunks_mfma(int N, int H, int W, int cin, int cout) {
     return std::max(1, std::min(ntiles / 2, (1024 + blocks - 1) / blocks));
 }
 
-hipError_t conv3x3_dw_mfma(const View &x, const float *dz, int N, int cin, int cout, float *partial, int chunks,
+hipError_t conv3x3_dw_mfma(const View &x, const __bf16 *dz, int N, int cin, int cout, float *partial, int chunks,
                            float *dw, hipStream_t s) {
     const int ntiles = N * ((x.W + DM_TW - 1) / DM_TW) * ((x.H + DM_TR - 1) / DM_TR);
     const int per = (ntiles + chunks - 1) / chunks;
@@ -774,7 +775,7 @@ hipError_t bias_grad(const float *dz, int N, int C, int HW, float *part, float *
 
 template <class TA>
 hipError_t relu_mask(const View &g, const View &y, int N, int C, float *dz, __bf16 *dzh, hipStream_t s) {
-    k_relu_mask<TA><<<nblk((size_t)N * C * y.H * y.W), 256, 0, s>>>(g, y, N, C, dz, dzh);
+    k_relu_mask<TA><<<pix_grid(y.H, y.W, C, N), 256, 0, s>>>(g, y, N, C, dz, dzh);
     return hipGetLastError();
 }
 template hipError_t relu_mask<float>(const View &, const View &, int, int, float *, __bf16 *, hipStream_t);
@@ -782,27 +783,27 @@ template hipError_t relu_mask<__bf16>(const View &, const View &, int, int, floa
 
 template <class TA>
 hipError_t pool(const View &in, const View &out, int N, int C, hipStream_t s) {
-    k_pool<TA><<<nblk((size_t)N * C * out.H * out.W), 256, 0, s>>>(in, out, N, C);
+    k_pool<TA><<<pix_grid(out.H, out.W, C, N), 256, 0, s>>>(in, out, N, C);
     return hipGetLastError();
 }
 template hipError_t pool<float>(const View &, const View &, int, int, hipStream_t);
 template hipError_t pool<__bf16>(const View &, const View &, int, int, hipStream_t);
 
 hipError_t pool_back_acc(const View &dy, const View &dx, int N, int C, hipStream_t s) {
-    k_pool_back_acc<<<nblk((size_t)N * C * dx.H * dx.W), 256, 0, s>>>(dy, dx, N, C);
+    k_pool_back_acc<<<pix_grid(dx.H, dx.W, C, N), 256, 0, s>>>(dy, dx, N, C);
     return hipGetLastError();
 }
 
 template <class TA>
 hipError_t up(const View &in, const View &out, int N, int C, hipStream_t s) {
-    k_up<TA><<<nblk((size_t)N * C * out.H * out.W), 256, 0, s>>>(in, out, N, C);
+    k_up<TA><<<pix_grid(out.H, out.W, C, N), 256, 0, s>>>(in, out, N, C);
     return hipGetLastError();
 }
 template hipError_t up<float>(const View &, const View &, int, int, hipStream_t);
 template hipError_t up<__bf16>(const View &, const View &, int, int, hipStream_t);
 
 hipError_t up_back(const View &dy, const View &dx, int N, int C, hipStream_t s) {
-    k_up_back<<<nblk((size_t)N * C * dx.H * dx.W), 256, 0, s>>>(dy, dx, N, C);
+    k_up_back<<<pix_grid(dx.H, dx.W, C, N), 256, 0, s>>>(dy, dx, N, C);
     return hipGetLastError();
 }
 

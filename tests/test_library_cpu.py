@@ -198,7 +198,8 @@ def test_net_param_count_matches_the_network_definition(lib):
 
 
 @pytest.mark.parametrize("bad", [dict(H=12), dict(W=4), dict(batch=0), dict(cin=0),
-                                 dict(chans=(32, 0, 8, 8))])
+                                 dict(chans=(32, 0, 8, 8)), dict(batch=513), dict(chans=(32, 64, 128, 4096)),
+                                 dict(cout=3000)])
 def test_net_rejects_invalid_configs_without_gpu_work(lib, bad):
     from paper_0708_4182_amd import net
     cfg = dict(H=64, W=256, batch=2)
