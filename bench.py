@@ -242,8 +242,9 @@ def main():
         print(f"# batch: {bt['channels']} channels, {bt['nodes']} nodes, tile {bt['tile']}, "
               f"{bt['ms_per_step']*1e3:.1f} us/step", file=sys.stderr, flush=True)
         out["batch"] = {"workload": "256-channel sweep table (width 32-256, length 512-4096, "
-                                    "step height 0-8, f in [0,3e-3), G in [-5.5,-4.5]), FP16 storage, "
-                                    "one launch per step (a workgroup per tile), hipGraph of 10 steps",
+                                    "step height 0-8, f in [0,3e-3), G in [-5.5,-4.5]), FP16 storage with "
+                                    "stochastic rounding, one launch per step (a workgroup per tile), "
+                                    "hipGraph of 10 steps",
                         "mlups": round(bt["mlups"], 1), "ms_per_step": round(bt["ms_per_step"], 4),
                         "tile": bt["tile"],
                         "roofline": {"bound": "hbm", "achieved": round(bt["achieved_GBs"], 1),

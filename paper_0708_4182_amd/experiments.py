@@ -45,7 +45,7 @@ def flux_vs_field(nx=1024, ny=128, fs=(0.0, 5e-4, 1e-3, 1.5e-3, 2e-3), seed=0, s
             "steps": res.steps.tolist(), "converged": res.converged.tolist(), "seconds": dt}
 
 
-def sweep_throughput(n=256, seed=0, storage=1, steps=60, warmup=20, graph=10, tune=True, rounding=0):
+def sweep_throughput(n=256, seed=0, storage=1, steps=60, warmup=20, graph=10, tune=True, rounding=1):
     import torch
     rows = I.sweep_table(n, seed)
     cases = [I.sweep_case(r, storage=storage, rounding=rounding) for r in rows]
@@ -196,15 +196,18 @@ def net_throughput(batch=32, H=64, W=256, steps=50, warmup=5, seed=0):
     return out
 
 
-def sweep_steady(n=256, seed=0, storage=1, max_steps=200_000, check_every=200, window=2000, rtol=1e-8,
-                 rounding=0):
+def sweep_steady(n=256, seed=0, storage=1, max_steps=200_000, check_every=200, window=2000, rtol=None,
+                 rounding=1):
     """The 256-channel sweep table driven to steady flux in one batch (one
     launch per step, hipGraph of check_every steps, channels retired as they
-    converge): per-channel steps, lattice updates and wall time.  With nearest
-    rounding (the default) a 16-bit lattice settles on an exact fixed point,
-    which the rtol test detects, but that point carries the rounding bias;
-    stochastic rounding (rounding=1) removes the bias and leaves noise of
-    about 1e-4 in the flux, which a 1e-8 test never passes."""
+    converge): per-channel steps, lattice updates and wall time.  16-bit
+    channels use stochastic rounding by default: with nearest rounding a
+    16-bit lattice settles on an exact fixed point that carries the rounding
+    bias (on the first 32 channels of the table, fluxes 18% off the FP32 ones
+    at the median after 100,000 steps, against 2.5e-4 with stochastic
+    rounding).  Stochastic rounding leaves a small noise in the flux, so the
+    averaged steady rule applies (window means, rtol 1e-5); nearest rounding
+    and FP32 keep the plain rule at rtol 1e-8."""
     import torch
     rows = I.sweep_table(n, seed)
     cases = [I.sweep_case(r, storage=storage, rounding=rounding) for r in rows]
@@ -212,8 +215,11 @@ def sweep_steady(n=256, seed=0, storage=1, max_steps=200_000, check_every=200, w
     bx, r, us = b.autotune(reps=3)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    average = storage != 0 and rounding == 1
+    if rtol is None:
+        rtol = 1e-5 if average else 1e-8
     res = run_to_steady(b, check_every=check_every, window=window, rtol=rtol, max_steps=max_steps,
-                        log=lambda m: print("#", m, flush=True), log_every=20_000)
+                        log=lambda m: print("#", m, flush=True), log_every=20_000, average=average)
     wall = time.perf_counter() - t0
     from .warmstart import steady_time
     nodes = np.array([c.params.nx * c.params.ny for c in cases], np.float64)
@@ -221,7 +227,8 @@ def sweep_steady(n=256, seed=0, storage=1, max_steps=200_000, check_every=200, w
     conv = res.converged
     # the steady time of the warm-start comparison: within 1e-4 of the final flux for 5000 steps
     st = np.array([steady_time(res.history[i], res.Q[i]) for i in range(n)])
-    return {"experiment": "sweep_steady", "channels": n, "storage": storage, "rounding": rounding, "tile": [bx, r],
+    return {"experiment": "sweep_steady", "channels": n, "storage": storage, "rounding": rounding,
+            "steady_rule": {"rtol": rtol, "averaged": average}, "tile": [bx, r],
             "max_steps": max_steps, "converged": int(conv.sum()),
             "steps_median": float(np.median(res.steps)), "steps_max": int(res.steps.max()),
             "lattice_updates": res.node_updates, "wall_seconds": wall,

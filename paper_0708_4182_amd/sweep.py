@@ -3,6 +3,9 @@
 Advances an ``lbm.Batch`` in blocks of ``check_every`` steps, records the flux
 Q of eq. (11) of every channel after each block, and retires a channel once
 its flux has stopped changing: |Q(t) - Q(t - window)| <= rtol * |Q(t)|.
+With ``average`` (for 16-bit storage with stochastic rounding, whose flux keeps
+a small rounding noise) the mean of the records of the last window is compared
+with the mean of the window before, and that mean is the reported flux.
 All stepping and reductions run on the GPU; this module only decides when to
 stop and keeps the history.
 """
@@ -36,7 +39,7 @@ class SweepResult:
 
 def run_to_steady(batch, check_every: int = 100, window: int = 1000, rtol: float = 1e-8,
                   max_steps: int = 200_000, graph_steps: int | None = None,
-                  min_steps: int = 0, log=None, log_every: int = 5000) -> SweepResult:
+                  min_steps: int = 0, log=None, log_every: int = 5000, average: bool = False) -> SweepResult:
     """Step every channel of ``batch`` until its flux is steady (see module doc);
     ``log`` (if given) receives a progress line every ``log_every`` steps."""
     n = batch.n
@@ -61,14 +64,24 @@ def run_to_steady(batch, check_every: int = 100, window: int = 1000, rtol: float
             if not np.isfinite(Q[i]):
                 done[i] = True          # diverged: stop it, not converged
                 continue
-            if t >= min_steps and len(hist[i]) > lag:
+            if t < min_steps:
+                continue
+            if average:
+                if len(hist[i]) >= 2 * lag:
+                    new = float(np.mean([q for _, q in hist[i][-lag:]]))
+                    old = float(np.mean([q for _, q in hist[i][-2 * lag:-lag]]))
+                    if abs(new - old) <= rtol * abs(new):
+                        done[i] = True
+                        conv[i] = True
+            elif len(hist[i]) > lag:
                 q_old = hist[i][-1 - lag][1]
                 if abs(Q[i] - q_old) <= rtol * abs(Q[i]):
                     done[i] = True
                     conv[i] = True
         for i in np.nonzero(done)[0]:
             steps[i] = t
-            Qfin[i] = hist[i][-1][1]
+            last = [q for _, q in hist[i][-lag:]]
+            Qfin[i] = float(np.mean(last)) if average and conv[i] else hist[i][-1][1]
         if done.any():
             active &= ~done
             batch.retire(~active)
