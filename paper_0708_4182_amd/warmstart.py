@@ -11,7 +11,7 @@ the number of lattice updates until the flux of eq. (11) is steady:
   - a run is steady at the first check (every 100 steps) from which every check
     of the next 5000 steps lies within 1e-4 of Q_inf.
 
-Every warm-started run is judged against the cold start's Q_inf, so a poor
+Every warm-started run is measured against the cold start's Q_inf, so a poor
 prediction costs steps, never accuracy; a run that does not settle on Q_inf
 (another steady branch) is counted as a failure.  The lattice conserves mass,
 so the seeded density is scaled to the cold start's mass (otherwise the warm

@@ -4,7 +4,7 @@ The warm start must (a) fall back to the plain cold start, step for step,
 when the network's prediction is unusable (small 64 x 32 channels), and (b)
 after training on steady channels, reach the cold start's steady flux in fewer
 lattice updates on held-out seeds.  Q_inf and the cold steady times come from
-the plain lattice Boltzmann runs (the judge of every warm start)."""
+the plain lattice Boltzmann runs (the reference of every warm start)."""
 import numpy as np
 import pytest
 
