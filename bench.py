@@ -152,6 +152,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-ceiling", action="store_true")
+    ap.add_argument("--no-warm-start", action="store_true",
+                    help="skip the learned warm-start line (about 40 s: 2112 steady states, training, 64 seeds)")
     ap.add_argument("--no-network", action="store_true",
                     help="skip the warm-start network line (training and inference rate)")
     ap.add_argument("--no-small", action="store_true",
@@ -250,6 +252,28 @@ def main():
                         "roofline": {"bound": "hbm", "achieved": round(bt["achieved_GBs"], 1),
                                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                      "frac": round(bt["achieved_GBs"] / HBM_PEAK_GBS, 4)}}
+    if not args.no_warm_start:
+        import contextlib
+        from paper_0708_4182_amd import experiments
+        t0 = time.perf_counter()
+        with contextlib.redirect_stdout(sys.stderr):     # the experiment's progress lines
+            ws = experiments.warm_start(train=2048, test=64, epochs=10, modes="flow")
+        r = ws["results"][0]
+        out["warm_start"] = {
+            "workload": "learned warm start on 256x64 channels (step height 0-8, f in [0,3e-3), G in "
+                        "[-5.5,-4.5], g = 1e-6, FP32): network trained by the library's kernels on 2048 "
+                        "steady states the method generates (10 epochs), then 64 held-out seeds seeded from "
+                        "its prediction (flow mode) against cold starts; steady = within 1e-4 of the cold "
+                        "start's steady flux for 5000 steps",
+            "lattice_updates_warm_over_plain": round(r["updates_ratio_all_seeds"], 4),
+            "lattice_updates_warm_over_plain_steady_both": round(r["updates_ratio_steady_both"], 4),
+            "median_speedup": round(r["median_speedup"], 3),
+            "warm_failures": r["warm_failures"], "seeds": r["n"],
+            "surrogate_flux_error_median": round(r["surrogate_flux_error_median"], 5),
+            "train_seconds": round(ws["train_seconds"], 2),
+            "wall_seconds": round(time.perf_counter() - t0, 1),
+            "note": "a failure (another steady branch) is charged 100,000 steps in lattice_updates_warm_over_plain"}
+        print(f"# warm start: {out['warm_start']}", file=sys.stderr, flush=True)
     if not args.no_network:
         from paper_0708_4182_amd import experiments
         nt = experiments.net_throughput()

@@ -298,6 +298,13 @@ def warm_start(train=4096, test=512, nx=256, ny=64, epochs=30, batch=32, lr=1e-3
         stats, warm, sur, q_end = WS.warm_vs_cold(model, scales, cases[train:], data["Q"][train:],
                                                   data["cold"][train:], max_steps=max_steps, log=log,
                                                   pred=pred, mode=mode)
+        # lattice updates warm / cold (all channels have nx x ny nodes): over the seeds steady both
+        # ways, and over all seeds with a failed warm run charged max_steps
+        cold = np.asarray(data["cold"][train:], np.float64)
+        w = np.asarray(warm, np.float64)
+        both = w >= 0
+        stats["updates_ratio_steady_both"] = float(w[both].sum() / cold[both].sum()) if both.any() else None
+        stats["updates_ratio_all_seeds"] = float(np.where(both, w, max_steps).sum() / cold.sum())
         res["results"].append(stats)
         per_seed.update({f"warm_{mode}": warm, f"surrogate_{mode}": sur, f"Q_end_{mode}": q_end})
     if out:
