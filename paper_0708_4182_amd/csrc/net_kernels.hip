@@ -454,24 +454,27 @@ __global__ void k_pack_weights_flip(const float *__restrict__ w, __bf16 *__restr
 }
 
 // TI: input type (bf16 activations, or the FP32 layer gradient, rounded to
-// bf16 as it is staged); TO: output type; bias may be NULL.
-template <class TI, class TO>
+// bf16 as it is staged); TO: output type; bias may be NULL.  NM: 16-channel
+// output tiles per workgroup (4: 64 channels; 2: 32 channels, for the coarse
+// layers with at most 32 output channels).
+template <class TI, class TO, int NM>
 __global__ void __launch_bounds__(256) k_conv3x3_mfma(View in, const __bf16 *__restrict__ wp,
                                                       const float *__restrict__ bias, View out, int cin,
                                                       int cout, int cin_pad, int relu) {
+    constexpr int CO = 16 * NM;
     __shared__ __attribute__((aligned(16))) __bf16 xs[(MH + 2) * (MW + 2) * MPS];
-    __shared__ __attribute__((aligned(16))) __bf16 ws[9 * MCO * MPS];
+    __shared__ __attribute__((aligned(16))) __bf16 ws[9 * CO * MPS];
     const int H = in.H, W = in.W;
     const int tiles_x = (W + MW - 1) / MW;
     const int tx0 = (blockIdx.x % tiles_x) * MW, ty0 = (blockIdx.x / tiles_x) * MH;
-    const int ncob = (cout + MCO - 1) / MCO;
-    const int n = blockIdx.y / ncob, co0 = (blockIdx.y % ncob) * MCO;
+    const int ncob = (cout + CO - 1) / CO;
+    const int n = blockIdx.y / ncob, co0 = (blockIdx.y % ncob) * CO;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = (lane >> 4) * 8;
     const TI *__restrict__ xin = static_cast<const TI *>(in.p) + (size_t)n * in.bs;
-    f32x4 acc[4][4];
+    f32x4 acc[NM][4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < NM; ++m)
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[m][q] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int ci0 = 0; ci0 < cin; ci0 += MCI) {
@@ -492,34 +495,34 @@ __global__ void __launch_bounds__(256) k_conv3x3_mfma(View in, const __bf16 *__r
             }
             *reinterpret_cast<bf16x8 *>(&xs[(r * (MW + 2) + q) * MPS + 8 * c8]) = v;
         }
-        for (int e = tid; e < 9 * MCO * (MCI / 8); e += 256) {
-            const int c8 = e % (MCI / 8), co = (e / (MCI / 8)) % MCO, t = e / ((MCI / 8) * MCO);
+        for (int e = tid; e < 9 * CO * (MCI / 8); e += 256) {
+            const int c8 = e % (MCI / 8), co = (e / (MCI / 8)) % CO, t = e / ((MCI / 8) * CO);
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
             if (co0 + co < cout)
                 v = *reinterpret_cast<const uint4 *>(wp + ((size_t)t * cout + co0 + co) * cin_pad + ci0 + 8 * c8);
-            *reinterpret_cast<uint4 *>(&ws[(t * MCO + co) * MPS + 8 * c8]) = v;
+            *reinterpret_cast<uint4 *>(&ws[(t * CO + co) * MPS + 8 * c8]) = v;
         }
         __syncthreads();
 #pragma unroll 1
         for (int t = 0; t < 9; ++t) {
             const int dy = t / 3, dx = t % 3;
-            bf16x8 a[4];
+            bf16x8 a[NM];
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
-                a[m] = *reinterpret_cast<const bf16x8 *>(&ws[(t * MCO + 16 * m + lr) * MPS + lk]);
+            for (int m = 0; m < NM; ++m)
+                a[m] = *reinterpret_cast<const bf16x8 *>(&ws[(t * CO + 16 * m + lr) * MPS + lk]);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int pr = 2 * wave + (q >> 1), pc = (q & 1) * 16 + lr;
                 const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&xs[((pr + dy) * (MW + 2) + pc + dx) * MPS + lk]);
 #pragma unroll
-                for (int m = 0; m < 4; ++m) acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b, acc[m][q], 0, 0, 0);
+                for (int m = 0; m < NM; ++m) acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b, acc[m][q], 0, 0, 0);
             }
         }
         __syncthreads();
     }
     TO *__restrict__ yo = static_cast<TO *>(out.p) + (size_t)n * out.bs;
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < NM; ++m)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int y = ty0 + 2 * wave + (q >> 1), x = tx0 + (q & 1) * 16 + lr;
@@ -684,6 +687,11 @@ template hipError_t conv3x3<__bf16, __bf16>(const View &, const float *, const f
 
 int pad32(int c) { return (c + MCI - 1) / MCI * MCI; }
 
+// 32-channel output tiles for 32 or fewer output channels (a 64-channel tile
+// would spend half its products on padding); 64 otherwise.  (Also choosing 32
+// where 64-channel tiles give fewer than 1024 workgroups measured the same.)
+bool mfma_narrow(int cout) { return cout <= 32; }
+
 hipError_t conv3x3_mfma(const View &in, const float *w, const float *bias, const View &out, int N, int cin,
                         int cout, bool relu, __bf16 *wp, hipStream_t s) {
     const int cin_pad = pad32(cin);
@@ -691,8 +699,13 @@ hipError_t conv3x3_mfma(const View &in, const float *w, const float *bias, const
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int tiles = ((in.W + MW - 1) / MW) * ((in.H + MH - 1) / MH);
-    const dim3 grid(tiles, N * ((cout + MCO - 1) / MCO));
-    k_conv3x3_mfma<__bf16, __bf16><<<grid, 256, 0, s>>>(in, wp, bias, out, cin, cout, cin_pad, relu ? 1 : 0);
+    if (mfma_narrow(cout)) {
+        const dim3 grid(tiles, N * ((cout + 31) / 32));
+        k_conv3x3_mfma<__bf16, __bf16, 2><<<grid, 256, 0, s>>>(in, wp, bias, out, cin, cout, cin_pad, relu ? 1 : 0);
+    } else {
+        const dim3 grid(tiles, N * ((cout + MCO - 1) / MCO));
+        k_conv3x3_mfma<__bf16, __bf16, 4><<<grid, 256, 0, s>>>(in, wp, bias, out, cin, cout, cin_pad, relu ? 1 : 0);
+    }
     return hipGetLastError();
 }
 
@@ -705,8 +718,13 @@ hipError_t conv3x3_mfma_dx(const View &dz, const float *w, const View &dx, int N
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int tiles = ((dz.W + MW - 1) / MW) * ((dz.H + MH - 1) / MH);
-    const dim3 grid(tiles, N * ((cin + MCO - 1) / MCO));
-    k_conv3x3_mfma<__bf16, float><<<grid, 256, 0, s>>>(dz, wp, nullptr, dx, cout, cin, cout_pad, 0);
+    if (mfma_narrow(cin)) {
+        const dim3 grid(tiles, N * ((cin + 31) / 32));
+        k_conv3x3_mfma<__bf16, float, 2><<<grid, 256, 0, s>>>(dz, wp, nullptr, dx, cout, cin, cout_pad, 0);
+    } else {
+        const dim3 grid(tiles, N * ((cin + MCO - 1) / MCO));
+        k_conv3x3_mfma<__bf16, float, 4><<<grid, 256, 0, s>>>(dz, wp, nullptr, dx, cout, cin, cout_pad, 0);
+    }
     return hipGetLastError();
 }
 

@@ -118,6 +118,33 @@ def test_gradient_matches_oracle(net, bf16, tol):
         assert e[w] <= 2e-1, e
 
 
+# channel counts above 32 (the 64-channel output tile of the matrix-core
+# convolution; SMALL runs the 32-channel one), ragged against both tiles
+WIDE = dict(H=16, W=64, chans=(12, 40, 48, 36))
+
+
+@pytest.mark.parametrize("bf16,tol", [(False, 1e-5), (True, 1e-2)])
+def test_wide_channels_match_oracle(net, bf16, tol):
+    """Seed 26 keeps every pre-activation at least 1.6e-5 of its layer's rms
+    away from zero (the oracle finds that).  With seed 7 one lies at 1.4e-8 rms,
+    FP32 and FP64 put it on different sides of the ReLU, and the gradient of
+    the 2 x 8 bottom layers moves by 1.3e-2 (two samples of 16 pixels there)."""
+    x, t, fluid, specs, theta = problem(n=2, seed=26, **WIDE)
+    m = net.Net(WIDE["H"], WIDE["W"], 2, chans=WIDE["chans"], act_bf16=bf16)
+    m.set_params(theta)
+    xd, td, fd = to_dev(x, t, fluid)
+    y = m.forward(xd).cpu().numpy()
+    ref = CNN.forward(theta, specs, x.astype(np.float64), **ROUND[bf16])
+    e_fwd = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    loss, g = m.gradient(xd, td, fd)
+    args = (theta, specs, x.astype(np.float64), t.astype(np.float64), fluid.astype(bool))
+    ref_loss, ref_g = CNN.backward(*args, **ROUND[bf16], **GROUND[bf16])
+    errs = layer_errors(g.astype(np.float64), ref_g, specs)
+    worst = max(errs, key=errs.get)
+    print(f"wide channels bf16={bf16}: forward {e_fwd:.3e}, gradient worst {worst} {errs[worst]:.3e}")
+    assert e_fwd <= tol and abs(loss - ref_loss) <= tol * ref_loss and errs[worst] <= tol, errs
+
+
 def test_gradient_is_deterministic(net):
     x, t, fluid, specs, theta = problem(n=2, seed=3, **SMALL)
     m = net.Net(SMALL["H"], SMALL["W"], 2, chans=SMALL["chans"])
