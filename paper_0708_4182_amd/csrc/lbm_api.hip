@@ -31,6 +31,7 @@ struct lbm_sim {
     uint16_t *flags = nullptr;
     double *partials = nullptr;
     double *result = nullptr;
+    uint32_t *rowplain = nullptr;   // rows whose flag words are all plain (one bit per row)
     uint32_t *rng = nullptr;   // two-slot step counter of stochastic rounding
     uint32_t rng_host[2] = {0u, 0u};
     int cur = 0;
@@ -61,7 +62,7 @@ size_t elem_size(int storage) { return storage == LBM_F32 ? 4 : 2; }
 
 struct Layout {
     Grid g;
-    size_t buf_bytes, flags_off, flags_bytes, part_off, res_off, rng_off, total;
+    size_t buf_bytes, flags_off, flags_bytes, rowplain_off, part_off, res_off, rng_off, total;
     size_t buf_off[2];
 };
 
@@ -111,7 +112,8 @@ bool make_layout(const lbm_params *p, Layout &L) {
     L.buf_off[1] = L.buf_bytes;
     L.flags_off = 2 * L.buf_bytes;
     L.flags_bytes = align_up(plane * sizeof(uint16_t), kAlign);
-    L.part_off = L.flags_off + L.flags_bytes;
+    L.rowplain_off = L.flags_off + L.flags_bytes;
+    L.part_off = L.rowplain_off + align_up(sizeof(uint32_t) * (size_t)((p->ny + 31) / 32), kAlign);
     L.res_off = L.part_off + align_up(4 * sizeof(double) * (size_t)lbm::max_reduce_blocks(), kAlign);
     L.rng_off = L.res_off + kAlign;
     L.total = L.rng_off + kAlign;
@@ -283,6 +285,18 @@ float storage_offset_of(const lbm_params *p) { return storage_offset(p); }
 void derive_flags_of(const lbm_params *p, const uint8_t *solid, std::vector<uint16_t> &out) {
     derive_flags(p, solid, out);
 }
+// Bit y (word y / 32) set when every node of row y has the plain flag word:
+// 0 below ny / 2, FL_TOP from there (a fluid node with no solid neighbour
+// outside the electric layer).  The step kernel then skips that row's flags.
+void row_plain_mask(int nx, int ny, const std::vector<uint16_t> &fl, std::vector<uint32_t> &mask) {
+    mask.assign((size_t)(ny + 31) / 32, 0u);
+    for (int y = 0; y < ny; ++y) {
+        const uint16_t plain = (uint16_t)(y >= ny / 2 ? lbm::FL_TOP : 0u);
+        bool all = true;
+        for (int x = 0; x < nx && all; ++x) all = fl[(size_t)y * nx + x] == plain;
+        if (all) mask[(size_t)y / 32] |= 1u << (y % 32);
+    }
+}
 }  // namespace lbm
 
 extern "C" {
@@ -337,6 +351,7 @@ lbm_status lbm_init(lbm_sim **out, const lbm_params *p, const uint8_t *solid, co
     s->partials = (double *)(ws + L.part_off);
     s->result = (double *)(ws + L.res_off);
     s->rng = (uint32_t *)(ws + L.rng_off);
+    s->rowplain = (uint32_t *)(ws + L.rowplain_off);
 
     // flags, padded to the row pitch
     std::vector<uint16_t> fl;
@@ -366,6 +381,10 @@ lbm_status lbm_init(lbm_sim **out, const lbm_params *p, const uint8_t *solid, co
         }                                                                            \
     } while (0)
     INIT_TRY(hipMemcpyAsync(s->flags, padded.data(), padded.size() * sizeof(uint16_t),
+                            hipMemcpyHostToDevice, s->stream));
+    std::vector<uint32_t> plain_rows;
+    lbm::row_plain_mask(p->nx, p->ny, fl, plain_rows);
+    INIT_TRY(hipMemcpyAsync(s->rowplain, plain_rows.data(), plain_rows.size() * sizeof(uint32_t),
                             hipMemcpyHostToDevice, s->stream));
     INIT_TRY(lbm::launch_fill(s->buf[0], s->buf_bytes, s->stream));
     float *dstage = (float *)s->buf[1];
@@ -430,6 +449,7 @@ lbm::StepArgs step_args(lbm_sim *s) {
     }
     lbm::StepArgs a;
     a.flags = s->flags;
+    a.rowplain = s->rowplain;
     a.g = s->g;
     a.m = s->m;
     a.chunks = s->chunks;

@@ -27,6 +27,7 @@ std::string check_params_str(const lbm_params *p);
 Model make_model_of(const lbm_params *p);
 float storage_offset_of(const lbm_params *p);
 void derive_flags_of(const lbm_params *p, const uint8_t *solid, std::vector<uint16_t> &out);
+void row_plain_mask(int nx, int ny, const std::vector<uint16_t> &fl, std::vector<uint32_t> &mask);
 }  // namespace lbm
 
 namespace {
@@ -38,7 +39,7 @@ thread_local std::string g_batch_init_error;
 
 struct BatchLayout {
     std::vector<Grid> g;
-    std::vector<size_t> buf0, buf1, flags;
+    std::vector<size_t> buf0, buf1, flags, rowplain;
     size_t buf_bytes_max = 0;
     size_t descs, tiles, counters, ids, cur, out, rng, total;
     size_t max_tiles;
@@ -96,6 +97,8 @@ bool make_batch_layout(int n, const lbm_params *p, BatchLayout &L, std::string &
         off += align_up(bytes, kAlign);
         L.flags.push_back(off);
         off += align_up(plane * 2, kAlign);
+        L.rowplain.push_back(off);
+        off += align_up(4 * (size_t)((g.ny + 31) / 32), kAlign);
         L.max_tiles += tile_bound(p[i]);
         L.buf_bytes_max = std::max(L.buf_bytes_max, align_up(bytes, kAlign));
     }
@@ -130,6 +133,7 @@ struct lbm_batch {
     std::vector<ChannelDesc> desc;     // host mirror of the device table
     std::vector<char *> buf0, buf1;
     std::vector<uint16_t *> flags;
+    std::vector<uint32_t *> rowplain;
     ChannelDesc *d_desc = nullptr;
     uint32_t *d_tiles = nullptr;
     uint32_t *d_counters = nullptr;
@@ -368,6 +372,7 @@ lbm_status lbm_batch_init(lbm_batch **out, int32_t n, const lbm_params *p, const
         b->buf0.push_back(ws + L.buf0[i]);
         b->buf1.push_back(ws + L.buf1[i]);
         b->flags.push_back((uint16_t *)(ws + L.flags[i]));
+        b->rowplain.push_back((uint32_t *)(ws + L.rowplain[i]));
         ChannelDesc &d = b->desc[i];
         std::memset(&d, 0, sizeof d);
         d.g = L.g[i];
@@ -376,9 +381,11 @@ lbm_status lbm_batch_init(lbm_batch **out, int32_t n, const lbm_params *p, const
         d.buf[0] = b->buf0[i];
         d.buf[1] = b->buf1[i];
         d.flags = b->flags[i];
+        d.rowplain = b->rowplain[i];
     }
     // geometry and initial populations, one channel at a time (host staging reused)
     std::vector<uint16_t> fl, padded;
+    std::vector<uint32_t> plain_rows;
     std::vector<float> stage;
     for (int i = 0; i < n; ++i) {
         const Grid &g = L.g[i];
@@ -396,6 +403,10 @@ lbm_status lbm_batch_init(lbm_batch **out, int32_t n, const lbm_params *p, const
         }
         const size_t bb = 9 * (size_t)g.plane * elem_size(b->storage);
         hipError_t e = hipMemcpyAsync(b->flags[i], padded.data(), 2 * padded.size(), hipMemcpyHostToDevice, b->stream);
+        lbm::row_plain_mask(g.nx, g.ny, fl, plain_rows);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->rowplain[i], plain_rows.data(), 4 * plain_rows.size(), hipMemcpyHostToDevice,
+                               b->stream);
         if (e == hipSuccess) e = lbm::launch_fill(b->buf0[i], align_up(bb, 16), b->stream);
         float *dstage = (float *)b->buf1[i];
         if (e == hipSuccess)

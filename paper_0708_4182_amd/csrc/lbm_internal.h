@@ -48,6 +48,9 @@ struct StepArgs {
     int32_t chunks;
     int32_t ntiles;
     int32_t tiles_per_xcd;
+    // bit y of word y / 32: every node of row y has the plain flag word, 0 in
+    // the bottom half (y < ny / 2) and FL_TOP in the top half
+    const uint32_t *rowplain;
     // Stochastic rounding: two-slot step counter (slot par is this step's,
     // the kernel writes the next count to the other slot).
     uint32_t *rng;
@@ -62,6 +65,7 @@ struct ChannelDesc {
     int32_t pad;
     const void *buf[2];        // population buffers A and B
     const uint16_t *flags;
+    const uint32_t *rowplain;  // bit y: every node of row y has the plain flag word (see lbm_kernels.hip)
 };
 
 // Persistent batched step: workgroups take tiles from a queue (one counter

@@ -366,8 +366,8 @@ constexpr int RING = 4;
 
 template <int S, bool TRT = false, bool SR = false>
 __device__ __forceinline__ void step_tile(const void *src_ptr, void *dst_ptr, const uint16_t *flags_ptr,
-                                          const Grid &g, const Model &m, int x0, int y0, int y1, bool up,
-                                          float *ring, uint32_t mix = 0u) {
+                                          const uint32_t *__restrict__ rowplain, const Grid &g, const Model &m,
+                                          int x0, int y0, int y1, bool up, float *ring, uint32_t mix = 0u) {
     using C = Codec<S>;
     using T = typename C::T;
     const int BX = blockDim.x, W = BX + 2;
@@ -460,7 +460,38 @@ __device__ __forceinline__ void step_tile(const void *src_ptr, void *dst_ptr, co
             hraw = bload<T>(rs, off * E, 0u);
         }
     };
-    auto issue_flags = [&](int yr, uint32_t &fl, uint32_t &hfl) {
+    // FP32 storage: a row whose nodes all carry the plain flag word (fluid,
+    // no solid neighbour, outside the electric layer: 0, or FL_TOP in the top
+    // half) takes it from the row's bit instead of loading its flags (2 of
+    // the 74 bytes per node).  The bits of the 128 rows from the word holding
+    // row y0 - 1 are read once per tile into uniform registers, so the test
+    // per row is scalar arithmetic with no wait; rows outside that window,
+    // and the halo rows that wrap around the lattice, load their flags.  The
+    // 16-bit kernels measured no faster with it and keep the plain loads.
+    constexpr bool ROWBITS = S == ST_F32;
+    const int ubase = max(y0 - 1, 0) & ~31;
+    uint64_t plo = 0, phi = 0;
+    if constexpr (ROWBITS) {
+        const uint32_t nwords = ((uint32_t)ny + 31u) >> 5, w0 = (uint32_t)ubase >> 5;
+        uint32_t w[4];
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) w[k] = w0 + k < nwords ? rowplain[w0 + k] : 0u;
+        plo = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+        phi = (uint64_t)w[2] | ((uint64_t)w[3] << 32);
+    }
+    auto issue_flags = [&](int i, int yr, uint32_t &fl, uint32_t &hfl) {
+        if constexpr (ROWBITS) {
+            const int u = up ? y0 - 1 + i : y1 - i;   // the row before wrapping
+            const int d = u - ubase;
+            const bool plain = u >= 0 && u < ny && d >= 0 && d < 128 &&
+                               ((d < 64 ? plo >> d : phi >> (d - 64)) & 1u);   // uniform for the workgroup
+            if (plain) {
+                const uint32_t v = yr >= (ny >> 1) ? FL_TOP : 0u;
+                fl = v;
+                if (tid < 64) hfl = v;
+                return;
+            }
+        }
         const uint32_t r0b = (uint32_t)yr * pitch * 2u;
         fl = bload_flag(rf, vf, r0b);
         if (tid < 64) hfl = bload_flag(rf, (uint32_t)halo_x(opaque(tid)) * 2u, r0b);
@@ -469,8 +500,8 @@ __device__ __forceinline__ void step_tile(const void *src_ptr, void *dst_ptr, co
     // prologue: flags of rows 0 and 1, populations of row 0
     {
         uint32_t f0 = FL_SOLID, h0 = FL_SOLID;
-        issue_flags(row_at(0), f0, h0);
-        issue_flags(row_at(1), fl2, hfl2);
+        issue_flags(0, row_at(0), f0, h0);
+        issue_flags(1, row_at(1), fl2, hfl2);
         issue_pops(row_at(0), f0, h0);
         fl1 = f0;
         hfl1 = h0;
@@ -488,7 +519,7 @@ __device__ __forceinline__ void step_tile(const void *src_ptr, void *dst_ptr, co
         hfl1 = hfl2;
         // past the end of the chunk the last row is fetched again (cache hits),
         // which keeps the pipeline free of branches
-        issue_flags(row_at(min(i + 2, nrows - 1)), fl2, hfl2);
+        issue_flags(min(i + 2, nrows - 1), row_at(min(i + 2, nrows - 1)), fl2, hfl2);
         issue_pops(row_at(min(i + 1, nrows - 1)), fl1, hfl1);
 
         float *slot = ring + (i & (RING - 1)) * W;
@@ -539,7 +570,7 @@ __device__ __forceinline__ void step_tiles(const StepArgs &a, float *ring) {
     const int strip = tile / a.chunks, chunk = tile - strip * a.chunks;
     const int y0 = (int)(((int64_t)chunk * a.g.ny) / a.chunks);
     const int y1 = (int)(((int64_t)(chunk + 1) * a.g.ny) / a.chunks);
-    step_tile<S, TRT, SR>(a.src, a.dst, a.flags, a.g, a.m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0,
+    step_tile<S, TRT, SR>(a.src, a.dst, a.flags, a.rowplain, a.g, a.m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0,
                           ring, mix);
 }
 
@@ -1261,7 +1292,7 @@ __global__ void __launch_bounds__(512) k_batch_step(const ChannelDesc *__restric
         const int strip = local / chunks, chunk = local - strip * chunks;
         const int y0 = (int)(((int64_t)chunk * g.ny) / chunks);
         const int y1 = (int)(((int64_t)(chunk + 1) * g.ny) / chunks);
-        step_tile<S, TRT, SR>(src, dst, d->flags, g, m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring,
+        step_tile<S, TRT, SR>(src, dst, d->flags, d->rowplain, g, m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring,
                               mix);
     }
 }
@@ -1289,7 +1320,8 @@ __global__ void __launch_bounds__(512) k_batch_tiles(const ChannelDesc *__restri
     const int strip = local / chunks, chunk = local - strip * chunks;
     const int y0 = (int)(((int64_t)chunk * g.ny) / chunks);
     const int y1 = (int)(((int64_t)(chunk + 1) * g.ny) / chunks);
-    step_tile<S, TRT, SR>(src, dst, d->flags, g, m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring, mix);
+    step_tile<S, TRT, SR>(src, dst, d->flags, d->rowplain, g, m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0, ring,
+                          mix);
 }
 
 // Per-channel FP64 flux/mass reduction: one workgroup per channel, rows in
