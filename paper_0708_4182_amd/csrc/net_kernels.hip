@@ -760,8 +760,10 @@ template hipError_t conv3x3_dw<__bf16>(const View &, const float *, int, int, in
 int dw_chunks_mfma(int N, int H, int W, int cin, int cout) {
     const int ntiles = N * ((W + DM_TW - 1) / DM_TW) * ((H + DM_TR - 1) / DM_TR);
     const int blocks = ((cout + DM_CO - 1) / DM_CO) * ((cin + DM_CI - 1) / DM_CI);
-    // about 1024 workgroups (four fit a compute unit), at least 2 tiles per chunk
-    return std::max(1, std::min(ntiles / 2, (1024 + blocks - 1) / blocks));
+    // about 512 workgroups, at least 2 tiles per chunk: fewer chunk partials for
+    // k_sum_partials to read (training measured 3.75 ms per batch with 1024,
+    // 3.56 with 512, 3.74 with 256)
+    return std::max(1, std::min(ntiles / 2, (512 + blocks - 1) / blocks));
 }
 
 hipError_t conv3x3_dw_mfma(const View &x, const __bf16 *dz, int N, int cin, int cout, float *partial, int chunks,
