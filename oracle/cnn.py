@@ -19,25 +19,29 @@ channels (the upsampled tensor first).  Loss: mean over fluid nodes and
 output channels of (y - t)^2.  Parameters are one flat vector: for every layer
 in the order above, W[cout][cin][kh][kw] then b[cout].
 
-Plain loops over channels with numpy slicing over pixels: obviously correct,
-slow, FP64.  The gradients are checked against finite differences in
-tests/test_cnn_oracle.py.
+A 3x3 convolution is written as its definition, a sum over the nine taps
+(ky, kx) of channel contractions of the shifted input, each contraction a
+numpy einsum; every other layer is a numpy expression of its formula.  FP64
+throughout.  The gradients are checked against finite differences and a
+brute-force convolution in tests/test_cnn_oracle.py.
 
-Stored activations in bf16 (the production setting) are defined as the same
-network with every stored activation (each conv + ReLU output and each pooled
-tensor; upsampling and concatenation only move stored values) rounded to the
-nearest bf16 value, ties to even, and the gradient passed through the rounding
-unchanged.  ``forward``/``backward`` take that rounding as ``act=round_bf16``.
-The production build also multiplies on bf16 matrix cores in the forward 3x3
-convolutions after the first, with the weights rounded to bf16 there; that is
-``wround=round_bf16``: those forward convolutions use rounded weights, and the
-backward pass uses the unrounded weights (the gradient passes the weight
-rounding unchanged too).  Its backward contractions of the 3x3 layers after
-the first (input gradient and weight gradient) also run on bf16 matrix cores,
-with the layer gradient rounded to bf16 in both and the weights in the input
-gradient:
-``ground=round_bf16`` in ``backward`` (the bias gradient sums the unrounded
-layer gradient).
+Stored activations in bf16 (the production setting: FP32 weights, bf16
+activations) are defined as the same network with every stored activation
+(each conv + ReLU output and each pooled tensor; upsampling and concatenation
+only move stored values) rounded to the nearest bf16 value, ties to even, and
+the gradient passed through the rounding unchanged: ``act=round_bf16``.
+
+Error model of a bf16 build (``mca_gradient``): Monte Carlo arithmetic
+(D. S. Parker, "Monte Carlo Arithmetic", 1997).  Every tensor such a build may
+hold in 16 bits -- the weights, every stored activation and every layer
+gradient that enters a contraction -- is multiplied elementwise by 1 + d with
+d independent and uniform on [-u, u], u = 2^-8 (the unit roundoff of an 8-bit
+significand), and the network is evaluated in FP64.  The spread of a few such
+samples around the FP64 network estimates the size of the error that bf16
+storage causes, without reference to where a particular implementation rounds.
+The model is wider than round-to-nearest: its relative variance u^2/3 is about
+1.8 times that of rounding values whose significands are spread uniformly in
+log scale.
 """
 from __future__ import annotations
 
@@ -92,53 +96,51 @@ def _identity(a):
 
 
 # ------------------------------------------------------------------ layers
-def conv(x, W, b):
-    """x [N][ci][H][W] -> [N][co][H][W]; 3x3 periodic in x, zero in y, or 1x1."""
+def _pad(x):
+    """One-node halo: periodic along x (columns), zero along y (rows)."""
     N, ci, H, Wd = x.shape
-    co, _, k, _ = W.shape
-    y = np.zeros((N, co, H, Wd))
-    if k == 1:
-        for o in range(co):
-            y[:, o] = b[o] + np.einsum("c,nchw->nhw", W[o, :, 0, 0], x)
-        return y
     xp = np.zeros((N, ci, H + 2, Wd + 2))
     xp[:, :, 1:-1, 1:-1] = x
     xp[:, :, 1:-1, 0] = x[:, :, :, -1]
     xp[:, :, 1:-1, -1] = x[:, :, :, 0]
-    for o in range(co):
-        acc = np.full((N, H, Wd), b[o])
-        for c in range(ci):
-            for ky in range(3):
-                for kx in range(3):
-                    acc += W[o, c, ky, kx] * xp[:, c, ky:ky + H, kx:kx + Wd]
-        y[:, o] = acc
+    return xp
+
+
+def conv(x, W, b):
+    """x [N][ci][H][W] -> [N][co][H][W]; 3x3 periodic in x, zero in y, or 1x1:
+    y[n,o,i,j] = b[o] + sum over c, ky, kx of W[o,c,ky,kx] x[n,c,i+ky-1,j+kx-1]."""
+    N, ci, H, Wd = x.shape
+    co, _, k, _ = W.shape
+    y = np.empty((N, co, H, Wd))
+    y[:] = b[None, :, None, None]
+    if k == 1:
+        y += np.einsum("oc,nchw->nohw", W[:, :, 0, 0], x, optimize=True)
+        return y
+    xp = _pad(x)
+    for ky in range(3):
+        for kx in range(3):
+            y += np.einsum("oc,nchw->nohw", W[:, :, ky, kx], xp[:, :, ky:ky + H, kx:kx + Wd], optimize=True)
     return y
 
 
-def conv_backward(x, W, dy, dxr=None):
-    """Gradients (dx, dW, db) of conv for upstream dy; with ``dxr`` both
-    contractions of a 3x3 layer take dxr(dy), and the input gradient also
-    dxr(W) (the bias gradient keeps dy as it is)."""
+def conv_backward(x, W, dy):
+    """Gradients (dx, dW, db) of conv for the upstream gradient dy:
+    db[o] = sum dy[n,o,i,j]; dW[o,c,ky,kx] = sum dy[n,o,i,j] x[n,c,i+ky-1,j+kx-1];
+    dx is the adjoint of the tap sum (scattered back through the halo)."""
     N, ci, H, Wd = x.shape
     co, _, k, _ = W.shape
     db = dy.sum(axis=(0, 2, 3))
     if k == 1:
-        dW = np.einsum("nohw,nchw->oc", dy, x)[:, :, None, None]
-        dx = np.einsum("oc,nohw->nchw", W[:, :, 0, 0], dy)
+        dW = np.einsum("nohw,nchw->oc", dy, x, optimize=True)[:, :, None, None]
+        dx = np.einsum("oc,nohw->nchw", W[:, :, 0, 0], dy, optimize=True)
         return dx, dW, db
-    xp = np.zeros((N, ci, H + 2, Wd + 2))
-    xp[:, :, 1:-1, 1:-1] = x
-    xp[:, :, 1:-1, 0] = x[:, :, :, -1]
-    xp[:, :, 1:-1, -1] = x[:, :, :, 0]
-    dyx, Wx = (dy, W) if dxr is None else (dxr(dy), dxr(W))
-    dW = np.zeros_like(W)
+    xp = _pad(x)
+    dW = np.empty_like(W)
     dxp = np.zeros_like(xp)
-    for o in range(co):
-        for c in range(ci):
-            for ky in range(3):
-                for kx in range(3):
-                    dW[o, c, ky, kx] = (dyx[:, o] * xp[:, c, ky:ky + H, kx:kx + Wd]).sum()
-                    dxp[:, c, ky:ky + H, kx:kx + Wd] += Wx[o, c, ky, kx] * dyx[:, o]
+    for ky in range(3):
+        for kx in range(3):
+            dW[:, :, ky, kx] = np.einsum("nohw,nchw->oc", dy, xp[:, :, ky:ky + H, kx:kx + Wd], optimize=True)
+            dxp[:, :, ky:ky + H, kx:kx + Wd] += np.einsum("oc,nohw->nchw", W[:, :, ky, kx], dy, optimize=True)
     dx = dxp[:, :, 1:-1, 1:-1].copy()
     dx[:, :, :, -1] += dxp[:, :, 1:-1, 0]      # the left pad was column W-1
     dx[:, :, :, 0] += dxp[:, :, 1:-1, -1]      # the right pad was column 0
@@ -168,20 +170,15 @@ def up_backward(dy):
 
 
 # ----------------------------------------------------------------- network
-def forward(theta, specs, x, keep=False, act=_identity, wround=_identity):
-    """Network output; ``act`` rounds every stored activation and ``wround``
-    the weights of the forward 3x3 convolutions after the first (identity:
-    FP64 throughout)."""
+def forward(theta, specs, x, keep=False, act=_identity):
+    """Network output; ``act`` is applied to every stored activation (identity:
+    FP64 throughout; ``round_bf16``: bf16 activations)."""
     P = unpack(theta, specs)
     cache = {}
 
-    def cv(name, inp):
-        W, b = P[name]
-        return conv(inp, W if name == specs[0][0] else wround(W), b)
-
     def block(name_a, name_b, inp):
-        za = cv(name_a, inp); ya = act(relu(za))
-        zb = cv(name_b, ya); yb = act(relu(zb))
+        za = conv(inp, *P[name_a]); ya = act(relu(za))
+        zb = conv(ya, *P[name_b]); yb = act(relu(zb))
         cache[name_a] = (inp, za); cache[name_b] = (ya, zb)
         return yb
 
@@ -211,28 +208,28 @@ def loss_grad(y, t, fluid):
     return 2.0 * (y - t) * m / cnt
 
 
-def backward(theta, specs, x, t, fluid, act=_identity, wround=_identity, ground=None):
-    """(loss, gradient of the loss with respect to theta); with ``act`` and
-    ``wround`` the gradient passes through both roundings unchanged; with
-    ``ground`` both backward contractions of every 3x3 layer after the first
-    take the rounded layer gradient and the input gradient also the rounded
-    weights (the bf16 build runs them on matrix cores)."""
-    y, cache = forward(theta, specs, x, keep=True, act=act, wround=wround)
+def backward(theta, specs, x, t, fluid, act=_identity, gact=_identity, with_output=False):
+    """(loss, gradient of the loss with respect to theta), and the network
+    output as a third item with ``with_output``.  The gradient passes ``act``
+    unchanged; ``gact`` is applied to the layer gradient (dL/dz of a layer,
+    after the ReLU mask) that enters each layer's weight-, bias- and
+    input-gradient contractions (identity: FP64 throughout)."""
+    y, cache = forward(theta, specs, x, keep=True, act=act)
     P = unpack(theta, specs)
     grads = {}
-    dy = loss_grad(y, t, fluid)
+    dy = gact(loss_grad(y, t, fluid))
     d1_in, _ = cache["out"]
     dd1, dW, db = conv_backward(d1_in, P["out"][0], dy)
     grads["out"] = (dW, db)
 
     def block_back(name_a, name_b, dout):
         ya, zb = cache[name_b]
-        dzb = dout * (zb > 0)
-        dya, dW, db = conv_backward(ya, P[name_b][0], dzb, ground)
+        dzb = gact(dout * (zb > 0))
+        dya, dW, db = conv_backward(ya, P[name_b][0], dzb)
         grads[name_b] = (dW, db)
         inp, za = cache[name_a]
-        dza = dya * (za > 0)
-        dinp, dW, db = conv_backward(inp, P[name_a][0], dza, ground if name_a != specs[0][0] else None)
+        dza = gact(dya * (za > 0))
+        dinp, dW, db = conv_backward(inp, P[name_a][0], dza)
         grads[name_a] = (dW, db)
         return dinp
 
@@ -255,7 +252,34 @@ def backward(theta, specs, x, t, fluid, act=_identity, wround=_identity, ground=
     for name, *_ in specs:
         flat.append(grads[name][0].ravel())
         flat.append(grads[name][1].ravel())
+    if with_output:
+        return loss(y, t, fluid), np.concatenate(flat), y
     return loss(y, t, fluid), np.concatenate(flat)
+
+
+def weight_mask(specs):
+    """Boolean mask over theta: True on weights, False on biases."""
+    parts = []
+    for _, ci, co, k in specs:
+        parts.append(np.ones(co * ci * k * k, bool))
+        parts.append(np.zeros(co, bool))
+    return np.concatenate(parts)
+
+
+def mca_gradient(theta, specs, x, t, fluid, rng, u=2.0 ** -8):
+    """One Monte Carlo arithmetic sample of a bf16 build (module docstring):
+    returns (output, loss, gradient) of the FP64 network whose weights, stored
+    activations and layer gradients each carry an independent relative error
+    uniform on [-u, u].  u = 0 gives the FP64 network exactly."""
+    def perturb(a):
+        a = np.asarray(a, np.float64)
+        return a * (1.0 + rng.uniform(-u, u, a.shape))
+
+    th = theta.copy()
+    w = weight_mask(specs)
+    th[w] = perturb(theta[w])
+    L, g, y = backward(th, specs, x, t, fluid, act=perturb, gact=perturb, with_output=True)
+    return y, L, g
 
 
 def adam(theta, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

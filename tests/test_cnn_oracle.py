@@ -114,40 +114,11 @@ def test_rounded_network_is_close_and_identity_is_default():
     assert 1e-5 < err < 5e-2          # rounding is applied, and it is a small perturbation
 
 
-def test_weight_rounding_applies_to_the_inner_3x3_layers_only():
-    """wround rounds exactly the forward 3x3 convolutions after the first:
-    the same as pre-rounding those weights by hand."""
-    specs = cnn.layer_specs(chans=(3, 4, 4, 5))
-    theta = cnn.init_params(specs, seed=6)
-    x = np.random.default_rng(7).standard_normal((1, 3, 8, 16))
-    y0 = cnn.forward(theta, specs, x)
-    assert np.array_equal(y0, cnn.forward(theta, specs, x, wround=lambda w: w))
-    manual, o = theta.copy(), 0
-    for i, (name, ci, co, k) in enumerate(specs):
-        n = co * ci * k * k
-        if i > 0 and k == 3:
-            manual[o:o + n] = cnn.round_bf16(theta[o:o + n])
-        o += n + co
-    y1 = cnn.forward(theta, specs, x, wround=cnn.round_bf16)
-    np.testing.assert_array_equal(y1, cnn.forward(manual, specs, x))
-    assert not np.array_equal(y1, y0)
-    # the backward pass differentiates with the unrounded weights
-    t = np.zeros_like(y0)
-    fluid = np.ones((1, 8, 16), bool)
-    _, g1 = cnn.backward(theta, specs, x, t, fluid, wround=cnn.round_bf16)
-    _, g2 = cnn.backward(manual, specs, x, t, fluid)
-    rel = np.linalg.norm(g1 - g2) / np.linalg.norm(g2)
-    assert 0 < rel < 2e-2          # differs only through the 2^-9 weight rounding in dx
-
-
-def test_backward_rounding_hook():
-    """ground rounds the layer gradient in the 3x3 layers' weight- and
-    input-gradient contractions and the weights in the input gradient:
-    identity leaves the gradient unchanged; rounding keeps the output layer's
-    gradients and every bias gradient of the last 3x3 layer (their inputs are
-    not rounded), and moves the other gradients by about the bf16 rounding;
-    the last 3x3 layer's weight gradient equals the one formed by hand from
-    the rounded layer gradient."""
+def test_layer_gradient_hook():
+    """gact acts on the layer gradient that enters each layer's contractions:
+    identity leaves the gradient unchanged; with rounding, the last 3x3 layer's
+    weight and bias gradients equal those formed by hand from the rounded layer
+    gradient, and every block moves by about the bf16 rounding."""
     specs = cnn.layer_specs(chans=(3, 4, 4, 5))
     theta = cnn.init_params(specs, seed=8)
     rng = np.random.default_rng(9)
@@ -155,28 +126,87 @@ def test_backward_rounding_hook():
     t = rng.standard_normal((2, 3, 8, 16))
     fluid = rng.random((2, 8, 16)) > 0.2
     _, g0 = cnn.backward(theta, specs, x, t, fluid)
-    _, gi = cnn.backward(theta, specs, x, t, fluid, ground=lambda a: a)
+    _, gi = cnn.backward(theta, specs, x, t, fluid, gact=lambda a: a)
     assert np.array_equal(g0, gi)
-    _, g1 = cnn.backward(theta, specs, x, t, fluid, ground=cnn.round_bf16)
+    _, g1 = cnn.backward(theta, specs, x, t, fluid, gact=cnn.round_bf16)
     o = 0
     for name, ci, co, k in specs:
-        nw = co * ci * k * k
-        aw, bw = g0[o:o + nw], g1[o:o + nw]
-        ab, bb = g0[o + nw:o + nw + co], g1[o + nw:o + nw + co]
-        if name == "out":
-            assert np.array_equal(aw, bw) and np.array_equal(ab, bb)
-        else:
-            rel = np.linalg.norm(aw - bw) / np.linalg.norm(aw)
-            assert 0 < rel < 2e-2, (name, rel)
-        if name == "d1b":
-            assert np.array_equal(ab, bb)
-        o += nw + co
-    # d1b by hand: its layer gradient is (dL/d output of d1b) * relu'(z)
+        n = co * ci * k * k + co
+        rel = np.linalg.norm(g0[o:o + n] - g1[o:o + n]) / np.linalg.norm(g0[o:o + n])
+        assert 0 < rel < 5e-2, (name, rel)
+        o += n
+    # d1b by hand: its layer gradient is (dL/d output of d1b) * relu'(z), where
+    # dL/d output comes from the output layer fed the rounded loss gradient
     y, cache = cnn.forward(theta, specs, x, keep=True)
     P = cnn.unpack(theta, specs)
-    dd1, _, _ = cnn.conv_backward(cache["out"][0], P["out"][0], cnn.loss_grad(y, t, fluid))
+    dd1, _, _ = cnn.conv_backward(cache["out"][0], P["out"][0], cnn.round_bf16(cnn.loss_grad(y, t, fluid)))
     ya, zb = cache["d1b"]
-    _, dW, _ = cnn.conv_backward(ya, P["d1b"][0], cnn.round_bf16(dd1 * (zb > 0)))
+    _, dW, db = cnn.conv_backward(ya, P["d1b"][0], cnn.round_bf16(dd1 * (zb > 0)))
     names = [nm for nm, *_ in specs]
     o = sum(co_ * ci_ * k_ * k_ + co_ for _, ci_, co_, k_ in specs[:names.index("d1b")])
-    np.testing.assert_allclose(g1[o:o + dW.size], dW.ravel(), rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(g1[o:o + dW.size], dW.ravel())
+    np.testing.assert_array_equal(g1[o + dW.size:o + dW.size + db.size], db)
+
+
+def test_mca_sample_is_the_network_at_u0_and_scales_with_u():
+    """Monte Carlo arithmetic: u = 0 is the FP64 network exactly; the spread
+    of the perturbed outputs is linear in u (first-order error propagation),
+    so halving u halves their rms error.  The gradient is not continuous where
+    a perturbation moves a pre-activation across zero (its ReLU branch flips),
+    which happens at u = 2^-8 in a network this small, so for the gradient
+    only the size of the spread is checked."""
+    specs = cnn.layer_specs(chans=(3, 4, 4, 5))
+    theta = cnn.init_params(specs, seed=10)
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal((2, 3, 8, 16))
+    t = rng.standard_normal((2, 3, 8, 16))
+    fluid = rng.random((2, 8, 16)) > 0.2
+    L0, g0, y0 = cnn.backward(theta, specs, x, t, fluid, with_output=True)
+    y, L, g = cnn.mca_gradient(theta, specs, x, t, fluid, np.random.default_rng(0), u=0.0)
+    assert np.array_equal(y, y0) and L == L0 and np.array_equal(g, g0)
+
+    def rms(u, n=8):
+        r = np.random.default_rng(1)
+        ey, eg = [], []
+        for _ in range(n):
+            y, _, g = cnn.mca_gradient(theta, specs, x, t, fluid, r, u=u)
+            ey.append(np.linalg.norm(y - y0) / np.linalg.norm(y0))
+            eg.append(np.linalg.norm(g - g0) / np.linalg.norm(g0))
+        return np.sqrt(np.mean(np.square(ey))), np.sqrt(np.mean(np.square(eg)))
+
+    ya, ga = rms(2.0 ** -8)
+    yb, gb = rms(2.0 ** -9)
+    assert 1e-4 < ya < 5e-2 and 1e-4 < ga < 2e-1
+    assert 1.6 < ya / yb < 2.5
+
+
+def test_mca_perturbation_is_relative_and_uniform():
+    """Each perturbed value is a (1 + d) with |d| <= u, d of mean 0 and
+    variance u^2 / 3 (uniform on [-u, u]); weights are perturbed, biases not."""
+    specs = cnn.layer_specs(chans=(3, 4, 4, 5))
+    theta = cnn.init_params(specs, seed=12)
+    b = ~cnn.weight_mask(specs)
+    theta[b] = 0.1
+    u = 2.0 ** -8
+    seen = []
+
+    def spy(th, sp, xx, tt, ff, act, gact, with_output):
+        seen.append(th.copy())
+        a = np.linspace(1.0, 2.0, 200001)
+        d = act(a) / a - 1.0
+        assert np.abs(d).max() <= u
+        assert abs(d.mean()) < 4 * u / np.sqrt(3 * a.size)
+        assert abs(d.var() / (u * u / 3) - 1) < 0.02
+        return 0.0, np.zeros_like(th), np.zeros((1,))
+
+    orig = cnn.backward
+    try:
+        cnn.backward = spy
+        cnn.mca_gradient(theta, specs, None, None, None, np.random.default_rng(3), u=u)
+    finally:
+        cnn.backward = orig
+    th = seen[0]
+    w = cnn.weight_mask(specs)
+    d = th[w] / theta[w] - 1.0
+    assert np.abs(d).max() <= u and np.abs(d).max() > 0.5 * u
+    assert np.array_equal(th[b], theta[b])
