@@ -33,13 +33,20 @@ def contour_points(rho: np.ndarray, level: float, fluid: np.ndarray | None = Non
 
 
 def fit_circle(pts: np.ndarray):
-    """Kasa algebraic circle fit: returns (xc, yc, R)."""
+    """Kasa algebraic circle fit: returns (xc, yc, R).  Raises ValueError when
+    the points do not determine a circle (fewer than 5, or a fit whose R^2 is
+    not positive and finite)."""
+    if len(pts) < 5:
+        raise ValueError(f"circle fit needs at least 5 contour points, got {len(pts)}")
     x, y = pts[:, 0], pts[:, 1]
     A = np.stack([x, y, np.ones_like(x)], 1)
     rhs = -(x * x + y * y)
     (D, E, F), *_ = np.linalg.lstsq(A, rhs, rcond=None)
     xc, yc = -D / 2, -E / 2
-    return xc, yc, float(np.sqrt(xc * xc + yc * yc - F))
+    r2 = xc * xc + yc * yc - F
+    if not (np.isfinite(r2) and r2 > 0):
+        raise ValueError(f"degenerate circle fit (R^2 = {r2})")
+    return xc, yc, float(np.sqrt(r2))
 
 
 def contact_angle(rho: np.ndarray, fluid: np.ndarray, level: float = 1.0,
@@ -47,7 +54,9 @@ def contact_angle(rho: np.ndarray, fluid: np.ndarray, level: float = 1.0,
     """Contact angle (radians) of a droplet sitting on the bottom wall.
 
     Returns (theta, (xc, yc, R)).  ``y_max`` bounds the contour points from
-    above (to exclude a film on the top wall).
+    above (to exclude a film on the top wall).  Raises ValueError if the
+    contour left after dropping the near-wall points does not determine a
+    circle (e.g. a droplet that has spread or fallen apart).
     """
     pts = contour_points(rho, level, fluid)
     keep = pts[:, 1] >= y_wall + skip

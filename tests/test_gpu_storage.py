@@ -16,10 +16,15 @@ the 1e-5 FP32 parity is held over 300-1000 steps in test_gpu_parity.py.
 16-bit storage with nearest rounding: near a steady state a node's
 post-collision values repeat from step to step and so do their rounding
 errors, which then add up linearly.  The droplet gains 11% of its mass in
-FP16 (the angle moves 1.7 degrees) and falls apart in BF16; how much, and in
-which direction, depends on the last bit of the FP32 arithmetic, so those
-cases are stated, not bounded.  Stochastic rounding makes every rounding
-error zero-mean, and mass errors become a random walk: about 1.1e-4 per
+FP16 (the angle moves 1.7 degrees) and falls apart in BF16, and the BF16
+channel's flux is 38% off; how much, and in which direction, depends on the
+last bit of the FP32 arithmetic.  Those cases are held to the bars of the same
+format with stochastic rounding and marked as expected failures (not strict:
+a change of the arithmetic can make one pass by luck): nearest rounding is not
+fit for long runs towards a steady state in these formats.
+
+Stochastic rounding makes every rounding error zero-mean, and mass errors
+become a random walk: about 1.1e-4 per
 droplet node and step in FP16 (the rest population dominates: deviations
 near 0.4, last place 2^-12), 1.4 mass units (6e-4) after 20,000 steps over
 8,000 nodes, eight times that in BF16.  The bars below are about three
@@ -62,15 +67,20 @@ def droplet_ref():
     return c, contact_angle(rho, c.solid == 0, y_max=c.params.ny - 8)[0]
 
 
+NEAREST_DRIFT = pytest.mark.xfail(strict=False, reason=(
+    "nearest rounding of 16-bit storage: repeated rounding errors add up linearly near a steady state, "
+    "so the run drifts past the bars of stochastic rounding (not fit for long steady runs)"))
+
 # (storage, rounding): bar on the field errors, bar on the flux error
 CHANNEL = {(0, 0): (1e-3, 1e-3),      # measured 2e-5 / 4e-5, flux 1e-5
            (1, 0): (0.1, 0.1),        # measured 2.2e-2 / 4.5e-2, flux 5.2e-2
            (1, 1): (0.06, 0.01),      # measured 1.6e-3 / 2.0e-2, flux 1.4e-4
-           (2, 0): (None, None),      # measured 0.28 / 0.43, flux 0.38: stated
+           (2, 0): (0.3, 0.03),       # the bars of (2, 1); measured 0.28 / 0.43, flux 0.38
            (2, 1): (0.3, 0.03)}       # measured 1.9e-2 / 0.13, flux 4.6e-3
+CHANNEL_CASES = [pytest.param(*k, marks=NEAREST_DRIFT) if k == (2, 0) else k for k in CHANNEL]
 
 
-@pytest.mark.parametrize("storage,rounding", list(CHANNEL))
+@pytest.mark.parametrize("storage,rounding", CHANNEL_CASES)
 def test_channel_error_after_20k_steps(lbm, channel_ref, storage, rounding):
     c, (ro, uxo, uyo), Qo = channel_ref
     c = I.random_channel_case(nx=512, ny=128, seed=0, storage=storage)
@@ -87,19 +97,19 @@ def test_channel_error_after_20k_steps(lbm, channel_ref, storage, rounding):
           f"err_u {eu:.2e}, flux {eq:.2e} (Q oracle {Qo:.6e})")
     assert np.isfinite([er, eu, eq]).all()
     field, flux = CHANNEL[(storage, rounding)]
-    if field is not None:
-        assert er < field and eu < field and eq < flux
+    assert er < field and eu < field and eq < flux
 
 
 # (storage, rounding): bar on the angle difference (degrees), bar on the relative mass drift
 DROPLET = {(0, 0): (0.1, 1e-4),       # measured 0.000, 5.7e-6
-           (1, 0): (None, None),      # measured -1.70, +1.1e-1: stated
+           (1, 0): (0.3, 2e-3),       # the bars of (1, 1); measured -1.70, +1.1e-1
            (1, 1): (0.3, 2e-3),       # measured -0.041, +9.9e-4
-           (2, 0): (None, None),      # the droplet falls apart (mass -47%): stated
+           (2, 0): (1.5, 1.5e-2),     # the bars of (2, 1); the droplet falls apart (mass -47%)
            (2, 1): (1.5, 1.5e-2)}     # measured -0.45, +1.4e-3
+DROPLET_CASES = [pytest.param(*k, marks=NEAREST_DRIFT) if k[0] and not k[1] else k for k in DROPLET]
 
 
-@pytest.mark.parametrize("storage,rounding", list(DROPLET))
+@pytest.mark.parametrize("storage,rounding", DROPLET_CASES)
 def test_droplet_after_20k_steps(lbm, droplet_ref, storage, rounding):
     c0, theta_o = droplet_ref
     c = I.droplet_case(f_elec=1e-3)
@@ -113,11 +123,11 @@ def test_droplet_after_20k_steps(lbm, droplet_ref, storage, rounding):
     drift = rho[fl].sum() / m0 - 1
     try:
         theta = contact_angle(rho, fl, y_max=c.params.ny - 8)[0]
-    except (ValueError, np.linalg.LinAlgError):
+    except ValueError as e:            # the contour no longer determines a droplet
+        print(f"storage {storage} rounding {rounding}: no contact angle ({e})")
         theta = float("nan")
     d = np.degrees(theta - theta_o)
     print(f"storage {storage} rounding {rounding}: droplet angle {np.degrees(theta):.3f} deg, oracle "
           f"{np.degrees(theta_o):.3f} deg, difference {d:+.3f} deg, mass drift {drift:+.2e}")
     angle, mass = DROPLET[(storage, rounding)]
-    if angle is not None:
-        assert abs(d) < angle and abs(drift) < mass
+    assert abs(d) < angle and abs(drift) < mass
