@@ -7,7 +7,8 @@ loops, FP64), and this module only marshals numpy arrays through ctypes.
 
 Every function cites the passage of the paper (arXiv:0708.4182) it follows in
 ``lbm_oracle.c``.  Pins against closed forms, invariants and textbook limits
-live in ``tests/test_oracle_*.py``.
+live in ``tests/test_oracle_*.py``.  ``round_storage`` (numpy, here) defines
+the 16-bit population storage, which is not part of the paper's model.
 """
 from __future__ import annotations
 
@@ -23,8 +24,9 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 
 def build() -> str:
-    """Compile the oracle with gcc (FP64, no contraction, no fast-math)."""
-    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
+    """Compile the oracle with gcc (FP64, no contraction, no fast-math; the
+    per-node loops run on OpenMP threads, with bitwise the same results)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-fopenmp",
            "-ffp-contract=off", "-o", _LIB + ".tmp", _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(_LIB + ".tmp", _LIB)
@@ -72,6 +74,8 @@ def _load():
         lib.orc_profile.argtypes = [P, u8, dp, dp]
         lib.orc_trt_omega_minus.argtypes = [C.c_double, C.c_double]
         lib.orc_trt_omega_minus.restype = C.c_double
+        lib.orc_threads.argtypes = [C.c_int]
+        lib.orc_threads.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -205,6 +209,44 @@ def profile(p, solid, f):
     out = np.zeros(p.ny)
     _load().orc_profile(C.byref(_params(p)), _u8(s), _d(f), _d(out))
     return out
+
+
+def threads(n: int = 0) -> int:
+    """Set the oracle's thread count (n > 0) and return the count in use."""
+    return int(_load().orc_threads(int(n)))
+
+
+def _round_bf16(a):
+    """Nearest value with 8 significant bits (bfloat16), ties to even."""
+    m, e = np.frexp(np.asarray(a, np.float64))     # a = m 2^e, 1/2 <= |m| < 1
+    return np.ldexp(np.round(np.ldexp(m, 8)), e - 8)
+
+
+def round_storage(p, solid, f, storage: int) -> np.ndarray:
+    """The populations as a 16-bit deviation store holds them (in place; returns f).
+
+    On every fluid node each f_a becomes w_a rho_ref + r(f_a - w_a rho_ref),
+    with r rounding to the nearest FP16 (storage 1) or BF16 (storage 2) value,
+    ties to even; rho_ref is p.rho_ref, or rho0 where that is 0.  Storage 0
+    (FP32) leaves f unchanged: the oracle keeps FP64.  Applied after every step
+    this is the FP64 model with the storage format's rounding and nothing else.
+    """
+    if storage == 0:
+        return f
+    s = _solid(p, solid)
+    _, w, _ = velocity_set()
+    ref = p.rho_ref if p.rho_ref > 0 else p.rho0
+    off = (w * ref)[:, None, None]
+    fl = (s == 0)[None, :, :]
+    d = f - off
+    if storage == 1:
+        r = d.astype(np.float16).astype(np.float64)
+    elif storage == 2:
+        r = _round_bf16(d)
+    else:
+        raise ValueError("storage must be 0, 1 or 2")
+    np.copyto(f, np.where(fl, off + r, f))
+    return f
 
 
 def run(case, nsteps: int):

@@ -218,6 +218,58 @@ def test_full_size_random_channel_parity(lbm):
     assert er < TOL and eu < TOL
 
 
+def rms_errors(case, a, b):
+    """Norm-wise (2-norm over fluid nodes) relative differences of density and
+    velocity between two (rho, ux, uy) triples, relative to the second."""
+    fl = case.solid == 0
+    er = np.linalg.norm((a[0] - b[0])[fl]) / np.linalg.norm(b[0][fl])
+    eu = (np.linalg.norm(np.hypot(a[1] - b[1], a[2] - b[2])[fl]) /
+          np.linalg.norm(np.hypot(b[1], b[2])[fl]))
+    return er, eu
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_full_size_16bit_storage_against_rounded_oracle(lbm, storage):
+    """8192x2048 random-step channel with FP16 / BF16 deviation storage, at the
+    tile the autotuner picks (as the benchmark does), 5 steps, against the FP64
+    oracle whose populations are rounded to the same format after every step
+    (oracle.round_storage: the format and nothing else).  FP32 arithmetic and
+    FP64 arithmetic round a value to different 16-bit neighbours only where it
+    lies within ~1e-7 of a rounding boundary, so the two differ on a small
+    fraction of the values, by one last place.  Bars: the 2-norm difference
+    from the rounded oracle is at most 1/10 of the format's own error (the
+    rounded against the unrounded oracle), and the maximum difference at most
+    the format's own maximum error."""
+    nsteps = 5
+    c = I.random_channel_case(nx=8192, ny=2048, seed=0, storage=storage)
+    p, s = c.params, c.solid
+    sim = lbm.from_case(c)
+    bx, rows, us = sim.autotune(reps=5)
+    kernel = sim.tile()[0]
+    sim.step(nsteps)
+    gpu = tuple(a.astype(np.float64) for a in sim.moments())
+    f = O.init(p, s, c.rho, c.ux, c.uy)
+    fr = O.round_storage(p, s, f.copy(), storage)
+    for _ in range(nsteps):
+        O.step(p, s, f, 1)
+        O.step(p, s, fr, 1)
+        O.round_storage(p, s, fr, storage)
+    exact = O.moments(p, s, f)
+    rounded = O.moments(p, s, fr)
+    er, eu = rms_errors(c, gpu, rounded)
+    fr_, fu_ = rms_errors(c, rounded, exact)
+    fl = s == 0
+    mr = np.abs(gpu[0] - rounded[0])[fl].max()
+    mu = np.hypot(gpu[1] - rounded[1], gpu[2] - rounded[2])[fl].max()
+    fmr = np.abs(rounded[0] - exact[0])[fl].max()
+    fmu = np.hypot(rounded[1] - exact[1], rounded[2] - exact[2])[fl].max()
+    print(f"storage {storage} ({kernel} {bx}x{rows}) 8192x2048 N={nsteps}: GPU vs rounded oracle rms "
+          f"{er:.2e} / {eu:.2e} (format's own {fr_:.2e} / {fu_:.2e}); max {mr:.2e} / {mu:.2e} "
+          f"(format's own {fmr:.2e} / {fmu:.2e})")
+    assert er <= 0.1 * fr_ and eu <= 0.1 * fu_
+    assert mr <= fmr and mu <= fmu
+
+
 def test_checkpoint_resume_is_bitwise(lbm):
     c = CASES["ragged130x67"]()
     a = lbm.from_case(c)

@@ -8,6 +8,8 @@ the FP64 oracle, through the C ABI.
     run (closest approach <= 1.6e-6), where FP32 and FP64 may legitimately
     switch the force on a step apart, so those two run without the field; the
     droplet (margin 2.9e-5) and the other two lattices (1e-3, 1.8e-2) keep it;
+    the rough crop also runs with the field at a critical density below every
+    density of the run (the whole layer conducts);
   - plane Poiseuille flow at Lambda = 3/16: the oracle is exact at the nodes
     for every tau (pinned on the CPU); the GPU's FP32 profile must match the
     parabola to 2e-3 at tau = 0.6 and 1.7;
@@ -66,6 +68,33 @@ def test_trt_fp32_parity(lbm, name, nsteps):
     Q, M = sim.flux()
     Qo, Mo = O.flux(c.params, c.solid, f)
     assert abs(M - Mo) / Mo < 1e-6
+
+
+def test_trt_field_on_rough_wall(lbm):
+    """TRT with the electric force on the rough-wall crop.  With rho_c = 0.05,
+    below every density of the run, the whole electric layer conducts, so the
+    force acts on every layer node of both rough walls at every step and no
+    node sits near the conductivity switch (which the BGK cases cover with
+    the same flag and threshold code)."""
+    c = CASES["rough256x128"]()
+    c.params = c.params.replace(collision=1, trt_magic=3 / 16, rho_c=0.05, f_elec=2e-3)
+    margin = conductivity_margin(c, 1000)
+    assert margin > 1e-2
+    sim = lbm.from_case(c)
+    sim.step(1000)
+    rho, ux, uy = (a.astype(np.float64) for a in sim.moments())
+    f = O.run(c, 1000)
+    er, eu, umax = errors(c, rho, ux, uy, f)
+    # the field matters: without it the oracle's state differs by far more than the bar
+    c0 = CASES["rough256x128"]()
+    c0.params = c.params.replace(f_elec=0.0)
+    r0, ux0, uy0 = O.moments(c0.params, c0.solid, O.run(c0, 1000))
+    _, uxo, uyo = O.moments(c.params, c.solid, f)
+    effect = np.hypot(ux0 - uxo, uy0 - uyo)[c.solid == 0].max() / umax
+    print(f"TRT rough crop with field (rho_c 0.05): err_rho={er:.2e} err_u={eu:.2e} (margin {margin:.1e}, "
+          f"effect of the field on u {effect:.2e})")
+    assert effect > 100 * TOL
+    assert er < TOL and eu < TOL
 
 
 @pytest.mark.parametrize("magic", [1 / 4, 0.02])
