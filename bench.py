@@ -119,19 +119,44 @@ def copy_ceiling(nbytes: int, reps: int = 20):
     return {"GB/s": round(2 * nbytes / (ms * 1e-3) / 1e9, 1), "bytes_copied": nbytes, "ms": round(ms, 4)}
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(steps: int):
+    """The FP64 oracle on the host: single-threaded, then on all the threads its
+    OpenMP loops use (OMP_NUM_THREADS, else every core); both runs step the
+    same state bitwise alike.  The line's value is the all-threads rate."""
     import oracle as O
     from paper_0708_4182_amd import inputs as I
 
     c = I.random_channel_case(nx=512, ny=128, seed=0)
-    f = O.init(c.params, c.solid, c.rho)
-    t0 = time.perf_counter()
-    O.step(c.params, c.solid, f, steps)
-    dt = time.perf_counter() - t0
-    return {"value": round(512 * 128 * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1,
-            "kind": "oracle",
-            "sample": f"FP64 oracle, single thread, 512x128 instance of the same random-step "
-                      f"generator (seed 0), {steps} steps, {dt:.1f} s"}
+    n0 = O.threads()
+    rates = {}
+    try:
+        for nth, nsteps in ((1, steps), (n0, 4 * steps)):
+            O.threads(nth)
+            f = O.init(c.params, c.solid, c.rho)
+            t0 = time.perf_counter()
+            O.step(c.params, c.solid, f, nsteps)
+            dt = time.perf_counter() - t0
+            rates[nth] = (512 * 128 * nsteps / dt / 1e6, nsteps, dt)
+    finally:
+        O.threads(n0)
+    v, nsteps, dt = rates[n0]
+    v1, steps1, dt1 = rates[1]
+    return {"value": round(v, 3), "unit": "MLUPS", "cores": n0, "kind": "oracle",
+            "sample": f"FP64 oracle, {n0} OpenMP threads, 512x128 instance of the same random-step "
+                      f"generator (seed 0), {nsteps} steps, {dt:.1f} s",
+            "single_thread": {"value": round(v1, 3), "unit": "MLUPS", "cores": 1,
+                              "sample": f"the same, one thread, {steps1} steps, {dt1:.1f} s"},
+            "cpu_model": cpu_model(), "cpus_visible": os.cpu_count()}
 
 
 def main():

@@ -54,6 +54,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
     int32_t nx, ny;
@@ -121,6 +124,20 @@ void orc_equilibrium(double rho, double ux, double uy, double *feq)
         double eu = E[a][0] * ux + E[a][1] * uy;
         feq[a] = WT[a] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
     }
+}
+
+/* Threads of the per-node loops (OpenMP builds): n > 0 sets the count; returns
+ * the count the next parallel loop uses (1 without OpenMP).  Every loop
+ * writes only its own node, so results do not depend on the count. */
+int orc_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* pseudopotential phi(rho) */
@@ -220,6 +237,7 @@ void orc_moments(const orc_params *p, const uint8_t *solid, const double *f,
 {
     lattice_init();
     size_t n = (size_t)p->nx * p->ny;
+#pragma omp parallel for schedule(static)
     for (size_t i = 0; i < n; ++i) {
         if (solid[i]) { rho[i] = ux[i] = uy[i] = 0.0; continue; }
         double r = 0, jx = 0, jy = 0;
@@ -248,8 +266,10 @@ static void forces_on(const orc_params *p, const uint8_t *solid, const uint8_t *
     for (int a = 5; a <= 8; ++a) { G[a] = p->g_diag; W[a] = p->w_diag; }
 
     double *phi = malloc(n * sizeof(double));
+#pragma omp parallel for schedule(static)
     for (size_t i = 0; i < n; ++i) phi[i] = solid[i] ? 0.0 : orc_phi(p->rho0, rho[i]);
 
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < p->ny; ++y)
         for (int x = 0; x < p->nx; ++x) {
             size_t i = at(p, x, y);
@@ -377,14 +397,16 @@ int orc_step(const orc_params *p, const uint8_t *solid, double *f, int64_t nstep
 
     for (int64_t t = 0; t < nsteps && !bad; ++t) {
         orc_moments(p, solid, f, rho, ux, uy);
+#pragma omp parallel for schedule(static) reduction(| : bad)
         for (size_t i = 0; i < n; ++i)
             if (!solid[i] && !(rho[i] > 0.0 && isfinite(rho[i]))) bad = 1;
         if (bad) break;
         forces_on(p, solid, layer, top, code, rho, Fs, Fw, Fe);
 
         /* collision */
-        double feq[9];
+#pragma omp parallel for schedule(static)
         for (size_t i = 0; i < n; ++i) {
+            double feq[9];
             if (solid[i]) { for (int a = 0; a < 9; ++a) fs[(size_t)a * n + i] = 0.0; continue; }
             double Fx = Fs[i] + Fw[i] + Fe[i] + rho[i] * p->accel_x;
             double Fy = Fs[n + i] + Fw[n + i] + Fe[n + i] + rho[i] * p->accel_y;
@@ -402,6 +424,7 @@ int orc_step(const orc_params *p, const uint8_t *solid, double *f, int64_t nstep
         }
 
         /* streaming with halfway bounce-back */
+#pragma omp parallel for schedule(static)
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
                 size_t i = at(p, x, y);

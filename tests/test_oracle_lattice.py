@@ -61,3 +61,23 @@ def test_pseudopotential_special_values(rho0):
     assert abs(O.phi(rho0, 50 * rho0) - rho0) < 1e-15
     h = 1e-7
     assert abs(O.phi(rho0, h) / h - 1) < 1e-6
+
+
+def test_threads_give_bitwise_the_same_step():
+    """The oracle's per-node loops run on OpenMP threads; every loop writes only
+    its own node, so 1 thread and all threads give bitwise the same state
+    (both collision operators, rough walls, the field on)."""
+    import oracle as O
+    from paper_0708_4182_amd import inputs as I
+    n0 = O.threads()
+    try:
+        for collision in (0, 1):
+            c = I.rough_channel_case(nx=96, ny=40, f_elec=2e-3, accel=1e-5, seed=3, layers=2)
+            c.params = c.params.replace(collision=collision)
+            O.threads(1)
+            a = O.run(c, 60)
+            O.threads(max(n0, 4))
+            b = O.run(c, 60)
+            np.testing.assert_array_equal(a, b)
+    finally:
+        O.threads(n0)
