@@ -34,15 +34,18 @@ template <> struct Codec<ST_F16> {
     // FP16 subnormal range (last place 2^-24), where the 13 random bits are
     // shifted to the top of the dropped field (rounding probabilities then
     // resolved to 2^-13).  Below 2^-24, sh stops at 10 and the result is 0 or
-    // 2^-24 (error below 2^-24).  The cleared word is exact in FP16 (Inf and
-    // NaN keep their class), so the final conversion does not round.
+    // 2^-24 (error below 2^-24).  The cleared word is exact in FP16, so the
+    // final conversion does not round.  Inf and NaN (e = 255) are converted
+    // as they are: adding random bits to a NaN's mantissa could carry into the
+    // sign and exponent and turn it into a finite value, hiding a diverged
+    // node from the density guard.
     __device__ static T enc_sr(float v, uint32_t r) {
         uint32_t u = __builtin_bit_cast(uint32_t, v);
         const int e = (int)((u >> 23) & 0xFFu);
         const uint32_t sh = (uint32_t)min(max(113 - e, 0), 10);
         const uint32_t mask = (0x2000u << sh) - 1u;
-        u = (u + ((r & 0x1FFFu) << sh)) & ~mask;
-        return (_Float16)__builtin_bit_cast(float, u);
+        const uint32_t w = (u + ((r & 0x1FFFu) << sh)) & ~mask;
+        return (_Float16)__builtin_bit_cast(float, e < 255 ? w : u);
     }
 };
 template <> struct Codec<ST_BF16> {

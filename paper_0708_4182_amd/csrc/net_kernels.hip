@@ -709,8 +709,9 @@ hipError_t conv3x3_mfma(const View &in, const float *w, const float *bias, const
     return hipGetLastError();
 }
 
-// Input gradient dX = conv(dz, flipped transposed W) on matrix cores: dz (FP32,
-// cout planes) and the weights rounded to bf16, FP32 accumulation, FP32 out.
+// Input gradient dX = conv(dz, flipped transposed W) on matrix cores: dz (the
+// bf16 copy of the layer gradient, cout planes) and the weights rounded to
+// bf16, FP32 accumulation, FP32 out.
 hipError_t conv3x3_mfma_dx(const View &dz, const float *w, const View &dx, int N, int cin, int cout, __bf16 *wp,
                            hipStream_t s) {
     const int cout_pad = pad32(cout);
