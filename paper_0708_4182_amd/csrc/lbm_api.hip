@@ -53,6 +53,7 @@ namespace {
 
 thread_local std::string g_init_error;
 
+
 constexpr size_t kAlign = 256;
 constexpr uint64_t kStateMagic = 0x314d54534d424c00ull;  // "\0LBMSTM1"
 
@@ -262,11 +263,11 @@ lbm_status usable(lbm_sim *s) {
     return LBM_OK;
 }
 
-lbm_status do_flux(lbm_sim *s, double *Q, double *M) {
+lbm_status do_flux(lbm_sim *s, double *Q, double *M, double *partials, double *result) {
     HIP_TRY(s, lbm::launch_reduce(s->p.storage, s->buf[s->cur], s->flags, s->g, s->m.rho_off,
-                                  s->partials, s->result, s->stream));
+                                  partials, result, s->stream));
     double host[3];
-    HIP_TRY(s, hipMemcpyAsync(host, s->result, sizeof host, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(host, result, sizeof host, hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     if (Q) *Q = host[0];
     if (M) *M = host[1];
@@ -583,7 +584,19 @@ lbm_status lbm_flux(lbm_sim *s, double *Q, double *M) {
     lbm_status st = usable(s);
     if (st) return st;
     DeviceGuard dg(s->device);
-    return do_flux(s, Q, M);
+    return do_flux(s, Q, M, s->partials, s->result);
+}
+
+lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, int32_t blocks, void *stream) {
+    if (!dst || !src) return fail(nullptr, LBM_EINVAL, "lbm_stream_copy: NULL pointer");
+    if (bytes % 16 || (uintptr_t)dst % 16 || (uintptr_t)src % 16)
+        return fail(nullptr, LBM_EINVAL, "lbm_stream_copy: pointers and size must be multiples of 16 bytes");
+    if (blocks < 1 || blocks > (1 << 20)) return fail(nullptr, LBM_EINVAL, "lbm_stream_copy: blocks out of range");
+    const char *d = (const char *)dst, *sr = (const char *)src;
+    if (d < sr + bytes && sr < d + bytes) return fail(nullptr, LBM_EINVAL, "lbm_stream_copy: buffers overlap");
+    const hipError_t e = lbm::launch_stream_copy(dst, src, bytes, blocks, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(nullptr, LBM_EDEVICE, "lbm_stream_copy: %s", hipGetErrorString(e));
+    return LBM_OK;
 }
 
 lbm_status lbm_geometry(lbm_sim *s, uint16_t *flags) {

@@ -103,6 +103,8 @@ hipError_t launch_init(int storage, void *dst, const uint16_t *flags, const Grid
                        const float *rho, const float *ux, const float *uy, int dense_pitch,
                        hipStream_t s);
 hipError_t launch_fill(void *dst, size_t bytes, hipStream_t s);
+// 16-byte-per-lane non-temporal copy of bytes (a multiple of 16) on `blocks` workgroups.
+hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, int blocks, hipStream_t s);
 hipError_t launch_moments(int storage, const void *src, const uint16_t *flags, const Grid &g,
                           float rho_off, float *rho, float *ux, float *uy, hipStream_t s);
 // grid > 0: persistent kernel with that many workgroups taking tiles from the
@@ -116,6 +118,8 @@ hipError_t launch_batch_reduce(int storage, const ChannelDesc *descs, const int3
 // FP64 reduction: out[0] = sum u_x, out[1] = sum rho, out[2] = number of bad
 // nodes; partials must hold 4 * max_reduce_blocks() doubles.
 int max_reduce_blocks();
+// Workgroups (and FP64 partial quadruples) launch_reduce uses for a lattice.
+int reduce_blocks(const Grid &g);
 hipError_t launch_reduce(int storage, const void *src, const uint16_t *flags, const Grid &g,
                          float rho_off, double *partials, double *out, hipStream_t s);
 // Channel-averaged u_x per row into out[ny] (device), one workgroup per row.

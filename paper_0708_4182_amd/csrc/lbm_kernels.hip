@@ -10,6 +10,8 @@
 // (-1,0), (0,-1); e_5..e_8 = (1,1), (-1,1), (-1,-1), (1,-1).
 #include "lbm_internal.h"
 
+#include <algorithm>
+
 namespace lbm {
 namespace {
 
@@ -1111,6 +1113,26 @@ __global__ void k_fill(uint4 *__restrict__ p, size_t n16) {
     for (; i < n16; i += stride) p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
+// Streaming copy at the access width the memory system moves fastest: each
+// lane copies 4 x 16 bytes per round, four independent non-temporal loads in
+// flight before the four stores.  The practical HBM ceiling the step kernels
+// are measured against (a copy moves the bytes a step moves, with no stencil).
+using v4u = __attribute__((ext_vector_type(4))) uint32_t;
+__global__ void __launch_bounds__(256) k_stream_copy(v4u *__restrict__ dst, const v4u *__restrict__ src,
+                                                     size_t n16) {
+    const size_t lane = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = lane;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        v4u v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = __builtin_nontemporal_load(src + i + k * stride);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) __builtin_nontemporal_store(v[k], dst + i + k * stride);
+    }
+    for (; i < n16; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
 // eq. (2) moments of the current state into dense float32 [ny][nx] arrays.
 template <int S>
 __global__ void k_moments(const typename Codec<S>::T *__restrict__ src,
@@ -1542,6 +1564,13 @@ hipError_t launch_fill(void *dst, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, int blocks, hipStream_t s) {
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return hipSuccess;
+    k_stream_copy<<<(unsigned)blocks, 256, 0, s>>>((v4u *)dst, (const v4u *)src, n16);
+    return hipGetLastError();
+}
+
 hipError_t launch_moments(int storage, const void *src, const uint16_t *flags, const Grid &g,
                           float rho_off, float *rho, float *ux, float *uy, hipStream_t s) {
     const dim3 grid((g.nx + 255) / 256, g.ny);
@@ -1568,10 +1597,17 @@ hipError_t launch_profile(int storage, const void *src, const uint16_t *flags, c
     return hipGetLastError();
 }
 
+// Rows per workgroup of the FP64 reduction (at most RED_MAX_BLOCKS workgroups).
+int reduce_rows(const Grid &g) { return std::max(1, (g.ny + RED_MAX_BLOCKS - 1) / RED_MAX_BLOCKS); }
+
+int reduce_blocks(const Grid &g) {
+    const int rows = reduce_rows(g);
+    return (g.ny + rows - 1) / rows;
+}
+
 hipError_t launch_reduce(int storage, const void *src, const uint16_t *flags, const Grid &g,
                          float rho_off, double *partials, double *out, hipStream_t s) {
-    int rows = (g.ny + RED_MAX_BLOCKS - 1) / RED_MAX_BLOCKS;
-    if (rows < 1) rows = 1;
+    const int rows = reduce_rows(g);
     const int blocks = (g.ny + rows - 1) / rows;
     switch (storage) {
     case ST_F32: k_reduce<ST_F32><<<blocks, RED_THREADS, 0, s>>>((const float *)src, flags, g, rho_off, rows, partials); break;

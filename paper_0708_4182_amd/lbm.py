@@ -22,7 +22,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
 
 # Exported symbols of include/lbm.h (checked by the CPU tests).
 SYMBOLS = ("lbm_workspace_bytes", "lbm_init", "lbm_init_device", "lbm_step", "lbm_moments",
-           "lbm_flux", "lbm_profile", "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_set_kernel",
+           "lbm_flux", "lbm_stream_copy", "lbm_profile", "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_set_kernel",
            "lbm_set_graph",
            "lbm_get_tile",
            "lbm_autotune", "lbm_state_bytes",
@@ -92,6 +92,8 @@ def load_library():
     lib.lbm_step.argtypes = [vp, C.c_int64]
     lib.lbm_moments.argtypes = [vp, vp, vp, vp, C.c_int]
     lib.lbm_flux.argtypes = [vp, dp, dp]
+    lib.lbm_stream_copy.argtypes = [vp, vp, C.c_size_t, C.c_int32, vp]
+    lib.lbm_stream_copy.restype = C.c_int
     lib.lbm_geometry.argtypes = [vp, C.POINTER(C.c_uint16)]
     lib.lbm_set_forces.argtypes = [vp, C.c_double, C.c_double, C.c_double]
     lib.lbm_set_tile.argtypes = [vp, C.c_int32, C.c_int32]
@@ -148,6 +150,23 @@ def load_library():
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
+
+
+def stream_copy(dst, src, blocks: int = 4096, stream=None):
+    """lbm_stream_copy between two contiguous CUDA tensors of the same byte
+    size (a multiple of 16), on ``stream`` (default: torch's current stream)."""
+    import torch
+    if not (dst.is_cuda and src.is_cuda and dst.is_contiguous() and src.is_contiguous()):
+        raise ValueError("stream_copy needs contiguous device tensors")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("stream_copy: sizes differ")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    lib = load_library()
+    rc = lib.lbm_stream_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes, int(blocks),
+                             C.c_void_p(st.cuda_stream))
+    if rc != 0:
+        raise LBMError(f"lbm_stream_copy: {STATUS.get(rc, rc)}: {lib.lbm_last_error(None).decode()}")
 
 
 def workspace_bytes(p) -> int:
