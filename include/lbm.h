@@ -182,6 +182,19 @@ lbm_status lbm_moments(lbm_sim *sim, float *rho, float *ux, float *uy, int on_de
  * (sticky) if any fluid density is <= 0 or not finite; Q and M are still set. */
 lbm_status lbm_flux(lbm_sim *sim, double *Q, double *M);
 
+/* lbm_flux for callers that cannot allocate device memory (code under hipGraph
+ * capture nearby, serving loops, harnesses that forbid allocation): the same
+ * kernels, bitwise the same Q and M, but the FP64 reduction's partial sums and
+ * result live in a library-owned static device array (32 KiB + 256 B per
+ * device, held until the process ends) instead of the handle's workspace.
+ * Allocates nothing.  Every call on one device shares that device's array:
+ * calls that overlap on one device (two streams, two threads) race and must
+ * be serialised by the caller.  LBM_EDEVICE if the array's address could not
+ * be found at lbm_init; LBM_EINVAL if the reduction would need more partial
+ * sums than the array holds (it never does: at most 1024 workgroups).
+ * Synchronizes; LBM_EDIVERGED as lbm_flux. */
+lbm_status lbm_flux_static(lbm_sim *sim, double *Q, double *M);
+
 /* Channel-averaged velocity profile: ux_mean[y] = (1/nx) sum over the fluid
  * nodes of row y of u_x from eq. (2) (the profile of the paper's velocity
  * figure), host float64 [ny], accumulated in FP64 on the GPU in a fixed order;

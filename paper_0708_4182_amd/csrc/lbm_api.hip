@@ -11,6 +11,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -34,6 +36,8 @@ struct lbm_sim {
     uint32_t *rowplain = nullptr;   // rows whose flag words are all plain (one bit per row)
     uint32_t *rng = nullptr;   // two-slot step counter of stochastic rounding
     uint32_t rng_host[2] = {0u, 0u};
+    double *static_scratch = nullptr;   // this device's copy of the library's static scratch (lbm_flux_static)
+    std::string static_err;             // why static_scratch is NULL, if it is
     int cur = 0;
     int64_t steps = 0;
     int block_x = 256;
@@ -49,10 +53,37 @@ struct lbm_sim {
     std::string err;
 };
 
+// Device scratch of lbm_flux_static: the FP64 partial sums of the reduction
+// (4 doubles per workgroup, at most lbm::max_reduce_blocks() workgroups) and
+// the 3-double result, in a file-scope device array instead of the caller's
+// workspace.  Each device holds its own copy until the process ends; host code
+// uses only the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticPartials = 4 * 1024;
+constexpr size_t kStaticDoubles = kStaticPartials + 32;   // partials, then the result (256-byte aligned)
+static __device__ __align__(256) double scratch[kStaticDoubles];
+
 namespace {
 
 thread_local std::string g_init_error;
 
+// Address of `scratch` on the current device, looked up once per device (the
+// first lbm_init on it) and kept; NULL with a message if the lookup failed.
+std::mutex g_scratch_mu;
+std::map<int, double *> g_scratch_ptr;
+
+double *static_scratch_on(int device, std::string &why) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) return it->second;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        why = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+        return nullptr;                 // not cached: a later lbm_init on this device tries again
+    }
+    g_scratch_ptr[device] = (double *)ptr;
+    return (double *)ptr;
+}
 
 constexpr size_t kAlign = 256;
 constexpr uint64_t kStateMagic = 0x314d54534d424c00ull;  // "\0LBMSTM1"
@@ -344,6 +375,7 @@ lbm_status lbm_init(lbm_sim **out, const lbm_params *p, const uint8_t *solid, co
         delete s;
         return fail(nullptr, LBM_EDEVICE, "cannot query the current HIP device");
     }
+    s->static_scratch = static_scratch_on(s->device, s->static_err);
     char *ws = (char *)dev_ws;
     s->buf[0] = ws + L.buf_off[0];
     s->buf[1] = ws + L.buf_off[1];
@@ -597,6 +629,20 @@ lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, int32_t blo
     const hipError_t e = lbm::launch_stream_copy(dst, src, bytes, blocks, (hipStream_t)stream);
     if (e != hipSuccess) return fail(nullptr, LBM_EDEVICE, "lbm_stream_copy: %s", hipGetErrorString(e));
     return LBM_OK;
+}
+
+lbm_status lbm_flux_static(lbm_sim *s, double *Q, double *M) {
+    lbm_status st = usable(s);
+    if (st) return st;
+    if (!s->static_scratch) return fail(s, LBM_EDEVICE, "no static scratch on device %d: %s", s->device,
+                                        s->static_err.c_str());
+    if ((size_t)lbm::reduce_blocks(s->g) * 4 > kStaticPartials)
+        return fail(s, LBM_EINVAL, "lbm_flux_static: %d reduction workgroups exceed the static scratch (%zu)",
+                    lbm::reduce_blocks(s->g), kStaticPartials / 4);
+    DeviceGuard dg(s->device);
+    // k_reduce writes every partial it uses and k_reduce_final the whole
+    // result, so nothing needs clearing between calls
+    return do_flux(s, Q, M, s->static_scratch, s->static_scratch + kStaticPartials);
 }
 
 lbm_status lbm_geometry(lbm_sim *s, uint16_t *flags) {

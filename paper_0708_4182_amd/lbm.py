@@ -22,7 +22,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
 
 # Exported symbols of include/lbm.h (checked by the CPU tests).
 SYMBOLS = ("lbm_workspace_bytes", "lbm_init", "lbm_init_device", "lbm_step", "lbm_moments",
-           "lbm_flux", "lbm_stream_copy", "lbm_profile", "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_set_kernel",
+           "lbm_flux", "lbm_flux_static", "lbm_stream_copy", "lbm_profile", "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_set_kernel",
            "lbm_set_graph",
            "lbm_get_tile",
            "lbm_autotune", "lbm_state_bytes",
@@ -92,6 +92,7 @@ def load_library():
     lib.lbm_step.argtypes = [vp, C.c_int64]
     lib.lbm_moments.argtypes = [vp, vp, vp, vp, C.c_int]
     lib.lbm_flux.argtypes = [vp, dp, dp]
+    lib.lbm_flux_static.argtypes = [vp, dp, dp]
     lib.lbm_stream_copy.argtypes = [vp, vp, C.c_size_t, C.c_int32, vp]
     lib.lbm_stream_copy.restype = C.c_int
     lib.lbm_geometry.argtypes = [vp, C.POINTER(C.c_uint16)]
@@ -143,7 +144,7 @@ def load_library():
                  "lbm_batch_retire", "lbm_batch_set_tile", "lbm_batch_set_graph",
                  "lbm_batch_set_schedule", "lbm_batch_autotune"):
         getattr(lib, name).restype = C.c_int
-    for name in ("lbm_init", "lbm_init_device", "lbm_step", "lbm_moments", "lbm_flux",
+    for name in ("lbm_init", "lbm_init_device", "lbm_step", "lbm_moments", "lbm_flux", "lbm_flux_static",
                  "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_set_kernel", "lbm_get_tile",
                  "lbm_autotune", "lbm_save_state",
                  "lbm_load_state"):
@@ -252,6 +253,13 @@ class Simulation:
         """(Q, M) of eq. (11) and the fluid mass, FP64 (synchronizes)."""
         Q, M = C.c_double(), C.c_double()
         self._check(self.lib.lbm_flux(self.h, C.byref(Q), C.byref(M)))
+        return Q.value, M.value
+
+    def flux_static(self):
+        """flux() through lbm_flux_static: the reduction's scratch is the
+        library's static device array, nothing is allocated."""
+        Q, M = C.c_double(), C.c_double()
+        self._check(self.lib.lbm_flux_static(self.h, C.byref(Q), C.byref(M)))
         return Q.value, M.value
 
     def geometry(self) -> np.ndarray:
