@@ -99,10 +99,10 @@ def time_storage(case, storage, steps, warmup, tile, collision=0, rounding=0):
 
 
 def copy_ceiling(nbytes: int, reps: int = 20):
-    """GB/s (read + write counted) of the library's 16-byte-per-lane
-    non-temporal streaming copy (lbm_stream_copy) of a buffer the size of one
-    population buffer, best over a few grid sizes: the practical HBM ceiling.
-    torch's device copy of the same buffer is reported beside it."""
+    """GB/s (read + write counted) of the library's one-pass non-temporal
+    streaming copy (lbm_stream_copy) of a buffer the size of one population
+    buffer, best over 1, 2 and 4 chunks of 16 bytes per lane: the practical
+    HBM ceiling.  torch's device copy of the same buffer is reported beside it."""
     import torch
     from paper_0708_4182_amd import lbm
 
@@ -110,17 +110,17 @@ def copy_ceiling(nbytes: int, reps: int = 20):
     b = torch.empty_like(a)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     best = None
-    for blocks in (1024, 2048, 4096, 8192, 16384):
-        lbm.stream_copy(b, a, blocks)
+    for per_lane in (1, 2, 4):
+        lbm.stream_copy(b, a, per_lane)
         torch.cuda.synchronize()
         e0.record()
         for _ in range(reps):
-            lbm.stream_copy(b, a, blocks)
+            lbm.stream_copy(b, a, per_lane)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         if best is None or ms < best[0]:
-            best = (ms, blocks)
+            best = (ms, per_lane)
     assert torch.equal(a, b)
     b.copy_(a)
     torch.cuda.synchronize()
@@ -132,9 +132,9 @@ def copy_ceiling(nbytes: int, reps: int = 20):
     tms = e0.elapsed_time(e1) / reps
     del a, b
     torch.cuda.empty_cache()
-    ms, blocks = best
+    ms, per_lane = best
     return {"GB/s": round(2 * nbytes / (ms * 1e-3) / 1e9, 1), "bytes_copied": nbytes, "ms": round(ms, 4),
-            "kernel": f"lbm_stream_copy (16 B per lane, non-temporal), {blocks} workgroups of 256",
+            "kernel": f"lbm_stream_copy (one pass, {per_lane} x 16 B per lane, non-temporal)",
             "torch_copy_GB/s": round(2 * nbytes / (tms * 1e-3) / 1e9, 1)}
 
 
@@ -301,22 +301,24 @@ def main():
         from paper_0708_4182_amd import experiments
         t0 = time.perf_counter()
         with contextlib.redirect_stdout(sys.stderr):     # the experiment's progress lines
-            ws = experiments.warm_start(train=2048, test=64, epochs=10, modes="flow")
-        r = ws["results"][0]
+            ws = experiments.warm_detect(train=2048, val=128, test=64, epochs=10, t_cold="0")
         out["warm_start"] = {
             "workload": "learned warm start on 256x64 channels (step height 0-8, f in [0,3e-3), G in "
                         "[-5.5,-4.5], g = 1e-6, FP32): network trained by the library's kernels on 2048 "
-                        "steady states the method generates (10 epochs), then 64 held-out seeds seeded from "
-                        "its prediction (flow mode) against cold starts; steady = within 1e-4 of the cold "
-                        "start's steady flux for 5000 steps",
-            "lattice_updates_warm_over_plain": round(r["updates_ratio_all_seeds"], 4),
-            "lattice_updates_warm_over_plain_steady_both": round(r["updates_ratio_steady_both"], 4),
-            "median_speedup": round(r["median_speedup"], 3),
-            "warm_failures": r["warm_failures"], "seeds": r["n"],
-            "surrogate_flux_error_median": round(r["surrogate_flux_error_median"], 5),
-            "train_seconds": round(ws["train_seconds"], 2),
+                        "steady states the method generates (10 epochs); 64 held-out seeds seeded from its "
+                        "predicted velocity (flow mode), each run to its own steady flux (|dQ| <= 1e-8 |Q| "
+                        "over 1000 steps, the cold runs' rule) with no cold reference; a settled run whose "
+                        "flux departs from its seeded flux by more than a margin calibrated on 128 other "
+                        "seeds restarts cold in the same batch",
+            "lattice_updates_warm_over_plain": round(ws["updates_warm_with_fallback_over_cold"], 4),
+            "median_speedup": round(ws["median_speedup"], 3),
+            "seeds": ws["test"], "warm_off_cold_branch": ws["test_warm_off_branch"],
+            "caught": ws["caught"], "missed": ws["missed"], "false_alarms": ws["false_alarms"],
+            "final_within_1e-4_of_cold": ws["final_on_branch"],
+            "flux_margin": round(ws["q_margin"], 4),
             "wall_seconds": round(time.perf_counter() - t0, 1),
-            "note": "a failure (another steady branch) is charged 100,000 steps in lattice_updates_warm_over_plain"}
+            "note": "off-branch: the warm run settles more than 1e-4 from the cold start's steady flux; the "
+                    "cold reference is used only to count caught / missed / false alarms"}
         print(f"# warm start: {out['warm_start']}", file=sys.stderr, flush=True)
     if not args.no_network:
         from paper_0708_4182_amd import experiments

@@ -361,12 +361,13 @@ void lbm_batch_free(lbm_batch *b);
 const char *lbm_batch_last_error(const lbm_batch *b);
 
 /* Measurement reference, not part of the model: copy `bytes` (a multiple of
- * 16; device pointers 16-byte aligned, not overlapping) from src to dst with a
- * streaming kernel of `blocks` workgroups of 256 threads, each lane moving
- * 16 bytes per access with non-temporal loads and stores.  Its rate is the
- * practical HBM ceiling the step kernels are compared with.  Asynchronous on
- * `stream`; LBM_EINVAL for bad arguments (message in lbm_last_error(NULL)). */
-lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, int32_t blocks, void *stream);
+ * 16; device pointers 16-byte aligned, not overlapping) from src to dst in one
+ * pass of short-lived workgroups of 256 threads, each lane moving per_lane
+ * (1, 2 or 4) chunks of 16 bytes with non-temporal loads and stores.  Its
+ * rate is the practical HBM ceiling the step kernels are compared with.
+ * Asynchronous on `stream`; LBM_EINVAL for bad arguments (message in
+ * lbm_last_error(NULL)). */
+lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, int32_t per_lane, void *stream);
 
 /* Time steps taken since lbm_init (or the loaded checkpoint). */
 int64_t lbm_steps_done(const lbm_sim *sim);

@@ -619,14 +619,15 @@ lbm_status lbm_flux(lbm_sim *s, double *Q, double *M) {
     return do_flux(s, Q, M, s->partials, s->result);
 }
 
-lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, int32_t blocks, void *stream) {
+lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, int32_t per_lane, void *stream) {
     if (!dst || !src) return fail(nullptr, LBM_EINVAL, "lbm_stream_copy: NULL pointer");
     if (bytes % 16 || (uintptr_t)dst % 16 || (uintptr_t)src % 16)
         return fail(nullptr, LBM_EINVAL, "lbm_stream_copy: pointers and size must be multiples of 16 bytes");
-    if (blocks < 1 || blocks > (1 << 20)) return fail(nullptr, LBM_EINVAL, "lbm_stream_copy: blocks out of range");
+    if (per_lane != 1 && per_lane != 2 && per_lane != 4)
+        return fail(nullptr, LBM_EINVAL, "lbm_stream_copy: per_lane must be 1, 2 or 4");
     const char *d = (const char *)dst, *sr = (const char *)src;
     if (d < sr + bytes && sr < d + bytes) return fail(nullptr, LBM_EINVAL, "lbm_stream_copy: buffers overlap");
-    const hipError_t e = lbm::launch_stream_copy(dst, src, bytes, blocks, (hipStream_t)stream);
+    const hipError_t e = lbm::launch_stream_copy(dst, src, bytes, per_lane, (hipStream_t)stream);
     if (e != hipSuccess) return fail(nullptr, LBM_EDEVICE, "lbm_stream_copy: %s", hipGetErrorString(e));
     return LBM_OK;
 }

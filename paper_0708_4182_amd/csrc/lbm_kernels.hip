@@ -1113,24 +1113,29 @@ __global__ void k_fill(uint4 *__restrict__ p, size_t n16) {
     for (; i < n16; i += stride) p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-// Streaming copy at the access width the memory system moves fastest: each
-// lane copies 4 x 16 bytes per round, four independent non-temporal loads in
-// flight before the four stores.  The practical HBM ceiling the step kernels
-// are measured against (a copy moves the bytes a step moves, with no stencil).
+// Streaming copy: the practical HBM ceiling the step kernels are measured
+// against (a copy moves the bytes a step moves, with no stencil).  One pass:
+// lane i of the grid copies the U 16-byte chunks i, i + T, ..., i + (U-1) T of
+// its workgroup's range (T threads per workgroup) with non-temporal loads and
+// stores, all loads before the stores, and the workgroup exits.  Short-lived
+// workgroups keep the concurrently touched memory in a narrow band, which the
+// memory system streams faster than long-running loops over the whole buffer.
 using v4u = __attribute__((ext_vector_type(4))) uint32_t;
+template <int U>
 __global__ void __launch_bounds__(256) k_stream_copy(v4u *__restrict__ dst, const v4u *__restrict__ src,
                                                      size_t n16) {
-    const size_t lane = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    size_t i = lane;
-    for (; i + 3 * stride < n16; i += 4 * stride) {
-        v4u v[4];
+    const size_t base = (size_t)blockIdx.x * blockDim.x * U + threadIdx.x;
+    v4u v[U];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = __builtin_nontemporal_load(src + i + k * stride);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) __builtin_nontemporal_store(v[k], dst + i + k * stride);
+    for (int k = 0; k < U; ++k) {
+        const size_t i = base + (size_t)k * blockDim.x;
+        if (i < n16) v[k] = __builtin_nontemporal_load(src + i);
     }
-    for (; i < n16; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        const size_t i = base + (size_t)k * blockDim.x;
+        if (i < n16) __builtin_nontemporal_store(v[k], dst + i);
+    }
 }
 
 // eq. (2) moments of the current state into dense float32 [ny][nx] arrays.
@@ -1564,10 +1569,18 @@ hipError_t launch_fill(void *dst, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, int blocks, hipStream_t s) {
+hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, int per_lane, hipStream_t s) {
     const size_t n16 = bytes / 16;
     if (n16 == 0) return hipSuccess;
-    k_stream_copy<<<(unsigned)blocks, 256, 0, s>>>((v4u *)dst, (const v4u *)src, n16);
+    const size_t per_block = (size_t)256 * per_lane;
+    const size_t blocks = (n16 + per_block - 1) / per_block;
+    if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
+    switch (per_lane) {
+    case 1: k_stream_copy<1><<<(unsigned)blocks, 256, 0, s>>>((v4u *)dst, (const v4u *)src, n16); break;
+    case 2: k_stream_copy<2><<<(unsigned)blocks, 256, 0, s>>>((v4u *)dst, (const v4u *)src, n16); break;
+    case 4: k_stream_copy<4><<<(unsigned)blocks, 256, 0, s>>>((v4u *)dst, (const v4u *)src, n16); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -315,6 +315,104 @@ def warm_start(train=4096, test=512, nx=256, ny=64, epochs=30, batch=32, lr=1e-3
     return res
 
 
+def warm_detect(train=2048, val=256, test=64, nx=256, ny=64, epochs=10, batch=32, bf16=1,
+                chans="32,64,128,128", max_steps=100_000, seed=0, out="", t_cold="0,500,1000,2000,4000"):
+    """Learned warm start that needs no cold reference: warm runs settle by their
+    own flux rule and are checked against the prediction they started from; a
+    channel judged to have settled on another steady branch restarts cold in
+    the same batch (warmstart.warm_with_fallback).  The two margins of the
+    check are calibrated on ``val`` held-out seeds (warm runs accepted
+    unconditionally, the cold reference telling which settled on its branch);
+    the ``test`` seeds are then run with the check, and only the evaluation
+    uses the cold reference: failures caught, missed, false alarms, and the
+    lattice updates of the warm runs (fallbacks included) against the cold
+    runs, both to their own steady rule.  ``t_cold`` lists the cold prefixes
+    (steps run cold before the prediction's velocity is seeded) tried on the
+    validation seeds; the one with the fewest lattice updates is used."""
+    import torch
+
+    from . import net, warmstart as WS
+
+    def log(msg):
+        print(f"# {msg}", flush=True)
+
+    chans = tuple(int(c) for c in str(chans).split(","))
+    n_all = train + val + test
+    cases = [I.warm_case(s, nx=nx, ny=ny) for s in range(n_all)]
+    log(f"{n_all} channels {nx}x{ny}: steady states (cold starts)")
+    t0 = time.perf_counter()
+    data = WS.steady_states(cases, max_steps=max_steps, log=log)
+    X, fluid = WS.features(cases)
+    T = data["T"]
+    scales = WS.Scales.fit(T[:train], fluid[:train])
+    Tn = (T - scales.mean.reshape(1, 3, 1, 1)) / scales.std.reshape(1, 3, 1, 1)
+    Xd = torch.from_numpy(X).cuda()
+    Td = torch.from_numpy(Tn.astype(np.float32)).cuda()
+    Fd = torch.from_numpy(fluid).cuda()
+    model = net.Net(ny, nx, batch, chans=chans, act_bf16=bool(int(bf16)))
+    model.set_params(net.he_init(net.layer_shapes(chans=chans), seed))
+    log(f"training: {model.n_params} parameters, {epochs} epochs of {train // batch} steps")
+    WS.train(model, Xd[:train], Td[:train], Fd[:train], epochs, batch, 1e-3, 1e-5, seed, log=None)
+    Q_inf = np.asarray(data["Q"])
+    cold_steps = np.asarray(data["steps"], np.int64)
+
+    def on_branch(q, idx):
+        return np.abs(q - Q_inf[idx]) <= 1e-4 * np.abs(Q_inf[idx])
+
+    # calibration on the validation seeds, every warm run accepted: the cold prefix
+    # (the fewest steps with the fewest off-branch warm runs) and the flux margin
+    # (99th percentile of the on-branch runs' deviation from their seeded flux)
+    vi = np.arange(train, train + val)
+    vcases = [cases[i] for i in vi]
+    calib = []
+    for tc in (int(v) for v in str(t_cold).split(",")):
+        rv = WS.warm_with_fallback(model, scales, vcases, q_margin=np.inf, phase_margin=1 << 30,
+                                   max_steps=max_steps, t_cold=tc)
+        good = on_branch(rv["Q_warm"], vi)
+        upd = float(np.where(good, rv["steps"], max_steps).sum() / cold_steps[vi].sum())
+        calib.append(dict(t_cold=tc, off_branch=int((~good).sum()), updates_over_cold=upd, run=rv, good=good))
+        log(f"validation, cold prefix {tc}: {int((~good).sum())} of {val} warm runs off the cold branch, "
+            f"updates warm / cold {upd:.3f} (off-branch runs charged {max_steps} steps)")
+    best = min(calib, key=lambda c: (c["updates_over_cold"], c["t_cold"]))
+    tc_best = best["t_cold"]
+    rv, good = best["run"], best["good"]
+    qdev = np.abs(rv["Q_warm"] - rv["Q_pred"]) / np.abs(rv["Q_pred"])
+    q_margin = float(np.percentile(qdev[good], 99)) if good.any() else 0.02
+    phase_margin = 1 << 30            # the phase signal does not separate branches (0 on every run)
+    log(f"chosen cold prefix {tc_best} steps; flux margin {q_margin:.4f}")
+    # test seeds with the check and the cold fallback
+    ti = np.arange(train + val, n_all)
+    rt = WS.warm_with_fallback(model, scales, [cases[i] for i in ti], q_margin=q_margin,
+                               phase_margin=phase_margin, max_steps=max_steps, t_cold=tc_best)
+    warm_good = on_branch(rt["Q_warm"], ti)
+    final_good = on_branch(rt["Q"], ti)
+    caught = int((rt["flagged"] & ~warm_good).sum())
+    missed = int((~rt["flagged"] & ~final_good).sum())
+    false_alarms = int((rt["flagged"] & warm_good).sum())
+    wrong_warm = int((~warm_good).sum())
+    nodes = float(nx * ny)
+    res = {"experiment": "warm_detect", "nx": nx, "ny": ny, "train": train, "val": val, "test": test,
+           "epochs": epochs, "t_cold": tc_best, "q_margin": q_margin,
+           "calibration": [{k: v for k, v in c.items() if k not in ("run", "good")} for c in calib],
+           "val_on_branch": int(good.sum()),
+           "test_warm_off_branch": wrong_warm, "caught": caught, "missed": missed,
+           "false_alarms": false_alarms, "flagged": int(rt["flagged"].sum()),
+           "final_on_branch": int(final_good.sum()),
+           "updates_warm_with_fallback_over_cold": float(rt["steps"].sum() / cold_steps[ti].sum()),
+           "median_speedup": float(np.median(cold_steps[ti] / np.maximum(rt["steps"], 100))),
+           "wall_seconds": time.perf_counter() - t0}
+    log("warm detect: " + json.dumps(res))
+    if out:
+        import os
+        os.makedirs(out, exist_ok=True)
+        per = {"val": {k: np.asarray(v).tolist() for k, v in rv.items()},
+               "test": {k: np.asarray(v).tolist() for k, v in rt.items()},
+               "Q_inf_val": Q_inf[vi].tolist(), "Q_inf_test": Q_inf[ti].tolist(),
+               "cold_steps_val": cold_steps[vi].tolist(), "cold_steps_test": cold_steps[ti].tolist()}
+        json.dump({**res, "per_seed": per}, open(os.path.join(out, "warm_detect.json"), "w"))
+    return res
+
+
 def _kwargs(items):
     kw = {}
     for it in items:
@@ -333,7 +431,7 @@ def main(argv):
     name = argv[1] if len(argv) > 1 else "flux_vs_field"
     fn = {"flux_vs_field": flux_vs_field, "sweep_throughput": sweep_throughput,
           "sweep_steady": sweep_steady, "warm_start": warm_start, "channel_study": channel_study,
-          "small_configs": small_configs, "net_throughput": net_throughput}[name]
+          "small_configs": small_configs, "net_throughput": net_throughput, "warm_detect": warm_detect}[name]
     print(json.dumps(fn(**_kwargs(argv[2:]))), flush=True)
 
 

@@ -153,7 +153,7 @@ def load_library():
     return lib
 
 
-def stream_copy(dst, src, blocks: int = 4096, stream=None):
+def stream_copy(dst, src, per_lane: int = 1, stream=None):
     """lbm_stream_copy between two contiguous CUDA tensors of the same byte
     size (a multiple of 16), on ``stream`` (default: torch's current stream)."""
     import torch
@@ -164,7 +164,7 @@ def stream_copy(dst, src, blocks: int = 4096, stream=None):
         raise ValueError("stream_copy: sizes differ")
     st = stream if stream is not None else torch.cuda.current_stream()
     lib = load_library()
-    rc = lib.lbm_stream_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes, int(blocks),
+    rc = lib.lbm_stream_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes, int(per_lane),
                              C.c_void_p(st.cuda_stream))
     if rc != 0:
         raise LBMError(f"lbm_stream_copy: {STATUS.get(rc, rc)}: {lib.lbm_last_error(None).decode()}")

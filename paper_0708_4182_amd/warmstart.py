@@ -304,3 +304,128 @@ def warm_vs_cold(model, scales: Scales, cases, Q_inf, cold, max_steps: int = 100
     if log:
         log("warm vs cold: " + json.dumps(stats))
     return stats, warm, surrogate, Q_end
+
+
+# ----------------------------------------------------------- branch detection
+def phase_mismatch(rho, rho_pred, solid, G: float) -> int:
+    """Fluid nodes whose phase (liquid: rho >= (rho_v + rho_l) / 2 at G) in
+    ``rho`` differs from the phase in the prediction ``rho_pred``, not counting
+    nodes next to an interface of the prediction (within one node of a node of
+    the other phase), where the phase of a diffuse interface is ambiguous."""
+    rv, rl = I.coexistence(G)
+    mid = 0.5 * (rv + rl)
+    fl = solid == 0
+    liq_p = (rho_pred >= mid) & fl
+    liq = (rho >= mid) & fl
+    # nodes of the prediction with a neighbour (8-connected, periodic in x) of the other phase
+    edge = np.zeros_like(fl)
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            if dx == 0 and dy == 0:
+                continue
+            nb = np.roll(np.roll(liq_p, dx, axis=1), dy, axis=0)
+            nfl = np.roll(np.roll(fl, dx, axis=1), dy, axis=0)
+            edge |= nfl & (nb != liq_p)
+    return int(((liq != liq_p) & fl & ~edge).sum())
+
+
+def warm_with_fallback(model, scales: Scales, cases, check_every: int = 100, window: int = 1000,
+                       rtol: float = 1e-8, max_steps: int = 100_000, q_margin: float = 0.02,
+                       phase_margin: int = 8, mode: str = "flow", pred=None, t_cold: int = 0, log=None):
+    """Warm-start every case from the network and run it to a steady flux by
+    its own rule (|Q(t) - Q(t - window)| <= rtol |Q|, as the cold runs), without
+    any cold reference.
+
+    With t_cold > 0 every channel first runs t_cold steps from its cold start,
+    and the prediction's velocity is then seeded onto the density it has
+    reached (mode "flow"): the early cold transient is where a channel's
+    steady branch (how its cavities and films form) is decided, and the
+    prediction then only shortens the slow viscous decay that follows.
+
+    A settled warm channel is accepted when its flux is within q_margin of the
+    flux of the seeded state and at most phase_margin fluid nodes away from the
+    predicted interfaces have the other phase; otherwise it is flagged as
+    settled on another steady branch, re-initialised cold (the case's initial
+    fields) inside the same batch, and run to its own steady flux.  A
+    prediction that is not finite starts cold.
+
+    Returns per-channel arrays: steps (lattice steps run: the cold prefix,
+    warm, and any cold restart), Q (accepted flux), flagged, Q_warm (settled
+    warm flux, NaN if none), Q_pred (flux of the seeded state), mismatch
+    (phase mismatch at settling)."""
+    import torch
+    n = len(cases)
+    X, fluid = features(cases)
+    Xd = torch.from_numpy(X).cuda()
+    if pred is None:
+        pred = predict(model, Xd, scales)
+    P = pred.cpu().numpy()
+    b = lbm.Batch(cases)
+    rho_start = [c.rho for c in cases]
+    if t_cold > 0:
+        b.set_graph(100 if t_cold % 100 == 0 else 0)
+        b.step(t_cold)
+        rho_start = [b.moments_device(i)[0].cpu().numpy().astype(np.float64) for i in range(n)]
+    seeded = []
+    warm = np.zeros(n, bool)
+    for i, c in enumerate(cases):
+        mass = float(c.rho[c.solid == 0].sum())
+        F = warm_fields(P[i], c.solid, c.meta["G"], mass, mode, rho_cold=rho_start[i])
+        if F is not None:
+            Fd = torch.from_numpy(F).to(pred.device)
+            seeded.append(Fd)
+            b.init_device(i, Fd[0], Fd[1], Fd[2])
+            warm[i] = True
+    Q_pred, _, _ = b.flux_nocheck()           # synchronizes; the seeded states are read
+    del seeded
+    b.set_graph(check_every if check_every % 2 == 0 else 0)
+    lag = max(1, window // check_every)
+    hist = [[] for _ in range(n)]
+    active = np.ones(n, bool)
+    steps = np.full(n, int(t_cold), np.int64)
+    flagged = np.zeros(n, bool)
+    Q_out = np.full(n, np.nan)
+    Q_warm = np.full(n, np.nan)
+    mism = np.full(n, -1, np.int64)
+    cold_fields = {}
+    t = 0
+    while active.any() and t < max_steps:
+        b.step(check_every)
+        t += check_every
+        steps[active] += check_every
+        Q, _, _ = b.flux_nocheck()
+        settled = []
+        for i in np.nonzero(active)[0]:
+            hist[i].append(float(Q[i]))
+            if not np.isfinite(Q[i]):
+                settled.append(i)
+                continue
+            if len(hist[i]) > lag and abs(Q[i] - hist[i][-1 - lag]) <= rtol * abs(Q[i]):
+                settled.append(i)
+        retire = np.zeros(n, bool)
+        for i in settled:
+            if warm[i] and not flagged[i]:
+                Q_warm[i] = Q[i]
+                rho = b.moments_device(i)[0].cpu().numpy()
+                mism[i] = phase_mismatch(rho, P[i][0], cases[i].solid, cases[i].meta["G"])
+                off = abs(Q[i] - Q_pred[i]) > q_margin * abs(Q_pred[i])
+                if off or mism[i] > phase_margin or not np.isfinite(Q[i]):
+                    flagged[i] = True
+                    c = cases[i]
+                    fields = torch.from_numpy(np.stack([c.rho, c.ux, c.uy]).astype(np.float32)).cuda()
+                    cold_fields[i] = fields
+                    b.init_device(i, fields[0], fields[1], fields[2])
+                    hist[i] = []
+                    continue
+            Q_out[i] = Q[i]
+            retire[i] = True
+        if retire.any():
+            active &= ~retire
+            b.retire(~active)
+        if log and t % 5000 == 0:
+            log(f"  step {t}: {int(active.sum())} of {n} channels running, {int(flagged.sum())} restarted cold")
+    for i in np.nonzero(active)[0]:
+        Q_out[i] = hist[i][-1] if hist[i] else np.nan
+    del b, cold_fields
+    return dict(steps=steps, Q=Q_out, flagged=flagged, Q_warm=Q_warm, Q_pred=np.asarray(Q_pred),
+                mismatch=mism, warm=warm, converged=~active)

@@ -162,3 +162,26 @@ def test_scales_fit():
         assert s.mean[p] == pytest.approx(T[:, p][m].mean())
         assert s.std[p] == pytest.approx(T[:, p][m].std())
     assert WS.Scales.from_dict(s.to_dict()).std.tolist() == s.std.tolist()
+
+
+def test_phase_mismatch_counts_phase_flips_away_from_interfaces():
+    """A cavity that fills (8 x 3 vapour nodes turned liquid, away from the
+    predicted interface except its rim) is counted; a one-node shift of an
+    interface is not (those nodes lie next to the predicted interface)."""
+    from paper_0708_4182_amd import inputs as I
+    from paper_0708_4182_amd.warmstart import phase_mismatch
+    G = -5.0
+    rv, rl = I.coexistence(G)
+    ny, nx = 32, 64
+    solid = I.flat_channel(nx, ny)
+    pred = np.full((ny, nx), rl)
+    pred[1:6, :] = rv                        # a vapour film at the bottom wall
+    pred[solid == 1] = 0.0
+    assert phase_mismatch(pred, pred, solid, G) == 0
+    shifted = pred.copy()
+    shifted[6, :] = rv                       # the film one node thicker: interface nodes only
+    assert phase_mismatch(shifted, pred, solid, G) == 0
+    filled = pred.copy()
+    filled[1:4, 10:18] = rl                  # rows 1-3 of a cavity turn liquid
+    # rows 1-3 are at least two nodes from the film's top (row 5 / 6 interface)
+    assert phase_mismatch(filled, pred, solid, G) == 3 * 8
