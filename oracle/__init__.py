@@ -70,6 +70,8 @@ def _load():
         lib.orc_init.argtypes = [P, u8, dp, dp, dp, dp]
         lib.orc_step.argtypes = [P, u8, dp, C.c_int64]
         lib.orc_step.restype = C.c_int
+        lib.orc_step_ext.argtypes = [P, u8, dp, C.c_int64, dp]
+        lib.orc_step_ext.restype = C.c_int
         lib.orc_flux.argtypes = [P, u8, dp, dp, dp]
         lib.orc_profile.argtypes = [P, u8, dp, dp]
         lib.orc_trt_omega_minus.argtypes = [C.c_double, C.c_double]
@@ -189,6 +191,19 @@ def step(p, solid, f, nsteps: int) -> np.ndarray:
     s = _solid(p, solid)
     assert f.dtype == np.float64 and f.flags.c_contiguous and f.shape == (9,) + s.shape
     if _load().orc_step(C.byref(_params(p)), _u8(s), _d(f), int(nsteps)):
+        raise FloatingPointError("oracle: density became non-positive or not finite")
+    return f
+
+
+def step_ext(p, solid, f, nsteps: int, acc) -> np.ndarray:
+    """``step`` with a per-node acceleration field acc [2][ny][nx] (x plane,
+    then y plane) added to the driving acceleration: body force rho (g + acc).
+    Raises FloatingPointError as ``step``."""
+    s = _solid(p, solid)
+    assert f.dtype == np.float64 and f.flags.c_contiguous and f.shape == (9,) + s.shape
+    acc = np.ascontiguousarray(acc, np.float64)
+    assert acc.shape == (2,) + s.shape
+    if _load().orc_step_ext(C.byref(_params(p)), _u8(s), _d(f), int(nsteps), _d(acc)):
         raise FloatingPointError("oracle: density became non-positive or not finite")
     return f
 

@@ -381,7 +381,19 @@ static void collide_trt_guo(const orc_params *p, const double *f, double *fs, si
  *      population arriving from a solid node replaced by bounce-back.
  * Returns 0, or 1 if a fluid density became non-positive or not finite.
  */
+int orc_step_ext(const orc_params *p, const uint8_t *solid, double *f, int64_t nsteps, const double *acc);
+
 int orc_step(const orc_params *p, const uint8_t *solid, double *f, int64_t nsteps)
+{
+    return orc_step_ext(p, solid, f, nsteps, NULL);
+}
+
+/* orc_step with a per-node acceleration field acc [2][ny][nx] (x plane, then
+ * y plane; NULL for none) added to the driving acceleration: the body force
+ * on node x is rho (g + acc(x)).  It carries forces the paper applies to the
+ * fluid's mass in a prescribed pattern, like the artificial attraction that
+ * gathers the fluid of its droplet run into one droplet. */
+int orc_step_ext(const orc_params *p, const uint8_t *solid, double *f, int64_t nsteps, const double *acc)
 {
     lattice_init();
     size_t n = (size_t)p->nx * p->ny;
@@ -408,8 +420,10 @@ int orc_step(const orc_params *p, const uint8_t *solid, double *f, int64_t nstep
         for (size_t i = 0; i < n; ++i) {
             double feq[9];
             if (solid[i]) { for (int a = 0; a < 9; ++a) fs[(size_t)a * n + i] = 0.0; continue; }
-            double Fx = Fs[i] + Fw[i] + Fe[i] + rho[i] * p->accel_x;
-            double Fy = Fs[n + i] + Fw[n + i] + Fe[n + i] + rho[i] * p->accel_y;
+            double gx = p->accel_x, gy = p->accel_y;
+            if (acc) { gx += acc[i]; gy += acc[n + i]; }
+            double Fx = Fs[i] + Fw[i] + Fe[i] + rho[i] * gx;
+            double Fy = Fs[n + i] + Fw[n + i] + Fe[n + i] + rho[i] * gy;
             if (p->collision == 1) {
                 collide_trt_guo(p, f, fs, n, i, rho[i], ux[i], uy[i], Fx, Fy);
                 continue;

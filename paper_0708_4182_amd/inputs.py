@@ -234,6 +234,53 @@ class Case:
         self.uy = np.ascontiguousarray(np.where(self.solid != 0, 0.0, self.uy), np.float64)
 
 
+# The paper's droplet run: a 100 x 50 box, calG = -0.52, w = -0.14, tau = 0.9,
+# rho0 = 1, rho_c = 1, a homogeneous density of 0.85.  Reading of eq. (4)
+# used for it (the printed 2 calG / calG diverges, see tests/test_golden_paper.py):
+# the 2 : 1 ratio of axis to diagonal Green function with calG on the axes,
+# G_a = calG (|e| = 1), calG / 2 (|e| = sqrt 2), and W_a = w, w / 2 likewise.
+PAPER_G, PAPER_W, PAPER_TAU, PAPER_RHO = -0.52, -0.14, 0.9, 0.85
+
+
+def paper_params(nx: int = 100, ny: int = 50, f_elec: float = 0.0, **kw) -> Params:
+    """Parameters of the paper's droplet run under the reading above: the
+    electric force acts on the single layer next to the bottom substrate."""
+    base = dict(nx=nx, ny=ny, tau=PAPER_TAU, rho0=1.0, g_axis=PAPER_G, g_diag=PAPER_G / 2,
+                w_axis=PAPER_W, w_diag=PAPER_W / 2, rho_c=1.0, f_elec=f_elec, elec_layers=1,
+                elec_walls=ELEC_BOTTOM)
+    base.update(kw)
+    return Params(**base)
+
+
+def paper_droplet_case(seed: int = 0, nx: int = 100, ny: int = 50, noise_amp: float = 1e-3) -> Case:
+    """The paper's initial state: homogeneous density 0.85 (plus seeded noise of
+    +-noise_amp) between a solid substrate (row 0) and a solid top row."""
+    p = paper_params(nx, ny)
+    solid = flat_channel(nx, ny)
+    rho = np.full((ny, nx), PAPER_RHO)
+    if noise_amp:
+        rho = rho + noise(seed, rho.shape, noise_amp)
+    return Case(p, solid, rho, name=f"paper_droplet{nx}x{ny}_s{seed}")
+
+
+def attraction_field(nx: int, ny: int, g: float, solid: np.ndarray | None = None,
+                     cx: float | None = None, cy: float = 0.5) -> np.ndarray:
+    """Acceleration of magnitude g towards the point (cx, cy) (default: the
+    middle of the substrate, on the wall plane), [2][ny][nx] float32, zero on
+    solid nodes: the artificial attraction that gathers the fluid into one
+    droplet in the middle of the substrate."""
+    if cx is None:
+        cx = (nx - 1) / 2.0
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    dx, dy = cx - x, cy - y
+    r = np.hypot(dx, dy)
+    r = np.where(r > 0, r, 1.0)
+    a = np.stack([g * dx / r, g * dy / r])
+    if solid is not None:
+        a[:, solid != 0] = 0.0
+    return a.astype(np.float32)
+
+
 def droplet_case(f_elec: float = 0.0, seed: int = 0, nx: int = 128, ny: int = 64,
                  R: float = 20.0, noise_amp: float = 1e-3, G: float = -5.0,
                  rho_l: float = 2.0, rho_v: float = 0.15, layers: int = 2) -> Case:

@@ -1,0 +1,145 @@
+"""Pins of the acceleration-field step and of the paper's droplet run under
+reading R29 of eq. (4) (CPU, the FP64 oracle).
+
+The paper's run: a 100 x 50 box, calG = -0.52, w = -0.14, tau = 0.9, rho0 = 1,
+homogeneous density 0.85; an artificial attraction gathers the fluid into one
+droplet in the middle of the substrate and is then removed; the single layer
+of fluid next to the substrate is conductive between x1 and x2 (rho >= rho_c =
+1.0) and insulating (vapour) outside; the electric force on that layer makes
+cos(theta) - cos(theta_0) grow in proportion to f (its eq. (9) check).
+
+Reading R29: G_a = calG on the axes and calG / 2 on the diagonals (W_a = w,
+w / 2), the printed 2 : 1 ratio with calG on the axes.  The printed 2 calG /
+calG diverges from the paper's own initial state (tests/test_golden_paper.py).
+Under R29 the pressure is p = rho / 3 + 2 calG phi^2, the usual Shan-Chen
+form with G = 12 calG = -6.24.
+"""
+import numpy as np
+import pytest
+
+import measure
+import oracle as O
+from paper_0708_4182_amd import inputs as I
+from test_oracle_physics import maxwell_coexistence
+
+
+def test_uniform_field_equals_the_driving_acceleration_bitwise():
+    """A field equal to g everywhere with no driving acceleration is the
+    driving acceleration g with no field, bit for bit."""
+    c = I.rough_channel_case(nx=48, ny=24, f_elec=2e-3, accel=0.0, seed=2)
+    g = (3e-5, -1e-5)
+    acc = np.empty((2, 24, 48))
+    acc[0], acc[1] = g
+    f1 = O.init(c.params, c.solid, c.rho)
+    O.step_ext(c.params, c.solid, f1, 40, acc)
+    p2 = c.params.replace(accel_x=g[0], accel_y=g[1])
+    f2 = O.init(p2, c.solid, c.rho)
+    O.step(p2, c.solid, f2, 40)
+    np.testing.assert_array_equal(f1, f2)
+
+
+def test_field_adds_its_force_to_the_momentum():
+    """No walls, no interaction forces: one step changes the total momentum by
+    exactly the sum of rho(x) a(x) (the body force of eq. (10) is a momentum
+    source of F per step)."""
+    n = 24
+    p = I.params_for_G(n, n, 0.0, tau=0.8).replace(w_axis=0.0, w_diag=0.0)
+    s = np.zeros((n, n), np.uint8)
+    rng = np.random.default_rng(3)
+    rho = rng.uniform(0.5, 1.5, (n, n))
+    f = O.init(p, s, rho, rng.uniform(-0.02, 0.02, (n, n)), rng.uniform(-0.02, 0.02, (n, n)))
+    acc = rng.uniform(-1e-3, 1e-3, (2, n, n))
+    r0, ux0, uy0 = O.moments(p, s, f)
+    O.step_ext(p, s, f, 1, acc)
+    r1, ux1, uy1 = O.moments(p, s, f)
+    for comp, (u0, u1) in enumerate(((ux0, ux1), (uy0, uy1))):
+        gain = (r1 * u1).sum() - (r0 * u0).sum()
+        assert abs(gain - (r0 * acc[comp]).sum()) < 1e-14
+    assert abs(r1.sum() - r0.sum()) < 1e-12
+
+
+def test_r29_coexistence_is_the_maxwell_rule_at_12_calG():
+    """A flat liquid slab under R29 settles at the liquid density of the
+    mechanical-stability coexistence of p = rho/3 + (G/6) phi^2 with
+    G = 12 calG (within 2%), with a vapour far below rho_c.  At this |G| the
+    vapour branch of the lattice model lies well below the continuum rule
+    (0.043 against 0.062: the interface spans few nodes), so only the liquid
+    branch is pinned to it."""
+    nx, ny = 4, 160
+    p = I.paper_params(nx, ny)
+    s = np.zeros((ny, nx), np.uint8)
+    rv, rl = maxwell_coexistence(12 * I.PAPER_G)
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    rho = rv + (rl - rv) * 0.5 * (np.tanh((y - 40) / 2) - np.tanh((y - 120) / 2))
+    f = O.init(p, s, rho)
+    O.step(p, s, f, 15000)
+    r, _, _ = O.moments(p, s, f)
+    assert abs(r[80, 0] / rl - 1) < 0.02
+    assert r[0, 0] < 0.1 < 1.0 < rl               # rho_c = 1.0 separates the phases
+    assert abs(r[80, 0] - r[80, 3]) < 1e-12
+    # the paper's homogeneous 0.85 lies inside the spinodal: dp/drho < 0 there
+    phi = 1 - np.exp(-0.85)
+    assert 1 / 3 + (12 * I.PAPER_G / 3) * phi * np.exp(-0.85) < 0
+
+
+def condensed_droplet(seed=0, gc=3e-4, t_attract=10_000, t_release=20_000):
+    c = I.paper_droplet_case(seed)
+    p, s = c.params, c.solid
+    f = O.init(p, s, c.rho)
+    O.step_ext(p, s, f, t_attract, I.attraction_field(p.nx, p.ny, gc, s).astype(np.float64))
+    O.step(p, s, f, t_release)
+    return c, f
+
+
+@pytest.mark.slow
+def test_paper_droplet_forms_with_a_conductive_layer_between_x1_and_x2():
+    """The attraction gathers the fluid into one droplet in the middle of the
+    substrate; after its removal the droplet is steady, and the single layer
+    next to the substrate has rho >= rho_c exactly on one interval [x1, x2]
+    under the droplet and vapour outside (the paper's density figure)."""
+    c, f = condensed_droplet()
+    p, s = c.params, c.solid
+    r, ux, uy = O.moments(p, s, f)
+    th0, (xc, yc, R) = measure.contact_angle(r, s == 0, y_max=p.ny - 4)
+    g = f.copy()
+    O.step(p, s, g, 5000)
+    r2, _, _ = O.moments(p, s, g)
+    th1, _ = measure.contact_angle(r2, s == 0, y_max=p.ny - 4)
+    assert abs(np.degrees(th1 - th0)) < 0.05                  # steady
+    assert abs(xc - (p.nx - 1) / 2) < 1.0                     # in the middle of the substrate
+    row = r[1]
+    cond = np.nonzero(row >= p.rho_c)[0]
+    assert len(cond) > 10 and np.array_equal(cond, np.arange(cond[0], cond[-1] + 1))
+    assert cond[0] < xc < cond[-1]
+    # away from the contact line the layer holds vapour (0.07 at the wall, 0.04 in the bulk)
+    assert row[:cond[0] - 6].max() < 0.1 and row[cond[-1] + 7:].max() < 0.1
+    # one droplet: the liquid nodes form a single 8-connected region
+    from scipy import ndimage
+    _, ncomp = ndimage.label((r >= p.rho_c) & (s == 0), structure=np.ones((3, 3)))
+    assert ncomp == 1
+
+
+@pytest.mark.slow
+def test_paper_droplet_young_lippmann_linearity():
+    """eq. (9): cos(theta) - cos(theta_0) grows in proportion to the force f
+    on the conductive single layer (the paper's own check), over the paper's
+    force scale (0 .. 0.15).  The conductive extent x2 - x1 grows in whole
+    nodes (35 to 45 here), so cos(theta)(f) is a line with a staircase of
+    that step on it: R^2 > 0.98 and a near-zero intercept."""
+    c, f0 = condensed_droplet()
+    p, s = c.params, c.solid
+    fs = np.array([0.0, 0.03, 0.06, 0.09, 0.12, 0.15])
+    cos = []
+    for fe in fs:
+        f = f0.copy()
+        q = p.replace(f_elec=fe)
+        O.step(q, s, f, 10_000)
+        r, _, _ = O.moments(q, s, f)
+        cos.append(np.cos(measure.contact_angle(r, s == 0, y_max=p.ny - 4)[0]))
+    d = np.array(cos) - cos[0]
+    A = np.stack([fs, np.ones_like(fs)], 1)
+    (slope, b), *_ = np.linalg.lstsq(A, d, rcond=None)
+    pred = A @ [slope, b]
+    r2 = 1 - ((d - pred) ** 2).sum() / ((d - d.mean()) ** 2).sum()
+    print(f"R29 droplet: slope {slope:.3f}, intercept {b:.2e}, R^2 {r2:.5f}, dcos {np.round(d, 4)}")
+    assert slope > 0 and r2 > 0.98 and abs(b) < 0.05 * d.max()
