@@ -213,6 +213,20 @@ lbm_status lbm_geometry(lbm_sim *sim, uint16_t *flags);
  * re-initialising (parameter sweeps).  Takes effect at the next lbm_step. */
 lbm_status lbm_set_forces(lbm_sim *sim, double f_elec, double accel_x, double accel_y);
 
+/* Per-node acceleration field: acc is a device float32 array [2][ny][nx]
+ * (the x components, then the y components; NULL removes the field).  Each
+ * fluid node then feels the body force rho (g + acc(x)) in place of rho g,
+ * through the velocity shift of eq. (10).  It carries forces that act on the
+ * fluid's mass in a prescribed pattern, such as the artificial attraction the
+ * paper applies to gather a homogeneous fluid into one droplet in the middle
+ * of the substrate before releasing it (the droplet run of its EWOD section).
+ * The caller owns acc and keeps it unchanged and alive while it is set (the
+ * kernels read it at every step).  Runs in LBM_KERNEL_FUSED with
+ * LBM_COLLIDE_BGK and nearest rounding only (LBM_EINVAL otherwise, also
+ * from lbm_set_kernel and lbm_autotune while a field is set).  Takes effect
+ * at the next lbm_step; drops captured graphs. */
+lbm_status lbm_set_accel_field(lbm_sim *sim, const float *acc);
+
 /* Kernel tile: block_x columns per workgroup (64, 128, 256 or 512; 128 or 256
  * for the split kernel) and about
  * rows_per_block rows marched by one workgroup; 0 picks as many row chunks as

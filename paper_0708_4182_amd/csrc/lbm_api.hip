@@ -36,6 +36,7 @@ struct lbm_sim {
     uint32_t *rowplain = nullptr;   // rows whose flag words are all plain (one bit per row)
     uint32_t *rng = nullptr;   // two-slot step counter of stochastic rounding
     uint32_t rng_host[2] = {0u, 0u};
+    const float *acc = nullptr;         // per-node acceleration field [2][ny][nx] (caller's device memory)
     double *static_scratch = nullptr;   // this device's copy of the library's static scratch (lbm_flux_static)
     std::string static_err;             // why static_scratch is NULL, if it is
     int cur = 0;
@@ -492,6 +493,7 @@ lbm::StepArgs step_args(lbm_sim *s) {
     a.dst = s->buf[s->cur ^ 1];
     a.rng = s->rng;
     a.par = s->cur;
+    a.acc = s->acc;
     return a;
 }
 
@@ -688,6 +690,20 @@ lbm_status lbm_set_tile(lbm_sim *s, int32_t block_x, int32_t rows) {
     return LBM_OK;
 }
 
+lbm_status lbm_set_accel_field(lbm_sim *s, const float *acc) {
+    lbm_status st = usable(s);
+    if (st) return st;
+    if (acc) {
+        if (s->m.trt || s->m.sround)
+            return fail(s, LBM_EINVAL, "an acceleration field runs with LBM_COLLIDE_BGK and nearest rounding only");
+        if (s->kernel != LBM_KERNEL_FUSED)
+            return fail(s, LBM_EINVAL, "an acceleration field runs in LBM_KERNEL_FUSED only");
+    }
+    s->acc = acc;
+    drop_graphs(s);
+    return LBM_OK;
+}
+
 lbm_status lbm_set_kernel(lbm_sim *s, int32_t kernel) {
     lbm_status st = usable(s);
     if (st) return st;
@@ -697,6 +713,8 @@ lbm_status lbm_set_kernel(lbm_sim *s, int32_t kernel) {
         return fail(s, LBM_EINVAL, "the TRT operator runs in LBM_KERNEL_FUSED and LBM_KERNEL_FUSED8 only");
     if (s->m.sround && kernel != LBM_KERNEL_FUSED && kernel != LBM_KERNEL_FUSED8)
         return fail(s, LBM_EINVAL, "stochastic rounding runs in LBM_KERNEL_FUSED and LBM_KERNEL_FUSED8 only");
+    if (s->acc && kernel != LBM_KERNEL_FUSED)
+        return fail(s, LBM_EINVAL, "an acceleration field runs in LBM_KERNEL_FUSED only");
     s->kernel = kernel;
     if (kernel == LBM_KERNEL_SPLIT && s->block_x != 128 && s->block_x != 256) s->block_x = 128;
     if ((kernel == LBM_KERNEL_WIDE2 || kernel == LBM_KERNEL_WIDE4) && s->block_x > 256) s->block_x = 256;
@@ -727,6 +745,7 @@ lbm_status lbm_get_tile(const lbm_sim *s, int32_t *kernel, int32_t *block_x, int
 lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *rows, float *us_per_step) {
     lbm_status st = usable(s);
     if (st) return st;
+    if (s->acc) return fail(s, LBM_EINVAL, "lbm_autotune: clear the acceleration field first");
     if (reps < 1) return fail(s, LBM_EINVAL, "reps must be >= 1");
     DeviceGuard dg(s->device);
     struct Cand { int kernel, bx; };

@@ -55,6 +55,9 @@ struct StepArgs {
     // the kernel writes the next count to the other slot).
     uint32_t *rng;
     int32_t par;
+    // Per-node acceleration field [2][ny][nx] (x plane, then y plane), added
+    // to (gx, gy); NULL for none (fused kernel, BGK, nearest rounding only).
+    const float *acc;
 };
 
 // One channel of a batch: its lattice, model and device arrays.

@@ -369,10 +369,13 @@ __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >
 // chunks of a strip run on the same XCD.
 constexpr int RING = 4;
 
-template <int S, bool TRT = false, bool SR = false>
+// EXT: a per-node acceleration field acc [2][ny][nx] (x plane, then y plane;
+// dense rows of nx) is added to the driving acceleration of each node.
+template <int S, bool TRT = false, bool SR = false, bool EXT = false>
 __device__ __forceinline__ void step_tile(const void *src_ptr, void *dst_ptr, const uint16_t *flags_ptr,
                                           const uint32_t *__restrict__ rowplain, const Grid &g, const Model &m,
-                                          int x0, int y0, int y1, bool up, float *ring, uint32_t mix = 0u) {
+                                          int x0, int y0, int y1, bool up, float *ring, uint32_t mix = 0u,
+                                          const float *__restrict__ acc = nullptr) {
     using C = Codec<S>;
     using T = typename C::T;
     const int BX = blockDim.x, W = BX + 2;
@@ -553,8 +556,18 @@ __device__ __forceinline__ void step_tile(const void *src_ptr, void *dst_ptr, co
             const float *mid = ring + ((i - 1) & (RING - 1)) * W;
             const float *rowm = up ? older : slot;
             const float *rowp = up ? slot : older;
-            collide_store<C, TRT, SR>(m, pd, ps, pjx, pjy, pfl, rowm, mid, rowp, tid + 1, rd, plane,
-                                      (uint32_t)pyr * pitch, v0, mix);
+            if constexpr (EXT) {
+                // the node's acceleration joins the uniform one: rho (g + acc)
+                const size_t k = (size_t)pyr * (size_t)nx + (size_t)x;
+                Model mx = m;
+                mx.gx = m.gx + acc[k];
+                mx.gy = m.gy + acc[(size_t)nx * (size_t)ny + k];
+                collide_store<C, TRT, SR>(mx, pd, ps, pjx, pjy, pfl, rowm, mid, rowp, tid + 1, rd, plane,
+                                          (uint32_t)pyr * pitch, v0, mix);
+            } else {
+                collide_store<C, TRT, SR>(m, pd, ps, pjx, pjy, pfl, rowm, mid, rowp, tid + 1, rd, plane,
+                                          (uint32_t)pyr * pitch, v0, mix);
+            }
         }
 #pragma unroll
         for (int q = 0; q < 9; ++q) pd[q] = cd[q];
@@ -566,7 +579,7 @@ __device__ __forceinline__ void step_tile(const void *src_ptr, void *dst_ptr, co
     }
 }
 
-template <int S, bool TRT, bool SR>
+template <int S, bool TRT, bool SR, bool EXT = false>
 __device__ __forceinline__ void step_tiles(const StepArgs &a, float *ring) {
     uint32_t mix = 0u;
     if constexpr (SR) mix = sr_step_mix(a.rng, a.par);
@@ -575,8 +588,8 @@ __device__ __forceinline__ void step_tiles(const StepArgs &a, float *ring) {
     const int strip = tile / a.chunks, chunk = tile - strip * a.chunks;
     const int y0 = (int)(((int64_t)chunk * a.g.ny) / a.chunks);
     const int y1 = (int)(((int64_t)(chunk + 1) * a.g.ny) / a.chunks);
-    step_tile<S, TRT, SR>(a.src, a.dst, a.flags, a.rowplain, a.g, a.m, strip * (int)blockDim.x, y0, y1, (chunk & 1) == 0,
-                          ring, mix);
+    step_tile<S, TRT, SR, EXT>(a.src, a.dst, a.flags, a.rowplain, a.g, a.m, strip * (int)blockDim.x, y0, y1,
+                               (chunk & 1) == 0, ring, mix, a.acc);
 }
 
 // TRT selects the collision operator and SR the rounding of 16-bit stores at
@@ -586,6 +599,14 @@ template <int S, bool TRT, bool SR>
 __global__ void __launch_bounds__(512) k_step(const StepArgs a) {
     extern __shared__ float ring[];
     step_tiles<S, TRT, SR>(a, ring);
+}
+
+// The fused kernel with a per-node acceleration field (StepArgs::acc), the
+// paper's collision operator and nearest rounding.
+template <int S>
+__global__ void __launch_bounds__(512) k_step_acc(const StepArgs a) {
+    extern __shared__ float ring[];
+    step_tiles<S, false, false, true>(a, ring);
 }
 
 // The same kernel compiled for 8 resident waves per SIMD (64 VGPRs) instead of
@@ -1432,7 +1453,12 @@ StepKernel step_kernel(int storage, bool trt, bool sr) {
 
 template <bool EIGHT>
 hipError_t launch_step_k(int storage, const StepArgs &a, int block_x, hipStream_t s) {
-    const StepKernel k = step_kernel<EIGHT>(storage, a.m.trt != 0, a.m.sround != 0);
+    StepKernel k = step_kernel<EIGHT>(storage, a.m.trt != 0, a.m.sround != 0);
+    if (a.acc) {            // fused kernel, paper operator, nearest rounding only (checked by the host)
+        if (EIGHT || a.m.trt || a.m.sround) return hipErrorInvalidValue;
+        k = storage == ST_F32 ? k_step_acc<ST_F32> : storage == ST_F16 ? k_step_acc<ST_F16>
+                                                                       : k_step_acc<ST_BF16>;
+    }
     if (!k) return hipErrorInvalidValue;
     const unsigned blocks = 8u * (unsigned)a.tiles_per_xcd;
     const size_t lds = (size_t)RING * (block_x + 2) * sizeof(float);

@@ -413,6 +413,64 @@ def warm_detect(train=2048, val=256, test=64, nx=256, ny=64, epochs=10, batch=32
     return res
 
 
+def paper_droplet(seed=0, gc=3e-4, t_attract=10_000, t_release=20_000, t_field=10_000,
+                  fs="0,0.03,0.06,0.09,0.12,0.15", nx=100, ny=50):
+    """The paper's droplet run on the GPU (reading R29 of eq. (4), inputs.paper_params):
+    a homogeneous fluid of density 0.85 in a 100 x 50 box gathered into one
+    droplet in the middle of the substrate by an artificial attraction of
+    magnitude gc (t_attract steps), released (t_release steps), then the
+    electric force f on the conductive single layer next to the substrate
+    for t_field steps from the released state, for every f in fs.
+    Returns the released droplet's contact angle, the density of the single
+    layer next to the substrate with its conductive interval [x1, x2] (the
+    paper's density figure), and theta and cos(theta) - cos(theta_0) per f
+    with their linear fit (the paper's eq. (9) figure)."""
+    import torch
+
+    from . import measure
+
+    c = I.paper_droplet_case(seed, nx=nx, ny=ny)
+    p, s = c.params, c.solid
+    fl = s == 0
+    t0 = time.perf_counter()
+    sim = lbm.from_case(c)
+    acc = torch.from_numpy(I.attraction_field(nx, ny, gc, s)).cuda()
+    sim.set_accel_field(acc)
+    sim.step(t_attract)
+    sim.set_accel_field(None)
+    sim.step(t_release)
+    rho = sim.moments()[0].astype(np.float64)
+    theta0, (xc, yc, R) = measure.contact_angle(rho, fl, y_max=ny - 4)
+    row = rho[1]
+    cond = np.nonzero(row >= p.rho_c)[0]
+    state = sim.save_state()
+    out = {"experiment": "paper_droplet", "box": [nx, ny], "seed": seed, "attraction": gc,
+           "t_attract": t_attract, "t_release": t_release, "t_field": t_field,
+           "theta0_deg": float(np.degrees(theta0)), "center": [float(xc), float(yc)], "radius": R,
+           "layer_rho": [round(float(v), 5) for v in row],
+           "x1": int(cond[0]) if len(cond) else None, "x2": int(cond[-1]) if len(cond) else None,
+           "rho_range": [float(rho[fl].min()), float(rho[fl].max())], "fig3": []}
+    cos0 = np.cos(theta0)
+    for fe in (float(v) for v in str(fs).split(",")):
+        sim.load_state(state)
+        sim.set_forces(fe, 0.0, 0.0)
+        sim.step(t_field)
+        r = sim.moments()[0].astype(np.float64)
+        th, _ = measure.contact_angle(r, fl, y_max=ny - 4)
+        out["fig3"].append({"f": fe, "theta_deg": float(np.degrees(th)), "dcos": float(np.cos(th) - cos0),
+                            "conductive_nodes": int((r[1] >= p.rho_c).sum())})
+    f_ = np.array([e["f"] for e in out["fig3"]])
+    d = np.array([e["dcos"] for e in out["fig3"]])
+    if len(f_) > 1:
+        A = np.stack([f_, np.ones_like(f_)], 1)
+        (slope, b), *_ = np.linalg.lstsq(A, d, rcond=None)
+        pred = A @ [slope, b]
+        out["fit"] = {"slope": float(slope), "intercept": float(b),
+                      "r2": float(1 - ((d - pred) ** 2).sum() / max(((d - d.mean()) ** 2).sum(), 1e-300))}
+    out["wall_seconds"] = time.perf_counter() - t0
+    return out
+
+
 def _kwargs(items):
     kw = {}
     for it in items:
@@ -431,7 +489,8 @@ def main(argv):
     name = argv[1] if len(argv) > 1 else "flux_vs_field"
     fn = {"flux_vs_field": flux_vs_field, "sweep_throughput": sweep_throughput,
           "sweep_steady": sweep_steady, "warm_start": warm_start, "channel_study": channel_study,
-          "small_configs": small_configs, "net_throughput": net_throughput, "warm_detect": warm_detect}[name]
+          "small_configs": small_configs, "net_throughput": net_throughput, "warm_detect": warm_detect,
+          "paper_droplet": paper_droplet}[name]
     print(json.dumps(fn(**_kwargs(argv[2:]))), flush=True)
 
 

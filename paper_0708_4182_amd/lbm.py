@@ -22,7 +22,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
 
 # Exported symbols of include/lbm.h (checked by the CPU tests).
 SYMBOLS = ("lbm_workspace_bytes", "lbm_init", "lbm_init_device", "lbm_step", "lbm_moments",
-           "lbm_flux", "lbm_flux_static", "lbm_stream_copy", "lbm_profile", "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_set_kernel",
+           "lbm_flux", "lbm_flux_static", "lbm_stream_copy", "lbm_profile", "lbm_geometry", "lbm_set_forces", "lbm_set_accel_field", "lbm_set_tile", "lbm_set_kernel",
            "lbm_set_graph",
            "lbm_get_tile",
            "lbm_autotune", "lbm_state_bytes",
@@ -99,6 +99,8 @@ def load_library():
     lib.lbm_set_forces.argtypes = [vp, C.c_double, C.c_double, C.c_double]
     lib.lbm_set_tile.argtypes = [vp, C.c_int32, C.c_int32]
     lib.lbm_set_kernel.argtypes = [vp, C.c_int32]
+    lib.lbm_set_accel_field.argtypes = [vp, vp]
+    lib.lbm_set_accel_field.restype = C.c_int
     lib.lbm_set_graph.argtypes = [vp, C.c_int32]
     lib.lbm_profile.argtypes = [vp, dp]
     lib.lbm_batch_profile.argtypes = [vp, C.c_int32, dp]
@@ -254,6 +256,20 @@ class Simulation:
         Q, M = C.c_double(), C.c_double()
         self._check(self.lib.lbm_flux(self.h, C.byref(Q), C.byref(M)))
         return Q.value, M.value
+
+    def set_accel_field(self, acc):
+        """Per-node acceleration field: a float32 device tensor [2][ny][nx]
+        (x components, then y components), or None to remove it.  The
+        tensor is kept referenced while it is set."""
+        if acc is None:
+            self._check(self.lib.lbm_set_accel_field(self.h, None))
+            self._acc = None
+            return
+        if (not acc.is_cuda or acc.dtype != self.torch.float32 or not acc.is_contiguous()
+                or tuple(acc.shape) != (2, self.ny, self.nx)):
+            raise ValueError(f"acceleration field must be a contiguous float32 device tensor [2][{self.ny}][{self.nx}]")
+        self._check(self.lib.lbm_set_accel_field(self.h, C.c_void_p(acc.data_ptr())))
+        self._acc = acc
 
     def flux_static(self):
         """flux() through lbm_flux_static: the reduction's scratch is the

@@ -34,7 +34,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from measure import contact_angle
+from paper_0708_4182_amd.measure import contact_angle
 from paper_0708_4182_amd import inputs as I
 
 pytestmark = pytest.mark.gpu

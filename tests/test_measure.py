@@ -1,4 +1,4 @@
-"""Pins of the contact-angle measurement (tests/measure.py) on synthetic
+"""Pins of the contact-angle measurement (paper_0708_4182_amd/measure.py) on synthetic
 droplets of known angle (CPU only).
 
 A tanh droplet profile rho(r) = (rho_l + rho_v)/2 - (rho_l - rho_v)/2 tanh(2(r - R)/W)
@@ -11,7 +11,7 @@ and the offset of cos(theta) = (y_w - y_c)/R and the wall plane y_w = 0.5.
 import numpy as np
 import pytest
 
-from measure import base_angle, contact_angle
+from paper_0708_4182_amd.measure import base_angle, contact_angle
 from paper_0708_4182_amd import inputs as I
 
 RL, RV, W = 2.0, 0.15, 2.0

@@ -17,7 +17,7 @@ form with G = 12 calG = -6.24.
 import numpy as np
 import pytest
 
-import measure
+from paper_0708_4182_amd import measure
 import oracle as O
 from paper_0708_4182_amd import inputs as I
 from test_oracle_physics import maxwell_coexistence

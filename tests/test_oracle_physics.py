@@ -20,7 +20,7 @@ import pytest
 from scipy.integrate import quad
 from scipy.optimize import fsolve
 
-import measure
+from paper_0708_4182_amd import measure
 import oracle as O
 from paper_0708_4182_amd import inputs as I
 
