@@ -8,6 +8,8 @@
 // channels are periodic in x and bounded by walls in y).
 #include "net_internal.h"
 
+#include <type_traits>
+
 namespace lbmnet {
 namespace {
 
@@ -477,30 +479,55 @@ __global__ void __launch_bounds__(256) k_conv3x3_mfma(View in, const __bf16 *__r
     for (int m = 0; m < NM; ++m)
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[m][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // Staging tasks of a thread: XT (pixel, 8 channels) gathers of the input
+    // tile and WT 16-byte loads of the packed weights.  All of a thread's
+    // global loads are issued before any of them is stored to LDS, so the
+    // chunk waits for memory once instead of once per task.
+    constexpr int XTASKS = (MCI / 8) * (MH + 2) * (MW + 2), XT = (XTASKS + 255) / 256;
+    constexpr int WTASKS = 9 * CO * (MCI / 8), WT = (WTASKS + 255) / 256;
     for (int ci0 = 0; ci0 < cin; ci0 += MCI) {
-        // one pixel and 8 channels per thread: 8 coalesced loads, one 16-byte LDS store
-        for (int e = tid; e < (MCI / 8) * (MH + 2) * (MW + 2); e += 256) {
+        bf16x8 xv[XT];
+        uint4 wv[WT];
+#pragma unroll
+        for (int k = 0; k < XT; ++k) {
+            const int e = tid + 256 * k;
             const int q = e % (MW + 2), r = (e / (MW + 2)) % (MH + 2), c8 = e / ((MW + 2) * (MH + 2));
             const int y = ty0 - 1 + r;
-            int x = tx0 - 1 + q;      // periodic in x; x < W + 33, so the loop ends
+            int x = tx0 - 1 + q;      // periodic in x
             if (x < 0) x += W;
-            while (x >= W) x -= W;
-            const bool row_ok = y >= 0 && y < H;
-            const TI *src = xin + (size_t)(row_ok ? y : 0) * W + x;
-            bf16x8 v;
+            if (x >= W) x -= W;
+            if (x >= W) x %= W;       // lattices narrower than a tile
+            const bool ok = e < XTASKS && y >= 0 && y < H;
+            const TI *src = xin + (size_t)(ok ? y : 0) * W + x;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int c = ci0 + 8 * c8 + j;
-                v[j] = (row_ok && c < cin) ? (__bf16)src[(size_t)c * H * W] : (__bf16)0.f;
+                xv[k][j] = (ok && c < cin) ? (__bf16)src[(size_t)c * H * W] : (__bf16)0.f;
             }
-            *reinterpret_cast<bf16x8 *>(&xs[(r * (MW + 2) + q) * MPS + 8 * c8]) = v;
         }
-        for (int e = tid; e < 9 * CO * (MCI / 8); e += 256) {
+#pragma unroll
+        for (int k = 0; k < WT; ++k) {
+            const int e = tid + 256 * k;
             const int c8 = e % (MCI / 8), co = (e / (MCI / 8)) % CO, t = e / ((MCI / 8) * CO);
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (co0 + co < cout)
-                v = *reinterpret_cast<const uint4 *>(wp + ((size_t)t * cout + co0 + co) * cin_pad + ci0 + 8 * c8);
-            *reinterpret_cast<uint4 *>(&ws[(t * CO + co) * MPS + 8 * c8]) = v;
+            wv[k] = make_uint4(0u, 0u, 0u, 0u);
+            if (e < WTASKS && co0 + co < cout)
+                wv[k] = *reinterpret_cast<const uint4 *>(wp + ((size_t)t * cout + co0 + co) * cin_pad + ci0 + 8 * c8);
+        }
+#pragma unroll
+        for (int k = 0; k < XT; ++k) {
+            const int e = tid + 256 * k;
+            if (e < XTASKS) {
+                const int q = e % (MW + 2), r = (e / (MW + 2)) % (MH + 2), c8 = e / ((MW + 2) * (MH + 2));
+                *reinterpret_cast<bf16x8 *>(&xs[(r * (MW + 2) + q) * MPS + 8 * c8]) = xv[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < WT; ++k) {
+            const int e = tid + 256 * k;
+            if (e < WTASKS) {
+                const int c8 = e % (MCI / 8), co = (e / (MCI / 8)) % CO, t = e / ((MCI / 8) * CO);
+                *reinterpret_cast<uint4 *>(&ws[(t * CO + co) * MPS + 8 * c8]) = wv[k];
+            }
         }
         __syncthreads();
 #pragma unroll 1
@@ -566,8 +593,127 @@ __device__ __forceinline__ int dw_col(int tx0, int c, int W) {
     return col < W ? col : -1;
 }
 
+// Staging of one tile: each thread's share of the dz rows, the x rows and the
+// x halo columns, loaded into registers in one batch (one wait for memory per
+// tile) and written to LDS afterwards.  VEC: whole, aligned 32-pixel rows move
+// as 16-byte loads; otherwise one value per load.
+template <bool VEC>
+struct DwStage {
+    static constexpr int DZ_T = VEC ? (DM_CO * DM_TR * (DM_TW / 8) + 255) / 256 : (DM_CO * DM_PX + 255) / 256;
+    static constexpr int X_T = VEC ? (DM_CI * (DM_TR + 2) * (DM_TW / 8) + 255) / 256
+                                   : (DM_CI * (DM_TR + 2) * DM_TW + 255) / 256;
+    static constexpr int H_T = (DM_CI * (DM_TR + 2) * 2 + 255) / 256;
+    using V = typename std::conditional<VEC, bf16x8, __bf16>::type;
+    V dzv[DZ_T], xv[X_T];
+    __bf16 hv[H_T];
+};
+
+template <bool VEC>
+__device__ __forceinline__ void dw_load(DwStage<VEC> &st, const View &x, const __bf16 *__restrict__ dz, int cin,
+                                        int cout, int co0, int ci0, int tile, int tiles_x, int tiles_y, int tid) {
+    const int H = x.H, W = x.W;
+    const int n = tile / (tiles_x * tiles_y), rem = tile % (tiles_x * tiles_y);
+    const int ty0 = (rem / tiles_x) * DM_TR, tx0 = (rem % tiles_x) * DM_TW;
+    const __bf16 *__restrict__ xin = static_cast<const __bf16 *>(x.p) + (size_t)n * x.bs;
+    const __bf16 *__restrict__ dzn = dz + (size_t)n * cout * H * W;
+    const __bf16 zero = (__bf16)0.f;
+    if constexpr (VEC) {
+#pragma unroll
+        for (int k = 0; k < DwStage<VEC>::DZ_T; ++k) {
+            const int e = tid + 256 * k;
+            const int q = (e % (DM_TW / 8)) * 8, j = (e / (DM_TW / 8)) % DM_TR, o = e / (DM_TR * DM_TW / 8);
+            const int y = ty0 + j;
+            st.dzv[k] = bf16x8{zero, zero, zero, zero, zero, zero, zero, zero};
+            if (e < DM_CO * DM_TR * (DM_TW / 8) && co0 + o < cout && y < H)
+                st.dzv[k] = *reinterpret_cast<const bf16x8 *>(&dzn[(size_t)(co0 + o) * H * W + (size_t)y * W + tx0 + q]);
+        }
+#pragma unroll
+        for (int k = 0; k < DwStage<VEC>::X_T; ++k) {
+            const int e = tid + 256 * k;
+            const int q = (e % (DM_TW / 8)) * 8, r = (e / (DM_TW / 8)) % (DM_TR + 2), c = e / ((DM_TR + 2) * DM_TW / 8);
+            const int y = ty0 - 1 + r;
+            st.xv[k] = bf16x8{zero, zero, zero, zero, zero, zero, zero, zero};
+            if (e < DM_CI * (DM_TR + 2) * (DM_TW / 8) && ci0 + c < cin && y >= 0 && y < H)
+                st.xv[k] = *reinterpret_cast<const bf16x8 *>(&xin[(size_t)(ci0 + c) * H * W + (size_t)y * W + tx0 + q]);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < DwStage<VEC>::DZ_T; ++k) {
+            const int e = tid + 256 * k;
+            const int o = e / DM_PX, p = e % DM_PX;
+            const int y = ty0 + p / DM_TW, xx = tx0 + p % DM_TW;
+            st.dzv[k] = zero;
+            if (e < DM_CO * DM_PX && co0 + o < cout && y < H && xx < W)
+                st.dzv[k] = dzn[(size_t)(co0 + o) * H * W + (size_t)y * W + xx];
+        }
+#pragma unroll
+        for (int k = 0; k < DwStage<VEC>::X_T; ++k) {
+            const int e = tid + 256 * k;
+            const int q = e % DM_TW, r = (e / DM_TW) % (DM_TR + 2), c = e / ((DM_TR + 2) * DM_TW);
+            const int y = ty0 - 1 + r, col = dw_col(tx0, q, W);
+            st.xv[k] = zero;
+            if (e < DM_CI * (DM_TR + 2) * DM_TW && ci0 + c < cin && y >= 0 && y < H && col >= 0)
+                st.xv[k] = xin[(size_t)(ci0 + c) * H * W + (size_t)y * W + col];
+        }
+    }
+    // halo columns -1 and 32 of every staged row
+#pragma unroll
+    for (int k = 0; k < DwStage<VEC>::H_T; ++k) {
+        const int e = tid + 256 * k;
+        const int side = e & 1, r = (e >> 1) % (DM_TR + 2), c = (e >> 1) / (DM_TR + 2);
+        const int y = ty0 - 1 + r, col = dw_col(tx0, side ? DM_TW : -1, W);
+        st.hv[k] = zero;
+        if (e < DM_CI * (DM_TR + 2) * 2 && ci0 + c < cin && y >= 0 && y < H && col >= 0)
+            st.hv[k] = xin[(size_t)(ci0 + c) * H * W + (size_t)y * W + col];
+    }
+}
+
+template <bool VEC>
+__device__ __forceinline__ void dw_store(const DwStage<VEC> &st, __bf16 *dzs, __bf16 *xs, int tid) {
+    if constexpr (VEC) {
+#pragma unroll
+        for (int k = 0; k < DwStage<VEC>::DZ_T; ++k) {
+            const int e = tid + 256 * k;
+            if (e >= DM_CO * DM_TR * (DM_TW / 8)) continue;
+            const int q = (e % (DM_TW / 8)) * 8, j = (e / (DM_TW / 8)) % DM_TR, o = e / (DM_TR * DM_TW / 8);
+            *reinterpret_cast<bf16x8 *>(&dzs[o * DM_DZS + j * DM_TW + q]) = st.dzv[k];
+        }
+#pragma unroll
+        for (int k = 0; k < DwStage<VEC>::X_T; ++k) {
+            const int e = tid + 256 * k;
+            if (e >= DM_CI * (DM_TR + 2) * (DM_TW / 8)) continue;
+            const int q = (e % (DM_TW / 8)) * 8, r = (e / (DM_TW / 8)) % (DM_TR + 2), c = e / ((DM_TR + 2) * DM_TW / 8);
+            *reinterpret_cast<bf16x8 *>(&xs[c * DM_XSC + r * DM_XR + 8 + q]) = st.xv[k];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < DwStage<VEC>::DZ_T; ++k) {
+            const int e = tid + 256 * k;
+            if (e >= DM_CO * DM_PX) continue;
+            dzs[(e / DM_PX) * DM_DZS + e % DM_PX] = st.dzv[k];
+        }
+#pragma unroll
+        for (int k = 0; k < DwStage<VEC>::X_T; ++k) {
+            const int e = tid + 256 * k;
+            if (e >= DM_CI * (DM_TR + 2) * DM_TW) continue;
+            const int q = e % DM_TW, r = (e / DM_TW) % (DM_TR + 2), c = e / ((DM_TR + 2) * DM_TW);
+            xs[c * DM_XSC + r * DM_XR + 8 + q] = st.xv[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < DwStage<VEC>::H_T; ++k) {
+        const int e = tid + 256 * k;
+        if (e >= DM_CI * (DM_TR + 2) * 2) continue;
+        const int side = e & 1, r = (e >> 1) % (DM_TR + 2), c = (e >> 1) / (DM_TR + 2);
+        xs[c * DM_XSC + r * DM_XR + (side ? 8 + DM_TW : 7)] = st.hv[k];
+    }
+}
+
+// The tiles of a chunk are software-pipelined: the next tile's loads are in
+// flight (in registers) while the current tile's products run from LDS.
+template <bool VEC>
 __global__ void __launch_bounds__(256) k_conv3x3_dw_mfma(View x, const __bf16 *__restrict__ dz, int N, int cin,
-                                                         int cout, int tiles_per_chunk, int vec,
+                                                         int cout, int tiles_per_chunk,
                                                          float *__restrict__ partial) {
     __shared__ __attribute__((aligned(16))) __bf16 dzs[DM_CO * DM_DZS];
     __shared__ __attribute__((aligned(16))) __bf16 xs[DM_CI * DM_XSC];
@@ -581,56 +727,13 @@ __global__ void __launch_bounds__(256) k_conv3x3_dw_mfma(View x, const __bf16 *_
     f32x4 acc[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const __bf16 zero = (__bf16)0.f;
     const int t_begin = chunk * tiles_per_chunk, t_end = min(ntiles, t_begin + tiles_per_chunk);
+    DwStage<VEC> st;
+    if (t_begin < t_end) dw_load<VEC>(st, x, dz, cin, cout, co0, ci0, t_begin, tiles_x, tiles_y, tid);
     for (int tile = t_begin; tile < t_end; ++tile) {
-        const int n = tile / (tiles_x * tiles_y), rem = tile % (tiles_x * tiles_y);
-        const int ty0 = (rem / tiles_x) * DM_TR, tx0 = (rem % tiles_x) * DM_TW;
-        const __bf16 *__restrict__ xin = static_cast<const __bf16 *>(x.p) + (size_t)n * x.bs;
-        const __bf16 *__restrict__ dzn = dz + (size_t)n * cout * H * W;
-        if (vec) {
-            // whole 32-pixel rows, 16-byte aligned: 8 dz or x values per load
-            for (int e = tid; e < DM_CO * DM_TR * (DM_TW / 8); e += 256) {
-                const int q = (e % (DM_TW / 8)) * 8, j = (e / (DM_TW / 8)) % DM_TR, o = e / (DM_TR * DM_TW / 8);
-                const int y = ty0 + j;
-                bf16x8 v = bf16x8{zero, zero, zero, zero, zero, zero, zero, zero};
-                if (co0 + o < cout && y < H)
-                    v = *reinterpret_cast<const bf16x8 *>(&dzn[(size_t)(co0 + o) * H * W + (size_t)y * W + tx0 + q]);
-                *reinterpret_cast<bf16x8 *>(&dzs[o * DM_DZS + j * DM_TW + q]) = v;
-            }
-            for (int e = tid; e < DM_CI * (DM_TR + 2) * (DM_TW / 8); e += 256) {
-                const int q = (e % (DM_TW / 8)) * 8, r = (e / (DM_TW / 8)) % (DM_TR + 2), c = e / ((DM_TR + 2) * DM_TW / 8);
-                const int y = ty0 - 1 + r;
-                bf16x8 v = bf16x8{zero, zero, zero, zero, zero, zero, zero, zero};
-                if (ci0 + c < cin && y >= 0 && y < H)
-                    v = *reinterpret_cast<const bf16x8 *>(&xin[(size_t)(ci0 + c) * H * W + (size_t)y * W + tx0 + q]);
-                *reinterpret_cast<bf16x8 *>(&xs[c * DM_XSC + r * DM_XR + 8 + q]) = v;
-            }
-        } else {
-            for (int e = tid; e < DM_CO * DM_PX; e += 256) {
-                const int o = e / DM_PX, p = e % DM_PX;
-                const int y = ty0 + p / DM_TW, xx = tx0 + p % DM_TW;
-                __bf16 v = zero;
-                if (co0 + o < cout && y < H && xx < W) v = dzn[(size_t)(co0 + o) * H * W + (size_t)y * W + xx];
-                dzs[o * DM_DZS + p] = v;
-            }
-            for (int e = tid; e < DM_CI * (DM_TR + 2) * DM_TW; e += 256) {
-                const int q = e % DM_TW, r = (e / DM_TW) % (DM_TR + 2), c = e / ((DM_TR + 2) * DM_TW);
-                const int y = ty0 - 1 + r, col = dw_col(tx0, q, W);
-                __bf16 v = zero;
-                if (ci0 + c < cin && y >= 0 && y < H && col >= 0) v = xin[(size_t)(ci0 + c) * H * W + (size_t)y * W + col];
-                xs[c * DM_XSC + r * DM_XR + 8 + q] = v;
-            }
-        }
-        // halo columns -1 and 32 of every staged row
-        for (int e = tid; e < DM_CI * (DM_TR + 2) * 2; e += 256) {
-            const int side = e & 1, r = (e >> 1) % (DM_TR + 2), c = (e >> 1) / (DM_TR + 2);
-            const int y = ty0 - 1 + r, col = dw_col(tx0, side ? DM_TW : -1, W);
-            __bf16 v = zero;
-            if (ci0 + c < cin && y >= 0 && y < H && col >= 0) v = xin[(size_t)(ci0 + c) * H * W + (size_t)y * W + col];
-            xs[c * DM_XSC + r * DM_XR + (side ? 8 + DM_TW : 7)] = v;
-        }
+        dw_store<VEC>(st, dzs, xs, tid);
         __syncthreads();
+        if (tile + 1 < t_end) dw_load<VEC>(st, x, dz, cin, cout, co0, ci0, tile + 1, tiles_x, tiles_y, tid);
         bf16x8 a[DM_TR];
 #pragma unroll
         for (int j = 0; j < DM_TR; ++j)
@@ -776,7 +879,8 @@ hipError_t conv3x3_dw_mfma(const View &x, const __bf16 *dz, int N, int cin, int 
     const int vec = x.W % DM_TW == 0 && hw % 8 == 0 && x.bs % 8 == 0 && (uintptr_t)x.p % 16 == 0 &&
                     (uintptr_t)dz % 16 == 0;
     const dim3 grid(chunks, (cout + DM_CO - 1) / DM_CO, (cin + DM_CI - 1) / DM_CI);
-    k_conv3x3_dw_mfma<<<grid, 256, 0, s>>>(x, dz, N, cin, cout, per, vec, partial);
+    if (vec) k_conv3x3_dw_mfma<true><<<grid, 256, 0, s>>>(x, dz, N, cin, cout, per, partial);
+    else k_conv3x3_dw_mfma<false><<<grid, 256, 0, s>>>(x, dz, N, cin, cout, per, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int n = cout * cin * 9;
