@@ -104,23 +104,31 @@ def small_configs(steps=2000, warmup=200, graph=50):
     return out
 
 
-def channel_study(widths="80,160", forces="0,5e-4,1e-3,1.5e-3,2e-3,3e-3", nx=256, storage=0,
-                  max_steps=400_000, check_every=200, window=4000, rtol=1e-8, layers=2, out=""):
+def channel_study(widths="80,160", forces="", nx=256, storage=0, max_steps=400_000, check_every=200,
+                  window=4000, rtol=1e-8, layers=2, out="", reading="configs"):
     """Rough channels of the paper's two widths (steps a = 8, b = 4, p = 32 on
     both walls, both walls electrodes) over a sweep of the electric force, all
     in one batch driven to steady flux: Q / Q0 per width and the
-    channel-averaged velocity profiles (the paper's flux and velocity figures)
-    in the normalisation of reading R1.  Writes profiles.npz and study.json
-    under ``out`` if given."""
+    channel-averaged velocity profiles (the paper's flux and velocity figures).
+    reading "configs": the normalisation of reading R1 (G = -5), fields
+    0..3e-3 on ``layers`` layers; reading "paper": the paper's own parameters
+    under reading R29 (calG = -0.52, w = -0.14, tau = 0.9, f_b = 8e-6), its
+    fields 0..0.25 on the single layer next to the walls.  Writes
+    profiles.npz and study.json under ``out`` if given."""
     import json
     import os
     import torch
+    if not forces:
+        forces = "0,0.05,0.1,0.15,0.2,0.25" if reading == "paper" else "0,5e-4,1e-3,1.5e-3,2e-3,3e-3"
     ws = [int(v) for v in str(widths).split(",")]
     fs = [float(v) for v in str(forces).split(",")]
     cases, keys = [], []
     for w in ws:
         for f in fs:
-            cases.append(I.rough_channel_case(nx=nx, ny=w, f_elec=f, seed=0, layers=layers, storage=storage))
+            if reading == "paper":
+                cases.append(I.paper_channel_case(nx=nx, ny=w, f_elec=f, seed=0, storage=storage))
+            else:
+                cases.append(I.rough_channel_case(nx=nx, ny=w, f_elec=f, seed=0, layers=layers, storage=storage))
             keys.append((w, f))
     b = lbm.Batch(cases)
     b.autotune(reps=3)
@@ -137,8 +145,18 @@ def channel_study(widths="80,160", forces="0,5e-4,1e-3,1.5e-3,2e-3,3e-3", nx=256
                                "Q_over_Q0": float(res.Q[keys.index((w, f))] / q0),
                                "steps": int(res.steps[keys.index((w, f))]),
                                "converged": bool(res.converged[keys.index((w, f))])} for f in fs}
-    summary = {"experiment": "channel_study", "nx": nx, "widths": ws, "forces": fs, "storage": storage,
-               "layers": layers, "wall_s": wall, "node_updates": res.node_updates, "table": table}
+    asym = {}
+    for i, (w, f) in enumerate(keys):
+        # liquid nodes in the lower half minus the upper half, over all liquid nodes: 0 for a
+        # liquid that stays in the middle, +-1 for one absorbed by one wall
+        rho = b.moments(i)[0]
+        fluid = cases[i].solid == 0
+        liq = (rho >= cases[i].params.rho_c) & fluid
+        lo, hi = liq[: w // 2].sum(), liq[w // 2:].sum()
+        asym[f"{w}/{f:g}"] = float((lo - hi) / max(lo + hi, 1))
+    summary = {"experiment": "channel_study", "reading": reading, "nx": nx, "widths": ws, "forces": fs,
+               "storage": storage, "layers": 1 if reading == "paper" else layers, "wall_s": wall,
+               "node_updates": res.node_updates, "table": table, "liquid_asymmetry": asym}
     if out:
         os.makedirs(out, exist_ok=True)
         np.savez(os.path.join(out, "profiles.npz"), keys=np.array(keys), **{f"p{i}": p for i, p in enumerate(prof)})

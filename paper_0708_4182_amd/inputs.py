@@ -263,6 +263,31 @@ def paper_droplet_case(seed: int = 0, nx: int = 100, ny: int = 50, noise_amp: fl
     return Case(p, solid, rho, name=f"paper_droplet{nx}x{ny}_s{seed}")
 
 
+# Flat-interface coexistence densities of the lattice model under reading R29
+# (vapour, liquid), from a settled slab in the oracle (tests/test_oracle_paper_droplet.py).
+PAPER_COEX = (0.0426, 2.83)
+PAPER_BODY_FORCE = 8.0e-6      # the rightward body force f_b of the paper's channel runs
+
+
+def paper_channel_case(nx: int = 256, ny: int = 80, f_elec: float = 0.0, seed: int = 0, a: int = 8, b: int = 4,
+                       p: int = 32, vapor_layer: int = 2, noise_amp: float = 1e-3, storage: int = 0) -> Case:
+    """The paper's rough-wall channel run under reading R29: steps of width a,
+    height b and pitch p on both walls (random phases), width ny, periodic in
+    x; liquid with a vapour layer within ``vapor_layer`` nodes of the walls;
+    both walls electrodes with the electric force on the single fluid layer
+    next to them; the rightward body force f_b = 8e-6 applied as rho g with
+    g = f_b (per unit density, the form of the other channel runs)."""
+    solid = periodic_bumps(nx, ny, a, b, p, seed)
+    rv, rl = PAPER_COEX
+    near = chebyshev_dilate(solid, vapor_layer)
+    rho = np.where(near, rv, rl).astype(np.float64)
+    prm = paper_params(nx, ny, f_elec=f_elec, elec_walls=ELEC_BOTTOM | ELEC_TOP, accel_x=PAPER_BODY_FORCE,
+                       storage=storage, rho_ref=rl)
+    if noise_amp:
+        rho = rho + noise(seed, rho.shape, noise_amp)
+    return Case(prm, solid, rho, name=f"paper_channel{nx}x{ny}_f{f_elec:g}_s{seed}")
+
+
 def attraction_field(nx: int, ny: int, g: float, solid: np.ndarray | None = None,
                      cx: float | None = None, cy: float = 0.5) -> np.ndarray:
     """Acceleration of magnitude g towards the point (cx, cy) (default: the
