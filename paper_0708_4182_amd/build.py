@@ -39,7 +39,25 @@ def build(verbose: bool = False) -> str:
     if noise and verbose:
         print("\n".join(noise), file=sys.stderr)
     os.replace(tmp, LIB)
+    build_driver(verbose)
     return LIB
+
+
+DRIVER = os.path.join(HERE, "step_driver")
+
+
+def build_driver(verbose: bool = False) -> str:
+    """The standalone profiling driver (csrc/step_driver.cpp), linked to liblbm.so."""
+    tmp = DRIVER + ".tmp"
+    cmd = [hipcc(), "--offload-arch=gfx950", "-O2", "-std=c++17", "-I", INCLUDE, "-o", tmp,
+           os.path.join(CSRC, "step_driver.cpp"), "-L", HERE, "-llbm", "-Wl,-rpath,$ORIGIN"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed (step_driver):\n" + res.stderr)
+    os.replace(tmp, DRIVER)
+    return DRIVER
 
 
 if __name__ == "__main__":

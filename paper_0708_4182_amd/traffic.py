@@ -3,11 +3,11 @@
     python -m paper_0708_4182_amd.traffic FETCH_DIR WRITE_DIR --tile fused8:512x0
 
 FETCH_DIR and WRITE_DIR hold the pmc_counter_collection.csv of a
-``rocprofv3 --pmc FETCH_SIZE`` and a ``--pmc WRITE_SIZE`` run of
-``bench.py --no-batch --no-cpu-baseline --tile T`` on the 8192 x 2048 channel
-(one run per tile and counter).  Each counter is scaled by what it reads for
-the device copy of one FP32 population buffer that bench.py times in the same
-run (__amd_rocclr_copyBuffer, 9 * nx * ny * 4 bytes each way).  The result is
+``rocprofv3 --pmc FETCH_SIZE`` and a ``--pmc WRITE_SIZE`` run of the profiling
+driver (csrc/step_driver.cpp) on the 8192 x 2048 channel (one run per tile and
+counter).  Each counter is scaled by what it reads for the copy of one FP32
+population buffer in the same run (k_stream_copy, 9 * nx * ny * 4 bytes each
+way; torch's __amd_rocclr_copyBuffer in runs of bench.py).  The result is
 merged into profiles/traffic.json, keyed by storage and tile and stamped with
 the hash of the kernel source, and printed as a markdown table.
 """
@@ -77,9 +77,13 @@ def main():
     write = per_kernel(args.write_dir, "WRITE_SIZE")
 
     def copy_kib(d):
-        vals = [v for name, rows_ in d.items() if "copyBuffer" in name for g, v in rows_]
-        big = max(vals)
-        return mean([v for v in vals if v > 0.9 * big])
+        # the library's streaming copy (the profiling driver's calibration), else torch's device copy
+        for key in ("k_stream_copy", "copyBuffer"):
+            vals = [v for name, rows_ in d.items() if key in name for g, v in rows_]
+            if vals:
+                big = max(vals)
+                return mean([v for v in vals if v > 0.9 * big])
+        raise SystemExit("no calibration copy dispatch in the counter runs")
 
     ff = copy_bytes / 1024 / copy_kib(fetch)
     wf = copy_bytes / 1024 / copy_kib(write)
