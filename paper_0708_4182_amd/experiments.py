@@ -45,17 +45,25 @@ def flux_vs_field(nx=1024, ny=128, fs=(0.0, 5e-4, 1e-3, 1.5e-3, 2e-3), seed=0, s
             "steps": res.steps.tolist(), "converged": res.converged.tolist(), "seconds": dt}
 
 
-def sweep_throughput(n=256, seed=0, storage=1, steps=60, warmup=20, graph=10, tune=True, rounding=1):
+def sweep_throughput(n=256, seed=0, storage=1, steps=60, warmup=20, graph=10, tune=True, rounding=1, tile=""):
+    """The sweep table's batched step: time per step over ``steps`` steps (hipGraph
+    replays of ``graph`` steps).  ``tile`` "block_x,rows" fixes the tile (no
+    autotune trial launches, for profiler traces); else ``tune`` autotunes."""
     import torch
     rows = I.sweep_table(n, seed)
     cases = [I.sweep_case(r, storage=storage, rounding=rounding) for r in rows]
     nodes = sum(c.params.nx * c.params.ny for c in cases)
     fluid = sum(int((c.solid == 0).sum()) for c in cases)
     b = lbm.Batch(cases)
-    tile = None
-    if tune:
+    if tile:
+        bx, r = (int(v) for v in str(tile).split(","))
+        b.set_tile(bx, r)
+        tile = [bx, r]
+    elif tune:
         bx, r, us = b.autotune(reps=3)
         tile = [bx, r]
+    else:
+        tile = None
     b.set_graph(graph)
     b.step(warmup)
     b.flux()
