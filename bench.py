@@ -45,6 +45,7 @@ KERNEL_NAMES = {
     "wide4": "k_step_wide<4> (the fused step, four adjacent columns per thread)",
     "split": "k_step_split (producer wave streams rows into LDS; compute waves collide and store)",
     "fused8": "k_step8 (the fused step compiled for 8 waves per SIMD, one column per thread)",
+    "two": "k_step2 (two time steps per launch, the first step's results in LDS: temporal blocking)",
 }
 
 

@@ -45,7 +45,9 @@ struct lbm_sim {
     int rows = 0;          // rows per chunk; 0 = one wave of resident workgroups
     int kernel = LBM_KERNEL_FUSED;
     int cus = 0;           // compute units of the device
+    int max_lds = 0;       // LDS bytes one workgroup may use on the device
     int chunks = 0;        // cached tiling (0 = recompute)
+    int chunks1 = 0;       // cached tiling of the fused kernel, which runs the odd step of LBM_KERNEL_TWO
     int graph_steps = 0;   // steps per hipGraph replay (0: eager launches only)
     hipStream_t cap = nullptr;                  // private stream used only for graph capture
     hipGraph_t graph[2] = {nullptr, nullptr};   // per source-buffer parity
@@ -372,7 +374,8 @@ lbm_status lbm_init(lbm_sim **out, const lbm_params *p, const uint8_t *solid, co
     s->m = make_model(p);
     s->stream = (hipStream_t)stream;
     if (hipGetDevice(&s->device) != hipSuccess ||
-        hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess) {
+        hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess ||
+        hipDeviceGetAttribute(&s->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, s->device) != hipSuccess) {
         delete s;
         return fail(nullptr, LBM_EDEVICE, "cannot query the current HIP device");
     }
@@ -448,19 +451,21 @@ lbm_status lbm_init_device(lbm_sim *s, const float *rho, const float *ux, const 
 }
 
 namespace {
-// Columns of one strip (one workgroup's width) for the handle's kernel.
-int strip_columns(const lbm_sim *s) {
-    switch (s->kernel) {
+// Columns of one strip (one workgroup's output width) for a kernel.
+int strip_columns(const lbm_sim *s, int kernel) {
+    switch (kernel) {
     case LBM_KERNEL_WIDE2: return 2 * s->block_x;
     case LBM_KERNEL_WIDE4: return 4 * s->block_x;
+    case LBM_KERNEL_TWO: return s->block_x - 6;
     default: return s->block_x;
     }
 }
 
-// Launch arguments of the step kernel for the handle's current tile.
-lbm::StepArgs step_args(lbm_sim *s) {
-    const int cols = strip_columns(s);
-    if (s->chunks == 0) {
+// Launch arguments of a step kernel for the handle's current tile; `cache`
+// holds that kernel's row chunking (0 = recompute).
+lbm::StepArgs step_args_for(lbm_sim *s, int kernel, int &cache) {
+    const int cols = strip_columns(s, kernel);
+    if (cache == 0) {
         const int strips = (s->p.nx + cols - 1) / cols;
         int chunks;
         if (s->rows > 0) {
@@ -468,7 +473,8 @@ lbm::StepArgs step_args(lbm_sim *s) {
         } else {
             // one wave of resident workgroups, chunks of at least 8 rows
             int per_cu;
-            switch (s->kernel) {
+            switch (kernel) {
+            case LBM_KERNEL_TWO: per_cu = lbm::step2_blocks_per_cu(s->p.storage, s->block_x, s->m.trt != 0, s->m.sround != 0); break;
             case LBM_KERNEL_SPLIT: per_cu = lbm::split_blocks_per_cu(s->p.storage, s->block_x); break;
             case LBM_KERNEL_WIDE2: per_cu = lbm::wide_blocks_per_cu(s->p.storage, s->block_x, 2); break;
             case LBM_KERNEL_WIDE4: per_cu = lbm::wide_blocks_per_cu(s->p.storage, s->block_x, 4); break;
@@ -479,15 +485,15 @@ lbm::StepArgs step_args(lbm_sim *s) {
             chunks = std::max(1, cap / strips);
             chunks = std::min(chunks, std::max(1, s->p.ny / 8));
         }
-        s->chunks = std::max(1, std::min(chunks, s->p.ny));
+        cache = std::max(1, std::min(chunks, s->p.ny));
     }
     lbm::StepArgs a;
     a.flags = s->flags;
     a.rowplain = s->rowplain;
     a.g = s->g;
     a.m = s->m;
-    a.chunks = s->chunks;
-    a.ntiles = ((s->p.nx + cols - 1) / cols) * s->chunks;
+    a.chunks = cache;
+    a.ntiles = ((s->p.nx + cols - 1) / cols) * cache;
     a.tiles_per_xcd = (a.ntiles + 7) / 8;
     a.src = s->buf[s->cur];
     a.dst = s->buf[s->cur ^ 1];
@@ -497,8 +503,11 @@ lbm::StepArgs step_args(lbm_sim *s) {
     return a;
 }
 
+lbm::StepArgs step_args(lbm_sim *s) { return step_args_for(s, s->kernel, s->chunks); }
+
 hipError_t launch_on(const lbm_sim *s, const lbm::StepArgs &a, hipStream_t st) {
     switch (s->kernel) {
+    case LBM_KERNEL_TWO: return lbm::launch_step2(s->p.storage, a, s->block_x, st);
     case LBM_KERNEL_SPLIT: return lbm::launch_step_split(s->p.storage, a, s->block_x, st);
     case LBM_KERNEL_WIDE2: return lbm::launch_step_wide(s->p.storage, a, s->block_x, 2, st);
     case LBM_KERNEL_WIDE4: return lbm::launch_step_wide(s->p.storage, a, s->block_x, 4, st);
@@ -519,7 +528,17 @@ void drop_graphs(lbm_sim *s) {
     }
 }
 
-// Capture graph_steps launches starting from buffer `parity` on the private
+// The two-step kernel's LDS at this block_x fits one workgroup on the device.
+bool two_fits(const lbm_sim *s, int block_x) {
+    return lbm::step2_lds_bytes(s->p.storage, block_x) <= (size_t)s->max_lds;
+}
+
+// Launches of one graph replay: LBM_KERNEL_TWO advances two steps per launch.
+int launches_per_graph(const lbm_sim *s) {
+    return s->kernel == LBM_KERNEL_TWO ? s->graph_steps / 2 : s->graph_steps;
+}
+
+// Capture the launches of graph_steps steps starting from buffer `parity` on the private
 // stream (kernel launches only: no memset or copy nodes).
 lbm_status capture_graph(lbm_sim *s, int parity) {
     if (!s->cap && hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking) != hipSuccess) {
@@ -529,7 +548,7 @@ lbm_status capture_graph(lbm_sim *s, int parity) {
     lbm::StepArgs a = step_args(s);
     HIP_TRY(s, hipStreamBeginCapture(s->cap, hipStreamCaptureModeRelaxed));
     hipError_t e = hipSuccess;
-    for (int k = 0; k < s->graph_steps && e == hipSuccess; ++k) {
+    for (int k = 0; k < launches_per_graph(s) && e == hipSuccess; ++k) {
         const int from = parity ^ (k & 1);
         a.src = s->buf[from];
         a.dst = s->buf[from ^ 1];
@@ -564,16 +583,27 @@ lbm_status lbm_step(lbm_sim *s, int64_t nsteps) {
         while (left >= s->graph_steps) {
             if (!s->gexec[s->cur] && (st = capture_graph(s, s->cur)) != LBM_OK) return st;
             HIP_TRY(s, hipGraphLaunch(s->gexec[s->cur], s->stream));
-            left -= s->graph_steps;     // an even number of steps: the parity is unchanged
+            left -= s->graph_steps;
             s->steps += s->graph_steps;
+            if (launches_per_graph(s) & 1) s->cur ^= 1;     // each launch flips the buffer parity
         }
     }
     lbm::StepArgs a = step_args(s);
-    for (int64_t k = 0; k < left; ++k) {
+    const int per_launch = s->kernel == LBM_KERNEL_TWO ? 2 : 1;
+    for (; left >= per_launch; left -= per_launch) {
         a.src = s->buf[s->cur];
         a.dst = s->buf[s->cur ^ 1];
         a.par = s->cur;
         HIP_TRY(s, launch(s, a));
+        s->cur ^= 1;
+        s->steps += per_launch;
+    }
+    if (left) {     // the odd step of LBM_KERNEL_TWO: one fused-kernel step at the same block_x
+        lbm::StepArgs b = step_args_for(s, LBM_KERNEL_FUSED, s->chunks1);
+        b.src = s->buf[s->cur];
+        b.dst = s->buf[s->cur ^ 1];
+        b.par = s->cur;
+        HIP_TRY(s, lbm::launch_step(s->p.storage, b, s->block_x, s->stream));
         s->cur ^= 1;
         ++s->steps;
     }
@@ -682,10 +712,16 @@ lbm_status lbm_set_tile(lbm_sim *s, int32_t block_x, int32_t rows) {
         return fail(s, LBM_EINVAL, "the split kernel takes block_x 128 or 256");
     if ((s->kernel == LBM_KERNEL_WIDE2 || s->kernel == LBM_KERNEL_WIDE4) && block_x > 256)
         return fail(s, LBM_EINVAL, "the wide kernels take block_x 64, 128 or 256");
+    if (s->kernel == LBM_KERNEL_TWO && block_x < 128)
+        return fail(s, LBM_EINVAL, "the two-step kernel takes block_x 128, 256 or 512");
+    if (s->kernel == LBM_KERNEL_TWO && !two_fits(s, block_x))
+        return fail(s, LBM_EINVAL, "the two-step kernel at block_x %d needs %zu bytes of LDS per workgroup (device: %d)",
+                    block_x, lbm::step2_lds_bytes(s->p.storage, block_x), s->max_lds);
     if (rows < 0) return fail(s, LBM_EINVAL, "rows_per_block must be >= 0");
     s->block_x = block_x;
     s->rows = rows;
     s->chunks = 0;
+    s->chunks1 = 0;
     drop_graphs(s);
     return LBM_OK;
 }
@@ -707,18 +743,22 @@ lbm_status lbm_set_accel_field(lbm_sim *s, const float *acc) {
 lbm_status lbm_set_kernel(lbm_sim *s, int32_t kernel) {
     lbm_status st = usable(s);
     if (st) return st;
-    if (kernel < LBM_KERNEL_FUSED || kernel > LBM_KERNEL_FUSED8)
-        return fail(s, LBM_EINVAL, "kernel must be one of LBM_KERNEL_FUSED, _SPLIT, _WIDE2, _WIDE4, _FUSED8");
-    if (s->m.trt && kernel != LBM_KERNEL_FUSED && kernel != LBM_KERNEL_FUSED8)
-        return fail(s, LBM_EINVAL, "the TRT operator runs in LBM_KERNEL_FUSED and LBM_KERNEL_FUSED8 only");
-    if (s->m.sround && kernel != LBM_KERNEL_FUSED && kernel != LBM_KERNEL_FUSED8)
-        return fail(s, LBM_EINVAL, "stochastic rounding runs in LBM_KERNEL_FUSED and LBM_KERNEL_FUSED8 only");
+    if (kernel < LBM_KERNEL_FUSED || kernel > LBM_KERNEL_TWO)
+        return fail(s, LBM_EINVAL, "kernel must be one of LBM_KERNEL_FUSED, _SPLIT, _WIDE2, _WIDE4, _FUSED8, _TWO");
+    const bool trt_sr_ok = kernel == LBM_KERNEL_FUSED || kernel == LBM_KERNEL_FUSED8 || kernel == LBM_KERNEL_TWO;
+    if (s->m.trt && !trt_sr_ok)
+        return fail(s, LBM_EINVAL, "the TRT operator runs in LBM_KERNEL_FUSED, _FUSED8 and _TWO only");
+    if (s->m.sround && !trt_sr_ok)
+        return fail(s, LBM_EINVAL, "stochastic rounding runs in LBM_KERNEL_FUSED, _FUSED8 and _TWO only");
     if (s->acc && kernel != LBM_KERNEL_FUSED)
         return fail(s, LBM_EINVAL, "an acceleration field runs in LBM_KERNEL_FUSED only");
     s->kernel = kernel;
     if (kernel == LBM_KERNEL_SPLIT && s->block_x != 128 && s->block_x != 256) s->block_x = 128;
     if ((kernel == LBM_KERNEL_WIDE2 || kernel == LBM_KERNEL_WIDE4) && s->block_x > 256) s->block_x = 256;
+    if (kernel == LBM_KERNEL_TWO && s->block_x < 128) s->block_x = 128;
+    if (kernel == LBM_KERNEL_TWO && !two_fits(s, s->block_x)) s->block_x = 256;
     s->chunks = 0;
+    s->chunks1 = 0;
     drop_graphs(s);
     return LBM_OK;
 }
@@ -753,7 +793,8 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *row
                                  {LBM_KERNEL_FUSED, 512}, {LBM_KERNEL_WIDE2, 64},  {LBM_KERNEL_WIDE2, 128},
                                  {LBM_KERNEL_WIDE2, 256}, {LBM_KERNEL_WIDE4, 64},  {LBM_KERNEL_WIDE4, 128},
                                  {LBM_KERNEL_SPLIT, 128}, {LBM_KERNEL_SPLIT, 256}, {LBM_KERNEL_FUSED8, 128},
-                                 {LBM_KERNEL_FUSED8, 256}, {LBM_KERNEL_FUSED8, 512}};
+                                 {LBM_KERNEL_FUSED8, 256}, {LBM_KERNEL_FUSED8, 512}, {LBM_KERNEL_TWO, 128},
+                                 {LBM_KERNEL_TWO, 256},    {LBM_KERNEL_TWO, 512}};
     static const int kRows[] = {0, 4, 8, 16, 32, 64, 128};
     hipEvent_t e0, e1;
     HIP_TRY(s, hipEventCreate(&e0));
@@ -767,14 +808,17 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *row
     lbm_status res = LBM_OK;
     for (const Cand &cand : kCand) {
         const int bx = cand.bx;
-        if ((s->m.trt || s->m.sround) && cand.kernel != LBM_KERNEL_FUSED && cand.kernel != LBM_KERNEL_FUSED8)
+        if ((s->m.trt || s->m.sround) && cand.kernel != LBM_KERNEL_FUSED && cand.kernel != LBM_KERNEL_FUSED8 &&
+            cand.kernel != LBM_KERNEL_TWO)
             continue;
+        if (cand.kernel == LBM_KERNEL_TWO && !two_fits(s, bx)) continue;
         for (int r : kRows) {
             if (r > 0 && r >= s->p.ny) continue;
             s->kernel = cand.kernel;
             s->block_x = bx;
             s->rows = r;
             s->chunks = 0;
+            s->chunks1 = 0;
             // trial launches read the current buffer and write the spare one,
             // so the state is left as it was
             lbm::StepArgs a = step_args(s);
@@ -789,7 +833,8 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *row
                 res = fail(s, LBM_EDEVICE, "autotune trial %dx%d failed: %s", bx, r, hipGetErrorString(e));
                 break;
             }
-            const float us = 1000.f * ms / (float)reps;
+            // per step: a launch of LBM_KERNEL_TWO advances two
+            const float us = 1000.f * ms / (float)reps / (cand.kernel == LBM_KERNEL_TWO ? 2.f : 1.f);
             if (best == 0.f || us < best) {
                 best = us;
                 best_bx = bx;
@@ -807,12 +852,14 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *row
         s->block_x = keep_bx;
         s->rows = keep_rows;
         s->chunks = 0;
+        s->chunks1 = 0;
         return res;
     }
     s->kernel = best_kernel;
     s->block_x = best_bx;
     s->rows = best_rows;
     s->chunks = 0;
+    s->chunks1 = 0;
     if (block_x) *block_x = best_bx;
     if (rows) *rows = best_rows;
     if (us_per_step) *us_per_step = best;

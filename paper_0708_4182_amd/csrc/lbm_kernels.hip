@@ -622,6 +622,241 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8, 8))
 }
 
 // ---------------------------------------------------------------------------
+// Two time steps per launch (temporal blocking).  A step moves every
+// population through HBM once each way; two steps in one pass move them once
+// for both, with the intermediate post-collision rows kept in LDS in the
+// storage format (so that the result is bitwise that of two single steps:
+// the second step decodes exactly what the first would have stored).
+//
+// A workgroup of BX threads covers BX - 6 output columns: thread t works on
+// column x0 - 3 + t (periodic), and each level of the dependency chain uses
+// up one column on each side: the first step's collision needs phi of both
+// x-neighbours, the second step pulls from both, and its collision again
+// needs their phi.  For the same reason a chunk of rows [y0, y1) marches
+// through rows y0 - 3 .. y1 + 2.  Iteration i of the march (row a_i):
+//   A: pull row a_i from HBM (prefetched one row ahead), rho and phi of the
+//      first step, phi and the flag word into LDS rings;            barrier
+//   B: first collision of row a_{i-1} (phi of rows a_{i-2..i}), its nine
+//      results, encoded, into the LDS ring F;                       barrier
+//   C: second pull of row a_{i-2} from F (rows a_{i-3..i-1}, bounce-back from
+//      the node's own results), rho and phi of the second step;     barrier
+//   D: second collision of row a_{i-3} (phi rows a_{i-4..i-2}) and its store.
+// Rings hold four rows; each row slot is rewritten only after a barrier that
+// follows its last read.  Threads outside [3, 3 + nact) and rows outside the
+// chunk are computed for their neighbours and not stored.
+template <int S>
+constexpr size_t two_lds_bytes(int bx) {
+    return (size_t)2 * 4 * (bx + 2) * sizeof(float) + (size_t)4 * bx * sizeof(uint32_t) +
+           (size_t)4 * 9 * (bx + 2) * sizeof(typename Codec<S>::T);
+}
+
+template <int S, bool TRT, bool SR>
+__device__ __forceinline__ void step2_tile(const StepArgs &a, int x0, int y0, int y1, bool up, char *lds,
+                                           uint32_t mix0, uint32_t mix1) {
+    using C = Codec<S>;
+    using T = typename C::T;
+    constexpr uint32_t E = sizeof(T);
+    const Grid &g = a.g;
+    const Model &m = a.m;
+    const int BX = blockDim.x, P = BX + 2;   // ring rows carry one padding slot per side
+    const int tid = threadIdx.x;
+    const int nx = g.nx, ny = g.ny;
+    const uint32_t pitch = (uint32_t)g.pitch, plane = g.plane;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.src, 9u * plane * E);
+    const __amdgpu_buffer_rsrc_t rd = make_rsrc(a.dst, 9u * plane * E);
+    const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.flags, plane * 2u);
+    const int nrows = y1 - y0 + 6;
+
+    const int nact = min(BX - 6, nx - x0);
+    const bool out_col = tid >= 3 && tid < 3 + nact;
+    int xc = (x0 - 3 + tid) % nx;
+    if (xc < 0) xc += nx;
+    const uint32_t x = (uint32_t)xc;
+    const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x == (uint32_t)nx - 1 ? 0 : x + 1;
+
+    float *psiA = reinterpret_cast<float *>(lds);      // phi of the first step  [4][P]
+    float *psiB = psiA + 4 * P;                         // phi of the second step [4][P]
+    uint32_t *flr = reinterpret_cast<uint32_t *>(psiB + 4 * P);   // flag words [4][BX]
+    T *F = reinterpret_cast<T *>(flr + 4 * BX);         // first-step results [4][9][P]
+    if (tid < 8) {      // padding slots (read only by threads whose results are unused)
+        const int k = tid >> 1, side = (tid & 1) ? P - 1 : 0;
+        psiA[k * P + side] = 0.f;
+        psiB[k * P + side] = 0.f;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) F[(k * 9 + q) * P + side] = C::enc(0.f);
+    }
+
+    auto row_at = [&](int i) { return wrapi(up ? y0 - 3 + i : y1 + 2 - i, ny); };
+
+    const uint32_t v0 = x * E, vm = xm * E, vp = xp * E, vf = x * 2u;
+    T raw[9];
+    auto issue_pops = [&](int yr, uint32_t fl) {
+        const int ym = yr == 0 ? ny - 1 : yr - 1, yp = yr == ny - 1 ? 0 : yr + 1;
+        const uint32_t r0 = (uint32_t)yr * pitch, rm = (uint32_t)ym * pitch, rp = (uint32_t)yp * pitch;
+        if (__builtin_amdgcn_ballot_w64((fl & 0xFFu) != 0u) == 0) {
+            raw[0] = bload<T>(rs, v0, (0u * plane + r0) * E);
+            raw[1] = bload<T>(rs, vm, (1u * plane + r0) * E);
+            raw[2] = bload<T>(rs, v0, (2u * plane + rm) * E);
+            raw[3] = bload<T>(rs, vp, (3u * plane + r0) * E);
+            raw[4] = bload<T>(rs, v0, (4u * plane + rp) * E);
+            raw[5] = bload<T>(rs, vm, (5u * plane + rm) * E);
+            raw[6] = bload<T>(rs, vp, (6u * plane + rm) * E);
+            raw[7] = bload<T>(rs, vp, (7u * plane + rp) * E);
+            raw[8] = bload<T>(rs, vm, (8u * plane + rp) * E);
+        } else {
+            uint32_t o[9];
+            pull_offsets(fl & 0xFFu, plane, rm, r0, rp, xm, x, xp, o);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) raw[q] = bload<T>(rs, o[q] * E, 0u);
+        }
+    };
+    auto load_flags = [&](int yr) { return bload_flag(rf, vf, (uint32_t)yr * pitch * 2u); };
+
+    // first step: pulled populations of the previous row (decoded) and their moments
+    float pd[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float ps = 0.f, pjx = 0.f, pjy = 0.f;
+    uint32_t pfl = FL_SOLID;
+    int pyr = 0;
+    // second step: the same for the row the next D stage collides
+    float qd[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float qs = 0.f, qjx = 0.f, qjy = 0.f;
+    uint32_t qfl = FL_SOLID;
+    int qyr = 0;
+
+    uint32_t fl1, fl2;
+    {
+        const uint32_t f0 = load_flags(row_at(0));
+        fl2 = load_flags(row_at(1));
+        issue_pops(row_at(0), f0);
+        fl1 = f0;
+    }
+
+    for (int i = 0; i < nrows; ++i) {
+        // A: row a_i
+        const int yr = row_at(i);
+        const uint32_t cfl = fl1;
+        T craw[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) craw[q] = raw[q];
+        fl1 = fl2;
+        fl2 = load_flags(row_at(min(i + 2, nrows - 1)));
+        issue_pops(row_at(min(i + 1, nrows - 1)), fl1);
+        float cd[9], cs, cjx, cjy;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) cd[q] = C::dec(craw[q]);
+        moments9(cd, cs, cjx, cjy);
+        const int s0 = i & 3;
+        psiA[s0 * P + tid + 1] = (cfl & FL_SOLID) ? 0.f : pseudopotential(m, m.rho_off + cs);
+        flr[s0 * BX + tid] = cfl;
+        lds_barrier();
+
+        // B: first collision of row a_{i-1}
+        if (i >= 2 && !(pfl & FL_SOLID)) {
+            const float *older = psiA + ((i - 2) & 3) * P, *mid = psiA + ((i - 1) & 3) * P, *newer = psiA + s0 * P;
+            float p[9];
+            collide_post<TRT>(m, pd, ps, pjx, pjy, pfl, up ? older : newer, mid, up ? newer : older, tid + 1, p);
+            T *fr = F + ((i - 1) & 3) * 9 * P + tid + 1;
+            if constexpr (SR) {
+                const uint32_t k0 = ((uint32_t)pyr * pitch + x) * 5u;
+                uint32_t h[5];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) h[k] = lowbias32((k0 + (uint32_t)k) ^ mix0);
+#pragma unroll
+                for (int q = 0; q < 9; ++q) fr[q * P] = C::enc_sr(p[q], (q & 1) ? (h[q >> 1] >> 16) : (h[q >> 1] & 0xFFFFu));
+            } else {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) fr[q * P] = C::enc(p[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) pd[q] = cd[q];
+        ps = cs;
+        pjx = cjx;
+        pjy = cjy;
+        pfl = cfl;
+        pyr = yr;
+        lds_barrier();
+
+        // C: second pull of row a_{i-2} from F, rho and phi of the second step
+        float ed[9], es = 0.f, ejx = 0.f, ejy = 0.f;
+        uint32_t efl = FL_SOLID;
+        if (i >= 4) {
+            const int k = (i - 2) & 3;
+            const int km = up ? (i - 3) & 3 : (i - 1) & 3;     // slot of row y - 1
+            const int kp = up ? (i - 1) & 3 : (i - 3) & 3;     // slot of row y + 1
+            efl = flr[k * BX + tid];
+            const uint32_t nb = efl & 0xFFu;
+            const T *Fk = F + k * 9 * P + tid + 1, *Fm = F + km * 9 * P + tid + 1, *Fp = F + kp * 9 * P + tid + 1;
+            // population a from x - e_a, or (bounce-back) opp(a) of the node itself
+            T v[9];
+            v[0] = Fk[0 * P];
+            v[1] = (nb & 0x04u) ? Fk[3 * P] : Fk[1 * P - 1];
+            v[2] = (nb & 0x08u) ? Fk[4 * P] : Fm[2 * P];
+            v[3] = (nb & 0x01u) ? Fk[1 * P] : Fk[3 * P + 1];
+            v[4] = (nb & 0x02u) ? Fk[2 * P] : Fp[4 * P];
+            v[5] = (nb & 0x40u) ? Fk[7 * P] : Fm[5 * P - 1];
+            v[6] = (nb & 0x80u) ? Fk[8 * P] : Fm[6 * P + 1];
+            v[7] = (nb & 0x10u) ? Fk[5 * P] : Fp[7 * P + 1];
+            v[8] = (nb & 0x20u) ? Fk[6 * P] : Fp[8 * P - 1];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) ed[q] = C::dec(v[q]);
+            moments9(ed, es, ejx, ejy);
+            psiB[k * P + tid + 1] = (efl & FL_SOLID) ? 0.f : pseudopotential(m, m.rho_off + es);
+        }
+        lds_barrier();
+
+        // D: second collision of row a_{i-3}, stored
+        if (i >= 6 && out_col && !(qfl & FL_SOLID)) {
+            const float *older = psiB + ((i - 4) & 3) * P, *mid = psiB + ((i - 3) & 3) * P,
+                        *newer = psiB + ((i - 2) & 3) * P;
+            float p[9];
+            collide_post<TRT>(m, qd, qs, qjx, qjy, qfl, up ? older : newer, mid, up ? newer : older, tid + 1, p);
+            const uint32_t prow = (uint32_t)qyr * pitch;
+            T o[9];
+            if constexpr (SR) {
+                const uint32_t k0 = (prow + x) * 5u;
+                uint32_t h[5];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) h[k] = lowbias32((k0 + (uint32_t)k) ^ mix1);
+#pragma unroll
+                for (int q = 0; q < 9; ++q) o[q] = C::enc_sr(p[q], (q & 1) ? (h[q >> 1] >> 16) : (h[q >> 1] & 0xFFFFu));
+            } else {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) o[q] = C::enc(p[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < 9; ++q) bstore(rd, v0, ((uint32_t)q * plane + prow) * E, o[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) qd[q] = ed[q];
+        qs = es;
+        qjx = ejx;
+        qjy = ejy;
+        qfl = efl;
+        qyr = row_at(i - 2 >= 0 ? i - 2 : 0);
+    }
+}
+
+template <int S, bool TRT, bool SR>
+__global__ void __launch_bounds__(512) k_step2(const StepArgs a) {
+    extern __shared__ char lds2[];
+    uint32_t mix0 = 0u, mix1 = 0u;
+    if constexpr (SR) {
+        // the step counts of both steps; the next launch reads count + 2
+        const uint32_t count = a.rng[a.par];
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.rng[a.par ^ 1] = count + 2u;
+        mix0 = lowbias32(count + 0x9e3779b9u);
+        mix1 = lowbias32(count + 1u + 0x9e3779b9u);
+    }
+    const int tile = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
+    if (tile >= a.ntiles) return;   // uniform for the workgroup, before any barrier
+    const int strip = tile / a.chunks, chunk = tile - strip * a.chunks;
+    const int y0 = (int)(((int64_t)chunk * a.g.ny) / a.chunks);
+    const int y1 = (int)(((int64_t)(chunk + 1) * a.g.ny) / a.chunks);
+    step2_tile<S, TRT, SR>(a, strip * ((int)blockDim.x - 6), y0, y1, (chunk & 1) == 0, lds2, mix0, mix1);
+}
+
+// ---------------------------------------------------------------------------
 // Wide step: step_tile with V adjacent columns per thread, so that a row of
 // one population plane moves as V * sizeof(T) bytes per lane (8 or 16 bytes
 // instead of 4 or 2), which the memory pipeline streams markedly faster.  Per
@@ -1468,6 +1703,41 @@ hipError_t launch_step_k(int storage, const StepArgs &a, int block_x, hipStream_
 
 hipError_t launch_step(int storage, const StepArgs &a, int block_x, hipStream_t s) {
     return launch_step_k<false>(storage, a, block_x, s);
+}
+
+template <int S>
+StepKernel step2_k16(bool trt, bool sr) {
+    return trt ? (sr ? k_step2<S, true, true> : k_step2<S, true, false>)
+               : (sr ? k_step2<S, false, true> : k_step2<S, false, false>);
+}
+StepKernel step2_kernel(int storage, bool trt, bool sr) {
+    switch (storage) {
+    case ST_F32:
+        if (sr) return nullptr;
+        return trt ? k_step2<ST_F32, true, false> : k_step2<ST_F32, false, false>;
+    case ST_F16: return step2_k16<ST_F16>(trt, sr);
+    case ST_BF16: return step2_k16<ST_BF16>(trt, sr);
+    default: return nullptr;
+    }
+}
+size_t step2_lds_bytes(int storage, int block_x) {
+    return storage == ST_F32 ? two_lds_bytes<ST_F32>(block_x) : two_lds_bytes<ST_F16>(block_x);
+}
+
+hipError_t launch_step2(int storage, const StepArgs &a, int block_x, hipStream_t s) {
+    StepKernel k = step2_kernel(storage, a.m.trt != 0, a.m.sround != 0);
+    if (!k || a.acc || block_x <= 6) return hipErrorInvalidValue;
+    const unsigned blocks = 8u * (unsigned)a.tiles_per_xcd;
+    k<<<blocks, block_x, step2_lds_bytes(storage, block_x), s>>>(a);
+    return hipGetLastError();
+}
+
+int step2_blocks_per_cu(int storage, int block_x, bool trt, bool sr) {
+    StepKernel k = step2_kernel(storage, trt, sr);
+    if (!k) return 1;
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, block_x, step2_lds_bytes(storage, block_x));
+    return e == hipSuccess && n > 0 ? n : 1;
 }
 
 hipError_t launch_step8(int storage, const StepArgs &a, int block_x, hipStream_t s) {

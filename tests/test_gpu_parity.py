@@ -156,21 +156,29 @@ def test_tile_shapes_bitwise_identical(lbm, tile):
 KERNEL_TILES = [("split", (128, 0)), ("split", (256, 0)), ("split", (128, 7)), ("split", (256, 64)),
                 ("wide2", (64, 0)), ("wide2", (128, 7)), ("wide2", (256, 64)),
                 ("wide4", (64, 5)), ("wide4", (128, 0)),
-                ("fused8", (256, 0)), ("fused8", (128, 7)), ("fused8", (512, 64))]
+                ("fused8", (256, 0)), ("fused8", (128, 7)), ("fused8", (512, 64)),
+                ("two", (128, 0)), ("two", (256, 7)), ("two", (512, 64)), ("two", (128, 3))]
 
 
 @pytest.mark.parametrize("storage", [0, 1, 2])
 @pytest.mark.parametrize("kernel,tile", KERNEL_TILES)
 def test_kernels_bitwise_equal_fused(lbm, storage, kernel, tile):
-    """The split, wide and 8-wave kernels do the fused kernel's arithmetic: bitwise
-    equal moments and flux on every parity case, ragged ones included."""
+    """The split, wide, 8-wave and two-step kernels do the fused kernel's
+    arithmetic: bitwise equal moments and flux on every parity case, ragged ones
+    included (40 steps: twenty launches of the two-step kernel)."""
     for name in sorted(CASES):
         c = CASES[name]()
         c.params = c.params.replace(storage=storage)
         a = lbm.from_case(c)
         b = lbm.from_case(c)
         b.set_kernel(kernel)
-        b.set_tile(*tile)
+        try:
+            b.set_tile(*tile)
+        except lbm.LBMError as e:
+            # the two-step kernel's LDS grows with block_x (FP32 at 512: 98.7 KB)
+            if kernel == "two" and "LDS" in str(e):
+                pytest.skip(f"device LDS per workgroup: {e}")
+            raise
         assert b.tile() == (kernel,) + tile
         a.step(40)
         b.step(40)
@@ -179,7 +187,29 @@ def test_kernels_bitwise_equal_fused(lbm, storage, kernel, tile):
         assert a.flux() == b.flux()
 
 
-@pytest.mark.parametrize("kernel", ["split", "wide2", "wide4", "fused8"])
+@pytest.mark.parametrize("storage", [0, 1, 2])
+@pytest.mark.parametrize("nsteps", [1, 7, 20])
+def test_two_step_odd_counts_and_calls(lbm, storage, nsteps):
+    """LBM_KERNEL_TWO over step counts that are odd (the last step runs the
+    fused kernel) and split over several calls: every call ends on the state
+    of the fused kernel after the same number of steps."""
+    for name in ("ragged37x19", "ragged130x67", "droplet128x64", "ragged300x5"):
+        c = CASES[name]()
+        c.params = c.params.replace(storage=storage)
+        a = lbm.from_case(c)
+        b = lbm.from_case(c)
+        b.set_kernel("two")
+        b.set_tile(128, 0)
+        for n in (nsteps, nsteps + 1, 3):
+            a.step(n)
+            b.step(n)
+            assert a.steps_done == b.steps_done
+            for x, y in zip(a.moments(), b.moments()):
+                np.testing.assert_array_equal(x, y, err_msg=f"{name} after {a.steps_done} steps")
+        assert a.flux() == b.flux()
+
+
+@pytest.mark.parametrize("kernel", ["split", "wide2", "wide4", "fused8", "two"])
 def test_kernels_full_size(lbm, kernel):
     c = I.random_channel_case(nx=8192, ny=2048, seed=0)
     a = lbm.from_case(c)

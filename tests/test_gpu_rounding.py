@@ -134,7 +134,14 @@ def test_reproducible_graph_kernel8(lbm):
     k8 = lbm.from_case(c)
     k8.set_kernel("fused8")
     k8.step(61)
-    for name, other in (("per-call", b), ("graph", g), ("fused8", k8)):
+    k2 = lbm.from_case(c)
+    k2.set_kernel("two")             # thirty two-step launches and one fused step
+    k2.step(61)
+    k2g = lbm.from_case(c)
+    k2g.set_kernel("two")
+    k2g.set_graph(10)                # five launches per replay: the parity flips at each replay
+    k2g.step(61)
+    for name, other in (("per-call", b), ("graph", g), ("fused8", k8), ("two", k2), ("two graph", k2g)):
         for x, y in zip(ref, other.moments()):
             np.testing.assert_array_equal(x, y, err_msg=name)
     rn = lbm.from_case(droplet(1, 0))
@@ -179,4 +186,5 @@ def test_other_kernels_rejected(lbm):
         with pytest.raises(lbm.LBMError, match="EINVAL"):
             s.set_kernel(k)
     s.set_kernel("fused8")
+    s.set_kernel("two")
     s.set_kernel("fused")

@@ -140,6 +140,21 @@ def test_trt_fused8_bitwise_equal(lbm):
             np.testing.assert_array_equal(x, y, err_msg=name)
 
 
+@pytest.mark.parametrize("storage", [0, 1])
+def test_trt_two_step_bitwise_equal(lbm, storage):
+    for name in ("droplet128x64", "ragged37x19", "ragged300x5", "ragged130x67"):
+        c = trt_case(name)
+        c.params = c.params.replace(storage=storage)
+        a = lbm.from_case(c)
+        b = lbm.from_case(c)
+        b.set_kernel("two")
+        b.set_tile(256, 0)
+        a.step(41)
+        b.step(41)
+        for x, y in zip(a.moments(), b.moments()):
+            np.testing.assert_array_equal(x, y, err_msg=name)
+
+
 @pytest.mark.parametrize("persistent", [False, True])
 def test_trt_batch_bitwise_single(lbm, persistent):
     cases = [trt_case(n) for n in ("ragged37x19", "ragged130x67", "ragged300x5")]
@@ -161,3 +176,5 @@ def test_trt_rejects_split_and_wide(lbm):
     sim.set_kernel("fused8")
     kernel, bx, rows = sim.tile()
     assert kernel == "fused8"
+    sim.set_kernel("two")
+    assert sim.tile()[0] == "two"
