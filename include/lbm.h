@@ -247,9 +247,10 @@ lbm_status lbm_set_tile(lbm_sim *sim, int32_t block_x, int32_t rows_per_block);
  * LBM_KERNEL_TWO: two time steps per launch (temporal blocking): the first
  * step's results stay in LDS, in the storage format, for the second, so the
  * populations cross HBM once per two steps; a workgroup of block_x threads
- * (128, 256 or 512; selecting it with block_x 64 sets 128) yields block_x - 6
- * columns, and an odd remaining step of an lbm_step call runs the fused
- * kernel.  Every lbm_step call still ends on the exact state after nsteps.
+ * (256 or 512; selecting it with a smaller block_x sets 256, and 512 is
+ * refused where its LDS (up to 98.7 KB) exceeds the device's per-workgroup
+ * limit) yields block_x - 6 columns, and an odd remaining step of an
+ * lbm_step call runs the fused kernel.  Every lbm_step call still ends on the exact state after nsteps.
  * All give bitwise the same results.  Default LBM_KERNEL_FUSED.  Takes effect
  * at the next lbm_step.  With LBM_COLLIDE_TRT_GUO or LBM_ROUND_STOCHASTIC
  * only LBM_KERNEL_FUSED, LBM_KERNEL_FUSED8 and LBM_KERNEL_TWO are accepted

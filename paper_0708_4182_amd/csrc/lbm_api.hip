@@ -167,7 +167,7 @@ Model make_model(const lbm_params *p) {
     m.tau = (float)p->tau;
     m.omega = (float)(1.0 / p->tau);
     m.rho0 = (float)p->rho0;
-    m.inv_rho0 = (float)(1.0 / p->rho0);
+    m.log2e_inv_rho0 = (float)(1.0 / (p->rho0 * std::log(2.0)));
     m.rho_off = storage_offset(p);
     m.ga = (float)p->g_axis;
     m.gd = (float)p->g_diag;
@@ -712,8 +712,8 @@ lbm_status lbm_set_tile(lbm_sim *s, int32_t block_x, int32_t rows) {
         return fail(s, LBM_EINVAL, "the split kernel takes block_x 128 or 256");
     if ((s->kernel == LBM_KERNEL_WIDE2 || s->kernel == LBM_KERNEL_WIDE4) && block_x > 256)
         return fail(s, LBM_EINVAL, "the wide kernels take block_x 64, 128 or 256");
-    if (s->kernel == LBM_KERNEL_TWO && block_x < 128)
-        return fail(s, LBM_EINVAL, "the two-step kernel takes block_x 128, 256 or 512");
+    if (s->kernel == LBM_KERNEL_TWO && block_x < 256)
+        return fail(s, LBM_EINVAL, "the two-step kernel takes block_x 256 or 512");
     if (s->kernel == LBM_KERNEL_TWO && !two_fits(s, block_x))
         return fail(s, LBM_EINVAL, "the two-step kernel at block_x %d needs %zu bytes of LDS per workgroup (device: %d)",
                     block_x, lbm::step2_lds_bytes(s->p.storage, block_x), s->max_lds);
@@ -755,7 +755,7 @@ lbm_status lbm_set_kernel(lbm_sim *s, int32_t kernel) {
     s->kernel = kernel;
     if (kernel == LBM_KERNEL_SPLIT && s->block_x != 128 && s->block_x != 256) s->block_x = 128;
     if ((kernel == LBM_KERNEL_WIDE2 || kernel == LBM_KERNEL_WIDE4) && s->block_x > 256) s->block_x = 256;
-    if (kernel == LBM_KERNEL_TWO && s->block_x < 128) s->block_x = 128;
+    if (kernel == LBM_KERNEL_TWO && s->block_x < 256) s->block_x = 256;
     if (kernel == LBM_KERNEL_TWO && !two_fits(s, s->block_x)) s->block_x = 256;
     s->chunks = 0;
     s->chunks1 = 0;
@@ -793,8 +793,8 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *row
                                  {LBM_KERNEL_FUSED, 512}, {LBM_KERNEL_WIDE2, 64},  {LBM_KERNEL_WIDE2, 128},
                                  {LBM_KERNEL_WIDE2, 256}, {LBM_KERNEL_WIDE4, 64},  {LBM_KERNEL_WIDE4, 128},
                                  {LBM_KERNEL_SPLIT, 128}, {LBM_KERNEL_SPLIT, 256}, {LBM_KERNEL_FUSED8, 128},
-                                 {LBM_KERNEL_FUSED8, 256}, {LBM_KERNEL_FUSED8, 512}, {LBM_KERNEL_TWO, 128},
-                                 {LBM_KERNEL_TWO, 256},    {LBM_KERNEL_TWO, 512}};
+                                 {LBM_KERNEL_FUSED8, 256}, {LBM_KERNEL_FUSED8, 512}, {LBM_KERNEL_TWO, 256},
+                                 {LBM_KERNEL_TWO, 512}};
     static const int kRows[] = {0, 4, 8, 16, 32, 64, 128};
     hipEvent_t e0, e1;
     HIP_TRY(s, hipEventCreate(&e0));

@@ -23,7 +23,7 @@ struct Grid {
 // Model constants in FP32 as the kernels use them.
 struct Model {
     float tau, omega;          // omega = 1 / tau
-    float rho0, inv_rho0;
+    float rho0, log2e_inv_rho0;   // rho0 and log2(e) / rho0 (eq. (4) on the base-2 exponential)
     float rho_off;             // reference density of the stored deviations (0: raw f)
     float ga, gd, wa, wd;      // G_a and W_a per direction class
     float rho_c, f_elec;

@@ -175,8 +175,10 @@ __device__ __forceinline__ void moments9(const float d[9], float &s, float &jx, 
     jy = (d[2] - d[4]) + ((d[5] - d[7]) + (d[6] - d[8]));
 }
 
+// eq. (4): psi = rho0 (1 - exp(-rho / rho0)), with exp(-rho / rho0) taken as
+// 2^(-rho log2(e) / rho0) on the hardware's base-2 exponential
 __device__ __forceinline__ float pseudopotential(const Model &m, float rho) {
-    return m.rho0 * (1.f - expf(-rho * m.inv_rho0));
+    return m.rho0 * (1.f - __builtin_amdgcn_exp2f(-rho * m.log2e_inv_rho0));
 }
 
 // f^eq of eq. (3) minus the stored rest offset w_a rho_off, for density rho
@@ -650,7 +652,7 @@ constexpr size_t two_lds_bytes(int bx) {
            (size_t)4 * 9 * (bx + 2) * sizeof(typename Codec<S>::T);
 }
 
-template <int S, bool TRT, bool SR>
+template <int S, bool TRT, bool SR, int BX>
 __device__ __forceinline__ void step2_tile(const StepArgs &a, int x0, int y0, int y1, bool up, char *lds,
                                            uint32_t mix0, uint32_t mix1) {
     using C = Codec<S>;
@@ -658,7 +660,7 @@ __device__ __forceinline__ void step2_tile(const StepArgs &a, int x0, int y0, in
     constexpr uint32_t E = sizeof(T);
     const Grid &g = a.g;
     const Model &m = a.m;
-    const int BX = blockDim.x, P = BX + 2;   // ring rows carry one padding slot per side
+    constexpr int P = BX + 2;   // ring rows carry one padding slot per side (compile-time strides)
     const int tid = threadIdx.x;
     const int nx = g.nx, ny = g.ny;
     const uint32_t pitch = (uint32_t)g.pitch, plane = g.plane;
@@ -787,17 +789,29 @@ __device__ __forceinline__ void step2_tile(const StepArgs &a, int x0, int y0, in
             efl = flr[k * BX + tid];
             const uint32_t nb = efl & 0xFFu;
             const T *Fk = F + k * 9 * P + tid + 1, *Fm = F + km * 9 * P + tid + 1, *Fp = F + kp * 9 * P + tid + 1;
-            // population a from x - e_a, or (bounce-back) opp(a) of the node itself
+            // population a from x - e_a, or (bounce-back) opp(a) of the node itself;
+            // a wave none of whose nodes has a solid neighbour skips the selection
             T v[9];
             v[0] = Fk[0 * P];
-            v[1] = (nb & 0x04u) ? Fk[3 * P] : Fk[1 * P - 1];
-            v[2] = (nb & 0x08u) ? Fk[4 * P] : Fm[2 * P];
-            v[3] = (nb & 0x01u) ? Fk[1 * P] : Fk[3 * P + 1];
-            v[4] = (nb & 0x02u) ? Fk[2 * P] : Fp[4 * P];
-            v[5] = (nb & 0x40u) ? Fk[7 * P] : Fm[5 * P - 1];
-            v[6] = (nb & 0x80u) ? Fk[8 * P] : Fm[6 * P + 1];
-            v[7] = (nb & 0x10u) ? Fk[5 * P] : Fp[7 * P + 1];
-            v[8] = (nb & 0x20u) ? Fk[6 * P] : Fp[8 * P - 1];
+            if (__builtin_amdgcn_ballot_w64(nb != 0u) == 0) {
+                v[1] = Fk[1 * P - 1];
+                v[2] = Fm[2 * P];
+                v[3] = Fk[3 * P + 1];
+                v[4] = Fp[4 * P];
+                v[5] = Fm[5 * P - 1];
+                v[6] = Fm[6 * P + 1];
+                v[7] = Fp[7 * P + 1];
+                v[8] = Fp[8 * P - 1];
+            } else {
+                v[1] = (nb & 0x04u) ? Fk[3 * P] : Fk[1 * P - 1];
+                v[2] = (nb & 0x08u) ? Fk[4 * P] : Fm[2 * P];
+                v[3] = (nb & 0x01u) ? Fk[1 * P] : Fk[3 * P + 1];
+                v[4] = (nb & 0x02u) ? Fk[2 * P] : Fp[4 * P];
+                v[5] = (nb & 0x40u) ? Fk[7 * P] : Fm[5 * P - 1];
+                v[6] = (nb & 0x80u) ? Fk[8 * P] : Fm[6 * P + 1];
+                v[7] = (nb & 0x10u) ? Fk[5 * P] : Fp[7 * P + 1];
+                v[8] = (nb & 0x20u) ? Fk[6 * P] : Fp[8 * P - 1];
+            }
 #pragma unroll
             for (int q = 0; q < 9; ++q) ed[q] = C::dec(v[q]);
             moments9(ed, es, ejx, ejy);
@@ -837,8 +851,8 @@ __device__ __forceinline__ void step2_tile(const StepArgs &a, int x0, int y0, in
     }
 }
 
-template <int S, bool TRT, bool SR>
-__global__ void __launch_bounds__(512) k_step2(const StepArgs a) {
+template <int S, bool TRT, bool SR, int BX>
+__global__ void __launch_bounds__(BX) k_step2(const StepArgs a) {
     extern __shared__ char lds2[];
     uint32_t mix0 = 0u, mix1 = 0u;
     if constexpr (SR) {
@@ -853,7 +867,7 @@ __global__ void __launch_bounds__(512) k_step2(const StepArgs a) {
     const int strip = tile / a.chunks, chunk = tile - strip * a.chunks;
     const int y0 = (int)(((int64_t)chunk * a.g.ny) / a.chunks);
     const int y1 = (int)(((int64_t)(chunk + 1) * a.g.ny) / a.chunks);
-    step2_tile<S, TRT, SR>(a, strip * ((int)blockDim.x - 6), y0, y1, (chunk & 1) == 0, lds2, mix0, mix1);
+    step2_tile<S, TRT, SR, BX>(a, strip * (BX - 6), y0, y1, (chunk & 1) == 0, lds2, mix0, mix1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1705,18 +1719,28 @@ hipError_t launch_step(int storage, const StepArgs &a, int block_x, hipStream_t 
     return launch_step_k<false>(storage, a, block_x, s);
 }
 
-template <int S>
+// The two-step kernel is compiled for block_x 256 and 512 (ring strides are
+// compile-time constants).
+template <int S, int BX>
 StepKernel step2_k16(bool trt, bool sr) {
-    return trt ? (sr ? k_step2<S, true, true> : k_step2<S, true, false>)
-               : (sr ? k_step2<S, false, true> : k_step2<S, false, false>);
+    return trt ? (sr ? k_step2<S, true, true, BX> : k_step2<S, true, false, BX>)
+               : (sr ? k_step2<S, false, true, BX> : k_step2<S, false, false, BX>);
 }
-StepKernel step2_kernel(int storage, bool trt, bool sr) {
+template <int BX>
+StepKernel step2_kernel_bx(int storage, bool trt, bool sr) {
     switch (storage) {
     case ST_F32:
         if (sr) return nullptr;
-        return trt ? k_step2<ST_F32, true, false> : k_step2<ST_F32, false, false>;
-    case ST_F16: return step2_k16<ST_F16>(trt, sr);
-    case ST_BF16: return step2_k16<ST_BF16>(trt, sr);
+        return trt ? k_step2<ST_F32, true, false, BX> : k_step2<ST_F32, false, false, BX>;
+    case ST_F16: return step2_k16<ST_F16, BX>(trt, sr);
+    case ST_BF16: return step2_k16<ST_BF16, BX>(trt, sr);
+    default: return nullptr;
+    }
+}
+StepKernel step2_kernel(int storage, int block_x, bool trt, bool sr) {
+    switch (block_x) {
+    case 256: return step2_kernel_bx<256>(storage, trt, sr);
+    case 512: return step2_kernel_bx<512>(storage, trt, sr);
     default: return nullptr;
     }
 }
@@ -1725,15 +1749,15 @@ size_t step2_lds_bytes(int storage, int block_x) {
 }
 
 hipError_t launch_step2(int storage, const StepArgs &a, int block_x, hipStream_t s) {
-    StepKernel k = step2_kernel(storage, a.m.trt != 0, a.m.sround != 0);
-    if (!k || a.acc || block_x <= 6) return hipErrorInvalidValue;
+    StepKernel k = step2_kernel(storage, block_x, a.m.trt != 0, a.m.sround != 0);
+    if (!k || a.acc) return hipErrorInvalidValue;
     const unsigned blocks = 8u * (unsigned)a.tiles_per_xcd;
     k<<<blocks, block_x, step2_lds_bytes(storage, block_x), s>>>(a);
     return hipGetLastError();
 }
 
 int step2_blocks_per_cu(int storage, int block_x, bool trt, bool sr) {
-    StepKernel k = step2_kernel(storage, trt, sr);
+    StepKernel k = step2_kernel(storage, block_x, trt, sr);
     if (!k) return 1;
     int n = 0;
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, block_x, step2_lds_bytes(storage, block_x));

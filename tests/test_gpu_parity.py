@@ -157,7 +157,7 @@ KERNEL_TILES = [("split", (128, 0)), ("split", (256, 0)), ("split", (128, 7)), (
                 ("wide2", (64, 0)), ("wide2", (128, 7)), ("wide2", (256, 64)),
                 ("wide4", (64, 5)), ("wide4", (128, 0)),
                 ("fused8", (256, 0)), ("fused8", (128, 7)), ("fused8", (512, 64)),
-                ("two", (128, 0)), ("two", (256, 7)), ("two", (512, 64)), ("two", (128, 3))]
+                ("two", (256, 0)), ("two", (256, 7)), ("two", (512, 64)), ("two", (512, 3))]
 
 
 @pytest.mark.parametrize("storage", [0, 1, 2])
@@ -199,7 +199,7 @@ def test_two_step_odd_counts_and_calls(lbm, storage, nsteps):
         a = lbm.from_case(c)
         b = lbm.from_case(c)
         b.set_kernel("two")
-        b.set_tile(128, 0)
+        b.set_tile(256, 0)
         for n in (nsteps, nsteps + 1, 3):
             a.step(n)
             b.step(n)
