@@ -31,6 +31,7 @@ STORAGES = {"f32": 0, "f16": 1, "bf16": 2}
 # forcing, rounding 1 the stochastic rounding of 16-bit stores
 VARIANTS = {"f16": (1, 0, 0), "bf16": (2, 0, 0), "f32_trt": (0, 1, 0), "f16_sr": (1, 0, 1), "bf16_sr": (2, 0, 1)}
 ELEM_BYTES = {0: 4, 1: 2, 2: 2}
+STEPS_PER_LAUNCH = {"two": 2}       # kernels that advance more than one time step per launch
 KERNEL_SRC = os.path.join(ROOT, "paper_0708_4182_amd", "csrc", "lbm_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -139,6 +140,34 @@ def copy_ceiling(nbytes: int, reps: int = 20):
             "torch_copy_GB/s": round(2 * nbytes / (tms * 1e-3) / 1e9, 1)}
 
 
+def step_line(name: str, r: dict, nsites: int, nfluid: int) -> dict:
+    """Bench line of one storage/variant run r (time_storage's result) on a
+    lattice of nsites nodes, nfluid of them fluid: rate and HBM roofline."""
+    s = STORAGES[name] if name in STORAGES else VARIANTS[name][0]
+    # algorithmic HBM bytes of one launch: every population read once and
+    # written once (18 values per fluid node); the two-step kernel's launch
+    # covers two time steps
+    steps_per_launch = STEPS_PER_LAUNCH.get(r["tile"][2], 1)
+    alg_bytes = 18 * ELEM_BYTES[s] * nfluid
+    launch_ms = r["step_ms"] * steps_per_launch
+    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic(name, r["tile"])
+    line = {
+        "tile": r["tile"],
+        "mlups": round(nsites / (r["step_ms"] * 1e-3) / 1e6, 1),
+        "ms_per_step": round(r["step_ms"], 5),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "steps_per_launch": steps_per_launch,
+                     "launch_ms": round(launch_ms, 5)},
+    }
+    if steps_per_launch > 1:
+        # what a kernel that streams the populations once per step would need for this step rate
+        eq = alg_bytes / (r["step_ms"] * 1e-3) / 1e9
+        line["roofline"]["single_step_equivalent"] = {"GB/s": round(eq, 1), "frac": round(eq / HBM_PEAK_GBS, 4)}
+    return line
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -230,25 +259,12 @@ def main():
     nsites = args.nx * args.ny
     nfluid = int((case.solid == 0).sum())
 
-    def line_for(name, r):
-        s = STORAGES[name] if name in STORAGES else VARIANTS[name][0]
-        alg_bytes = 18 * ELEM_BYTES[s] * nfluid
-        achieved = alg_bytes / (r["step_ms"] * 1e-3) / 1e9
-        traffic = measured_traffic(name, r["tile"])
-        return {
-            "tile": r["tile"],
-            "mlups": round(nsites / (r["step_ms"] * 1e-3) / 1e6, 1),
-            "ms_per_step": round(r["step_ms"], 5),
-            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                         "traffic": traffic},
-        }
 
     main_r = time_storage(case, STORAGES[args.storage], args.steps, args.warmup, tile)
     print(f"# {args.storage}: tile {main_r['tile']} {main_r['step_ms']*1e3:.1f} us/step, "
           f"Q={main_r['Q']:.6e} M={main_r['M']:.6e}",
           file=sys.stderr, flush=True)
-    main_line = line_for(args.storage, main_r)
+    main_line = step_line(args.storage, main_r, nsites, nfluid)
     variants = {}
     for v in [v for v in args.variants.split(",") if v and v != args.storage]:
         st, coll, rnd = VARIANTS[v] if v in VARIANTS else (STORAGES[v], 0, 0)
@@ -257,7 +273,7 @@ def main():
             vt = ("fused", tile[1], tile[2])     # TRT and stochastic rounding run in the fused kernels only
         r = time_storage(case, st, args.steps, args.warmup, vt, collision=coll, rounding=rnd)
         print(f"# {v}: tile {r['tile']} {r['step_ms']*1e3:.1f} us/step", file=sys.stderr, flush=True)
-        variants[v] = line_for(v, r)
+        variants[v] = step_line(v, r, nsites, nfluid)
 
     ms_per_step = main_r["total_ms"] / args.steps
     value = nsites * args.steps / (main_r["total_ms"] * 1e-3) / 1e6

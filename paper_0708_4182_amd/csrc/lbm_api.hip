@@ -812,7 +812,20 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *row
             cand.kernel != LBM_KERNEL_TWO)
             continue;
         if (cand.kernel == LBM_KERNEL_TWO && !two_fits(s, bx)) continue;
-        for (int r : kRows) {
+        // the two-step kernel recomputes six halo rows per chunk, so it is also
+        // tried at the chunk heights that give exactly k resident workgroups per
+        // compute unit (k = 1 .. its occupancy): longer chunks against more waves
+        std::vector<int> rows_list(std::begin(kRows), std::end(kRows));
+        if (cand.kernel == LBM_KERNEL_TWO) {
+            const int strips = (s->p.nx + bx - 7) / (bx - 6);
+            const int per_cu = lbm::step2_blocks_per_cu(s->p.storage, bx, s->m.trt != 0, s->m.sround != 0);
+            for (int k = 1; k <= per_cu; ++k) {
+                const int chunks = std::max(1, (k * s->cus) / strips);
+                const int r = (s->p.ny + chunks - 1) / chunks;
+                if (std::find(rows_list.begin(), rows_list.end(), r) == rows_list.end()) rows_list.push_back(r);
+            }
+        }
+        for (int r : rows_list) {
             if (r > 0 && r >= s->p.ny) continue;
             s->kernel = cand.kernel;
             s->block_x = bx;

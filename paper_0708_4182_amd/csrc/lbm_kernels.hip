@@ -643,13 +643,14 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8, 8))
 //   C: second pull of row a_{i-2} from F (rows a_{i-3..i-1}, bounce-back from
 //      the node's own results), rho and phi of the second step;     barrier
 //   D: second collision of row a_{i-3} (phi rows a_{i-4..i-2}) and its store.
-// Rings hold four rows; each row slot is rewritten only after a barrier that
-// follows its last read.  Threads outside [3, 3 + nact) and rows outside the
+// Rings hold three rows (slot of row a_j: j mod 3); each slot is rewritten
+// only after a barrier that follows its last read (stage D carries its row's
+// pulled values from stage C instead of pulling again).  Threads outside [3, 3 + nact) and rows outside the
 // chunk are computed for their neighbours and not stored.
 template <int S>
 constexpr size_t two_lds_bytes(int bx) {
-    return (size_t)2 * 4 * (bx + 2) * sizeof(float) + (size_t)4 * bx * sizeof(uint32_t) +
-           (size_t)4 * 9 * (bx + 2) * sizeof(typename Codec<S>::T);
+    return (size_t)2 * 3 * (bx + 2) * sizeof(float) + (size_t)3 * bx * sizeof(uint32_t) +
+           (size_t)3 * 9 * (bx + 2) * sizeof(typename Codec<S>::T);
 }
 
 template <int S, bool TRT, bool SR, int BX>
@@ -676,11 +677,11 @@ __device__ __forceinline__ void step2_tile(const StepArgs &a, int x0, int y0, in
     const uint32_t x = (uint32_t)xc;
     const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x == (uint32_t)nx - 1 ? 0 : x + 1;
 
-    float *psiA = reinterpret_cast<float *>(lds);      // phi of the first step  [4][P]
-    float *psiB = psiA + 4 * P;                         // phi of the second step [4][P]
-    uint32_t *flr = reinterpret_cast<uint32_t *>(psiB + 4 * P);   // flag words [4][BX]
-    T *F = reinterpret_cast<T *>(flr + 4 * BX);         // first-step results [4][9][P]
-    if (tid < 8) {      // padding slots (read only by threads whose results are unused)
+    float *psiA = reinterpret_cast<float *>(lds);      // phi of the first step  [3][P]
+    float *psiB = psiA + 3 * P;                         // phi of the second step [3][P]
+    uint32_t *flr = reinterpret_cast<uint32_t *>(psiB + 3 * P);   // flag words [3][BX]
+    T *F = reinterpret_cast<T *>(flr + 3 * BX);         // first-step results [3][9][P]
+    if (tid < 6) {      // padding slots (read only by threads whose results are unused)
         const int k = tid >> 1, side = (tid & 1) ? P - 1 : 0;
         psiA[k * P + side] = 0.f;
         psiB[k * P + side] = 0.f;
@@ -733,7 +734,9 @@ __device__ __forceinline__ void step2_tile(const StepArgs &a, int x0, int y0, in
         fl1 = f0;
     }
 
-    for (int i = 0; i < nrows; ++i) {
+    int sl0 = 0;     // slot of row a_i (i mod 3); sl1: a_{i-1}, sl2: a_{i-2} (= a_{i-4} and a_{i-3} one round later)
+    for (int i = 0; i < nrows; ++i, sl0 = sl0 == 2 ? 0 : sl0 + 1) {
+        const int sl1 = sl0 == 0 ? 2 : sl0 - 1, sl2 = sl0 == 2 ? 0 : sl0 + 1;
         // A: row a_i
         const int yr = row_at(i);
         const uint32_t cfl = fl1;
@@ -747,17 +750,16 @@ __device__ __forceinline__ void step2_tile(const StepArgs &a, int x0, int y0, in
 #pragma unroll
         for (int q = 0; q < 9; ++q) cd[q] = C::dec(craw[q]);
         moments9(cd, cs, cjx, cjy);
-        const int s0 = i & 3;
-        psiA[s0 * P + tid + 1] = (cfl & FL_SOLID) ? 0.f : pseudopotential(m, m.rho_off + cs);
-        flr[s0 * BX + tid] = cfl;
+        psiA[sl0 * P + tid + 1] = (cfl & FL_SOLID) ? 0.f : pseudopotential(m, m.rho_off + cs);
+        flr[sl0 * BX + tid] = cfl;
         lds_barrier();
 
         // B: first collision of row a_{i-1}
         if (i >= 2 && !(pfl & FL_SOLID)) {
-            const float *older = psiA + ((i - 2) & 3) * P, *mid = psiA + ((i - 1) & 3) * P, *newer = psiA + s0 * P;
+            const float *older = psiA + sl2 * P, *mid = psiA + sl1 * P, *newer = psiA + sl0 * P;
             float p[9];
             collide_post<TRT>(m, pd, ps, pjx, pjy, pfl, up ? older : newer, mid, up ? newer : older, tid + 1, p);
-            T *fr = F + ((i - 1) & 3) * 9 * P + tid + 1;
+            T *fr = F + sl1 * 9 * P + tid + 1;
             if constexpr (SR) {
                 const uint32_t k0 = ((uint32_t)pyr * pitch + x) * 5u;
                 uint32_t h[5];
@@ -783,9 +785,9 @@ __device__ __forceinline__ void step2_tile(const StepArgs &a, int x0, int y0, in
         float ed[9], es = 0.f, ejx = 0.f, ejy = 0.f;
         uint32_t efl = FL_SOLID;
         if (i >= 4) {
-            const int k = (i - 2) & 3;
-            const int km = up ? (i - 3) & 3 : (i - 1) & 3;     // slot of row y - 1
-            const int kp = up ? (i - 1) & 3 : (i - 3) & 3;     // slot of row y + 1
+            const int k = sl2;                  // row a_{i-2}
+            const int km = up ? sl0 : sl1;       // slot of row y - 1 (a_{i-3} marching up)
+            const int kp = up ? sl1 : sl0;       // slot of row y + 1
             efl = flr[k * BX + tid];
             const uint32_t nb = efl & 0xFFu;
             const T *Fk = F + k * 9 * P + tid + 1, *Fm = F + km * 9 * P + tid + 1, *Fp = F + kp * 9 * P + tid + 1;
@@ -821,8 +823,7 @@ __device__ __forceinline__ void step2_tile(const StepArgs &a, int x0, int y0, in
 
         // D: second collision of row a_{i-3}, stored
         if (i >= 6 && out_col && !(qfl & FL_SOLID)) {
-            const float *older = psiB + ((i - 4) & 3) * P, *mid = psiB + ((i - 3) & 3) * P,
-                        *newer = psiB + ((i - 2) & 3) * P;
+            const float *older = psiB + sl1 * P, *mid = psiB + sl0 * P, *newer = psiB + sl2 * P;   // a_{i-4..i-2}
             float p[9];
             collide_post<TRT>(m, qd, qs, qjx, qjy, qfl, up ? older : newer, mid, up ? newer : older, tid + 1, p);
             const uint32_t prow = (uint32_t)qyr * pitch;

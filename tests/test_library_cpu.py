@@ -248,3 +248,23 @@ def test_bench_traffic_lookup(tmp_path, monkeypatch):
     assert bench.measured_traffic("f32", [256, 0, "fused8"]) is None      # another tile
     assert bench.measured_traffic("f16", (512, 0, "fused")) == 45
     assert bench.measured_traffic("bf16", [512, 0, "fused"]) is None
+
+
+def test_bench_roofline_per_launch(monkeypatch):
+    """The bench's HBM roofline charges each launch its algorithmic bytes
+    (18 values per fluid node, read once and written once): a two-step launch
+    covers two time steps with the bytes of one, so its achieved rate is half
+    the single-step equivalent, which is reported beside it."""
+    import bench
+    monkeypatch.setattr(bench, "measured_traffic", lambda name, tile: None)
+    nsites, nfluid = 1000, 800
+    one = bench.step_line("f32", {"step_ms": 0.001, "tile": [256, 64, "fused"]}, nsites, nfluid)
+    two = bench.step_line("f32", {"step_ms": 0.001, "tile": [512, 137, "two"]}, nsites, nfluid)
+    half = bench.step_line("f16", {"step_ms": 0.001, "tile": [256, 67, "two"]}, nsites, nfluid)
+    assert one["roofline"]["achieved"] == round(72 * 800 / 1e-6 / 1e9, 1)
+    assert one["roofline"]["steps_per_launch"] == 1 and "single_step_equivalent" not in one["roofline"]
+    assert two["roofline"]["steps_per_launch"] == 2 and two["roofline"]["launch_ms"] == 0.002
+    assert two["roofline"]["achieved"] == round(one["roofline"]["achieved"] / 2, 1)
+    assert two["roofline"]["single_step_equivalent"]["GB/s"] == one["roofline"]["achieved"]
+    assert half["roofline"]["achieved"] == round(36 * 800 / 2e-6 / 1e9, 1)
+    assert one["mlups"] == two["mlups"] == round(nsites / 1e-6 / 1e6, 1)
