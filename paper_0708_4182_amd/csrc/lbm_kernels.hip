@@ -175,10 +175,18 @@ __device__ __forceinline__ void moments9(const float d[9], float &s, float &jx, 
     jy = (d[2] - d[4]) + ((d[5] - d[7]) + (d[6] - d[8]));
 }
 
-// eq. (4): psi = rho0 (1 - exp(-rho / rho0)), with exp(-rho / rho0) taken as
-// 2^(-rho log2(e) / rho0) on the hardware's base-2 exponential
+// eq. (4): psi = rho0 (1 - exp(-x)), x = rho / rho0.  In the vapour (x ~ 0.05)
+// 1 - exp(-x) cancels about four bits of exp(-x), so it is evaluated as
+// -expm1(-x) in W. Kahan's form: with t = -x log2(e) and u = 2^t (the hardware's
+// base-2 exponential), expm1 = (u - 1) t / log2(u); the rounding error of u
+// appears in both factors and cancels, which keeps psi to a few ulp at any x.
+// u == 1 (|t| below half an ulp of 1) leaves the first-order term t ln 2.
 __device__ __forceinline__ float pseudopotential(const Model &m, float rho) {
-    return m.rho0 * (1.f - __builtin_amdgcn_exp2f(-rho * m.log2e_inv_rho0));
+    const float t = -rho * m.log2e_inv_rho0;
+    const float u = __builtin_amdgcn_exp2f(t);
+    const float em1 = u == 1.f ? t * 0.693147180559945309f
+                               : (u - 1.f) * (t * __builtin_amdgcn_rcpf(__builtin_amdgcn_logf(u)));
+    return -m.rho0 * em1;
 }
 
 // f^eq of eq. (3) minus the stored rest offset w_a rho_off, for density rho
