@@ -31,7 +31,7 @@ STORAGES = {"f32": 0, "f16": 1, "bf16": 2}
 # forcing, rounding 1 the stochastic rounding of 16-bit stores
 VARIANTS = {"f16": (1, 0, 0), "bf16": (2, 0, 0), "f32_trt": (0, 1, 0), "f16_sr": (1, 0, 1), "bf16_sr": (2, 0, 1)}
 ELEM_BYTES = {0: 4, 1: 2, 2: 2}
-STEPS_PER_LAUNCH = {"two": 2}       # kernels that advance more than one time step per launch
+STEPS_PER_LAUNCH = {"two": 2, "three": 3}     # kernels that advance more than one time step per launch
 KERNEL_SRC = os.path.join(ROOT, "paper_0708_4182_amd", "csrc", "lbm_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -46,7 +46,8 @@ KERNEL_NAMES = {
     "wide4": "k_step_wide<4> (the fused step, four adjacent columns per thread)",
     "split": "k_step_split (producer wave streams rows into LDS; compute waves collide and store)",
     "fused8": "k_step8 (the fused step compiled for 8 waves per SIMD, one column per thread)",
-    "two": "k_step2 (two time steps per launch, the first step's results in LDS: temporal blocking)",
+    "two": "k_stepk<..., 2> (two time steps per launch, the first step's results in LDS: temporal blocking)",
+    "three": "k_stepk<..., 3> (three time steps per launch, intermediate results in LDS: temporal blocking)",
 }
 
 
@@ -221,8 +222,8 @@ def main():
     ap.add_argument("--nx", type=int, default=8192)
     ap.add_argument("--ny", type=int, default=2048)
     ap.add_argument("--tile", default="auto",
-                    help="[kernel:]block_x x rows, e.g. 512x64 or split:128x0 (rows 0 = one wave of "
-                         "workgroups; kernel fused or split), or 'auto'")
+                    help="[kernel:]block_x x rows, e.g. 512x64, split:128x0 or two:512x137 (rows 0 = one wave "
+                         "of workgroups; kernel fused, fused8, split, wide2, wide4 or two), or 'auto'")
     ap.add_argument("--cpu-steps", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-ceiling", action="store_true")
@@ -269,8 +270,8 @@ def main():
     for v in [v for v in args.variants.split(",") if v and v != args.storage]:
         st, coll, rnd = VARIANTS[v] if v in VARIANTS else (STORAGES[v], 0, 0)
         vt = tile
-        if (coll or rnd) and tile and tile[0] not in ("fused", "fused8"):
-            vt = ("fused", tile[1], tile[2])     # TRT and stochastic rounding run in the fused kernels only
+        if (coll or rnd) and tile and tile[0] not in ("fused", "fused8", "two"):
+            vt = ("fused", tile[1], tile[2])     # TRT and stochastic rounding run in the fused and two-step kernels only
         r = time_storage(case, st, args.steps, args.warmup, vt, collision=coll, rounding=rnd)
         print(f"# {v}: tile {r['tile']} {r['step_ms']*1e3:.1f} us/step", file=sys.stderr, flush=True)
         variants[v] = step_line(v, r, nsites, nfluid)

@@ -244,23 +244,26 @@ lbm_status lbm_set_tile(lbm_sim *sim, int32_t block_x, int32_t rows_per_block);
  * (block_x 128 or 256; selecting it with another block_x sets block_x to 128).
  * LBM_KERNEL_FUSED8: the fused kernel compiled for 8 resident waves per SIMD
  * (64 registers; a few loop invariants live in scratch memory) instead of 7.
- * LBM_KERNEL_TWO: two time steps per launch (temporal blocking): the first
- * step's results stay in LDS, in the storage format, for the second, so the
- * populations cross HBM once per two steps; a workgroup of block_x threads
- * (256 or 512; selecting it with a smaller block_x sets 256, and 512 is
- * refused where its LDS (up to 98.7 KB) exceeds the device's per-workgroup
- * limit) yields block_x - 6 columns, and an odd remaining step of an
- * lbm_step call runs the fused kernel.  Every lbm_step call still ends on the exact state after nsteps.
+ * LBM_KERNEL_TWO / LBM_KERNEL_THREE: two or three time steps per launch
+ * (temporal blocking): each step's results stay in LDS, in the storage
+ * format, for the next, so the populations cross HBM once per two or three
+ * steps; a workgroup of block_x threads (256 or 512; selecting one with a
+ * smaller block_x sets 256, and a block_x whose LDS exceeds the device's
+ * per-workgroup limit is refused) yields block_x - 6 or block_x - 10
+ * columns, and the nsteps mod 2 (or 3) remaining steps of an lbm_step call
+ * run the fused kernel.  Every lbm_step call still ends on the exact state
+ * after nsteps.
  * All give bitwise the same results.  Default LBM_KERNEL_FUSED.  Takes effect
  * at the next lbm_step.  With LBM_COLLIDE_TRT_GUO or LBM_ROUND_STOCHASTIC
- * only LBM_KERNEL_FUSED, LBM_KERNEL_FUSED8 and LBM_KERNEL_TWO are accepted
- * (LBM_EINVAL otherwise) and tuned. */
+ * only LBM_KERNEL_FUSED, LBM_KERNEL_FUSED8, LBM_KERNEL_TWO and
+ * LBM_KERNEL_THREE are accepted (LBM_EINVAL otherwise) and tuned. */
 #define LBM_KERNEL_FUSED 0
 #define LBM_KERNEL_SPLIT 1
 #define LBM_KERNEL_WIDE2 2
 #define LBM_KERNEL_WIDE4 3
 #define LBM_KERNEL_FUSED8 4
 #define LBM_KERNEL_TWO 5
+#define LBM_KERNEL_THREE 6
 lbm_status lbm_set_kernel(lbm_sim *sim, int32_t kernel);
 
 /* Replay steps as hipGraphs: lbm_step(n) runs floor(n / steps_per_graph)

@@ -47,7 +47,7 @@ struct lbm_sim {
     int cus = 0;           // compute units of the device
     int max_lds = 0;       // LDS bytes one workgroup may use on the device
     int chunks = 0;        // cached tiling (0 = recompute)
-    int chunks1 = 0;       // cached tiling of the fused kernel, which runs the odd step of LBM_KERNEL_TWO
+    int chunks1 = 0;       // cached tiling of the fused kernel, which runs the remainder steps of a multi-step kernel
     int graph_steps = 0;   // steps per hipGraph replay (0: eager launches only)
     hipStream_t cap = nullptr;                  // private stream used only for graph capture
     hipGraph_t graph[2] = {nullptr, nullptr};   // per source-buffer parity
@@ -451,12 +451,18 @@ lbm_status lbm_init_device(lbm_sim *s, const float *rho, const float *ux, const 
 }
 
 namespace {
+// Time steps one launch of a kernel advances (2 or 3 for the multi-step kernels).
+int steps_per_launch(int kernel) {
+    return kernel == LBM_KERNEL_TWO ? 2 : kernel == LBM_KERNEL_THREE ? 3 : 1;
+}
+
 // Columns of one strip (one workgroup's output width) for a kernel.
 int strip_columns(const lbm_sim *s, int kernel) {
     switch (kernel) {
     case LBM_KERNEL_WIDE2: return 2 * s->block_x;
     case LBM_KERNEL_WIDE4: return 4 * s->block_x;
-    case LBM_KERNEL_TWO: return s->block_x - 6;
+    case LBM_KERNEL_TWO:
+    case LBM_KERNEL_THREE: return s->block_x - 2 * (2 * steps_per_launch(kernel) - 1);
     default: return s->block_x;
     }
 }
@@ -474,7 +480,11 @@ lbm::StepArgs step_args_for(lbm_sim *s, int kernel, int &cache) {
             // one wave of resident workgroups, chunks of at least 8 rows
             int per_cu;
             switch (kernel) {
-            case LBM_KERNEL_TWO: per_cu = lbm::step2_blocks_per_cu(s->p.storage, s->block_x, s->m.trt != 0, s->m.sround != 0); break;
+            case LBM_KERNEL_TWO:
+            case LBM_KERNEL_THREE:
+                per_cu = lbm::stepk_blocks_per_cu(s->p.storage, s->block_x, steps_per_launch(kernel), s->m.trt != 0,
+                                                  s->m.sround != 0);
+                break;
             case LBM_KERNEL_SPLIT: per_cu = lbm::split_blocks_per_cu(s->p.storage, s->block_x); break;
             case LBM_KERNEL_WIDE2: per_cu = lbm::wide_blocks_per_cu(s->p.storage, s->block_x, 2); break;
             case LBM_KERNEL_WIDE4: per_cu = lbm::wide_blocks_per_cu(s->p.storage, s->block_x, 4); break;
@@ -507,7 +517,8 @@ lbm::StepArgs step_args(lbm_sim *s) { return step_args_for(s, s->kernel, s->chun
 
 hipError_t launch_on(const lbm_sim *s, const lbm::StepArgs &a, hipStream_t st) {
     switch (s->kernel) {
-    case LBM_KERNEL_TWO: return lbm::launch_step2(s->p.storage, a, s->block_x, st);
+    case LBM_KERNEL_TWO:
+    case LBM_KERNEL_THREE: return lbm::launch_stepk(s->p.storage, a, s->block_x, steps_per_launch(s->kernel), st);
     case LBM_KERNEL_SPLIT: return lbm::launch_step_split(s->p.storage, a, s->block_x, st);
     case LBM_KERNEL_WIDE2: return lbm::launch_step_wide(s->p.storage, a, s->block_x, 2, st);
     case LBM_KERNEL_WIDE4: return lbm::launch_step_wide(s->p.storage, a, s->block_x, 4, st);
@@ -528,14 +539,45 @@ void drop_graphs(lbm_sim *s) {
     }
 }
 
-// The two-step kernel's LDS at this block_x fits one workgroup on the device.
-bool two_fits(const lbm_sim *s, int block_x) {
-    return lbm::step2_lds_bytes(s->p.storage, block_x) <= (size_t)s->max_lds;
+// A multi-step kernel's LDS at this block_x fits one workgroup on the device.
+bool multi_fits(const lbm_sim *s, int kernel, int block_x) {
+    return lbm::stepk_lds_bytes(s->p.storage, block_x, steps_per_launch(kernel)) <= (size_t)s->max_lds;
 }
 
-// Launches of one graph replay: LBM_KERNEL_TWO advances two steps per launch.
-int launches_per_graph(const lbm_sim *s) {
-    return s->kernel == LBM_KERNEL_TWO ? s->graph_steps / 2 : s->graph_steps;
+// Issue the launches of nsteps steps from buffer parity `par` on stream st:
+// launches of the handle's kernel, then the nsteps mod k steps a multi-step
+// kernel leaves as fused-kernel launches at the same block_x.  par follows
+// the buffer parity (one flip per launch).
+hipError_t issue_steps(lbm_sim *s, hipStream_t st, int64_t nsteps, int &par) {
+    const int k = steps_per_launch(s->kernel);
+    lbm::StepArgs a = step_args(s);
+    for (int64_t n = 0; n + k <= nsteps; n += k) {
+        a.src = s->buf[par];
+        a.dst = s->buf[par ^ 1];
+        a.par = par;
+        const hipError_t e = launch_on(s, a, st);
+        if (e != hipSuccess) return e;
+        par ^= 1;
+    }
+    const int rem = (int)(nsteps % k);
+    if (rem) {
+        lbm::StepArgs b = step_args_for(s, LBM_KERNEL_FUSED, s->chunks1);
+        for (int r = 0; r < rem; ++r) {
+            b.src = s->buf[par];
+            b.dst = s->buf[par ^ 1];
+            b.par = par;
+            const hipError_t e = lbm::launch_step(s->p.storage, b, s->block_x, st);
+            if (e != hipSuccess) return e;
+            par ^= 1;
+        }
+    }
+    return hipSuccess;
+}
+
+// Launches of nsteps steps (see issue_steps).
+int64_t launches_for(const lbm_sim *s, int64_t nsteps) {
+    const int k = steps_per_launch(s->kernel);
+    return nsteps / k + nsteps % k;
 }
 
 // Capture the launches of graph_steps steps starting from buffer `parity` on the private
@@ -545,16 +587,9 @@ lbm_status capture_graph(lbm_sim *s, int parity) {
         s->cap = nullptr;
         return fail(s, LBM_EDEVICE, "cannot create the capture stream");
     }
-    lbm::StepArgs a = step_args(s);
     HIP_TRY(s, hipStreamBeginCapture(s->cap, hipStreamCaptureModeRelaxed));
-    hipError_t e = hipSuccess;
-    for (int k = 0; k < launches_per_graph(s) && e == hipSuccess; ++k) {
-        const int from = parity ^ (k & 1);
-        a.src = s->buf[from];
-        a.dst = s->buf[from ^ 1];
-        a.par = from;
-        e = launch_on(s, a, s->cap);
-    }
+    int par = parity;
+    const hipError_t e = issue_steps(s, s->cap, s->graph_steps, par);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(s->cap, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -585,28 +620,13 @@ lbm_status lbm_step(lbm_sim *s, int64_t nsteps) {
             HIP_TRY(s, hipGraphLaunch(s->gexec[s->cur], s->stream));
             left -= s->graph_steps;
             s->steps += s->graph_steps;
-            if (launches_per_graph(s) & 1) s->cur ^= 1;     // each launch flips the buffer parity
+            if (launches_for(s, s->graph_steps) & 1) s->cur ^= 1;     // each launch flips the buffer parity
         }
     }
-    lbm::StepArgs a = step_args(s);
-    const int per_launch = s->kernel == LBM_KERNEL_TWO ? 2 : 1;
-    for (; left >= per_launch; left -= per_launch) {
-        a.src = s->buf[s->cur];
-        a.dst = s->buf[s->cur ^ 1];
-        a.par = s->cur;
-        HIP_TRY(s, launch(s, a));
-        s->cur ^= 1;
-        s->steps += per_launch;
-    }
-    if (left) {     // the odd step of LBM_KERNEL_TWO: one fused-kernel step at the same block_x
-        lbm::StepArgs b = step_args_for(s, LBM_KERNEL_FUSED, s->chunks1);
-        b.src = s->buf[s->cur];
-        b.dst = s->buf[s->cur ^ 1];
-        b.par = s->cur;
-        HIP_TRY(s, lbm::launch_step(s->p.storage, b, s->block_x, s->stream));
-        s->cur ^= 1;
-        ++s->steps;
-    }
+    int par = s->cur;
+    HIP_TRY(s, issue_steps(s, s->stream, left, par));
+    s->cur = par;
+    s->steps += left;
     return LBM_OK;
 }
 
@@ -712,11 +732,12 @@ lbm_status lbm_set_tile(lbm_sim *s, int32_t block_x, int32_t rows) {
         return fail(s, LBM_EINVAL, "the split kernel takes block_x 128 or 256");
     if ((s->kernel == LBM_KERNEL_WIDE2 || s->kernel == LBM_KERNEL_WIDE4) && block_x > 256)
         return fail(s, LBM_EINVAL, "the wide kernels take block_x 64, 128 or 256");
-    if (s->kernel == LBM_KERNEL_TWO && block_x < 256)
-        return fail(s, LBM_EINVAL, "the two-step kernel takes block_x 256 or 512");
-    if (s->kernel == LBM_KERNEL_TWO && !two_fits(s, block_x))
-        return fail(s, LBM_EINVAL, "the two-step kernel at block_x %d needs %zu bytes of LDS per workgroup (device: %d)",
-                    block_x, lbm::step2_lds_bytes(s->p.storage, block_x), s->max_lds);
+    if (steps_per_launch(s->kernel) > 1 && block_x < 256)
+        return fail(s, LBM_EINVAL, "the multi-step kernels take block_x 256 or 512");
+    if (steps_per_launch(s->kernel) > 1 && !multi_fits(s, s->kernel, block_x))
+        return fail(s, LBM_EINVAL, "the %d-step kernel at block_x %d needs %zu bytes of LDS per workgroup (device: %d)",
+                    steps_per_launch(s->kernel), block_x,
+                    lbm::stepk_lds_bytes(s->p.storage, block_x, steps_per_launch(s->kernel)), s->max_lds);
     if (rows < 0) return fail(s, LBM_EINVAL, "rows_per_block must be >= 0");
     s->block_x = block_x;
     s->rows = rows;
@@ -743,20 +764,20 @@ lbm_status lbm_set_accel_field(lbm_sim *s, const float *acc) {
 lbm_status lbm_set_kernel(lbm_sim *s, int32_t kernel) {
     lbm_status st = usable(s);
     if (st) return st;
-    if (kernel < LBM_KERNEL_FUSED || kernel > LBM_KERNEL_TWO)
-        return fail(s, LBM_EINVAL, "kernel must be one of LBM_KERNEL_FUSED, _SPLIT, _WIDE2, _WIDE4, _FUSED8, _TWO");
-    const bool trt_sr_ok = kernel == LBM_KERNEL_FUSED || kernel == LBM_KERNEL_FUSED8 || kernel == LBM_KERNEL_TWO;
+    if (kernel < LBM_KERNEL_FUSED || kernel > LBM_KERNEL_THREE)
+        return fail(s, LBM_EINVAL, "kernel must be one of LBM_KERNEL_FUSED, _SPLIT, _WIDE2, _WIDE4, _FUSED8, _TWO, _THREE");
+    const bool trt_sr_ok = kernel == LBM_KERNEL_FUSED || kernel == LBM_KERNEL_FUSED8 || steps_per_launch(kernel) > 1;
     if (s->m.trt && !trt_sr_ok)
-        return fail(s, LBM_EINVAL, "the TRT operator runs in LBM_KERNEL_FUSED, _FUSED8 and _TWO only");
+        return fail(s, LBM_EINVAL, "the TRT operator runs in LBM_KERNEL_FUSED, _FUSED8, _TWO and _THREE only");
     if (s->m.sround && !trt_sr_ok)
-        return fail(s, LBM_EINVAL, "stochastic rounding runs in LBM_KERNEL_FUSED, _FUSED8 and _TWO only");
+        return fail(s, LBM_EINVAL, "stochastic rounding runs in LBM_KERNEL_FUSED, _FUSED8, _TWO and _THREE only");
     if (s->acc && kernel != LBM_KERNEL_FUSED)
         return fail(s, LBM_EINVAL, "an acceleration field runs in LBM_KERNEL_FUSED only");
     s->kernel = kernel;
     if (kernel == LBM_KERNEL_SPLIT && s->block_x != 128 && s->block_x != 256) s->block_x = 128;
     if ((kernel == LBM_KERNEL_WIDE2 || kernel == LBM_KERNEL_WIDE4) && s->block_x > 256) s->block_x = 256;
-    if (kernel == LBM_KERNEL_TWO && s->block_x < 256) s->block_x = 256;
-    if (kernel == LBM_KERNEL_TWO && !two_fits(s, s->block_x)) s->block_x = 256;
+    if (steps_per_launch(kernel) > 1 && s->block_x < 256) s->block_x = 256;
+    if (steps_per_launch(kernel) > 1 && !multi_fits(s, kernel, s->block_x)) s->block_x = 256;
     s->chunks = 0;
     s->chunks1 = 0;
     drop_graphs(s);
@@ -794,7 +815,7 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *row
                                  {LBM_KERNEL_WIDE2, 256}, {LBM_KERNEL_WIDE4, 64},  {LBM_KERNEL_WIDE4, 128},
                                  {LBM_KERNEL_SPLIT, 128}, {LBM_KERNEL_SPLIT, 256}, {LBM_KERNEL_FUSED8, 128},
                                  {LBM_KERNEL_FUSED8, 256}, {LBM_KERNEL_FUSED8, 512}, {LBM_KERNEL_TWO, 256},
-                                 {LBM_KERNEL_TWO, 512}};
+                                 {LBM_KERNEL_TWO, 512},    {LBM_KERNEL_THREE, 256},  {LBM_KERNEL_THREE, 512}};
     static const int kRows[] = {0, 4, 8, 16, 32, 64, 128};
     hipEvent_t e0, e1;
     HIP_TRY(s, hipEventCreate(&e0));
@@ -808,17 +829,19 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *row
     lbm_status res = LBM_OK;
     for (const Cand &cand : kCand) {
         const int bx = cand.bx;
-        if ((s->m.trt || s->m.sround) && cand.kernel != LBM_KERNEL_FUSED && cand.kernel != LBM_KERNEL_FUSED8 &&
-            cand.kernel != LBM_KERNEL_TWO)
+        const int kst = steps_per_launch(cand.kernel);
+        if ((s->m.trt || s->m.sround) && cand.kernel != LBM_KERNEL_FUSED && cand.kernel != LBM_KERNEL_FUSED8 && kst == 1)
             continue;
-        if (cand.kernel == LBM_KERNEL_TWO && !two_fits(s, bx)) continue;
-        // the two-step kernel recomputes six halo rows per chunk, so it is also
-        // tried at the chunk heights that give exactly k resident workgroups per
-        // compute unit (k = 1 .. its occupancy): longer chunks against more waves
+        if (kst > 1 && !multi_fits(s, cand.kernel, bx)) continue;
+        // the multi-step kernels recompute 2 (2k - 1) halo rows per chunk, so they
+        // are also tried at the chunk heights that give exactly j resident
+        // workgroups per compute unit (j = 1 .. their occupancy): longer chunks
+        // against more waves
         std::vector<int> rows_list(std::begin(kRows), std::end(kRows));
-        if (cand.kernel == LBM_KERNEL_TWO) {
-            const int strips = (s->p.nx + bx - 7) / (bx - 6);
-            const int per_cu = lbm::step2_blocks_per_cu(s->p.storage, bx, s->m.trt != 0, s->m.sround != 0);
+        if (kst > 1) {
+            const int cols = bx - 2 * (2 * kst - 1);
+            const int strips = (s->p.nx + cols - 1) / cols;
+            const int per_cu = lbm::stepk_blocks_per_cu(s->p.storage, bx, kst, s->m.trt != 0, s->m.sround != 0);
             for (int k = 1; k <= per_cu; ++k) {
                 const int chunks = std::max(1, (k * s->cus) / strips);
                 const int r = (s->p.ny + chunks - 1) / chunks;
@@ -846,8 +869,8 @@ lbm_status lbm_autotune(lbm_sim *s, int32_t reps, int32_t *block_x, int32_t *row
                 res = fail(s, LBM_EDEVICE, "autotune trial %dx%d failed: %s", bx, r, hipGetErrorString(e));
                 break;
             }
-            // per step: a launch of LBM_KERNEL_TWO advances two
-            const float us = 1000.f * ms / (float)reps / (cand.kernel == LBM_KERNEL_TWO ? 2.f : 1.f);
+            // per step: a launch of a multi-step kernel advances kst
+            const float us = 1000.f * ms / (float)reps / (float)kst;
             if (best == 0.f || us < best) {
                 best = us;
                 best_bx = bx;

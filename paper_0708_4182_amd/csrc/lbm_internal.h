@@ -93,11 +93,12 @@ int step_blocks_per_cu(int storage, int block_x, bool trt, bool sr);
 // The step kernel compiled for 8 waves per SIMD, and its resident workgroups.
 hipError_t launch_step8(int storage, const StepArgs &a, int block_x, hipStream_t s);
 int step8_blocks_per_cu(int storage, int block_x, bool trt, bool sr);
-// Two time steps per launch (src -> dst after two steps; strips of block_x - 6
-// columns), and its resident workgroups per compute unit.
-hipError_t launch_step2(int storage, const StepArgs &a, int block_x, hipStream_t s);
-size_t step2_lds_bytes(int storage, int block_x);
-int step2_blocks_per_cu(int storage, int block_x, bool trt, bool sr);
+// k = 2 or 3 time steps per launch (src -> dst after k steps; strips of
+// block_x - 2 (2k - 1) columns), its LDS per workgroup and its resident
+// workgroups per compute unit.
+hipError_t launch_stepk(int storage, const StepArgs &a, int block_x, int k, hipStream_t s);
+size_t stepk_lds_bytes(int storage, int block_x, int k);
+int stepk_blocks_per_cu(int storage, int block_x, int k, bool trt, bool sr);
 // The split step (a producer wave streams rows into LDS for block_x compute
 // threads; block_x = 128 or 256) and its resident workgroups per compute unit.
 hipError_t launch_step_split(int storage, const StepArgs &a, int block_x, hipStream_t s);

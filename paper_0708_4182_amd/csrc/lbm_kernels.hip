@@ -11,6 +11,7 @@
 #include "lbm_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace lbm {
 namespace {
@@ -632,41 +633,59 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8, 8))
 }
 
 // ---------------------------------------------------------------------------
-// Two time steps per launch (temporal blocking).  A step moves every
-// population through HBM once each way; two steps in one pass move them once
-// for both, with the intermediate post-collision rows kept in LDS in the
-// storage format (so that the result is bitwise that of two single steps:
-// the second step decodes exactly what the first would have stored).
+// K time steps per launch (temporal blocking, K = 2 or 3).  A step moves every
+// population through HBM once each way; K steps in one pass move them once
+// for all K, with the intermediate post-collision rows kept in LDS in the
+// storage format, so the result is bitwise that of K single steps (each level
+// decodes exactly what the level below would have stored).
 //
-// A workgroup of BX threads covers BX - 6 output columns: thread t works on
-// column x0 - 3 + t (periodic), and each level of the dependency chain uses
-// up one column on each side: the first step's collision needs phi of both
-// x-neighbours, the second step pulls from both, and its collision again
-// needs their phi.  For the same reason a chunk of rows [y0, y1) marches
-// through rows y0 - 3 .. y1 + 2.  Iteration i of the march (row a_i):
-//   A: pull row a_i from HBM (prefetched one row ahead), rho and phi of the
-//      first step, phi and the flag word into LDS rings;            barrier
-//   B: first collision of row a_{i-1} (phi of rows a_{i-2..i}), its nine
-//      results, encoded, into the LDS ring F;                       barrier
-//   C: second pull of row a_{i-2} from F (rows a_{i-3..i-1}, bounce-back from
-//      the node's own results), rho and phi of the second step;     barrier
-//   D: second collision of row a_{i-3} (phi rows a_{i-4..i-2}) and its store.
-// Rings hold three rows (slot of row a_j: j mod 3); each slot is rewritten
-// only after a barrier that follows its last read (stage D carries its row's
-// pulled values from stage C instead of pulling again).  Threads outside [3, 3 + nact) and rows outside the
-// chunk are computed for their neighbours and not stored.
-template <int S>
-constexpr size_t two_lds_bytes(int bx) {
-    return (size_t)2 * 3 * (bx + 2) * sizeof(float) + (size_t)3 * bx * sizeof(uint32_t) +
-           (size_t)3 * 9 * (bx + 2) * sizeof(typename Codec<S>::T);
+// Each level of the dependency chain uses up one column and one row on each
+// side twice (its pull reads the neighbours of the level below; its collision
+// needs the neighbours' phi), so with H = 2K - 1 a workgroup of BX threads
+// covers BX - 2H output columns (thread t works on column x0 - H + t,
+// periodic) and a chunk of rows [y0, y1) marches through rows y0 - H .. y1 +
+// H - 1.  Iteration i of the march (row a_i), for levels k = 0 .. K-1:
+//   A:    pull row a_i from HBM (prefetched one row ahead), rho and phi of
+//         level 0, phi and the flag word into LDS rings;             barrier
+//   B_0:  level-0 collision of row a_{i-1} (phi of rows a_{i-2..i}), its
+//         nine results, encoded, into the LDS ring F_0;               barrier
+//   C_k:  (k >= 1) level-k pull of row a_{i-2k} from F_{k-1} (rows
+//         a_{i-2k-1..i-2k+1}, bounce-back from the node's own results), rho
+//         and phi of level k;                                         barrier
+//   B_k:  level-k collision of row a_{i-2k-1} (phi rows a_{i-2k-2..i-2k}),
+//         into F_k, or for the last level stored to HBM;  barrier (not last)
+// B_k uses the pulled values C_k produced one iteration earlier (carried in
+// registers).  The phi and F rings hold three rows (slot of row a_j: j mod 3)
+// and the flag ring four (K = 2) or eight rows (slot j mod FR); every slot is
+// rewritten only after a barrier that follows its last read.  Threads outside
+// [H, H + nact) and rows outside the chunk are computed for their neighbours
+// and not stored.
+template <int K> struct Multi {
+    static constexpr int H = 2 * K - 1;       // halo columns and rows per side
+    static constexpr int FR = K == 2 ? 4 : 8; // flag ring rows (holds row a_{i-2(K-1)} while a_i is written)
+};
+
+template <int S, int K>
+constexpr size_t multi_lds_bytes(int bx) {
+    return (size_t)K * 3 * (bx + 2) * sizeof(float) + (size_t)Multi<K>::FR * bx * sizeof(uint16_t) +
+           (size_t)(K - 1) * 3 * 9 * (bx + 2) * sizeof(typename Codec<S>::T);
 }
 
-template <int S, bool TRT, bool SR, int BX>
-__device__ __forceinline__ void step2_tile(const StepArgs &a, int x0, int y0, int y1, bool up, char *lds,
-                                           uint32_t mix0, uint32_t mix1) {
+// Slot of row a_{i-d} in a three-row ring, from the slot s0 of row a_i.
+template <int D>
+__device__ __forceinline__ int slot_back(int s0) {
+    constexpr int r = D % 3;
+    if constexpr (r == 0) return s0;
+    else return s0 >= r ? s0 - r : s0 + 3 - r;
+}
+
+template <int S, bool TRT, bool SR, int BX, int K>
+__device__ __forceinline__ void stepk_tile(const StepArgs &a, int x0, int y0, int y1, bool up, char *lds,
+                                           const uint32_t (&mix)[K]) {
     using C = Codec<S>;
     using T = typename C::T;
     constexpr uint32_t E = sizeof(T);
+    constexpr int H = Multi<K>::H, FR = Multi<K>::FR;
     const Grid &g = a.g;
     const Model &m = a.m;
     constexpr int P = BX + 2;   // ring rows carry one padding slot per side (compile-time strides)
@@ -676,28 +695,29 @@ __device__ __forceinline__ void step2_tile(const StepArgs &a, int x0, int y0, in
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.src, 9u * plane * E);
     const __amdgpu_buffer_rsrc_t rd = make_rsrc(a.dst, 9u * plane * E);
     const __amdgpu_buffer_rsrc_t rf = make_rsrc(a.flags, plane * 2u);
-    const int nrows = y1 - y0 + 6;
+    const int nrows = y1 - y0 + 2 * H;
 
-    const int nact = min(BX - 6, nx - x0);
-    const bool out_col = tid >= 3 && tid < 3 + nact;
-    int xc = (x0 - 3 + tid) % nx;
+    const int nact = min(BX - 2 * H, nx - x0);
+    const bool out_col = tid >= H && tid < H + nact;
+    int xc = (x0 - H + tid) % nx;
     if (xc < 0) xc += nx;
     const uint32_t x = (uint32_t)xc;
     const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x == (uint32_t)nx - 1 ? 0 : x + 1;
 
-    float *psiA = reinterpret_cast<float *>(lds);      // phi of the first step  [3][P]
-    float *psiB = psiA + 3 * P;                         // phi of the second step [3][P]
-    uint32_t *flr = reinterpret_cast<uint32_t *>(psiB + 3 * P);   // flag words [3][BX]
-    T *F = reinterpret_cast<T *>(flr + 3 * BX);         // first-step results [3][9][P]
+    float *psi = reinterpret_cast<float *>(lds);                     // phi of level k  [K][3][P]
+    uint16_t *flr = reinterpret_cast<uint16_t *>(psi + K * 3 * P);   // flag words      [FR][BX]
+    T *F = reinterpret_cast<T *>(flr + FR * BX);                     // level-k results [K-1][3][9][P]
     if (tid < 6) {      // padding slots (read only by threads whose results are unused)
-        const int k = tid >> 1, side = (tid & 1) ? P - 1 : 0;
-        psiA[k * P + side] = 0.f;
-        psiB[k * P + side] = 0.f;
+        const int r = tid >> 1, side = (tid & 1) ? P - 1 : 0;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) F[(k * 9 + q) * P + side] = C::enc(0.f);
+        for (int k = 0; k < K; ++k) psi[(k * 3 + r) * P + side] = 0.f;
+#pragma unroll
+        for (int k = 0; k < K - 1; ++k)
+#pragma unroll
+            for (int q = 0; q < 9; ++q) F[((k * 3 + r) * 9 + q) * P + side] = C::enc(0.f);
     }
 
-    auto row_at = [&](int i) { return wrapi(up ? y0 - 3 + i : y1 + 2 - i, ny); };
+    auto row_at = [&](int i) { return wrapi(up ? y0 - H + i : y1 + H - 1 - i, ny); };
 
     const uint32_t v0 = x * E, vm = xm * E, vp = xp * E, vf = x * 2u;
     T raw[9];
@@ -723,16 +743,67 @@ __device__ __forceinline__ void step2_tile(const StepArgs &a, int x0, int y0, in
     };
     auto load_flags = [&](int yr) { return bload_flag(rf, vf, (uint32_t)yr * pitch * 2u); };
 
-    // first step: pulled populations of the previous row (decoded) and their moments
-    float pd[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    float ps = 0.f, pjx = 0.f, pjy = 0.f;
-    uint32_t pfl = FL_SOLID;
-    int pyr = 0;
-    // second step: the same for the row the next D stage collides
-    float qd[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    float qs = 0.f, qjx = 0.f, qjy = 0.f;
-    uint32_t qfl = FL_SOLID;
-    int qyr = 0;
+    // per level: pulled populations (decoded), moments, flag word and row of
+    // the row its next collision takes
+    float pd[K][9], ps[K], pjx[K], pjy[K];
+    uint32_t pfl[K];
+    int pyr[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) pd[k][q] = 0.f;
+        ps[k] = pjx[k] = pjy[k] = 0.f;
+        pfl[k] = FL_SOLID;
+        pyr[k] = 0;
+    }
+
+    // collision of level k from its carried values; results encoded (nearest or
+    // stochastic with the level's mix) into out
+    auto collide_level = [&](auto kc, const float *rowm, const float *row0, const float *rowp, T out[9]) {
+        constexpr int k = decltype(kc)::value;
+        float p[9];
+        collide_post<TRT>(m, pd[k], ps[k], pjx[k], pjy[k], pfl[k], rowm, row0, rowp, tid + 1, p);
+        if constexpr (SR) {
+            const uint32_t k0 = ((uint32_t)pyr[k] * pitch + x) * 5u;
+            uint32_t h[5];
+#pragma unroll
+            for (int j = 0; j < 5; ++j) h[j] = lowbias32((k0 + (uint32_t)j) ^ mix[k]);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) out[q] = C::enc_sr(p[q], (q & 1) ? (h[q >> 1] >> 16) : (h[q >> 1] & 0xFFFFu));
+        } else {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) out[q] = C::enc(p[q]);
+        }
+    };
+    // level k >= 1 pull of row a_{i-2k} (slot k0 of ring F_{k-1}; km / kp: rows y -+ 1)
+    auto pull_level = [&](const T *Fb, int ks, int km, int kp, uint32_t nb, float d[9]) {
+        const T *Fk = Fb + ks * 9 * P + tid + 1, *Fm = Fb + km * 9 * P + tid + 1, *Fp = Fb + kp * 9 * P + tid + 1;
+        // population a from x - e_a, or (bounce-back) opp(a) of the node itself;
+        // a wave none of whose nodes has a solid neighbour skips the selection
+        T v[9];
+        v[0] = Fk[0 * P];
+        if (__builtin_amdgcn_ballot_w64(nb != 0u) == 0) {
+            v[1] = Fk[1 * P - 1];
+            v[2] = Fm[2 * P];
+            v[3] = Fk[3 * P + 1];
+            v[4] = Fp[4 * P];
+            v[5] = Fm[5 * P - 1];
+            v[6] = Fm[6 * P + 1];
+            v[7] = Fp[7 * P + 1];
+            v[8] = Fp[8 * P - 1];
+        } else {
+            v[1] = (nb & 0x04u) ? Fk[3 * P] : Fk[1 * P - 1];
+            v[2] = (nb & 0x08u) ? Fk[4 * P] : Fm[2 * P];
+            v[3] = (nb & 0x01u) ? Fk[1 * P] : Fk[3 * P + 1];
+            v[4] = (nb & 0x02u) ? Fk[2 * P] : Fp[4 * P];
+            v[5] = (nb & 0x40u) ? Fk[7 * P] : Fm[5 * P - 1];
+            v[6] = (nb & 0x80u) ? Fk[8 * P] : Fm[6 * P + 1];
+            v[7] = (nb & 0x10u) ? Fk[5 * P] : Fp[7 * P + 1];
+            v[8] = (nb & 0x20u) ? Fk[6 * P] : Fp[8 * P - 1];
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) d[q] = C::dec(v[q]);
+    };
 
     uint32_t fl1, fl2;
     {
@@ -742,10 +813,9 @@ __device__ __forceinline__ void step2_tile(const StepArgs &a, int x0, int y0, in
         fl1 = f0;
     }
 
-    int sl0 = 0;     // slot of row a_i (i mod 3); sl1: a_{i-1}, sl2: a_{i-2} (= a_{i-4} and a_{i-3} one round later)
-    for (int i = 0; i < nrows; ++i, sl0 = sl0 == 2 ? 0 : sl0 + 1) {
-        const int sl1 = sl0 == 0 ? 2 : sl0 - 1, sl2 = sl0 == 2 ? 0 : sl0 + 1;
-        // A: row a_i
+    int s0 = 0;     // slot of row a_i in the three-row rings (i mod 3)
+    for (int i = 0; i < nrows; ++i, s0 = s0 == 2 ? 0 : s0 + 1) {
+        // A: row a_i, level 0
         const int yr = row_at(i);
         const uint32_t cfl = fl1;
         T craw[9];
@@ -758,125 +828,104 @@ __device__ __forceinline__ void step2_tile(const StepArgs &a, int x0, int y0, in
 #pragma unroll
         for (int q = 0; q < 9; ++q) cd[q] = C::dec(craw[q]);
         moments9(cd, cs, cjx, cjy);
-        psiA[sl0 * P + tid + 1] = (cfl & FL_SOLID) ? 0.f : pseudopotential(m, m.rho_off + cs);
-        flr[sl0 * BX + tid] = cfl;
+        psi[s0 * P + tid + 1] = (cfl & FL_SOLID) ? 0.f : pseudopotential(m, m.rho_off + cs);
+        flr[(i & (FR - 1)) * BX + tid] = (uint16_t)cfl;
         lds_barrier();
 
-        // B: first collision of row a_{i-1}
-        if (i >= 2 && !(pfl & FL_SOLID)) {
-            const float *older = psiA + sl2 * P, *mid = psiA + sl1 * P, *newer = psiA + sl0 * P;
-            float p[9];
-            collide_post<TRT>(m, pd, ps, pjx, pjy, pfl, up ? older : newer, mid, up ? newer : older, tid + 1, p);
-            T *fr = F + sl1 * 9 * P + tid + 1;
-            if constexpr (SR) {
-                const uint32_t k0 = ((uint32_t)pyr * pitch + x) * 5u;
-                uint32_t h[5];
+        // B_0: level-0 collision of row a_{i-1} into F_0 (or, for K = 1, HBM)
+        {
+            const float *older = psi + slot_back<2>(s0) * P, *mid = psi + slot_back<1>(s0) * P,
+                        *newer = psi + s0 * P;
+            if (i >= 2 && !(pfl[0] & FL_SOLID)) {
+                T o[9];
+                collide_level(std::integral_constant<int, 0>{}, up ? older : newer, mid, up ? newer : older, o);
+                T *fr = F + slot_back<1>(s0) * 9 * P + tid + 1;
 #pragma unroll
-                for (int k = 0; k < 5; ++k) h[k] = lowbias32((k0 + (uint32_t)k) ^ mix0);
-#pragma unroll
-                for (int q = 0; q < 9; ++q) fr[q * P] = C::enc_sr(p[q], (q & 1) ? (h[q >> 1] >> 16) : (h[q >> 1] & 0xFFFFu));
-            } else {
-#pragma unroll
-                for (int q = 0; q < 9; ++q) fr[q * P] = C::enc(p[q]);
+                for (int q = 0; q < 9; ++q) fr[q * P] = o[q];
             }
         }
 #pragma unroll
-        for (int q = 0; q < 9; ++q) pd[q] = cd[q];
-        ps = cs;
-        pjx = cjx;
-        pjy = cjy;
-        pfl = cfl;
-        pyr = yr;
+        for (int q = 0; q < 9; ++q) pd[0][q] = cd[q];
+        ps[0] = cs;
+        pjx[0] = cjx;
+        pjy[0] = cjy;
+        pfl[0] = cfl;
+        pyr[0] = yr;
         lds_barrier();
 
-        // C: second pull of row a_{i-2} from F, rho and phi of the second step
-        float ed[9], es = 0.f, ejx = 0.f, ejy = 0.f;
-        uint32_t efl = FL_SOLID;
-        if (i >= 4) {
-            const int k = sl2;                  // row a_{i-2}
-            const int km = up ? sl0 : sl1;       // slot of row y - 1 (a_{i-3} marching up)
-            const int kp = up ? sl1 : sl0;       // slot of row y + 1
-            efl = flr[k * BX + tid];
-            const uint32_t nb = efl & 0xFFu;
-            const T *Fk = F + k * 9 * P + tid + 1, *Fm = F + km * 9 * P + tid + 1, *Fp = F + kp * 9 * P + tid + 1;
-            // population a from x - e_a, or (bounce-back) opp(a) of the node itself;
-            // a wave none of whose nodes has a solid neighbour skips the selection
-            T v[9];
-            v[0] = Fk[0 * P];
-            if (__builtin_amdgcn_ballot_w64(nb != 0u) == 0) {
-                v[1] = Fk[1 * P - 1];
-                v[2] = Fm[2 * P];
-                v[3] = Fk[3 * P + 1];
-                v[4] = Fp[4 * P];
-                v[5] = Fm[5 * P - 1];
-                v[6] = Fm[6 * P + 1];
-                v[7] = Fp[7 * P + 1];
-                v[8] = Fp[8 * P - 1];
-            } else {
-                v[1] = (nb & 0x04u) ? Fk[3 * P] : Fk[1 * P - 1];
-                v[2] = (nb & 0x08u) ? Fk[4 * P] : Fm[2 * P];
-                v[3] = (nb & 0x01u) ? Fk[1 * P] : Fk[3 * P + 1];
-                v[4] = (nb & 0x02u) ? Fk[2 * P] : Fp[4 * P];
-                v[5] = (nb & 0x40u) ? Fk[7 * P] : Fm[5 * P - 1];
-                v[6] = (nb & 0x80u) ? Fk[8 * P] : Fm[6 * P + 1];
-                v[7] = (nb & 0x10u) ? Fk[5 * P] : Fp[7 * P + 1];
-                v[8] = (nb & 0x20u) ? Fk[6 * P] : Fp[8 * P - 1];
-            }
-#pragma unroll
-            for (int q = 0; q < 9; ++q) ed[q] = C::dec(v[q]);
-            moments9(ed, es, ejx, ejy);
-            psiB[k * P + tid + 1] = (efl & FL_SOLID) ? 0.f : pseudopotential(m, m.rho_off + es);
-        }
-        lds_barrier();
-
-        // D: second collision of row a_{i-3}, stored
-        if (i >= 6 && out_col && !(qfl & FL_SOLID)) {
-            const float *older = psiB + sl1 * P, *mid = psiB + sl0 * P, *newer = psiB + sl2 * P;   // a_{i-4..i-2}
-            float p[9];
-            collide_post<TRT>(m, qd, qs, qjx, qjy, qfl, up ? older : newer, mid, up ? newer : older, tid + 1, p);
-            const uint32_t prow = (uint32_t)qyr * pitch;
-            T o[9];
-            if constexpr (SR) {
-                const uint32_t k0 = (prow + x) * 5u;
-                uint32_t h[5];
-#pragma unroll
-                for (int k = 0; k < 5; ++k) h[k] = lowbias32((k0 + (uint32_t)k) ^ mix1);
-#pragma unroll
-                for (int q = 0; q < 9; ++q) o[q] = C::enc_sr(p[q], (q & 1) ? (h[q >> 1] >> 16) : (h[q >> 1] & 0xFFFFu));
+        // levels 1 .. K-1: C_k, barrier, B_k (barrier between levels)
+        auto level = [&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            // C_k: pull of row a_{i-2k} from F_{k-1}, rho and phi of level k
+            float ed[9], es = 0.f, ejx = 0.f, ejy = 0.f;
+            uint32_t efl = FL_SOLID;
+            const int sk = slot_back<2 * k>(s0);
+            if (i >= 4 * k) {
+                const int km = up ? slot_back<2 * k + 1>(s0) : slot_back<2 * k - 1>(s0);   // row y - 1
+                const int kp = up ? slot_back<2 * k - 1>(s0) : slot_back<2 * k + 1>(s0);   // row y + 1
+                efl = flr[((i - 2 * k) & (FR - 1)) * BX + tid];
+                pull_level(F + (k - 1) * 3 * 9 * P, sk, km, kp, efl & 0xFFu, ed);
+                moments9(ed, es, ejx, ejy);
+                psi[(k * 3 + sk) * P + tid + 1] = (efl & FL_SOLID) ? 0.f : pseudopotential(m, m.rho_off + es);
             } else {
 #pragma unroll
-                for (int q = 0; q < 9; ++q) o[q] = C::enc(p[q]);
+                for (int q = 0; q < 9; ++q) ed[q] = 0.f;
+            }
+            lds_barrier();
+            // B_k: level-k collision of row a_{i-2k-1} (phi rows a_{i-2k-2 .. i-2k})
+            const float *pk = psi + k * 3 * P;
+            const float *older = pk + slot_back<2 * k + 2>(s0) * P, *mid = pk + slot_back<2 * k + 1>(s0) * P,
+                        *newer = pk + sk * P;
+            if constexpr (k == K - 1) {
+                if (i >= 4 * k + 2 && out_col && !(pfl[k] & FL_SOLID)) {
+                    T o[9];
+                    collide_level(kc, up ? older : newer, mid, up ? newer : older, o);
+                    const uint32_t prow = (uint32_t)pyr[k] * pitch;
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) bstore(rd, v0, ((uint32_t)q * plane + prow) * E, o[q]);
+                }
+            } else {
+                if (i >= 4 * k + 2 && !(pfl[k] & FL_SOLID)) {
+                    T o[9];
+                    collide_level(kc, up ? older : newer, mid, up ? newer : older, o);
+                    T *fr = F + (k * 3 + slot_back<2 * k + 1>(s0)) * 9 * P + tid + 1;
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) fr[q * P] = o[q];
+                }
             }
 #pragma unroll
-            for (int q = 0; q < 9; ++q) bstore(rd, v0, ((uint32_t)q * plane + prow) * E, o[q]);
-        }
-#pragma unroll
-        for (int q = 0; q < 9; ++q) qd[q] = ed[q];
-        qs = es;
-        qjx = ejx;
-        qjy = ejy;
-        qfl = efl;
-        qyr = row_at(i - 2 >= 0 ? i - 2 : 0);
+            for (int q = 0; q < 9; ++q) pd[k][q] = ed[q];
+            ps[k] = es;
+            pjx[k] = ejx;
+            pjy[k] = ejy;
+            pfl[k] = efl;
+            pyr[k] = row_at(i - 2 * k >= 0 ? i - 2 * k : 0);
+            if constexpr (k < K - 1) lds_barrier();
+        };
+        level(std::integral_constant<int, 1>{});
+        if constexpr (K >= 3) level(std::integral_constant<int, 2>{});
     }
 }
 
-template <int S, bool TRT, bool SR, int BX>
-__global__ void __launch_bounds__(BX) k_step2(const StepArgs a) {
-    extern __shared__ char lds2[];
-    uint32_t mix0 = 0u, mix1 = 0u;
+template <int S, bool TRT, bool SR, int BX, int K>
+__global__ void __launch_bounds__(BX) k_stepk(const StepArgs a) {
+    extern __shared__ char ldsk[];
+    uint32_t mix[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) mix[k] = 0u;
     if constexpr (SR) {
-        // the step counts of both steps; the next launch reads count + 2
+        // the step counts of the K steps; the next launch reads count + K
         const uint32_t count = a.rng[a.par];
-        if (blockIdx.x == 0 && threadIdx.x == 0) a.rng[a.par ^ 1] = count + 2u;
-        mix0 = lowbias32(count + 0x9e3779b9u);
-        mix1 = lowbias32(count + 1u + 0x9e3779b9u);
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.rng[a.par ^ 1] = count + (uint32_t)K;
+#pragma unroll
+        for (int k = 0; k < K; ++k) mix[k] = lowbias32(count + (uint32_t)k + 0x9e3779b9u);
     }
     const int tile = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
     if (tile >= a.ntiles) return;   // uniform for the workgroup, before any barrier
     const int strip = tile / a.chunks, chunk = tile - strip * a.chunks;
     const int y0 = (int)(((int64_t)chunk * a.g.ny) / a.chunks);
     const int y1 = (int)(((int64_t)(chunk + 1) * a.g.ny) / a.chunks);
-    step2_tile<S, TRT, SR, BX>(a, strip * (BX - 6), y0, y1, (chunk & 1) == 0, lds2, mix0, mix1);
+    stepk_tile<S, TRT, SR, BX, K>(a, strip * (BX - 2 * Multi<K>::H), y0, y1, (chunk & 1) == 0, ldsk, mix);
 }
 
 // ---------------------------------------------------------------------------
@@ -1728,48 +1777,58 @@ hipError_t launch_step(int storage, const StepArgs &a, int block_x, hipStream_t 
     return launch_step_k<false>(storage, a, block_x, s);
 }
 
-// The two-step kernel is compiled for block_x 256 and 512 (ring strides are
-// compile-time constants).
-template <int S, int BX>
-StepKernel step2_k16(bool trt, bool sr) {
-    return trt ? (sr ? k_step2<S, true, true, BX> : k_step2<S, true, false, BX>)
-               : (sr ? k_step2<S, false, true, BX> : k_step2<S, false, false, BX>);
+// The multi-step kernels are compiled for K = 2, 3 steps per launch and
+// block_x 256 and 512 (ring strides are compile-time constants).
+template <int S, int BX, int K>
+StepKernel stepk_k16(bool trt, bool sr) {
+    return trt ? (sr ? k_stepk<S, true, true, BX, K> : k_stepk<S, true, false, BX, K>)
+               : (sr ? k_stepk<S, false, true, BX, K> : k_stepk<S, false, false, BX, K>);
 }
-template <int BX>
-StepKernel step2_kernel_bx(int storage, bool trt, bool sr) {
+template <int BX, int K>
+StepKernel stepk_kernel_bx(int storage, bool trt, bool sr) {
     switch (storage) {
     case ST_F32:
         if (sr) return nullptr;
-        return trt ? k_step2<ST_F32, true, false, BX> : k_step2<ST_F32, false, false, BX>;
-    case ST_F16: return step2_k16<ST_F16, BX>(trt, sr);
-    case ST_BF16: return step2_k16<ST_BF16, BX>(trt, sr);
+        return trt ? k_stepk<ST_F32, true, false, BX, K> : k_stepk<ST_F32, false, false, BX, K>;
+    case ST_F16: return stepk_k16<ST_F16, BX, K>(trt, sr);
+    case ST_BF16: return stepk_k16<ST_BF16, BX, K>(trt, sr);
     default: return nullptr;
     }
 }
-StepKernel step2_kernel(int storage, int block_x, bool trt, bool sr) {
+template <int K>
+StepKernel stepk_kernel_k(int storage, int block_x, bool trt, bool sr) {
     switch (block_x) {
-    case 256: return step2_kernel_bx<256>(storage, trt, sr);
-    case 512: return step2_kernel_bx<512>(storage, trt, sr);
+    case 256: return stepk_kernel_bx<256, K>(storage, trt, sr);
+    case 512: return stepk_kernel_bx<512, K>(storage, trt, sr);
     default: return nullptr;
     }
 }
-size_t step2_lds_bytes(int storage, int block_x) {
-    return storage == ST_F32 ? two_lds_bytes<ST_F32>(block_x) : two_lds_bytes<ST_F16>(block_x);
+StepKernel stepk_kernel(int storage, int block_x, int k, bool trt, bool sr) {
+    switch (k) {
+    case 2: return stepk_kernel_k<2>(storage, block_x, trt, sr);
+    case 3: return stepk_kernel_k<3>(storage, block_x, trt, sr);
+    default: return nullptr;
+    }
+}
+size_t stepk_lds_bytes(int storage, int block_x, int k) {
+    if (k == 3) return storage == ST_F32 ? multi_lds_bytes<ST_F32, 3>(block_x) : multi_lds_bytes<ST_F16, 3>(block_x);
+    return storage == ST_F32 ? multi_lds_bytes<ST_F32, 2>(block_x) : multi_lds_bytes<ST_F16, 2>(block_x);
 }
 
-hipError_t launch_step2(int storage, const StepArgs &a, int block_x, hipStream_t s) {
-    StepKernel k = step2_kernel(storage, block_x, a.m.trt != 0, a.m.sround != 0);
-    if (!k || a.acc) return hipErrorInvalidValue;
+hipError_t launch_stepk(int storage, const StepArgs &a, int block_x, int k, hipStream_t s) {
+    StepKernel kern = stepk_kernel(storage, block_x, k, a.m.trt != 0, a.m.sround != 0);
+    if (!kern || a.acc) return hipErrorInvalidValue;
     const unsigned blocks = 8u * (unsigned)a.tiles_per_xcd;
-    k<<<blocks, block_x, step2_lds_bytes(storage, block_x), s>>>(a);
+    kern<<<blocks, block_x, stepk_lds_bytes(storage, block_x, k), s>>>(a);
     return hipGetLastError();
 }
 
-int step2_blocks_per_cu(int storage, int block_x, bool trt, bool sr) {
-    StepKernel k = step2_kernel(storage, block_x, trt, sr);
-    if (!k) return 1;
+int stepk_blocks_per_cu(int storage, int block_x, int k, bool trt, bool sr) {
+    StepKernel kern = stepk_kernel(storage, block_x, k, trt, sr);
+    if (!kern) return 1;
     int n = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, block_x, step2_lds_bytes(storage, block_x));
+    const hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, block_x, stepk_lds_bytes(storage, block_x, k));
     return e == hipSuccess && n > 0 ? n : 1;
 }
 

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LBM_LIB") or os.path.join(HERE, "liblbm.so")
 
 LBM_F32, LBM_F16, LBM_BF16 = 0, 1, 2
-KERNELS = {"fused": 0, "split": 1, "wide2": 2, "wide4": 3, "fused8": 4, "two": 5}
+KERNELS = {"fused": 0, "split": 1, "wide2": 2, "wide4": 3, "fused8": 4, "two": 5, "three": 6}
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
           -4: "LBM_EDIVERGED", -5: "LBM_ESTATE"}
 

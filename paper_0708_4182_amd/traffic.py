@@ -5,7 +5,9 @@
 FETCH_DIR and WRITE_DIR hold the pmc_counter_collection.csv of a
 ``rocprofv3 --pmc FETCH_SIZE`` and a ``--pmc WRITE_SIZE`` run of the profiling
 driver (csrc/step_driver.cpp) on the 8192 x 2048 channel (one run per tile and
-counter).  Each counter is scaled by what it reads for the copy of one FP32
+counter).  A launch of a multi-step kernel (k_stepk) covers two or three time
+steps and, like every step kernel, reads and writes each population once: its
+algorithmic bytes per launch are the same 18 values per fluid node.  Each counter is scaled by what it reads for the copy of one FP32
 population buffer in the same run (k_stream_copy, 9 * nx * ny * 4 bytes each
 way; torch's __amd_rocclr_copyBuffer in runs of bench.py).  The result is
 merged into profiles/traffic.json, keyed by storage and tile and stamped with
@@ -26,7 +28,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_0708_4182_amd", "csrc", "lbm_kernels.hip"
 OUT = os.path.join(ROOT, "profiles", "traffic.json")
 STORAGE_NAMES = {0: "f32", 1: "f16", 2: "bf16"}
 BYTES = {0: 4, 1: 2, 2: 2}
-STEP_RE = re.compile(r"(k_step(?:8|_wide|_split)?)<(\d)[^>]*>")
+STEP_RE = re.compile(r"(k_step(?:k|2|8|_wide|_split)?)<(\d)[^>]*>")
 
 
 def kernel_sha() -> str:

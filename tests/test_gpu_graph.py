@@ -30,7 +30,8 @@ def same(a, b):
 
 
 @pytest.mark.parametrize("name,kernel", [("ragged130x67", "fused"), ("droplet128x64", "fused8"),
-                                         ("ragged37x19", "split"), ("ragged130x67", "two")])
+                                         ("ragged37x19", "split"), ("ragged130x67", "two"),
+                                         ("droplet128x64", "three")])
 def test_graph_replays_equal_launches(lbm, name, kernel):
     c = CASES[name]()
     a = lbm.from_case(c)

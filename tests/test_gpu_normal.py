@@ -93,7 +93,7 @@ def test_flat_walls_equal_electrode_direction(lbm):
 
 
 @pytest.mark.parametrize("kernel,tile", [("fused8", (256, 0)), ("wide2", (64, 0)), ("split", (128, 0)),
-                                         ("two", (256, 0))])
+                                         ("two", (256, 0)), ("three", (512, 0))])
 def test_normal_kernels_bitwise_equal_fused(lbm, kernel, tile):
     c = normal_case("ragged130x67")
     a = lbm.from_case(c)

@@ -157,7 +157,8 @@ KERNEL_TILES = [("split", (128, 0)), ("split", (256, 0)), ("split", (128, 7)), (
                 ("wide2", (64, 0)), ("wide2", (128, 7)), ("wide2", (256, 64)),
                 ("wide4", (64, 5)), ("wide4", (128, 0)),
                 ("fused8", (256, 0)), ("fused8", (128, 7)), ("fused8", (512, 64)),
-                ("two", (256, 0)), ("two", (256, 7)), ("two", (512, 64)), ("two", (512, 3))]
+                ("two", (256, 0)), ("two", (256, 7)), ("two", (512, 64)), ("two", (512, 3)),
+                ("three", (256, 0)), ("three", (256, 5)), ("three", (512, 64)), ("three", (512, 2))]
 
 
 @pytest.mark.parametrize("storage", [0, 1, 2])
@@ -176,7 +177,7 @@ def test_kernels_bitwise_equal_fused(lbm, storage, kernel, tile):
             b.set_tile(*tile)
         except lbm.LBMError as e:
             # the two-step kernel's LDS grows with block_x (FP32 at 512: 98.7 KB)
-            if kernel == "two" and "LDS" in str(e):
+            if kernel in ("two", "three") and "LDS" in str(e):
                 pytest.skip(f"device LDS per workgroup: {e}")
             raise
         assert b.tile() == (kernel,) + tile
@@ -187,20 +188,22 @@ def test_kernels_bitwise_equal_fused(lbm, storage, kernel, tile):
         assert a.flux() == b.flux()
 
 
+@pytest.mark.parametrize("kernel", ["two", "three"])
 @pytest.mark.parametrize("storage", [0, 1, 2])
 @pytest.mark.parametrize("nsteps", [1, 7, 20])
-def test_two_step_odd_counts_and_calls(lbm, storage, nsteps):
-    """LBM_KERNEL_TWO over step counts that are odd (the last step runs the
-    fused kernel) and split over several calls: every call ends on the state
-    of the fused kernel after the same number of steps."""
+def test_multi_step_counts_and_calls(lbm, kernel, storage, nsteps):
+    """The multi-step kernels over step counts that are not multiples of their
+    steps per launch (the remainder runs the fused kernel) and split over
+    several calls: every call ends on the state of the fused kernel after the
+    same number of steps."""
     for name in ("ragged37x19", "ragged130x67", "droplet128x64", "ragged300x5"):
         c = CASES[name]()
         c.params = c.params.replace(storage=storage)
         a = lbm.from_case(c)
         b = lbm.from_case(c)
-        b.set_kernel("two")
+        b.set_kernel(kernel)
         b.set_tile(256, 0)
-        for n in (nsteps, nsteps + 1, 3):
+        for n in (nsteps, nsteps + 1, 3, 5):
             a.step(n)
             b.step(n)
             assert a.steps_done == b.steps_done
@@ -209,7 +212,7 @@ def test_two_step_odd_counts_and_calls(lbm, storage, nsteps):
         assert a.flux() == b.flux()
 
 
-@pytest.mark.parametrize("kernel", ["split", "wide2", "wide4", "fused8", "two"])
+@pytest.mark.parametrize("kernel", ["split", "wide2", "wide4", "fused8", "two", "three"])
 def test_kernels_full_size(lbm, kernel):
     c = I.random_channel_case(nx=8192, ny=2048, seed=0)
     a = lbm.from_case(c)

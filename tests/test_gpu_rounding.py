@@ -141,7 +141,15 @@ def test_reproducible_graph_kernel8(lbm):
     k2g.set_kernel("two")
     k2g.set_graph(10)                # five launches per replay: the parity flips at each replay
     k2g.step(61)
-    for name, other in (("per-call", b), ("graph", g), ("fused8", k8), ("two", k2), ("two graph", k2g)):
+    k3 = lbm.from_case(c)
+    k3.set_kernel("three")           # twenty three-step launches and one fused step
+    k3.step(61)
+    k3g = lbm.from_case(c)
+    k3g.set_kernel("three")
+    k3g.set_graph(10)                # three three-step launches and one fused step per replay
+    k3g.step(61)
+    for name, other in (("per-call", b), ("graph", g), ("fused8", k8), ("two", k2), ("two graph", k2g),
+                        ("three", k3), ("three graph", k3g)):
         for x, y in zip(ref, other.moments()):
             np.testing.assert_array_equal(x, y, err_msg=name)
     rn = lbm.from_case(droplet(1, 0))
@@ -187,4 +195,5 @@ def test_other_kernels_rejected(lbm):
             s.set_kernel(k)
     s.set_kernel("fused8")
     s.set_kernel("two")
+    s.set_kernel("three")
     s.set_kernel("fused")

@@ -140,14 +140,15 @@ def test_trt_fused8_bitwise_equal(lbm):
             np.testing.assert_array_equal(x, y, err_msg=name)
 
 
+@pytest.mark.parametrize("kernel", ["two", "three"])
 @pytest.mark.parametrize("storage", [0, 1])
-def test_trt_two_step_bitwise_equal(lbm, storage):
+def test_trt_multi_step_bitwise_equal(lbm, storage, kernel):
     for name in ("droplet128x64", "ragged37x19", "ragged300x5", "ragged130x67"):
         c = trt_case(name)
         c.params = c.params.replace(storage=storage)
         a = lbm.from_case(c)
         b = lbm.from_case(c)
-        b.set_kernel("two")
+        b.set_kernel(kernel)
         b.set_tile(256, 0)
         a.step(41)
         b.step(41)

@@ -26,16 +26,20 @@ def ws():
 def test_unusable_prediction_falls_back_to_cold_start(ws):
     from paper_0708_4182_amd import inputs as I
     from paper_0708_4182_amd import net
-    cases = [I.warm_case(s, nx=NX, ny=NY) for s in (100, 101, 102)]
-    data = ws.steady_states(cases, max_steps=60_000)
-    sel = [0, 1, 2]
+    # the comparison needs cold runs that settle (the steady rule); some seeds of
+    # this small channel keep changing their flux by more than the rule allows,
+    # so the first three seeds of six that settle are used
+    cases = [I.warm_case(s, nx=NX, ny=NY) for s in range(100, 106)]
+    data = ws.steady_states(cases, max_steps=100_000)
+    settled = np.flatnonzero(data["cold"] > 0)
+    assert settled.size >= 3, f"only {settled.size} of 6 cold runs settle"
+    sel = settled[:3]
     m = net.Net(NY, NX, 4, chans=(8, 8, 8, 8))
     m.set_params(np.full(m.n_params, np.nan, np.float32))       # every prediction is NaN
     scales = ws.Scales(np.zeros(3), np.ones(3))
     stats, warm, _, _ = ws.warm_vs_cold(m, scales, [cases[i] for i in sel], data["Q"][sel],
-                                     data["cold"][sel], max_steps=60_000)
+                                     data["cold"][sel], max_steps=100_000)
     assert stats["used_prediction"] == 0
-    assert (data["cold"][sel] > 0).all()
     np.testing.assert_array_equal(warm, data["cold"][sel])
 
 
