@@ -56,7 +56,9 @@ typedef struct {
     int32_t H, W;      /* lattice rows and columns, multiples of 8           */
     int32_t batch;     /* largest n a call may pass, 1..512                  */
     int32_t cin, cout; /* input and output planes, 1..2048                   */
-    int32_t chans[4];  /* c1..c4, 1..2048 each                               */
+    int32_t chans[4];  /* c1..c4, 1..2048 each; the widest layer (including
+                          the concatenations c4 + c3, c3 + c2, c2 + c1) times
+                          H x W must be below 2^31                          */
     int32_t act_bf16;  /* 1: bf16 activations, 0: FP32 activations          */
 } lbm_net_config;
 

@@ -6,6 +6,7 @@
 // net_kernels.hip on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -63,6 +64,13 @@ bool make_plan(const lbm_net_config *cfg, Plan &P, std::string &why) {
         o += P.lcout[l];
     }
     P.nparams = o;
+    // the 3x3 convolutions index within one sample with 32-bit offsets
+    int widest = 0;
+    for (int l = 0; l < NLAYERS; ++l) widest = std::max(widest, std::max(P.lcin[l], P.lcout[l]));
+    if ((int64_t)widest * P.H * P.W >= ((int64_t)1 << 31)) {
+        why = "the widest layer of one sample must hold fewer than 2^31 values";
+        return false;
+    }
     return true;
 }
 

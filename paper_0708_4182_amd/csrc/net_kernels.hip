@@ -35,49 +35,62 @@ __global__ void __launch_bounds__(256) k_conv3x3(View in, const float *__restric
     const int n = blockIdx.y / ncob, co0 = (blockIdx.y % ncob) * CO_T;
     const int tid = threadIdx.x, px = tid % TW, py = tid / TW;
     const TI *__restrict__ xin = static_cast<const TI *>(in.p) + (size_t)n * in.bs;
+    // biases read up front (a load in the epilogue would make each store wait)
+    float bv[CO_T];
+#pragma unroll
+    for (int o = 0; o < CO_T; ++o) bv[o] = (bias != nullptr && co0 + o < cout) ? bias[co0 + o] : 0.f;
     float acc[CO_T];
 #pragma unroll
     for (int o = 0; o < CO_T; ++o) acc[o] = 0.f;
-    for (int ci0 = 0; ci0 < cin; ci0 += CI_T) {
-        for (int e = tid; e < CI_T * (TH + 2) * (TW + 2); e += 256) {
+    int ci0 = 0;
+    do {       // cin >= 1
+        // only the chunk's real channels are staged and summed (the first
+        // layer has 3 input planes); many workgroups per CU hide the load
+        // latency of this loop
+        const int cn = min(CI_T, cin - ci0);
+        for (int e = tid; e < cn * (TH + 2) * (TW + 2); e += 256) {
             const int c = e / ((TH + 2) * (TW + 2)), r = (e / (TW + 2)) % (TH + 2), q = e % (TW + 2);
             const int y = ty0 - 1 + r;
-            const int x = (tx0 - 1 + q + W) % W;   // periodic; W may be narrower than a tile
+            int x = tx0 - 1 + q;       // periodic
+            if (x < 0) x += W;
+            if (x >= W) x -= W;
+            if (x >= W) x %= W;        // lattices narrower than a tile
             float v = 0.f;
-            if (ci0 + c < cin && y >= 0 && y < H) v = tof(xin[(size_t)(ci0 + c) * H * W + (size_t)y * W + x]);
+            if (y >= 0 && y < H) v = tof(xin[(size_t)(ci0 + c) * H * W + (size_t)y * W + x]);
             xs[c][r][q] = v;
         }
-        for (int e = tid; e < CI_T * 9 * CO_T; e += 256) {
+        for (int e = tid; e < cn * 9 * CO_T; e += 256) {
             const int c = e / (9 * CO_T), t = (e / CO_T) % 9, o = e % CO_T;
             float v = 0.f;
-            if (ci0 + c < cin && co0 + o < cout) v = w[((size_t)(co0 + o) * cin + ci0 + c) * 9 + t];
+            if (co0 + o < cout) v = w[((size_t)(co0 + o) * cin + ci0 + c) * 9 + t];
             reinterpret_cast<float *>(&ws[c][t][0])[o] = v;
         }
         __syncthreads();
 #pragma unroll 2
-        for (int c = 0; c < CI_T; ++c) {
+        for (int c = 0; c < cn; ++c) {
 #pragma unroll
             for (int t = 0; t < 9; ++t) {
-                const float xv = xs[c][py + t / 3][px + t % 3];
+                const float xc = xs[c][py + t / 3][px + t % 3];
 #pragma unroll
                 for (int o4 = 0; o4 < CO_T / 4; ++o4) {
-                    const float4 wv = ws[c][t][o4];
-                    acc[4 * o4 + 0] += wv.x * xv;
-                    acc[4 * o4 + 1] += wv.y * xv;
-                    acc[4 * o4 + 2] += wv.z * xv;
-                    acc[4 * o4 + 3] += wv.w * xv;
+                    const float4 wq = ws[c][t][o4];
+                    acc[4 * o4 + 0] += wq.x * xc;
+                    acc[4 * o4 + 1] += wq.y * xc;
+                    acc[4 * o4 + 2] += wq.z * xc;
+                    acc[4 * o4 + 3] += wq.w * xc;
                 }
             }
         }
         __syncthreads();
-    }
+        ci0 += CI_T;
+    } while (ci0 < cin);
     const int y = ty0 + py, x = tx0 + px;
     if (y >= H || x >= W) return;
     TO *__restrict__ yo = static_cast<TO *>(out.p) + (size_t)n * out.bs;
 #pragma unroll
     for (int o = 0; o < CO_T; ++o) {
         if (co0 + o >= cout) break;
-        float v = acc[o] + (bias ? bias[co0 + o] : 0.f);
+        float v = acc[o] + bv[o];
         if (relu) v = fmaxf(v, 0.f);
         yo[(size_t)(co0 + o) * H * W + (size_t)y * W + x] = fromf<TO>(v);
     }
@@ -284,23 +297,51 @@ __global__ void k_conv1x1(View in, const float *__restrict__ w, const float *__r
     if (i >= (size_t)N * HW) return;
     const size_t n = i / HW, p = i % HW;
     const TA *s = static_cast<const TA *>(in.p) + n * in.bs + p;
-    for (int o = 0; o < cout; ++o) {
-        float acc = b[o];
-        for (int c = 0; c < cin; ++c) acc += w[o * cin + c] * tof(s[(size_t)c * HW]);
-        out[(n * cout + o) * HW + p] = acc;
+    // four outputs per pass over the input planes (the layer has 3), the
+    // sums in channel order as before
+    for (int o0 = 0; o0 < cout; o0 += 4) {
+        float acc[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = o0 + j < cout ? b[o0 + j] : 0.f;
+#pragma unroll 8
+        for (int c = 0; c < cin; ++c) {
+            const float xc = tof(s[(size_t)c * HW]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (o0 + j < cout) acc[j] += w[(o0 + j) * cin + c] * xc;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (o0 + j < cout) out[(n * cout + o0 + j) * HW + p] = acc[j];
     }
 }
 
-// gradient of 1x1 input: dx[c] = sum_o w[o][c] g[o]
+// gradient of 1x1 input: dx[c] = sum_o w[o][c] g[o]; layers with at most 4
+// outputs keep their gradients in registers across the channels
 __global__ void k_conv1x1_dx(const float *__restrict__ g, const float *__restrict__ w, int N, int cin, int cout,
                              int HW, View dx) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (size_t)N * HW) return;
     const size_t n = i / HW, p = i % HW;
+    float *__restrict__ d = static_cast<float *>(dx.p) + n * dx.bs + p;
+    if (cout <= 4) {
+        float gv[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) gv[o] = o < cout ? g[(n * cout + o) * HW + p] : 0.f;
+#pragma unroll 4
+        for (int c = 0; c < cin; ++c) {
+            float acc = 0.f;
+#pragma unroll
+            for (int o = 0; o < 4; ++o)
+                if (o < cout) acc += w[o * cin + c] * gv[o];
+            d[(size_t)c * HW] = acc;
+        }
+        return;
+    }
     for (int c = 0; c < cin; ++c) {
         float acc = 0.f;
         for (int o = 0; o < cout; ++o) acc += w[o * cin + c] * g[(n * cout + o) * HW + p];
-        static_cast<float *>(dx.p)[n * dx.bs + (size_t)c * HW + p] = acc;
+        d[(size_t)c * HW] = acc;
     }
 }
 
@@ -435,7 +476,7 @@ __global__ void k_zero(float *__restrict__ p, size_t n) {
 // k_pack_weights) likewise.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int MH = 8, MW = 32, MCO = 64, MCI = 32, MPS = 40;
+constexpr int MH = 8, MCI = 32, MPS = 40;
 
 // Wp[t][co][ci] (bf16, ci padded with zeros to cin_pad) from W[co][ci][t] (FP32)
 __global__ void k_pack_weights(const float *__restrict__ w, __bf16 *__restrict__ wp, int cin, int cout, int cin_pad) {
@@ -455,81 +496,253 @@ __global__ void k_pack_weights_flip(const float *__restrict__ w, __bf16 *__restr
     wp[i] = (__bf16)(co < cout ? w[((size_t)co * cin + ci) * 9 + (8 - t)] : 0.f);
 }
 
-// TI: input type (bf16 activations, or the FP32 layer gradient, rounded to
-// bf16 as it is staged); TO: output type; bias may be NULL.  NM: 16-channel
-// output tiles per workgroup (4: 64 channels; 2: 32 channels, for the coarse
-// layers with at most 32 output channels).
-template <class TI, class TO, int NM>
-__global__ void __launch_bounds__(256) k_conv3x3_mfma(View in, const __bf16 *__restrict__ wp,
-                                                      const float *__restrict__ bias, View out, int cin,
-                                                      int cout, int cin_pad, int relu) {
-    constexpr int CO = 16 * NM;
-    __shared__ __attribute__((aligned(16))) __bf16 xs[(MH + 2) * (MW + 2) * MPS];
-    __shared__ __attribute__((aligned(16))) __bf16 ws[9 * CO * MPS];
+// Tile of k_conv3x3_mfma: MH rows x TWD columns of one sample, computed by
+// TWD / 4 waves (NT threads); each wave owns four 16-pixel N tiles (two rows
+// of 32 columns, or one row of 64).
+template <int TWD>
+struct ConvTile {
+    static_assert(TWD == 32 || TWD == 64, "tile width 32 or 64");
+    static constexpr int TW = TWD, NT = 8 * TWD, QR = TWD / 16, RPW = 4 / QR;
+};
+
+// Staging of one 32-channel chunk of the input tile (rows ty0 - 1 .. ty0 + MH,
+// columns tx0 - 1 .. tx0 + TW, periodic in x, zero outside the rows and
+// channels) and of its packed weights, in two halves: load() issues the
+// global loads into registers, store() writes them to LDS (channel-last,
+// MPS bf16 per pixel).  The loads of chunk k + 1 are issued before the
+// products of chunk k, so they are in flight while the matrix cores work.
+//
+// VEC (rows of whole 8-pixel groups: W % 8 == 0, 16-byte aligned planes): a
+// task is 8 channels x 8 pixels of one row, eight 16-byte loads (one per
+// channel plane) transposed in registers into eight 16-byte LDS stores (one
+// per pixel); the halo columns tx0 - 1 and tx0 + TW are tasks of 8 channels
+// x 1 pixel; at most one task per thread.  Otherwise each thread gathers 8
+// channels of a pixel with 2-byte loads, XT pixels per thread.
+template <int NM, bool VEC, int TWD>
+struct ConvStage {
+    using T = ConvTile<TWD>;
+    static constexpr int TW = T::TW, NT = T::NT, CO = 16 * NM;
+    static constexpr int XTASKS = (MCI / 8) * (MH + 2) * (TW + 2), XT = (XTASKS + NT - 1) / NT;
+    static constexpr int WTASKS = 9 * CO * (MCI / 8), WT = (WTASKS + NT - 1) / NT;
+    static constexpr int VIN = (MCI / 8) * (MH + 2) * (TW / 8);   // 8 x 8 tasks
+    static constexpr int VHALO = (MCI / 8) * (MH + 2) * 2;        // 8 x 1 tasks
+    static_assert(!VEC || VIN + VHALO <= NT, "one vector staging task per thread");
+    uint4 v[VEC ? 8 : 1];              // VEC: 8 channel planes x 8 pixels
+    uint32_t hv[VEC ? 8 : 1];          // VEC: 8 channels of a halo pixel
+    bf16x8 xv[VEC ? 1 : XT];
+    uint4 wv[WT];
+    uint32_t vmask = 0u, xmask[VEC ? 1 : XT] = {}, wmask = 0u;   // loaded values that are real
+
+    __device__ __forceinline__ static int wrap(int x, int W) {
+        if (x < 0) x += W;
+        if (x >= W) x -= W;
+        if (x >= W) x %= W;                  // lattices narrower than a tile
+        return x;
+    }
+
+    __device__ __forceinline__ void load(const __bf16 *__restrict__ xin, const __bf16 *__restrict__ wp, int H,
+                                         int W, int tx0, int ty0, int ci0, int cin, int cout, int co0, int cin_pad,
+                                         int tid) {
+        // 32-bit offsets within the sample (its planes hold fewer than 2^31
+        // values, checked when the network is made).  Every load is issued
+        // (a value that is not needed comes from a clamped row and channel
+        // and is replaced by zero in store(), when it has arrived): loads
+        // under a condition, or values cleared right after their load, make
+        // the compiler split the loads up or wait for each one; clamping
+        // rather than one fixed address keeps those loads from all landing
+        // on one cache line.
+        const uint32_t HW = (uint32_t)(H * W);
+        if constexpr (VEC) {
+            if (tid < VIN) {
+                const int g = tid % (TW / 8), r = (tid / (TW / 8)) % (MH + 2), c8 = tid / ((TW / 8) * (MH + 2));
+                const int y = ty0 - 1 + r;
+                const int x = wrap(tx0 + 8 * g, W);
+                const bool oky = y >= 0 && y < H;
+                const uint32_t pix = (uint32_t)(min(max(y, 0), H - 1) * W + x);
+                vmask = 0u;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int c = ci0 + 8 * c8 + j;
+                    const bool ok = oky && c < cin;
+                    v[j] = *reinterpret_cast<const uint4 *>(xin + (uint32_t)min(c, cin - 1) * HW + pix);
+                    vmask |= (ok ? 1u : 0u) << j;
+                }
+            } else if (tid < VIN + VHALO) {
+                const int h = tid - VIN;
+                const int side = h % 2, r = (h / 2) % (MH + 2), c8 = h / (2 * (MH + 2));
+                const int y = ty0 - 1 + r;
+                const int x = wrap(side ? tx0 + TW : tx0 - 1, W);
+                const bool oky = y >= 0 && y < H;
+                const uint32_t pix = (uint32_t)(min(max(y, 0), H - 1) * W + x);
+                const unsigned short *__restrict__ xs16 = reinterpret_cast<const unsigned short *>(xin);
+                vmask = 0u;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int c = ci0 + 8 * c8 + j;
+                    const bool ok = oky && c < cin;
+                    hv[j] = xs16[(uint32_t)min(c, cin - 1) * HW + pix];
+                    vmask |= (ok ? 1u : 0u) << j;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < XT; ++k) {
+                const int e = tid + NT * k;
+                const int q = e % (TW + 2), r = (e / (TW + 2)) % (MH + 2), c8 = e / ((TW + 2) * (MH + 2));
+                const int y = ty0 - 1 + r;
+                const int x = wrap(tx0 - 1 + q, W);
+                const bool oky = e < XTASKS && y >= 0 && y < H;
+                const uint32_t pix = (uint32_t)(min(max(y, 0), H - 1) * W + x);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int c = ci0 + 8 * c8 + j;
+                    const bool ok = oky && c < cin;
+                    xv[k][j] = xin[(uint32_t)min(c, cin - 1) * HW + pix];
+                    xmask[k] = (xmask[k] & ~(1u << j)) | (ok ? 1u : 0u) << j;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < WT; ++k) {
+            const int e = tid + NT * k;
+            const int c8 = e % (MCI / 8), co = (e / (MCI / 8)) % CO, t = e / ((MCI / 8) * CO);
+            const bool ok = e < WTASKS && co0 + co < cout;
+            wv[k] = *reinterpret_cast<const uint4 *>(wp + ((size_t)min(t, 8) * cout + min(co0 + co, cout - 1)) * cin_pad + ci0 + 8 * c8);
+            wmask = (wmask & ~(1u << k)) | (ok ? 1u : 0u) << k;
+        }
+    }
+
+    __device__ __forceinline__ void store(__bf16 *xs, __bf16 *ws, int tid) const {
+        if constexpr (VEC) {
+            if (tid < VIN) {
+                const int g = tid % (TW / 8), r = (tid / (TW / 8)) % (MH + 2), c8 = tid / ((TW / 8) * (MH + 2));
+                uint4 w[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) w[j] = (vmask >> j & 1u) ? v[j] : make_uint4(0u, 0u, 0u, 0u);
+                // w[j] holds pixels 2d, 2d + 1 of channel j in dword d; pixel p's
+                // eight channels go out as one 16-byte word (channel 2m in the
+                // low half of dword m)
+                const uint32_t *u = reinterpret_cast<const uint32_t *>(w);
+#pragma unroll
+                for (int p = 0; p < 8; ++p) {
+                    const uint32_t sel = (p & 1) ? 0x07060302u : 0x05040100u;
+                    const int d = p >> 1;
+                    uint4 o;
+                    o.x = __builtin_amdgcn_perm(u[4 * 1 + d], u[4 * 0 + d], sel);
+                    o.y = __builtin_amdgcn_perm(u[4 * 3 + d], u[4 * 2 + d], sel);
+                    o.z = __builtin_amdgcn_perm(u[4 * 5 + d], u[4 * 4 + d], sel);
+                    o.w = __builtin_amdgcn_perm(u[4 * 7 + d], u[4 * 6 + d], sel);
+                    *reinterpret_cast<uint4 *>(&xs[(r * (TW + 2) + 1 + 8 * g + p) * MPS + 8 * c8]) = o;
+                }
+            } else if (tid < VIN + VHALO) {
+                const int h = tid - VIN;
+                const int side = h % 2, r = (h / 2) % (MH + 2), c8 = h / (2 * (MH + 2));
+                const int q = side ? TW + 1 : 0;
+                uint32_t hz[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) hz[j] = (vmask >> j & 1u) ? hv[j] & 0xffffu : 0u;
+                *reinterpret_cast<uint4 *>(&xs[(r * (TW + 2) + q) * MPS + 8 * c8]) =
+                    make_uint4(hz[0] | hz[1] << 16, hz[2] | hz[3] << 16, hz[4] | hz[5] << 16, hz[6] | hz[7] << 16);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < XT; ++k) {
+                const int e = tid + NT * k;
+                if (e < XTASKS) {
+                    const int q = e % (TW + 2), r = (e / (TW + 2)) % (MH + 2), c8 = e / ((TW + 2) * (MH + 2));
+                    bf16x8 o = xv[k];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        if (!(xmask[k] >> j & 1u)) o[j] = (__bf16)0.f;
+                    *reinterpret_cast<bf16x8 *>(&xs[(r * (TW + 2) + q) * MPS + 8 * c8]) = o;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < WT; ++k) {
+            const int e = tid + NT * k;
+            if (e < WTASKS) {
+                const int c8 = e % (MCI / 8), co = (e / (MCI / 8)) % CO, t = e / ((MCI / 8) * CO);
+                *reinterpret_cast<uint4 *>(&ws[(t * CO + co) * MPS + 8 * c8]) =
+                    (wmask >> k & 1u) ? wv[k] : make_uint4(0u, 0u, 0u, 0u);
+            }
+        }
+    }
+};
+
+// LDS of the convolution: the staged input tile and weights, reused after the
+// channel loop for the output tile (CO rows of OS values) on its way to
+// 16-byte stores.
+template <class TO, int NM, int TWD>
+struct ConvLds {
+    static constexpr int CO = 16 * NM, TW = TWD;
+    static constexpr int XS = (MH + 2) * (TW + 2) * MPS, WS = 9 * CO * MPS;   // bf16
+    static constexpr int OS = MH * TW + 16 / (int)sizeof(TO);                 // output row stride
+    static constexpr int IN_BYTES = 2 * (XS + WS), OUT_BYTES = CO * OS * (int)sizeof(TO);
+    static constexpr int BYTES = IN_BYTES > OUT_BYTES ? IN_BYTES : OUT_BYTES;
+};
+
+// Input: bf16 activations (or the bf16 copy of the layer gradient); TO:
+// output type; bias may be NULL.  NM: 16-channel output tiles per workgroup
+// (4: 64 channels; 2: 32 channels).  VEC: see ConvStage; it also sends the
+// output tile through LDS so that each lane stores 16 contiguous bytes of one
+// plane.  TWD: tile width (32, or 64 with 512 threads, which halves the
+// staged weight bytes per output).
+//
+// Workgroups are dispatched round-robin over the 8 XCDs; block b is given
+// tile b' = (b mod 8) * (nb / 8) + b / 8 so that each XCD computes a
+// contiguous run of tiles, and the halo rows and the cache lines that
+// neighbouring tiles share, and the weights, stay in its L2.
+template <class TO, int NM, bool VEC, int TWD>
+__global__ void __launch_bounds__(ConvTile<TWD>::NT) k_conv3x3_mfma(View in, const __bf16 *__restrict__ wp,
+                                                                     const float *__restrict__ bias, View out,
+                                                                     int cin, int cout, int cin_pad, int relu) {
+    using L = ConvLds<TO, NM, TWD>;
+    using T = ConvTile<TWD>;
+    constexpr int CO = L::CO, TW = T::TW, NT = T::NT;
+    __shared__ __attribute__((aligned(16))) char lds[L::BYTES];
+    __bf16 *xs = reinterpret_cast<__bf16 *>(lds);
+    __bf16 *ws = xs + L::XS;
     const int H = in.H, W = in.W;
-    const int tiles_x = (W + MW - 1) / MW;
-    const int tx0 = (blockIdx.x % tiles_x) * MW, ty0 = (blockIdx.x / tiles_x) * MH;
+    int bxy;
+    {
+        const int nb = gridDim.x * gridDim.y, b = blockIdx.x + gridDim.x * blockIdx.y;
+        const int full = nb / 8 * 8;
+        bxy = b < full ? (b % 8) * (full / 8) + b / 8 : b;
+    }
+    const int bx = bxy % gridDim.x, by = bxy / gridDim.x;
+    const int tiles_x = (W + TW - 1) / TW;
+    const int tx0 = (bx % tiles_x) * TW, ty0 = (bx / tiles_x) * MH;
     const int ncob = (cout + CO - 1) / CO;
-    const int n = blockIdx.y / ncob, co0 = (blockIdx.y % ncob) * CO;
+    const int n = by / ncob, co0 = (by % ncob) * CO;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = (lane >> 4) * 8;
-    const TI *__restrict__ xin = static_cast<const TI *>(in.p) + (size_t)n * in.bs;
+    const __bf16 *__restrict__ xin = static_cast<const __bf16 *>(in.p) + (size_t)n * in.bs;
+    // The lane's biases, read before the channel loop: loaded in the epilogue
+    // they would put a wait for memory (which on this architecture also waits
+    // for every store before it) in front of each of the output stores.
+    float bv[NM][4];
+#pragma unroll
+    for (int m = 0; m < NM; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int co = co0 + 16 * m + (lane >> 4) * 4 + r;
+            bv[m][r] = (bias != nullptr && co < cout) ? bias[co] : 0.f;
+        }
     f32x4 acc[NM][4];
 #pragma unroll
     for (int m = 0; m < NM; ++m)
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[m][q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // Staging tasks of a thread: XT (pixel, 8 channels) gathers of the input
-    // tile and WT 16-byte loads of the packed weights.  All of a thread's
-    // global loads are issued before any of them is stored to LDS, so the
-    // chunk waits for memory once instead of once per task.
-    constexpr int XTASKS = (MCI / 8) * (MH + 2) * (MW + 2), XT = (XTASKS + 255) / 256;
-    constexpr int WTASKS = 9 * CO * (MCI / 8), WT = (WTASKS + 255) / 256;
-    for (int ci0 = 0; ci0 < cin; ci0 += MCI) {
-        bf16x8 xv[XT];
-        uint4 wv[WT];
-#pragma unroll
-        for (int k = 0; k < XT; ++k) {
-            const int e = tid + 256 * k;
-            const int q = e % (MW + 2), r = (e / (MW + 2)) % (MH + 2), c8 = e / ((MW + 2) * (MH + 2));
-            const int y = ty0 - 1 + r;
-            int x = tx0 - 1 + q;      // periodic in x
-            if (x < 0) x += W;
-            if (x >= W) x -= W;
-            if (x >= W) x %= W;       // lattices narrower than a tile
-            const bool ok = e < XTASKS && y >= 0 && y < H;
-            const TI *src = xin + (size_t)(ok ? y : 0) * W + x;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int c = ci0 + 8 * c8 + j;
-                xv[k][j] = (ok && c < cin) ? (__bf16)src[(size_t)c * H * W] : (__bf16)0.f;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < WT; ++k) {
-            const int e = tid + 256 * k;
-            const int c8 = e % (MCI / 8), co = (e / (MCI / 8)) % CO, t = e / ((MCI / 8) * CO);
-            wv[k] = make_uint4(0u, 0u, 0u, 0u);
-            if (e < WTASKS && co0 + co < cout)
-                wv[k] = *reinterpret_cast<const uint4 *>(wp + ((size_t)t * cout + co0 + co) * cin_pad + ci0 + 8 * c8);
-        }
-#pragma unroll
-        for (int k = 0; k < XT; ++k) {
-            const int e = tid + 256 * k;
-            if (e < XTASKS) {
-                const int q = e % (MW + 2), r = (e / (MW + 2)) % (MH + 2), c8 = e / ((MW + 2) * (MH + 2));
-                *reinterpret_cast<bf16x8 *>(&xs[(r * (MW + 2) + q) * MPS + 8 * c8]) = xv[k];
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < WT; ++k) {
-            const int e = tid + 256 * k;
-            if (e < WTASKS) {
-                const int c8 = e % (MCI / 8), co = (e / (MCI / 8)) % CO, t = e / ((MCI / 8) * CO);
-                *reinterpret_cast<uint4 *>(&ws[(t * CO + co) * MPS + 8 * c8]) = wv[k];
-            }
-        }
+    ConvStage<NM, VEC, TWD> st;
+    st.load(xin, wp, H, W, tx0, ty0, 0, cin, cout, co0, cin_pad, tid);
+    // (cin >= 1: a loop that always runs once lets its wait for the staged
+    // loads cover the bias loads too, so the epilogue's stores need no waits.)
+    int ci0 = 0;
+    do {
+        st.store(xs, ws, tid);
         __syncthreads();
+        if (ci0 + MCI < cin) st.load(xin, wp, H, W, tx0, ty0, ci0 + MCI, cin, cout, co0, cin_pad, tid);
 #pragma unroll 1
         for (int t = 0; t < 9; ++t) {
             const int dy = t / 3, dx = t % 3;
@@ -539,30 +752,61 @@ __global__ void __launch_bounds__(256) k_conv3x3_mfma(View in, const __bf16 *__r
                 a[m] = *reinterpret_cast<const bf16x8 *>(&ws[(t * CO + 16 * m + lr) * MPS + lk]);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int pr = 2 * wave + (q >> 1), pc = (q & 1) * 16 + lr;
-                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&xs[((pr + dy) * (MW + 2) + pc + dx) * MPS + lk]);
+                const int pr = T::RPW * wave + q / T::QR, pc = (q % T::QR) * 16 + lr;
+                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&xs[((pr + dy) * (TW + 2) + pc + dx) * MPS + lk]);
 #pragma unroll
                 for (int m = 0; m < NM; ++m) acc[m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b, acc[m][q], 0, 0, 0);
             }
         }
         __syncthreads();
-    }
+        ci0 += MCI;
+    } while (ci0 < cin);
     TO *__restrict__ yo = static_cast<TO *>(out.p) + (size_t)n * out.bs;
+    if constexpr (VEC) {
+        // D[4 (l / 16) + r][l % 16] of tile (m, q) -> LDS row co, then each
+        // lane stores 16 bytes of one output row of one plane
+        TO *os = reinterpret_cast<TO *>(lds);
 #pragma unroll
-    for (int m = 0; m < NM; ++m)
+        for (int m = 0; m < NM; ++m)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int y = ty0 + 2 * wave + (q >> 1), x = tx0 + (q & 1) * 16 + lr;
-            if (y >= H || x >= W) continue;
+            for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int co = co0 + 16 * m + (lane >> 4) * 4 + r;
-                if (co >= cout) continue;
-                float v = acc[m][q][r] + (bias ? bias[co] : 0.f);
-                if (relu) v = fmaxf(v, 0.f);
-                yo[(size_t)co * H * W + (size_t)y * W + x] = fromf<TO>(v);
-            }
+                for (int r = 0; r < 4; ++r) {
+                    const int col = 16 * m + (lane >> 4) * 4 + r;
+                    const int pix = (T::RPW * wave + q / T::QR) * TW + (q % T::QR) * 16 + lr;
+                    float v = acc[m][q][r] + bv[m][r];
+                    if (relu) v = fmaxf(v, 0.f);
+                    os[col * L::OS + pix] = fromf<TO>(v);
+                }
+        __syncthreads();
+        constexpr int EPP = 16 / (int)sizeof(TO), PPR = TW / EPP, PIECES = CO * MH * PPR;
+        const uint32_t HW = (uint32_t)(H * W);
+#pragma unroll
+        for (int k = 0; k < (PIECES + NT - 1) / NT; ++k) {
+            const int e = tid + NT * k;
+            const int kk = e % PPR, row = (e / PPR) % MH, col = e / (PPR * MH);
+            const int y = ty0 + row, x = tx0 + kk * EPP, co = co0 + col;
+            if (e < PIECES && co < cout && y < H && x < W)
+                *reinterpret_cast<uint4 *>(yo + (uint32_t)co * HW + (uint32_t)(y * W + x)) =
+                    *reinterpret_cast<const uint4 *>(&os[col * L::OS + row * TW + kk * EPP]);
         }
+    } else {
+#pragma unroll
+        for (int m = 0; m < NM; ++m)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int y = ty0 + T::RPW * wave + q / T::QR, x = tx0 + (q % T::QR) * 16 + lr;
+                if (y >= H || x >= W) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int co = co0 + 16 * m + (lane >> 4) * 4 + r;
+                    if (co >= cout) continue;
+                    float v = acc[m][q][r] + bv[m][r];
+                    if (relu) v = fmaxf(v, 0.f);
+                    yo[(size_t)co * H * W + (size_t)y * W + x] = fromf<TO>(v);
+                }
+            }
+    }
 }
 
 // Weight gradient on matrix cores (bf16 build, 3x3 layers after the first):
@@ -791,9 +1035,48 @@ template hipError_t conv3x3<__bf16, __bf16>(const View &, const float *, const f
 int pad32(int c) { return (c + MCI - 1) / MCI * MCI; }
 
 // 32-channel output tiles for 32 or fewer output channels (a 64-channel tile
-// would spend half its products on padding); 64 otherwise.  (Also choosing 32
-// where 64-channel tiles give fewer than 1024 workgroups measured the same.)
+// would spend half its products on padding).
 bool mfma_narrow(int cout) { return cout <= 32; }
+
+// Whole 8-pixel groups and 16-byte aligned planes in and out: the vector
+// staging and the 16-byte output stores of k_conv3x3_mfma.
+template <class TO>
+bool mfma_vec_ok(const View &in, const View &out) {
+    const int epp = 16 / (int)sizeof(TO);
+    return in.W % 8 == 0 && (uintptr_t)in.p % 16 == 0 && in.bs % 8 == 0 && (uintptr_t)out.p % 16 == 0 &&
+           out.bs % epp == 0;
+}
+
+// Shape of a convolution launch: 64-column tiles (512 threads) where the
+// rows are whole 64-column tiles and that still gives at least 256
+// workgroups, else 32; 32-channel output tiles for at most 32 output
+// channels or where 64-channel tiles would leave more than half of the 256
+// CUs idle.
+template <class TO, int NM, int TWD>
+hipError_t launch_conv3x3_mfma_t(const View &in, const __bf16 *wp, const float *bias, const View &out, int N,
+                                 int cin, int cout, int cin_pad, bool relu, bool vec, hipStream_t s) {
+    const int tiles = ((in.W + TWD - 1) / TWD) * ((in.H + MH - 1) / MH);
+    const dim3 grid(tiles, N * ((cout + 16 * NM - 1) / (16 * NM)));
+    const int r = relu ? 1 : 0, nt = ConvTile<TWD>::NT;
+    if (vec) k_conv3x3_mfma<TO, NM, true, TWD><<<grid, nt, 0, s>>>(in, wp, bias, out, cin, cout, cin_pad, r);
+    else k_conv3x3_mfma<TO, NM, false, TWD><<<grid, nt, 0, s>>>(in, wp, bias, out, cin, cout, cin_pad, r);
+    return hipGetLastError();
+}
+
+template <class TO>
+hipError_t launch_conv3x3_mfma(const View &in, const __bf16 *wp, const float *bias, const View &out, int N,
+                               int cin, int cout, int cin_pad, bool relu, hipStream_t s) {
+    const bool vec = mfma_vec_ok<TO>(in, out);
+    const long long rows = (in.H + MH - 1) / MH;
+    const bool narrow = mfma_narrow(cout) || rows * ((in.W + 31) / 32) * N * ((cout + 63) / 64) < 128;
+    const long long wide_wgs = rows * (in.W / 64) * N * (narrow ? (cout + 31) / 32 : (cout + 63) / 64);
+    const bool wide = vec && in.W % 64 == 0 && wide_wgs >= 256;
+    if (narrow)
+        return wide ? launch_conv3x3_mfma_t<TO, 2, 64>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, s)
+                    : launch_conv3x3_mfma_t<TO, 2, 32>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, s);
+    return wide ? launch_conv3x3_mfma_t<TO, 4, 64>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, s)
+                : launch_conv3x3_mfma_t<TO, 4, 32>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, s);
+}
 
 hipError_t conv3x3_mfma(const View &in, const float *w, const float *bias, const View &out, int N, int cin,
                         int cout, bool relu, __bf16 *wp, hipStream_t s) {
@@ -801,15 +1084,7 @@ hipError_t conv3x3_mfma(const View &in, const float *w, const float *bias, const
     k_pack_weights<<<nblk((size_t)9 * cout * cin_pad), 256, 0, s>>>(w, wp, cin, cout, cin_pad);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int tiles = ((in.W + MW - 1) / MW) * ((in.H + MH - 1) / MH);
-    if (mfma_narrow(cout)) {
-        const dim3 grid(tiles, N * ((cout + 31) / 32));
-        k_conv3x3_mfma<__bf16, __bf16, 2><<<grid, 256, 0, s>>>(in, wp, bias, out, cin, cout, cin_pad, relu ? 1 : 0);
-    } else {
-        const dim3 grid(tiles, N * ((cout + MCO - 1) / MCO));
-        k_conv3x3_mfma<__bf16, __bf16, 4><<<grid, 256, 0, s>>>(in, wp, bias, out, cin, cout, cin_pad, relu ? 1 : 0);
-    }
-    return hipGetLastError();
+    return launch_conv3x3_mfma<__bf16>(in, wp, bias, out, N, cin, cout, cin_pad, relu, s);
 }
 
 // Input gradient dX = conv(dz, flipped transposed W) on matrix cores: dz (the
@@ -821,15 +1096,7 @@ hipError_t conv3x3_mfma_dx(const View &dz, const float *w, const View &dx, int N
     k_pack_weights_flip<<<nblk((size_t)9 * cin * cout_pad), 256, 0, s>>>(w, wp, cin, cout, cout_pad);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int tiles = ((dz.W + MW - 1) / MW) * ((dz.H + MH - 1) / MH);
-    if (mfma_narrow(cin)) {
-        const dim3 grid(tiles, N * ((cin + 31) / 32));
-        k_conv3x3_mfma<__bf16, float, 2><<<grid, 256, 0, s>>>(dz, wp, nullptr, dx, cout, cin, cout_pad, 0);
-    } else {
-        const dim3 grid(tiles, N * ((cin + MCO - 1) / MCO));
-        k_conv3x3_mfma<__bf16, float, 4><<<grid, 256, 0, s>>>(dz, wp, nullptr, dx, cout, cin, cout_pad, 0);
-    }
-    return hipGetLastError();
+    return launch_conv3x3_mfma<float>(dz, wp, nullptr, dx, N, cout, cin, cout_pad, false, s);
 }
 
 hipError_t flip_transpose(const float *w, float *wt, int cin, int cout, hipStream_t s) {

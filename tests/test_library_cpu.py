@@ -195,12 +195,15 @@ def test_net_param_count_matches_the_network_definition(lib):
         n = net.param_count(H=64, W=256, batch=4, chans=chans)
         assert n == CNN.param_count(CNN.layer_specs(3, 3, chans))
     assert net.param_count(H=64, W=256, batch=4) == 1209411
+    assert net.param_count(H=2048, W=2048, batch=1) == 1209411     # 2^30 values in the widest layer
 
 
 @pytest.mark.parametrize("bad", [dict(H=12), dict(W=4), dict(batch=0), dict(cin=0),
                                  dict(chans=(32, 0, 8, 8)), dict(batch=513), dict(chans=(32, 64, 128, 4096)),
-                                 dict(cout=3000)])
+                                 dict(cout=3000), dict(H=4096, W=2048)])
 def test_net_rejects_invalid_configs_without_gpu_work(lib, bad):
+    """(H=4096, W=2048: the concatenation c4 + c3 = 256 planes of one sample
+    would hold 2^31 values, beyond the convolutions' 32-bit offsets.)"""
     from paper_0708_4182_amd import net
     cfg = dict(H=64, W=256, batch=2)
     cfg.update(bad)
