@@ -82,7 +82,9 @@ struct Buffers {
     float *g_e1a, *g_cat1, *g_p1, *g_e2a, *g_cat2, *g_p2, *g_e3a, *g_cat3, *g_p3, *g_ba, *g_bb, *g_d3a, *g_d3b,
         *g_d2a, *g_d2b, *g_d1a, *g_d1b, *g_out, *y, *dz, *wt, *partial;
     float *theta, *grad, *m, *v;
-    __bf16 *wp;                      // packed bf16 weights of the matrix-core convolution
+    __bf16 *wp;                      // packed bf16 weights of the matrix-core input gradient
+    __bf16 *wpf;                     // packed bf16 weights of every matrix-core forward layer
+    size_t wpoff[NLAYERS];           // (layer l at wpf + wpoff[l])
     __bf16 *dzh;                     // the layer gradient rounded to bf16 (bf16 build, input gradient)
     double *loss_part, *loss_stats;
     size_t total, partial_floats;
@@ -135,6 +137,12 @@ bool layout(const Plan &P, char *base, Buffers &b) {
             wpmax = std::max(wpmax, (size_t)9 * P.lcin[l] * lbmnet::pad32(P.lcout[l]));   // input gradient
         }
     b.wp = (__bf16 *)take(2 * wpmax);
+    size_t wpf = 0;
+    for (int l = 0; l < NLAYERS; ++l) {
+        b.wpoff[l] = wpf;
+        if (l > 0 && P.lk[l] == 3) wpf += (size_t)9 * P.lcout[l] * lbmnet::pad32(P.lcin[l]);
+    }
+    b.wpf = (__bf16 *)take(2 * wpf);
     b.dz = (float *)take(4 * dzmax);
     b.dzh = (__bf16 *)take(2 * dzmax);
     b.wt = (float *)take(4 * wtmax);
@@ -159,6 +167,7 @@ struct lbm_net {
     int device = 0;
     int64_t adam_t = 0;
     bool have_grad = false;
+    bool packed = false;             // b.wpf holds the current parameters
     std::string err;
 };
 
@@ -288,7 +297,8 @@ hipError_t conv_fwd(lbm_net *n, int l, const View &X, const View &Y, int N, bool
     const float *w = n->b.theta + P.woff[l], *bias = n->b.theta + P.boff[l];
     if (first) return lbmnet::conv3x3<float, TA>(X, w, bias, Y, N, P.lcin[l], P.lcout[l], true, n->s);
     if constexpr (sizeof(TA) == 2)
-        return lbmnet::conv3x3_mfma(X, w, bias, Y, N, P.lcin[l], P.lcout[l], true, n->b.wp, n->s);
+        return lbmnet::conv3x3_mfma_packed(X, n->b.wpf + n->b.wpoff[l], bias, Y, N, P.lcin[l], P.lcout[l], true,
+                                           n->s);
     else return lbmnet::conv3x3<TA, TA>(X, w, bias, Y, N, P.lcin[l], P.lcout[l], true, n->s);
 }
 
@@ -299,6 +309,13 @@ lbm_status forward_t(lbm_net *n, const float *x, float *y, int N) {
     LayerIO io[NLAYERS];
     layer_io(t, io);
     hipStream_t s = n->s;
+    if (sizeof(TA) == 2 && !n->packed) {     // pack once per parameter update
+        for (int l = 1; l < NLAYERS; ++l)
+            if (P.lk[l] == 3)
+                NHIP(n, lbmnet::pack_weights(n->b.theta + P.woff[l], n->b.wpf + n->b.wpoff[l], P.lcin[l], P.lcout[l],
+                                             s));
+        n->packed = true;
+    }
     NHIP(n, (conv_fwd<TA>(n, E1A, io[E1A].X, io[E1A].Y, N, true)));
     NHIP(n, (conv_fwd<TA>(n, E1B, io[E1B].X, io[E1B].Y, N, false)));
     NHIP(n, lbmnet::pool<TA>(t.e1, t.p1, N, P.c[0], s));
@@ -456,6 +473,7 @@ lbm_status lbm_net_create(lbm_net **out, const lbm_net_config *cfg, void *ws, si
 lbm_status lbm_net_set_params(lbm_net *n, const float *host, int64_t count) {
     if (!n || !host) return LBM_EINVAL;
     if (count != (int64_t)n->P.nparams) return nfail(n, LBM_EINVAL, "expected %zu parameters", n->P.nparams);
+    n->packed = false;
     NHIP(n, hipMemcpyAsync(n->b.theta, host, 4 * n->P.nparams, hipMemcpyHostToDevice, n->s));
     NHIP(n, lbmnet::zero(n->b.m, n->P.nparams, n->s));
     NHIP(n, lbmnet::zero(n->b.v, n->P.nparams, n->s));
@@ -504,6 +522,7 @@ lbm_status lbm_net_adam(lbm_net *n, float lr, float b1, float b2, float eps) {
     n->adam_t += 1;
     const double c1 = 1.0 - std::pow((double)b1, (double)n->adam_t);
     const double c2 = 1.0 - std::pow((double)b2, (double)n->adam_t);
+    n->packed = false;
     NHIP(n, lbmnet::adam(n->b.theta, n->b.grad, n->b.m, n->b.v, (int)n->P.nparams, lr, b1, b2, eps, (float)c1,
                          (float)c2, n->s));
     n->have_grad = false;

@@ -25,6 +25,12 @@ hipError_t conv3x3(const View &in, const float *w, const float *bias, const View
 int pad32(int c);
 hipError_t conv3x3_mfma(const View &in, const float *w, const float *bias, const View &out, int N, int cin,
                         int cout, bool relu, __bf16 *wp, hipStream_t s);
+// The two halves of conv3x3_mfma: packing alone, and the convolution on
+// weights packed earlier (the network keeps its packed weights until the
+// parameters change).
+hipError_t pack_weights(const float *w, __bf16 *wp, int cin, int cout, hipStream_t s);
+hipError_t conv3x3_mfma_packed(const View &in, const __bf16 *wp, const float *bias, const View &out, int N,
+                               int cin, int cout, bool relu, hipStream_t s);
 // Input gradient of a 3x3 layer on matrix cores: dz is the layer gradient
 // already rounded to bf16, the weights are rounded to bf16 as they are packed;
 // wp holds 9 * cin * pad32(cout) bf16.

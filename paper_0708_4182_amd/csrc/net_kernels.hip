@@ -1078,13 +1078,22 @@ hipError_t launch_conv3x3_mfma(const View &in, const __bf16 *wp, const float *bi
                 : launch_conv3x3_mfma_t<TO, 4, 32>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, s);
 }
 
-hipError_t conv3x3_mfma(const View &in, const float *w, const float *bias, const View &out, int N, int cin,
-                        int cout, bool relu, __bf16 *wp, hipStream_t s) {
+hipError_t pack_weights(const float *w, __bf16 *wp, int cin, int cout, hipStream_t s) {
     const int cin_pad = pad32(cin);
     k_pack_weights<<<nblk((size_t)9 * cout * cin_pad), 256, 0, s>>>(w, wp, cin, cout, cin_pad);
-    hipError_t e = hipGetLastError();
+    return hipGetLastError();
+}
+
+hipError_t conv3x3_mfma_packed(const View &in, const __bf16 *wp, const float *bias, const View &out, int N,
+                               int cin, int cout, bool relu, hipStream_t s) {
+    return launch_conv3x3_mfma<__bf16>(in, wp, bias, out, N, cin, cout, pad32(cin), relu, s);
+}
+
+hipError_t conv3x3_mfma(const View &in, const float *w, const float *bias, const View &out, int N, int cin,
+                        int cout, bool relu, __bf16 *wp, hipStream_t s) {
+    const hipError_t e = pack_weights(w, wp, cin, cout, s);
     if (e != hipSuccess) return e;
-    return launch_conv3x3_mfma<__bf16>(in, wp, bias, out, N, cin, cout, cin_pad, relu, s);
+    return conv3x3_mfma_packed(in, wp, bias, out, N, cin, cout, relu, s);
 }
 
 // Input gradient dX = conv(dz, flipped transposed W) on matrix cores: dz (the

@@ -226,6 +226,27 @@ def test_adam_step_matches_oracle(net):
         th = got
 
 
+def test_packed_weights_follow_parameter_updates(net):
+    """The bf16 build keeps its forward weights packed between calls: after
+    lbm_net_set_params and after an Adam step the forward must equal that of
+    a new network given the same parameters, bit for bit."""
+    x, t, fluid, specs, theta = problem(n=2, seed=9, **SMALL)
+    theta2 = problem(n=2, seed=10, **SMALL)[4]
+    d = to_dev(x, t, fluid)
+    mk = lambda th: (lambda m: (m.set_params(th), m)[1])(net.Net(SMALL["H"], SMALL["W"], 2, chans=SMALL["chans"],
+                                                                 act_bf16=True))
+    m = mk(theta)
+    y1 = m.forward(d[0]).cpu().numpy()
+    m.set_params(theta2)
+    y2 = m.forward(d[0]).cpu().numpy()
+    assert not np.array_equal(y1, y2)
+    np.testing.assert_array_equal(y2, mk(theta2).forward(d[0]).cpu().numpy())
+    m.train_step(*d, lr=1e-3)
+    y3 = m.forward(d[0]).cpu().numpy()
+    assert not np.array_equal(y2, y3)
+    np.testing.assert_array_equal(y3, mk(m.get_params().astype(np.float64)).forward(d[0]).cpu().numpy())
+
+
 def test_training_reduces_the_loss(net):
     """Fit a fixed small batch: the loss must fall well below its start."""
     x, t, fluid, specs, theta = problem(n=4, seed=6, **SMALL)
