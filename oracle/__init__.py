@@ -42,7 +42,7 @@ class _Params(C.Structure):
                 ("elec_layers", C.c_int32), ("elec_walls", C.c_uint32),
                 ("accel_x", C.c_double), ("accel_y", C.c_double),
                 ("collision", C.c_int32), ("trt_magic", C.c_double),
-                ("elec_normal", C.c_int32)]
+                ("elec_normal", C.c_int32), ("mrt_s_e", C.c_double), ("mrt_s_eps", C.c_double)]
 
 
 _lib = None
@@ -87,7 +87,8 @@ def _params(p) -> _Params:
                    float(p.g_diag), float(p.w_axis), float(p.w_diag), float(p.rho_c),
                    float(p.f_elec), int(p.elec_layers), int(p.elec_walls),
                    float(p.accel_x), float(p.accel_y), int(getattr(p, "collision", 0)),
-                   float(getattr(p, "trt_magic", 3.0 / 16.0)), int(getattr(p, "elec_normal", 0)))
+                   float(getattr(p, "trt_magic", 3.0 / 16.0)), int(getattr(p, "elec_normal", 0)),
+                   float(getattr(p, "mrt_s_e", 1.64)), float(getattr(p, "mrt_s_eps", 1.54)))
 
 
 def _d(a):

@@ -47,6 +47,16 @@
  * S_a = w_a [3 (e_a - u) + 9 (e_a . u) e_a] . F enters split the same way,
  * weighted (1 - omega+/2) and (1 - omega-/2).
  *
+ * A third (collision = 2), also not in the paper: multiple-relaxation-time
+ * (MRT) collision in the orthogonal moment basis of Lallemand & Luo (Phys.
+ * Rev. E 61, 6546, 2000), m = (rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy),
+ * with the same Guo forcing in moment space (Guo & Zheng 2008):
+ * m* = m - S (m - m^eq) + (I - S/2) M S, where m^eq = M f^eq(rho, u) with
+ * u = (sum f e + F/2) / rho, S = diag(0, s_e, s_eps, 0, s_q, 0, s_q, 1/tau,
+ * 1/tau), s_q = omega- of the TRT relation above (so Lambda keeps its
+ * meaning), and f* = M^-1 m*.  With s_e = s_eps = 1/tau it is the TRT
+ * operator; s_e sets the bulk viscosity, s_eps a kinetic mode.
+ *
  * Arrays are row-major [ny][nx]; populations are planes [9][ny][nx].
  * Solid nodes carry no populations (their entries are ignored and left 0).
  */
@@ -69,8 +79,9 @@ typedef struct {
     uint32_t elec_walls; /* bit 0: bottom wall is an electrode, bit 1: top */
     double accel_x, accel_y;
     int32_t collision;   /* 0: BGK with the velocity shift of eq. (10); 1: TRT with Guo forcing */
-    double trt_magic;    /* Lambda of the TRT operator */
+    double trt_magic;    /* Lambda of the TRT operator (and of MRT's s_q) */
     int32_t elec_normal; /* 0: n towards the electrode wall; 1: local face normal */
+    double mrt_s_e, mrt_s_eps; /* MRT rates of the energy moments e and eps */
 } orc_params;
 
 /* ---------------------------------------------------------------- lattice */
@@ -368,6 +379,60 @@ static void collide_trt_guo(const orc_params *p, const double *f, double *fs, si
     }
 }
 
+/* ------------------------------------------------------ MRT with Guo forcing */
+/* Rows of the moment matrix, from the velocities: 1, -4 + 3|e|^2,
+ * 4 - 21/2 |e|^2 + 9/2 |e|^4, e_x, (-5 + 3|e|^2) e_x, e_y, (-5 + 3|e|^2) e_y,
+ * e_x^2 - e_y^2, e_x e_y; the rows are orthogonal, so M^-1 = M^T diag(1/|row|^2). */
+static double MRT_M[9][9], MRT_N[9];
+static int mrt_ready = 0;
+
+static void mrt_init(void)
+{
+    if (mrt_ready) return;
+    for (int a = 0; a < 9; ++a) {
+        const double ex = E[a][0], ey = E[a][1], e2 = ex * ex + ey * ey;
+        const double row[9] = {1.0, -4.0 + 3.0 * e2, 4.0 - 10.5 * e2 + 4.5 * e2 * e2, ex, (-5.0 + 3.0 * e2) * ex,
+                               ey, (-5.0 + 3.0 * e2) * ey, ex * ex - ey * ey, ex * ey};
+        for (int k = 0; k < 9; ++k) MRT_M[k][a] = row[k];
+    }
+    for (int k = 0; k < 9; ++k) {
+        MRT_N[k] = 0.0;
+        for (int a = 0; a < 9; ++a) MRT_N[k] += MRT_M[k][a] * MRT_M[k][a];
+    }
+    mrt_ready = 1;
+}
+
+/* Collision of node i with the MRT operator (see the header). */
+static void collide_mrt_guo(const orc_params *p, const double *f, double *fs, size_t n, size_t i,
+                            double rho, double ux, double uy, double Fx, double Fy)
+{
+    const double sq = orc_trt_omega_minus(p->tau, p->trt_magic), sn = 1.0 / p->tau;
+    const double s[9] = {0.0, p->mrt_s_e, p->mrt_s_eps, 0.0, sq, 0.0, sq, sn, sn};
+    const double vx = ux + 0.5 * Fx / rho, vy = uy + 0.5 * Fy / rho;
+    double feq[9], S[9], ms[9];
+    orc_equilibrium(rho, vx, vy, feq);
+    for (int a = 0; a < 9; ++a) {
+        const double eu = E[a][0] * vx + E[a][1] * vy;
+        const double eF = E[a][0] * Fx + E[a][1] * Fy;
+        const double uF = vx * Fx + vy * Fy;
+        S[a] = WT[a] * (3.0 * (eF - uF) + 9.0 * eu * eF);
+    }
+    for (int k = 0; k < 9; ++k) {
+        double m = 0.0, meq = 0.0, sf = 0.0;
+        for (int a = 0; a < 9; ++a) {
+            m += MRT_M[k][a] * f[(size_t)a * n + i];
+            meq += MRT_M[k][a] * feq[a];
+            sf += MRT_M[k][a] * S[a];
+        }
+        ms[k] = m - s[k] * (m - meq) + (1.0 - 0.5 * s[k]) * sf;
+    }
+    for (int a = 0; a < 9; ++a) {
+        double v = 0.0;
+        for (int k = 0; k < 9; ++k) v += MRT_M[k][a] * ms[k] / MRT_N[k];
+        fs[(size_t)a * n + i] = v;
+    }
+}
+
 /* --------------------------------------------------------------------- step */
 /*
  * Advance nsteps time steps in place.  f holds the populations after
@@ -376,7 +441,8 @@ static void collide_trt_guo(const orc_params *p, const double *f, double *fs, si
  *   2. forces Fs (5), Fw (6), electric f n, body rho g;
  *   3. u' from eq. (10);
  *   4. collision f* = f - (f - f^eq(rho, u'))/tau (right side of eq. (1));
- *      (collision = 1: steps 3-4 are the TRT collision with Guo forcing);
+ *      (collision = 1 or 2: steps 3-4 are the TRT or MRT collision with Guo
+ *      forcing);
  *   5. streaming f(x + e, t + 1) = f*(x) (left side of eq. (1)), with a
  *      population arriving from a solid node replaced by bounce-back.
  * Returns 0, or 1 if a fluid density became non-positive or not finite.
@@ -396,6 +462,7 @@ int orc_step(const orc_params *p, const uint8_t *solid, double *f, int64_t nstep
 int orc_step_ext(const orc_params *p, const uint8_t *solid, double *f, int64_t nsteps, const double *acc)
 {
     lattice_init();
+    mrt_init();
     size_t n = (size_t)p->nx * p->ny;
     double *rho = malloc(n * sizeof(double)), *ux = malloc(n * sizeof(double)),
            *uy = malloc(n * sizeof(double));
@@ -426,6 +493,10 @@ int orc_step_ext(const orc_params *p, const uint8_t *solid, double *f, int64_t n
             double Fy = Fs[n + i] + Fw[n + i] + Fe[n + i] + rho[i] * gy;
             if (p->collision == 1) {
                 collide_trt_guo(p, f, fs, n, i, rho[i], ux[i], uy[i], Fx, Fy);
+                continue;
+            }
+            if (p->collision == 2) {
+                collide_mrt_guo(p, f, fs, n, i, rho[i], ux[i], uy[i], Fx, Fy);
                 continue;
             }
             double upx = (rho[i] * ux[i] + p->tau * Fx) / rho[i];  /* eq. (10) */

@@ -117,10 +117,12 @@ class Params:
     accel_y: float = 0.0
     storage: int = 0  # 0 = fp32, 1 = fp16, 2 = bf16
     rho_ref: float = 0.0  # stored deviations are f - w rho_ref (0: raw f for fp32, rho0 for 16-bit)
-    collision: int = 0  # 0: BGK with the velocity shift of eq. (10); 1: TRT with Guo forcing
-    trt_magic: float = 3.0 / 16.0  # Lambda of the TRT operator
+    collision: int = 0  # 0: BGK with the velocity shift of eq. (10); 1: TRT, 2: MRT, both with Guo forcing
+    trt_magic: float = 3.0 / 16.0  # Lambda of the TRT operator (and the s_q of MRT)
     elec_normal: int = 0  # 0: electric force towards the electrode wall; 1: along the local face normal
     rounding: int = 0  # 16-bit storage: 0 nearest even, 1 stochastic (unbiased; see lbm_params.rounding)
+    mrt_s_e: float = 1.64  # MRT rate of the energy moment e (bulk viscosity); Lallemand & Luo's value
+    mrt_s_eps: float = 1.54  # MRT rate of the moment eps; Lallemand & Luo's value
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)
