@@ -83,12 +83,14 @@ typedef struct {
                               liquid density keeps the stored numbers small where the
                               flow is, which FP32 needs to resolve slow velocity modes  */
     int32_t collision;     /* LBM_COLLIDE_BGK: the paper's velocity shift, eq. (10), and
-                              BGK relaxation, eq. (1).  LBM_COLLIDE_TRT_GUO (not in the
-                              paper): the same force F with Guo's forcing term and a
-                              two-relaxation-time collision, see below               */
-    double trt_magic;      /* Lambda of LBM_COLLIDE_TRT_GUO (> 0; 3/16 puts halfway
-                              bounce-back walls exactly halfway for plane Poiseuille
-                              flow at any tau); ignored for LBM_COLLIDE_BGK           */
+                              BGK relaxation, eq. (1).  LBM_COLLIDE_TRT_GUO and
+                              LBM_COLLIDE_MRT_GUO (not in the paper): the same force F
+                              with Guo's forcing term and a two- or multiple-
+                              relaxation-time collision, see below                   */
+    double trt_magic;      /* Lambda of LBM_COLLIDE_TRT_GUO and LBM_COLLIDE_MRT_GUO
+                              (> 0; 3/16 puts halfway bounce-back walls exactly
+                              halfway for plane Poiseuille flow at any tau); ignored
+                              for LBM_COLLIDE_BGK                                     */
     int32_t elec_normal;   /* direction n of the electric force f n.  0: towards the
                               electrode wall, (0, -1) on the bottom half and (0, +1)
                               on the top half.  1: the local face normal of the
@@ -100,6 +102,9 @@ typedef struct {
     int32_t rounding;      /* rounding of the stored 16-bit deviations, see below:
                               LBM_ROUND_NEAREST (default) or LBM_ROUND_STOCHASTIC
                               (LBM_F16 and LBM_BF16 only; LBM_EINVAL with LBM_F32)    */
+    double mrt_s_e, mrt_s_eps; /* LBM_COLLIDE_MRT_GUO: relaxation rates of the energy
+                              moments e and eps, each in (0, 2) (Lallemand & Luo use
+                              1.64 and 1.54); ignored by the other operators         */
 } lbm_params;
 
 /* Rounding of 16-bit storage (lbm_params.rounding).  LBM_ROUND_NEAREST rounds
@@ -138,6 +143,15 @@ typedef struct {
  * lbm_moments and lbm_flux report u = sum f e / rho of eq. (2) for both. */
 #define LBM_COLLIDE_BGK 0
 #define LBM_COLLIDE_TRT_GUO 1
+/* LBM_COLLIDE_MRT_GUO: multiple-relaxation-time collision in the orthogonal
+ * moment basis m = M f = (rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy) of
+ * Lallemand & Luo (Phys. Rev. E 61, 6546, 2000), with the same u, F and Guo
+ * source as TRT taken to moment space: m* = m - S (m - M f^eq) + (I - S/2) M S,
+ * S = diag(0, mrt_s_e, mrt_s_eps, 0, s_q, 0, s_q, 1/tau, 1/tau), s_q = omega-
+ * of the TRT relation; f* = M^-1 m*.  Shear viscosity (tau - 1/2)/3, bulk
+ * viscosity (1/mrt_s_e - 1/2)/3; with mrt_s_e = mrt_s_eps = 1/tau it is
+ * LBM_COLLIDE_TRT_GUO.  Runs wherever TRT runs (the same kernels). */
+#define LBM_COLLIDE_MRT_GUO 2
 
 typedef struct lbm_sim lbm_sim;
 

@@ -120,9 +120,13 @@ std::string check_params(const lbm_params *p) {
     if (p->storage < LBM_F32 || p->storage > LBM_BF16) return "storage must be LBM_F32, LBM_F16 or LBM_BF16";
     if (p->elec_layers < 0 || p->elec_layers > 1024) return "elec_layers must be in [0, 1024]";
     if (p->elec_walls > 3u) return "elec_walls must be a combination of LBM_ELEC_BOTTOM and LBM_ELEC_TOP";
-    if (p->collision != LBM_COLLIDE_BGK && p->collision != LBM_COLLIDE_TRT_GUO)
-        return "collision must be LBM_COLLIDE_BGK or LBM_COLLIDE_TRT_GUO";
-    if (p->collision == LBM_COLLIDE_TRT_GUO && !(p->trt_magic > 0.0)) return "trt_magic must be > 0";
+    if (p->collision != LBM_COLLIDE_BGK && p->collision != LBM_COLLIDE_TRT_GUO &&
+        p->collision != LBM_COLLIDE_MRT_GUO)
+        return "collision must be LBM_COLLIDE_BGK, LBM_COLLIDE_TRT_GUO or LBM_COLLIDE_MRT_GUO";
+    if (p->collision != LBM_COLLIDE_BGK && !(p->trt_magic > 0.0)) return "trt_magic must be > 0";
+    if (p->collision == LBM_COLLIDE_MRT_GUO &&
+        !(p->mrt_s_e > 0.0 && p->mrt_s_e < 2.0 && p->mrt_s_eps > 0.0 && p->mrt_s_eps < 2.0))
+        return "mrt_s_e and mrt_s_eps must be in (0, 2)";
     if (p->elec_normal != 0 && p->elec_normal != 1) return "elec_normal must be 0 or 1";
     if (p->rounding != LBM_ROUND_NEAREST && p->rounding != LBM_ROUND_STOCHASTIC)
         return "rounding must be LBM_ROUND_NEAREST or LBM_ROUND_STOCHASTIC";
@@ -178,7 +182,9 @@ Model make_model(const lbm_params *p) {
     m.f_elec_diag = (float)(p->f_elec / std::sqrt(2.0));
     m.gx = (float)p->accel_x;
     m.gy = (float)p->accel_y;
-    m.trt = p->collision == LBM_COLLIDE_TRT_GUO ? 1 : 0;
+    m.trt = p->collision == LBM_COLLIDE_TRT_GUO ? 1 : p->collision == LBM_COLLIDE_MRT_GUO ? 2 : 0;
+    m.mrt_se = (float)(p->collision == LBM_COLLIDE_MRT_GUO ? p->mrt_s_e : 0.0);
+    m.mrt_seps = (float)(p->collision == LBM_COLLIDE_MRT_GUO ? p->mrt_s_eps : 0.0);
     const double om_m = m.trt ? 1.0 / (p->trt_magic / (p->tau - 0.5) + 0.5) : 1.0 / p->tau;
     m.omega_m = (float)om_m;
     m.src_p = (float)(1.0 - 0.5 / p->tau);

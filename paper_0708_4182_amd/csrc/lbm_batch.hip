@@ -331,7 +331,7 @@ lbm_status lbm_batch_init(lbm_batch **out, int32_t n, const lbm_params *p, const
     lbm_batch *b = new lbm_batch();
     b->n = n;
     b->storage = p[0].storage;
-    b->trt = p[0].collision == LBM_COLLIDE_TRT_GUO;
+    b->trt = p[0].collision != LBM_COLLIDE_BGK;   // TRT and MRT share the kernels
     b->sround = p[0].rounding == LBM_ROUND_STOCHASTIC;
     b->p.assign(p, p + n);
     b->g = L.g;

@@ -29,8 +29,9 @@ struct Model {
     float rho_c, f_elec;
     float f_elec_diag;         // f_elec / sqrt 2 (force along a diagonal face normal)
     float gx, gy;              // driving acceleration
-    int32_t trt;               // 0: BGK with the velocity shift; 1: TRT with Guo forcing
-    float omega_m;             // TRT: relaxation rate of the antisymmetric part
+    int32_t trt;               // 0: BGK with the velocity shift; 1: TRT, 2: MRT, with Guo forcing
+    float omega_m;             // TRT: relaxation rate of the antisymmetric part (MRT: s_q)
+    float mrt_se, mrt_seps;    // MRT: rates of the energy moments e and eps
     float src_p, src_m;        // TRT: source weights 1 - omega/2 and 1 - omega_m/2
     int32_t sround;            // 1: stochastic rounding of 16-bit stores (0: nearest)
 };

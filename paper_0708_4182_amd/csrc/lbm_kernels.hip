@@ -261,6 +261,60 @@ __device__ __forceinline__ void collide_trt(const Model &m, const float d[9], fl
     pair(6, 8, uy - ux, Fy - Fx, W5);
 }
 
+// Multiple-relaxation-time collision with Guo's forcing term
+// (lbm_params.collision = LBM_COLLIDE_MRT_GUO; not the paper's scheme), run
+// by the TRT kernels.  The non-equilibrium parts n = d - feq (feq at
+// u = (j + F/2) / rho, the offset w rho_off cancelling as in TRT) go to the
+// six non-conserved moments of the orthogonal basis (e, eps, q_x, q_y, p_xx,
+// p_xy), built from the sums P and differences D of opposite pairs; each
+// relaxes at its rate and gets (1 - s/2) times its moment of Guo's source,
+// which in this basis is (6 u.F, -6 u.F, -F_x, -F_y, 2 (u_x F_x - u_y F_y),
+// u_x F_y + u_y F_x); j gains F, rho nothing.  The changes go back through
+// M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4).
+__device__ __forceinline__ void collide_mrt(const Model &m, const float d[9], float rho, float s, float jx,
+                                            float jy, float Fx, float Fy, float out[9]) {
+#pragma clang fp contract(off)
+    const float hx = jx + 0.5f * Fx, hy = jy + 0.5f * Fy;
+    float feq[9];
+    equilibrium(rho, s, hx, hy, feq);
+    const float inv = __builtin_amdgcn_rcpf(rho);
+    const float ux = hx * inv, uy = hy * inv;
+    float n[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) n[a] = d[a] - feq[a];
+    const float P1 = n[1] + n[3], D1 = n[1] - n[3], P2 = n[2] + n[4], D2 = n[2] - n[4];
+    const float P5 = n[5] + n[7], D5 = n[5] - n[7], P6 = n[6] + n[8], D6 = n[6] - n[8];
+    const float ne = 2.f * (P5 + P6) - (P1 + P2) - 4.f * n[0];
+    const float neps = (P5 + P6) - 2.f * (P1 + P2) + 4.f * n[0];
+    const float nqx = (D5 - D6) - 2.f * D1, nqy = (D5 + D6) - 2.f * D2;
+    const float npxx = P1 - P2, npxy = P5 - P6;
+    const float se = m.mrt_se, seps = m.mrt_seps, sq = m.omega_m, sn = m.omega;
+    const float uF = ux * Fx + uy * Fy;
+    const float de = (1.f - 0.5f * se) * (6.f * uF) - se * ne;
+    const float deps = (1.f - 0.5f * seps) * (-6.f * uF) - seps * neps;
+    const float dqx = (1.f - 0.5f * sq) * (-Fx) - sq * nqx;
+    const float dqy = (1.f - 0.5f * sq) * (-Fy) - sq * nqy;
+    const float dpxx = (1.f - 0.5f * sn) * (2.f * (ux * Fx - uy * Fy)) - sn * npxx;
+    const float dpxy = (1.f - 0.5f * sn) * (ux * Fy + uy * Fx) - sn * npxy;
+    const float ce = de * (1.f / 36.f), cp = deps * (1.f / 36.f);
+    const float cjx = Fx * (1.f / 6.f), cjy = Fy * (1.f / 6.f);
+    const float cqx = dqx * (1.f / 12.f), cqy = dqy * (1.f / 12.f);
+    const float cxx = 0.25f * dpxx, cxy = 0.25f * dpxy;
+    const float ax = -ce - 2.f * cp;              // even part shared by the axis directions
+    const float dg = 2.f * ce + cp;               // and by the diagonals
+    const float ox = cjx - 2.f * cqx, oy = cjy - 2.f * cqy;
+    const float gx = cjx + cqx, gy = cjy + cqy;
+    out[0] = d[0] + 4.f * (cp - ce);
+    out[1] = d[1] + ((ax + cxx) + ox);
+    out[3] = d[3] + ((ax + cxx) - ox);
+    out[2] = d[2] + ((ax - cxx) + oy);
+    out[4] = d[4] + ((ax - cxx) - oy);
+    out[5] = d[5] + ((dg + cxy) + (gx + gy));
+    out[7] = d[7] + ((dg + cxy) - (gx + gy));
+    out[6] = d[6] + ((dg - cxy) + (gy - gx));
+    out[8] = d[8] + ((dg - cxy) - (gy - gx));
+}
+
 // Force, velocity shift (eq. (10)) and BGK collision (eq. (1)) of one node,
 // then the store of its nine post-collision populations.  phi of the 3x3
 // neighbourhood comes from LDS rows rowm (y-1), row0 (y), rowp (y+1) at
@@ -302,7 +356,8 @@ __device__ __forceinline__ void collide_post(const Model &m, const float d[9], f
     Fx += rho * m.gx;
     Fy += rho * m.gy;
     if constexpr (TRT) {
-        collide_trt(m, d, rho, s, jx, jy, Fx, Fy, out);
+        if (m.trt == 2) collide_mrt(m, d, rho, s, jx, jy, Fx, Fy, out);
+        else collide_trt(m, d, rho, s, jx, jy, Fx, Fy, out);
         return;
     }
     // eq. (10): rho u' = rho u + tau F

@@ -55,7 +55,8 @@ class lbm_params(C.Structure):
                 ("accel_x", C.c_double), ("accel_y", C.c_double),
                 ("storage", C.c_int32), ("rho_ref", C.c_double),
                 ("collision", C.c_int32), ("trt_magic", C.c_double),
-                ("elec_normal", C.c_int32), ("rounding", C.c_int32)]
+                ("elec_normal", C.c_int32), ("rounding", C.c_int32),
+                ("mrt_s_e", C.c_double), ("mrt_s_eps", C.c_double)]
 
 
 def to_c_params(p) -> lbm_params:
@@ -64,7 +65,8 @@ def to_c_params(p) -> lbm_params:
                       float(p.f_elec), int(p.elec_layers), int(p.elec_walls), float(p.accel_x),
                       float(p.accel_y), int(getattr(p, "storage", 0)), float(getattr(p, "rho_ref", 0.0)),
                       int(getattr(p, "collision", 0)), float(getattr(p, "trt_magic", 3.0 / 16.0)),
-                      int(getattr(p, "elec_normal", 0)), int(getattr(p, "rounding", 0)))
+                      int(getattr(p, "elec_normal", 0)), int(getattr(p, "rounding", 0)),
+                      float(getattr(p, "mrt_s_e", 1.64)), float(getattr(p, "mrt_s_eps", 1.54)))
 
 
 _lib = None

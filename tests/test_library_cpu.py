@@ -58,9 +58,10 @@ def test_workspace_bytes(lib):
     assert lbm.workspace_bytes(p.replace(rho_ref=-1.0)) == 0
     assert lbm.workspace_bytes(p.replace(rho_ref=float("nan"))) == 0
     assert lbm.workspace_bytes(p.replace(rho_ref=1.8)) == n32
-    # collision operator: BGK (0) or TRT with Guo forcing (1), Lambda > 0 for TRT
+    # collision operator: BGK (0), TRT (1) or MRT (2) with Guo forcing, Lambda > 0 for both
     assert lbm.workspace_bytes(p.replace(collision=1)) == n32
-    assert lbm.workspace_bytes(p.replace(collision=2)) == 0
+    assert lbm.workspace_bytes(p.replace(collision=2)) == n32
+    assert lbm.workspace_bytes(p.replace(collision=3)) == 0
     assert lbm.workspace_bytes(p.replace(collision=-1)) == 0
     assert lbm.workspace_bytes(p.replace(collision=1, trt_magic=0.0)) == 0
     assert lbm.workspace_bytes(p.replace(collision=1, trt_magic=float("inf"))) == 0
@@ -73,6 +74,10 @@ def test_workspace_bytes(lib):
     assert lbm.workspace_bytes(p.replace(storage=2, rounding=1)) == lbm.workspace_bytes(p.replace(storage=2))
     assert lbm.workspace_bytes(p.replace(storage=0, rounding=1)) == 0
     assert lbm.workspace_bytes(p.replace(storage=1, rounding=2)) == 0
+    # MRT: rates of e and eps in (0, 2), unused by the other operators
+    assert lbm.workspace_bytes(p.replace(collision=2)) == lbm.workspace_bytes(p.replace(collision=1))
+    assert lbm.workspace_bytes(p.replace(collision=2, mrt_s_e=2.0)) == 0
+    assert lbm.workspace_bytes(p.replace(collision=1, mrt_s_e=0.0, mrt_s_eps=0.0)) > 0
     # one population buffer must stay below 4 GiB (32-bit offsets)
     assert lbm.workspace_bytes(I.Params(nx=65536, ny=4096)) == 0
 
@@ -80,7 +85,9 @@ def test_workspace_bytes(lib):
 @pytest.mark.parametrize("bad", [dict(nx=2), dict(tau=0.4), dict(elec_walls=4),
                                  dict(elec_layers=-1), dict(storage=3), dict(rho_ref=-0.5),
                                  dict(collision=5), dict(collision=1, trt_magic=-1.0),
-                                 dict(elec_normal=-1), dict(rounding=1), dict(storage=1, rounding=-1)])
+                                 dict(elec_normal=-1), dict(rounding=1), dict(storage=1, rounding=-1),
+                                 dict(collision=2, mrt_s_e=0.0), dict(collision=2, mrt_s_eps=2.0),
+                                 dict(collision=2, trt_magic=0.0)])
 def test_init_rejects_invalid_params_without_gpu_work(lib, bad):
     from paper_0708_4182_amd import lbm
     import numpy as np
