@@ -75,9 +75,20 @@ def test_mrt_fp32_parity(lbm, name, nsteps):
     parity(lbm, mrt_case(name), nsteps, name)
 
 
-@pytest.mark.parametrize("se,seps", [(1.2, 1.9), (1.9, 1.1)])
+@pytest.mark.parametrize("se,seps", [(1.2, 1.9), (1.8, 1.3)])
 def test_mrt_other_rates_parity(lbm, se, seps):
-    parity(lbm, mrt_case("ragged37x19", mrt_s_e=se, mrt_s_eps=seps), 300, f"s_e={se} s_eps={seps}")
+    """Other rates of e and eps on the thin ragged lattice (its interface
+    currents stay below 0.035; the droplet and the 37 x 19 lattice diverge at
+    s_e = 1.2 or carry |u| = 0.16, the FP32 floor of the tests above).  The
+    rates change u there by 8% and 2.5% of its norm, far above the bar."""
+    c = mrt_case("ragged300x5", mrt_s_e=se, mrt_s_eps=seps)
+    parity(lbm, c, 300, f"s_e={se} s_eps={seps}")
+    ref = mrt_case("ragged300x5")
+    _, ux0, uy0 = O.moments(ref.params, ref.solid, O.run(ref, 300))
+    _, ux1, uy1 = O.moments(c.params, c.solid, O.run(c, 300))
+    fl = c.solid == 0
+    effect = np.linalg.norm(np.hypot(ux1 - ux0, uy1 - uy0)[fl]) / np.linalg.norm(np.hypot(ux0, uy0)[fl])
+    assert effect > 100 * TOL
 
 
 @pytest.mark.parametrize("tau", [0.6, 1.7])
