@@ -29,7 +29,8 @@ HBM_PEAK_GBS = 8000.0
 STORAGES = {"f32": 0, "f16": 1, "bf16": 2}
 # extra lines: name -> (storage, collision, rounding); collision 1 is the TRT operator with Guo
 # forcing, rounding 1 the stochastic rounding of 16-bit stores
-VARIANTS = {"f16": (1, 0, 0), "bf16": (2, 0, 0), "f32_trt": (0, 1, 0), "f16_sr": (1, 0, 1), "bf16_sr": (2, 0, 1)}
+VARIANTS = {"f16": (1, 0, 0), "bf16": (2, 0, 0), "f32_trt": (0, 1, 0), "f32_mrt": (0, 2, 0), "f16_sr": (1, 0, 1),
+            "bf16_sr": (2, 0, 1)}
 ELEM_BYTES = {0: 4, 1: 2, 2: 2}
 STEPS_PER_LAUNCH = {"two": 2, "three": 3}     # kernels that advance more than one time step per launch
 KERNEL_SRC = os.path.join(ROOT, "paper_0708_4182_amd", "csrc", "lbm_kernels.hip")
@@ -215,10 +216,10 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--storage", default="f32", choices=sorted(STORAGES))
-    ap.add_argument("--variants", default="f16,bf16,f32_trt,f16_sr,bf16_sr",
-                    help="other lines timed after the main one: f16, bf16 (storage), f32_trt (FP32 storage "
-                         "with the TRT collision and Guo forcing), f16_sr, bf16_sr (16-bit storage with "
-                         "stochastic rounding); '' for none")
+    ap.add_argument("--variants", default="f16,bf16,f32_trt,f32_mrt,f16_sr,bf16_sr",
+                    help="other lines timed after the main one: f16, bf16 (storage), f32_trt, f32_mrt (FP32 "
+                         "storage with the TRT or MRT collision and Guo forcing), f16_sr, bf16_sr (16-bit "
+                         "storage with stochastic rounding); '' for none")
     ap.add_argument("--nx", type=int, default=8192)
     ap.add_argument("--ny", type=int, default=2048)
     ap.add_argument("--tile", default="auto",
@@ -270,8 +271,8 @@ def main():
     for v in [v for v in args.variants.split(",") if v and v != args.storage]:
         st, coll, rnd = VARIANTS[v] if v in VARIANTS else (STORAGES[v], 0, 0)
         vt = tile
-        if (coll or rnd) and tile and tile[0] not in ("fused", "fused8", "two"):
-            vt = ("fused", tile[1], tile[2])     # TRT and stochastic rounding run in the fused and two-step kernels only
+        if (coll or rnd) and tile and tile[0] not in ("fused", "fused8", "two", "three"):
+            vt = ("fused", tile[1], tile[2])     # TRT, MRT and stochastic rounding: fused and multi-step kernels only
         r = time_storage(case, st, args.steps, args.warmup, vt, collision=coll, rounding=rnd)
         print(f"# {v}: tile {r['tile']} {r['step_ms']*1e3:.1f} us/step", file=sys.stderr, flush=True)
         variants[v] = step_line(v, r, nsites, nfluid)

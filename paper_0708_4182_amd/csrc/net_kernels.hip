@@ -205,9 +205,15 @@ __global__ void __launch_bounds__(256) k_bias_partial(const float *__restrict__ 
     const size_t total = (size_t)N * HW, len = (total + BIAS_PARTS - 1) / BIAS_PARTS;
     const size_t e0 = (size_t)b * len, e1 = min(total, e0 + len);
     float s = 0.f;
-    for (size_t e = e0 + threadIdx.x; e < e1; e += 256) {
-        const size_t n = e / (size_t)HW, p = e % (size_t)HW;
-        s += dz[(n * C + co) * HW + p];
+    size_t e = e0 + threadIdx.x;
+    if (e < e1) {
+        // (sample, pixel) of e, advanced by 256 each pass instead of divided
+        uint32_t n = (uint32_t)(e / (size_t)HW), p = (uint32_t)(e % (size_t)HW);
+        for (; e < e1; e += 256) {
+            s += dz[((size_t)n * C + co) * HW + p];
+            p += 256;
+            while (p >= (uint32_t)HW) { p -= (uint32_t)HW; ++n; }
+        }
     }
     sh[threadIdx.x] = s;
     __syncthreads();
@@ -243,6 +249,39 @@ __global__ void k_relu_mask(View g, View y, int N, int C, float *__restrict__ dz
     if (dzh) dzh[i] = (__bf16)v;
 }
 
+// The same, four pixels per thread (HW % 4 == 0 and aligned planes): 16-byte
+// FP32 and 8-byte bf16 accesses.
+template <class TA>
+__global__ void k_relu_mask4(View g, View y, int N, int C, float *__restrict__ dz, __bf16 *__restrict__ dzh) {
+    const uint32_t HW = (uint32_t)y.H * (uint32_t)y.W;
+    const uint32_t p = 4u * (blockIdx.x * blockDim.x + threadIdx.x);
+    if (p >= HW) return;
+    const uint32_t c = blockIdx.y, n = blockIdx.z;
+    const size_t r = (size_t)c * HW + p, i = ((size_t)n * C + c) * HW + p;
+    const float4 gv = *reinterpret_cast<const float4 *>(static_cast<const float *>(g.p) + n * g.bs + r);
+    float yv[4];
+    if constexpr (sizeof(TA) == 2) {
+        const uint2 yb = *reinterpret_cast<const uint2 *>(static_cast<const TA *>(y.p) + n * y.bs + r);
+        yv[0] = __uint_as_float(yb.x << 16);
+        yv[1] = __uint_as_float(yb.x & 0xffff0000u);
+        yv[2] = __uint_as_float(yb.y << 16);
+        yv[3] = __uint_as_float(yb.y & 0xffff0000u);
+    } else {
+        const float4 yf = *reinterpret_cast<const float4 *>(static_cast<const TA *>(y.p) + n * y.bs + r);
+        yv[0] = yf.x; yv[1] = yf.y; yv[2] = yf.z; yv[3] = yf.w;
+    }
+    const float4 v = make_float4(yv[0] > 0.f ? gv.x : 0.f, yv[1] > 0.f ? gv.y : 0.f, yv[2] > 0.f ? gv.z : 0.f,
+                                 yv[3] > 0.f ? gv.w : 0.f);
+    *reinterpret_cast<float4 *>(dz + i) = v;
+    if (dzh) {
+        const __bf16 h0 = (__bf16)v.x, h1 = (__bf16)v.y, h2 = (__bf16)v.z, h3 = (__bf16)v.w;
+        uint2 o;
+        o.x = (uint32_t)__builtin_bit_cast(unsigned short, h0) | (uint32_t)__builtin_bit_cast(unsigned short, h1) << 16;
+        o.y = (uint32_t)__builtin_bit_cast(unsigned short, h2) | (uint32_t)__builtin_bit_cast(unsigned short, h3) << 16;
+        *reinterpret_cast<uint2 *>(dzh + i) = o;
+    }
+}
+
 // ------------------------------------------------------ pool / upsample
 template <class TA>
 __global__ void k_pool(View in, View out, int N, int C) {
@@ -274,6 +313,25 @@ __global__ void k_up(View in, View out, int N, int C) {
     const uint32_t y = p / W, x = p - y * W, c = blockIdx.y, n = blockIdx.z;
     static_cast<TA *>(out.p)[n * out.bs + (size_t)c * H * W + p] =
         static_cast<const TA *>(in.p)[n * in.bs + (size_t)c * in.H * in.W + (size_t)(y / 2) * in.W + x / 2];
+}
+
+// The same, four fine pixels of a row per thread (W % 4 == 0, aligned planes):
+// two coarse values in, each written twice.
+template <class TA>
+__global__ void k_up4(View in, View out, int N, int C) {
+    const uint32_t H = out.H, W = out.W;
+    const uint32_t p = 4u * (blockIdx.x * blockDim.x + threadIdx.x);
+    if (p >= H * W) return;
+    const uint32_t y = p / W, x = p - y * W, c = blockIdx.y, n = blockIdx.z;
+    const TA *src = static_cast<const TA *>(in.p) + n * in.bs + (size_t)c * in.H * in.W + (size_t)(y / 2) * in.W + x / 2;
+    TA *dst = static_cast<TA *>(out.p) + n * out.bs + (size_t)c * H * W + p;
+    if constexpr (sizeof(TA) == 2) {
+        const uint32_t v = *reinterpret_cast<const uint32_t *>(src);
+        *reinterpret_cast<uint2 *>(dst) = make_uint2((v & 0xffffu) * 0x10001u, (v >> 16) * 0x10001u);
+    } else {
+        const float2 v = *reinterpret_cast<const float2 *>(src);
+        *reinterpret_cast<float4 *>(dst) = make_float4(v.x, v.x, v.y, v.y);
+    }
 }
 
 // gradient of upsample: dx (coarse, fp32) = sum of the 2x2 block of dy
@@ -362,10 +420,16 @@ __global__ void __launch_bounds__(256) k_conv1x1_dw_partial(View x, const float 
     const size_t e0 = (size_t)b * len, e1 = min(total, e0 + len);
     const TA *__restrict__ xp = static_cast<const TA *>(x.p);
     float s = 0.f;
-    for (size_t e = e0 + threadIdx.x; e < e1; e += 256) {
-        const size_t n = e / HW, p = e % HW;
-        const float gv = g[(n * cout + o) * HW + p];
-        s += c < cin ? gv * tof(xp[n * x.bs + (size_t)c * HW + p]) : gv;
+    size_t e = e0 + threadIdx.x;
+    if (e < e1) {
+        // (sample, pixel) of e, advanced by 256 each pass instead of divided
+        uint32_t n = (uint32_t)(e / HW), p = (uint32_t)(e % HW);
+        for (; e < e1; e += 256) {
+            const float gv = g[((size_t)n * cout + o) * HW + p];
+            s += c < cin ? gv * tof(xp[(size_t)n * x.bs + (size_t)c * HW + p]) : gv;
+            p += 256;
+            while (p >= (uint32_t)HW) { p -= (uint32_t)HW; ++n; }
+        }
     }
     sh[threadIdx.x] = s;
     __syncthreads();
@@ -1176,7 +1240,15 @@ hipError_t bias_grad(const float *dz, int N, int C, int HW, float *part, float *
 
 template <class TA>
 hipError_t relu_mask(const View &g, const View &y, int N, int C, float *dz, __bf16 *dzh, hipStream_t s) {
-    k_relu_mask<TA><<<pix_grid(y.H, y.W, C, N), 256, 0, s>>>(g, y, N, C, dz, dzh);
+    const long long HW = (long long)y.H * y.W;
+    const bool v4 = HW % 4 == 0 && g.bs % 4 == 0 && y.bs % 4 == 0 && (uintptr_t)g.p % 16 == 0 &&
+                    (uintptr_t)y.p % 16 == 0 && (uintptr_t)dz % 16 == 0 && (uintptr_t)dzh % 8 == 0;
+    if (v4) {
+        const dim3 grid((unsigned)((HW / 4 + 255) / 256), (unsigned)C, (unsigned)N);
+        k_relu_mask4<TA><<<grid, 256, 0, s>>>(g, y, N, C, dz, dzh);
+    } else {
+        k_relu_mask<TA><<<pix_grid(y.H, y.W, C, N), 256, 0, s>>>(g, y, N, C, dz, dzh);
+    }
     return hipGetLastError();
 }
 template hipError_t relu_mask<float>(const View &, const View &, int, int, float *, __bf16 *, hipStream_t);
@@ -1197,7 +1269,14 @@ hipError_t pool_back_acc(const View &dy, const View &dx, int N, int C, hipStream
 
 template <class TA>
 hipError_t up(const View &in, const View &out, int N, int C, hipStream_t s) {
-    k_up<TA><<<pix_grid(out.H, out.W, C, N), 256, 0, s>>>(in, out, N, C);
+    const bool v4 = out.W % 4 == 0 && in.W * 2 == out.W && in.bs % 2 == 0 && out.bs % 4 == 0 &&
+                    (uintptr_t)in.p % 16 == 0 && (uintptr_t)out.p % 16 == 0;
+    if (v4) {
+        const dim3 grid((unsigned)(((size_t)out.H * out.W / 4 + 255) / 256), (unsigned)C, (unsigned)N);
+        k_up4<TA><<<grid, 256, 0, s>>>(in, out, N, C);
+    } else {
+        k_up<TA><<<pix_grid(out.H, out.W, C, N), 256, 0, s>>>(in, out, N, C);
+    }
     return hipGetLastError();
 }
 template hipError_t up<float>(const View &, const View &, int, int, hipStream_t);

@@ -151,6 +151,23 @@ def test_wide_channels_match_oracle(net, bf16):
     check_against_fp64(m, bf16, x, t, fluid, specs, theta, samples=6)
 
 
+# Widths that are not multiples of 8 below the top level (40, 20, 10, 5
+# columns; 3 rows at the bottom): the convolutions' gather staging and
+# per-element stores, and the scalar forms of the ReLU mask and the
+# upsampling, which the other shapes (whole 8-pixel groups) do not reach.
+RAGGED = dict(H=24, W=40, chans=(8, 12, 16, 8))
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_ragged_widths_match_oracle(net, bf16):
+    """Seed 40 keeps every pre-activation at least 5.6e-5 of its layer's rms
+    away from zero (the oracle finds that)."""
+    x, t, fluid, specs, theta = problem(n=2, seed=40, **RAGGED)
+    m = net.Net(RAGGED["H"], RAGGED["W"], 2, chans=RAGGED["chans"], act_bf16=bf16)
+    m.set_params(theta)
+    check_against_fp64(m, bf16, x, t, fluid, specs, theta, samples=6)
+
+
 def test_gradient_is_deterministic(net):
     x, t, fluid, specs, theta = problem(n=2, seed=3, **SMALL)
     m = net.Net(SMALL["H"], SMALL["W"], 2, chans=SMALL["chans"])
