@@ -305,6 +305,23 @@ __global__ void k_pool_back_acc(View dy, View dx, int N, int C) {
     static_cast<float *>(dx.p)[n * dx.bs + (size_t)c * H * W + p] += 0.25f * g;
 }
 
+// The same, four fine pixels of a row per thread (W % 4 == 0, aligned planes).
+__global__ void k_pool_back_acc4(View dy, View dx, int N, int C) {
+    const uint32_t H = dx.H, W = dx.W;
+    const uint32_t p = 4u * (blockIdx.x * blockDim.x + threadIdx.x);
+    if (p >= H * W) return;
+    const uint32_t y = p / W, x = p - y * W, c = blockIdx.y, n = blockIdx.z;
+    const float2 g = *reinterpret_cast<const float2 *>(static_cast<const float *>(dy.p) + n * dy.bs +
+                                                       (size_t)c * dy.H * dy.W + (size_t)(y / 2) * dy.W + x / 2);
+    float4 *d = reinterpret_cast<float4 *>(static_cast<float *>(dx.p) + n * dx.bs + (size_t)c * H * W + p);
+    float4 v = *d;
+    v.x += 0.25f * g.x;
+    v.y += 0.25f * g.x;
+    v.z += 0.25f * g.y;
+    v.w += 0.25f * g.y;
+    *d = v;
+}
+
 template <class TA>
 __global__ void k_up(View in, View out, int N, int C) {
     const uint32_t H = out.H, W = out.W;
@@ -1263,7 +1280,14 @@ template hipError_t pool<float>(const View &, const View &, int, int, hipStream_
 template hipError_t pool<__bf16>(const View &, const View &, int, int, hipStream_t);
 
 hipError_t pool_back_acc(const View &dy, const View &dx, int N, int C, hipStream_t s) {
-    k_pool_back_acc<<<pix_grid(dx.H, dx.W, C, N), 256, 0, s>>>(dy, dx, N, C);
+    const bool v4 = dx.W % 4 == 0 && dy.W * 2 == dx.W && dy.bs % 2 == 0 && dx.bs % 4 == 0 &&
+                    (uintptr_t)dy.p % 16 == 0 && (uintptr_t)dx.p % 16 == 0;
+    if (v4) {
+        const dim3 grid((unsigned)(((size_t)dx.H * dx.W / 4 + 255) / 256), (unsigned)C, (unsigned)N);
+        k_pool_back_acc4<<<grid, 256, 0, s>>>(dy, dx, N, C);
+    } else {
+        k_pool_back_acc<<<pix_grid(dx.H, dx.W, C, N), 256, 0, s>>>(dy, dx, N, C);
+    }
     return hipGetLastError();
 }
 
