@@ -341,6 +341,154 @@ def warm_start(train=4096, test=512, nx=256, ny=64, epochs=30, batch=32, lr=1e-3
     return res
 
 
+SWEEP_HP, SWEEP_WN = 256, 256     # padded height and window width of the sweep's network
+
+
+def _sweep_windows(c, hp: int = SWEEP_HP, wn: int = SWEEP_WN):
+    """Network inputs for one channel of uneven size: windows of wn columns at a
+    stride of wn / 2 (the channel is periodic in x, so they wrap), rows padded to
+    hp with solid nodes; each window's middle wn / 2 columns are kept."""
+    from . import warmstart as WS
+    ny, nx = c.solid.shape
+    half = wn // 2
+    starts = [k * half - wn // 4 for k in range((nx + half - 1) // half)]
+    X = np.zeros((len(starts), 3, hp, wn), np.float32)
+    X[:, 0] = 1.0
+    cols = [np.arange(s0, s0 + wn) % nx for s0 in starts]
+    for k, cc in enumerate(cols):
+        X[k, 0, :ny] = c.solid[:, cc]
+    X[:, 1] = c.params.f_elec / WS.F_SCALE
+    X[:, 2] = (c.meta["G"] - WS.G_MID) / WS.G_HALF
+    return X, starts
+
+
+def sweep_warm(n=256, train=1024, epochs=10, batch=32, bf16=1, chans="32,64,128,128", max_steps=700_000,
+               data_max_steps=400_000, seed=0, train_seed=1, check_every=200, window=2000, rtol=None,
+               storage=0):
+    """Learned warm start of the batched sweep (the 256-channel table of uneven
+    widths 32-256 and lengths 512-4096), FP32 storage with the plain steady rule
+    (rtol 1e-8), or FP16 with stochastic rounding and the averaged rule of
+    sweep_steady (rtol 1e-5).
+
+    Training data: ``train`` channels drawn from the same distribution as the
+    table (seed ``train_seed``, a different stream) but 256 columns long, run
+    cold to steady flux; network inputs and targets padded to 256 rows with
+    solid nodes (outside the fluid mask of the loss).  The table's channels are
+    predicted in overlapping 256-column windows (middle halves kept) and seeded
+    with the predicted velocity on the cold start's density ("flow" mode), then
+    run to steady flux in one batch with the same rule as the cold batch, which
+    this experiment also runs.  Reported: lattice updates warm and cold, and how
+    many warm channels settle within 1e-4 of their cold flux."""
+    import torch
+
+    from . import net, warmstart as WS
+
+    def log(msg):
+        print(f"# {msg}", flush=True)
+
+    storage = int(storage)
+    rounding = 1 if storage else 0
+    average = storage != 0
+    if rtol is None:
+        rtol = 1e-5 if average else 1e-8
+
+    def to_steady(cases, steps):
+        b = lbm.Batch(cases)
+        b.autotune(reps=3)
+        t0 = time.perf_counter()
+        res = run_to_steady(b, check_every=check_every, window=window, rtol=rtol, max_steps=steps,
+                            log=log, log_every=20_000, average=average)
+        return b, res, time.perf_counter() - t0
+
+    chans = tuple(int(c) for c in str(chans).split(","))
+    hp, wn = SWEEP_HP, SWEEP_WN
+    # ---- training data
+    rows = I.sweep_table(train, train_seed)
+    tcases = []
+    for r in rows:
+        c = I.sweep_case(dict(r, nx=wn), storage=storage, rounding=rounding)
+        c.meta["G"] = r["G"]
+        tcases.append(c)
+    log(f"training data: {train} channels {wn} x 32..256, cold to steady flux")
+    b, res, wall_data = to_steady(tcases, data_max_steps)
+    X = np.zeros((train, 3, hp, wn), np.float32)
+    T = np.zeros((train, 3, hp, wn), np.float32)
+    fluid = np.zeros((train, hp, wn), np.uint8)
+    for i, c in enumerate(tcases):
+        ny = c.solid.shape[0]
+        X[i, 0] = 1.0
+        X[i, 0, :ny] = c.solid
+        X[i, 1] = c.params.f_elec / WS.F_SCALE
+        X[i, 2] = (c.meta["G"] - WS.G_MID) / WS.G_HALF
+        T[i, :, :ny] = b.moments_device(i).cpu().numpy()
+        fluid[i, :ny] = c.solid == 0
+    del b
+    log(f"training data ready: {int(res.converged.sum())} of {train} converged, {wall_data:.0f} s")
+    scales = WS.Scales.fit(T, fluid)
+    Tn = (T - scales.mean.reshape(1, 3, 1, 1)) / scales.std.reshape(1, 3, 1, 1) * fluid[:, None]
+    Xd = torch.from_numpy(X).cuda()
+    Td = torch.from_numpy(Tn.astype(np.float32)).cuda()
+    Fd = torch.from_numpy(fluid).cuda()
+    model = net.Net(hp, wn, batch, chans=chans, act_bf16=bool(int(bf16)))
+    model.set_params(net.he_init(net.layer_shapes(chans=chans), seed))
+    t0 = time.perf_counter()
+    losses = WS.train(model, Xd, Td, Fd, epochs, batch, 1e-3, 1e-5, seed, log=log, log_every=100)
+    train_s = time.perf_counter() - t0
+    del Xd, Td, Fd
+    # ---- the table: cold
+    table = I.sweep_table(n, seed)
+    cold_cases = []
+    for r in table:
+        c = I.sweep_case(r, storage=storage, rounding=rounding)
+        c.meta["G"] = r["G"]
+        cold_cases.append(c)
+    log(f"cold batch: {n} channels")
+    b, cold, wall_cold = to_steady(cold_cases, max_steps)
+    del b
+    # ---- predictions and the warm batch
+    t0 = time.perf_counter()
+    warm_cases, used = [], 0
+    for c in cold_cases:
+        ny, nx = c.solid.shape
+        Xw, starts = _sweep_windows(c, hp, wn)
+        pred = WS.predict(model, torch.from_numpy(Xw).cuda(), scales).cpu().numpy()
+        full = np.zeros((3, ny, nx), np.float32)
+        for k, s0 in enumerate(starts):
+            cc = np.arange(s0 + wn // 4, s0 + 3 * wn // 4) % nx
+            full[:, :, cc] = pred[k, :, :ny, wn // 4:3 * wn // 4]
+        fields = WS.warm_fields(full, c.solid, c.meta["G"], float(c.rho[c.solid == 0].sum()), mode="flow",
+                                rho_cold=c.rho)
+        if fields is None:
+            warm_cases.append(c)
+            continue
+        used += 1
+        w = I.Case(c.params, c.solid, c.rho, fields[1].astype(np.float64), fields[2].astype(np.float64),
+                   name=c.name, meta=dict(c.meta))
+        warm_cases.append(w)
+    predict_s = time.perf_counter() - t0
+    log(f"warm batch: {used} of {n} channels seeded from the prediction ({predict_s:.1f} s)")
+    b, warm, wall_warm = to_steady(warm_cases, max_steps)
+    del b
+    dq = np.abs(warm.Q - cold.Q) / np.abs(cold.Q)
+    both = warm.converged & cold.converged
+    nodes = np.array([c.params.nx * c.params.ny for c in cold_cases], np.float64)
+    return {"experiment": "sweep_warm", "channels": n, "train_channels": train, "train_shape": [hp, wn],
+            "epochs": epochs, "train_seconds": train_s, "data_seconds": wall_data,
+            "data_converged": int(res.converged.sum()), "final_train_loss": losses[-1][1],
+            "storage": storage, "steady_rule": {"rtol": rtol, "averaged": average, "window": window},
+            "cold": {"converged": int(cold.converged.sum()), "lattice_updates": cold.node_updates,
+                     "wall_seconds": wall_cold, "steps_median": float(np.median(cold.steps))},
+            "warm": {"seeded": used, "converged": int(warm.converged.sum()),
+                     "lattice_updates": warm.node_updates, "wall_seconds": wall_warm + predict_s,
+                     "steps_median": float(np.median(warm.steps))},
+            "lattice_updates_warm_over_cold": warm.node_updates / cold.node_updates,
+            "lattice_updates_warm_over_cold_both_converged":
+                float((nodes * warm.steps)[both].sum() / (nodes * cold.steps)[both].sum()) if both.any() else None,
+            "within_1e-4_of_cold": int((dq[both] <= 1e-4).sum()), "both_converged": int(both.sum()),
+            "flux_dev_median": float(np.median(dq[both])) if both.any() else None,
+            "flux_dev_max": float(dq[both].max()) if both.any() else None}
+
+
 def warm_detect(train=2048, val=256, test=64, nx=256, ny=64, epochs=10, batch=32, bf16=1,
                 chans="32,64,128,128", max_steps=100_000, seed=0, out="", t_cold="0,500,1000,2000,4000"):
     """Learned warm start that needs no cold reference: warm runs settle by their
@@ -516,7 +664,7 @@ def main(argv):
     fn = {"flux_vs_field": flux_vs_field, "sweep_throughput": sweep_throughput,
           "sweep_steady": sweep_steady, "warm_start": warm_start, "channel_study": channel_study,
           "small_configs": small_configs, "net_throughput": net_throughput, "warm_detect": warm_detect,
-          "paper_droplet": paper_droplet}[name]
+          "paper_droplet": paper_droplet, "sweep_warm": sweep_warm}[name]
     print(json.dumps(fn(**_kwargs(argv[2:]))), flush=True)
 
 
