@@ -147,8 +147,8 @@ def step_line(name: str, r: dict, nsites: int, nfluid: int) -> dict:
     lattice of nsites nodes, nfluid of them fluid: rate and HBM roofline."""
     s = STORAGES[name] if name in STORAGES else VARIANTS[name][0]
     # algorithmic HBM bytes of one launch: every population read once and
-    # written once (18 values per fluid node); the two-step kernel's launch
-    # covers two time steps
+    # written once (18 values per fluid node); a multi-step kernel's launch
+    # covers two or three time steps
     steps_per_launch = STEPS_PER_LAUNCH.get(r["tile"][2], 1)
     alg_bytes = 18 * ELEM_BYTES[s] * nfluid
     launch_ms = r["step_ms"] * steps_per_launch

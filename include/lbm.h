@@ -268,8 +268,8 @@ lbm_status lbm_set_tile(lbm_sim *sim, int32_t block_x, int32_t rows_per_block);
  * run the fused kernel.  Every lbm_step call still ends on the exact state
  * after nsteps.
  * All give bitwise the same results.  Default LBM_KERNEL_FUSED.  Takes effect
- * at the next lbm_step.  With LBM_COLLIDE_TRT_GUO or LBM_ROUND_STOCHASTIC
- * only LBM_KERNEL_FUSED, LBM_KERNEL_FUSED8, LBM_KERNEL_TWO and
+ * at the next lbm_step.  With LBM_COLLIDE_TRT_GUO, LBM_COLLIDE_MRT_GUO or
+ * LBM_ROUND_STOCHASTIC only LBM_KERNEL_FUSED, LBM_KERNEL_FUSED8, LBM_KERNEL_TWO and
  * LBM_KERNEL_THREE are accepted (LBM_EINVAL otherwise) and tuned. */
 #define LBM_KERNEL_FUSED 0
 #define LBM_KERNEL_SPLIT 1
