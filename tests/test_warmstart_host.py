@@ -185,3 +185,26 @@ def test_phase_mismatch_counts_phase_flips_away_from_interfaces():
     filled[1:4, 10:18] = rl                  # rows 1-3 of a cavity turn liquid
     # rows 1-3 are at least two nodes from the film's top (row 5 / 6 interface)
     assert phase_mismatch(filled, pred, solid, G) == 3 * 8
+
+
+def test_sweep_windows_cover_every_column_once_stitched():
+    """The sweep's warm start predicts a channel of any length in 256-column
+    windows at a stride of 128 (wrapping, as the channel is periodic in x) and
+    keeps each window's middle half: stitched back, the windows' solid planes
+    give the channel's mask exactly, and the rows above the channel are solid
+    padding."""
+    from paper_0708_4182_amd.experiments import _sweep_windows
+    for r in I.sweep_table(8, 3):
+        c = I.sweep_case(r, storage=1, rounding=1)
+        c.meta["G"] = r["G"]
+        ny, nx = c.solid.shape
+        X, starts = _sweep_windows(c)
+        assert X.shape == (len(starts), 3, 256, 256) and len(starts) == -(-nx // 128)
+        full = np.full((ny, nx), -1.0)
+        for k, s0 in enumerate(starts):
+            cc = np.arange(s0 + 64, s0 + 192) % nx
+            full[:, cc] = X[k, 0, :ny, 64:192]
+        np.testing.assert_array_equal(full, c.solid.astype(float))
+        assert (X[:, 0, ny:] == 1).all()
+        np.testing.assert_allclose(X[:, 1], r["f_elec"] / WS.F_SCALE)
+        np.testing.assert_allclose(X[:, 2], (r["G"] - WS.G_MID) / WS.G_HALF)
