@@ -320,7 +320,8 @@ lbm_status lbm_load_state(lbm_sim *sim, const void *host, size_t bytes);
  * one kernel launch over the tiles of all active channels: by default one
  * workgroup per tile, or a persistent grid whose workgroups take tiles from a
  * queue (lbm_batch_set_schedule); K steps can be captured as one hipGraph and
- * replayed.
+ * replayed.  With lbm_batch_set_kernel a launch can advance the batch by two
+ * or three steps (k_stepk's temporal blocking on each channel's tiles).
  * Conventions as above; all channels share one storage format, collision
  * operator and rounding (LBM_EINVAL otherwise); all active channels advance
  * together.  A retired channel keeps its last state and is
@@ -340,8 +341,10 @@ lbm_status lbm_batch_init(lbm_batch **out, int32_t n, const lbm_params *p, const
                           const double *const *uy_init, void *dev_ws, size_t ws_bytes, void *stream);
 
 /* Advance every active channel by nsteps time steps.  With a graph length K
- * (lbm_batch_set_graph) the steps run as hipGraph replays of K persistent
- * launches, the remainder eagerly.  Asynchronous. */
+ * (lbm_batch_set_graph) the steps run as hipGraph replays of K steps, the
+ * remainder eagerly.  Under a multi-step kernel (lbm_batch_set_kernel) a run
+ * of steps is floor(steps / k) k-step launches followed by single-step
+ * launches for the rest.  Asynchronous. */
 lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
 
 /* Flux Q_i (eq. (11), L = nx_i) and mass M_i of every channel, FP64, fixed
@@ -379,13 +382,27 @@ lbm_status lbm_batch_set_tile(lbm_batch *b, int32_t block_x, int32_t rows_per_ti
  * Results are bitwise the same.  Default 0. */
 lbm_status lbm_batch_set_schedule(lbm_batch *b, int32_t persistent);
 
+/* Steps per launch: LBM_KERNEL_FUSED (one; default), LBM_KERNEL_TWO or
+ * LBM_KERNEL_THREE (two or three steps per launch from one workgroup per
+ * tile, strips of block_x - 6 or block_x - 10 output columns, block_x 512 if
+ * lbm_batch_set_tile chose 512, else 256).  Bitwise the same results as the
+ * one-step kernel, for every storage format, operator and rounding mode.
+ * LBM_EINVAL for another value.  Rebuilds the tile list; synchronizes. */
+lbm_status lbm_batch_set_kernel(lbm_batch *b, int32_t kernel);
+
+/* Current steps-per-launch setting as an LBM_KERNEL_* value (-1 for NULL). */
+int32_t lbm_batch_get_kernel(const lbm_batch *b);
+
 /* Time steps per captured graph: 0 (eager launches) or an even number up to
  * 1024.  Default 0. */
 lbm_status lbm_batch_set_graph(lbm_batch *b, int32_t steps_per_graph);
 
 /* Autotuner for the batch: schedule (persistent or one workgroup per tile) x
- * block_x x rows in {16, 32, 64}; keeps the fastest.  Trial launches write
- * only the spare buffers, so the state is unchanged. */
+ * block_x x rows in {16, 32, 64} for the one-step kernel, and the two- and
+ * three-step kernels at block_x 256 and 512 x the same rows; keeps the
+ * fastest time per step (its kernel, schedule and tile shape stay set;
+ * lbm_batch_get_kernel reports the kernel).  Trial launches write only the
+ * spare buffers, so the state is unchanged. */
 lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *block_x, int32_t *rows_per_tile,
                               float *us_per_step);
 

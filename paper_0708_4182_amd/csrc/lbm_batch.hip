@@ -41,7 +41,7 @@ struct BatchLayout {
     std::vector<Grid> g;
     std::vector<size_t> buf0, buf1, flags, rowplain;
     size_t buf_bytes_max = 0;
-    size_t descs, tiles, counters, ids, cur, out, rng, total;
+    size_t descs, tiles, tiles_k, counters, ids, cur, out, rng, total;
     size_t max_tiles;
 };
 
@@ -106,6 +106,8 @@ bool make_batch_layout(int n, const lbm_params *p, BatchLayout &L, std::string &
     off += align_up(sizeof(ChannelDesc) * n, kAlign);
     L.tiles = off;
     off += align_up(4 * L.max_tiles, kAlign);
+    L.tiles_k = off;                  // the multi-step kernel's list (wider strips: never longer)
+    off += align_up(4 * L.max_tiles, kAlign);
     L.counters = off;
     off += align_up(4 * kMaxGraphSteps, kAlign);
     L.ids = off;
@@ -136,6 +138,7 @@ struct lbm_batch {
     std::vector<uint32_t *> rowplain;
     ChannelDesc *d_desc = nullptr;
     uint32_t *d_tiles = nullptr;
+    uint32_t *d_tiles_k = nullptr;     // tiles of the multi-step kernel
     uint32_t *d_counters = nullptr;
     int32_t *d_ids = nullptr, *d_cur = nullptr;
     double *d_out = nullptr;
@@ -150,8 +153,11 @@ struct lbm_batch {
     int block_x = 256;
     int tile_rows = 32;
     int ntiles = 0;
+    int kstep = 1;                     // time steps per launch: 1, or 2 / 3 (k_batch_tilesk)
+    int kbx = 256;                     // block_x of the multi-step kernel (256 or 512)
+    int ntiles_k = 0;
     bool tiles_dirty = true;
-    std::vector<uint32_t> host_tiles;
+    std::vector<uint32_t> host_tiles, host_tiles_k;
     std::vector<int32_t> host_ids;
     int graph_steps = 0;
     int persistent = 0;                // 1: persistent queue kernel, 0: one workgroup per tile
@@ -215,18 +221,31 @@ lbm_status upload_tiles(lbm_batch *b) {
         return (int64_t)b->g[a].nx * b->g[a].ny > (int64_t)b->g[c].nx * b->g[c].ny;
     });
     b->host_tiles.clear();
+    b->host_tiles_k.clear();
+    const int kcols = b->kbx - 2 * (2 * std::max(b->kstep, 2) - 1);   // output columns of a multi-step strip
     for (int i : order) {
         const int strips = (b->g[i].nx + b->block_x - 1) / b->block_x;
         const int chunks = chunks_for(b->g[i].ny, b->tile_rows);
         b->desc[i].chunks = chunks;
         for (int t = 0; t < strips * chunks; ++t) b->host_tiles.push_back(((uint32_t)i << 16) | (uint32_t)t);
+        if (b->kstep > 1) {
+            const int kstrips = (b->g[i].nx + kcols - 1) / kcols;
+            b->desc[i].chunks_k = chunks;
+            for (int t = 0; t < kstrips * chunks; ++t)
+                b->host_tiles_k.push_back(((uint32_t)i << 16) | (uint32_t)t);
+        }
     }
-    if (b->host_tiles.size() > b->max_tiles) return bfail(b, LBM_EINVAL, "tile list overflow");
+    if (b->host_tiles.size() > b->max_tiles || b->host_tiles_k.size() > b->max_tiles)
+        return bfail(b, LBM_EINVAL, "tile list overflow");
     b->ntiles = (int)b->host_tiles.size();
+    b->ntiles_k = (int)b->host_tiles_k.size();
     BHIP(b, hipMemcpyAsync(b->d_desc, b->desc.data(), sizeof(ChannelDesc) * b->n, hipMemcpyHostToDevice,
                            b->stream));
     if (b->ntiles)
         BHIP(b, hipMemcpyAsync(b->d_tiles, b->host_tiles.data(), 4 * b->host_tiles.size(),
+                               hipMemcpyHostToDevice, b->stream));
+    if (b->ntiles_k)
+        BHIP(b, hipMemcpyAsync(b->d_tiles_k, b->host_tiles_k.data(), 4 * b->host_tiles_k.size(),
                                hipMemcpyHostToDevice, b->stream));
     // pageable sources: make sure the copies are done before the vectors change
     BHIP(b, hipStreamSynchronize(b->stream));
@@ -256,11 +275,35 @@ hipError_t enqueue_step(lbm_batch *b, hipStream_t s, int slot, int parity, int g
     return lbm::launch_batch_step(b->storage, a, b->block_x, grid, s);
 }
 
+// One launch of the multi-step kernel: kstep time steps from buffer `parity`.
+hipError_t enqueue_stepk(lbm_batch *b, hipStream_t s, int parity) {
+    lbm::BatchStepArgs a;
+    a.descs = b->d_desc;
+    a.tiles = b->d_tiles_k;
+    a.counters = b->d_counters;
+    a.ntiles = b->ntiles_k;
+    a.slot = 0;
+    a.parity = parity;
+    a.trt = b->trt ? 1 : 0;
+    a.sround = b->sround ? 1 : 0;
+    a.rng = b->d_rng;
+    return lbm::launch_batch_stepk(b->storage, a, b->kbx, b->kstep, s);
+}
+
+// Launches of nsteps steps: nsteps / kstep multi-step launches, then the rest
+// one step each; each launch flips the buffer parity.
+int launches_of(const lbm_batch *b, int64_t nsteps) {
+    return (int)(nsteps / b->kstep + nsteps % b->kstep);
+}
+
 lbm_status capture_graph(lbm_batch *b, int parity) {
     const int K = b->graph_steps, grid = persistent_grid(b);
     BHIP(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
     hipError_t e = grid > 0 ? lbm::launch_fill(b->d_counters, align_up(4 * (size_t)K, 16), b->cap) : hipSuccess;
-    for (int k = 0; k < K && e == hipSuccess; ++k) e = enqueue_step(b, b->cap, k, parity ^ (k & 1), grid);
+    int par = parity, slot = 0, left = K;
+    for (; b->kstep > 1 && left >= b->kstep && e == hipSuccess; left -= b->kstep, par ^= 1)
+        e = enqueue_stepk(b, b->cap, par);
+    for (; left > 0 && e == hipSuccess; --left, par ^= 1) e = enqueue_step(b, b->cap, slot++, par, grid);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(b->cap, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -282,6 +325,11 @@ lbm_status capture_graph(lbm_batch *b, int parity) {
 lbm_status eager_step(lbm_batch *b, int parity, int grid) {
     if (grid > 0) BHIP(b, lbm::launch_fill(b->d_counters, 16, b->stream));
     BHIP(b, enqueue_step(b, b->stream, 0, parity, grid));
+    return LBM_OK;
+}
+
+lbm_status eager_stepk(lbm_batch *b, int parity) {
+    BHIP(b, enqueue_stepk(b, b->stream, parity));
     return LBM_OK;
 }
 
@@ -355,6 +403,7 @@ lbm_status lbm_batch_init(lbm_batch **out, int32_t n, const lbm_params *p, const
     char *ws = (char *)dev_ws;
     b->d_desc = (ChannelDesc *)(ws + L.descs);
     b->d_tiles = (uint32_t *)(ws + L.tiles);
+    b->d_tiles_k = (uint32_t *)(ws + L.tiles_k);
     b->d_counters = (uint32_t *)(ws + L.counters);
     b->d_ids = (int32_t *)(ws + L.ids);
     b->d_cur = (int32_t *)(ws + L.cur);
@@ -437,11 +486,18 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps) {
     int64_t left = nsteps;
     const int K = b->graph_steps;
     if (K > 0) {
+        const int flip = launches_of(b, K) & 1;   // parity change of one replay
         while (left >= K) {
             if (!b->gexec[b->parity] && (st = capture_graph(b, b->parity)) != LBM_OK) return st;
             BHIP(b, hipGraphLaunch(b->gexec[b->parity], b->stream));
-            left -= K;   // K is even: the parity is unchanged
+            b->parity ^= flip;
+            left -= K;
         }
+    }
+    while (b->kstep > 1 && left >= b->kstep) {
+        if ((st = eager_stepk(b, b->parity)) != LBM_OK) return st;
+        b->parity ^= 1;
+        left -= b->kstep;
     }
     while (left > 0) {
         if ((st = eager_step(b, b->parity, grid)) != LBM_OK) return st;
@@ -571,6 +627,7 @@ lbm_status lbm_batch_set_tile(lbm_batch *b, int32_t block_x, int32_t rows) {
         return bfail(b, LBM_EINVAL, "block_x must be 64, 128, 256 or 512");
     if (rows < 8) return bfail(b, LBM_EINVAL, "rows_per_tile must be >= 8");
     b->block_x = block_x;
+    b->kbx = block_x == 512 ? 512 : 256;
     b->tile_rows = rows;
     return upload_tiles(b);
 }
@@ -581,6 +638,28 @@ lbm_status lbm_batch_set_schedule(lbm_batch *b, int32_t persistent) {
     b->persistent = persistent ? 1 : 0;
     drop_graphs(b);
     return LBM_OK;
+}
+
+lbm_status lbm_batch_set_kernel(lbm_batch *b, int32_t kernel) {
+    lbm_status st = busable(b);
+    if (st) return st;
+    const int k = kernel == LBM_KERNEL_FUSED ? 1 : kernel == LBM_KERNEL_TWO ? 2 : kernel == LBM_KERNEL_THREE ? 3 : 0;
+    if (!k) return bfail(b, LBM_EINVAL, "kernel must be LBM_KERNEL_FUSED, LBM_KERNEL_TWO or LBM_KERNEL_THREE");
+    const int kbx = b->block_x == 512 ? 512 : 256;
+    if (k > 1) {
+        int max_lds = 0;
+        BHIP(b, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device));
+        if (lbm::stepk_lds_bytes(b->storage, kbx, k) > (size_t)max_lds)
+            return bfail(b, LBM_EINVAL, "the %d-step kernel at block_x %d needs more LDS than the device has", k, kbx);
+    }
+    b->kstep = k;
+    b->kbx = kbx;
+    return upload_tiles(b);
+}
+
+int32_t lbm_batch_get_kernel(const lbm_batch *b) {
+    if (!b) return -1;
+    return b->kstep == 1 ? LBM_KERNEL_FUSED : b->kstep == 2 ? LBM_KERNEL_TWO : LBM_KERNEL_THREE;
 }
 
 lbm_status lbm_batch_set_graph(lbm_batch *b, int32_t steps_per_graph) {
@@ -605,23 +684,42 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *block_x, int3
         (void)hipEventDestroy(e0);
         return bfail(b, LBM_EDEVICE, "hipEventCreate failed");
     }
+    // candidates: the one-step kernel (both schedules, every block_x) and the
+    // multi-step kernels (one workgroup per tile, block_x 256 or 512, where the
+    // device's LDS allows), each at every chunk height; time per step
+    struct Cand { int kstep, pers, bx; };
+    std::vector<Cand> cands;
+    for (int pers = 0; pers < 2; ++pers)
+        for (int bx : kBX) cands.push_back({1, pers, bx});
+    int max_lds = 0;
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device) != hipSuccess)
+        max_lds = 0;
+    for (int k = 2; k <= 3; ++k)
+        for (int bx : {256, 512})
+            if (lbm::stepk_lds_bytes(b->storage, bx, k) <= (size_t)max_lds) cands.push_back({k, 0, bx});
     float best = 0.f;
-    int best_bx = b->block_x, best_rows = b->tile_rows, best_pers = b->persistent;
-    for (int pers = 0; pers < 2 && st == LBM_OK; ++pers)
-    for (int bx : kBX) {
+    Cand bestc{b->kstep, b->persistent, b->block_x};
+    int best_rows = b->tile_rows;
+    for (const Cand &c : cands) {
         for (int r : kRows) {
-            b->persistent = pers;
-            b->block_x = bx;
+            b->persistent = c.pers;
+            b->kstep = c.kstep;
+            b->block_x = c.bx;
+            b->kbx = c.bx == 512 ? 512 : 256;
             b->tile_rows = r;
             if ((st = upload_tiles(b)) != LBM_OK) break;
-            if (b->ntiles == 0) continue;
-            const int grid = persistent_grid(b);
+            if ((c.kstep > 1 ? b->ntiles_k : b->ntiles) == 0) continue;
+            const int grid = c.kstep > 1 ? 0 : persistent_grid(b);
             // trial launches read the current buffers and write the spare ones
-            if ((st = eager_step(b, b->parity, grid)) != LBM_OK) break;
+            if ((st = c.kstep > 1 ? eager_stepk(b, b->parity) : eager_step(b, b->parity, grid)) != LBM_OK) break;
             hipError_t e = hipEventRecord(e0, b->stream);
             for (int k = 0; k < reps && e == hipSuccess; ++k) {
-                if (grid > 0) e = lbm::launch_fill(b->d_counters, 16, b->stream);
-                if (e == hipSuccess) e = enqueue_step(b, b->stream, 0, b->parity, grid);
+                if (c.kstep > 1) {
+                    e = enqueue_stepk(b, b->stream, b->parity);
+                } else {
+                    if (grid > 0) e = lbm::launch_fill(b->d_counters, 16, b->stream);
+                    if (e == hipSuccess) e = enqueue_step(b, b->stream, 0, b->parity, grid);
+                }
             }
             if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -631,12 +729,11 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *block_x, int3
                 st = bfail(b, LBM_EDEVICE, "batch autotune trial failed: %s", hipGetErrorString(e));
                 break;
             }
-            const float us = 1000.f * ms / (float)reps;
+            const float us = 1000.f * ms / (float)(reps * c.kstep);
             if (best == 0.f || us < best) {
                 best = us;
-                best_bx = bx;
+                bestc = c;
                 best_rows = r;
-                best_pers = pers;
             }
         }
         if (st != LBM_OK) break;
@@ -644,11 +741,13 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *block_x, int3
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != LBM_OK) return st;
-    b->block_x = best_bx;
+    b->kstep = bestc.kstep;
+    b->persistent = bestc.pers;
+    b->block_x = bestc.bx;
+    b->kbx = bestc.bx == 512 ? 512 : 256;
     b->tile_rows = best_rows;
-    b->persistent = best_pers;
     if ((st = upload_tiles(b)) != LBM_OK) return st;
-    if (block_x) *block_x = best_bx;
+    if (block_x) *block_x = bestc.bx;
     if (rows) *rows = best_rows;
     if (us_per_step) *us_per_step = best;
     return LBM_OK;

@@ -66,7 +66,7 @@ struct ChannelDesc {
     Grid g;
     Model m;
     int32_t chunks;            // row chunks per strip
-    int32_t pad;
+    int32_t chunks_k;          // row chunks per strip of the multi-step batch kernel
     const void *buf[2];        // population buffers A and B
     const uint16_t *flags;
     const uint32_t *rowplain;  // bit y: every node of row y has the plain flag word (see lbm_kernels.hip)
@@ -122,6 +122,10 @@ hipError_t launch_moments(int storage, const void *src, const uint16_t *flags, c
 // queue (counter a.slot); grid <= 0: one workgroup per tile (no counter).
 hipError_t launch_batch_step(int storage, const BatchStepArgs &a, int block_x, int grid, hipStream_t s);
 int batch_blocks_per_cu(int storage, int block_x, bool trt, bool sr);
+// The batched step with k = 2 or 3 time steps per launch (k_batch_tilesk), one
+// workgroup per tile of a.tiles (strips of block_x - 2(2k - 1) columns,
+// ChannelDesc::chunks_k chunks per strip); block_x 256 or 512.
+hipError_t launch_batch_stepk(int storage, const BatchStepArgs &a, int block_x, int k, hipStream_t s);
 // Per-channel FP64 reduction of channels ids[0..n): out[4*k] = Q, out[4*k+1] =
 // mass, out[4*k+2] = bad nodes, for the buffer index cur[ids[k]].
 hipError_t launch_batch_reduce(int storage, const ChannelDesc *descs, const int32_t *ids,

@@ -1737,6 +1737,44 @@ __global__ void __launch_bounds__(512) k_batch_tiles(const ChannelDesc *__restri
                           mix);
 }
 
+// The batched step with K time steps per launch (the multi-step tile of
+// k_stepk on every tile of every active channel): one workgroup per tile,
+// tiles mapped to XCDs in contiguous ranges, a tile is (channel << 16) |
+// (strip * chunks_k + chunk) with strips of BX - 2H output columns.  With
+// stochastic rounding the K steps take the step counts count .. count + K - 1
+// and the next launch reads count + K, as in k_stepk.
+template <int S, bool TRT, bool SR, int BX, int K>
+__global__ void __launch_bounds__(BX) k_batch_tilesk(const ChannelDesc *__restrict__ descs,
+                                                      const uint32_t *__restrict__ tiles, int ntiles,
+                                                      int tiles_per_xcd, int parity, uint32_t *rng) {
+    extern __shared__ char ldsk[];
+    uint32_t mix[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) mix[k] = 0u;
+    if constexpr (SR) {
+        const uint32_t count = rng[parity];
+        if (blockIdx.x == 0 && threadIdx.x == 0) rng[parity ^ 1] = count + (uint32_t)K;
+#pragma unroll
+        for (int k = 0; k < K; ++k) mix[k] = lowbias32(count + (uint32_t)k + 0x9e3779b9u);
+    }
+    const int t = (int)(blockIdx.x & 7u) * tiles_per_xcd + (int)(blockIdx.x >> 3);
+    if (t >= ntiles) return;        // uniform for the workgroup, before any barrier
+    const uint32_t packed = __builtin_amdgcn_readfirstlane(tiles[t]);
+    const ChannelDesc *d = descs + (packed >> 16);
+    StepArgs a;
+    a.src = parity ? d->buf[1] : d->buf[0];
+    a.dst = const_cast<void *>(parity ? d->buf[0] : d->buf[1]);
+    a.flags = d->flags;
+    a.g = d->g;
+    a.m = d->m;
+    const int chunks = d->chunks_k;
+    const int local = (int)(packed & 0xFFFFu);
+    const int strip = local / chunks, chunk = local - strip * chunks;
+    const int y0 = (int)(((int64_t)chunk * a.g.ny) / chunks);
+    const int y1 = (int)(((int64_t)(chunk + 1) * a.g.ny) / chunks);
+    stepk_tile<S, TRT, SR, BX, K>(a, strip * (BX - 2 * Multi<K>::H), y0, y1, (chunk & 1) == 0, ldsk, mix);
+}
+
 // Per-channel FP64 flux/mass reduction: one workgroup per channel, rows in
 // order, fixed reduction tree (bitwise reproducible).
 template <int S>
@@ -2126,6 +2164,43 @@ int batch_blocks_per_cu(int storage, int block_x, bool trt, bool sr) {
     int n = 0;
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, block_x, lds);
     return e == hipSuccess && n > 0 ? n : 1;
+}
+
+using BatchTilesKKernel = void (*)(const ChannelDesc *, const uint32_t *, int, int, int, uint32_t *);
+template <int S, int BX, int K>
+BatchTilesKKernel batchk_k16(bool trt, bool sr) {
+    return trt ? (sr ? k_batch_tilesk<S, true, true, BX, K> : k_batch_tilesk<S, true, false, BX, K>)
+               : (sr ? k_batch_tilesk<S, false, true, BX, K> : k_batch_tilesk<S, false, false, BX, K>);
+}
+template <int BX, int K>
+BatchTilesKKernel batchk_kernel_bx(int storage, bool trt, bool sr) {
+    switch (storage) {
+    case ST_F32:
+        if (sr) return nullptr;
+        return trt ? k_batch_tilesk<ST_F32, true, false, BX, K> : k_batch_tilesk<ST_F32, false, false, BX, K>;
+    case ST_F16: return batchk_k16<ST_F16, BX, K>(trt, sr);
+    case ST_BF16: return batchk_k16<ST_BF16, BX, K>(trt, sr);
+    default: return nullptr;
+    }
+}
+template <int K>
+BatchTilesKKernel batchk_kernel_k(int storage, int block_x, bool trt, bool sr) {
+    switch (block_x) {
+    case 256: return batchk_kernel_bx<256, K>(storage, trt, sr);
+    case 512: return batchk_kernel_bx<512, K>(storage, trt, sr);
+    default: return nullptr;
+    }
+}
+
+hipError_t launch_batch_stepk(int storage, const BatchStepArgs &a, int block_x, int k, hipStream_t s) {
+    BatchTilesKKernel kern = k == 2 ? batchk_kernel_k<2>(storage, block_x, a.trt != 0, a.sround != 0)
+                           : k == 3 ? batchk_kernel_k<3>(storage, block_x, a.trt != 0, a.sround != 0)
+                                    : nullptr;
+    if (!kern) return hipErrorInvalidValue;
+    const int per = (a.ntiles + 7) / 8;
+    kern<<<8 * per, block_x, stepk_lds_bytes(storage, block_x, k), s>>>(a.descs, a.tiles, a.ntiles, per, a.parity,
+                                                                       a.rng);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch_reduce(int storage, const ChannelDesc *descs, const int32_t *ids,

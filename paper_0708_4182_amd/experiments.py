@@ -45,10 +45,13 @@ def flux_vs_field(nx=1024, ny=128, fs=(0.0, 5e-4, 1e-3, 1.5e-3, 2e-3), seed=0, s
             "steps": res.steps.tolist(), "converged": res.converged.tolist(), "seconds": dt}
 
 
-def sweep_throughput(n=256, seed=0, storage=1, steps=60, warmup=20, graph=10, tune=True, rounding=1, tile=""):
+def sweep_throughput(n=256, seed=0, storage=1, steps=60, warmup=20, graph=10, tune=True, rounding=1, tile="",
+                     kernel=""):
     """The sweep table's batched step: time per step over ``steps`` steps (hipGraph
     replays of ``graph`` steps).  ``tile`` "block_x,rows" fixes the tile (no
-    autotune trial launches, for profiler traces); else ``tune`` autotunes."""
+    autotune trial launches, for profiler traces); else ``tune`` autotunes
+    (steps per launch included).  ``kernel`` ("fused", "two", "three") then
+    fixes the steps per launch."""
     import torch
     rows = I.sweep_table(n, seed)
     cases = [I.sweep_case(r, storage=storage, rounding=rounding) for r in rows]
@@ -64,6 +67,8 @@ def sweep_throughput(n=256, seed=0, storage=1, steps=60, warmup=20, graph=10, tu
         tile = [bx, r]
     else:
         tile = None
+    if kernel:
+        b.set_kernel(kernel)
     b.set_graph(graph)
     b.step(warmup)
     b.flux()
@@ -76,7 +81,8 @@ def sweep_throughput(n=256, seed=0, storage=1, steps=60, warmup=20, graph=10, tu
     ms = e0.elapsed_time(e1) / steps
     es = {0: 4, 1: 2, 2: 2}[storage]
     return {"experiment": "sweep_throughput", "channels": n, "nodes": nodes, "fluid_nodes": fluid,
-            "storage": storage, "rounding": rounding, "tile": tile, "graph_steps": graph, "ms_per_step": ms,
+            "storage": storage, "rounding": rounding, "tile": tile, "kernel": b.kernel(), "graph_steps": graph,
+            "ms_per_step": ms,
             "mlups": nodes / (ms * 1e-3) / 1e6,
             "achieved_GBs": 18 * es * fluid / (ms * 1e-3) / 1e9}
 

@@ -31,7 +31,7 @@ SYMBOLS = ("lbm_workspace_bytes", "lbm_init", "lbm_init_device", "lbm_step", "lb
            "lbm_batch_flux", "lbm_batch_moments", "lbm_batch_profile", "lbm_batch_geometry",
            "lbm_batch_init_device",
            "lbm_batch_set_forces", "lbm_batch_retire", "lbm_batch_set_tile", "lbm_batch_set_graph",
-           "lbm_batch_set_schedule",
+           "lbm_batch_set_schedule", "lbm_batch_set_kernel", "lbm_batch_get_kernel",
            "lbm_batch_autotune", "lbm_batch_steps_done", "lbm_batch_free", "lbm_batch_last_error")
 
 
@@ -135,6 +135,9 @@ def load_library():
     lib.lbm_batch_set_tile.argtypes = [vp, C.c_int32, C.c_int32]
     lib.lbm_batch_set_graph.argtypes = [vp, C.c_int32]
     lib.lbm_batch_set_schedule.argtypes = [vp, C.c_int32]
+    lib.lbm_batch_set_kernel.argtypes = [vp, C.c_int32]
+    lib.lbm_batch_get_kernel.argtypes = [vp]
+    lib.lbm_batch_get_kernel.restype = C.c_int32
     lib.lbm_batch_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                        C.POINTER(C.c_float)]
     lib.lbm_batch_steps_done.argtypes = [vp, C.c_int32]
@@ -146,7 +149,7 @@ def load_library():
     for name in ("lbm_batch_init", "lbm_batch_step", "lbm_batch_flux", "lbm_batch_moments",
                  "lbm_batch_geometry", "lbm_batch_init_device", "lbm_batch_set_forces",
                  "lbm_batch_retire", "lbm_batch_set_tile", "lbm_batch_set_graph",
-                 "lbm_batch_set_schedule", "lbm_batch_autotune"):
+                 "lbm_batch_set_schedule", "lbm_batch_set_kernel", "lbm_batch_autotune"):
         getattr(lib, name).restype = C.c_int
     for name in ("lbm_init", "lbm_init_device", "lbm_step", "lbm_moments", "lbm_flux", "lbm_flux_static",
                  "lbm_geometry", "lbm_set_forces", "lbm_set_tile", "lbm_set_kernel", "lbm_get_tile",
@@ -465,6 +468,15 @@ class Batch:
 
     def set_schedule(self, persistent: bool):
         self._check(self.lib.lbm_batch_set_schedule(self.h, int(bool(persistent))))
+
+    def set_kernel(self, kernel: str):
+        """Steps per launch: "fused" (one), "two" or "three"."""
+        if kernel not in ("fused", "two", "three"):
+            raise ValueError(f"batch kernel must be fused, two or three, not {kernel!r}")
+        self._check(self.lib.lbm_batch_set_kernel(self.h, KERNELS[kernel]))
+
+    def kernel(self) -> str:
+        return {v: n for n, v in KERNELS.items()}[int(self.lib.lbm_batch_get_kernel(self.h))]
 
     def set_graph(self, steps_per_graph: int):
         self._check(self.lib.lbm_batch_set_graph(self.h, int(steps_per_graph)))

@@ -4,7 +4,9 @@ The batch runs every channel with the same tile code as a single lattice, so a
 channel inside the batch must be bitwise identical to the same channel run
 alone; graph replays must be bitwise identical to eager launches; retiring a
 channel freezes it.  Parity against the FP64 oracle uses the same 1e-5 bar as
-the single-lattice tests.
+the single-lattice tests.  The two- and three-step kernels (set_kernel) must
+give bitwise the one-step results, eagerly, in graphs whose length is not a
+multiple of the steps per launch, and after retiring channels.
 """
 import numpy as np
 import pytest
@@ -147,6 +149,8 @@ def test_batch_autotune_keeps_state(lbm):
     before = [b.moments(i) for i in range(len(cases))]
     bx, rows, us = b.autotune(reps=2)
     assert bx in (64, 128, 256, 512) and rows in (16, 32, 64) and us > 0
+    assert b.kernel() in ("fused", "two", "three")
+    print(f"batch autotune: {b.kernel()} block_x {bx} rows {rows}: {us:.1f} us/step")
     for i in range(len(cases)):
         for x, y in zip(b.moments(i), before[i]):
             np.testing.assert_array_equal(x, y)
@@ -173,3 +177,68 @@ def test_batch_set_forces_and_init_device(lbm):
     b.step(30)
     for x, y in zip(b.moments(2), run_single(lbm, cases[2], 30).moments()):
         np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("kernel,storage,block_x", [("two", 0, 256), ("three", 0, 512), ("two", 1, 512),
+                                                    ("three", 1, 256), ("two", 2, 256), ("three", 2, 512)])
+def test_multi_step_batch_is_bitwise_single(lbm, kernel, storage, block_x):
+    cases = small_sweep(storage=storage)
+    b = lbm.Batch(cases)
+    b.set_tile(block_x, 16)
+    b.set_kernel(kernel)
+    assert b.kernel() == kernel
+    b.step(61)     # 61 = 20 x 3 + 1 = 30 x 2 + 1: the last step runs alone
+    for i, c in enumerate(cases):
+        ref = run_single(lbm, c, 61).moments()
+        for x, y in zip(b.moments(i), ref):
+            np.testing.assert_array_equal(x, y, err_msg=f"channel {i}")
+        assert b.steps_done(i) == 61
+
+
+@pytest.mark.parametrize("kernel,graph_steps", [("two", 2), ("two", 10), ("three", 4), ("three", 10)])
+def test_multi_step_graph_equals_eager(lbm, kernel, graph_steps):
+    """Replays of graphs of k-step launches plus single-step remainders (two
+    steps under the two-step kernel is one launch: each replay flips the
+    buffers) against eager one-step launches."""
+    cases = small_sweep(n=5, seed=7)
+    eager = lbm.Batch(cases)
+    graph = lbm.Batch(cases)
+    graph.set_kernel(kernel)
+    graph.set_graph(graph_steps)
+    for rep in range(3):
+        eager.step(graph_steps)
+        graph.step(graph_steps)
+        Qe, Me = eager.flux()
+        Qg, Mg = graph.flux()
+        np.testing.assert_array_equal(Qe, Qg)
+        np.testing.assert_array_equal(Me, Mg)
+    eager.step(13)
+    graph.step(13)
+    for i in range(len(cases)):
+        for x, y in zip(eager.moments(i), graph.moments(i)):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_multi_step_retire(lbm):
+    cases = small_sweep(n=5, seed=11)
+    b = lbm.Batch(cases)
+    b.set_kernel("three")
+    b.step(20)
+    frozen = {i: b.moments(i) for i in (0, 4)}
+    b.retire([1, 0, 0, 0, 1])
+    b.step(22)
+    for i in (0, 4):
+        for x, y in zip(b.moments(i), frozen[i]):
+            np.testing.assert_array_equal(x, y)
+    for i in (1, 2, 3):
+        for x, y in zip(b.moments(i), run_single(lbm, cases[i], 42).moments()):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_multi_step_rejects_other_kernels(lbm):
+    b = lbm.Batch(small_sweep(n=2, seed=2))
+    for k in (1, 2, 3, 4, 7, -1):
+        assert b.lib.lbm_batch_set_kernel(b.h, k) == -1
+    b.set_kernel("two")
+    b.set_kernel("fused")
+    assert b.kernel() == "fused"

@@ -125,11 +125,13 @@ def test_mrt_kernels_bitwise_equal(lbm, storage, kernel):
             np.testing.assert_array_equal(x, y, err_msg=name)
 
 
-@pytest.mark.parametrize("persistent", [False, True])
-def test_mrt_batch_bitwise_single(lbm, persistent):
+@pytest.mark.parametrize("persistent,kernel", [(False, "fused"), (True, "fused"), (False, "two"),
+                                               (False, "three")])
+def test_mrt_batch_bitwise_single(lbm, persistent, kernel):
     cases = [mrt_case(n) for n in ("ragged37x19", "ragged130x67", "ragged300x5")]
     b = lbm.Batch(cases)
     b.set_schedule(persistent)
+    b.set_kernel(kernel)
     b.step(50)
     for i, c in enumerate(cases):
         ref = lbm.from_case(c)

@@ -170,8 +170,11 @@ def test_state_continues_the_count(lbm):
         np.testing.assert_array_equal(x, y)
 
 
-@pytest.mark.parametrize("persistent", [False, True])
-def test_batch_equals_single(lbm, persistent):
+@pytest.mark.parametrize("persistent,kernel", [(False, "fused"), (True, "fused"), (False, "two"),
+                                               (True, "three")])
+def test_batch_equals_single(lbm, persistent, kernel):
+    """The batch continues the rounding step count like a single lattice, also
+    when launches advance two or three steps (graph of 4 steps: 2 + 2 or 3 + 1)."""
     cases = []
     for name in ("ragged37x19", "ragged130x67", "ragged300x5"):
         c = CASES[name]()
@@ -179,11 +182,12 @@ def test_batch_equals_single(lbm, persistent):
         cases.append(c)
     b = lbm.Batch(cases)
     b.set_schedule(persistent)
+    b.set_kernel(kernel)
     b.set_graph(4)
-    b.step(30)
+    b.step(31)
     for i, c in enumerate(cases):
         ref = lbm.from_case(c)
-        ref.step(30)
+        ref.step(31)
         for x, y in zip(b.moments(i), ref.moments()):
             np.testing.assert_array_equal(x, y)
 

@@ -156,11 +156,13 @@ def test_trt_multi_step_bitwise_equal(lbm, storage, kernel):
             np.testing.assert_array_equal(x, y, err_msg=name)
 
 
-@pytest.mark.parametrize("persistent", [False, True])
-def test_trt_batch_bitwise_single(lbm, persistent):
+@pytest.mark.parametrize("persistent,kernel", [(False, "fused"), (True, "fused"), (False, "two"),
+                                               (False, "three")])
+def test_trt_batch_bitwise_single(lbm, persistent, kernel):
     cases = [trt_case(n) for n in ("ragged37x19", "ragged130x67", "ragged300x5")]
     b = lbm.Batch(cases)
     b.set_schedule(persistent)
+    b.set_kernel(kernel)
     b.step(50)
     for i, c in enumerate(cases):
         ref = lbm.from_case(c)
