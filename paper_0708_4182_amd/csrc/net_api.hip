@@ -82,12 +82,13 @@ struct Buffers {
     float *g_e1a, *g_cat1, *g_p1, *g_e2a, *g_cat2, *g_p2, *g_e3a, *g_cat3, *g_p3, *g_ba, *g_bb, *g_d3a, *g_d3b,
         *g_d2a, *g_d2b, *g_d1a, *g_d1b, *g_out, *y, *dz, *wt, *partial;
     float *theta, *grad, *m, *v;
-    __bf16 *wp;                      // packed bf16 weights of the matrix-core input gradient
-    __bf16 *wpf;                     // packed bf16 weights of every matrix-core forward layer
-    size_t wpoff[NLAYERS];           // (layer l at wpf + wpoff[l])
+    __bf16 *wpf;                     // packed bf16 weights of every matrix-core layer: forward
+    size_t wpoff[NLAYERS];           // layout of layer l at wpf + wpoff[l], flipped (input
+    size_t wpboff[NLAYERS];          // gradient) at wpf + wpboff[l]
     __bf16 *dzh;                     // the layer gradient rounded to bf16 (bf16 build, input gradient)
     double *loss_part, *loss_stats;
-    size_t total, partial_floats;
+    float *bpart;                    // per-workgroup partial sums of a layer's bias gradient
+    size_t total, partial_floats, bpart_floats;
 };
 
 bool layout(const Plan &P, char *base, Buffers &b) {
@@ -113,7 +114,7 @@ bool layout(const Plan &P, char *base, Buffers &b) {
     b.g_d3a = grd(c3, H4, W4); b.g_d3b = grd(c3, H4, W4); b.g_d2a = grd(c2, H2, W2); b.g_d2b = grd(c2, H2, W2);
     b.g_d1a = grd(c1, H, W); b.g_d1b = grd(c1, H, W); b.g_out = grd(P.cout, H, W); b.y = grd(P.cout, H, W);
     // scratch: the largest layer output (dz) and transposed weights
-    size_t dzmax = 0, wtmax = 0, partmax = 0;
+    size_t dzmax = 0, wtmax = 0, partmax = 0, bpartmax = 0;
     const int lh[NLAYERS] = {(int)H, (int)H, (int)H2, (int)H2, (int)H4, (int)H4, (int)H8, (int)H8,
                              (int)H4, (int)H4, (int)H2, (int)H2, (int)H, (int)H, (int)H};
     const int lw[NLAYERS] = {(int)W, (int)W, (int)W2, (int)W2, (int)W4, (int)W4, (int)W8, (int)W8,
@@ -125,22 +126,19 @@ bool layout(const Plan &P, char *base, Buffers &b) {
             const int ch = std::max(lbmnet::dw_chunks(P.B, lh[l], lw[l], P.lcin[l], P.lcout[l]),
                                     lbmnet::dw_chunks_mfma(P.B, lh[l], lw[l], P.lcin[l], P.lcout[l]));
             partmax = std::max(partmax, (size_t)ch * P.lcout[l] * P.lcin[l] * 9);
-            partmax = std::max(partmax, (size_t)lbmnet::bias_scratch(P.lcout[l]));
+            bpartmax = std::max(bpartmax, lbmnet::bias_scratch(P.B, P.lcout[l], lh[l], lw[l]));
         } else {
             partmax = std::max(partmax, (size_t)lbmnet::conv1x1_dw_scratch(P.lcin[l], P.lcout[l]));
         }
     }
-    size_t wpmax = 0;
-    for (int l = 1; l < NLAYERS; ++l)
-        if (P.lk[l] == 3) {
-            wpmax = std::max(wpmax, (size_t)9 * P.lcout[l] * lbmnet::pad32(P.lcin[l]));   // forward
-            wpmax = std::max(wpmax, (size_t)9 * P.lcin[l] * lbmnet::pad32(P.lcout[l]));   // input gradient
-        }
-    b.wp = (__bf16 *)take(2 * wpmax);
     size_t wpf = 0;
     for (int l = 0; l < NLAYERS; ++l) {
         b.wpoff[l] = wpf;
         if (l > 0 && P.lk[l] == 3) wpf += (size_t)9 * P.lcout[l] * lbmnet::pad32(P.lcin[l]);
+    }
+    for (int l = 0; l < NLAYERS; ++l) {
+        b.wpboff[l] = wpf;
+        if (l > 0 && P.lk[l] == 3) wpf += (size_t)9 * P.lcin[l] * lbmnet::pad32(P.lcout[l]);
     }
     b.wpf = (__bf16 *)take(2 * wpf);
     b.dz = (float *)take(4 * dzmax);
@@ -148,6 +146,8 @@ bool layout(const Plan &P, char *base, Buffers &b) {
     b.wt = (float *)take(4 * wtmax);
     b.partial = (float *)take(4 * partmax);
     b.partial_floats = partmax;
+    b.bpart = (float *)take(4 * bpartmax);
+    b.bpart_floats = bpartmax;
     b.theta = (float *)take(4 * P.nparams);
     b.grad = (float *)take(4 * P.nparams);
     b.m = (float *)take(4 * P.nparams);
@@ -167,7 +167,8 @@ struct lbm_net {
     int device = 0;
     int64_t adam_t = 0;
     bool have_grad = false;
-    bool packed = false;             // b.wpf holds the current parameters
+    bool packed = false;             // b.wpf holds the current parameters in the forward layout
+    bool packed_back = false;        // ... and in the flipped layout of the input gradient
     std::string err;
 };
 
@@ -302,6 +303,30 @@ hipError_t conv_fwd(lbm_net *n, int l, const View &X, const View &Y, int N, bool
     else return lbmnet::conv3x3<TA, TA>(X, w, bias, Y, N, P.lcin[l], P.lcout[l], true, n->s);
 }
 
+// Pack the bf16 weights of every matrix-core layer in one launch: the forward
+// layout, and with backward also the flipped one of the input gradients.
+lbm_status pack(lbm_net *n, bool backward) {
+    const Plan &P = n->P;
+    lbmnet::PackJobs jobs{};
+    for (int flip = 0; flip < (backward ? 2 : 1); ++flip)
+        for (int l = 1; l < NLAYERS; ++l) {
+            if (P.lk[l] != 3) continue;
+            if (jobs.n >= lbmnet::PackJobs::MAX) return nfail(n, LBM_EINVAL, "too many packing jobs");
+            lbmnet::PackJob &j = jobs.job[jobs.n++];
+            j.woff = (int64_t)P.woff[l];
+            j.out = (int64_t)(flip ? n->b.wpboff[l] : n->b.wpoff[l]);
+            j.cin = P.lcin[l];
+            j.cout = P.lcout[l];
+            j.flip = flip;
+            j.rows = flip ? P.lcin[l] : P.lcout[l];
+            j.pad = lbmnet::pad32(flip ? P.lcout[l] : P.lcin[l]);
+        }
+    NHIP(n, lbmnet::pack_all(n->b.theta, n->b.wpf, jobs, n->s));
+    n->packed = true;
+    n->packed_back = backward;
+    return LBM_OK;
+}
+
 template <class TA>
 lbm_status forward_t(lbm_net *n, const float *x, float *y, int N) {
     const Plan &P = n->P;
@@ -310,11 +335,7 @@ lbm_status forward_t(lbm_net *n, const float *x, float *y, int N) {
     layer_io(t, io);
     hipStream_t s = n->s;
     if (sizeof(TA) == 2 && !n->packed) {     // pack once per parameter update
-        for (int l = 1; l < NLAYERS; ++l)
-            if (P.lk[l] == 3)
-                NHIP(n, lbmnet::pack_weights(n->b.theta + P.woff[l], n->b.wpf + n->b.wpoff[l], P.lcin[l], P.lcout[l],
-                                             s));
-        n->packed = true;
+        if (lbm_status st = pack(n, false)) return st;
     }
     NHIP(n, (conv_fwd<TA>(n, E1A, io[E1A].X, io[E1A].Y, N, true)));
     NHIP(n, (conv_fwd<TA>(n, E1B, io[E1B].X, io[E1B].Y, N, false)));
@@ -346,23 +367,32 @@ lbm_status conv_back(lbm_net *n, int l, const LayerIO &io, int N) {
     const Plan &P = n->P;
     Buffers &b = n->b;
     const int cin = P.lcin[l], cout = P.lcout[l], H = io.Y.H, W = io.Y.W;
-    NHIP(n, lbmnet::relu_mask<TA>(io.gY, io.Y, N, cout, b.dz, sizeof(TA) == 2 ? b.dzh : nullptr, n->s));
     const bool mfma = sizeof(TA) == 2 && l != E1A;   // bf16 build, bf16 input activations
+    // dz in FP32 where an FP32 gradient kernel reads it, rounded to bf16 for the
+    // matrix-core ones, and the bias gradient's per-workgroup sums, which the
+    // weight-gradient launch finishes
+    if (lbmnet::bias_scratch(N, cout, H, W) > b.bpart_floats) return nfail(n, LBM_EINVAL, "bias scratch too small");
+    int nb = 0;
+    NHIP(n, lbmnet::relu_mask_bias<TA>(io.gY, io.Y, N, cout, mfma ? nullptr : b.dz, sizeof(TA) == 2 ? b.dzh : nullptr,
+                                       b.bpart, &nb, n->s));
+    float *db = b.grad + P.boff[l];
     const int chunks = mfma ? lbmnet::dw_chunks_mfma(N, H, W, cin, cout) : lbmnet::dw_chunks(N, H, W, cin, cout);
     if ((size_t)chunks * cout * cin * 9 > b.partial_floats) return nfail(n, LBM_EINVAL, "dW scratch too small");
     if (l == E1A)
-        NHIP(n, lbmnet::conv3x3_dw<float>(io.X, b.dz, N, cin, cout, b.partial, chunks, b.grad + P.woff[l], n->s));
+        NHIP(n, lbmnet::conv3x3_dw<float>(io.X, b.dz, N, cin, cout, b.partial, chunks, b.grad + P.woff[l], b.bpart, nb,
+                                          db, n->s));
     else if (mfma)
-        NHIP(n, lbmnet::conv3x3_dw_mfma(io.X, b.dzh, N, cin, cout, b.partial, chunks, b.grad + P.woff[l], n->s));
+        NHIP(n, lbmnet::conv3x3_dw_mfma(io.X, b.dzh, N, cin, cout, b.partial, chunks, b.grad + P.woff[l], b.bpart, nb,
+                                        db, n->s));
     else
-        NHIP(n, lbmnet::conv3x3_dw<TA>(io.X, b.dz, N, cin, cout, b.partial, chunks, b.grad + P.woff[l], n->s));
-    NHIP(n, lbmnet::bias_grad(b.dz, N, cout, H * W, b.partial, b.grad + P.boff[l], n->s));
+        NHIP(n, lbmnet::conv3x3_dw<TA>(io.X, b.dz, N, cin, cout, b.partial, chunks, b.grad + P.woff[l], b.bpart, nb, db,
+                                       n->s));
     if (io.has_gx) {
         const View dz = view(b.dz, cout, H, W, cout, 0, 4);
         if (sizeof(TA) == 2) {
             // bf16 build: matrix cores, dz (rounded to bf16 by relu_mask) and W rounded to bf16
             const View dzh = view(b.dzh, cout, H, W, cout, 0, 2);
-            NHIP(n, lbmnet::conv3x3_mfma_dx(dzh, b.theta + P.woff[l], io.gX, N, cin, cout, b.wp, n->s));
+            NHIP(n, lbmnet::conv3x3_mfma_dx_packed(dzh, b.wpf + b.wpboff[l], io.gX, N, cin, cout, n->s));
         } else {
             NHIP(n, lbmnet::flip_transpose(b.theta + P.woff[l], b.wt, cin, cout, n->s));
             NHIP(n, (lbmnet::conv3x3<float, float>(dz, b.wt, nullptr, io.gX, N, cout, cin, false, n->s)));
@@ -376,7 +406,9 @@ lbm_status gradient_t(lbm_net *n, const float *x, const float *tgt, const uint8_
     const Plan &P = n->P;
     Buffers &b = n->b;
     hipStream_t s = n->s;
-    lbm_status st = forward_t<TA>(n, x, b.y, N);
+    lbm_status st;
+    if (sizeof(TA) == 2 && !(n->packed && n->packed_back) && (st = pack(n, true))) return st;
+    st = forward_t<TA>(n, x, b.y, N);
     if (st) return st;
     const int HW = P.H * P.W;
     NHIP(n, lbmnet::loss_and_grad(b.y, tgt, fluid, N, P.cout, HW, b.loss_part, b.loss_stats, b.g_out, s));
@@ -474,6 +506,7 @@ lbm_status lbm_net_set_params(lbm_net *n, const float *host, int64_t count) {
     if (!n || !host) return LBM_EINVAL;
     if (count != (int64_t)n->P.nparams) return nfail(n, LBM_EINVAL, "expected %zu parameters", n->P.nparams);
     n->packed = false;
+    n->packed_back = false;
     NHIP(n, hipMemcpyAsync(n->b.theta, host, 4 * n->P.nparams, hipMemcpyHostToDevice, n->s));
     NHIP(n, lbmnet::zero(n->b.m, n->P.nparams, n->s));
     NHIP(n, lbmnet::zero(n->b.v, n->P.nparams, n->s));
@@ -523,6 +556,7 @@ lbm_status lbm_net_adam(lbm_net *n, float lr, float b1, float b2, float eps) {
     const double c1 = 1.0 - std::pow((double)b1, (double)n->adam_t);
     const double c2 = 1.0 - std::pow((double)b2, (double)n->adam_t);
     n->packed = false;
+    n->packed_back = false;
     NHIP(n, lbmnet::adam(n->b.theta, n->b.grad, n->b.m, n->b.v, (int)n->P.nparams, lr, b1, b2, eps, (float)c1,
                          (float)c2, n->s));
     n->have_grad = false;

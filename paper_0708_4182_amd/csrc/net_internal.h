@@ -23,35 +23,49 @@ hipError_t conv3x3(const View &in, const float *w, const float *bias, const View
 // packed to bf16 [tap][cout][cin rounded up to 32] in wp (9 * cout * pad32(cin)
 // values), then the convolution accumulates bf16 products in FP32.
 int pad32(int c);
-hipError_t conv3x3_mfma(const View &in, const float *w, const float *bias, const View &out, int N, int cin,
-                        int cout, bool relu, __bf16 *wp, hipStream_t s);
-// The two halves of conv3x3_mfma: packing alone, and the convolution on
-// weights packed earlier (the network keeps its packed weights until the
-// parameters change).
-hipError_t pack_weights(const float *w, __bf16 *wp, int cin, int cout, hipStream_t s);
+// The convolution on weights packed by pack_all (the network keeps its packed
+// weights until the parameters change).
 hipError_t conv3x3_mfma_packed(const View &in, const __bf16 *wp, const float *bias, const View &out, int N,
                                int cin, int cout, bool relu, hipStream_t s);
-// Input gradient of a 3x3 layer on matrix cores: dz is the layer gradient
-// already rounded to bf16, the weights are rounded to bf16 as they are packed;
-// wp holds 9 * cin * pad32(cout) bf16.
-hipError_t conv3x3_mfma_dx(const View &dz, const float *w, const View &dx, int N, int cin, int cout, __bf16 *wp,
-                           hipStream_t s);
+// Packing jobs of one launch (k_pack_all): the weights of a 3x3 layer at
+// theta + woff, [cout][cin][9] FP32, rounded to bf16 at base + out in the
+// forward layout [t][co][pad32(cin)] (flip = 0, rows = cout, pad = pad32(cin))
+// or flipped for the input gradient, [t][ci][pad32(cout)] with tap 8 - t
+// (flip = 1, rows = cin, pad = pad32(cout)).
+struct PackJob {
+    int64_t woff, out;
+    int32_t cin, cout, rows, pad, flip, unused;
+};
+struct PackJobs {
+    static constexpr int MAX = 32;
+    int32_t n, unused;
+    PackJob job[MAX];
+};
+hipError_t pack_all(const float *theta, __bf16 *base, const PackJobs &jobs, hipStream_t s);
+// The input gradient on weights packed (flipped) by pack_all.
+hipError_t conv3x3_mfma_dx_packed(const View &dz, const __bf16 *wp, const View &dx, int N, int cin, int cout,
+                                  hipStream_t s);
 hipError_t flip_transpose(const float *w, float *wt, int cin, int cout, hipStream_t s);
 int dw_chunks(int N, int H, int W, int cin, int cout);
 // The weight gradient on matrix cores (bf16 activations x, the layer gradient
 // dz already rounded to bf16), and its chunk count (partials hold chunks *
-// cout * cin * 9 floats).
+// cout * cin * 9 floats).  Both weight-gradient launchers also finish the
+// layer's bias gradient, db[c] = sum of the nb partial sums bpart[c * nb ...]
+// that relu_mask_bias left (skipped when bpart is NULL).
 int dw_chunks_mfma(int N, int H, int W, int cin, int cout);
 hipError_t conv3x3_dw_mfma(const View &x, const __bf16 *dz, int N, int cin, int cout, float *partial, int chunks,
-                           float *dw, hipStream_t s);
+                           float *dw, const float *bpart, int nb, float *db, hipStream_t s);
 template <class TI>
 hipError_t conv3x3_dw(const View &x, const float *dz, int N, int cin, int cout, float *partial, int chunks,
-                      float *dw, hipStream_t s);
-// floats of scratch bias_grad needs for C channels
-int bias_scratch(int C);
-hipError_t bias_grad(const float *dz, int N, int C, int HW, float *part, float *db, hipStream_t s);
+                      float *dw, const float *bpart, int nb, float *db, hipStream_t s);
+// Layer gradient through the ReLU, dz = g * (y > 0), written in FP32 (dz) and/or
+// rounded to bf16 (dzh) (either may be NULL), and the first pass of the bias
+// gradient: per-workgroup sums of dz in part (bias_scratch(N, C, H, W) floats
+// at most), *nparts of them per channel, contiguous by channel.
+size_t bias_scratch(int N, int C, int H, int W);
 template <class TA>
-hipError_t relu_mask(const View &g, const View &y, int N, int C, float *dz, __bf16 *dzh, hipStream_t s);
+hipError_t relu_mask_bias(const View &g, const View &y, int N, int C, float *dz, __bf16 *dzh, float *part,
+                          int *nparts, hipStream_t s);
 template <class TA>
 hipError_t pool(const View &in, const View &out, int N, int C, hipStream_t s);
 hipError_t pool_back_acc(const View &dy, const View &dx, int N, int C, hipStream_t s);

@@ -107,19 +107,25 @@ __global__ void k_flip_transpose(const float *__restrict__ w, float *__restrict_
 
 // ------------------------------------------------------- weight gradient
 // dW[co][ci][t] = sum over samples and pixels of dz[co](p) x[ci](p + shift t).
-// Workgroup (chunk, co block of 16, ci block of 16) accumulates over the tiles
-// of its chunk; thread t owns (co = t / 16, ci = t % 16) and all 9 taps.  For
-// each output row it walks the three staged input rows with a sliding window
-// of 3 values, so one dz read and three x reads feed 9 FMAs.  Channel strides
-// in LDS are odd, so the 16 ci (and 4 co) of a wave hit distinct banks.
-// Partials [chunk][co][ci][tap] are summed in chunk order by k_sum_partials.
-constexpr int DW_CO = 16, DW_CI = 16;
+// Workgroup (chunk, co block of CO_B, ci block of CI_B) accumulates over the
+// tiles of its chunk; thread t owns (co, ci) = ((t / CI_B) % CO_B, t % CI_B),
+// all 9 taps and the output rows of part t / (CO_B CI_B) of PS parts of the
+// tile.  For each output row it walks the three staged input rows with a
+// sliding window of 3 values, so one dz read and three x reads feed 9 FMAs.
+// Channel strides in LDS are odd, so the ci (and co) of a wave hit distinct
+// banks.  The PS row parts are added in order at the end.  Partials
+// [chunk][co][ci][tap] are summed in chunk order by k_sum_grads.  16 x 16 x 1
+// in general; 32 x 4 x 2 for the first layer (three input planes), which
+// would leave 13 of 16 threads idle in the general shape.
 constexpr int XS_STRIDE = (TH + 2) * (TW + 2) + 1, DS_STRIDE = TH * TW + 1;
 
-template <class TI>
+template <class TI, int CO_B, int CI_B, int PS>
 __global__ void __launch_bounds__(256) k_conv3x3_dw(View x, const float *__restrict__ dz, int N, int cin,
                                                     int cout, int tiles_per_chunk,
                                                     float *__restrict__ partial) {
+    static_assert(CO_B * CI_B * PS == 256 && TH % PS == 0, "thread mapping");
+    static_assert((PS - 1) * 9 * CO_B * CI_B <= CO_B * DS_STRIDE, "row-part sums fit in the dz stage");
+    constexpr int DW_CO = CO_B, DW_CI = CI_B, ROWS = TH / PS;
     __shared__ float xs[DW_CI * XS_STRIDE];
     __shared__ float ds[DW_CO * DS_STRIDE];
     const int H = x.H, W = x.W;
@@ -127,7 +133,7 @@ __global__ void __launch_bounds__(256) k_conv3x3_dw(View x, const float *__restr
     const int ntiles = N * tiles_x * tiles_y;
     const int chunk = blockIdx.x, co0 = blockIdx.y * DW_CO, ci0 = blockIdx.z * DW_CI;
     const int tid = threadIdx.x;
-    const int my_co = tid / DW_CI, my_ci = tid % DW_CI;
+    const int my_co = (tid / DW_CI) % DW_CO, my_ci = tid % DW_CI, part = tid / (DW_CO * DW_CI);
     float acc[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) acc[t] = 0.f;
@@ -155,7 +161,7 @@ __global__ void __launch_bounds__(256) k_conv3x3_dw(View x, const float *__restr
         __syncthreads();
         const float *__restrict__ xc = xs + my_ci * XS_STRIDE;
         const float *__restrict__ dc = ds + my_co * DS_STRIDE;
-        for (int py = 0; py < TH; ++py) {
+        for (int py = part * ROWS; py < (part + 1) * ROWS; ++py) {
             const float *r0 = xc + py * (TW + 2), *r1 = r0 + (TW + 2), *r2 = r1 + (TW + 2);
             float a0 = r0[0], a1 = r0[1], b0 = r1[0], b1 = r1[1], c0 = r2[0], c1 = r2[1];
 #pragma unroll 8
@@ -170,116 +176,144 @@ __global__ void __launch_bounds__(256) k_conv3x3_dw(View x, const float *__restr
         }
         __syncthreads();
     }
+    if constexpr (PS > 1) {
+        constexpr int Q = DW_CO * DW_CI;
+        const int q = tid % Q;
+        if (part > 0)
+#pragma unroll
+            for (int t = 0; t < 9; ++t) ds[((part - 1) * 9 + t) * Q + q] = acc[t];
+        __syncthreads();
+        if (part > 0) return;
+        for (int k = 1; k < PS; ++k)
+#pragma unroll
+            for (int t = 0; t < 9; ++t) acc[t] += ds[((k - 1) * 9 + t) * Q + q];
+    }
     if (ci0 + my_ci >= cin || co0 + my_co >= cout) return;
     float *__restrict__ dst = partial + (((size_t)chunk * cout + co0 + my_co) * cin + ci0 + my_ci) * 9;
 #pragma unroll
     for (int t = 0; t < 9; ++t) dst[t] = acc[t];
 }
 
-// out[i] = sum over k of partial[k][i] (deterministic): eight running sums
-// over k = j mod 8, so eight loads are in flight, then added in a fixed tree.
-__global__ void k_sum_partials(const float *__restrict__ partial, int nchunks, int n, float *__restrict__ out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    int k = 0;
-    for (; k + 8 <= nchunks; k += 8) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) s[j] += partial[(size_t)(k + j) * n + i];
-    }
-#pragma unroll
-    for (int j = 0; j < 7; ++j)
-        if (k + j < nchunks) s[j] += partial[(size_t)(k + j) * n + i];
-    out[i] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
-}
-
-// db[co] = sum of dz[n][co][...] over samples and pixels, in two passes with a
-// fixed order: workgroup (co, b) sums its contiguous share of the N * HW
-// values of channel co (fixed tree), then one thread per channel adds the
-// BIAS_PARTS shares in order.
-constexpr int BIAS_PARTS = 64;
-__global__ void __launch_bounds__(256) k_bias_partial(const float *__restrict__ dz, int N, int C, int HW,
-                                                      float *__restrict__ part) {
+// The two gradient sums of a 3x3 layer in one launch, each in a fixed order:
+// dw[i] = sum over k < nchunks of partial[k n + i] (i < n), and, in the
+// workgroups after the first wblocks, db[c] = sum over k < nb of
+// bpart[c nb + k] (c < C; skipped when bpart is NULL).  A workgroup covers OB
+// outputs with G = 256 / OB threads each: thread (o, g) adds the terms k = g,
+// g + G, ... in eight running sums (eight loads in flight), those are added in
+// a fixed tree, then the G thread sums in order of g.
+template <int OB>
+__global__ void __launch_bounds__(256) k_sum_grads(const float *__restrict__ partial, int nchunks, int n,
+                                                   float *__restrict__ dw, const float *__restrict__ bpart, int nb,
+                                                   int C, float *__restrict__ db, int wblocks) {
+    constexpr int G = 256 / OB;
     __shared__ float sh[256];
-    const int co = blockIdx.x, b = blockIdx.y;
-    const size_t total = (size_t)N * HW, len = (total + BIAS_PARTS - 1) / BIAS_PARTS;
-    const size_t e0 = (size_t)b * len, e1 = min(total, e0 + len);
-    float s = 0.f;
-    size_t e = e0 + threadIdx.x;
-    if (e < e1) {
-        // (sample, pixel) of e, advanced by 256 each pass instead of divided
-        uint32_t n = (uint32_t)(e / (size_t)HW), p = (uint32_t)(e % (size_t)HW);
-        for (; e < e1; e += 256) {
-            s += dz[((size_t)n * C + co) * HW + p];
-            p += 256;
-            while (p >= (uint32_t)HW) { p -= (uint32_t)HW; ++n; }
+    const int o = threadIdx.x % OB, g = threadIdx.x / OB;
+    const bool bias = (int)blockIdx.x >= wblocks;
+    const int i = (bias ? (int)blockIdx.x - wblocks : (int)blockIdx.x) * OB + o;
+    const int count = bias ? nb : nchunks;
+    const bool live = bias ? i < C : i < n;
+    // term k of output i
+    const float *base = bias ? bpart + (size_t)i * nb : partial + i;
+    const size_t step = bias ? 1 : (size_t)n;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (live) {
+        int k = g;
+        for (; k + 7 * G < count; k += 8 * G) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s[j] += base[(size_t)(k + j * G) * step];
         }
+#pragma unroll
+        for (int j = 0; j < 7; ++j)
+            if (k + j * G < count) s[j] += base[(size_t)(k + j * G) * step];
     }
-    sh[threadIdx.x] = s;
+    sh[threadIdx.x] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
     __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[(size_t)co * BIAS_PARTS + b] = sh[0];
+    if (g != 0 || !live) return;
+    float t = sh[o];
+    for (int q = 1; q < G; ++q) t += sh[q * OB + o];
+    if (bias) db[i] = t;
+    else dw[i] = t;
 }
 
-__global__ void k_bias_final(const float *__restrict__ part, int C, float *__restrict__ db) {
-    const int co = blockIdx.x * blockDim.x + threadIdx.x;
-    if (co >= C) return;
-    float s = 0.f;
-    for (int b = 0; b < BIAS_PARTS; ++b) s += part[(size_t)co * BIAS_PARTS + b];
-    db[co] = s;
+// Sum of v over the workgroup (256 threads), the same tree on every run: a
+// butterfly within each wave, then the four wave sums in order.  Every thread
+// of the workgroup must call it.
+__device__ __forceinline__ float wg_sum256(float v, float *sh4) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sh4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (sh4[0] + sh4[1]) + (sh4[2] + sh4[3]);
 }
 
-// dz = g * (y > 0) (ReLU derivative from the stored output), dense fp32 out.
+// Layer gradient through the ReLU, dz = g * (y > 0) (the derivative from the
+// stored output), with the bias gradient's first pass folded in: workgroup
+// (b, c, n) covers a block of pixels of plane (n, c) and writes the sum of its
+// dz values to part[(c * N + n) * gridDim.x + b]; k_sum_grads adds those in
+// a fixed order.  dz is written in FP32 (dz, when non-null: the FP32 weight
+// and input gradients) and rounded to bf16 (dzh, when non-null: the matrix-
+// core gradients).  Grids are (pixel blocks, channel, sample), so a thread
+// finds its element without 64-bit divisions.
 template <class TA>
-// Elementwise kernels run on (pixel blocks, channel, sample) grids, so that a
-// thread finds its element without 64-bit divisions.
-__global__ void k_relu_mask(View g, View y, int N, int C, float *__restrict__ dz, __bf16 *__restrict__ dzh) {
+__global__ void __launch_bounds__(256) k_relu_mask(View g, View y, int N, int C, float *__restrict__ dz,
+                                                   __bf16 *__restrict__ dzh, float *__restrict__ part) {
+    __shared__ float sh4[4];
     const uint32_t HW = (uint32_t)y.H * (uint32_t)y.W;
     const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= HW) return;
     const uint32_t c = blockIdx.y, n = blockIdx.z;
-    const size_t r = (size_t)c * HW + p, i = ((size_t)n * C + c) * HW + p;
-    const float gv = static_cast<const float *>(g.p)[n * g.bs + r];
-    const float yv = tof(static_cast<const TA *>(y.p)[n * y.bs + r]);
-    const float v = yv > 0.f ? gv : 0.f;
-    dz[i] = v;
-    if (dzh) dzh[i] = (__bf16)v;
+    float v = 0.f;
+    if (p < HW) {
+        const size_t r = (size_t)c * HW + p, i = ((size_t)n * C + c) * HW + p;
+        const float gv = static_cast<const float *>(g.p)[n * g.bs + r];
+        const float yv = tof(static_cast<const TA *>(y.p)[n * y.bs + r]);
+        v = yv > 0.f ? gv : 0.f;
+        if (dz) dz[i] = v;
+        if (dzh) dzh[i] = (__bf16)v;
+    }
+    const float t = wg_sum256(v, sh4);
+    if (threadIdx.x == 0) part[((size_t)c * N + n) * gridDim.x + blockIdx.x] = t;
 }
 
 // The same, four pixels per thread (HW % 4 == 0 and aligned planes): 16-byte
 // FP32 and 8-byte bf16 accesses.
 template <class TA>
-__global__ void k_relu_mask4(View g, View y, int N, int C, float *__restrict__ dz, __bf16 *__restrict__ dzh) {
+__global__ void __launch_bounds__(256) k_relu_mask4(View g, View y, int N, int C, float *__restrict__ dz,
+                                                    __bf16 *__restrict__ dzh, float *__restrict__ part) {
+    __shared__ float sh4[4];
     const uint32_t HW = (uint32_t)y.H * (uint32_t)y.W;
     const uint32_t p = 4u * (blockIdx.x * blockDim.x + threadIdx.x);
-    if (p >= HW) return;
     const uint32_t c = blockIdx.y, n = blockIdx.z;
-    const size_t r = (size_t)c * HW + p, i = ((size_t)n * C + c) * HW + p;
-    const float4 gv = *reinterpret_cast<const float4 *>(static_cast<const float *>(g.p) + n * g.bs + r);
-    float yv[4];
-    if constexpr (sizeof(TA) == 2) {
-        const uint2 yb = *reinterpret_cast<const uint2 *>(static_cast<const TA *>(y.p) + n * y.bs + r);
-        yv[0] = __uint_as_float(yb.x << 16);
-        yv[1] = __uint_as_float(yb.x & 0xffff0000u);
-        yv[2] = __uint_as_float(yb.y << 16);
-        yv[3] = __uint_as_float(yb.y & 0xffff0000u);
-    } else {
-        const float4 yf = *reinterpret_cast<const float4 *>(static_cast<const TA *>(y.p) + n * y.bs + r);
-        yv[0] = yf.x; yv[1] = yf.y; yv[2] = yf.z; yv[3] = yf.w;
+    float sum = 0.f;
+    if (p < HW) {
+        const size_t r = (size_t)c * HW + p, i = ((size_t)n * C + c) * HW + p;
+        const float4 gv = *reinterpret_cast<const float4 *>(static_cast<const float *>(g.p) + n * g.bs + r);
+        float yv[4];
+        if constexpr (sizeof(TA) == 2) {
+            const uint2 yb = *reinterpret_cast<const uint2 *>(static_cast<const TA *>(y.p) + n * y.bs + r);
+            yv[0] = __uint_as_float(yb.x << 16);
+            yv[1] = __uint_as_float(yb.x & 0xffff0000u);
+            yv[2] = __uint_as_float(yb.y << 16);
+            yv[3] = __uint_as_float(yb.y & 0xffff0000u);
+        } else {
+            const float4 yf = *reinterpret_cast<const float4 *>(static_cast<const TA *>(y.p) + n * y.bs + r);
+            yv[0] = yf.x; yv[1] = yf.y; yv[2] = yf.z; yv[3] = yf.w;
+        }
+        const float4 v = make_float4(yv[0] > 0.f ? gv.x : 0.f, yv[1] > 0.f ? gv.y : 0.f, yv[2] > 0.f ? gv.z : 0.f,
+                                     yv[3] > 0.f ? gv.w : 0.f);
+        sum = (v.x + v.y) + (v.z + v.w);
+        if (dz) *reinterpret_cast<float4 *>(dz + i) = v;
+        if (dzh) {
+            const __bf16 h0 = (__bf16)v.x, h1 = (__bf16)v.y, h2 = (__bf16)v.z, h3 = (__bf16)v.w;
+            uint2 o;
+            o.x = (uint32_t)__builtin_bit_cast(unsigned short, h0) |
+                  (uint32_t)__builtin_bit_cast(unsigned short, h1) << 16;
+            o.y = (uint32_t)__builtin_bit_cast(unsigned short, h2) |
+                  (uint32_t)__builtin_bit_cast(unsigned short, h3) << 16;
+            *reinterpret_cast<uint2 *>(dzh + i) = o;
+        }
     }
-    const float4 v = make_float4(yv[0] > 0.f ? gv.x : 0.f, yv[1] > 0.f ? gv.y : 0.f, yv[2] > 0.f ? gv.z : 0.f,
-                                 yv[3] > 0.f ? gv.w : 0.f);
-    *reinterpret_cast<float4 *>(dz + i) = v;
-    if (dzh) {
-        const __bf16 h0 = (__bf16)v.x, h1 = (__bf16)v.y, h2 = (__bf16)v.z, h3 = (__bf16)v.w;
-        uint2 o;
-        o.x = (uint32_t)__builtin_bit_cast(unsigned short, h0) | (uint32_t)__builtin_bit_cast(unsigned short, h1) << 16;
-        o.y = (uint32_t)__builtin_bit_cast(unsigned short, h2) | (uint32_t)__builtin_bit_cast(unsigned short, h3) << 16;
-        *reinterpret_cast<uint2 *>(dzh + i) = o;
-    }
+    const float t = wg_sum256(sum, sh4);
+    if (threadIdx.x == 0) part[((size_t)c * N + n) * gridDim.x + blockIdx.x] = t;
 }
 
 // ------------------------------------------------------ pool / upsample
@@ -426,6 +460,7 @@ __global__ void k_conv1x1_dx(const float *__restrict__ g, const float *__restric
 // cin), in two passes with a fixed order: workgroup (pair, b) sums its
 // contiguous share of the N * HW products (fixed tree) into part[pair][b],
 // then k_pair_final adds the BIAS_PARTS shares of each pair in order.
+constexpr int BIAS_PARTS = 64;
 template <class TA>
 __global__ void __launch_bounds__(256) k_conv1x1_dw_partial(View x, const float *__restrict__ g, int N, int cin,
                                                             int cout, float *__restrict__ part) {
@@ -554,27 +589,27 @@ __global__ void k_zero(float *__restrict__ p, size_t n) {
 // channel-last ([y][x][ci], 40 bf16 per pixel so that the 16-byte fragment
 // reads of 16 consecutive pixels fall in distinct banks), with the one-pixel
 // halo (periodic x, zero y); the packed weights ([t][co][ci], see
-// k_pack_weights) likewise.
+// k_pack_all) likewise.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int MH = 8, MCI = 32, MPS = 40;
 
-// Wp[t][co][ci] (bf16, ci padded with zeros to cin_pad) from W[co][ci][t] (FP32)
-__global__ void k_pack_weights(const float *__restrict__ w, __bf16 *__restrict__ wp, int cin, int cout, int cin_pad) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 9 * cout * cin_pad) return;
-    const int ci = i % cin_pad, co = (i / cin_pad) % cout, t = i / (cin_pad * cout);
-    wp[i] = (__bf16)(ci < cin ? w[((size_t)co * cin + ci) * 9 + t] : 0.f);
-}
-
-// W'[t][ci][co] = W[co][ci][8 - t] packed as bf16 with co padded to cout_pad:
-// the weights of the input-gradient convolution in the layout above.
-__global__ void k_pack_weights_flip(const float *__restrict__ w, __bf16 *__restrict__ wp, int cin, int cout,
-                                    int cout_pad) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 9 * cin * cout_pad) return;
-    const int co = i % cout_pad, ci = (i / cout_pad) % cin, t = i / (cout_pad * cin);
-    wp[i] = (__bf16)(co < cout ? w[((size_t)co * cin + ci) * 9 + (8 - t)] : 0.f);
+// Packed bf16 weights of every 3x3 matrix-core layer in one launch (workgroup
+// row y packs job y).  Forward layout Wp[t][co][ci] from W[co][ci][t], ci
+// padded with zeros to pad; flipped layout W'[t][ci][co] = W[co][ci][8 - t],
+// co padded: the weights of the input-gradient convolution.
+__global__ void __launch_bounds__(256) k_pack_all(const float *__restrict__ theta, __bf16 *__restrict__ base,
+                                                  PackJobs jobs) {
+    const PackJob j = jobs.job[blockIdx.y];
+    const int n = 9 * j.rows * j.pad;   // rows: cout (forward) or cin (flipped)
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int k = i % j.pad, r = (i / j.pad) % j.rows, t = i / (j.pad * j.rows);
+        const float *w = theta + j.woff;
+        float v;
+        if (j.flip) v = k < j.cout ? w[((size_t)k * j.cin + r) * 9 + (8 - t)] : 0.f;   // k = co, r = ci
+        else v = k < j.cin ? w[((size_t)r * j.cin + k) * 9 + t] : 0.f;                  // k = ci, r = co
+        base[j.out + i] = (__bf16)v;
+    }
 }
 
 // Tile of k_conv3x3_mfma: MH rows x TWD columns of one sample, computed by
@@ -900,7 +935,7 @@ __global__ void __launch_bounds__(ConvTile<TWD>::NT) k_conv3x3_mfma(View in, con
 // operands of the three column shifts come from one 16-byte LDS read of the
 // staged input row plus one neighbouring dword each; each staged row r then
 // serves the dz rows r - dy of the three row shifts.  Partials
-// [chunk][co][ci][tap] are summed in chunk order by k_sum_partials.
+// [chunk][co][ci][tap] are summed in a fixed order by k_sum_grads.
 constexpr int DM_CO = 32, DM_CI = 32, DM_TR = 4, DM_TW = 32, DM_PX = DM_TR * DM_TW;
 constexpr int DM_DZS = DM_PX + 8;                 // dz channel stride (bf16)
 constexpr int DM_XR = DM_TW + 16;                 // staged x row: 8 | 32 pixels | 8, halo at 7 and 40
@@ -1159,10 +1194,18 @@ hipError_t launch_conv3x3_mfma(const View &in, const __bf16 *wp, const float *bi
                 : launch_conv3x3_mfma_t<TO, 4, 32>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, s);
 }
 
-hipError_t pack_weights(const float *w, __bf16 *wp, int cin, int cout, hipStream_t s) {
-    const int cin_pad = pad32(cin);
-    k_pack_weights<<<nblk((size_t)9 * cout * cin_pad), 256, 0, s>>>(w, wp, cin, cout, cin_pad);
+hipError_t pack_all(const float *theta, __bf16 *base, const PackJobs &jobs, hipStream_t s) {
+    if (jobs.n <= 0) return hipSuccess;
+    if (jobs.n > PackJobs::MAX) return hipErrorInvalidValue;
+    int most = 0;
+    for (int k = 0; k < jobs.n; ++k) most = std::max(most, 9 * jobs.job[k].rows * jobs.job[k].pad);
+    k_pack_all<<<dim3(std::min(nblk((size_t)most), 64u), (unsigned)jobs.n), 256, 0, s>>>(theta, base, jobs);
     return hipGetLastError();
+}
+
+hipError_t conv3x3_mfma_dx_packed(const View &dz, const __bf16 *wp, const View &dx, int N, int cin, int cout,
+                                  hipStream_t s) {
+    return launch_conv3x3_mfma<float>(dz, wp, nullptr, dx, N, cout, cin, pad32(cout), false, s);
 }
 
 hipError_t conv3x3_mfma_packed(const View &in, const __bf16 *wp, const float *bias, const View &out, int N,
@@ -1170,65 +1213,77 @@ hipError_t conv3x3_mfma_packed(const View &in, const __bf16 *wp, const float *bi
     return launch_conv3x3_mfma<__bf16>(in, wp, bias, out, N, cin, cout, pad32(cin), relu, s);
 }
 
-hipError_t conv3x3_mfma(const View &in, const float *w, const float *bias, const View &out, int N, int cin,
-                        int cout, bool relu, __bf16 *wp, hipStream_t s) {
-    const hipError_t e = pack_weights(w, wp, cin, cout, s);
-    if (e != hipSuccess) return e;
-    return conv3x3_mfma_packed(in, wp, bias, out, N, cin, cout, relu, s);
-}
-
-// Input gradient dX = conv(dz, flipped transposed W) on matrix cores: dz (the
-// bf16 copy of the layer gradient, cout planes) and the weights rounded to
-// bf16, FP32 accumulation, FP32 out.
-hipError_t conv3x3_mfma_dx(const View &dz, const float *w, const View &dx, int N, int cin, int cout, __bf16 *wp,
-                           hipStream_t s) {
-    const int cout_pad = pad32(cout);
-    k_pack_weights_flip<<<nblk((size_t)9 * cin * cout_pad), 256, 0, s>>>(w, wp, cin, cout, cout_pad);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_conv3x3_mfma<float>(dz, wp, nullptr, dx, N, cout, cin, cout_pad, false, s);
-}
-
 hipError_t flip_transpose(const float *w, float *wt, int cin, int cout, hipStream_t s) {
     k_flip_transpose<<<nblk((size_t)cin * cout * 9), 256, 0, s>>>(w, wt, cin, cout);
     return hipGetLastError();
 }
 
+namespace {
+// The first layer (at most four input planes) uses the 32 x 4 x 2 shape of
+// k_conv3x3_dw, every other layer 16 x 16 x 1.
+bool dw_small(int cin) { return cin <= 4; }
+
+// Both gradient sums of a layer (k_sum_grads): OB = 64 outputs per workgroup
+// when there are many, else 16 (more threads per output, fewer loads each).
+hipError_t sum_grads(const float *partial, int chunks, int n, float *dw, const float *bpart, int nb, int C,
+                     float *db, hipStream_t s) {
+    if (!bpart) C = 0;
+    if (n >= 64 * 512) {
+        const int wb = (n + 63) / 64;
+        k_sum_grads<64><<<wb + (C + 63) / 64, 256, 0, s>>>(partial, chunks, n, dw, bpart, nb, C, db, wb);
+    } else {
+        const int wb = (n + 15) / 16;
+        k_sum_grads<16><<<wb + (C + 15) / 16, 256, 0, s>>>(partial, chunks, n, dw, bpart, nb, C, db, wb);
+    }
+    return hipGetLastError();
+}
+}  // namespace
+
 int dw_chunks(int N, int H, int W, int cin, int cout) {
     const int ntiles = N * ((W + TW - 1) / TW) * ((H + TH - 1) / TH);
-    const int blocks = ((cout + DW_CO - 1) / DW_CO) * ((cin + DW_CI - 1) / DW_CI);
+    if (dw_small(cin)) {
+        // about 1024 workgroups of at least 2 tiles (256 workgroups of 8 tiles
+        // measured 132 us at 64 x 256 x 32 samples: too few to hide the staging)
+        const int blocks = (cout + 31) / 32;
+        return std::max(1, std::min(ntiles / 2, (1024 + blocks - 1) / blocks));
+    }
+    const int blocks = ((cout + 15) / 16) * ((cin + 15) / 16);
     // aim for >= 2048 workgroups, at least 2 tiles per chunk
-    int chunks = std::max(1, std::min(ntiles / 2, (2048 + blocks - 1) / blocks));
-    return std::max(1, chunks);
+    return std::max(1, std::min(ntiles / 2, (2048 + blocks - 1) / blocks));
 }
 
 template <class TI>
 hipError_t conv3x3_dw(const View &x, const float *dz, int N, int cin, int cout, float *partial, int chunks,
-                      float *dw, hipStream_t s) {
+                      float *dw, const float *bpart, int nb, float *db, hipStream_t s) {
     const int ntiles = N * ((x.W + TW - 1) / TW) * ((x.H + TH - 1) / TH);
     const int per = (ntiles + chunks - 1) / chunks;
-    const dim3 grid(chunks, (cout + DW_CO - 1) / DW_CO, (cin + DW_CI - 1) / DW_CI);
-    k_conv3x3_dw<TI><<<grid, 256, 0, s>>>(x, dz, N, cin, cout, per, partial);
-    hipError_t e = hipGetLastError();
+    if (dw_small(cin)) {
+        const dim3 grid(chunks, (cout + 31) / 32, 1);
+        k_conv3x3_dw<TI, 32, 4, 2><<<grid, 256, 0, s>>>(x, dz, N, cin, cout, per, partial);
+    } else {
+        const dim3 grid(chunks, (cout + 15) / 16, (cin + 15) / 16);
+        k_conv3x3_dw<TI, 16, 16, 1><<<grid, 256, 0, s>>>(x, dz, N, cin, cout, per, partial);
+    }
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int n = cout * cin * 9;
-    k_sum_partials<<<nblk(n), 256, 0, s>>>(partial, chunks, n, dw);
-    return hipGetLastError();
+    return sum_grads(partial, chunks, cout * cin * 9, dw, bpart, nb, cout, db, s);
 }
-template hipError_t conv3x3_dw<float>(const View &, const float *, int, int, int, float *, int, float *, hipStream_t);
-template hipError_t conv3x3_dw<__bf16>(const View &, const float *, int, int, int, float *, int, float *, hipStream_t);
+template hipError_t conv3x3_dw<float>(const View &, const float *, int, int, int, float *, int, float *,
+                                      const float *, int, float *, hipStream_t);
+template hipError_t conv3x3_dw<__bf16>(const View &, const float *, int, int, int, float *, int, float *,
+                                       const float *, int, float *, hipStream_t);
 
 int dw_chunks_mfma(int N, int H, int W, int cin, int cout) {
     const int ntiles = N * ((W + DM_TW - 1) / DM_TW) * ((H + DM_TR - 1) / DM_TR);
     const int blocks = ((cout + DM_CO - 1) / DM_CO) * ((cin + DM_CI - 1) / DM_CI);
-    // about 512 workgroups, at least 2 tiles per chunk: fewer chunk partials for
-    // k_sum_partials to read (training measured 3.75 ms per batch with 1024,
-    // 3.56 with 512, 3.74 with 256)
+    // about 512 workgroups, at least 2 tiles per chunk: fewer chunk partials to
+    // sum (training measured 3.75 ms per batch with 1024, 3.56 with 512, 3.74
+    // with 256, with a one-thread-per-output sum)
     return std::max(1, std::min(ntiles / 2, (512 + blocks - 1) / blocks));
 }
 
 hipError_t conv3x3_dw_mfma(const View &x, const __bf16 *dz, int N, int cin, int cout, float *partial, int chunks,
-                           float *dw, hipStream_t s) {
+                           float *dw, const float *bpart, int nb, float *db, hipStream_t s) {
     const int ntiles = N * ((x.W + DM_TW - 1) / DM_TW) * ((x.H + DM_TR - 1) / DM_TR);
     const int per = (ntiles + chunks - 1) / chunks;
     // vector staging: whole tile rows and 16-byte aligned rows of x and dz
@@ -1238,38 +1293,43 @@ hipError_t conv3x3_dw_mfma(const View &x, const __bf16 *dz, int N, int cin, int 
     const dim3 grid(chunks, (cout + DM_CO - 1) / DM_CO, (cin + DM_CI - 1) / DM_CI);
     if (vec) k_conv3x3_dw_mfma<true><<<grid, 256, 0, s>>>(x, dz, N, cin, cout, per, partial);
     else k_conv3x3_dw_mfma<false><<<grid, 256, 0, s>>>(x, dz, N, cin, cout, per, partial);
-    hipError_t e = hipGetLastError();
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int n = cout * cin * 9;
-    k_sum_partials<<<nblk(n), 256, 0, s>>>(partial, chunks, n, dw);
-    return hipGetLastError();
+    return sum_grads(partial, chunks, cout * cin * 9, dw, bpart, nb, cout, db, s);
 }
 
-int bias_scratch(int C) { return C * BIAS_PARTS; }
+namespace {
+bool relu_vec4(const View &g, const View &y, const float *dz, const __bf16 *dzh) {
+    const long long HW = (long long)y.H * y.W;
+    return HW % 4 == 0 && g.bs % 4 == 0 && y.bs % 4 == 0 && (uintptr_t)g.p % 16 == 0 && (uintptr_t)y.p % 16 == 0 &&
+           (uintptr_t)dz % 16 == 0 && (uintptr_t)dzh % 8 == 0;
+}
+}  // namespace
 
-hipError_t bias_grad(const float *dz, int N, int C, int HW, float *part, float *db, hipStream_t s) {
-    k_bias_partial<<<dim3(C, BIAS_PARTS), 256, 0, s>>>(dz, N, C, HW, part);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_bias_final<<<nblk(C, 64), 64, 0, s>>>(part, C, db);
-    return hipGetLastError();
+size_t bias_scratch(int N, int C, int H, int W) {
+    return (size_t)N * C * nblk((size_t)H * W);   // the one-pixel-per-thread grid: the larger one
 }
 
 template <class TA>
-hipError_t relu_mask(const View &g, const View &y, int N, int C, float *dz, __bf16 *dzh, hipStream_t s) {
+hipError_t relu_mask_bias(const View &g, const View &y, int N, int C, float *dz, __bf16 *dzh, float *part,
+                          int *nparts, hipStream_t s) {
     const long long HW = (long long)y.H * y.W;
-    const bool v4 = HW % 4 == 0 && g.bs % 4 == 0 && y.bs % 4 == 0 && (uintptr_t)g.p % 16 == 0 &&
-                    (uintptr_t)y.p % 16 == 0 && (uintptr_t)dz % 16 == 0 && (uintptr_t)dzh % 8 == 0;
-    if (v4) {
-        const dim3 grid((unsigned)((HW / 4 + 255) / 256), (unsigned)C, (unsigned)N);
-        k_relu_mask4<TA><<<grid, 256, 0, s>>>(g, y, N, C, dz, dzh);
+    unsigned nb;
+    if (relu_vec4(g, y, dz, dzh)) {
+        nb = (unsigned)((HW / 4 + 255) / 256);
+        k_relu_mask4<TA><<<dim3(nb, (unsigned)C, (unsigned)N), 256, 0, s>>>(g, y, N, C, dz, dzh, part);
     } else {
-        k_relu_mask<TA><<<pix_grid(y.H, y.W, C, N), 256, 0, s>>>(g, y, N, C, dz, dzh);
+        const dim3 grid = pix_grid(y.H, y.W, C, N);
+        nb = grid.x;
+        k_relu_mask<TA><<<grid, 256, 0, s>>>(g, y, N, C, dz, dzh, part);
     }
+    *nparts = (int)(nb * (unsigned)N);
     return hipGetLastError();
 }
-template hipError_t relu_mask<float>(const View &, const View &, int, int, float *, __bf16 *, hipStream_t);
-template hipError_t relu_mask<__bf16>(const View &, const View &, int, int, float *, __bf16 *, hipStream_t);
+template hipError_t relu_mask_bias<float>(const View &, const View &, int, int, float *, __bf16 *, float *, int *,
+                                          hipStream_t);
+template hipError_t relu_mask_bias<__bf16>(const View &, const View &, int, int, float *, __bf16 *, float *, int *,
+                                           hipStream_t);
 
 template <class TA>
 hipError_t pool(const View &in, const View &out, int N, int C, hipStream_t s) {
