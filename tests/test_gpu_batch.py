@@ -242,3 +242,54 @@ def test_multi_step_rejects_other_kernels(lbm):
     b.set_kernel("two")
     b.set_kernel("fused")
     assert b.kernel() == "fused"
+
+
+def test_sweep_table_in_the_bench_configuration(lbm):
+    """The 256-channel sweep table (82 M nodes) as bench.py times it: FP16
+    storage with stochastic rounding, kernel (steps per launch), schedule and
+    tile autotuned, hipGraphs of 12 steps; 24 steps.  On sampled channels (the
+    smallest, the largest and two between): bitwise equal to the same channel
+    run alone (single-lattice kernel, same rounding step counts), and, except
+    the largest (~1 M nodes, to keep the oracle's share of the test short),
+    against the FP64 oracle within twice the error of the format itself (the
+    oracle rounded to FP16 to nearest after every step, against the unrounded
+    oracle): for a value spread evenly between its two neighbours, stochastic
+    rounding's mean squared error is 1/6 of a last place squared against 1/12
+    for rounding to nearest, a ratio of sqrt(2) in the 2-norm (measured
+    1.36-1.52)."""
+    nsteps = 24
+    cases = [I.sweep_case(r, storage=1, rounding=1) for r in I.sweep_table(256, 0)]
+    b = lbm.Batch(cases)
+    b.autotune(reps=3)
+    b.set_graph(12)
+    b.step(nsteps)
+    kernel = b.kernel()
+    sizes = np.array([c.params.nx * c.params.ny for c in cases])
+    order = np.argsort(sizes, kind="stable")
+    for i in (order[0], order[len(order) // 3], order[2 * len(order) // 3], order[-1]):
+        c = cases[int(i)]
+        got = b.moments(int(i))
+        ref = lbm.from_case(c)
+        ref.step(nsteps)
+        for x, y in zip(got, ref.moments()):
+            np.testing.assert_array_equal(x, y, err_msg=f"channel {i}")
+        if i == order[-1]:
+            continue
+        p, s = c.params, c.solid
+        f = O.init(p, s, c.rho, c.ux, c.uy)
+        fr = O.round_storage(p, s, f.copy(), 1)
+        for _ in range(nsteps):
+            O.step(p, s, f, 1)
+            O.step(p, s, fr, 1)
+            O.round_storage(p, s, fr, 1)
+        exact = O.moments(p, s, f)
+        rounded = O.moments(p, s, fr)
+        gpu = tuple(a.astype(np.float64) for a in got)
+        fl = s == 0
+        er = np.linalg.norm((gpu[0] - exact[0])[fl])
+        eu = np.linalg.norm(np.hypot(gpu[1] - exact[1], gpu[2] - exact[2])[fl])
+        fr_ = np.linalg.norm((rounded[0] - exact[0])[fl])
+        fu_ = np.linalg.norm(np.hypot(rounded[1] - exact[1], rounded[2] - exact[2])[fl])
+        print(f"channel {i} {p.nx}x{p.ny} ({kernel}): 2-norm error rho {er:.2e} u {eu:.2e}; "
+              f"format's own (nearest) {fr_:.2e} / {fu_:.2e}")
+        assert er <= 2 * fr_ and eu <= 2 * fu_
