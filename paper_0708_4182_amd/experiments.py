@@ -230,9 +230,10 @@ def net_throughput(batch=32, H=64, W=256, steps=50, warmup=5, seed=0):
 
 def sweep_steady(n=256, seed=0, storage=1, max_steps=200_000, check_every=200, window=2000, rtol=None,
                  rounding=1):
-    """The 256-channel sweep table driven to steady flux in one batch (one
-    launch per step, hipGraph of check_every steps, channels retired as they
-    converge): per-channel steps, lattice updates and wall time.  16-bit
+    """The 256-channel sweep table driven to steady flux in one batch (kernel,
+    with one, two or three steps per launch, schedule and tile autotuned;
+    hipGraph of check_every steps, channels retired as they converge):
+    per-channel steps, lattice updates and wall time.  16-bit
     channels use stochastic rounding by default: with nearest rounding a
     16-bit lattice settles on an exact fixed point that carries the rounding
     bias (on the first 32 channels of the table, fluxes 18% off the FP32 ones
@@ -260,7 +261,7 @@ def sweep_steady(n=256, seed=0, storage=1, max_steps=200_000, check_every=200, w
     # the steady time of the warm-start comparison: within 1e-4 of the final flux for 5000 steps
     st = np.array([steady_time(res.history[i], res.Q[i]) for i in range(n)])
     return {"experiment": "sweep_steady", "channels": n, "storage": storage, "rounding": rounding,
-            "steady_rule": {"rtol": rtol, "averaged": average}, "tile": [bx, r],
+            "steady_rule": {"rtol": rtol, "averaged": average}, "kernel": b.kernel(), "tile": [bx, r],
             "max_steps": max_steps, "converged": int(conv.sum()),
             "steps_median": float(np.median(res.steps)), "steps_max": int(res.steps.max()),
             "lattice_updates": res.node_updates, "wall_seconds": wall,
