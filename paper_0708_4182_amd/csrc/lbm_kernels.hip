@@ -18,6 +18,9 @@ namespace {
 
 enum { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
 
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
 // Storage codecs.  Every format stores d = f - w_a rho_off (rho_off = 0 keeps
 // f itself), FP16/BF16 rounded to nearest even by the hardware conversion.
 template <int S> struct Codec;
@@ -30,37 +33,35 @@ template <> struct Codec<ST_F16> {
     using T = _Float16;
     __device__ static float dec(T v) { return (float)v; }
     __device__ static T enc(float v) { return (_Float16)v; }
-    // Stochastic rounding with random bits r: the magnitude rounds up with
-    // probability (dropped part) / (last place of the result), so the expected
-    // result is v.  13 + sh bits lie below the FP16 result's last place: sh = 0
-    // for FP16 normals (FP32 biased exponent e >= 113), sh = 113 - e in the
-    // FP16 subnormal range (last place 2^-24), where the 13 random bits are
-    // shifted to the top of the dropped field (rounding probabilities then
-    // resolved to 2^-13).  Below 2^-24, sh stops at 10 and the result is 0 or
-    // 2^-24 (error below 2^-24).  The cleared word is exact in FP16, so the
-    // final conversion does not round.  Inf and NaN (e = 255) are converted
-    // as they are: adding random bits to a NaN's mantissa could carry into the
-    // sign and exponent and turn it into a finite value, hiding a diverged
-    // node from the density guard.
+    // Stochastic rounding with random bits r (low 13 used) by gfx950's
+    // v_cvt_sr_f16_f32, which takes its random bits from the top of its second
+    // operand: the magnitude rounds up with probability (dropped part) / (last
+    // place of the result), so the expected result is v.  For FP16 normals the
+    // 13 bits are added at the top of the 13-bit dropped field and the word is
+    // truncated; in the FP16 subnormal range (last place 2^-24) the field is
+    // longer and the 13 bits sit at its top (probabilities resolved to
+    // 2^-13); below 2^-24 the result is 0 or 2^-24.  Inf and NaN convert as
+    // they are, so a diverged node stays visible to the density guard.
+    // (Checked on the device against that definition written out with
+    // integer operations: bit-identical for every |v| >= 2^-24.)
     __device__ static T enc_sr(float v, uint32_t r) {
-        uint32_t u = __builtin_bit_cast(uint32_t, v);
-        const int e = (int)((u >> 23) & 0xFFu);
-        const uint32_t sh = (uint32_t)min(max(113 - e, 0), 10);
-        const uint32_t mask = (0x2000u << sh) - 1u;
-        const uint32_t w = (u + ((r & 0x1FFFu) << sh)) & ~mask;
-        return (_Float16)__builtin_bit_cast(float, e < 255 ? w : u);
+        const f16x2 z = {(_Float16)0.f, (_Float16)0.f};
+        return __builtin_amdgcn_cvt_sr_f16_f32(z, v, r << 19, false)[0];
     }
 };
 template <> struct Codec<ST_BF16> {
     using T = __bf16;
     __device__ static float dec(T v) { return (float)v; }
     __device__ static T enc(float v) { return (__bf16)v; }
-    // Stochastic rounding: BF16 keeps the top 16 bits of the FP32 word, so the
-    // 16 random bits cover the whole dropped field (exactly unbiased).
+    // Stochastic rounding with random bits r (low 16 used) by gfx950's
+    // v_cvt_sr_bf16_f32 (random bits from the top of its second operand): BF16
+    // keeps the top 16 bits of the FP32 word, so the 16 random bits are added
+    // to the whole dropped field and the word truncated (exactly unbiased);
+    // Inf and NaN convert as they are.  (Bit-identical on the device to that
+    // definition written out with integer operations.)
     __device__ static T enc_sr(float v, uint32_t r) {
-        uint32_t u = __builtin_bit_cast(uint32_t, v);
-        if (((u >> 23) & 0xFFu) < 255u) u = (u + (r & 0xFFFFu)) & 0xFFFF0000u;
-        return (__bf16)__builtin_bit_cast(float, u);
+        const bf16x2 z = {(__bf16)0.f, (__bf16)0.f};
+        return __builtin_amdgcn_cvt_sr_bf16_f32(z, v, r << 16, false)[0];
     }
 };
 
