@@ -425,6 +425,19 @@ const char *lbm_batch_last_error(const lbm_batch *b);
  * lbm_last_error(NULL)). */
 lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, int32_t per_lane, void *stream);
 
+/* The stochastic rounding the step kernels apply to 16-bit stores
+ * (LBM_ROUND_STOCHASTIC), value by value, for checking the encoder itself:
+ * out[i] = in[i] rounded to FP16 (storage LBM_F16) or BF16 (LBM_BF16) with the
+ * random bits r[i] (its low 13 bits for FP16, 16 for BF16): the bits are added
+ * below the result's last place (for FP16 subnormal results, at the top of the
+ * longer dropped field; below 2^-24 the result is 0 or 2^-24) and the word is
+ * truncated, so the magnitude rounds up with probability (dropped part) /
+ * (last place); Inf and NaN are converted as they are.  out holds the 16-bit
+ * patterns.  Device pointers, n in [0, 2^32); asynchronous on `stream`;
+ * LBM_EINVAL for another storage or a NULL pointer with n > 0 (message in
+ * lbm_last_error(NULL)). */
+lbm_status lbm_round_sr(const float *in, const uint32_t *r, uint16_t *out, int64_t n, int32_t storage, void *stream);
+
 /* Time steps taken since lbm_init (or the loaded checkpoint). */
 int64_t lbm_steps_done(const lbm_sim *sim);
 

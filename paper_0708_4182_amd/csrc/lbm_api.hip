@@ -690,6 +690,17 @@ lbm_status lbm_stream_copy(void *dst, const void *src, size_t bytes, int32_t per
     return LBM_OK;
 }
 
+lbm_status lbm_round_sr(const float *in, const uint32_t *r, uint16_t *out, int64_t n, int32_t storage,
+                        void *stream) {
+    if (n < 0 || n > 0xFFFFFFFFll) return fail(nullptr, LBM_EINVAL, "lbm_round_sr: n must be in [0, 2^32)");
+    if (storage != LBM_F16 && storage != LBM_BF16)
+        return fail(nullptr, LBM_EINVAL, "lbm_round_sr: storage must be LBM_F16 or LBM_BF16");
+    if (n > 0 && (!in || !r || !out)) return fail(nullptr, LBM_EINVAL, "lbm_round_sr: NULL pointer");
+    const hipError_t e = lbm::launch_round_sr(in, r, out, (uint32_t)n, storage, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(nullptr, LBM_EDEVICE, "lbm_round_sr: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
 lbm_status lbm_flux_static(lbm_sim *s, double *Q, double *M) {
     lbm_status st = usable(s);
     if (st) return st;

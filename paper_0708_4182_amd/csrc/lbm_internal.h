@@ -116,6 +116,8 @@ hipError_t launch_fill(void *dst, size_t bytes, hipStream_t s);
 // One-pass non-temporal copy of bytes (a multiple of 16): each lane moves
 // per_lane (1, 2 or 4) chunks of 16 bytes.
 hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, int per_lane, hipStream_t s);
+hipError_t launch_round_sr(const float *in, const uint32_t *r, uint16_t *out, uint32_t n, int storage,
+                           hipStream_t s);
 hipError_t launch_moments(int storage, const void *src, const uint16_t *flags, const Grid &g,
                           float rho_off, float *rho, float *ux, float *uy, hipStream_t s);
 // grid > 0: persistent kernel with that many workgroups taking tiles from the

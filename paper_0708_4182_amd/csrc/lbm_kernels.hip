@@ -2051,6 +2051,26 @@ hipError_t launch_fill(void *dst, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
+// The 16-bit stochastic rounding of the step kernels' stores, value by value
+// (Codec<S>::enc_sr), for tests of the encoder itself.
+template <int S>
+__global__ void __launch_bounds__(256) k_round_sr(const float *__restrict__ in, const uint32_t *__restrict__ r,
+                                                  uint16_t *__restrict__ out, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = __builtin_bit_cast(uint16_t, Codec<S>::enc_sr(in[i], r[i]));
+}
+
+hipError_t launch_round_sr(const float *in, const uint32_t *r, uint16_t *out, uint32_t n, int storage,
+                           hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const unsigned blocks = (n + 255u) / 256u;
+    if (storage == ST_F16) k_round_sr<ST_F16><<<blocks, 256, 0, s>>>(in, r, out, n);
+    else if (storage == ST_BF16) k_round_sr<ST_BF16><<<blocks, 256, 0, s>>>(in, r, out, n);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t launch_stream_copy(void *dst, const void *src, size_t bytes, int per_lane, hipStream_t s) {
     const size_t n16 = bytes / 16;
     if (n16 == 0) return hipSuccess;

@@ -22,7 +22,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
 
 # Exported symbols of include/lbm.h (checked by the CPU tests).
 SYMBOLS = ("lbm_workspace_bytes", "lbm_init", "lbm_init_device", "lbm_step", "lbm_moments",
-           "lbm_flux", "lbm_flux_static", "lbm_stream_copy", "lbm_profile", "lbm_geometry", "lbm_set_forces", "lbm_set_accel_field", "lbm_set_tile", "lbm_set_kernel",
+           "lbm_flux", "lbm_flux_static", "lbm_stream_copy", "lbm_round_sr", "lbm_profile", "lbm_geometry", "lbm_set_forces", "lbm_set_accel_field", "lbm_set_tile", "lbm_set_kernel",
            "lbm_set_graph",
            "lbm_get_tile",
            "lbm_autotune", "lbm_state_bytes",
@@ -97,6 +97,8 @@ def load_library():
     lib.lbm_flux_static.argtypes = [vp, dp, dp]
     lib.lbm_stream_copy.argtypes = [vp, vp, C.c_size_t, C.c_int32, vp]
     lib.lbm_stream_copy.restype = C.c_int
+    lib.lbm_round_sr.argtypes = [vp, vp, vp, C.c_int64, C.c_int32, vp]
+    lib.lbm_round_sr.restype = C.c_int
     lib.lbm_geometry.argtypes = [vp, C.POINTER(C.c_uint16)]
     lib.lbm_set_forces.argtypes = [vp, C.c_double, C.c_double, C.c_double]
     lib.lbm_set_tile.argtypes = [vp, C.c_int32, C.c_int32]
@@ -174,7 +176,27 @@ def stream_copy(dst, src, per_lane: int = 1, stream=None):
     rc = lib.lbm_stream_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes, int(per_lane),
                              C.c_void_p(st.cuda_stream))
     if rc != 0:
-        raise LBMError(f"lbm_stream_copy: {STATUS.get(rc, rc)}: {lib.lbm_last_error(None).decode()}")
+        raise LBMError(rc, lib.lbm_last_error(None).decode())
+
+
+def round_sr(values, bits, storage: int, stream=None):
+    """lbm_round_sr: the 16-bit stochastic rounding of the step kernels applied
+    to a CUDA float32 tensor with CUDA uint32 (int32 storage) random words of
+    the same size; returns the 16-bit patterns as an int16 tensor."""
+    import torch
+    if not (values.is_cuda and bits.is_cuda and values.dtype == torch.float32 and bits.dtype == torch.int32):
+        raise ValueError("round_sr needs a float32 and an int32 CUDA tensor")
+    if values.numel() != bits.numel():
+        raise ValueError("round_sr: sizes differ")
+    v, r = values.contiguous(), bits.contiguous()
+    out = torch.empty(v.numel(), dtype=torch.int16, device=v.device)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    lib = load_library()
+    rc = lib.lbm_round_sr(C.c_void_p(v.data_ptr()), C.c_void_p(r.data_ptr()), C.c_void_p(out.data_ptr()),
+                          v.numel(), int(storage), C.c_void_p(st.cuda_stream))
+    if rc != 0:
+        raise LBMError(rc, lib.lbm_last_error(None).decode())
+    return out
 
 
 def workspace_bytes(p) -> int:

@@ -201,3 +201,55 @@ def test_other_kernels_rejected(lbm):
     s.set_kernel("two")
     s.set_kernel("three")
     s.set_kernel("fused")
+
+
+def sr_definition(v, r, storage):
+    """Stochastic rounding written out with integer operations on the FP32
+    word u of each value: the random bits (low 13 for FP16, 16 for BF16) are
+    added below the result's last place and the word is truncated; for FP16
+    results in the subnormal range (FP32 biased exponent e < 113) the dropped
+    field is 113 - e bits longer and the random bits sit at its top.  Returns
+    the 16-bit patterns (finite values only)."""
+    u = v.view(np.uint32).astype(np.uint64)
+    r = r.astype(np.uint64)
+    if storage == 2:
+        return (((u + (r & 0xFFFF)) & 0xFFFF0000) >> 16).astype(np.uint16)
+    e = ((u >> 23) & 0xFF).astype(np.int64)
+    sh = np.clip(113 - e, 0, 10).astype(np.uint64)
+    mask = (np.uint64(0x2000) << sh) - np.uint64(1)
+    w = ((u + ((r & 0x1FFF) << sh)) & ~mask & 0xFFFFFFFF).astype(np.uint32)
+    return w.view(np.float32).astype(np.float16).view(np.uint16)
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_encoder_matches_its_definition(lbm, storage):
+    """lbm_round_sr, the encoder of the step kernels' stochastic rounding (a
+    gfx950 conversion instruction), against sr_definition bit by bit: every
+    finite value for BF16; for FP16 every value of magnitude 2^-24 .. 2^15
+    (below 2^-24 the result must be 0 or 2^-24 with the value's sign; the
+    range of the stored deviations lies far below 2^15); Inf and NaN pass."""
+    import torch
+    rng = np.random.default_rng(7 + storage)
+    n = 1 << 20
+    mag = 10.0 ** rng.uniform(-12, 4.5 if storage == 2 else 4.3, n)
+    v = (np.where(rng.random(n) < 0.5, -1.0, 1.0) * mag).astype(np.float32)
+    v[:6] = [0.0, -0.0, np.inf, -np.inf, np.nan, 1.0]
+    r = rng.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+    out = lbm.round_sr(torch.from_numpy(v).cuda(), torch.from_numpy(r.view(np.int32)).cuda(), storage)
+    got = out.cpu().numpy().view(np.uint16)
+    fin = np.isfinite(v)
+    ref = sr_definition(v, r, storage)
+    if storage == 2:
+        sel = fin
+        dec = (got.astype(np.uint32) << 16).view(np.float32)
+    else:
+        sel = fin & (np.abs(v) >= 2.0 ** -24)
+        dec = got.view(np.float16).astype(np.float32)
+        tiny = fin & (np.abs(v) < 2.0 ** -24)
+        assert np.all((dec[tiny] == 0) | (np.abs(dec[tiny]) == np.float32(2.0 ** -24)))
+        assert np.all(np.signbit(dec[tiny]) == np.signbit(v[tiny]))
+    bad = int((got[sel] != ref[sel]).sum())
+    print(f"storage {storage}: {int(sel.sum())} values compared, {bad} differ")
+    assert bad == 0
+    assert np.isposinf(dec[2]) and np.isneginf(dec[3]) and np.isnan(dec[4]) and dec[5] == 1.0
+    assert np.signbit(dec[1]) and dec[0] == 0

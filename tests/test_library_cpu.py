@@ -141,6 +141,18 @@ def test_null_handle_calls(lib):
     assert lib.lbm_get_tile(None, None, None, None) == -1
     lib.lbm_free(None)
     assert lib.lbm_status_string(-4) == b"LBM_EDIVERGED"
+    assert lib.lbm_batch_set_kernel(None, 5) == -1
+    assert lib.lbm_batch_get_kernel(None) == -1
+
+
+def test_round_sr_validation_without_gpu_work(lib):
+    # argument checks come before any HIP call; n = 0 launches nothing
+    assert lib.lbm_round_sr(None, None, None, 4, 0, None) == -1      # FP32 storage has no rounding
+    assert lib.lbm_round_sr(None, None, None, 4, 3, None) == -1
+    assert lib.lbm_round_sr(None, None, None, -1, 1, None) == -1
+    assert lib.lbm_round_sr(None, None, None, 4, 1, None) == -1      # NULL pointers with n > 0
+    assert b"NULL" in lib.lbm_last_error(None)
+    assert lib.lbm_round_sr(None, None, None, 0, 2, None) == 0
 
 
 def test_product_path_has_no_oracle_dependency():
