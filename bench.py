@@ -326,11 +326,11 @@ def main():
         from paper_0708_4182_amd import experiments
         t0 = time.perf_counter()
         with contextlib.redirect_stdout(sys.stderr):     # the experiment's progress lines
-            ws = experiments.warm_detect(train=2048, val=128, test=64, epochs=10, t_cold="0")
+            ws = experiments.warm_detect(train=4096, val=128, test=64, epochs=30, t_cold="0")
         out["warm_start"] = {
             "workload": "learned warm start on 256x64 channels (step height 0-8, f in [0,3e-3), G in "
-                        "[-5.5,-4.5], g = 1e-6, FP32): network trained by the library's kernels on 2048 "
-                        "steady states the method generates (10 epochs); 64 held-out seeds seeded from its "
+                        "[-5.5,-4.5], g = 1e-6, FP32): network trained by the library's kernels on 4096 "
+                        "steady states the method generates (30 epochs); 64 held-out seeds seeded from its "
                         "predicted velocity (flow mode), each run to its own steady flux (|dQ| <= 1e-8 |Q| "
                         "over 1000 steps, the cold runs' rule) with no cold reference; a settled run whose "
                         "flux departs from its seeded flux by more than a margin calibrated on 128 other "
