@@ -805,6 +805,11 @@ struct ConvLds {
 // plane.  TWD: tile width (32, or 64 with 512 threads, which halves the
 // staged weight bytes per output).
 //
+// pool.p != NULL (bf16 output, VEC, even H and W): the epilogue also writes
+// the 2 x 2 means of the output tile to pool (H / 2 x W / 2 planes), with the
+// arithmetic of k_pool on the same bf16 values, so the separate pooling pass
+// is not needed.
+//
 // Workgroups are dispatched round-robin over the 8 XCDs; block b is given
 // tile b' = (b mod 8) * (nb / 8) + b / 8 so that each XCD computes a
 // contiguous run of tiles, and the halo rows and the cache lines that
@@ -812,7 +817,8 @@ struct ConvLds {
 template <class TO, int NM, bool VEC, int TWD>
 __global__ void __launch_bounds__(ConvTile<TWD>::NT) k_conv3x3_mfma(View in, const __bf16 *__restrict__ wp,
                                                                      const float *__restrict__ bias, View out,
-                                                                     int cin, int cout, int cin_pad, int relu) {
+                                                                     View pool, int cin, int cout, int cin_pad,
+                                                                     int relu) {
     using L = ConvLds<TO, NM, TWD>;
     using T = ConvTile<TWD>;
     constexpr int CO = L::CO, TW = T::TW, NT = T::NT;
@@ -905,6 +911,36 @@ __global__ void __launch_bounds__(ConvTile<TWD>::NT) k_conv3x3_mfma(View in, con
             if (e < PIECES && co < cout && y < H && x < W)
                 *reinterpret_cast<uint4 *>(yo + (uint32_t)co * HW + (uint32_t)(y * W + x)) =
                     *reinterpret_cast<const uint4 *>(&os[col * L::OS + row * TW + kk * EPP]);
+        }
+        if constexpr (sizeof(TO) == 2) {
+            if (pool.p != nullptr) {
+                // eight pooled values (16 bytes) of one pooled row per piece,
+                // from two 16-value runs of output rows 2 r and 2 r + 1
+                constexpr int PPR2 = TW / 16, PP = CO * (MH / 2) * PPR2;
+                const uint32_t HWo = (uint32_t)(pool.H * pool.W);
+                TO *__restrict__ po = static_cast<TO *>(pool.p) + (size_t)n * pool.bs;
+#pragma unroll
+                for (int k = 0; k < (PP + NT - 1) / NT; ++k) {
+                    const int e = tid + NT * k;
+                    const int kk = e % PPR2, r = (e / PPR2) % (MH / 2), col = e / (PPR2 * (MH / 2));
+                    const int y = ty0 / 2 + r, x = tx0 / 2 + 8 * kk, co = co0 + col;
+                    if (e < PP && co < cout && y < pool.H && x < pool.W) {
+                        const TO *r0 = &os[col * L::OS + (2 * r) * TW + 16 * kk], *r1 = r0 + TW;
+                        uint32_t w4[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const float a0 = 0.25f * ((tof(r0[4 * j]) + tof(r0[4 * j + 1])) +
+                                                      (tof(r1[4 * j]) + tof(r1[4 * j + 1])));
+                            const float a1 = 0.25f * ((tof(r0[4 * j + 2]) + tof(r0[4 * j + 3])) +
+                                                      (tof(r1[4 * j + 2]) + tof(r1[4 * j + 3])));
+                            w4[j] = (uint32_t)__builtin_bit_cast(unsigned short, fromf<TO>(a0)) |
+                                    (uint32_t)__builtin_bit_cast(unsigned short, fromf<TO>(a1)) << 16;
+                        }
+                        *reinterpret_cast<uint4 *>(po + (uint32_t)co * HWo + (uint32_t)(y * pool.W + x)) =
+                            make_uint4(w4[0], w4[1], w4[2], w4[3]);
+                    }
+                }
+            }
         }
     } else {
 #pragma unroll
@@ -1170,28 +1206,41 @@ bool mfma_vec_ok(const View &in, const View &out) {
 // CUs idle.
 template <class TO, int NM, int TWD>
 hipError_t launch_conv3x3_mfma_t(const View &in, const __bf16 *wp, const float *bias, const View &out, int N,
-                                 int cin, int cout, int cin_pad, bool relu, bool vec, hipStream_t s) {
+                                 int cin, int cout, int cin_pad, bool relu, bool vec, const View &pool,
+                                 hipStream_t s) {
     const int tiles = ((in.W + TWD - 1) / TWD) * ((in.H + MH - 1) / MH);
     const dim3 grid(tiles, N * ((cout + 16 * NM - 1) / (16 * NM)));
     const int r = relu ? 1 : 0, nt = ConvTile<TWD>::NT;
-    if (vec) k_conv3x3_mfma<TO, NM, true, TWD><<<grid, nt, 0, s>>>(in, wp, bias, out, cin, cout, cin_pad, r);
-    else k_conv3x3_mfma<TO, NM, false, TWD><<<grid, nt, 0, s>>>(in, wp, bias, out, cin, cout, cin_pad, r);
+    if (vec)
+        k_conv3x3_mfma<TO, NM, true, TWD><<<grid, nt, 0, s>>>(in, wp, bias, out, pool, cin, cout, cin_pad, r);
+    else
+        k_conv3x3_mfma<TO, NM, false, TWD><<<grid, nt, 0, s>>>(in, wp, bias, out, pool, cin, cout, cin_pad, r);
     return hipGetLastError();
 }
 
+// pool (may be NULL): the 2 x 2 pooled output the epilogue also writes when
+// the tile goes through LDS (*pooled set to whether it did).
 template <class TO>
 hipError_t launch_conv3x3_mfma(const View &in, const __bf16 *wp, const float *bias, const View &out, int N,
-                               int cin, int cout, int cin_pad, bool relu, hipStream_t s) {
+                               int cin, int cout, int cin_pad, bool relu, hipStream_t s,
+                               const View *pool = nullptr, bool *pooled = nullptr) {
     const bool vec = mfma_vec_ok<TO>(in, out);
+    View pv{};
+    const bool fuse = pool != nullptr && vec && sizeof(TO) == 2 && in.H % 2 == 0 && in.W % 2 == 0 &&
+                      2 * pool->H == in.H && 2 * pool->W == in.W && pool->W % 8 == 0 &&
+                      ((long long)pool->H * pool->W) % 8 == 0 && pool->bs % 8 == 0 &&
+                      (uintptr_t)pool->p % 16 == 0;
+    if (fuse) pv = *pool;
+    if (pooled) *pooled = fuse;
     const long long rows = (in.H + MH - 1) / MH;
     const bool narrow = mfma_narrow(cout) || rows * ((in.W + 31) / 32) * N * ((cout + 63) / 64) < 128;
     const long long wide_wgs = rows * (in.W / 64) * N * (narrow ? (cout + 31) / 32 : (cout + 63) / 64);
     const bool wide = vec && in.W % 64 == 0 && wide_wgs >= 256;
     if (narrow)
-        return wide ? launch_conv3x3_mfma_t<TO, 2, 64>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, s)
-                    : launch_conv3x3_mfma_t<TO, 2, 32>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, s);
-    return wide ? launch_conv3x3_mfma_t<TO, 4, 64>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, s)
-                : launch_conv3x3_mfma_t<TO, 4, 32>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, s);
+        return wide ? launch_conv3x3_mfma_t<TO, 2, 64>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, pv, s)
+                    : launch_conv3x3_mfma_t<TO, 2, 32>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, pv, s);
+    return wide ? launch_conv3x3_mfma_t<TO, 4, 64>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, pv, s)
+                : launch_conv3x3_mfma_t<TO, 4, 32>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, pv, s);
 }
 
 hipError_t pack_all(const float *theta, __bf16 *base, const PackJobs &jobs, hipStream_t s) {
@@ -1209,8 +1258,8 @@ hipError_t conv3x3_mfma_dx_packed(const View &dz, const __bf16 *wp, const View &
 }
 
 hipError_t conv3x3_mfma_packed(const View &in, const __bf16 *wp, const float *bias, const View &out, int N,
-                               int cin, int cout, bool relu, hipStream_t s) {
-    return launch_conv3x3_mfma<__bf16>(in, wp, bias, out, N, cin, cout, pad32(cin), relu, s);
+                               int cin, int cout, bool relu, hipStream_t s, const View *pool, bool *pooled) {
+    return launch_conv3x3_mfma<__bf16>(in, wp, bias, out, N, cin, cout, pad32(cin), relu, s, pool, pooled);
 }
 
 hipError_t flip_transpose(const float *w, float *wt, int cin, int cout, hipStream_t s) {
