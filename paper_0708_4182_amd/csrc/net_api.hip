@@ -292,18 +292,20 @@ void layer_io(const Tensors &t, LayerIO io[NLAYERS]) {
 // Forward convolution of layer l: the first layer reads the FP32 input with
 // FP32 products; with bf16 activations every other layer runs on matrix
 // cores (bf16 weights and activations, FP32 accumulation).
-// pool (may be NULL): the 2 x 2 pooled output, produced by the same launch
-// where possible (*pooled), else by the caller.
+// pool, up (may be NULL): the 2 x 2 pooled and the 2x upsampled output,
+// produced by the same launch where possible (*pooled, *upped), else by the
+// caller.
 template <class TA>
 hipError_t conv_fwd(lbm_net *n, int l, const View &X, const View &Y, int N, bool first, const View *pool = nullptr,
-                    bool *pooled = nullptr) {
+                    bool *pooled = nullptr, const View *up = nullptr, bool *upped = nullptr) {
     const Plan &P = n->P;
     const float *w = n->b.theta + P.woff[l], *bias = n->b.theta + P.boff[l];
     if (pooled) *pooled = false;
+    if (upped) *upped = false;
     if (first) return lbmnet::conv3x3<float, TA>(X, w, bias, Y, N, P.lcin[l], P.lcout[l], true, n->s);
     if constexpr (sizeof(TA) == 2)
         return lbmnet::conv3x3_mfma_packed(X, n->b.wpf + n->b.wpoff[l], bias, Y, N, P.lcin[l], P.lcout[l], true,
-                                           n->s, pool, pooled);
+                                           n->s, pool, pooled, up, upped);
     else return lbmnet::conv3x3<TA, TA>(X, w, bias, Y, N, P.lcin[l], P.lcout[l], true, n->s);
 }
 
@@ -341,7 +343,7 @@ lbm_status forward_t(lbm_net *n, const float *x, float *y, int N) {
     if (sizeof(TA) == 2 && !n->packed) {     // pack once per parameter update
         if (lbm_status st = pack(n, false)) return st;
     }
-    bool pooled = false;
+    bool pooled = false, upped = false;
     NHIP(n, (conv_fwd<TA>(n, E1A, io[E1A].X, io[E1A].Y, N, true)));
     NHIP(n, (conv_fwd<TA>(n, E1B, io[E1B].X, io[E1B].Y, N, false, &t.p1, &pooled)));
     if (!pooled) NHIP(n, lbmnet::pool<TA>(t.e1, t.p1, N, P.c[0], s));
@@ -352,14 +354,14 @@ lbm_status forward_t(lbm_net *n, const float *x, float *y, int N) {
     NHIP(n, (conv_fwd<TA>(n, E3B, io[E3B].X, io[E3B].Y, N, false, &t.p3, &pooled)));
     if (!pooled) NHIP(n, lbmnet::pool<TA>(t.e3, t.p3, N, P.c[2], s));
     NHIP(n, (conv_fwd<TA>(n, BA, io[BA].X, io[BA].Y, N, false)));
-    NHIP(n, (conv_fwd<TA>(n, BB, io[BB].X, io[BB].Y, N, false)));
-    NHIP(n, lbmnet::up<TA>(t.bb, t.up3, N, P.c[3], s));
+    NHIP(n, (conv_fwd<TA>(n, BB, io[BB].X, io[BB].Y, N, false, nullptr, nullptr, &t.up3, &upped)));
+    if (!upped) NHIP(n, lbmnet::up<TA>(t.bb, t.up3, N, P.c[3], s));
     NHIP(n, (conv_fwd<TA>(n, D3A, io[D3A].X, io[D3A].Y, N, false)));
-    NHIP(n, (conv_fwd<TA>(n, D3B, io[D3B].X, io[D3B].Y, N, false)));
-    NHIP(n, lbmnet::up<TA>(t.d3b, t.up2, N, P.c[2], s));
+    NHIP(n, (conv_fwd<TA>(n, D3B, io[D3B].X, io[D3B].Y, N, false, nullptr, nullptr, &t.up2, &upped)));
+    if (!upped) NHIP(n, lbmnet::up<TA>(t.d3b, t.up2, N, P.c[2], s));
     NHIP(n, (conv_fwd<TA>(n, D2A, io[D2A].X, io[D2A].Y, N, false)));
-    NHIP(n, (conv_fwd<TA>(n, D2B, io[D2B].X, io[D2B].Y, N, false)));
-    NHIP(n, lbmnet::up<TA>(t.d2b, t.up1, N, P.c[1], s));
+    NHIP(n, (conv_fwd<TA>(n, D2B, io[D2B].X, io[D2B].Y, N, false, nullptr, nullptr, &t.up1, &upped)));
+    if (!upped) NHIP(n, lbmnet::up<TA>(t.d2b, t.up1, N, P.c[1], s));
     NHIP(n, (conv_fwd<TA>(n, D1A, io[D1A].X, io[D1A].Y, N, false)));
     NHIP(n, (conv_fwd<TA>(n, D1B, io[D1B].X, io[D1B].Y, N, false)));
     NHIP(n, lbmnet::conv1x1<TA>(t.d1b, n->b.theta + P.woff[OUT], n->b.theta + P.boff[OUT], N, P.c[0], P.cout, y, s));

@@ -28,10 +28,11 @@ int pad32(int c);
 // pool (may be NULL): the 2 x 2 mean-pooled output ([C][H/2][W/2] per sample),
 // written by the same launch where the layout allows (bf16 output, whole
 // 8-pixel groups, 16-byte aligned planes, even H and W); *pooled (may be
-// NULL) tells whether it was, otherwise the caller pools separately.
+// NULL) tells whether it was, otherwise the caller pools separately.  up,
+// upped: the same for the nearest 2x upsampled output ([C][2H][2W]).
 hipError_t conv3x3_mfma_packed(const View &in, const __bf16 *wp, const float *bias, const View &out, int N,
                                int cin, int cout, bool relu, hipStream_t s, const View *pool = nullptr,
-                               bool *pooled = nullptr);
+                               bool *pooled = nullptr, const View *up = nullptr, bool *upped = nullptr);
 // Packing jobs of one launch (k_pack_all): the weights of a 3x3 layer at
 // theta + woff, [cout][cin][9] FP32, rounded to bf16 at base + out in the
 // forward layout [t][co][pad32(cin)] (flip = 0, rows = cout, pad = pad32(cin))

@@ -808,7 +808,9 @@ struct ConvLds {
 // pool.p != NULL (bf16 output, VEC, even H and W): the epilogue also writes
 // the 2 x 2 means of the output tile to pool (H / 2 x W / 2 planes), with the
 // arithmetic of k_pool on the same bf16 values, so the separate pooling pass
-// is not needed.
+// is not needed.  up.p != NULL (same conditions): the epilogue also writes the
+// nearest 2x upsampling of the output tile to up (2H x 2W planes: each value
+// copied to a 2 x 2 block), so the separate upsampling pass is not needed.
 //
 // Workgroups are dispatched round-robin over the 8 XCDs; block b is given
 // tile b' = (b mod 8) * (nb / 8) + b / 8 so that each XCD computes a
@@ -817,8 +819,8 @@ struct ConvLds {
 template <class TO, int NM, bool VEC, int TWD>
 __global__ void __launch_bounds__(ConvTile<TWD>::NT) k_conv3x3_mfma(View in, const __bf16 *__restrict__ wp,
                                                                      const float *__restrict__ bias, View out,
-                                                                     View pool, int cin, int cout, int cin_pad,
-                                                                     int relu) {
+                                                                     View pool, View up, int cin, int cout,
+                                                                     int cin_pad, int relu) {
     using L = ConvLds<TO, NM, TWD>;
     using T = ConvTile<TWD>;
     constexpr int CO = L::CO, TW = T::TW, NT = T::NT;
@@ -908,9 +910,26 @@ __global__ void __launch_bounds__(ConvTile<TWD>::NT) k_conv3x3_mfma(View in, con
             const int e = tid + NT * k;
             const int kk = e % PPR, row = (e / PPR) % MH, col = e / (PPR * MH);
             const int y = ty0 + row, x = tx0 + kk * EPP, co = co0 + col;
-            if (e < PIECES && co < cout && y < H && x < W)
-                *reinterpret_cast<uint4 *>(yo + (uint32_t)co * HW + (uint32_t)(y * W + x)) =
-                    *reinterpret_cast<const uint4 *>(&os[col * L::OS + row * TW + kk * EPP]);
+            if (e < PIECES && co < cout && y < H && x < W) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(&os[col * L::OS + row * TW + kk * EPP]);
+                *reinterpret_cast<uint4 *>(yo + (uint32_t)co * HW + (uint32_t)(y * W + x)) = v;
+                if constexpr (sizeof(TO) == 2) {
+                    if (up.p != nullptr) {
+                        // eight values -> sixteen (each twice) in rows 2 y and 2 y + 1
+                        auto dup = [](uint32_t w) {
+                            return make_uint2((w & 0xffffu) * 0x10001u, (w >> 16) * 0x10001u);
+                        };
+                        const uint2 d0 = dup(v.x), d1 = dup(v.y), d2 = dup(v.z), d3 = dup(v.w);
+                        const uint4 lo = make_uint4(d0.x, d0.y, d1.x, d1.y), hi = make_uint4(d2.x, d2.y, d3.x, d3.y);
+                        TO *uo = static_cast<TO *>(up.p) + (size_t)n * up.bs +
+                                 (size_t)co * ((uint32_t)up.H * (uint32_t)up.W) + (uint32_t)(2 * y * up.W + 2 * x);
+                        *reinterpret_cast<uint4 *>(uo) = lo;
+                        *reinterpret_cast<uint4 *>(uo + 8) = hi;
+                        *reinterpret_cast<uint4 *>(uo + up.W) = lo;
+                        *reinterpret_cast<uint4 *>(uo + up.W + 8) = hi;
+                    }
+                }
+            }
         }
         if constexpr (sizeof(TO) == 2) {
             if (pool.p != nullptr) {
@@ -1207,23 +1226,25 @@ bool mfma_vec_ok(const View &in, const View &out) {
 template <class TO, int NM, int TWD>
 hipError_t launch_conv3x3_mfma_t(const View &in, const __bf16 *wp, const float *bias, const View &out, int N,
                                  int cin, int cout, int cin_pad, bool relu, bool vec, const View &pool,
-                                 hipStream_t s) {
+                                 const View &up, hipStream_t s) {
     const int tiles = ((in.W + TWD - 1) / TWD) * ((in.H + MH - 1) / MH);
     const dim3 grid(tiles, N * ((cout + 16 * NM - 1) / (16 * NM)));
     const int r = relu ? 1 : 0, nt = ConvTile<TWD>::NT;
     if (vec)
-        k_conv3x3_mfma<TO, NM, true, TWD><<<grid, nt, 0, s>>>(in, wp, bias, out, pool, cin, cout, cin_pad, r);
+        k_conv3x3_mfma<TO, NM, true, TWD><<<grid, nt, 0, s>>>(in, wp, bias, out, pool, up, cin, cout, cin_pad, r);
     else
-        k_conv3x3_mfma<TO, NM, false, TWD><<<grid, nt, 0, s>>>(in, wp, bias, out, pool, cin, cout, cin_pad, r);
+        k_conv3x3_mfma<TO, NM, false, TWD><<<grid, nt, 0, s>>>(in, wp, bias, out, pool, up, cin, cout, cin_pad, r);
     return hipGetLastError();
 }
 
-// pool (may be NULL): the 2 x 2 pooled output the epilogue also writes when
-// the tile goes through LDS (*pooled set to whether it did).
+// pool, up (may be NULL): the 2 x 2 pooled and the 2x upsampled output the
+// epilogue also writes when the tile goes through LDS (*pooled, *upped set to
+// whether it did).
 template <class TO>
 hipError_t launch_conv3x3_mfma(const View &in, const __bf16 *wp, const float *bias, const View &out, int N,
                                int cin, int cout, int cin_pad, bool relu, hipStream_t s,
-                               const View *pool = nullptr, bool *pooled = nullptr) {
+                               const View *pool = nullptr, bool *pooled = nullptr, const View *up = nullptr,
+                               bool *upped = nullptr) {
     const bool vec = mfma_vec_ok<TO>(in, out);
     View pv{};
     const bool fuse = pool != nullptr && vec && sizeof(TO) == 2 && in.H % 2 == 0 && in.W % 2 == 0 &&
@@ -1232,15 +1253,21 @@ hipError_t launch_conv3x3_mfma(const View &in, const __bf16 *wp, const float *bi
                       (uintptr_t)pool->p % 16 == 0;
     if (fuse) pv = *pool;
     if (pooled) *pooled = fuse;
+    View uv{};
+    const bool fuse_up = up != nullptr && vec && sizeof(TO) == 2 && up->H == 2 * in.H && up->W == 2 * in.W &&
+                         up->W % 16 == 0 && ((long long)up->H * up->W) % 8 == 0 && up->bs % 8 == 0 &&
+                         (uintptr_t)up->p % 16 == 0;
+    if (fuse_up) uv = *up;
+    if (upped) *upped = fuse_up;
     const long long rows = (in.H + MH - 1) / MH;
     const bool narrow = mfma_narrow(cout) || rows * ((in.W + 31) / 32) * N * ((cout + 63) / 64) < 128;
     const long long wide_wgs = rows * (in.W / 64) * N * (narrow ? (cout + 31) / 32 : (cout + 63) / 64);
     const bool wide = vec && in.W % 64 == 0 && wide_wgs >= 256;
     if (narrow)
-        return wide ? launch_conv3x3_mfma_t<TO, 2, 64>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, pv, s)
-                    : launch_conv3x3_mfma_t<TO, 2, 32>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, pv, s);
-    return wide ? launch_conv3x3_mfma_t<TO, 4, 64>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, pv, s)
-                : launch_conv3x3_mfma_t<TO, 4, 32>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, pv, s);
+        return wide ? launch_conv3x3_mfma_t<TO, 2, 64>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, pv, uv, s)
+                    : launch_conv3x3_mfma_t<TO, 2, 32>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, pv, uv, s);
+    return wide ? launch_conv3x3_mfma_t<TO, 4, 64>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, pv, uv, s)
+                : launch_conv3x3_mfma_t<TO, 4, 32>(in, wp, bias, out, N, cin, cout, cin_pad, relu, vec, pv, uv, s);
 }
 
 hipError_t pack_all(const float *theta, __bf16 *base, const PackJobs &jobs, hipStream_t s) {
@@ -1258,8 +1285,10 @@ hipError_t conv3x3_mfma_dx_packed(const View &dz, const __bf16 *wp, const View &
 }
 
 hipError_t conv3x3_mfma_packed(const View &in, const __bf16 *wp, const float *bias, const View &out, int N,
-                               int cin, int cout, bool relu, hipStream_t s, const View *pool, bool *pooled) {
-    return launch_conv3x3_mfma<__bf16>(in, wp, bias, out, N, cin, cout, pad32(cin), relu, s, pool, pooled);
+                               int cin, int cout, bool relu, hipStream_t s, const View *pool, bool *pooled,
+                               const View *up, bool *upped) {
+    return launch_conv3x3_mfma<__bf16>(in, wp, bias, out, N, cin, cout, pad32(cin), relu, s, pool, pooled, up,
+                                       upped);
 }
 
 hipError_t flip_transpose(const float *w, float *wt, int cin, int cout, hipStream_t s) {
