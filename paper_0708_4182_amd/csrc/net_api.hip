@@ -369,8 +369,12 @@ lbm_status forward_t(lbm_net *n, const float *x, float *y, int N) {
 }
 
 // Gradients of one conv3x3 layer from the gradient of its (post-ReLU) output.
+// pool_g / up_g (may be NULL): the layer's output also feeds a 2 x 2 pooling
+// with gradient pool_g, or only a 2x upsampling with gradient up_g; their
+// adjoints run in the ReLU-mask pass (folded where the layout allows).
 template <class TA>
-lbm_status conv_back(lbm_net *n, int l, const LayerIO &io, int N) {
+lbm_status conv_back(lbm_net *n, int l, const LayerIO &io, int N, const View *pool_g = nullptr,
+                     const View *up_g = nullptr) {
     const Plan &P = n->P;
     Buffers &b = n->b;
     const int cin = P.lcin[l], cout = P.lcout[l], H = io.Y.H, W = io.Y.W;
@@ -381,7 +385,7 @@ lbm_status conv_back(lbm_net *n, int l, const LayerIO &io, int N) {
     if (lbmnet::bias_scratch(N, cout, H, W) > b.bpart_floats) return nfail(n, LBM_EINVAL, "bias scratch too small");
     int nb = 0;
     NHIP(n, lbmnet::relu_mask_bias<TA>(io.gY, io.Y, N, cout, mfma ? nullptr : b.dz, sizeof(TA) == 2 ? b.dzh : nullptr,
-                                       b.bpart, &nb, n->s));
+                                       b.bpart, &nb, n->s, pool_g, up_g));
     float *db = b.grad + P.boff[l];
     const int chunks = mfma ? lbmnet::dw_chunks_mfma(N, H, W, cin, cout) : lbmnet::dw_chunks(N, H, W, cin, cout);
     if ((size_t)chunks * cout * cin * 9 > b.partial_floats) return nfail(n, LBM_EINVAL, "dW scratch too small");
@@ -425,29 +429,23 @@ lbm_status gradient_t(lbm_net *n, const float *x, const float *tgt, const uint8_
     NHIP(n, lbmnet::conv1x1_dw<TA>(t.d1b, b.g_out, N, P.c[0], P.cout, b.partial, b.grad + P.woff[OUT],
                                     b.grad + P.boff[OUT], s));
     NHIP(n, lbmnet::conv1x1_dx(b.g_out, b.theta + P.woff[OUT], N, P.c[0], P.cout, HW, t.g_d1b, s));
-#define BACK(L)                                          \
-    do {                                                 \
-        if ((st = conv_back<TA>(n, L, io[L], N))) return st; \
+#define BACK(L, ...)                                                  \
+    do {                                                              \
+        if ((st = conv_back<TA>(n, L, io[L], N, ##__VA_ARGS__))) return st; \
     } while (0)
     BACK(D1B);
     BACK(D1A);
-    NHIP(n, lbmnet::up_back(t.g_up1, t.g_d2b, N, P.c[1], s));
-    BACK(D2B);
+    BACK(D2B, nullptr, &t.g_up1);
     BACK(D2A);
-    NHIP(n, lbmnet::up_back(t.g_up2, t.g_d3b, N, P.c[2], s));
-    BACK(D3B);
+    BACK(D3B, nullptr, &t.g_up2);
     BACK(D3A);
-    NHIP(n, lbmnet::up_back(t.g_up3, t.g_bb, N, P.c[3], s));
-    BACK(BB);
+    BACK(BB, nullptr, &t.g_up3);
     BACK(BA);
-    NHIP(n, lbmnet::pool_back_acc(t.g_p3, t.g_e3, N, P.c[2], s));
-    BACK(E3B);
+    BACK(E3B, &t.g_p3);
     BACK(E3A);
-    NHIP(n, lbmnet::pool_back_acc(t.g_p2, t.g_e2, N, P.c[1], s));
-    BACK(E2B);
+    BACK(E2B, &t.g_p2);
     BACK(E2A);
-    NHIP(n, lbmnet::pool_back_acc(t.g_p1, t.g_e1, N, P.c[0], s));
-    BACK(E1B);
+    BACK(E1B, &t.g_p1);
     BACK(E1A);
 #undef BACK
     n->have_grad = true;

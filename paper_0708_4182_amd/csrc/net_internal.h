@@ -70,8 +70,13 @@ hipError_t conv3x3_dw(const View &x, const float *dz, int N, int cin, int cout, 
 // at most), *nparts of them per channel, contiguous by channel.
 size_t bias_scratch(int N, int C, int H, int W);
 template <class TA>
+// pool_g / up_g (may be NULL): the adjoint of a following 2 x 2 mean pooling
+// (g += pool_g / 4 at the pooled pixel) or of a following nearest 2x
+// upsampling (g = sum of the 2 x 2 block of up_g) of the layer's output,
+// folded into the same pass where the layout allows (g then not written, and
+// for up_g not read), else run on g first.
 hipError_t relu_mask_bias(const View &g, const View &y, int N, int C, float *dz, __bf16 *dzh, float *part,
-                          int *nparts, hipStream_t s);
+                          int *nparts, hipStream_t s, const View *pool_g = nullptr, const View *up_g = nullptr);
 template <class TA>
 hipError_t pool(const View &in, const View &out, int N, int C, hipStream_t s);
 hipError_t pool_back_acc(const View &dy, const View &dx, int N, int C, hipStream_t s);

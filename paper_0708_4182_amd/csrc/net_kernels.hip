@@ -276,9 +276,18 @@ __global__ void __launch_bounds__(256) k_relu_mask(View g, View y, int N, int C,
 
 // The same, four pixels per thread (HW % 4 == 0 and aligned planes): 16-byte
 // FP32 and 8-byte bf16 accesses.
+//
+// The layer's output gradient g itself may be given in one of two other
+// forms, so that the adjoint passes of pooling and upsampling are not needed:
+// pg.p != NULL: g plus a quarter of the gradient pg of its 2 x 2 mean pooling
+// (H / 2 x W / 2 planes), as the pooling adjoint would accumulate it;
+// ug.p != NULL: g is the sum over each 2 x 2 block of ug, the gradient of its
+// nearest 2x upsampling (2H x 2W planes), and g.p is not read.  Both in the
+// operand order of the adjoint kernels.
 template <class TA>
 __global__ void __launch_bounds__(256) k_relu_mask4(View g, View y, int N, int C, float *__restrict__ dz,
-                                                    __bf16 *__restrict__ dzh, float *__restrict__ part) {
+                                                    __bf16 *__restrict__ dzh, float *__restrict__ part, View pg,
+                                                    View ug) {
     __shared__ float sh4[4];
     const uint32_t HW = (uint32_t)y.H * (uint32_t)y.W;
     const uint32_t p = 4u * (blockIdx.x * blockDim.x + threadIdx.x);
@@ -286,7 +295,28 @@ __global__ void __launch_bounds__(256) k_relu_mask4(View g, View y, int N, int C
     float sum = 0.f;
     if (p < HW) {
         const size_t r = (size_t)c * HW + p, i = ((size_t)n * C + c) * HW + p;
-        const float4 gv = *reinterpret_cast<const float4 *>(static_cast<const float *>(g.p) + n * g.bs + r);
+        float4 gv;
+        const uint32_t W = (uint32_t)y.W, yy = p / W, xx = p - yy * W;   // four pixels of one row
+        if (ug.p != nullptr) {
+            const float *u = static_cast<const float *>(ug.p) + n * ug.bs + (size_t)c * ug.H * ug.W +
+                             (size_t)(2 * yy) * ug.W + 2 * xx;
+            const float4 a0 = *reinterpret_cast<const float4 *>(u), a1 = *reinterpret_cast<const float4 *>(u + 4);
+            const float4 b0 = *reinterpret_cast<const float4 *>(u + ug.W),
+                         b1 = *reinterpret_cast<const float4 *>(u + ug.W + 4);
+            gv = make_float4((a0.x + a0.y) + (b0.x + b0.y), (a0.z + a0.w) + (b0.z + b0.w),
+                             (a1.x + a1.y) + (b1.x + b1.y), (a1.z + a1.w) + (b1.z + b1.w));
+        } else {
+            gv = *reinterpret_cast<const float4 *>(static_cast<const float *>(g.p) + n * g.bs + r);
+            if (pg.p != nullptr) {
+                const float2 q = *reinterpret_cast<const float2 *>(
+                    static_cast<const float *>(pg.p) + n * pg.bs + (size_t)c * pg.H * pg.W +
+                    (size_t)(yy / 2) * pg.W + xx / 2);
+                gv.x += 0.25f * q.x;
+                gv.y += 0.25f * q.x;
+                gv.z += 0.25f * q.y;
+                gv.w += 0.25f * q.y;
+            }
+        }
         float yv[4];
         if constexpr (sizeof(TA) == 2) {
             const uint2 yb = *reinterpret_cast<const uint2 *>(static_cast<const TA *>(y.p) + n * y.bs + r);
@@ -1390,12 +1420,35 @@ size_t bias_scratch(int N, int C, int H, int W) {
 
 template <class TA>
 hipError_t relu_mask_bias(const View &g, const View &y, int N, int C, float *dz, __bf16 *dzh, float *part,
-                          int *nparts, hipStream_t s) {
+                          int *nparts, hipStream_t s, const View *pool_g, const View *up_g) {
     const long long HW = (long long)y.H * y.W;
+    const bool v4 = relu_vec4(g, y, dz, dzh);
+    // the adjoint folded into the pass where its reads stay aligned (four fine
+    // pixels of a row map to two pooled values, 8 bytes, or to two rows of
+    // eight upsampled values, 2 x 32 bytes); otherwise it runs first, on g
+    View pv{}, uv{};
+    if (pool_g) {
+        if (v4 && y.W % 4 == 0 && 2 * pool_g->H == y.H && 2 * pool_g->W == y.W && pool_g->W % 2 == 0 &&
+            pool_g->bs % 2 == 0 && (uintptr_t)pool_g->p % 8 == 0) {
+            pv = *pool_g;
+        } else {
+            const hipError_t e = pool_back_acc(*pool_g, g, N, C, s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    if (up_g) {
+        if (v4 && y.W % 4 == 0 && up_g->H == 2 * y.H && up_g->W == 2 * y.W && up_g->bs % 4 == 0 &&
+            (uintptr_t)up_g->p % 16 == 0) {
+            uv = *up_g;
+        } else {
+            const hipError_t e = up_back(*up_g, g, N, C, s);
+            if (e != hipSuccess) return e;
+        }
+    }
     unsigned nb;
-    if (relu_vec4(g, y, dz, dzh)) {
+    if (v4) {
         nb = (unsigned)((HW / 4 + 255) / 256);
-        k_relu_mask4<TA><<<dim3(nb, (unsigned)C, (unsigned)N), 256, 0, s>>>(g, y, N, C, dz, dzh, part);
+        k_relu_mask4<TA><<<dim3(nb, (unsigned)C, (unsigned)N), 256, 0, s>>>(g, y, N, C, dz, dzh, part, pv, uv);
     } else {
         const dim3 grid = pix_grid(y.H, y.W, C, N);
         nb = grid.x;
@@ -1405,9 +1458,9 @@ hipError_t relu_mask_bias(const View &g, const View &y, int N, int C, float *dz,
     return hipGetLastError();
 }
 template hipError_t relu_mask_bias<float>(const View &, const View &, int, int, float *, __bf16 *, float *, int *,
-                                          hipStream_t);
+                                          hipStream_t, const View *, const View *);
 template hipError_t relu_mask_bias<__bf16>(const View &, const View &, int, int, float *, __bf16 *, float *, int *,
-                                           hipStream_t);
+                                           hipStream_t, const View *, const View *);
 
 template <class TA>
 hipError_t pool(const View &in, const View &out, int N, int C, hipStream_t s) {
