@@ -170,6 +170,27 @@ def step_line(name: str, r: dict, nsites: int, nfluid: int) -> dict:
     return line
 
 
+def batch_line(bt: dict) -> dict:
+    """Bench line of the sweep-table batch (experiments.sweep_throughput's
+    result bt, hipGraphs of 12 steps: whole numbers of one-, two- and
+    three-step launches): the roofline per launch, whose algorithmic bytes
+    are those of one step, and the single-step equivalent beside it."""
+    spl = {"fused": 1, "two": 2, "three": 3}[bt["kernel"]]
+    per_launch = bt["achieved_GBs"] / spl
+    line = {"workload": "256-channel sweep table (width 32-256, length 512-4096, "
+                        "step height 0-8, f in [0,3e-3), G in [-5.5,-4.5]), FP16 storage with "
+                        "stochastic rounding, steps per launch and tile autotuned (a workgroup "
+                        "per tile or a persistent queue), hipGraph of 12 steps",
+            "mlups": round(bt["mlups"], 1), "ms_per_step": round(bt["ms_per_step"], 4),
+            "kernel": bt["kernel"], "tile": bt["tile"],
+            "roofline": {"bound": "hbm", "achieved": round(per_launch, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(per_launch / HBM_PEAK_GBS, 4), "steps_per_launch": spl}}
+    if spl > 1:
+        line["roofline"]["single_step_equivalent"] = {
+            "GB/s": round(bt["achieved_GBs"], 1), "frac": round(bt["achieved_GBs"] / HBM_PEAK_GBS, 4)}
+    return line
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -306,21 +327,7 @@ def main():
         bt = experiments.sweep_throughput(graph=12)
         print(f"# batch: {bt['channels']} channels, {bt['nodes']} nodes, {bt['kernel']} tile {bt['tile']}, "
               f"{bt['ms_per_step']*1e3:.1f} us/step", file=sys.stderr, flush=True)
-        # graphs of 12 steps: whole numbers of one-, two- and three-step launches
-        spl = {"fused": 1, "two": 2, "three": 3}[bt["kernel"]]
-        per_launch = bt["achieved_GBs"] / spl
-        out["batch"] = {"workload": "256-channel sweep table (width 32-256, length 512-4096, "
-                                    "step height 0-8, f in [0,3e-3), G in [-5.5,-4.5]), FP16 storage with "
-                                    "stochastic rounding, steps per launch and tile autotuned (a workgroup "
-                                    "per tile or a persistent queue), hipGraph of 12 steps",
-                        "mlups": round(bt["mlups"], 1), "ms_per_step": round(bt["ms_per_step"], 4),
-                        "kernel": bt["kernel"], "tile": bt["tile"],
-                        "roofline": {"bound": "hbm", "achieved": round(per_launch, 1),
-                                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                     "frac": round(per_launch / HBM_PEAK_GBS, 4), "steps_per_launch": spl}}
-        if spl > 1:
-            out["batch"]["roofline"]["single_step_equivalent"] = {
-                "GB/s": round(bt["achieved_GBs"], 1), "frac": round(bt["achieved_GBs"] / HBM_PEAK_GBS, 4)}
+        out["batch"] = batch_line(bt)
     if not args.no_warm_start:
         import contextlib
         from paper_0708_4182_amd import experiments

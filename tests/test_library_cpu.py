@@ -290,3 +290,19 @@ def test_bench_roofline_per_launch(monkeypatch):
     assert two["roofline"]["single_step_equivalent"]["GB/s"] == one["roofline"]["achieved"]
     assert half["roofline"]["achieved"] == round(36 * 800 / 2e-6 / 1e9, 1)
     assert one["mlups"] == two["mlups"] == round(nsites / 1e-6 / 1e6, 1)
+
+
+def test_bench_batch_line_per_launch():
+    """The batch line charges a launch of the sweep table the bytes of one step
+    (each population read and written once per launch), so at two steps per
+    launch its achieved rate is half the single-step equivalent."""
+    import bench
+    bt = {"kernel": "two", "tile": [256, 32], "mlups": 1.0, "ms_per_step": 0.5, "achieved_GBs": 4000.0}
+    two = bench.batch_line(bt)
+    one = bench.batch_line(dict(bt, kernel="fused"))
+    three = bench.batch_line(dict(bt, kernel="three"))
+    assert one["roofline"]["achieved"] == 4000.0 and "single_step_equivalent" not in one["roofline"]
+    assert two["roofline"]["achieved"] == 2000.0 and two["roofline"]["steps_per_launch"] == 2
+    assert two["roofline"]["single_step_equivalent"] == {"GB/s": 4000.0, "frac": 0.5}
+    assert three["roofline"]["frac"] == round(4000.0 / 3 / 8000.0, 4)
+    assert two["kernel"] == "two" and two["tile"] == [256, 32]
